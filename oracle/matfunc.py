@@ -48,17 +48,21 @@ def sgn_spectral_apply(A: np.ndarray, x: np.ndarray) -> np.ndarray:
 def sgn_roberts(A: np.ndarray, tol: float = 1e-14, maxit: int = 100):
     """Eq. (Roberts), unscaled.  Returns (sgn(A), iterations).
 
-    Stops once ||S_{n+1} - S_n||_F <= tol ||S_{n+1}||_F and then takes one more
-    step (quadratic convergence makes that step settle the last digits).
+    Stops once d_n = ||S_{n+1} - S_n||_F / ||S_{n+1}||_F <= tol, or once d_n has
+    reached rounding level (d_n < 1e-8 and no longer shrinking, d_n > d_{n-1}/2,
+    where a quadratically convergent iteration would have squared it), and then
+    takes one more step to settle the last digits.
     """
     S = np.array(A, dtype=np.complex128)
+    prev = np.inf
     for it in range(1, maxit + 1):
         S_new = 0.5 * (S + np.linalg.inv(S))
-        done = np.linalg.norm(S_new - S) <= tol * np.linalg.norm(S_new)
+        d = np.linalg.norm(S_new - S) / np.linalg.norm(S_new)
         S = S_new
-        if done:
+        if d <= tol or (d < 1e-8 and d > 0.5 * prev):
             S = 0.5 * (S + np.linalg.inv(S))
             return S, it + 1
+        prev = d
     raise RuntimeError("Roberts iteration did not converge")
 
 
