@@ -1,0 +1,173 @@
+/*
+ * sgn.h -- C ABI of the MI355X (gfx950) implementation of y = sgn(H_w(mu)) x
+ *
+ * Method: Bloch, Frommer, Lang, Wettig, "An iterative method to compute the
+ * sign function of a non-Hermitian matrix and its application to the overlap
+ * Dirac operator at nonzero chemical potential" (2007).
+ *   H_w(mu) = gamma5 D_w(mu), D_w(mu) the Wilson-Dirac operator of Eq. (Dw)
+ *   (Section 2) with kappa = 1/(8 + 2 m_w), e^{+mu} on forward and e^{-mu}
+ *   on backward time hops.  sgn(A) is the spectral sign of Eqs. (fA), (sgnz).
+ *   y is approximated by the Schur-deflated modified Arnoldi method of
+ *   Section 5.2, steps (i)-(vi).
+ *
+ * Conventions fixed by this library (the paper does not print them):
+ *   - chiral gamma basis: gamma_k = [[0,-i s_k],[i s_k,0]] (k=1,2,3),
+ *     gamma_4 = [[0,1],[1,0]], gamma5 = gamma1 gamma2 gamma3 gamma4 = diag(1,1,-1,-1);
+ *   - periodic boundary conditions in x, y, z; antiperiodic in t.
+ *
+ * Layouts at the ABI (all complex numbers are interleaved complex128, i.e.
+ * two doubles re, im):
+ *   - dims = {Lx, Ly, Lz, Lt}, every L >= 2;  V = Lx Ly Lz Lt,  N = 12 V;
+ *   - site index n = x + Lx (y + Ly (z + Lz t));
+ *   - spinor:  psi[n][spin][colour]   (component 12 n + 3 spin + colour);
+ *   - gauge:   U[n][nu][row][col], nu = 0,1,2,3 <-> x,y,z,t, the SU(3) link
+ *              from n to n + e_nu (host memory, 4 V 9 complex numbers);
+ *   - S (deflation basis): column-major N x m, column j contiguous (device);
+ *   - T: column-major m x m upper triangular (host).
+ *
+ * Ownership: the gauge array is copied during sgn_create.  Vectors x, y are
+ * caller-owned device buffers that must stay valid for the duration of the
+ * call; y may alias x.  The context owns every internal buffer (links, Schur
+ * basis, Krylov workspace) and frees them in sgn_destroy.  A context is not
+ * thread-safe; use one context per host thread.
+ *
+ * Errors: functions return SGN_OK (0) or a negative status; no C++ exception
+ * crosses the ABI.  sgn_last_error() gives a message for the last failure on
+ * a context, sgn_create_error() for the last failed sgn_create on the calling
+ * thread.  All calls are synchronous with respect to the host: when they
+ * return, device results are written.
+ */
+#ifndef SGN_H
+#define SGN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgn_ctx sgn_ctx;
+
+enum {
+  SGN_OK = 0,
+  SGN_EINVAL = -1,     /* bad argument: dims, m_w, tol, kmax, NaN/Inf in x, ... */
+  SGN_ENOMEM = -2,     /* device allocation failed or budget exceeded */
+  SGN_EHIP = -3,       /* HIP runtime error */
+  SGN_ENOCONV = -4,    /* soft: kmax reached before tol; y holds the kmax estimate */
+  SGN_ESINGULAR = -5,  /* singular Newton iterate / eigenvalue on the imaginary axis */
+  SGN_ESTATE = -6,     /* call not valid in the current state (NULL context, ...) */
+  SGN_EDEFL = -7       /* deflation basis not accurate enough (||AS - ST|| too large) */
+};
+
+enum { SGN_PREC_FP64 = 0, SGN_PREC_MIXED = 1 };
+
+/* Per-apply statistics (sgn_last_info). */
+typedef struct sgn_info {
+  int k_used;         /* Krylov dimension of the returned approximation */
+  int converged;      /* 1 if the change between checkpoints fell below tol */
+  int newton_iters;   /* Roberts iterations summed over all checkpoints */
+  int n_matvec;       /* applications of H_w(mu) */
+  int n_checkpoints;  /* evaluations of the small-matrix sign */
+  int breakdown;      /* 1 if the Krylov space became invariant (exact result) */
+  double err_est;     /* ||c_k - c_k'|| / ||c_k|| at the last checkpoint */
+  double beta;        /* |x_perp| = |(1 - S S^dag) x| */
+  double ms_arnoldi;  /* wall time of the Arnoldi steps (device-synchronous) */
+  double ms_sign;     /* wall time of the small-matrix sign evaluations */
+  double ms_total;
+} sgn_info;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context for one gauge field (Eq. Dw).  gauge: host complex128
+ * U[V][4][3][3]; dims: {Lx,Ly,Lz,Lt}, each >= 2; requires 8 + 2 m_w > 0.
+ * The context uses the null stream until sgn_set_stream is called.
+ * Returns NULL on failure (see sgn_create_error). */
+sgn_ctx* sgn_create(const double* gauge, const int dims[4], double mu, double m_w);
+
+/* Message of the last failed sgn_create on this thread ("" if none). */
+const char* sgn_create_error(void);
+
+/* Free every device buffer of the context.  NULL is accepted. */
+void sgn_destroy(sgn_ctx* ctx);
+
+/* Launch all work of this context on the given hipStream_t (NULL = null
+ * stream).  The stream must use the default priority. */
+int sgn_set_stream(sgn_ctx* ctx, void* hip_stream);
+
+/* Lattice extents and vector length N = 12 V of a context. */
+int sgn_get_dims(const sgn_ctx* ctx, int dims[4], long long* n);
+
+/* ---- deflation (Section 5.2, steps (i)-(ii)) ------------------------- */
+
+/* Install a partial Schur pair A S = S T (Eq. pSd) computed elsewhere.
+ * S: device complex128, column-major N x m, orthonormal columns;
+ * T: host complex128, column-major m x m, upper triangular (the strictly
+ * lower part is ignored).  Computes sgn(T) with Roberts' iteration (Eq.
+ * Roberts) on the device.  m = 0 removes deflation.  Returns SGN_EINVAL if
+ * m < 0 or m > N/4, SGN_ESINGULAR if T has a diagonal entry with Re = 0. */
+int sgn_deflate_import(sgn_ctx* ctx, int m, const double* S, const double* T);
+
+/* Copy the installed pair out: S to device (N x m), T to host (m x m),
+ * evals to host (m complex = diag T).  Any pointer may be NULL. */
+int sgn_deflate_export(const sgn_ctx* ctx, double* S, double* T, double* evals);
+
+/* Number of installed deflation vectors (0 if none, <0 on error). */
+int sgn_deflation_size(const sgn_ctx* ctx);
+
+/* ---- the hot path (Section 5.2, steps (iii)-(vi)) ---------------------- */
+
+/* y = sgn(H_w(mu)) x by the deflated modified Arnoldi method.  Krylov steps
+ * continue until the change of the coefficient vector between two even-k
+ * checkpoints is <= tol (relative), or until k = kmax (then SGN_ENOCONV with
+ * y holding the kmax approximation).  x, y: device complex128, N entries.
+ * Requires tol > 0, 2 <= kmax <= N.  Returns SGN_EINVAL for NaN/Inf in x. */
+int sgn_apply(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
+
+/* Fixed Krylov dimension: exactly k modified Arnoldi steps (fewer only on an
+ * exact breakdown), then steps (v)-(vi) once.  k >= 0. */
+int sgn_apply_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
+
+/* Statistics of the last sgn_apply / sgn_apply_fixed. */
+int sgn_last_info(const sgn_ctx* ctx, sgn_info* info);
+
+/* Device bytes an apply with this kmax needs beyond the resident field. */
+size_t sgn_footprint_bytes(const sgn_ctx* ctx, int kmax, int nrhs);
+
+/* ---- building blocks exposed for testing and measurement -------------- */
+
+/* y = H_w(mu) x = gamma5 D_w(mu) x (Eq. Dw), FP64.  x, y: device, N entries;
+ * y must not alias x. */
+int sgn_matvec(sgn_ctx* ctx, const double* x, double* y);
+
+/* F = sgn(A) for a dense n x n complex128 column-major device matrix, by
+ * scaled Roberts/Newton iteration (Eq. Roberts) with a Gauss-Jordan inverse.
+ * Uses the context's stream and workspace.  iters (nullable) receives the
+ * iteration count.  SGN_ESINGULAR on a singular iterate. */
+int sgn_dense_sign(sgn_ctx* ctx, int n, const double* A, double* F, int* iters);
+
+/* Kernel-level timing with HIP events on the context's stream.  When on,
+ * every launch of the instrumented kernels is bracketed by events and its
+ * duration and algorithmic bytes are accumulated per kernel class. */
+int sgn_set_profiling(sgn_ctx* ctx, int on);
+
+typedef struct sgn_kstat {
+  char name[32];      /* kernel class */
+  long long launches;
+  double ms;          /* summed event-measured launch durations */
+  double bytes;       /* summed algorithmic bytes */
+  double flops;       /* summed algorithmic flops */
+} sgn_kstat;
+
+/* Copy up to max entries of the accumulated statistics; returns the count. */
+int sgn_profile_read(const sgn_ctx* ctx, sgn_kstat* out, int max);
+int sgn_profile_reset(sgn_ctx* ctx);
+
+/* ---- errors ------------------------------------------------------------ */
+const char* sgn_strerror(int status);
+const char* sgn_last_error(const sgn_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGN_H */

@@ -1,0 +1,264 @@
+"""Python binding of libsgn: y = sgn(H_w(mu)) x on an MI355X (gfx950).
+
+The functions below carry the names of the C ABI in include/sgn.h and only
+marshal arguments: device vectors are torch tensors (complex128, on the GPU),
+host arrays are numpy arrays.  Every computation runs in the HIP library;
+importing this package fails loudly if libsgn.so has not been built.
+
+    import torch, paper_0704_3486_amd as sg
+    ctx = sg.sgn_create(links, (L, L, L, L), mu, m_w)     # links: numpy (V,4,3,3)
+    sg.sgn_deflate_import(ctx, S, T)                       # optional deflation
+    y = torch.empty_like(x); sg.sgn_apply(ctx, x, y, 1e-10, 500)
+    sg.sgn_destroy(ctx)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgn.so")
+
+SGN_OK = 0
+SGN_EINVAL = -1
+SGN_ENOMEM = -2
+SGN_EHIP = -3
+SGN_ENOCONV = -4
+SGN_ESINGULAR = -5
+SGN_ESTATE = -6
+SGN_EDEFL = -7
+SGN_PREC_FP64 = 0
+SGN_PREC_MIXED = 1
+
+
+class sgn_info(C.Structure):
+    _fields_ = [
+        ("k_used", C.c_int), ("converged", C.c_int), ("newton_iters", C.c_int), ("n_matvec", C.c_int),
+        ("n_checkpoints", C.c_int), ("breakdown", C.c_int),
+        ("err_est", C.c_double), ("beta", C.c_double), ("ms_arnoldi", C.c_double), ("ms_sign", C.c_double),
+        ("ms_total", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class sgn_kstat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_longlong), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+class SgnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it first (python -m paper_0704_3486_amd.build); "
+            "there is no fallback implementation")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d, cp = C.c_void_p, C.c_int, C.c_double, C.c_char_p
+    sig = {
+        "sgn_create": (vp, [vp, C.POINTER(C.c_int), d, d]),
+        "sgn_create_error": (cp, []),
+        "sgn_destroy": (None, [vp]),
+        "sgn_set_stream": (i, [vp, vp]),
+        "sgn_get_dims": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)]),
+        "sgn_deflate_import": (i, [vp, i, vp, vp]),
+        "sgn_deflate_export": (i, [vp, vp, vp, vp]),
+        "sgn_deflation_size": (i, [vp]),
+        "sgn_apply": (i, [vp, vp, vp, d, i]),
+        "sgn_apply_fixed": (i, [vp, vp, vp, i]),
+        "sgn_last_info": (i, [vp, C.POINTER(sgn_info)]),
+        "sgn_footprint_bytes": (C.c_size_t, [vp, i, i]),
+        "sgn_matvec": (i, [vp, vp, vp]),
+        "sgn_dense_sign": (i, [vp, i, vp, vp, C.POINTER(C.c_int)]),
+        "sgn_set_profiling": (i, [vp, i]),
+        "sgn_profile_read": (i, [vp, C.POINTER(sgn_kstat), i]),
+        "sgn_profile_reset": (i, [vp]),
+        "sgn_strerror": (cp, [i]),
+        "sgn_last_error": (cp, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+lib = _lib
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def _dptr(t, n=None, name="tensor"):
+    """Device pointer of a contiguous complex128 CUDA/HIP tensor."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous complex128")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hptr(a, n=None, name="array"):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if n is not None and a.size != n:
+        raise ValueError(f"{name} must have {n} entries, has {a.size}")
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _check(ctx, st, soft=()):
+    if st == SGN_OK or st in soft:
+        return st
+    msg = _lib.sgn_last_error(ctx).decode() if ctx else ""
+    raise SgnError(st, f"{_lib.sgn_strerror(st).decode()}: {msg}")
+
+
+# ---------------------------------------------------------------------------
+# ABI functions (same names as include/sgn.h)
+# ---------------------------------------------------------------------------
+def sgn_create(gauge, dims, mu, m_w, stream=None):
+    """Create a context; gauge is the host link array U[n][nu][3][3] (complex128).
+
+    The context runs on torch's current stream unless another stream is given.
+    """
+    import torch
+
+    dims = [int(d) for d in dims]
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    g, gp = _hptr(gauge, 36 * V, "gauge")
+    cd = (C.c_int * 4)(*dims)
+    ctx = _lib.sgn_create(gp, cd, float(mu), float(m_w))
+    if not ctx:
+        raise SgnError(SGN_EINVAL, _lib.sgn_create_error().decode())
+    ctx = C.c_void_p(ctx)
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(ctx, _lib.sgn_set_stream(ctx, C.c_void_p(s)))
+    return ctx
+
+
+def sgn_destroy(ctx):
+    _lib.sgn_destroy(ctx)
+
+
+def sgn_set_stream(ctx, stream):
+    return _check(ctx, _lib.sgn_set_stream(ctx, C.c_void_p(stream)))
+
+
+def sgn_get_dims(ctx):
+    d = (C.c_int * 4)()
+    n = C.c_longlong()
+    _check(ctx, _lib.sgn_get_dims(ctx, d, C.byref(n)))
+    return tuple(d), int(n.value)
+
+
+def sgn_deflate_import(ctx, S, T):
+    """Install (S, T): S a GPU tensor (N, m) in column order (S.T contiguous), T host (m, m)."""
+    import torch
+
+    _, N = sgn_get_dims(ctx)
+    T = np.asarray(T, dtype=np.complex128)
+    m = T.shape[0]
+    if m == 0:
+        return _check(ctx, _lib.sgn_deflate_import(ctx, 0, None, None))
+    if S.shape != (N, m):
+        raise ValueError("S must have shape (N, m)")
+    Scols = S.transpose(0, 1).contiguous()  # column j contiguous
+    Tf, tp = _hptr(np.asfortranarray(T).ravel(order="F"), m * m, "T")
+    st = _lib.sgn_deflate_import(ctx, m, _dptr(Scols, N * m, "S"), tp)
+    torch.cuda.synchronize()
+    return _check(ctx, st)
+
+
+def sgn_deflate_export(ctx):
+    """Return (S as GPU tensor (N, m), T host (m, m), evals host (m,))."""
+    import torch
+
+    _, N = sgn_get_dims(ctx)
+    m = _lib.sgn_deflation_size(ctx)
+    if m == 0:
+        return None, np.zeros((0, 0), complex), np.zeros(0, complex)
+    Scols = torch.empty((m, N), dtype=torch.complex128, device="cuda")
+    T = np.zeros(m * m, dtype=np.complex128)
+    ev = np.zeros(m, dtype=np.complex128)
+    _check(ctx, _lib.sgn_deflate_export(ctx, _dptr(Scols), T.ctypes.data_as(C.c_void_p),
+                                       ev.ctypes.data_as(C.c_void_p)))
+    return Scols.transpose(0, 1), T.reshape(m, m, order="F"), ev
+
+
+def sgn_deflation_size(ctx):
+    return _lib.sgn_deflation_size(ctx)
+
+
+def sgn_apply(ctx, x, y, tol, kmax):
+    """y = sgn(H_w(mu)) x; returns SGN_OK or SGN_ENOCONV (soft)."""
+    _, N = sgn_get_dims(ctx)
+    st = _lib.sgn_apply(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), float(tol), int(kmax))
+    return _check(ctx, st, soft=(SGN_ENOCONV,))
+
+
+def sgn_apply_fixed(ctx, x, y, k):
+    _, N = sgn_get_dims(ctx)
+    return _check(ctx, _lib.sgn_apply_fixed(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), int(k)))
+
+
+def sgn_last_info(ctx):
+    info = sgn_info()
+    _check(ctx, _lib.sgn_last_info(ctx, C.byref(info)))
+    return info.as_dict()
+
+
+def sgn_footprint_bytes(ctx, kmax, nrhs=1):
+    return int(_lib.sgn_footprint_bytes(ctx, int(kmax), int(nrhs)))
+
+
+def sgn_matvec(ctx, x, y):
+    _, N = sgn_get_dims(ctx)
+    return _check(ctx, _lib.sgn_matvec(ctx, _dptr(x, N, "x"), _dptr(y, N, "y")))
+
+
+def sgn_dense_sign(ctx, A, F):
+    """F = sgn(A) for square GPU tensors in column-major order (pass A.T.contiguous())."""
+    n = int(round(A.numel() ** 0.5))
+    it = C.c_int()
+    _check(ctx, _lib.sgn_dense_sign(ctx, n, _dptr(A, n * n, "A"), _dptr(F, n * n, "F"), C.byref(it)))
+    return it.value
+
+
+def sgn_set_profiling(ctx, on):
+    return _check(ctx, _lib.sgn_set_profiling(ctx, int(bool(on))))
+
+
+def sgn_profile_read(ctx):
+    arr = (sgn_kstat * 16)()
+    n = _lib.sgn_profile_read(ctx, arr, 16)
+    _check(ctx, n if n < 0 else SGN_OK)
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes,
+                                   "flops": arr[i].flops} for i in range(n)}
+
+
+def sgn_profile_reset(ctx):
+    return _check(ctx, _lib.sgn_profile_reset(ctx))
+
+
+def sgn_strerror(status):
+    return _lib.sgn_strerror(int(status)).decode()
+
+
+def sgn_last_error(ctx):
+    return _lib.sgn_last_error(ctx).decode()
+
+
+def sgn_create_error():
+    return _lib.sgn_create_error().decode()

@@ -1,0 +1,688 @@
+// C ABI of libsgn: context management and the deflated modified Arnoldi
+// driver (Section 5.2, steps (iii)-(vi)).
+//
+// Per source x (step (iii)):  pack x, two classical Gram-Schmidt passes
+// against S_m give c0 = S^dag x and x_perp, beta = |x_perp|.
+// Per Krylov step j (step (iv), Eq. eq:modArnoldi), all on the device:
+//     w  = H_w(mu) v_j             (stencil; also stores v_j = w_prev / beta)
+//     h1 = Q^dag w, w -= Q h1      (pass 1 against Q = (S_m, v_1..v_j))
+//     h2 = Q^dag w, w -= Q h2      (pass 2, re-orthogonalisation)
+//     column j of H = h1 + h2, H_{j+1,j} = |w|
+// so X = S_m^dag A V_k and H_k accumulate in one composite matrix
+// H = [[T_m, X], [0, H_k]] (Eq. eq:newH).  At even checkpoints k (step (v))
+// the device computes sgn(H) by Roberts' iteration on the composite matrix,
+// which yields sgn(T_m), sgn(H_k) and the Sylvester block Y of Eq. (eq:f_H)
+// at once, and the coefficient vector c = sgn(H) Q^dag x with
+// Q^dag x = [c0; beta e_1].  Step (vi) is y = Q c (Eq. eq:formula).
+// Convergence: ||c_k - [c_k'; 0]|| / ||c_k|| <= tol between checkpoints;
+// because Q has orthonormal columns this is exactly the relative change of y.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+// ---------------------------------------------------------------------------
+// profiler
+// ---------------------------------------------------------------------------
+hipEvent_t Profiler::get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  SGN_HIP(hipEventCreate(&e));
+  return e;
+}
+
+int Profiler::begin(int cls) {
+  if (!on) return -1;
+  Pending p{get_event(), get_event(), cls};
+  SGN_HIP(hipEventRecord(p.a, stream));
+  pending.push_back(p);
+  return (int)pending.size() - 1;
+}
+
+void Profiler::end(int idx, double nbytes, double nflops) {
+  if (!on || idx < 0) return;
+  Pending& p = pending[idx];
+  SGN_HIP(hipEventRecord(p.b, stream));
+  launches[p.cls] += 1;
+  bytes[p.cls] += nbytes;
+  flops[p.cls] += nflops;
+}
+
+void Profiler::flush() {
+  if (pending.empty()) return;
+  SGN_HIP(hipStreamSynchronize(stream));
+  for (auto& p : pending) {
+    float t = 0.f;
+    SGN_HIP(hipEventElapsedTime(&t, p.a, p.b));
+    ms[p.cls] += t;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void Profiler::reset() {
+  for (int i = 0; i < K_NCLASS; ++i) {
+    launches[i] = 0;
+    ms[i] = bytes[i] = flops[i] = 0.0;
+  }
+}
+
+Profiler::~Profiler() {
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+static const char* kclass_name(int c) {
+  switch (c) {
+    case K_WILSON: return "wilson_hw";
+    case K_GS_DOT: return "gs_dot";
+    case K_GS_UPDATE: return "gs_update";
+    case K_GJ_PANEL: return "gj_inverse";
+    case K_NEWTON_COMBINE: return "newton_combine";
+    default: return "misc";
+  }
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct sgn_ctx {
+  Lattice lat{};
+  int N = 0;
+  size_t ldq = 0;
+  double mu = 0, m_w = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  sgn_info info{};
+  Profiler prof;
+
+  double2* links = nullptr;  // [4][9][V]
+
+  // deflation
+  int m = 0;
+  double2* S = nullptr;       // internal layout, ldq x m
+  std::vector<double2> T;     // host m x m (column-major, upper triangular)
+  double2* Tdev = nullptr;    // m x m
+  double2* sgnT = nullptr;    // m x m
+
+  // Krylov workspace
+  int kcap = 0;               // capacity in Krylov vectors
+  int ncap = 0;               // m + kcap + 1 (columns of Q, rows of H)
+  double2* Q = nullptr;       // ldq x ncap
+  double2* Hc = nullptr;      // ncap x ncap, column-major (ld = ncap)
+  double2* F = nullptr;       // sign output (m + kcap)^2, ld = n
+  double2* wA = nullptr;
+  double2* wB = nullptr;
+  double2* xin = nullptr;
+  double2* hbuf1 = nullptr;
+  double2* hbuf2 = nullptr;
+  double2* c0 = nullptr;
+  double2* cvec = nullptr;
+  double2* cprev = nullptr;
+  double* scal = nullptr;     // [0] beta0 [1] inv_beta [2] err [3] scratch
+  int* flag = nullptr;        // [0] breakdown/finite flag
+  double* hpin = nullptr;     // pinned host mirror
+  GsWork gs;
+  DenseWork dense;
+
+  ~sgn_ctx() { release(); }
+
+  void release_workspace() {
+    for (double2** p : {&Q, &Hc, &F, &wA, &wB, &xin, &hbuf1, &hbuf2, &c0, &cvec, &cprev})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    gs_free(gs);
+    kcap = 0;
+    ncap = 0;
+  }
+
+  void release() {
+    if (stream || true) (void)hipDeviceSynchronize();
+    release_workspace();
+    dense_free(dense);
+    for (double2** p : {&links, &S, &Tdev, &sgnT})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    if (scal) (void)hipFree(scal);
+    if (flag) (void)hipFree(flag);
+    if (hpin) (void)hipHostFree(hpin);
+    scal = nullptr;
+    flag = nullptr;
+    hpin = nullptr;
+  }
+
+  // make sure the Krylov workspace holds m + kmax + 1 columns
+  void ensure_workspace(int kmax) {
+    if (kmax <= kcap && Q) return;
+    release_workspace();
+    kcap = kmax;
+    ncap = m + kcap + 1;
+    SGN_HIP(hipMalloc(&Q, sizeof(double2) * ldq * (size_t)ncap));
+    SGN_HIP(hipMalloc(&Hc, sizeof(double2) * (size_t)ncap * ncap));
+    SGN_HIP(hipMalloc(&F, sizeof(double2) * (size_t)(m + kcap) * (m + kcap)));
+    SGN_HIP(hipMalloc(&wA, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&wB, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&xin, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&hbuf1, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&hbuf2, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&c0, sizeof(double2) * (size_t)(m > 0 ? m : 1)));
+    SGN_HIP(hipMalloc(&cvec, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&cprev, sizeof(double2) * (size_t)ncap));
+    gs_alloc(gs, N, ldq, ncap);
+    // the Schur block of Q and of H never changes between applies
+    if (m > 0) {
+      SGN_HIP(hipMemcpy2D(Q, ldq * sizeof(double2), S, ldq * sizeof(double2), ldq * sizeof(double2), m,
+                          hipMemcpyDeviceToDevice));
+    }
+    SGN_HIP(hipMemset(Hc, 0, sizeof(double2) * (size_t)ncap * ncap));
+    if (m > 0) dev_copy_mat(Tdev, m, Hc, ncap, m, m, nullptr);
+    SGN_HIP(hipDeviceSynchronize());
+  }
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(sgn_ctx* c, const SgnError& e) {
+  if (c) c->last_error = e.msg;
+  return e.status;
+}
+
+template <class F>
+int guarded(sgn_ctx* c, F&& f) {
+  if (!c) return SGN_ESTATE;
+  try {
+    return f();
+  } catch (const SgnError& e) {
+    return fail(c, e);
+  } catch (const std::bad_alloc&) {
+    return fail(c, SgnError{SGN_ENOMEM, "host allocation failed"});
+  } catch (...) {
+    return fail(c, SgnError{SGN_EHIP, "unexpected error"});
+  }
+}
+
+int even_up(int k) { return (k + 1) & ~1; }
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float t = 0.f;
+  SGN_HIP(hipEventElapsedTime(&t, a, b));
+  return (double)t;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    SGN_HIP(hipEventCreate(&a));
+    SGN_HIP(hipEventCreate(&b));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Result of the Arnoldi driver.
+struct ApplyResult {
+  int status = SGN_OK;
+};
+
+// Steps (iii)-(vi).  fixed_k >= 0: exactly that many steps, no convergence test.
+int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int kmax, int fixed_k) {
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = c->stream;
+  Profiler* prof = c->prof.on ? &c->prof : nullptr;
+  c->prof.stream = s;
+  const int m = c->m;
+  const int N = c->N;
+  const size_t ldq = c->ldq;
+  const int kwant = fixed_k >= 0 ? fixed_k : kmax;
+  c->ensure_workspace(std::max(kwant, 2));
+  const int ncap = c->ncap;
+  sgn_info info{};
+  double ms_sign = 0.0;
+
+  // step (iii): x_perp = (1 - S S^dag) x, beta = |x_perp|
+  SGN_HIP(hipMemsetAsync(c->flag, 0, sizeof(int) * 2, s));
+  wilson_pack(c->lat, x_abi, c->xin, s);
+  dev_check_finite(c->xin, (size_t)N, c->flag + 1, s);
+  SGN_HIP(hipMemcpyAsync(c->wA, c->xin, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+  if (m > 0) {
+    gs_dot(c->gs, c->Q, ldq, N, m, c->wA, c->hbuf1, s, prof);
+    gs_update(c->gs, c->Q, ldq, N, m, c->hbuf1, c->wA, nullptr, 0, s, prof);
+    gs_dot(c->gs, c->Q, ldq, N, m, c->wA, c->hbuf2, s, prof);
+    GsFinal fin{c->hbuf1, c->hbuf2 /*unused*/, &c->scal[0], &c->scal[1], c->flag};
+    // c0 = h1 + h2 goes to the c0 buffer (m entries + beta slot -> use hbuf2 scratch)
+    fin.hout = c->cvec;
+    gs_update(c->gs, c->Q, ldq, N, m, c->hbuf2, c->wA, &fin, 0, s, prof);
+    SGN_HIP(hipMemcpyAsync(c->c0, c->cvec, sizeof(double2) * m, hipMemcpyDeviceToDevice, s));
+  } else {
+    gs_norm(c->gs, N, c->wA, &c->scal[0], &c->scal[1], c->flag, s, prof);
+  }
+  SGN_HIP(hipMemcpyAsync(c->hpin, c->scal, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipMemcpyAsync(&c->hpin[4], c->flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipStreamSynchronize(s));
+  int hflag[2];
+  std::memcpy(hflag, &c->hpin[4], sizeof(int) * 2);
+  if (hflag[1] != 0 || hflag[0] < 0) throw SgnError{SGN_EINVAL, "x contains NaN or Inf"};
+  const double beta0 = c->hpin[0];
+  info.beta = beta0;
+  const bool x_in_schur = (hflag[0] == 1);  // beta == 0 relative to |S^dag x|
+
+  int k = 0;
+  bool converged = false;
+  bool breakdown = false;
+  int nprev = -1;  // size of cprev (m + k') or -1
+  double err = 1e30;
+  int ncheck = 0;
+  int newton_total = 0;
+  std::vector<std::pair<int, double>> hist;  // (k of the earlier checkpoint, change)
+  int prev_ck = -1;
+
+  auto checkpoint = [&](int kk) -> double {
+    // sign of the composite (m + kk) matrix, coefficients, change estimate
+    const int n = m + kk;
+    const auto t0 = std::chrono::steady_clock::now();
+    int it = 0;
+    if (n > 0) it = dense_sign(c->dense, n, c->Hc, ncap, c->F, n, s, prof);
+    newton_total += it;
+    dense_coeffs(n, m, c->F, n, c->c0, &c->scal[0], c->cvec, nprev >= 0 ? c->cprev : nullptr,
+                 nprev >= 0 ? nprev : 0, &c->scal[2], s);
+    SGN_HIP(hipMemcpyAsync(&c->hpin[2], &c->scal[2], sizeof(double), hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    ms_sign += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ++ncheck;
+    const double e = c->hpin[2];
+    SGN_HIP(hipMemcpyAsync(c->cprev, c->cvec, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+    nprev = n;
+    return e;
+  };
+
+  if (x_in_schur || kwant == 0) {
+    // y = S sgn(T) S^dag x exactly (no Krylov part), or k = 0 requested
+    SGN_HIP(hipMemsetAsync(&c->scal[0], 0, sizeof(double), s));
+    if (m > 0) {
+      err = checkpoint(0);
+    }
+    converged = true;
+    breakdown = x_in_schur;
+  } else {
+    // Krylov loop (step (iv)) with checkpoints (step (v))
+    int next_ck;
+    if (fixed_k >= 0) {
+      next_ck = fixed_k;
+    } else {
+      next_ck = std::min(kmax, std::max(2, even_up(std::min(32, kmax / 2))));
+    }
+    double2* wprev = c->wA;  // holds x_perp (unnormalised) for j = 0
+    double2* wcur = c->wB;
+    for (int j = 0; j < kwant; ++j) {
+      double2* vcol = c->Q + (size_t)(m + j) * ldq;
+      wilson_apply(c->lat, c->links, wprev, wcur, &c->scal[1], vcol, s, prof);
+      const int ncol = m + j + 1;
+      gs_dot(c->gs, c->Q, ldq, N, ncol, wcur, c->hbuf1, s, prof);
+      gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf1, wcur, nullptr, 0, s, prof);
+      gs_dot(c->gs, c->Q, ldq, N, ncol, wcur, c->hbuf2, s, prof);
+      GsFinal fin{c->hbuf1, c->Hc + (size_t)(m + j) * ncap, nullptr, &c->scal[1], c->flag};
+      gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf2, wcur, &fin, j + 1, s, prof);
+      std::swap(wprev, wcur);
+      k = j + 1;
+      info.n_matvec += 1;
+      if (k == next_ck || k == kwant) {
+        // breakdown check (flag = k_invariant + 1)
+        SGN_HIP(hipMemcpyAsync(&c->hpin[4], c->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        SGN_HIP(hipStreamSynchronize(s));
+        int f0;
+        std::memcpy(&f0, &c->hpin[4], sizeof(int));
+        if (f0 < 0) throw SgnError{SGN_EINVAL, "non-finite value in the Krylov basis"};
+        if (f0 > 0) {
+          k = f0 - 1;
+          breakdown = true;
+        }
+        const double e = checkpoint(k);
+        if (fixed_k >= 0 || breakdown) {
+          err = e;
+          converged = true;
+          break;
+        }
+        if (prev_ck >= 0 && e < 1e29) hist.emplace_back(prev_ck, e);
+        err = e;
+        if (e <= tol) {
+          converged = true;
+          break;
+        }
+        prev_ck = k;
+        // choose the next checkpoint
+        int nk;
+        if (hist.size() >= 2) {
+          const auto& a = hist[hist.size() - 2];
+          const auto& b = hist[hist.size() - 1];
+          const double rho_log = (std::log(b.second) - std::log(a.second)) / std::max(1, b.first - a.first);
+          if (rho_log < -1e-6) {
+            // err(k) ~ b.second * exp(rho_log (k - b.first)); want err(k_next - delta) <= tol / 2
+            const double steps = std::log(0.5 * tol / b.second) / rho_log;
+            int target = b.first + (int)std::ceil(1.05 * steps);
+            if (target <= k) {
+              nk = k + 4;  // the previous checkpoint should already be below tol: confirm
+            } else {
+              nk = target;
+            }
+          } else {
+            nk = k + std::max(8, k / 2);
+          }
+        } else {
+          nk = k + std::max(8, k / 2);
+        }
+        next_ck = std::min(kmax, even_up(std::max(nk, k + 2)));
+      }
+    }
+  }
+
+  // step (vi): y = Q c
+  const int n = m + k;
+  gs_combine(c->gs, c->Q, ldq, N, n, c->cvec, c->wA, nullptr, s, prof);
+  wilson_unpack(c->lat, c->wA, y_abi, s);
+  SGN_HIP(hipStreamSynchronize(s));
+  if (prof) c->prof.flush();
+
+  info.k_used = k;
+  info.converged = converged ? 1 : 0;
+  info.newton_iters = newton_total;
+  info.n_checkpoints = ncheck;
+  info.breakdown = breakdown ? 1 : 0;
+  info.err_est = err;
+  info.ms_sign = ms_sign;
+  info.ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  info.ms_arnoldi = info.ms_total - ms_sign;
+  c->info = info;
+  if (fixed_k < 0 && !converged) {
+    c->last_error = "kmax reached before the requested tolerance";
+    return SGN_ENOCONV;
+  }
+  return SGN_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sgn_strerror(int st) {
+  switch (st) {
+    case SGN_OK: return "ok";
+    case SGN_EINVAL: return "invalid argument";
+    case SGN_ENOMEM: return "out of memory";
+    case SGN_EHIP: return "HIP runtime error";
+    case SGN_ENOCONV: return "not converged within kmax";
+    case SGN_ESINGULAR: return "singular matrix or eigenvalue on the imaginary axis";
+    case SGN_ESTATE: return "invalid state";
+    case SGN_EDEFL: return "deflation basis not accurate enough";
+    default: return "unknown status";
+  }
+}
+
+const char* sgn_create_error(void) { return g_create_error.c_str(); }
+
+const char* sgn_last_error(const sgn_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+
+sgn_ctx* sgn_create(const double* gauge, const int dims[4], double mu, double m_w) {
+  g_create_error.clear();
+  if (!gauge || !dims) {
+    g_create_error = "gauge and dims must not be NULL";
+    return nullptr;
+  }
+  for (int d = 0; d < 4; ++d)
+    if (dims[d] < 2) {
+      g_create_error = "every lattice extent must be >= 2";
+      return nullptr;
+    }
+  if (!(8.0 + 2.0 * m_w > 0.0) || !std::isfinite(mu) || !std::isfinite(m_w)) {
+    g_create_error = "need 8 + 2 m_w > 0 and finite mu, m_w";
+    return nullptr;
+  }
+  const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V * 12 > (1LL << 30)) {
+    g_create_error = "lattice too large";
+    return nullptr;
+  }
+  std::unique_ptr<sgn_ctx> c(new (std::nothrow) sgn_ctx());
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return nullptr;
+  }
+  try {
+    for (int d = 0; d < 4; ++d) c->lat.L[d] = dims[d];
+    c->lat.V = (int)V;
+    c->lat.kappa = 1.0 / (8.0 + 2.0 * m_w);
+    c->lat.emu = std::exp(mu);
+    c->lat.emmu = std::exp(-mu);
+    c->mu = mu;
+    c->m_w = m_w;
+    c->N = (int)(12 * V);
+    c->ldq = ((size_t)c->N + 63) / 64 * 64;
+    SGN_HIP(hipMalloc(&c->links, sizeof(double2) * 36 * (size_t)V));
+    double2* graw = nullptr;
+    SGN_HIP(hipMalloc(&graw, sizeof(double2) * 36 * (size_t)V));
+    SGN_HIP(hipMemcpy(graw, gauge, sizeof(double2) * 36 * (size_t)V, hipMemcpyHostToDevice));
+    wilson_pack_links(c->lat, graw, c->links, nullptr);
+    SGN_HIP(hipDeviceSynchronize());
+    SGN_HIP(hipFree(graw));
+    SGN_HIP(hipMalloc(&c->scal, sizeof(double) * 8));
+    SGN_HIP(hipMalloc(&c->flag, sizeof(int) * 4));
+    SGN_HIP(hipHostMalloc(&c->hpin, sizeof(double) * 8, hipHostMallocDefault));
+    SGN_HIP(hipMemset(c->scal, 0, sizeof(double) * 8));
+    SGN_HIP(hipMemset(c->flag, 0, sizeof(int) * 4));
+  } catch (const SgnError& e) {
+    g_create_error = e.msg;
+    return nullptr;
+  }
+  return c.release();
+}
+
+void sgn_destroy(sgn_ctx* c) { delete c; }
+
+int sgn_set_stream(sgn_ctx* c, void* stream) {
+  return guarded(c, [&] {
+    SGN_HIP(hipDeviceSynchronize());
+    c->stream = (hipStream_t)stream;
+    c->prof.stream = c->stream;
+    return SGN_OK;
+  });
+}
+
+int sgn_get_dims(const sgn_ctx* c, int dims[4], long long* n) {
+  if (!c) return SGN_ESTATE;
+  if (dims)
+    for (int d = 0; d < 4; ++d) dims[d] = c->lat.L[d];
+  if (n) *n = c->N;
+  return SGN_OK;
+}
+
+int sgn_deflation_size(const sgn_ctx* c) { return c ? c->m : SGN_ESTATE; }
+
+int sgn_deflate_import(sgn_ctx* c, int m, const double* S_abi, const double* T_host) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(m >= 0 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 0 <= m <= N/4");
+    SGN_REQUIRE(m == 0 || (S_abi && T_host), SGN_EINVAL, "S and T must not be NULL");
+    hipStream_t s = c->stream;
+    SGN_HIP(hipStreamSynchronize(s));
+    // drop the old basis and the workspace (its layout depends on m)
+    c->release_workspace();
+    for (double2** p : {&c->S, &c->Tdev, &c->sgnT})
+      if (*p) {
+        SGN_HIP(hipFree(*p));
+        *p = nullptr;
+      }
+    c->T.clear();
+    c->m = 0;
+    if (m == 0) return SGN_OK;
+    std::vector<double2> Th((size_t)m * m);
+    std::memcpy(Th.data(), T_host, sizeof(double2) * Th.size());
+    for (int j = 0; j < m; ++j)
+      for (int i = j + 1; i < m; ++i) Th[(size_t)j * m + i] = make_double2(0.0, 0.0);
+    for (int i = 0; i < m; ++i) {
+      const double2 d = Th[(size_t)i * m + i];
+      SGN_REQUIRE(std::isfinite(d.x) && std::isfinite(d.y), SGN_EINVAL, "T has a non-finite diagonal");
+      SGN_REQUIRE(d.x != 0.0, SGN_ESINGULAR, "T has an eigenvalue on the imaginary axis");
+    }
+    SGN_HIP(hipMalloc(&c->S, sizeof(double2) * c->ldq * (size_t)m));
+    SGN_HIP(hipMemset(c->S, 0, sizeof(double2) * c->ldq * (size_t)m));
+    for (int j = 0; j < m; ++j)
+      wilson_pack(c->lat, reinterpret_cast<const double2*>(S_abi) + (size_t)j * c->N, c->S + (size_t)j * c->ldq, s);
+    SGN_HIP(hipMalloc(&c->Tdev, sizeof(double2) * (size_t)m * m));
+    SGN_HIP(hipMalloc(&c->sgnT, sizeof(double2) * (size_t)m * m));
+    SGN_HIP(hipMemcpyAsync(c->Tdev, Th.data(), sizeof(double2) * Th.size(), hipMemcpyHostToDevice, s));
+    dense_sign(c->dense, m, c->Tdev, m, c->sgnT, m, s, nullptr);  // step (ii)
+    SGN_HIP(hipStreamSynchronize(s));
+    c->T = std::move(Th);
+    c->m = m;
+    return SGN_OK;
+  });
+}
+
+int sgn_deflate_export(const sgn_ctx* cc, double* S_abi, double* T_host, double* evals) {
+  sgn_ctx* c = const_cast<sgn_ctx*>(cc);
+  return guarded(c, [&] {
+    const int m = c->m;
+    if (S_abi)
+      for (int j = 0; j < m; ++j)
+        wilson_unpack(c->lat, c->S + (size_t)j * c->ldq, reinterpret_cast<double2*>(S_abi) + (size_t)j * c->N,
+                      c->stream);
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    if (T_host && m) std::memcpy(T_host, c->T.data(), sizeof(double2) * (size_t)m * m);
+    if (evals)
+      for (int i = 0; i < m; ++i) {
+        evals[2 * i] = c->T[(size_t)i * m + i].x;
+        evals[2 * i + 1] = c->T[(size_t)i * m + i].y;
+      }
+    return SGN_OK;
+  });
+}
+
+int sgn_apply(sgn_ctx* c, const double* x, double* y, double tol, int kmax) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), tol, kmax, -1);
+  });
+}
+
+int sgn_apply_fixed(sgn_ctx* c, const double* x, double* y, int k) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
+    SGN_REQUIRE(k >= 0 && k <= c->N - c->m, SGN_EINVAL, "k must satisfy 0 <= k <= N - m");
+    return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), 1.0, k, k);
+  });
+}
+
+int sgn_last_info(const sgn_ctx* c, sgn_info* info) {
+  if (!c) return SGN_ESTATE;
+  if (!info) return SGN_EINVAL;
+  *info = c->info;
+  return SGN_OK;
+}
+
+size_t sgn_footprint_bytes(const sgn_ctx* c, int kmax, int nrhs) {
+  if (!c || kmax < 0 || nrhs < 1) return 0;
+  const size_t ncap = (size_t)c->m + kmax + 1;
+  const size_t per = sizeof(double2) * (c->ldq * (ncap + 3) + ncap * ncap + (ncap - 1) * (ncap - 1) + 4 * ncap) +
+                     sizeof(double2) * c->ldq * ((ncap + 31) / 32);
+  const size_t dense = 3 * sizeof(double2) * (ncap - 1) * (ncap - 1);
+  return per * (size_t)nrhs + dense;
+}
+
+int sgn_matvec(sgn_ctx* c, const double* x, double* y) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y && x != y, SGN_EINVAL, "x and y must be distinct non-NULL buffers");
+    double2 *a = nullptr, *b = nullptr;
+    SGN_HIP(hipMalloc(&a, sizeof(double2) * c->ldq));
+    SGN_HIP(hipMalloc(&b, sizeof(double2) * c->ldq));
+    try {
+      wilson_pack(c->lat, reinterpret_cast<const double2*>(x), a, c->stream);
+      wilson_apply(c->lat, c->links, a, b, nullptr, nullptr, c->stream, c->prof.on ? &c->prof : nullptr);
+      wilson_unpack(c->lat, b, reinterpret_cast<double2*>(y), c->stream);
+      SGN_HIP(hipStreamSynchronize(c->stream));
+      if (c->prof.on) c->prof.flush();
+    } catch (...) {
+      (void)hipFree(a);
+      (void)hipFree(b);
+      throw;
+    }
+    SGN_HIP(hipFree(a));
+    SGN_HIP(hipFree(b));
+    return SGN_OK;
+  });
+}
+
+int sgn_dense_sign(sgn_ctx* c, int n, const double* A, double* F, int* iters) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(n >= 1 && A && F, SGN_EINVAL, "need n >= 1 and non-NULL A, F");
+    c->prof.stream = c->stream;
+    const int it = dense_sign(c->dense, n, reinterpret_cast<const double2*>(A), n, reinterpret_cast<double2*>(F), n,
+                              c->stream, c->prof.on ? &c->prof : nullptr);
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    if (c->prof.on) c->prof.flush();
+    if (iters) *iters = it;
+    return SGN_OK;
+  });
+}
+
+int sgn_set_profiling(sgn_ctx* c, int on) {
+  return guarded(c, [&] {
+    c->prof.stream = c->stream;
+    if (!on) c->prof.flush();
+    c->prof.on = on != 0;
+    return SGN_OK;
+  });
+}
+
+int sgn_profile_read(const sgn_ctx* cc, sgn_kstat* out, int max) {
+  sgn_ctx* c = const_cast<sgn_ctx*>(cc);
+  return guarded(c, [&] {
+    c->prof.flush();
+    int cnt = 0;
+    for (int k = 0; k < K_NCLASS && cnt < max; ++k) {
+      if (!out) break;
+      sgn_kstat& o = out[cnt++];
+      std::memset(&o, 0, sizeof(o));
+      std::strncpy(o.name, kclass_name(k), sizeof(o.name) - 1);
+      o.launches = c->prof.launches[k];
+      o.ms = c->prof.ms[k];
+      o.bytes = c->prof.bytes[k];
+      o.flops = c->prof.flops[k];
+    }
+    return cnt;
+  });
+}
+
+int sgn_profile_reset(sgn_ctx* c) {
+  return guarded(c, [&] {
+    c->prof.flush();
+    c->prof.reset();
+    return SGN_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,461 @@
+// Sign of the small dense composite matrix H (Eq. eq:newH) on the device:
+// Roberts' iteration S <- (S + S^{-1})/2, S_0 = H (Eq. Roberts), in FP64,
+// with determinantal scaling S <- (mu S + (mu S)^{-1})/2, mu = |det S|^{-1/n},
+// while the iterates still move by more than 1e-2 (relative Frobenius norm).
+//
+// The inverse is a blocked in-place Gauss-Jordan elimination with partial
+// pivoting by rows.  Pivoting is implicit: no rows are swapped; column p is
+// eliminated with pivot row r_p, rows already used are excluded from later
+// pivot searches, and the inverse is read back as
+//     A^{-1}[p][q] = M[r_p][r^{-1}(q)].
+// One launch handles a panel of BP columns.  Every workgroup loads the panel
+// into LDS and factorises it redundantly (identical data and code, so every
+// workgroup picks the same pivots), then applies the accumulated elimination
+//     M[:, j] <- (I - P_R) M[:, j] + G M[R, j]        (R = panel pivot rows)
+// to its own tile of columns, where G (n x BP) is the factorised panel.  The
+// matrix is ping-ponged between two buffers so no workgroup reads data that
+// another one writes in the same launch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kGjThreads = 256;
+constexpr int kGjTile = 4;  // columns per workgroup in the trailing update
+
+inline size_t gj_lds_bytes(int n, int bp) {
+  return sizeof(double2) * (size_t)n * bp + sizeof(int) * (size_t)(2 * n + (n & 1)) + sizeof(double2) * (size_t)n;
+}
+
+__device__ inline void argmax_merge(double& v, int& i, double v2, int i2) {
+  if (v2 > v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+// LDS layout: panel[n][BP] (double2), used[n] (int), inR[n] (int), fcol[n] (double2)
+template <int BP>
+__global__ void __launch_bounds__(kGjThreads)
+gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int n, int p0,
+                int* __restrict__ rowpiv, double* __restrict__ logpiv, int* __restrict__ flag) {
+  extern __shared__ double2 smem[];
+  double2* panel = smem;                                   // n * BP
+  int* used = reinterpret_cast<int*>(panel + (size_t)n * BP);  // n
+  int* inR = used + n;                                     // n
+  double2* fcol = reinterpret_cast<double2*>(inR + n + (n & 1));  // n (16-byte aligned)
+  __shared__ int rp[BP];
+  __shared__ double redv[kGjThreads / 64];
+  __shared__ int redi[kGjThreads / 64];
+  __shared__ double2 pivinv;
+  const int tid = threadIdx.x;
+  const int b = min(BP, n - p0);
+
+  for (int idx = tid; idx < n * BP; idx += kGjThreads) {
+    const int row = idx / BP, col = idx - row * BP;
+    panel[idx] = (col < b) ? Min[(size_t)(p0 + col) * n + row] : make_double2(0.0, 0.0);
+  }
+  for (int i = tid; i < n; i += kGjThreads) {
+    used[i] = 0;
+    inR[i] = 0;
+  }
+  __syncthreads();
+  for (int p = tid; p < p0; p += kGjThreads) used[rowpiv[p]] = 1;
+  __syncthreads();
+
+  for (int t = 0; t < b; ++t) {
+    // pivot search over unused rows (ties -> smallest row index)
+    double bv = -1.0;
+    int bi = n;
+    for (int i = tid; i < n; i += kGjThreads)
+      if (!used[i]) argmax_merge(bv, bi, cabs2(panel[i * BP + t]), i);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(bv, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      argmax_merge(bv, bi, v2, i2);
+    }
+    if ((tid & 63) == 0) {
+      redv[tid >> 6] = bv;
+      redi[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = redv[0];
+      int i = redi[0];
+      for (int w = 1; w < kGjThreads / 64; ++w) argmax_merge(v, i, redv[w], redi[w]);
+      if (i >= n) i = 0;  // cannot happen for a valid permutation; keeps indices in range
+      rp[t] = i;
+      used[i] = 1;
+      inR[i] = 1;
+      double2 piv = panel[i * BP + t];
+      double a2 = cabs2(piv);
+      if (!(a2 > 0.0) || !isfinite(a2)) {
+        if (blockIdx.x == 0) *flag = 1;
+        piv = make_double2(1.0, 0.0);
+        a2 = 1.0;
+      }
+      pivinv = make_double2(piv.x / a2, -piv.y / a2);
+      if (blockIdx.x == 0) {
+        rowpiv[p0 + t] = i;
+        logpiv[p0 + t] = 0.5 * log(a2);
+      }
+    }
+    __syncthreads();
+    const int r = rp[t];
+    const double2 inv = pivinv;
+    // scale the pivot row; the eliminated entry becomes 1/piv
+    if (tid < BP) {
+      const double2 v = panel[r * BP + tid];
+      panel[r * BP + tid] = (tid == t) ? inv : cmul(v, inv);
+    }
+    __syncthreads();
+    // eliminate column t from every other row (multipliers staged first)
+    for (int i = tid; i < n; i += kGjThreads) fcol[i] = panel[i * BP + t];
+    __syncthreads();
+    for (int idx = tid; idx < n * BP; idx += kGjThreads) {
+      const int i = idx / BP, s = idx - i * BP;
+      if (i == r) continue;
+      const double2 base = (s == t) ? make_double2(0.0, 0.0) : panel[idx];
+      panel[idx] = csub(base, cmul(fcol[i], panel[r * BP + s]));
+    }
+    __syncthreads();
+  }
+
+  // workgroup 0 stores the factorised panel (G) into the output
+  if (blockIdx.x == 0) {
+    for (int idx = tid; idx < n * b; idx += kGjThreads) {
+      const int col = idx / n, row = idx - col * n;
+      Mout[(size_t)(p0 + col) * n + row] = panel[row * BP + col];
+    }
+  }
+  // trailing update of this workgroup's column tile
+  __shared__ double2 mr[kGjTile][BP];
+  const int j0 = blockIdx.x * kGjTile;
+  for (int jj = 0; jj < kGjTile; ++jj) {
+    const int j = j0 + jj;
+    if (tid < BP) {
+      mr[jj][tid] = (j < n && tid < b && !(j >= p0 && j < p0 + b)) ? Min[(size_t)j * n + rp[tid]]
+                                                                   : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  for (int jj = 0; jj < kGjTile; ++jj) {
+    const int j = j0 + jj;
+    if (j >= n || (j >= p0 && j < p0 + b)) continue;
+    for (int i = tid; i < n; i += kGjThreads) {
+      double2 acc = inR[i] ? make_double2(0.0, 0.0) : Min[(size_t)j * n + i];
+#pragma unroll
+      for (int s = 0; s < BP; ++s)
+        if (s < b) acc = cfma(panel[i * BP + s], mr[jj][s], acc);
+      Mout[(size_t)j * n + i] = acc;
+    }
+  }
+}
+
+// S <- (mu S + Ainv / mu) / 2 with Ainv[p][q] = M[r_p][rinv[q]]; accumulates
+// |S_new - S|^2 and |S_new|^2; the last workgroup writes the relative change
+// to scal[0], keeps it in scal[2] for the next scaling decision and scal[3] = mu.
+__global__ void __launch_bounds__(256)
+newton_combine_kernel(double2* __restrict__ S, const double2* __restrict__ M, int n,
+                      const int* __restrict__ rowpiv, const double* __restrict__ logpiv,
+                      double* __restrict__ scal, double* __restrict__ part, unsigned* __restrict__ counter,
+                      int nblk) {
+  extern __shared__ int rinv[];  // n
+  __shared__ double red[2][256];
+  __shared__ double mu_s;
+  __shared__ int is_last;
+  const int tid = threadIdx.x;
+  // rowpiv is a permutation unless a singular/non-finite pivot was flagged; the
+  // zero fill keeps every gathered index in range even then.
+  for (int q = tid; q < n; q += 256) rinv[q] = 0;
+  __syncthreads();
+  for (int p = tid; p < n; p += 256) {
+    const int r = rowpiv[p];
+    if (r >= 0 && r < n) rinv[r] = p;
+  }
+  if (tid == 0) {
+    double mu = 1.0;
+    if (scal[2] > 1e-2) {
+      double ld = 0.0;
+      for (int p = 0; p < n; ++p) ld += logpiv[p];
+      mu = exp(-ld / n);
+      if (!(mu > 0.0) || !isfinite(mu)) mu = 1.0;
+    }
+    mu_s = mu;
+  }
+  __syncthreads();
+  const double mu = mu_s, imu = 1.0 / mu;
+  double dsum = 0.0, ssum = 0.0;
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * 256 + tid; e < total; e += (size_t)gridDim.x * 256) {
+    const int q = (int)(e / n), p = (int)(e - (size_t)q * n);
+    const double2 s_old = S[e];
+    const int rp = min(max(rowpiv[p], 0), n - 1);
+    const double2 ai = M[(size_t)rinv[q] * n + rp];
+    const double2 s_new = make_double2(0.5 * (mu * s_old.x + imu * ai.x), 0.5 * (mu * s_old.y + imu * ai.y));
+    S[e] = s_new;
+    dsum += cabs2(csub(s_new, s_old));
+    ssum += cabs2(s_new);
+  }
+  red[0][tid] = dsum;
+  red[1][tid] = ssum;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      red[0][tid] += red[0][tid + off];
+      red[1][tid] += red[1][tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == (unsigned)nblk - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  if (tid == 0) {
+    double d = 0.0, s = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      d += part[2 * b];
+      s += part[2 * b + 1];
+    }
+    const double ch = sqrt(d / fmax(s, 1e-300));
+    scal[0] = ch;
+    scal[1] = sqrt(s);
+    scal[2] = ch;
+    scal[3] = mu;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void copy_mat_kernel(const double2* __restrict__ A, int lda, double2* __restrict__ B, int ldb, int rows,
+                                int cols) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rows * cols) return;
+  const int c = (int)(e / rows), r = (int)(e - (size_t)c * rows);
+  B[(size_t)c * ldb + r] = A[(size_t)c * lda + r];
+}
+
+__global__ void zero_kernel(double2* __restrict__ p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void set_scal_kernel(double* scal, int* flag) {
+  scal[0] = 1e30;
+  scal[1] = 0.0;
+  scal[2] = 1e30;
+  scal[3] = 1.0;
+  *flag = 0;
+}
+
+// c[i] = sum_{q<m} F[i][q] c0[q] + beta F[i][m];  err = |c - [cprev; 0]| / |c|
+__global__ void __launch_bounds__(256)
+coeffs_kernel(int n, int m, const double2* __restrict__ F, int ldf, const double2* __restrict__ c0,
+              const double* __restrict__ beta, double2* __restrict__ c, const double2* __restrict__ cprev,
+              int nprev, double* __restrict__ err) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  const double b = *beta;
+  double dsum = 0.0, csum = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < m; ++q) acc = cfma(F[(size_t)q * ldf + i], c0[q], acc);
+    if (m < n) acc = cadd(acc, cscale(F[(size_t)m * ldf + i], b));
+    c[i] = acc;
+    const double2 prev = (cprev && i < nprev) ? cprev[i] : make_double2(0.0, 0.0);
+    dsum += cabs2(csub(acc, prev));
+    csum += cabs2(acc);
+  }
+  red[0][tid] = dsum;
+  red[1][tid] = csum;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      red[0][tid] += red[0][tid + off];
+      red[1][tid] += red[1][tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && err) *err = cprev ? sqrt(red[0][0] / fmax(red[1][0], 1e-300)) : 1e30;
+}
+
+__global__ void negate_kernel(const double2* __restrict__ in, double2* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cneg(in[i]);
+}
+
+__global__ void finite_kernel(const double2* __restrict__ v, size_t n, int* __restrict__ flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double2 a = v[i];
+    if (!isfinite(a.x) || !isfinite(a.y)) *flag = 1;
+  }
+}
+
+template <int BP>
+void launch_panel(const double2* Min, double2* Mout, int n, int p0, DenseWork& d, hipStream_t s) {
+  const size_t lds = gj_lds_bytes(n, BP);
+  static size_t configured = 0;
+  if (lds > configured) {
+    SGN_HIP(hipFuncSetAttribute((const void*)gj_panel_kernel<BP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    configured = lds;
+  }
+  const int nblk = (n + kGjTile - 1) / kGjTile;
+  hipLaunchKernelGGL(gj_panel_kernel<BP>, dim3(nblk), dim3(kGjThreads), lds, s, Min, Mout, n, p0, d.rowpiv,
+                     d.logpiv, d.flag);
+}
+
+}  // namespace
+
+static size_t lds_budget() {
+  static size_t cached = 0;
+  if (!cached) {
+    int dev = 0, v = 0;
+    SGN_HIP(hipGetDevice(&dev));
+    SGN_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // leave room for the kernel's static LDS arrays
+    cached = (size_t)std::max(v, 16384) - 2048;
+  }
+  return cached;
+}
+
+static int panel_width(int n) {
+  const size_t budget = lds_budget();
+  for (int bp : {16, 8, 4, 2}) {
+    if (gj_lds_bytes(n, bp) <= budget) return bp;
+  }
+  return 0;
+}
+
+void dense_alloc(DenseWork& d, int n) {
+  if (n <= d.ncap) return;
+  dense_free(d);
+  d.ncap = n;
+  const size_t nn = (size_t)n * n;
+  SGN_HIP(hipMalloc(&d.S, sizeof(double2) * nn));
+  SGN_HIP(hipMalloc(&d.Ma, sizeof(double2) * nn));
+  SGN_HIP(hipMalloc(&d.Mb, sizeof(double2) * nn));
+  SGN_HIP(hipMalloc(&d.rowpiv, sizeof(int) * (size_t)n));
+  SGN_HIP(hipMalloc(&d.logpiv, sizeof(double) * (size_t)n));
+  SGN_HIP(hipMalloc(&d.scal, sizeof(double) * 8));
+  SGN_HIP(hipHostMalloc(&d.host_scal, sizeof(double) * 8, hipHostMallocDefault));
+  SGN_HIP(hipMalloc(&d.flag, sizeof(int) * 2));
+  SGN_HIP(hipMalloc(&d.counters, sizeof(unsigned) * 4));
+  SGN_HIP(hipMemset(d.counters, 0, sizeof(unsigned) * 4));
+  d.npart = 1024;
+  SGN_HIP(hipMalloc(&d.part, sizeof(double) * 2 * (size_t)d.npart));
+  SGN_HIP(hipDeviceSynchronize());
+}
+
+void dense_free(DenseWork& d) {
+  if (d.S) (void)hipFree(d.S);
+  if (d.Ma) (void)hipFree(d.Ma);
+  if (d.Mb) (void)hipFree(d.Mb);
+  if (d.rowpiv) (void)hipFree(d.rowpiv);
+  if (d.logpiv) (void)hipFree(d.logpiv);
+  if (d.scal) (void)hipFree(d.scal);
+  if (d.host_scal) (void)hipHostFree(d.host_scal);
+  if (d.flag) (void)hipFree(d.flag);
+  if (d.counters) (void)hipFree(d.counters);
+  if (d.part) (void)hipFree(d.part);
+  d = DenseWork{};
+}
+
+void dev_zero(double2* p, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  SGN_HIP(hipGetLastError());
+}
+
+void dev_copy_mat(const double2* A, int lda, double2* B, int ldb, int rows, int cols, hipStream_t s) {
+  const size_t tot = (size_t)rows * cols;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(copy_mat_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A, lda, B, ldb, rows,
+                     cols);
+  SGN_HIP(hipGetLastError());
+}
+
+void dev_negate(const double2* in, double2* out, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(negate_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+  SGN_HIP(hipGetLastError());
+}
+
+void dev_check_finite(const double2* v, size_t n, int* flag, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(finite_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, flag);
+  SGN_HIP(hipGetLastError());
+}
+
+void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, const double* beta, double2* c,
+                  const double2* cprev, int nprev, double* err, hipStream_t s) {
+  hipLaunchKernelGGL(coeffs_kernel, dim3(1), dim3(256), 0, s, n, m, F, ldf, c0, beta, c, cprev, nprev, err);
+  SGN_HIP(hipGetLastError());
+}
+
+int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
+               Profiler* prof) {
+  SGN_REQUIRE(n >= 1, SGN_EINVAL, "dense_sign: n must be positive");
+  const int bp = panel_width(n);
+  SGN_REQUIRE(bp > 0, SGN_EINVAL, "dense_sign: matrix too large for the LDS panel");
+  dense_alloc(d, n);
+  dev_copy_mat(A, lda, d.S, n, n, n, s);
+  hipLaunchKernelGGL(set_scal_kernel, dim3(1), dim3(1), 0, s, d.scal, d.flag);
+  SGN_HIP(hipGetLastError());
+  const int npanel = (n + bp - 1) / bp;
+  const int nblk_comb = (int)std::min<size_t>((size_t)d.npart, ((size_t)n * n + 255) / 256);
+  const int maxit = 100;
+  double prev = 1e30;
+  int done_extra = -1;
+  for (int it = 1; it <= maxit; ++it) {
+    const int idx = prof ? prof->begin(K_GJ_PANEL) : -1;
+    const double2* Min = d.S;
+    double2* bufs[2] = {d.Ma, d.Mb};
+    for (int pi = 0; pi < npanel; ++pi) {
+      double2* Mout = bufs[pi & 1];
+      switch (bp) {
+        case 16: launch_panel<16>(Min, Mout, n, pi * bp, d, s); break;
+        case 8: launch_panel<8>(Min, Mout, n, pi * bp, d, s); break;
+        case 4: launch_panel<4>(Min, Mout, n, pi * bp, d, s); break;
+        default: launch_panel<2>(Min, Mout, n, pi * bp, d, s); break;
+      }
+      SGN_HIP(hipGetLastError());
+      Min = Mout;
+    }
+    if (prof) prof->end(idx, 2.0 * 16.0 * (double)n * n * npanel, 8.0 * (double)n * n * n);
+    const int idx2 = prof ? prof->begin(K_NEWTON_COMBINE) : -1;
+    hipLaunchKernelGGL(newton_combine_kernel, dim3(nblk_comb), dim3(256), sizeof(int) * (size_t)n, s, d.S, Min, n,
+                       d.rowpiv, d.logpiv, d.scal, d.part, d.counters, nblk_comb);
+    SGN_HIP(hipGetLastError());
+    if (prof) prof->end(idx2, 3.0 * 16.0 * (double)n * n, 10.0 * (double)n * n);
+    SGN_HIP(hipMemcpyAsync(d.host_scal, d.scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+    int hflag = 0;
+    SGN_HIP(hipMemcpyAsync(&d.host_scal[4], d.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    std::memcpy(&hflag, &d.host_scal[4], sizeof(int));
+    if (hflag) throw SgnError{SGN_ESINGULAR, "Roberts iteration met a singular iterate"};
+    const double ch = d.host_scal[0];
+    if (!std::isfinite(ch)) throw SgnError{SGN_ESINGULAR, "Roberts iteration diverged (non-finite iterate)"};
+    if (done_extra >= 0) {
+      dev_copy_mat(d.S, n, F, ldf, n, n, s);
+      return it;
+    }
+    // converged (or stagnated at rounding level): one more step settles the last digits
+    if (ch <= 1e-13 || (it > 4 && ch < 1e-9 && ch > 0.5 * prev)) done_extra = it;
+    prev = ch;
+  }
+  throw SgnError{SGN_ESINGULAR, "Roberts iteration did not converge in 100 steps"};
+}

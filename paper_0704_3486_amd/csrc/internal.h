@@ -1,0 +1,178 @@
+// Internal declarations shared by the HIP translation units of libsgn.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sgn.h"
+
+// ----------------------------------------------------------------------------
+// complex helpers (double2 = re, im)
+// ----------------------------------------------------------------------------
+__host__ __device__ inline double2 cmake(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline double2 cmulc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// acc + a * b
+__host__ __device__ inline double2 cfma(double2 a, double2 b, double2 acc) {
+  return make_double2(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+// acc + conj(a) * b
+__host__ __device__ inline double2 cfmac(double2 a, double2 b, double2 acc) {
+  return make_double2(acc.x + a.x * b.x + a.y * b.y, acc.y + a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// i * a
+__host__ __device__ inline double2 cmuli(double2 a) { return make_double2(-a.y, a.x); }
+__host__ __device__ inline double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
+
+// ----------------------------------------------------------------------------
+// status helpers
+// ----------------------------------------------------------------------------
+struct SgnError {
+  int status;
+  std::string msg;
+};
+
+#define SGN_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw SgnError{SGN_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)};     \
+  } while (0)
+
+#define SGN_REQUIRE(cond, st, msg)                 \
+  do {                                             \
+    if (!(cond)) throw SgnError{(st), (msg)};      \
+  } while (0)
+
+// ----------------------------------------------------------------------------
+// kernel profiling (HIP events on the context stream)
+// ----------------------------------------------------------------------------
+enum KClass {
+  K_WILSON = 0,
+  K_GS_DOT,
+  K_GS_UPDATE,
+  K_GJ_PANEL,
+  K_NEWTON_COMBINE,
+  K_MISC,
+  K_NCLASS
+};
+
+struct Profiler {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  long long launches[K_NCLASS] = {};
+  double ms[K_NCLASS] = {};
+  double bytes[K_NCLASS] = {};
+  double flops[K_NCLASS] = {};
+  struct Pending {
+    hipEvent_t a, b;
+    int cls;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get_event();
+  // bracket a launch: returns index of pending record or -1
+  int begin(int cls);
+  void end(int idx, double nbytes, double nflops);
+  void flush();  // synchronise and accumulate the pending durations
+  void reset();
+  ~Profiler();
+};
+
+// ----------------------------------------------------------------------------
+// device workspace for Gram-Schmidt passes
+// ----------------------------------------------------------------------------
+struct GsWork {
+  int nrt_dot = 0;      // row tiles of the dot kernel
+  int nrt_upd = 0;      // row tiles of the update kernel
+  int ncol_cap = 0;     // max columns
+  double2* P = nullptr;      // dot partials [nrt_dot][ncol_cap]
+  double2* Upart = nullptr;  // update partials [ngroups][ldq]
+  int ngroups_cap = 0;
+  double* normpart = nullptr;  // [nrt_upd]
+  unsigned* counters = nullptr;  // zero-initialised, reset by the kernels
+  int ncounters = 0;
+};
+
+// GS kernels (gs.hip)
+void gs_alloc(GsWork& g, int N, size_t ldq, int ncol_cap);
+void gs_free(GsWork& g);
+// h[c] = sum_i conj(Q[c][i]) w[i], c < ncol
+void gs_dot(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* w, double2* h,
+            hipStream_t s, Profiler* prof);
+// w -= Q h ; if fin: also hout[c] = h1[c] + h[c] (h1 may be null), beta = |w|, inv_beta = 1/beta,
+// breakdown flag when beta <= tiny * |hout|
+struct GsFinal {
+  const double2* h1;  // first-pass coefficients (nullable)
+  double2* hout;      // ncol+1 outputs: sums, then beta as complex at hout[ncol] (nullable)
+  double* beta;       // device scalar (nullable)
+  double* inv_beta;   // device scalar (nullable)
+  int* flag;          // device int: set to 1 on breakdown / non-finite (nullable)
+};
+// kval: Krylov dimension completed by this pass; a breakdown records flag = kval + 1
+void gs_update(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* h, double2* w,
+               const GsFinal* fin, int kval, hipStream_t s, Profiler* prof);
+// beta = |w|, inv_beta = 1/beta (single vector, no projection)
+void gs_norm(const GsWork& g, int N, const double2* w, double* beta, double* inv_beta, int* flag,
+             hipStream_t s, Profiler* prof);
+
+// Wilson kernels (wilson.hip)
+struct Lattice {
+  int L[4];
+  int V;
+  double kappa;
+  double emu, emmu;  // e^{+mu}, e^{-mu}
+};
+void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, hipStream_t s);
+void wilson_pack(const Lattice& lat, const double2* x_abi, double2* v, hipStream_t s);
+void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStream_t s);
+// out = H_w(mu) (in * scale), optional copy_out = in * scale; scale = *inv_beta (or 1 if null)
+void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
+                  const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);
+
+// dense kernels (dense.hip)
+struct DenseWork {
+  int ncap = 0;
+  double2* S = nullptr;   // n x n iterate
+  double2* Ma = nullptr;  // Gauss-Jordan ping-pong
+  double2* Mb = nullptr;
+  int* rowpiv = nullptr;  // pivot row of each column
+  double* logpiv = nullptr;
+  double* scal = nullptr;  // [0] change, [1] |S|, [2] prev change, [3] mu
+  double* host_scal = nullptr;  // pinned mirror
+  int* flag = nullptr;          // singular flag
+  unsigned* counters = nullptr;
+  double* part = nullptr;  // reduction partials
+  int npart = 0;
+};
+void dense_alloc(DenseWork& d, int n);
+void dense_free(DenseWork& d);
+// F = sgn(A) (n x n, ld = lda); returns iterations; throws SGN_ESINGULAR
+int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
+               Profiler* prof);
+// c[i] = sum_{q<m} F[i][q] c0[q] + beta * F[i][m]  (i < n); err = |c - cprev_pad| / |c| if cprev
+void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, const double* beta, double2* c,
+                  const double2* cprev, int nprev, double* err, hipStream_t s);
+// zero a device vector
+void dev_zero(double2* p, size_t n, hipStream_t s);
+void dev_copy_mat(const double2* A, int lda, double2* B, int ldb, int rows, int cols, hipStream_t s);
+// y = sum_c Q[c] coef[c]  (fresh output)
+void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* coef,
+                double2* y, double2* scratch_neg, hipStream_t s, Profiler* prof);
+// vector scale in place: v[i] *= a (device scalar pointer)
+void dev_negate(const double2* in, double2* out, int n, hipStream_t s);
+// any non-finite entry -> flag = 1
+void dev_check_finite(const double2* v, size_t n, int* flag, hipStream_t s);
