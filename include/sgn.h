@@ -61,6 +61,15 @@ enum {
 
 enum { SGN_PREC_FP64 = 0, SGN_PREC_MIXED = 1 };
 
+/* Orthogonalisation of step (iv).  Both orthogonalise every new vector
+ * against the Schur vectors and all previous Arnoldi vectors twice (classical
+ * Gram-Schmidt with one re-orthogonalisation); they differ in scheduling:
+ *   SGN_ORTH_CGS2:    two passes per step (four sweeps over the basis);
+ *   SGN_ORTH_DELAYED: the re-orthogonalisation of v_j is merged with the
+ *                     first pass of v_{j+1} (one reduction, two sweeps over
+ *                     the basis per step; the default). */
+enum { SGN_ORTH_CGS2 = 0, SGN_ORTH_DELAYED = 1 };
+
 /* Per-apply statistics (sgn_last_info). */
 typedef struct sgn_info {
   int k_used;         /* Krylov dimension of the returned approximation */
@@ -99,6 +108,20 @@ int sgn_get_dims(const sgn_ctx* ctx, int dims[4], long long* n);
 
 /* ---- deflation (Section 5.2, steps (i)-(ii)) ------------------------- */
 
+/* Compute and install the partial Schur pair of the m critical eigenvalues
+ * (smallest |Re lambda|) of H_w(mu) on the device (Section 5.2, steps (i)-(ii);
+ * Results section): Arnoldi on H_w^2 for its smallest-magnitude eigenvalues
+ * with thick restarts, a Rayleigh-Ritz step with H_w on the converged span,
+ * selection by |Re lambda|, S_m = orthonormalised eigenvectors, T_m =
+ * S_m^dag A S_m, then sgn(T_m) by Roberts' iteration.  m = 0 removes
+ * deflation.  SGN_EDEFL if ||A S - S T||_F / ||A|| > 1e-10 or the eigensolver
+ * does not converge.  Requires 0 <= m <= N/4. */
+int sgn_deflate(sgn_ctx* ctx, int m);
+
+/* Statistics of the last sgn_deflate: restarts, applications of H_w(mu),
+ * and the relative Schur residual ||A S - S T||_F / ||A||. */
+int sgn_deflate_stats(const sgn_ctx* ctx, int* restarts, int* matvecs, double* residual);
+
 /* Install a partial Schur pair A S = S T (Eq. pSd) computed elsewhere.
  * S: device complex128, column-major N x m, orthonormal columns;
  * T: host complex128, column-major m x m, upper triangular (the strictly
@@ -126,6 +149,17 @@ int sgn_apply(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
 /* Fixed Krylov dimension: exactly k modified Arnoldi steps (fewer only on an
  * exact breakdown), then steps (v)-(vi) once.  k >= 0. */
 int sgn_apply_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
+
+/* Arithmetic of the Krylov loop.  SGN_PREC_FP64 (default): everything FP64.
+ * SGN_PREC_MIXED: the links, the stencil and the stored Krylov vectors v_j are
+ * FP32; the Schur vectors S_m, the candidate vector being orthogonalised,
+ * every dot product, the re-orthogonalisation, the composite matrix H, its
+ * sign (Roberts) and the assembly of y stay FP64 (always the delayed
+ * schedule).  x and y stay complex128 at the ABI. */
+int sgn_set_precision(sgn_ctx* ctx, int prec);
+
+/* Select the orthogonalisation schedule (SGN_ORTH_*); default DELAYED. */
+int sgn_set_orthogonalization(sgn_ctx* ctx, int mode);
 
 /* Statistics of the last sgn_apply / sgn_apply_fixed. */
 int sgn_last_info(const sgn_ctx* ctx, sgn_info* info);
@@ -161,6 +195,13 @@ typedef struct sgn_kstat {
 /* Copy up to max entries of the accumulated statistics; returns the count. */
 int sgn_profile_read(const sgn_ctx* ctx, sgn_kstat* out, int max);
 int sgn_profile_reset(sgn_ctx* ctx);
+
+/* Host-only helper (no GPU needed): eigenvalues w (n complex) and unit-norm
+ * right eigenvectors V (n x n column-major) of a dense complex n x n matrix
+ * A (column-major), by Householder-Hessenberg reduction and shifted QR.  This
+ * is the small eigensolver of the deflation setup.  SGN_ESINGULAR if the QR
+ * iteration does not converge. */
+int sgn_host_eig(int n, const double* A, double* w, double* V);
 
 /* ---- errors ------------------------------------------------------------ */
 const char* sgn_strerror(int status);

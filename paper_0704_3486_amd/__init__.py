@@ -29,6 +29,8 @@ SGN_ENOCONV = -4
 SGN_ESINGULAR = -5
 SGN_ESTATE = -6
 SGN_EDEFL = -7
+SGN_ORTH_CGS2 = 0
+SGN_ORTH_DELAYED = 1
 SGN_PREC_FP64 = 0
 SGN_PREC_MIXED = 1
 
@@ -59,7 +61,7 @@ class SgnError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
-            f"{LIB_PATH} is missing: build it first (python -m paper_0704_3486_amd.build); "
+            f"{LIB_PATH} is missing: build it first (python paper_0704_3486_amd/build.py); "
             "there is no fallback implementation")
     lib = C.CDLL(LIB_PATH)
     vp, i, d, cp = C.c_void_p, C.c_int, C.c_double, C.c_char_p
@@ -81,6 +83,11 @@ def _load():
         "sgn_set_profiling": (i, [vp, i]),
         "sgn_profile_read": (i, [vp, C.POINTER(sgn_kstat), i]),
         "sgn_profile_reset": (i, [vp]),
+        "sgn_deflate": (i, [vp, i]),
+        "sgn_set_orthogonalization": (i, [vp, i]),
+        "sgn_set_precision": (i, [vp, i]),
+        "sgn_deflate_stats": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
+        "sgn_host_eig": (i, [i, vp, vp, vp]),
         "sgn_strerror": (cp, [i]),
         "sgn_last_error": (cp, [vp]),
     }
@@ -163,6 +170,17 @@ def sgn_get_dims(ctx):
     return tuple(d), int(n.value)
 
 
+def sgn_deflate(ctx, m):
+    """Compute and install the m critical Schur vectors on the device."""
+    return _check(ctx, _lib.sgn_deflate(ctx, int(m)))
+
+
+def sgn_deflate_stats(ctx):
+    r, mv, res = C.c_int(), C.c_int(), C.c_double()
+    _check(ctx, _lib.sgn_deflate_stats(ctx, C.byref(r), C.byref(mv), C.byref(res)))
+    return {"restarts": r.value, "matvecs": mv.value, "residual": res.value}
+
+
 def sgn_deflate_import(ctx, S, T):
     """Install (S, T): S a GPU tensor (N, m) in column order (S.T contiguous), T host (m, m)."""
     import torch
@@ -211,6 +229,14 @@ def sgn_apply(ctx, x, y, tol, kmax):
 def sgn_apply_fixed(ctx, x, y, k):
     _, N = sgn_get_dims(ctx)
     return _check(ctx, _lib.sgn_apply_fixed(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), int(k)))
+
+
+def sgn_set_precision(ctx, prec):
+    return _check(ctx, _lib.sgn_set_precision(ctx, int(prec)))
+
+
+def sgn_set_orthogonalization(ctx, mode):
+    return _check(ctx, _lib.sgn_set_orthogonalization(ctx, int(mode)))
 
 
 def sgn_last_info(ctx):

@@ -1,8 +1,8 @@
 """Build libsgn.so (the HIP/gfx950 implementation behind include/sgn.h).
 
-    python -m paper_0704_3486_amd.build        # or build() from Python
+    python paper_0704_3486_amd/build.py        # or __graft_entry__.build()
 
-Every .hip file under csrc/ is compiled for gfx950 with hipcc into an object
+Every .hip / .cpp file under csrc/ is compiled for gfx950 with hipcc into an object
 under _build/, then linked into paper_0704_3486_amd/libsgn.so.  Packed FP32
 instructions are disabled for all device code.
 """
@@ -25,12 +25,13 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas",
+    "-fcx-limited-range",
     "-I", os.path.join(ROOT, "include"),
 ]
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src):

@@ -24,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "context.h"
 
 // ---------------------------------------------------------------------------
 // profiler
@@ -96,129 +96,9 @@ static const char* kclass_name(int c) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-struct sgn_ctx {
-  Lattice lat{};
-  int N = 0;
-  size_t ldq = 0;
-  double mu = 0, m_w = 0;
-  hipStream_t stream = nullptr;
-  std::string last_error;
-  sgn_info info{};
-  Profiler prof;
-
-  double2* links = nullptr;  // [4][9][V]
-
-  // deflation
-  int m = 0;
-  double2* S = nullptr;       // internal layout, ldq x m
-  std::vector<double2> T;     // host m x m (column-major, upper triangular)
-  double2* Tdev = nullptr;    // m x m
-  double2* sgnT = nullptr;    // m x m
-
-  // Krylov workspace
-  int kcap = 0;               // capacity in Krylov vectors
-  int ncap = 0;               // m + kcap + 1 (columns of Q, rows of H)
-  double2* Q = nullptr;       // ldq x ncap
-  double2* Hc = nullptr;      // ncap x ncap, column-major (ld = ncap)
-  double2* F = nullptr;       // sign output (m + kcap)^2, ld = n
-  double2* wA = nullptr;
-  double2* wB = nullptr;
-  double2* xin = nullptr;
-  double2* hbuf1 = nullptr;
-  double2* hbuf2 = nullptr;
-  double2* c0 = nullptr;
-  double2* cvec = nullptr;
-  double2* cprev = nullptr;
-  double* scal = nullptr;     // [0] beta0 [1] inv_beta [2] err [3] scratch
-  int* flag = nullptr;        // [0] breakdown/finite flag
-  double* hpin = nullptr;     // pinned host mirror
-  GsWork gs;
-  DenseWork dense;
-
-  ~sgn_ctx() { release(); }
-
-  void release_workspace() {
-    for (double2** p : {&Q, &Hc, &F, &wA, &wB, &xin, &hbuf1, &hbuf2, &c0, &cvec, &cprev})
-      if (*p) {
-        (void)hipFree(*p);
-        *p = nullptr;
-      }
-    gs_free(gs);
-    kcap = 0;
-    ncap = 0;
-  }
-
-  void release() {
-    if (stream || true) (void)hipDeviceSynchronize();
-    release_workspace();
-    dense_free(dense);
-    for (double2** p : {&links, &S, &Tdev, &sgnT})
-      if (*p) {
-        (void)hipFree(*p);
-        *p = nullptr;
-      }
-    if (scal) (void)hipFree(scal);
-    if (flag) (void)hipFree(flag);
-    if (hpin) (void)hipHostFree(hpin);
-    scal = nullptr;
-    flag = nullptr;
-    hpin = nullptr;
-  }
-
-  // make sure the Krylov workspace holds m + kmax + 1 columns
-  void ensure_workspace(int kmax) {
-    if (kmax <= kcap && Q) return;
-    release_workspace();
-    kcap = kmax;
-    ncap = m + kcap + 1;
-    SGN_HIP(hipMalloc(&Q, sizeof(double2) * ldq * (size_t)ncap));
-    SGN_HIP(hipMalloc(&Hc, sizeof(double2) * (size_t)ncap * ncap));
-    SGN_HIP(hipMalloc(&F, sizeof(double2) * (size_t)(m + kcap) * (m + kcap)));
-    SGN_HIP(hipMalloc(&wA, sizeof(double2) * ldq));
-    SGN_HIP(hipMalloc(&wB, sizeof(double2) * ldq));
-    SGN_HIP(hipMalloc(&xin, sizeof(double2) * ldq));
-    SGN_HIP(hipMalloc(&hbuf1, sizeof(double2) * (size_t)ncap));
-    SGN_HIP(hipMalloc(&hbuf2, sizeof(double2) * (size_t)ncap));
-    SGN_HIP(hipMalloc(&c0, sizeof(double2) * (size_t)(m > 0 ? m : 1)));
-    SGN_HIP(hipMalloc(&cvec, sizeof(double2) * (size_t)ncap));
-    SGN_HIP(hipMalloc(&cprev, sizeof(double2) * (size_t)ncap));
-    gs_alloc(gs, N, ldq, ncap);
-    // the Schur block of Q and of H never changes between applies
-    if (m > 0) {
-      SGN_HIP(hipMemcpy2D(Q, ldq * sizeof(double2), S, ldq * sizeof(double2), ldq * sizeof(double2), m,
-                          hipMemcpyDeviceToDevice));
-    }
-    SGN_HIP(hipMemset(Hc, 0, sizeof(double2) * (size_t)ncap * ncap));
-    if (m > 0) dev_copy_mat(Tdev, m, Hc, ncap, m, m, nullptr);
-    SGN_HIP(hipDeviceSynchronize());
-  }
-};
-
 namespace {
 
 thread_local std::string g_create_error;
-
-int fail(sgn_ctx* c, const SgnError& e) {
-  if (c) c->last_error = e.msg;
-  return e.status;
-}
-
-template <class F>
-int guarded(sgn_ctx* c, F&& f) {
-  if (!c) return SGN_ESTATE;
-  try {
-    return f();
-  } catch (const SgnError& e) {
-    return fail(c, e);
-  } catch (const std::bad_alloc&) {
-    return fail(c, SgnError{SGN_ENOMEM, "host allocation failed"});
-  } catch (...) {
-    return fail(c, SgnError{SGN_EHIP, "unexpected error"});
-  }
-}
 
 int even_up(int k) { return (k + 1) & ~1; }
 
@@ -257,21 +137,48 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   const int kwant = fixed_k >= 0 ? fixed_k : kmax;
   c->ensure_workspace(std::max(kwant, 2));
   const int ncap = c->ncap;
+  const bool mixed = (c->prec == SGN_PREC_MIXED);
+  const bool delayed = mixed || (c->orth == SGN_ORTH_DELAYED);
   sgn_info info{};
   double ms_sign = 0.0;
+
+  // argument block of the one-reduction step (krylov.hip)
+  KrylovArgs ka;
+  ka.N = N;
+  ka.ldq = ldq;
+  ka.m = m;
+  ka.S = c->Q;
+  ka.V = mixed ? (void*)c->V32 : (void*)(c->Q + (size_t)m * ldq);
+  ka.H = c->Hc;
+  ka.ldh = ncap;
+  ka.c0 = c->c0;
+  ka.beta = &c->scal[0];
+  ka.flag = c->flag;
+  double2* ucur = c->wA;   // FP64 candidate
+  double2* unext = c->wC;
+  float2* u32cur = c->u32a;
+  float2* u32next = c->u32b;
 
   // step (iii): x_perp = (1 - S S^dag) x, beta = |x_perp|
   SGN_HIP(hipMemsetAsync(c->flag, 0, sizeof(int) * 2, s));
   wilson_pack(c->lat, x_abi, c->xin, s);
   dev_check_finite(c->xin, (size_t)N, c->flag + 1, s);
   SGN_HIP(hipMemcpyAsync(c->wA, c->xin, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
-  if (m > 0) {
+  if (delayed) {
+    // one pass against S now; its re-orthogonalisation is folded into step 0
+    gs_norm(c->gs, N, c->xin, &c->scal[5], &c->scal[6], nullptr, s, prof);
+    SGN_HIP(hipMemcpyAsync(c->kw.sc + kScRef, &c->scal[5], sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (m > 0) {
+      gs_dot(c->gs, c->Q, ldq, N, m, c->wA, c->c0, s, prof);
+      gs_update(c->gs, c->Q, ldq, N, m, c->c0, c->wA, nullptr, 0, s, prof);
+    }
+    if (mixed) dev_to_f32(c->wA, u32cur, (size_t)N, s);
+  } else if (m > 0) {
     gs_dot(c->gs, c->Q, ldq, N, m, c->wA, c->hbuf1, s, prof);
     gs_update(c->gs, c->Q, ldq, N, m, c->hbuf1, c->wA, nullptr, 0, s, prof);
     gs_dot(c->gs, c->Q, ldq, N, m, c->wA, c->hbuf2, s, prof);
-    GsFinal fin{c->hbuf1, c->hbuf2 /*unused*/, &c->scal[0], &c->scal[1], c->flag};
-    // c0 = h1 + h2 goes to the c0 buffer (m entries + beta slot -> use hbuf2 scratch)
-    fin.hout = c->cvec;
+    // c0 = h1 + h2 (m entries; the beta slot lands in cvec[m])
+    GsFinal fin{c->hbuf1, c->cvec, &c->scal[0], &c->scal[1], c->flag};
     gs_update(c->gs, c->Q, ldq, N, m, c->hbuf2, c->wA, &fin, 0, s, prof);
     SGN_HIP(hipMemcpyAsync(c->c0, c->cvec, sizeof(double2) * m, hipMemcpyDeviceToDevice, s));
   } else {
@@ -283,9 +190,9 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   int hflag[2];
   std::memcpy(hflag, &c->hpin[4], sizeof(int) * 2);
   if (hflag[1] != 0 || hflag[0] < 0) throw SgnError{SGN_EINVAL, "x contains NaN or Inf"};
-  const double beta0 = c->hpin[0];
-  info.beta = beta0;
-  const bool x_in_schur = (hflag[0] == 1);  // beta == 0 relative to |S^dag x|
+  // the two-pass schedule knows x_perp already; the delayed one finds x_perp = 0
+  // as a breakdown of step 0
+  const bool x_in_schur = !delayed && (hflag[0] == 1);
 
   int k = 0;
   bool converged = false;
@@ -302,7 +209,21 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     const int n = m + kk;
     const auto t0 = std::chrono::steady_clock::now();
     int it = 0;
-    if (n > 0) it = dense_sign(c->dense, n, c->Hc, ncap, c->F, n, s, prof);
+    if (n > 0) {
+      if (delayed && kk > 0) {
+        // finish the re-orthogonalisation of the last column, on a copy
+        ka.J = n;
+        ka.u = ucur;
+        if (mixed)
+          krylov_dot<float2>(c->kw, ka, 1, false, false, s, prof);
+        else
+          krylov_dot<double2>(c->kw, ka, 1, false, false, s, prof);
+        krylov_patch(c->kw, ka, 1, n, c->F, 0, true, s);
+        it = dense_sign(c->dense, n, c->F, n, c->F, n, s, prof);
+      } else {
+        it = dense_sign(c->dense, n, c->Hc, ncap, c->F, n, s, prof);
+      }
+    }
     newton_total += it;
     dense_coeffs(n, m, c->F, n, c->c0, &c->scal[0], c->cvec, nprev >= 0 ? c->cprev : nullptr,
                  nprev >= 0 ? nprev : 0, &c->scal[2], s);
@@ -319,9 +240,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   if (x_in_schur || kwant == 0) {
     // y = S sgn(T) S^dag x exactly (no Krylov part), or k = 0 requested
     SGN_HIP(hipMemsetAsync(&c->scal[0], 0, sizeof(double), s));
-    if (m > 0) {
-      err = checkpoint(0);
-    }
+    if (m > 0) err = checkpoint(0);
     converged = true;
     breakdown = x_in_schur;
   } else {
@@ -332,18 +251,41 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     } else {
       next_ck = std::min(kmax, std::max(2, even_up(std::min(32, kmax / 2))));
     }
-    double2* wprev = c->wA;  // holds x_perp (unnormalised) for j = 0
+    double2* wprev = c->wA;  // two-pass schedule: x_perp (unnormalised) for j = 0
     double2* wcur = c->wB;
     for (int j = 0; j < kwant; ++j) {
-      double2* vcol = c->Q + (size_t)(m + j) * ldq;
-      wilson_apply(c->lat, c->links, wprev, wcur, &c->scal[1], vcol, s, prof);
-      const int ncol = m + j + 1;
-      gs_dot(c->gs, c->Q, ldq, N, ncol, wcur, c->hbuf1, s, prof);
-      gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf1, wcur, nullptr, 0, s, prof);
-      gs_dot(c->gs, c->Q, ldq, N, ncol, wcur, c->hbuf2, s, prof);
-      GsFinal fin{c->hbuf1, c->Hc + (size_t)(m + j) * ncap, nullptr, &c->scal[1], c->flag};
-      gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf2, wcur, &fin, j + 1, s, prof);
-      std::swap(wprev, wcur);
+      const int J = m + j;
+      if (delayed) {
+        ka.J = J;
+        ka.j = j;
+        ka.u = ucur;
+        ka.unext = unext;
+        if (mixed) {
+          wilson_apply_multi32(c->lat, c->links32, u32cur, 0, c->z32, 0, 1, s, prof);
+          ka.z = c->z32;
+          ka.ulonext = u32next;
+          krylov_dot<float2>(c->kw, ka, 1, true, true, s, prof);
+          krylov_update<float2>(c->kw, ka, 1, s, prof);
+          std::swap(u32cur, u32next);
+        } else {
+          wilson_apply(c->lat, c->links, ucur, c->wB, nullptr, nullptr, s, prof);
+          ka.z = c->wB;
+          ka.ulonext = nullptr;
+          krylov_dot<double2>(c->kw, ka, 1, true, true, s, prof);
+          krylov_update<double2>(c->kw, ka, 1, s, prof);
+        }
+        std::swap(ucur, unext);
+      } else {
+        double2* vcol = c->Q + (size_t)J * ldq;
+        wilson_apply(c->lat, c->links, wprev, wcur, &c->scal[1], vcol, s, prof);
+        const int ncol = J + 1;
+        gs_dot(c->gs, c->Q, ldq, N, ncol, wcur, c->hbuf1, s, prof);
+        gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf1, wcur, nullptr, 0, s, prof);
+        gs_dot(c->gs, c->Q, ldq, N, ncol, wcur, c->hbuf2, s, prof);
+        GsFinal fin{c->hbuf1, c->Hc + (size_t)J * ncap, nullptr, &c->scal[1], c->flag};
+        gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf2, wcur, &fin, j + 1, s, prof);
+        std::swap(wprev, wcur);
+      }
       k = j + 1;
       info.n_matvec += 1;
       if (k == next_ck || k == kwant) {
@@ -377,14 +319,10 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
           const auto& b = hist[hist.size() - 1];
           const double rho_log = (std::log(b.second) - std::log(a.second)) / std::max(1, b.first - a.first);
           if (rho_log < -1e-6) {
-            // err(k) ~ b.second * exp(rho_log (k - b.first)); want err(k_next - delta) <= tol / 2
+            // err(k) ~ b.second * exp(rho_log (k - b.first)); want err <= tol / 2
             const double steps = std::log(0.5 * tol / b.second) / rho_log;
-            int target = b.first + (int)std::ceil(1.05 * steps);
-            if (target <= k) {
-              nk = k + 4;  // the previous checkpoint should already be below tol: confirm
-            } else {
-              nk = target;
-            }
+            const int target = b.first + (int)std::ceil(1.05 * steps);
+            nk = (target <= k) ? k + 4 : target;  // previous checkpoint should be below tol: confirm
           } else {
             nk = k + std::max(8, k / 2);
           }
@@ -398,10 +336,18 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
 
   // step (vi): y = Q c
   const int n = m + k;
-  gs_combine(c->gs, c->Q, ldq, N, n, c->cvec, c->wA, nullptr, s, prof);
-  wilson_unpack(c->lat, c->wA, y_abi, s);
+  if (delayed) {
+    if (mixed)
+      krylov_combine<float2>(c->kw, ka, 1, c->cvec, 0, c->wB, 0, n, s, prof);
+    else
+      krylov_combine<double2>(c->kw, ka, 1, c->cvec, 0, c->wB, 0, n, s, prof);
+  } else {
+    gs_combine(c->gs, c->Q, ldq, N, n, c->cvec, c->wB, nullptr, s, prof);
+  }
+  wilson_unpack(c->lat, c->wB, y_abi, s);
   SGN_HIP(hipStreamSynchronize(s));
   if (prof) c->prof.flush();
+  SGN_HIP(hipMemcpy(&info.beta, &c->scal[0], sizeof(double), hipMemcpyDeviceToHost));
 
   info.k_used = k;
   info.converged = converged ? 1 : 0;
@@ -422,6 +368,38 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
 }
 
 }  // namespace
+
+void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std::vector<double2>& Tin) {
+  hipStream_t s = c->stream;
+  SGN_HIP(hipStreamSynchronize(s));
+  std::vector<double2> Th(Tin);
+  for (int j = 0; j < m; ++j)
+    for (int i = j + 1; i < m; ++i) Th[(size_t)j * m + i] = make_double2(0.0, 0.0);
+  for (int i = 0; i < m; ++i) {
+    const double2 d = Th[(size_t)i * m + i];
+    SGN_REQUIRE(std::isfinite(d.x) && std::isfinite(d.y), SGN_EINVAL, "T has a non-finite diagonal");
+    SGN_REQUIRE(d.x != 0.0, SGN_ESINGULAR, "T has an eigenvalue on the imaginary axis");
+  }
+  // drop the old basis and the workspace (its layout depends on m)
+  c->release_workspace();
+  for (double2** p : {&c->S, &c->Tdev, &c->sgnT})
+    if (*p) {
+      SGN_HIP(hipFree(*p));
+      *p = nullptr;
+    }
+  c->T.clear();
+  c->m = 0;
+  if (m == 0) return;
+  SGN_HIP(hipMalloc(&c->S, sizeof(double2) * c->ldq * (size_t)m));
+  SGN_HIP(hipMemcpyAsync(c->S, S_internal, sizeof(double2) * c->ldq * (size_t)m, hipMemcpyDeviceToDevice, s));
+  SGN_HIP(hipMalloc(&c->Tdev, sizeof(double2) * (size_t)m * m));
+  SGN_HIP(hipMalloc(&c->sgnT, sizeof(double2) * (size_t)m * m));
+  SGN_HIP(hipMemcpyAsync(c->Tdev, Th.data(), sizeof(double2) * Th.size(), hipMemcpyHostToDevice, s));
+  dense_sign(c->dense, m, c->Tdev, m, c->sgnT, m, s, nullptr);  // step (ii): sgn(T_m) by Eq. (Roberts)
+  SGN_HIP(hipStreamSynchronize(s));
+  c->T = std::move(Th);
+  c->m = m;
+}
 
 // ---------------------------------------------------------------------------
 // ABI
@@ -525,38 +503,23 @@ int sgn_deflate_import(sgn_ctx* c, int m, const double* S_abi, const double* T_h
   return guarded(c, [&] {
     SGN_REQUIRE(m >= 0 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 0 <= m <= N/4");
     SGN_REQUIRE(m == 0 || (S_abi && T_host), SGN_EINVAL, "S and T must not be NULL");
-    hipStream_t s = c->stream;
-    SGN_HIP(hipStreamSynchronize(s));
-    // drop the old basis and the workspace (its layout depends on m)
-    c->release_workspace();
-    for (double2** p : {&c->S, &c->Tdev, &c->sgnT})
-      if (*p) {
-        SGN_HIP(hipFree(*p));
-        *p = nullptr;
-      }
-    c->T.clear();
-    c->m = 0;
-    if (m == 0) return SGN_OK;
     std::vector<double2> Th((size_t)m * m);
-    std::memcpy(Th.data(), T_host, sizeof(double2) * Th.size());
-    for (int j = 0; j < m; ++j)
-      for (int i = j + 1; i < m; ++i) Th[(size_t)j * m + i] = make_double2(0.0, 0.0);
-    for (int i = 0; i < m; ++i) {
-      const double2 d = Th[(size_t)i * m + i];
-      SGN_REQUIRE(std::isfinite(d.x) && std::isfinite(d.y), SGN_EINVAL, "T has a non-finite diagonal");
-      SGN_REQUIRE(d.x != 0.0, SGN_ESINGULAR, "T has an eigenvalue on the imaginary axis");
+    if (m) std::memcpy(Th.data(), T_host, sizeof(double2) * Th.size());
+    double2* Sint = nullptr;
+    if (m) {
+      SGN_HIP(hipMalloc(&Sint, sizeof(double2) * c->ldq * (size_t)m));
+      SGN_HIP(hipMemsetAsync(Sint, 0, sizeof(double2) * c->ldq * (size_t)m, c->stream));
+      for (int j = 0; j < m; ++j)
+        wilson_pack(c->lat, reinterpret_cast<const double2*>(S_abi) + (size_t)j * c->N, Sint + (size_t)j * c->ldq,
+                    c->stream);
     }
-    SGN_HIP(hipMalloc(&c->S, sizeof(double2) * c->ldq * (size_t)m));
-    SGN_HIP(hipMemset(c->S, 0, sizeof(double2) * c->ldq * (size_t)m));
-    for (int j = 0; j < m; ++j)
-      wilson_pack(c->lat, reinterpret_cast<const double2*>(S_abi) + (size_t)j * c->N, c->S + (size_t)j * c->ldq, s);
-    SGN_HIP(hipMalloc(&c->Tdev, sizeof(double2) * (size_t)m * m));
-    SGN_HIP(hipMalloc(&c->sgnT, sizeof(double2) * (size_t)m * m));
-    SGN_HIP(hipMemcpyAsync(c->Tdev, Th.data(), sizeof(double2) * Th.size(), hipMemcpyHostToDevice, s));
-    dense_sign(c->dense, m, c->Tdev, m, c->sgnT, m, s, nullptr);  // step (ii)
-    SGN_HIP(hipStreamSynchronize(s));
-    c->T = std::move(Th);
-    c->m = m;
+    try {
+      install_schur_pair(c, m, Sint, Th);
+    } catch (...) {
+      if (Sint) (void)hipFree(Sint);
+      throw;
+    }
+    if (Sint) SGN_HIP(hipFree(Sint));
     return SGN_OK;
   });
 }
@@ -594,6 +557,30 @@ int sgn_apply_fixed(sgn_ctx* c, const double* x, double* y, int k) {
     SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
     SGN_REQUIRE(k >= 0 && k <= c->N - c->m, SGN_EINVAL, "k must satisfy 0 <= k <= N - m");
     return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), 1.0, k, k);
+  });
+}
+
+int sgn_set_precision(sgn_ctx* c, int prec) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(prec == SGN_PREC_FP64 || prec == SGN_PREC_MIXED, SGN_EINVAL, "unknown precision");
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    if (prec == c->prec) return SGN_OK;
+    c->release_workspace();
+    c->prec = prec;
+    if (prec == SGN_PREC_MIXED && !c->links32) {
+      SGN_HIP(hipMalloc(&c->links32, sizeof(float2) * 36 * (size_t)c->lat.V));
+      wilson_links_f32(c->links, c->links32, c->lat.V, c->stream);
+      SGN_HIP(hipStreamSynchronize(c->stream));
+    }
+    return SGN_OK;
+  });
+}
+
+int sgn_set_orthogonalization(sgn_ctx* c, int mode) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(mode == SGN_ORTH_CGS2 || mode == SGN_ORTH_DELAYED, SGN_EINVAL, "unknown orthogonalisation mode");
+    c->orth = mode;
+    return SGN_OK;
   });
 }
 

@@ -1,0 +1,163 @@
+// The sgn_ctx structure shared by the translation units that drive kernels.
+#pragma once
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "krylov.h"
+
+struct sgn_ctx {
+  Lattice lat{};
+  int N = 0;
+  size_t ldq = 0;
+  double mu = 0, m_w = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  sgn_info info{};
+  Profiler prof;
+
+  double2* links = nullptr;  // [4][9][V]
+
+  // deflation
+  int m = 0;
+  int defl_restarts = 0, defl_matvecs = 0;
+  double defl_residual = 0.0;
+  double2* S = nullptr;       // internal layout, ldq x m
+  std::vector<double2> T;     // host m x m (column-major, upper triangular)
+  double2* Tdev = nullptr;    // m x m
+  double2* sgnT = nullptr;    // m x m
+
+  // Krylov workspace
+  int kcap = 0;               // capacity in Krylov vectors
+  int ncap = 0;               // m + kcap + 1 (columns of Q, rows of H)
+  double2* Q = nullptr;       // ldq x ncap
+  double2* Hc = nullptr;      // ncap x ncap, column-major (ld = ncap)
+  double2* F = nullptr;       // sign output (m + kcap)^2, ld = n
+  double2* wA = nullptr;
+  double2* wB = nullptr;
+  double2* xin = nullptr;
+  double2* hbuf1 = nullptr;
+  double2* hbuf2 = nullptr;
+  double2* c0 = nullptr;
+  double2* cvec = nullptr;
+  double2* cprev = nullptr;
+  double* scal = nullptr;     // [0] beta0 [1] inv_beta [2] err [3] scratch
+  int* flag = nullptr;        // [0] breakdown/finite flag
+  double* hpin = nullptr;     // pinned host mirror
+  double2* wC = nullptr;
+  // mixed precision: FP32 links, Krylov columns and stencil operands
+  int prec = SGN_PREC_FP64;
+  float2* links32 = nullptr;
+  float2* V32 = nullptr;   // ldq x (kcap + 1)
+  float2* u32a = nullptr;  // FP32 copies of the candidate (ping-pong)
+  float2* u32b = nullptr;
+  float2* z32 = nullptr;
+  GsWork gs;
+  KrylovWork kw;
+  DenseWork dense;
+  int orth = 1;  // 0: two classical Gram-Schmidt passes per step; 1: one reduction, delayed re-orthogonalisation
+
+  ~sgn_ctx() { release(); }
+
+  void release_workspace() {
+    for (double2** p : {&Q, &Hc, &F, &wA, &wB, &wC, &xin, &hbuf1, &hbuf2, &c0, &cvec, &cprev})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    for (float2** p : {&V32, &u32a, &u32b, &z32})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    gs_free(gs);
+    krylov_free(kw);
+    kcap = 0;
+    ncap = 0;
+  }
+
+  void release() {
+    if (stream || true) (void)hipDeviceSynchronize();
+    release_workspace();
+    dense_free(dense);
+    for (double2** p : {&links, &S, &Tdev, &sgnT})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    if (links32) (void)hipFree(links32);
+    links32 = nullptr;
+    if (scal) (void)hipFree(scal);
+    if (flag) (void)hipFree(flag);
+    if (hpin) (void)hipHostFree(hpin);
+    scal = nullptr;
+    flag = nullptr;
+    hpin = nullptr;
+  }
+
+  // make sure the Krylov workspace holds m + kmax + 1 columns
+  void ensure_workspace(int kmax) {
+    if (kmax <= kcap && Q) return;
+    release_workspace();
+    kcap = kmax;
+    ncap = m + kcap + 1;
+    // FP64 mode keeps S and the Krylov columns in one matrix; mixed mode keeps
+    // only S in FP64 and the Krylov columns in V32
+    const size_t qcols = (prec == SGN_PREC_MIXED) ? (size_t)std::max(m, 1) : (size_t)ncap;
+    SGN_HIP(hipMalloc(&Q, sizeof(double2) * ldq * qcols));
+    if (prec == SGN_PREC_MIXED) {
+      SGN_HIP(hipMalloc(&V32, sizeof(float2) * ldq * (size_t)(kcap + 1)));
+      SGN_HIP(hipMalloc(&u32a, sizeof(float2) * ldq));
+      SGN_HIP(hipMalloc(&u32b, sizeof(float2) * ldq));
+      SGN_HIP(hipMalloc(&z32, sizeof(float2) * ldq));
+    }
+    SGN_HIP(hipMalloc(&Hc, sizeof(double2) * (size_t)ncap * ncap));
+    SGN_HIP(hipMalloc(&F, sizeof(double2) * (size_t)(m + kcap) * (m + kcap)));
+    SGN_HIP(hipMalloc(&wA, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&wB, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&wC, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&xin, sizeof(double2) * ldq));
+    SGN_HIP(hipMalloc(&hbuf1, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&hbuf2, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&c0, sizeof(double2) * (size_t)(m > 0 ? m : 1)));
+    SGN_HIP(hipMalloc(&cvec, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&cprev, sizeof(double2) * (size_t)ncap));
+    gs_alloc(gs, N, ldq, ncap);
+    krylov_alloc(kw, N, ldq, ncap, 1);
+    // the Schur block of Q and of H never changes between applies
+    if (m > 0) {
+      SGN_HIP(hipMemcpy2D(Q, ldq * sizeof(double2), S, ldq * sizeof(double2), ldq * sizeof(double2), m,
+                          hipMemcpyDeviceToDevice));
+    }
+    SGN_HIP(hipMemset(Hc, 0, sizeof(double2) * (size_t)ncap * ncap));
+    if (m > 0) dev_copy_mat(Tdev, m, Hc, ncap, m, m, nullptr);
+    SGN_HIP(hipDeviceSynchronize());
+  }
+};
+
+
+inline int fail(sgn_ctx* c, const SgnError& e) {
+  if (c) c->last_error = e.msg;
+  return e.status;
+}
+
+template <class F>
+inline int guarded(sgn_ctx* c, F&& f) {
+  if (!c) return SGN_ESTATE;
+  try {
+    return f();
+  } catch (const SgnError& e) {
+    return fail(c, e);
+  } catch (const std::bad_alloc&) {
+    return fail(c, SgnError{SGN_ENOMEM, "host allocation failed"});
+  } catch (...) {
+    return fail(c, SgnError{SGN_EHIP, "unexpected error"});
+  }
+}
+
+
+// Install a partial Schur pair (S in the internal layout, device, ldq x m;
+// T host column-major m x m, upper triangular) and compute sgn(T) on the device.
+void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std::vector<double2>& T);

@@ -1,0 +1,340 @@
+// Deflation setup (Section 5.2, steps (i)-(ii); Results section): the m
+// critical eigenvectors of A = H_w(mu) and the partial Schur pair (S_m, T_m).
+//
+// As in the paper, the eigenvalues of smallest magnitude are sought on the
+// squared operator A^2, where they lie on the boundary of the convex hull of
+// the spectrum, with an Arnoldi method that is restarted by keeping the wanted
+// Ritz vectors ("thick restart", the Krylov-Schur form
+// A^2 V_k = V_k T_k + v_{k+1} b^T with a full k x k block T_k).  The Arnoldi
+// steps run on the device (two stencil applications and two classical
+// Gram-Schmidt passes per step); the small projected eigenproblems are solved
+// on the host (hostla.cpp).
+//
+// After convergence, a Rayleigh-Ritz step with A itself on the span Z of the
+// converged vectors of A^2 resolves pairs +-lambda (which share lambda^2):
+// G = Z^dag A Z, G W = W diag(theta).  The m Ritz values with smallest
+// |Re theta| (ties: smaller |theta|, then larger Im theta) are kept; the QR
+// factor of their coefficient vectors, R = Q_R G_R, gives S_m = Z Q_R and
+// T_m = Q_R^dag G Q_R, upper triangular up to rounding (Eq. pSd).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <random>
+
+#include "context.h"
+#include "hostla.h"
+
+namespace {
+
+using hostla::cplx;
+
+// out = in * (*inv); in and out may alias
+__global__ void scale_kernel(const double2* in, double2* out, int n, const double* __restrict__ inv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cscale(in[i], *inv);
+}
+
+void dev_scale(const double2* in, double2* out, int n, const double* inv, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n, inv);
+  SGN_HIP(hipGetLastError());
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t bytes) { SGN_HIP(hipMalloc(&p, bytes)); }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <class T>
+  T* as() {
+    return static_cast<T*>(p);
+  }
+};
+
+inline double2 to_d2(cplx z) { return make_double2(z.real(), z.imag()); }
+inline cplx to_c(double2 z) { return cplx(z.x, z.y); }
+
+// indices of the wanted entries: smallest |Re|, then |.|, then larger Im, then index
+std::vector<int> select_critical(const std::vector<cplx>& lam, int m) {
+  std::vector<int> idx(lam.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    const double ra = std::abs(lam[a].real()), rb = std::abs(lam[b].real());
+    if (ra != rb) return ra < rb;
+    const double ma = std::abs(lam[a]), mb = std::abs(lam[b]);
+    if (ma != mb) return ma < mb;
+    if (lam[a].imag() != lam[b].imag()) return lam[a].imag() > lam[b].imag();
+    return a < b;
+  });
+  idx.resize(std::min<size_t>(m, idx.size()));
+  return idx;
+}
+
+}  // namespace
+
+struct DeflateStats {
+  int restarts = 0;
+  int matvecs = 0;
+  double residual = 0.0;  // ||A S - S T||_F / ||A||
+  double lower = 0.0;     // ||tril(T, -1)||_F before it is dropped
+};
+
+static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_restarts, double tol,
+                                unsigned long long seed) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const size_t ldq = c->ldq;
+  const int ldh = ncv + 1;
+  DeflateStats st;
+
+  DevBuf bV(sizeof(double2) * ldq * (size_t)(ncv + 1)), bVt(sizeof(double2) * ldq * (size_t)(ncv + 1));
+  DevBuf bt(sizeof(double2) * ldq), bw(sizeof(double2) * ldq);
+  DevBuf bH(sizeof(double2) * (size_t)ldh * ldh), bcoef(sizeof(double2) * (size_t)ldh * ldh);
+  DevBuf bh1(sizeof(double2) * ldh), bh2(sizeof(double2) * ldh);
+  DevBuf bsc(sizeof(double) * 8), bflag(sizeof(int) * 4);
+  double2* V = bV.as<double2>();
+  double2* Vt = bVt.as<double2>();
+  double2* t1 = bt.as<double2>();
+  double2* w = bw.as<double2>();
+  double2* Hd = bH.as<double2>();
+  double2* coef = bcoef.as<double2>();
+  double* sc = bsc.as<double>();
+  int* flag = bflag.as<int>();
+  GsWork g;
+  gs_alloc(g, N, ldq, ldh);
+  struct GsGuard {
+    GsWork& g;
+    ~GsGuard() { gs_free(g); }
+  } guard{g};
+  SGN_HIP(hipMemsetAsync(V, 0, sizeof(double2) * ldq * (ncv + 1), s));
+  SGN_HIP(hipMemsetAsync(Vt, 0, sizeof(double2) * ldq * (ncv + 1), s));
+  SGN_HIP(hipMemsetAsync(Hd, 0, sizeof(double2) * (size_t)ldh * ldh, s));
+  SGN_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, s));
+
+  // deterministic start vector (the internal layout is a permutation of the
+  // ABI layout, so this is simply some fixed unit vector)
+  {
+    std::vector<double2> v0((size_t)N);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd;
+    for (auto& z : v0) z = make_double2(nd(rng), nd(rng));
+    SGN_HIP(hipMemcpyAsync(w, v0.data(), sizeof(double2) * N, hipMemcpyHostToDevice, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    gs_norm(g, N, w, &sc[0], &sc[1], flag, s, nullptr);
+    dev_scale(w, V, N, &sc[1], s);
+  }
+
+  std::vector<double2> Hh((size_t)ldh * ldh);
+  std::vector<cplx> Hn((size_t)ncv * ncv), theta(ncv), Y((size_t)ncv * ncv);
+  int k = 0;
+  bool converged = false;
+  double bnorm = 1.0;
+  for (int rst = 0; rst <= max_restarts; ++rst) {
+    // Arnoldi extension k -> ncv on A^2 (Eq. Arnoldi with A^2 in place of A)
+    for (int j = k; j < ncv; ++j) {
+      double2* vj = V + (size_t)j * ldq;
+      wilson_apply(c->lat, c->links, vj, t1, nullptr, nullptr, s, nullptr);
+      wilson_apply(c->lat, c->links, t1, w, nullptr, nullptr, s, nullptr);
+      st.matvecs += 2;
+      const int ncol = j + 1;
+      gs_dot(g, V, ldq, N, ncol, w, bh1.as<double2>(), s, nullptr);
+      gs_update(g, V, ldq, N, ncol, bh1.as<double2>(), w, nullptr, 0, s, nullptr);
+      gs_dot(g, V, ldq, N, ncol, w, bh2.as<double2>(), s, nullptr);
+      GsFinal fin{bh1.as<double2>(), Hd + (size_t)j * ldh, nullptr, &sc[1], nullptr};
+      gs_update(g, V, ldq, N, ncol, bh2.as<double2>(), w, &fin, j + 1, s, nullptr);
+      dev_scale(w, V + (size_t)(j + 1) * ldq, N, &sc[1], s);
+    }
+    SGN_HIP(hipMemcpyAsync(Hh.data(), Hd, sizeof(double2) * Hh.size(), hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < ncv; ++j)
+      for (int i = 0; i < ncv; ++i) Hn[(size_t)j * ncv + i] = to_c(Hh[(size_t)j * ldh + i]);
+    const double beta = Hh[(size_t)(ncv - 1) * ldh + ncv].x;
+    SGN_REQUIRE(std::isfinite(beta), SGN_EDEFL, "deflation: non-finite Arnoldi coefficient");
+    SGN_REQUIRE(hostla::eig(ncv, Hn.data(), theta.data(), Y.data()), SGN_EDEFL,
+                "deflation: small eigenproblem did not converge");
+    // order by |theta| (wanted: smallest magnitude of lambda^2)
+    std::vector<int> ord(ncv);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(theta[a]) < std::abs(theta[b]); });
+    bnorm = 0.0;
+    for (auto& t : theta) bnorm = std::max(bnorm, std::abs(t));
+    int nconv = 0;
+    double worst = 0.0;
+    for (int i = 0; i < nev; ++i) {
+      const double r = std::abs(beta) * std::abs(Y[(size_t)ord[i] * ncv + (ncv - 1)]);
+      worst = std::max(worst, r / bnorm);
+      if (r <= tol * bnorm) ++nconv;
+    }
+    st.restarts = rst;
+    const bool last = (rst == max_restarts);
+    if (nconv == nev || last) {
+      converged = (nconv == nev) || worst < 1e-10;
+      // U = V Y[:, wanted nev]  -> Vt[:, 0..nev)
+      std::vector<double2> cf((size_t)ncv * nev);
+      for (int i = 0; i < nev; ++i)
+        for (int r = 0; r < ncv; ++r) cf[(size_t)i * ncv + r] = to_d2(Y[(size_t)ord[i] * ncv + r]);
+      SGN_HIP(hipMemcpyAsync(coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, s));
+      for (int i = 0; i < nev; ++i)
+        gs_combine(g, V, ldq, N, ncv, coef + (size_t)i * ncv, Vt + (size_t)i * ldq, nullptr, s, nullptr);
+      SGN_HIP(hipStreamSynchronize(s));  // cf is pageable host memory
+      break;
+    }
+    // thick restart: keep kk wanted Ritz vectors (orthonormalised)
+    int kk = std::min(nev + (ncv - nev) / 2, ncv - 2);
+    std::vector<cplx> Yq((size_t)ncv * kk);
+    for (int i = 0; i < kk; ++i)
+      for (int r = 0; r < ncv; ++r) Yq[(size_t)i * ncv + r] = Y[(size_t)ord[i] * ncv + r];
+    hostla::thin_qr(ncv, kk, Yq.data(), 1e-12);
+    // drop columns that became zero (numerically dependent Ritz vectors)
+    {
+      int w2 = 0;
+      for (int i = 0; i < kk; ++i) {
+        double nn = 0.0;
+        for (int r = 0; r < ncv; ++r) nn += std::norm(Yq[(size_t)i * ncv + r]);
+        if (nn > 0.5) {
+          if (w2 != i)
+            for (int r = 0; r < ncv; ++r) Yq[(size_t)w2 * ncv + r] = Yq[(size_t)i * ncv + r];
+          ++w2;
+        }
+      }
+      kk = w2;
+    }
+    // T_k = Yq^H H Yq, b = beta * Yq[ncv-1, :]
+    std::vector<cplx> HY((size_t)ncv * kk, cplx(0.0, 0.0));
+    for (int i = 0; i < kk; ++i)
+      for (int l = 0; l < ncv; ++l) {
+        const cplx y = Yq[(size_t)i * ncv + l];
+        if (y == cplx(0.0, 0.0)) continue;
+        for (int r = 0; r < ncv; ++r) HY[(size_t)i * ncv + r] += Hn[(size_t)l * ncv + r] * y;
+      }
+    std::fill(Hh.begin(), Hh.end(), make_double2(0.0, 0.0));
+    for (int i = 0; i < kk; ++i) {
+      for (int r = 0; r < kk; ++r) {
+        cplx sacc = 0.0;
+        for (int l = 0; l < ncv; ++l) sacc += std::conj(Yq[(size_t)r * ncv + l]) * HY[(size_t)i * ncv + l];
+        Hh[(size_t)i * ldh + r] = to_d2(sacc);
+      }
+      Hh[(size_t)i * ldh + kk] = to_d2(beta * Yq[(size_t)i * ncv + (ncv - 1)]);
+    }
+    std::vector<double2> cf((size_t)ncv * kk);
+    for (size_t e = 0; e < cf.size(); ++e) cf[e] = to_d2(Yq[e]);
+    SGN_HIP(hipMemcpyAsync(coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, s));
+    for (int i = 0; i < kk; ++i)
+      gs_combine(g, V, ldq, N, ncv, coef + (size_t)i * ncv, Vt + (size_t)i * ldq, nullptr, s, nullptr);
+    SGN_HIP(hipMemcpyAsync(Vt + (size_t)kk * ldq, V + (size_t)ncv * ldq, sizeof(double2) * ldq,
+                           hipMemcpyDeviceToDevice, s));
+    std::swap(V, Vt);
+    SGN_HIP(hipMemcpyAsync(Hd, Hh.data(), sizeof(double2) * Hh.size(), hipMemcpyHostToDevice, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    k = kk;
+  }
+  SGN_REQUIRE(converged, SGN_EDEFL, "deflation: Arnoldi on A^2 did not converge");
+
+  // Z = orth(U) on the device (classical Gram-Schmidt, two passes), in Vt
+  for (int i = 0; i < nev; ++i) {
+    double2* u = Vt + (size_t)i * ldq;
+    if (i > 0) {
+      gs_dot(g, Vt, ldq, N, i, u, bh1.as<double2>(), s, nullptr);
+      gs_update(g, Vt, ldq, N, i, bh1.as<double2>(), u, nullptr, 0, s, nullptr);
+      gs_dot(g, Vt, ldq, N, i, u, bh2.as<double2>(), s, nullptr);
+      GsFinal fin{nullptr, nullptr, &sc[0], &sc[1], nullptr};
+      gs_update(g, Vt, ldq, N, i, bh2.as<double2>(), u, &fin, 0, s, nullptr);
+    } else {
+      gs_norm(g, N, u, &sc[0], &sc[1], nullptr, s, nullptr);
+    }
+    dev_scale(u, u, N, &sc[1], s);
+  }
+  // W = A Z (in V), G = Z^dag W
+  std::vector<double2> Gd((size_t)nev * nev);
+  for (int i = 0; i < nev; ++i) {
+    wilson_apply(c->lat, c->links, Vt + (size_t)i * ldq, V + (size_t)i * ldq, nullptr, nullptr, s, nullptr);
+    st.matvecs += 1;
+    gs_dot(g, Vt, ldq, N, nev, V + (size_t)i * ldq, coef + (size_t)i * nev, s, nullptr);
+  }
+  SGN_HIP(hipMemcpyAsync(Gd.data(), coef, sizeof(double2) * Gd.size(), hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipStreamSynchronize(s));
+  std::vector<cplx> G((size_t)nev * nev), lam(nev), Wv((size_t)nev * nev);
+  for (size_t e = 0; e < G.size(); ++e) G[e] = to_c(Gd[e]);
+  SGN_REQUIRE(hostla::eig(nev, G.data(), lam.data(), Wv.data()), SGN_EDEFL,
+              "deflation: Rayleigh-Ritz eigenproblem did not converge");
+  const std::vector<int> sel = select_critical(lam, m);
+  std::vector<cplx> Rq((size_t)nev * m);
+  for (int j = 0; j < m; ++j)
+    for (int r = 0; r < nev; ++r) Rq[(size_t)j * nev + r] = Wv[(size_t)sel[j] * nev + r];
+  SGN_REQUIRE(hostla::thin_qr(nev, m, Rq.data(), 1e-10) == m, SGN_EDEFL,
+              "deflation: selected eigenvectors are linearly dependent");
+  // T = Rq^H G Rq
+  std::vector<cplx> GR((size_t)nev * m, cplx(0.0, 0.0)), T((size_t)m * m);
+  for (int j = 0; j < m; ++j)
+    for (int l = 0; l < nev; ++l)
+      for (int r = 0; r < nev; ++r) GR[(size_t)j * nev + r] += G[(size_t)l * nev + r] * Rq[(size_t)j * nev + l];
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      cplx sacc = 0.0;
+      for (int r = 0; r < nev; ++r) sacc += std::conj(Rq[(size_t)i * nev + r]) * GR[(size_t)j * nev + r];
+      T[(size_t)j * m + i] = sacc;
+    }
+  double low = 0.0;
+  for (int j = 0; j < m; ++j)
+    for (int i = j + 1; i < m; ++i) low += std::norm(T[(size_t)j * m + i]);
+  st.lower = std::sqrt(low);
+
+  // S = Z Rq (device, internal layout) and the residual ||A S - S T||_F
+  DevBuf bS(sizeof(double2) * ldq * (size_t)m);
+  double2* Sd = bS.as<double2>();
+  SGN_HIP(hipMemsetAsync(Sd, 0, sizeof(double2) * ldq * (size_t)m, s));
+  std::vector<double2> cf((size_t)nev * m), cf2((size_t)m * m);
+  for (size_t e = 0; e < cf.size(); ++e) cf[e] = to_d2(Rq[e]);
+  SGN_HIP(hipMemcpyAsync(coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, s));
+  for (int j = 0; j < m; ++j)
+    gs_combine(g, Vt, ldq, N, nev, coef + (size_t)j * nev, Sd + (size_t)j * ldq, nullptr, s, nullptr);
+  std::vector<double2> Tkeep((size_t)m * m);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) Tkeep[(size_t)j * m + i] = (i <= j) ? to_d2(T[(size_t)j * m + i]) : make_double2(0, 0);
+  SGN_HIP(hipMemcpyAsync(coef + (size_t)nev * m, Tkeep.data(), sizeof(double2) * Tkeep.size(),
+                         hipMemcpyHostToDevice, s));
+  double res2 = 0.0;
+  for (int j = 0; j < m; ++j) {
+    wilson_apply(c->lat, c->links, Sd + (size_t)j * ldq, w, nullptr, nullptr, s, nullptr);
+    GsFinal fin{nullptr, nullptr, &sc[0], &sc[1], nullptr};
+    gs_update(g, Sd, ldq, N, m, coef + (size_t)nev * m + (size_t)j * m, w, &fin, 0, s, nullptr);
+    double r = 0.0;
+    SGN_HIP(hipMemcpyAsync(&r, &sc[0], sizeof(double), hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    res2 += r * r;
+  }
+  const double anorm = std::sqrt(bnorm);
+  st.residual = std::sqrt(res2) / anorm;
+  SGN_REQUIRE(st.residual <= 1e-10, SGN_EDEFL,
+              "deflation basis not accurate enough: ||AS - ST||_F / ||A|| = " + std::to_string(st.residual));
+  std::vector<double2> Th(Tkeep);
+  install_schur_pair(c, m, Sd, Th);
+  return st;
+}
+
+extern "C" int sgn_deflate(sgn_ctx* c, int m) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(m >= 0 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 0 <= m <= N/4");
+    if (m == 0) {
+      install_schur_pair(c, 0, nullptr, {});
+      return SGN_OK;
+    }
+    const int nev = std::min(m + std::max(10, m / 2), c->N / 2);
+    const int ncv = std::min(std::max(3 * nev, nev + 40), c->N - 1);
+    SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
+    const DeflateStats st = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull);
+    c->defl_restarts = st.restarts;
+    c->defl_matvecs = st.matvecs;
+    c->defl_residual = st.residual;
+    return SGN_OK;
+  });
+}
+
+extern "C" int sgn_deflate_stats(const sgn_ctx* c, int* restarts, int* matvecs, double* residual) {
+  if (!c) return SGN_ESTATE;
+  if (restarts) *restarts = c->defl_restarts;
+  if (matvecs) *matvecs = c->defl_matvecs;
+  if (residual) *residual = c->defl_residual;
+  return SGN_OK;
+}

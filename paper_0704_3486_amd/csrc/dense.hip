@@ -296,6 +296,11 @@ __global__ void negate_kernel(const double2* __restrict__ in, double2* __restric
   if (i < n) out[i] = cneg(in[i]);
 }
 
+__global__ void to_f32_kernel(const double2* __restrict__ in, float2* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
 __global__ void finite_kernel(const double2* __restrict__ v, size_t n, int* __restrict__ flag) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -391,6 +396,12 @@ void dev_copy_mat(const double2* A, int lda, double2* B, int ldb, int rows, int 
 void dev_negate(const double2* in, double2* out, int n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(negate_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+  SGN_HIP(hipGetLastError());
+}
+
+void dev_to_f32(const double2* in, float2* out, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
   SGN_HIP(hipGetLastError());
 }
 

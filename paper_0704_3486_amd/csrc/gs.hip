@@ -297,3 +297,4 @@ void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, 
   dev_zero(y, (size_t)N, s);
   update_launch(g, Q, ldq, N, ncol, coef, +1.0, y, nullptr, 0, s, prof);
 }
+

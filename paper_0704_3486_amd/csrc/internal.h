@@ -143,6 +143,14 @@ void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStre
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);
 
+// Out_r = H_w(mu) In_r for nrhs vectors at fixed strides, one launch (links loaded once per hop)
+void wilson_apply_multi(const Lattice& lat, const double2* links, const double2* in, size_t istride, double2* out,
+                        size_t ostride, int nrhs, hipStream_t s, Profiler* prof);
+// FP32 links and spinors (mixed precision)
+void wilson_apply_multi32(const Lattice& lat, const float2* links, const float2* in, size_t istride, float2* out,
+                          size_t ostride, int nrhs, hipStream_t s, Profiler* prof);
+void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t s);
+
 // dense kernels (dense.hip)
 struct DenseWork {
   int ncap = 0;
@@ -174,5 +182,7 @@ void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, 
                 double2* y, double2* scratch_neg, hipStream_t s, Profiler* prof);
 // vector scale in place: v[i] *= a (device scalar pointer)
 void dev_negate(const double2* in, double2* out, int n, hipStream_t s);
+// precision conversion
+void dev_to_f32(const double2* in, float2* out, size_t n, hipStream_t s);
 // any non-finite entry -> flag = 1
 void dev_check_finite(const double2* v, size_t n, int* flag, hipStream_t s);

@@ -1,0 +1,95 @@
+// One-reduction modified Arnoldi step (krylov.hip): argument block and workspace.
+#pragma once
+
+#include <algorithm>
+
+#include "internal.h"
+
+// per-slot step scalars (doubles), kScStride apart
+enum {
+  kScC = 0,      // u^dag u
+  kScRho,        // |u| after re-orthogonalisation (0 on breakdown)
+  kScInv,        // 1 / rho (0 on breakdown)
+  kScGamRe,      // gam = q_J^dag z
+  kScGamIm,
+  kScGrRe,       // gam / rho
+  kScGrIm,
+  kScScale,      // |z| / rho: reference size of the next candidate
+  kScRef,        // reference size for this step's breakdown test
+  kScStride = 16
+};
+
+struct KrylovArgs {
+  int N = 0;
+  size_t ldq = 0;
+  int m = 0;                    // Schur columns (FP64, shared by all slots)
+  const double2* S = nullptr;   // ldq x m
+  int J = 0;                    // finished columns of Q
+  int j = 0;                    // step index (J = m + j)
+  // Krylov columns: column c >= m of slot r at V + r*vstride + (c-m)*ldq (element type VT)
+  void* V = nullptr;
+  size_t vstride = 0;
+  // FP64 candidate u (read) and next candidate (written), per slot at ustride
+  double2* u = nullptr;
+  double2* unext = nullptr;
+  size_t ustride = 0;
+  // stencil result z (VT, read) and the VT copy of the next candidate (written; nullable)
+  const void* z = nullptr;
+  void* ulonext = nullptr;
+  size_t zstride = 0;
+  // composite Hessenberg per slot
+  double2* H = nullptr;
+  int ldh = 0;
+  size_t hstride = 0;
+  double2* c0 = nullptr;  // S^dag x per slot (m entries at c0stride)
+  int c0stride = 0;
+  double* beta = nullptr;  // |x_perp| per slot (written at j = 0)
+  int* flag = nullptr;     // breakdown record per slot: k_invariant + 1, or -1 for non-finite values
+  const int* act = nullptr;  // blockIdx.z -> slot (nullable: identity)
+  // filled by krylov_bind from the workspace
+  double2 *Pa = nullptr, *Pb = nullptr;
+  double* Pcd = nullptr;
+  int ldp = 0;
+  size_t pstride = 0, cdstride = 0;
+  double2 *Upa = nullptr, *Upe = nullptr;
+  size_t upstride = 0;
+  double2 *a = nullptr, *b = nullptr;
+  size_t abstride = 0;
+  double* sc = nullptr;
+  unsigned* cnt = nullptr;
+  int cntstride = 0, cnt_all = 0, cnt_rows = 0;
+  int nrt_dot = 0;
+};
+
+struct KrylovWork {
+  int nrt_dot = 0, nrt_upd = 0, ncol_cap = 0, nslots = 0;
+  int ngroups_dot_cap = 0, ngroups_upd_cap = 0;
+  int ldp = 0;
+  size_t pstride = 0, cdstride = 0, upstride = 0, abstride = 0;
+  int cnt_all = 0, cnt_rows = 0, cntstride = 0;
+  double2 *Pa = nullptr, *Pb = nullptr;
+  double* Pcd = nullptr;
+  double2 *Upa = nullptr, *Upe = nullptr;
+  double2 *a = nullptr, *b = nullptr;
+  double* sc = nullptr;
+  unsigned* cnt = nullptr;
+};
+
+void krylov_alloc(KrylovWork& w, int N, size_t ldq, int ncol_cap, int nslots);
+void krylov_free(KrylovWork& w);
+void krylov_bind(const KrylovWork& w, KrylovArgs& A);
+
+// a = Q_J^dag u, b = Q_J^dag z (if with_z), step scalars; flag_on records breakdowns
+template <typename VT>
+void krylov_dot(const KrylovWork& w, const KrylovArgs& A, int nb, bool with_z, bool flag_on, hipStream_t s,
+                Profiler* prof);
+// v_J, next candidate, Hessenberg column J and re-orthogonalisation of column J-1
+template <typename VT>
+void krylov_update(const KrylovWork& w, const KrylovArgs& A, int nb, hipStream_t s, Profiler* prof);
+// y_r = Q_r coef_r over ncol columns
+template <typename VT>
+void krylov_combine(const KrylovWork& w, const KrylovArgs& A, int nb, const double2* coef, int cstride, double2* y,
+                    size_t ystride, int ncol, hipStream_t s, Profiler* prof);
+// dst_r = H_r[:n,:n] (dense n x n at dstride) with column n-1 += a_r when with_a
+void krylov_patch(const KrylovWork& w, const KrylovArgs& A, int nb, int n, double2* dst, size_t dstride,
+                  bool with_a, hipStream_t s);

@@ -1,0 +1,540 @@
+// One-reduction modified Arnoldi step with delayed re-orthogonalisation
+// (Section 5.2, step (iv), Eq. eq:modArnoldi), for FP64 or FP32 Krylov-vector
+// storage and for a batch of right-hand sides advancing in lock step.
+//
+// State before step j (J = m + j finished columns of Q = (S_m v_1 .. v_j)):
+// u, the candidate for column J, orthogonalised once against Q_J but neither
+// re-orthogonalised nor normalised.  With z = A u (the stencil, outside):
+//   dot:    a = Q_J^dag u, b = Q_J^dag z, c = u^dag u, d = u^dag z   (1 sweep)
+//           rho = sqrt(c - |a|^2),  gam = (d - a^dag b) / rho
+//   update: v_J = (u - Q_J a) / rho                                    (1 sweep)
+//           u'  = (z - (gam/rho) u - Q_J (b - (gam/rho) a)) / rho
+//               = (1 - Q_{J+1} Q_{J+1}^dag) A v_J
+//           column J-1 of H += a, H[J][J-1] = rho  (re-orthogonalisation)
+//           column J of H = ([b; gam] - Hbar_J a) / rho
+// Hbar_J is the (J+1) x J leading block of the composite H with the corrected
+// column J-1, so that A Q_J = Q_{J+1} Hbar_J.  At j = 0 the correction goes to
+// c0 = S^dag x and rho is beta = |x_perp|.  This is classical Gram-Schmidt
+// with one full re-orthogonalisation, rescheduled so that each step needs a
+// single global reduction and two sweeps over the basis.
+//
+// Precision: S, u, H, all dot products and all coefficients are FP64; the
+// Krylov columns v_j and the stencil operand/result (z) are stored as VT
+// (double2, or float2 in mixed precision).
+//
+// Batching: blockIdx.z selects a right-hand side; per-RHS buffers are laid
+// out at fixed strides.  All reductions are combined in a fixed order by the
+// last workgroup to finish, so results are bitwise independent of the batch.
+#include "internal.h"
+#include "krylov.h"
+
+namespace {
+
+constexpr int kRpl = 16;                // dot: rows per lane
+constexpr int kCpw = 4;                 // dot: columns per wavefront
+constexpr int kDRows = 64 * kRpl;       // dot: rows per tile
+constexpr int kDCols = kCpw * 4;        // dot: columns per workgroup (4 wavefronts)
+constexpr int kUpt = 4;                 // update: rows per thread
+constexpr int kURows = 256 * kUpt;      // update: rows per tile
+constexpr int kUCols = 32;              // update: columns per workgroup
+
+__device__ inline double2 ld2(const double2* p, size_t i) { return p[i]; }
+__device__ inline double2 ld2(const float2* p, size_t i) {
+  const float2 v = p[i];
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ inline void st2(double2* p, size_t i, double2 v) { p[i] = v; }
+__device__ inline void st2(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
+__device__ inline double2 wsum2(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+__device__ inline double wsum1(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline bool ticket_last(unsigned* counter, unsigned total) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == total - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = is_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+__device__ inline void ticket_reset(unsigned* counter) {
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// column c of Q for right-hand side slot r
+template <typename VT>
+__device__ inline double2 qload(const KrylovArgs& A, int r, int c, int i) {
+  if (c < A.m) return A.S[(size_t)c * A.ldq + i];
+  const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride + (size_t)(c - A.m) * A.ldq;
+  return ld2(V, i);
+}
+
+__device__ inline int slot_of(const KrylovArgs& A) { return A.act ? A.act[blockIdx.z] : (int)blockIdx.z; }
+
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z, int flag_on) {
+  const int r = slot_of(A);
+  const int rt = blockIdx.x, cg = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int N = A.N, J = A.J;
+  const int row0 = rt * kDRows;
+  const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
+  const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
+  double2* Pa = A.Pa + (size_t)r * A.pstride;
+  double2* Pb = A.Pb + (size_t)r * A.pstride;
+  double* Pcd = A.Pcd + (size_t)r * A.cdstride;
+  double2* av = A.a + (size_t)r * A.abstride;
+  double2* bv = A.b + (size_t)r * A.abstride;
+  double* sc = A.sc + (size_t)r * kScStride;
+  unsigned* cnt = A.cnt + (size_t)r * A.cntstride;
+  const int nrt = A.nrt_dot;
+  const int ngroups = gridDim.y;
+
+  double2 uv[kRpl], zv[kRpl];
+#pragma unroll
+  for (int q = 0; q < kRpl; ++q) {
+    const int i = row0 + q * 64 + lane;
+    uv[q] = (i < N) ? u[i] : make_double2(0.0, 0.0);
+    zv[q] = (with_z && i < N) ? ld2(z, i) : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int cc = 0; cc < kCpw; ++cc) {
+    const int c = cg * kDCols + wave * kCpw + cc;
+    if (c < J) {
+      double2 aa = make_double2(0.0, 0.0), bb = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < kRpl; ++q) {
+        const int i = row0 + q * 64 + lane;
+        if (i < N) {
+          const double2 qv = qload<VT>(A, r, c, i);
+          aa = cfmac(qv, uv[q], aa);
+          bb = cfmac(qv, zv[q], bb);
+        }
+      }
+      aa = wsum2(aa);
+      bb = wsum2(bb);
+      if (lane == 0) {
+        Pa[(size_t)rt * A.ldp + c] = aa;
+        Pb[(size_t)rt * A.ldp + c] = bb;
+      }
+    }
+  }
+  if (cg == 0) {
+    double cs = 0.0, zs = 0.0;
+    double2 ds = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < kRpl; ++q) {
+      cs += cabs2(uv[q]);
+      zs += cabs2(zv[q]);
+      ds = cfmac(uv[q], zv[q], ds);
+    }
+    __shared__ double red4[4][4];
+    cs = wsum1(cs);
+    zs = wsum1(zs);
+    ds = wsum2(ds);
+    if (lane == 0) {
+      red4[wave][0] = cs;
+      red4[wave][1] = ds.x;
+      red4[wave][2] = ds.y;
+      red4[wave][3] = zs;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int q = threadIdx.x;
+      Pcd[4 * rt + q] = ((red4[0][q] + red4[1][q]) + red4[2][q]) + red4[3][q];
+    }
+  }
+  if (!ticket_last(&cnt[cg], (unsigned)nrt)) return;
+  {
+    __shared__ double2 ra[16][kDCols + 1], rb[16][kDCols + 1];
+    const int cc = threadIdx.x & 15, sub = threadIdx.x >> 4;
+    const int c = cg * kDCols + cc;
+    double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+    if (c < J)
+      for (int t = sub; t < nrt; t += 16) {
+        sa = cadd(sa, Pa[(size_t)t * A.ldp + c]);
+        sb = cadd(sb, Pb[(size_t)t * A.ldp + c]);
+      }
+    ra[sub][cc] = sa;
+    rb[sub][cc] = sb;
+    __syncthreads();
+    if (threadIdx.x < 16 && c < J) {
+      double2 s1 = ra[0][cc], s2 = rb[0][cc];
+      for (int k = 1; k < 16; ++k) {
+        s1 = cadd(s1, ra[k][cc]);
+        s2 = cadd(s2, rb[k][cc]);
+      }
+      av[c] = s1;
+      bv[c] = s2;
+    }
+  }
+  ticket_reset(&cnt[cg]);
+  if (!ticket_last(&cnt[A.cnt_all], (unsigned)ngroups)) return;
+  // last workgroup of this right-hand side: the step scalars
+  __shared__ double tr[7][256];
+  const int tid = threadIdx.x;
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int t = tid; t < nrt; t += 256) {
+    s[0] += Pcd[4 * t];
+    s[1] += Pcd[4 * t + 1];
+    s[2] += Pcd[4 * t + 2];
+    s[3] += Pcd[4 * t + 3];
+  }
+  for (int c = tid; c < J; c += 256) {
+    const double2 x1 = av[c], x2 = bv[c];
+    s[4] += cabs2(x1);
+    const double2 ab = cmulc(x1, x2);
+    s[5] += ab.x;
+    s[6] += ab.y;
+  }
+  for (int q = 0; q < 7; ++q) tr[q][tid] = s[q];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off)
+      for (int q = 0; q < 7; ++q) tr[q][tid] += tr[q][tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double c = tr[0][0], aa = tr[4][0];
+    const double2 d = make_double2(tr[1][0], tr[2][0]);
+    const double2 ab = make_double2(tr[5][0], tr[6][0]);
+    const double rho2 = c - aa;
+    const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+    const bool finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(tr[3][0]);
+    const bool brk = !(rho > 1e-14 * sc[kScRef]) || !finite;
+    const double inv = brk ? 0.0 : 1.0 / rho;
+    const double2 gam = cscale(csub(d, ab), inv);
+    sc[kScC] = c;
+    sc[kScRho] = brk ? 0.0 : rho;
+    sc[kScInv] = inv;
+    sc[kScGamRe] = gam.x;
+    sc[kScGamIm] = gam.y;
+    sc[kScGrRe] = gam.x * inv;
+    sc[kScGrIm] = gam.y * inv;
+    sc[kScScale] = sqrt(tr[3][0]) * inv;
+    if (flag_on && A.flag) {
+      int* f = A.flag + r;
+      if (!finite)
+        *f = -1;
+      else if (brk && *f == 0)
+        *f = A.j + 1;
+    }
+  }
+  ticket_reset(&cnt[A.cnt_all]);
+}
+
+// ---------------------------------------------------------------------------
+// Hessenberg column J (one row per thread) and the re-orthogonalisation of
+// column J-1; at j = 0 the correction goes to c0 instead.
+__device__ void hcol_row(const KrylovArgs& A, int r, int row) {
+  const int J = A.J;
+  const double* sc = A.sc + (size_t)r * kScStride;
+  const double2* a = A.a + (size_t)r * A.abstride;
+  const double2* b = A.b + (size_t)r * A.abstride;
+  double2* H = A.H + (size_t)r * A.hstride;
+  const int ldh = A.ldh;
+  const double rho = sc[kScRho], inv = sc[kScInv];
+  const double2 g = (row < J) ? b[row] : make_double2(sc[kScGamRe], sc[kScGamIm]);
+  double2 ha = make_double2(0.0, 0.0);
+  const int lim = (A.j > 0) ? J - 1 : J;
+  for (int l = 0; l < lim; ++l) ha = cfma(H[(size_t)l * ldh + row], a[l], ha);
+  if (A.j > 0) {
+    const double2 hl = (row < J) ? cadd(H[(size_t)(J - 1) * ldh + row], a[row]) : make_double2(rho, 0.0);
+    ha = cfma(hl, a[J - 1], ha);
+    H[(size_t)(J - 1) * ldh + row] = hl;
+  } else if (row < A.m) {
+    double2* c0 = A.c0 + (size_t)r * A.c0stride;
+    c0[row] = cadd(c0[row], a[row]);
+  }
+  H[(size_t)J * ldh + row] = cscale(csub(g, ha), inv);
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
+  const int r = slot_of(A);
+  const int rt = blockIdx.x, g = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int N = A.N, J = A.J;
+  const double* sc = A.sc + (size_t)r * kScStride;
+  {
+    const int lin = g * gridDim.x + rt;
+    const int row = lin * 256 + tid;
+    if (row <= J) hcol_row(A, r, row);
+    if (lin == 0 && tid == 0) {
+      double* scw = A.sc + (size_t)r * kScStride;
+      if (A.j == 0 && A.beta) A.beta[r] = sc[kScRho];
+      scw[kScRef] = sc[kScScale];
+    }
+  }
+  const int ngroups = gridDim.y;
+  const int row0 = rt * kURows;
+  const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
+  const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
+  const double2* av = A.a + (size_t)r * A.abstride;
+  const double2* bv = A.b + (size_t)r * A.abstride;
+  __shared__ double2 as[kUCols], es[kUCols];
+  const int c0 = g * kUCols;
+  const int nc = min(kUCols, J - c0);
+  const double2 gr = make_double2(sc[kScGrRe], sc[kScGrIm]);
+  const double inv = sc[kScInv];
+  if (tid < nc) {
+    const double2 x1 = av[c0 + tid];
+    as[tid] = x1;
+    es[tid] = csub(bv[c0 + tid], cmul(gr, x1));
+  }
+  __syncthreads();
+  double2 sa[kUpt], se[kUpt];
+#pragma unroll
+  for (int q = 0; q < kUpt; ++q) sa[q] = se[q] = make_double2(0.0, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    const double2 ac = as[c], ec = es[c];
+#pragma unroll
+    for (int q = 0; q < kUpt; ++q) {
+      const int i = row0 + q * 256 + tid;
+      if (i < N) {
+        const double2 qv = qload<VT>(A, r, c0 + c, i);
+        sa[q] = cfma(qv, ac, sa[q]);
+        se[q] = cfma(qv, ec, se[q]);
+      }
+    }
+  }
+  if (ngroups > 1) {
+    double2* Upa = A.Upa + (size_t)r * A.upstride;
+    double2* Upe = A.Upe + (size_t)r * A.upstride;
+#pragma unroll
+    for (int q = 0; q < kUpt; ++q) {
+      const int i = row0 + q * 256 + tid;
+      if (i < N) {
+        Upa[(size_t)g * A.ldq + i] = sa[q];
+        Upe[(size_t)g * A.ldq + i] = se[q];
+      }
+    }
+    unsigned* cnt = A.cnt + (size_t)r * A.cntstride + A.cnt_rows;
+    if (!ticket_last(&cnt[rt], (unsigned)ngroups)) return;
+#pragma unroll
+    for (int q = 0; q < kUpt; ++q) {
+      const int i = row0 + q * 256 + tid;
+      double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+      if (i < N)
+        for (int gg = 0; gg < ngroups; ++gg) {
+          s1 = cadd(s1, Upa[(size_t)gg * A.ldq + i]);
+          s2 = cadd(s2, Upe[(size_t)gg * A.ldq + i]);
+        }
+      sa[q] = s1;
+      se[q] = s2;
+    }
+    ticket_reset(&cnt[rt]);
+  }
+  VT* vout = static_cast<VT*>(A.V) + (size_t)r * A.vstride + (size_t)(J - A.m) * A.ldq;
+  double2* un = A.unext + (size_t)r * A.ustride;
+  VT* ulo = A.ulonext ? static_cast<VT*>(A.ulonext) + (size_t)r * A.zstride : nullptr;
+#pragma unroll
+  for (int q = 0; q < kUpt; ++q) {
+    const int i = row0 + q * 256 + tid;
+    if (i < N) {
+      const double2 ui = u[i];
+      st2(vout, i, cscale(csub(ui, sa[q]), inv));
+      const double2 nx = cscale(csub(csub(ld2(z, i), cmul(gr, ui)), se[q]), inv);
+      un[i] = nx;
+      if (ulo) st2(ulo, i, nx);
+    }
+  }
+}
+
+// y = S c_S + V c_V for slot r (coefficients c[0..m+k))
+template <typename VT>
+__global__ void __launch_bounds__(256) kcombine_kernel(KrylovArgs A, const double2* __restrict__ coef, int cstride,
+                                                       double2* __restrict__ y, size_t ystride, int ncol) {
+  const int r = slot_of(A);
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * kURows;
+  const double2* cf = coef + (size_t)r * cstride;
+  double2 acc[kUpt];
+#pragma unroll
+  for (int q = 0; q < kUpt; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int c = 0; c < ncol; ++c) {
+    const double2 cc = cf[c];
+#pragma unroll
+    for (int q = 0; q < kUpt; ++q) {
+      const int i = i0 + q * 256 + tid;
+      if (i < A.N) acc[q] = cfma(qload<VT>(A, r, c, i), cc, acc[q]);
+    }
+  }
+  double2* yr = y + (size_t)r * ystride;
+#pragma unroll
+  for (int q = 0; q < kUpt; ++q) {
+    const int i = i0 + q * 256 + tid;
+    if (i < A.N) yr[i] = acc[q];
+  }
+}
+
+// dst = H[:n,:n] with column n-1 += a (slot r), dst dense n x n per slot
+__global__ void kpatch_kernel(KrylovArgs A, int n, double2* __restrict__ dst, size_t dstride, int with_a) {
+  const int r = slot_of(A);
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const int c = (int)(e / n), row = (int)(e - (size_t)c * n);
+  const double2* H = A.H + (size_t)r * A.hstride;
+  double2 v = H[(size_t)c * A.ldh + row];
+  if (with_a && c == n - 1) v = cadd(v, A.a[(size_t)r * A.abstride + row]);
+  dst[(size_t)r * dstride + e] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void krylov_alloc(KrylovWork& w, int N, size_t ldq, int ncol_cap, int nslots) {
+  krylov_free(w);
+  w.nrt_dot = (N + kDRows - 1) / kDRows;
+  w.nrt_upd = (N + kURows - 1) / kURows;
+  w.ncol_cap = ncol_cap;
+  w.nslots = nslots;
+  w.ngroups_dot_cap = (ncol_cap + kDCols - 1) / kDCols;
+  w.ngroups_upd_cap = std::max(1, (ncol_cap + kUCols - 1) / kUCols);
+  w.ldp = ncol_cap;
+  w.pstride = (size_t)w.nrt_dot * ncol_cap;
+  w.cdstride = (size_t)4 * w.nrt_dot;
+  w.upstride = ldq * (size_t)w.ngroups_upd_cap;
+  w.abstride = (size_t)ncol_cap;
+  w.cnt_all = w.ngroups_dot_cap;
+  w.cnt_rows = w.ngroups_dot_cap + 1;
+  w.cntstride = w.ngroups_dot_cap + 1 + w.nrt_upd;
+  const size_t S = (size_t)nslots;
+  SGN_HIP(hipMalloc(&w.Pa, sizeof(double2) * w.pstride * S));
+  SGN_HIP(hipMalloc(&w.Pb, sizeof(double2) * w.pstride * S));
+  SGN_HIP(hipMalloc(&w.Pcd, sizeof(double) * w.cdstride * S));
+  SGN_HIP(hipMalloc(&w.Upa, sizeof(double2) * w.upstride * S));
+  SGN_HIP(hipMalloc(&w.Upe, sizeof(double2) * w.upstride * S));
+  SGN_HIP(hipMalloc(&w.a, sizeof(double2) * w.abstride * S));
+  SGN_HIP(hipMalloc(&w.b, sizeof(double2) * w.abstride * S));
+  SGN_HIP(hipMalloc(&w.sc, sizeof(double) * kScStride * S));
+  SGN_HIP(hipMemset(w.sc, 0, sizeof(double) * kScStride * S));
+  SGN_HIP(hipMalloc(&w.cnt, sizeof(unsigned) * (size_t)w.cntstride * S));
+  SGN_HIP(hipMemset(w.cnt, 0, sizeof(unsigned) * (size_t)w.cntstride * S));
+  SGN_HIP(hipDeviceSynchronize());
+}
+
+void krylov_free(KrylovWork& w) {
+  for (void* p : {(void*)w.Pa, (void*)w.Pb, (void*)w.Pcd, (void*)w.Upa, (void*)w.Upe, (void*)w.a, (void*)w.b,
+                  (void*)w.sc, (void*)w.cnt})
+    if (p) (void)hipFree(p);
+  w = KrylovWork{};
+}
+
+void krylov_bind(const KrylovWork& w, KrylovArgs& A) {
+  A.Pa = w.Pa;
+  A.Pb = w.Pb;
+  A.Pcd = w.Pcd;
+  A.ldp = w.ldp;
+  A.pstride = w.pstride;
+  A.cdstride = w.cdstride;
+  A.Upa = w.Upa;
+  A.Upe = w.Upe;
+  A.upstride = w.upstride;
+  A.a = w.a;
+  A.b = w.b;
+  A.abstride = w.abstride;
+  A.sc = w.sc;
+  A.cnt = w.cnt;
+  A.cntstride = w.cntstride;
+  A.cnt_all = w.cnt_all;
+  A.cnt_rows = w.cnt_rows;
+  A.nrt_dot = w.nrt_dot;
+}
+
+static void check_args(const KrylovWork& w, const KrylovArgs& A, int nb) {
+  SGN_REQUIRE(A.J >= 0 && A.J <= w.ncol_cap, SGN_EINVAL, "krylov: J exceeds workspace");
+  SGN_REQUIRE(nb >= 1 && nb <= w.nslots, SGN_EINVAL, "krylov: batch exceeds workspace");
+  SGN_REQUIRE(A.J >= A.m, SGN_EINVAL, "krylov: J < m");
+}
+
+template <typename VT>
+void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, int nb, bool with_z, bool flag_on, hipStream_t s,
+                Profiler* prof) {
+  KrylovArgs A = Ain;
+  krylov_bind(w, A);
+  check_args(w, A, nb);
+  const int ngroups = A.J > 0 ? (A.J + kDCols - 1) / kDCols : 1;
+  const int idx = prof ? prof->begin(K_GS_DOT) : -1;
+  hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, nb), dim3(256), 0, s, A, with_z ? 1 : 0,
+                     flag_on ? 1 : 0);
+  SGN_HIP(hipGetLastError());
+  if (prof) {
+    const double vb = (double)sizeof(VT);
+    const double qbytes = (double)A.N * (16.0 * A.m + vb * (A.J - A.m));
+    prof->end(idx, nb * (qbytes + A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * A.J), nb * 16.0 * (double)A.N * A.J);
+  }
+}
+
+template <typename VT>
+void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, int nb, hipStream_t s, Profiler* prof) {
+  KrylovArgs A = Ain;
+  krylov_bind(w, A);
+  check_args(w, A, nb);
+  const int ngroups = A.J > 0 ? (A.J + kUCols - 1) / kUCols : 1;
+  SGN_REQUIRE((size_t)w.nrt_upd * ngroups * 256 >= (size_t)A.J + 1, SGN_EINVAL,
+              "krylov: grid too small for the Hessenberg column");
+  SGN_REQUIRE(A.J + 1 < A.ldh || A.J + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
+  const int idx = prof ? prof->begin(K_GS_UPDATE) : -1;
+  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(w.nrt_upd, ngroups, nb), dim3(256), 0, s, A);
+  SGN_HIP(hipGetLastError());
+  if (prof) {
+    const double vb = (double)sizeof(VT);
+    const double qbytes = (double)A.N * (16.0 * A.m + vb * (A.J - A.m));
+    // read Q, u, z; write v_J, u' (+ its low-precision copy)
+    const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
+    prof->end(idx, nb * (qbytes + vec + 32.0 * A.J), nb * 16.0 * (double)A.N * A.J);
+  }
+}
+
+template <typename VT>
+void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, int nb, const double2* coef, int cstride,
+                    double2* y, size_t ystride, int ncol, hipStream_t s, Profiler* prof) {
+  KrylovArgs A = Ain;
+  krylov_bind(w, A);
+  SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
+  const int idx = prof ? prof->begin(K_MISC) : -1;
+  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3(w.nrt_upd, 1, nb), dim3(256), 0, s, A, coef, cstride, y, ystride,
+                     ncol);
+  SGN_HIP(hipGetLastError());
+  if (prof) prof->end(idx, nb * (double)A.N * (16.0 * ncol + 16.0), nb * 8.0 * (double)A.N * ncol);
+}
+
+void krylov_patch(const KrylovWork& w, const KrylovArgs& Ain, int nb, int n, double2* dst, size_t dstride,
+                  bool with_a, hipStream_t s) {
+  KrylovArgs A = Ain;
+  krylov_bind(w, A);
+  const size_t tot = (size_t)n * n;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(kpatch_kernel, dim3((unsigned)((tot + 255) / 256), 1, nb), dim3(256), 0, s, A, n, dst,
+                     dstride, with_a ? 1 : 0);
+  SGN_HIP(hipGetLastError());
+}
+
+template void krylov_dot<double2>(const KrylovWork&, const KrylovArgs&, int, bool, bool, hipStream_t, Profiler*);
+template void krylov_dot<float2>(const KrylovWork&, const KrylovArgs&, int, bool, bool, hipStream_t, Profiler*);
+template void krylov_update<double2>(const KrylovWork&, const KrylovArgs&, int, hipStream_t, Profiler*);
+template void krylov_update<float2>(const KrylovWork&, const KrylovArgs&, int, hipStream_t, Profiler*);
+template void krylov_combine<double2>(const KrylovWork&, const KrylovArgs&, int, const double2*, int, double2*,
+                                      size_t, int, hipStream_t, Profiler*);
+template void krylov_combine<float2>(const KrylovWork&, const KrylovArgs&, int, const double2*, int, double2*,
+                                     size_t, int, hipStream_t, Profiler*);

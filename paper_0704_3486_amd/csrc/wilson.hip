@@ -24,54 +24,66 @@ namespace {
 
 constexpr int kWilsonBlock = 128;
 
-// chi = U h  (u row-major 3x3)
-__device__ inline void su3_mul(const double2 u[9], const double2 h[3], double2 out[3]) {
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc = cfma(u[3 * r + c], h[c], acc);
-    out[r] = acc;
-  }
+// complex helpers generic over double2 / float2
+template <typename C> struct Real;
+template <> struct Real<double2> { using type = double; };
+template <> struct Real<float2> { using type = float; };
+template <typename C>
+__device__ inline C mk(typename Real<C>::type x, typename Real<C>::type y) {
+  C c;
+  c.x = x;
+  c.y = y;
+  return c;
 }
-
-// chi = U^dag h
-__device__ inline void su3_dagmul(const double2 u[9], const double2 h[3], double2 out[3]) {
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc = cfmac(u[3 * c + r], h[c], acc);
-    out[r] = acc;
-  }
+template <typename C> __device__ inline C tadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ inline C tsub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ inline C tscale(C a, typename Real<C>::type s) { return mk<C>(a.x * s, a.y * s); }
+template <typename C> __device__ inline C tmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename C> __device__ inline C tfma(C a, C b, C acc) {
+  return mk<C>(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+// acc + conj(a) b
+template <typename C> __device__ inline C tfmac(C a, C b, C acc) {
+  return mk<C>(acc.x + a.x * b.x + a.y * b.y, acc.y + a.x * b.y - a.y * b.x);
 }
 
 // Spin-projection table of (1 + gamma_nu) in the chiral basis:
 //   h0 = p0 + a0 p[i0],  h1 = p1 + a1 p[i1]      (upper two spin components)
 //   lower0 = b0 chi[j0],  lower1 = b1 chi[j1]     (chi = U h, the colour-rotated half spinor)
-// with a, b in {+-1, +-i}; (1 - gamma_nu) negates a0, a1, b0, b1.
+// with a, b in {+-1, +-i} stored as (re, im) sign pairs; (1 - gamma_nu) negates a0, a1, b0, b1.
 struct SpinProj {
   int i0, i1, j0, j1;
-  double2 a0, a1, b0, b1;
+  int a0r, a0i, a1r, a1i, b0r, b0i, b1r, b1i;
 };
 
 __device__ inline SpinProj spin_proj(int nu) {
-  const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
-  const double2 im = make_double2(0.0, 1.0), mim = make_double2(0.0, -1.0);
   switch (nu) {
-    case 0: return SpinProj{3, 2, 1, 0, mim, mim, im, im};
-    case 1: return SpinProj{3, 2, 1, 0, mone, one, one, mone};
-    case 2: return SpinProj{2, 3, 0, 1, mim, im, im, mim};
-    default: return SpinProj{2, 3, 0, 1, one, one, one, one};
+    case 0: return SpinProj{3, 2, 1, 0, 0, -1, 0, -1, 0, 1, 0, 1};
+    case 1: return SpinProj{3, 2, 1, 0, -1, 0, 1, 0, 1, 0, -1, 0};
+    case 2: return SpinProj{2, 3, 0, 1, 0, -1, 0, 1, 0, 1, 0, -1};
+    default: return SpinProj{2, 3, 0, 1, 1, 0, 1, 0, 1, 0, 1, 0};
   }
 }
 
+// (re, im) * sign pair (exact: entries are 0 or +-1)
+template <typename C>
+__device__ inline C unit_mul(int sr, int si, C v, typename Real<C>::type sg) {
+  using R = typename Real<C>::type;
+  return mk<C>(sg * ((R)sr * v.x - (R)si * v.y), sg * ((R)sr * v.y + (R)si * v.x));
+}
+
+// Out_r = H_w(mu) In_r for RB right-hand sides per thread (blockIdx.y picks the
+// group of RB); the link of each hop is loaded once and applied to all RB.
+// Optional (single RHS): scale = *inv_beta on input and output, copy_out = In * scale.
+template <typename C, int RB>
 __global__ void __launch_bounds__(kWilsonBlock)
-wilson_hw_kernel(const double2* __restrict__ links, const double2* __restrict__ in, double2* __restrict__ out,
-                 const double* __restrict__ inv_beta, double2* __restrict__ copy_out, int Lx, int Ly, int Lz,
-                 int Lt, double kappa, double emu, double emmu) {
+wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
+                 size_t ostride, int nrhs, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx,
+                 int Ly, int Lz, int Lt, double kappa_d, double emu_d, double emmu_d) {
+  using R = typename Real<C>::type;
   const int V = Lx * Ly * Lz * Lt;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rb0 = blockIdx.y * RB;
   if (n >= V) return;
   const int x = n % Lx;
   const int y = (n / Lx) % Ly;
@@ -87,71 +99,98 @@ wilson_hw_kernel(const double2* __restrict__ links, const double2* __restrict__ 
   nb[5] = (z == 0) ? n + (Lz - 1) * sz : n - sz;
   nb[6] = (t == Lt - 1) ? n - (Lt - 1) * st : n + st;
   nb[7] = (t == 0) ? n + (Lt - 1) * st : n - st;
+  const R kappa = (R)kappa_d, emu = (R)emu_d, emmu = (R)emmu_d;
 
-  double2 acc[4][3];
+  C acc[RB][4][3];
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int b = 0; b < RB; ++b)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[s][c] = make_double2(0.0, 0.0);
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[b][s][c] = mk<C>(0, 0);
 
   // The eight hops run as a rolled loop so that only one hop's neighbour
-  // spinor and link are live at a time (an unrolled body spills on gfx950).
+  // spinors and link are live at a time (an unrolled body spills on gfx950).
 #pragma unroll 1
   for (int d = 0; d < 8; ++d) {
     const int nu = d >> 1;
     const bool fwd = (d & 1) == 0;  // forward hop: (1 + gamma) U_{n,nu} psi_{n+nu}
     const int m = nb[d];
-    const double sg = fwd ? 1.0 : -1.0;
-    const double phase = (nu == 3) ? (fwd ? emu : emmu) : 1.0;
+    const R sg = fwd ? (R)1 : (R)-1;
+    const R phase = (nu == 3) ? (fwd ? emu : emmu) : (R)1;
     const SpinProj P = spin_proj(nu);
-    double2 h0[3], h1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double2 p0 = in[c * V + m];
-      const double2 p1 = in[(3 + c) * V + m];
-      const double2 pa = in[(3 * P.i0 + c) * V + m];
-      const double2 pb = in[(3 * P.i1 + c) * V + m];
-      h0[c] = cadd(p0, cscale(cmul(P.a0, pa), sg));
-      h1[c] = cadd(p1, cscale(cmul(P.a1, pb), sg));
-    }
     const int ls = fwd ? n : m;  // site that owns the link
-    double2 u[9];
+    C u[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = links[(nu * 9 + e) * V + ls];
-    double2 c0[3], c1[3];
-    if (fwd) {
-      su3_mul(u, h0, c0);
-      su3_mul(u, h1, c1);
-    } else {
-      su3_dagmul(u, h0, c0);
-      su3_dagmul(u, h1, c1);
-    }
-    const double2 b0 = cscale(P.b0, sg * phase), b1 = cscale(P.b1, sg * phase);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      acc[0][c] = cadd(acc[0][c], cscale(c0[c], phase));
-      acc[1][c] = cadd(acc[1][c], cscale(c1[c], phase));
-      const double2 x0 = (P.j0 == 0) ? c0[c] : c1[c];
-      const double2 x1 = (P.j1 == 0) ? c0[c] : c1[c];
-      acc[2][c] = cfma(b0, x0, acc[2][c]);
-      acc[3][c] = cfma(b1, x1, acc[3][c]);
+    for (int b = 0; b < RB; ++b) {
+      if (rb0 + b >= nrhs) break;
+      const C* __restrict__ v = in + (size_t)(rb0 + b) * istride;
+      C h0[3], h1[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C p0 = v[c * V + m];
+        const C p1 = v[(3 + c) * V + m];
+        const C pa = v[(3 * P.i0 + c) * V + m];
+        const C pb = v[(3 * P.i1 + c) * V + m];
+        h0[c] = tadd(p0, unit_mul(P.a0r, P.a0i, pa, sg));
+        h1[c] = tadd(p1, unit_mul(P.a1r, P.a1i, pb, sg));
+      }
+      C c0[3], c1[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        C s0 = mk<C>(0, 0), s1 = mk<C>(0, 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (fwd) {
+            s0 = tfma(u[3 * r + c], h0[c], s0);
+            s1 = tfma(u[3 * r + c], h1[c], s1);
+          } else {
+            s0 = tfmac(u[3 * c + r], h0[c], s0);
+            s1 = tfmac(u[3 * c + r], h1[c], s1);
+          }
+        }
+        c0[r] = tscale(s0, phase);
+        c1[r] = tscale(s1, phase);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[b][0][c] = tadd(acc[b][0][c], c0[c]);
+        acc[b][1][c] = tadd(acc[b][1][c], c1[c]);
+        const C x0 = (P.j0 == 0) ? c0[c] : c1[c];
+        const C x1 = (P.j1 == 0) ? c0[c] : c1[c];
+        acc[b][2][c] = tadd(acc[b][2][c], unit_mul(P.b0r, P.b0i, x0, sg));
+        acc[b][3][c] = tadd(acc[b][3][c], unit_mul(P.b1r, P.b1i, x1, sg));
+      }
     }
   }
 
-  const double scale = inv_beta ? *inv_beta : 1.0;
+  const R scale = inv_beta ? (R)(*inv_beta) : (R)1;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const double g5 = (s < 2) ? 1.0 : -1.0;
+  for (int b = 0; b < RB; ++b) {
+    if (rb0 + b >= nrhs) break;
+    const C* __restrict__ v = in + (size_t)(rb0 + b) * istride;
+    C* __restrict__ o = out + (size_t)(rb0 + b) * ostride;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int idx = (3 * s + c) * V + n;
-      const double2 self = in[idx];
-      // gamma5 (psi - kappa * hops), all times 1/beta
-      const double2 r = csub(self, cscale(acc[s][c], kappa));
-      out[idx] = cscale(r, g5 * scale);
-      if (copy_out) copy_out[idx] = cscale(self, scale);
+    for (int s = 0; s < 4; ++s) {
+      const R g5 = (s < 2) ? (R)1 : (R)-1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int idx = (3 * s + c) * V + n;
+        const C self = v[idx];
+        // gamma5 (psi - kappa * hops), all times 1/beta
+        const C r = tsub(self, tscale(acc[b][s][c], kappa));
+        o[idx] = tscale(r, g5 * scale);
+        if (copy_out) copy_out[idx] = tscale(self, scale);
+      }
     }
   }
+}
+
+__global__ void links_to_f32_kernel(const double2* __restrict__ a, float2* __restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
 __global__ void pack_links_kernel(const double2* __restrict__ g, double2* __restrict__ U, int V, int Lt,
@@ -204,13 +243,57 @@ void wilson_apply(const Lattice& lat, const double2* links, const double2* in, d
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof) {
   const int V = lat.V;
   const int idx = prof ? prof->begin(K_WILSON) : -1;
-  hipLaunchKernelGGL(wilson_hw_kernel, dim3((V + kWilsonBlock - 1) / kWilsonBlock), dim3(kWilsonBlock), 0, s,
-                     links, in, out, inv_beta, copy_out, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa,
-                     lat.emu, lat.emmu);
+  hipLaunchKernelGGL((wilson_hw_kernel<double2, 1>), dim3((V + kWilsonBlock - 1) / kWilsonBlock, 1),
+                     dim3(kWilsonBlock), 0, s, links, in, (size_t)0, out, (size_t)0, 1, inv_beta, copy_out, lat.L[0],
+                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu);
   SGN_HIP(hipGetLastError());
   if (prof) {
     // algorithmic bytes: read v (12), write w (12), 4 links of 9 (36) per site; + copy (12)
     const double per_site = (60.0 + (copy_out ? 12.0 : 0.0)) * 16.0;
     prof->end(idx, per_site * V, 1392.0 * V);
   }
+}
+
+template <typename C>
+static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t istride, C* out, size_t ostride,
+                         int nrhs, hipStream_t s, Profiler* prof) {
+  const int V = lat.V;
+  SGN_REQUIRE(nrhs >= 1, SGN_EINVAL, "wilson: nrhs must be positive");
+  const int idx = prof ? prof->begin(K_WILSON) : -1;
+  const dim3 blk(kWilsonBlock);
+  const unsigned gx = (V + kWilsonBlock - 1) / kWilsonBlock;
+  if (nrhs >= 4 && sizeof(C) == 8) {
+    hipLaunchKernelGGL((wilson_hw_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), blk, 0, s, links, in, istride, out,
+                       ostride, nrhs, nullptr, nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
+                       lat.emmu);
+  } else if (nrhs >= 2) {
+    hipLaunchKernelGGL((wilson_hw_kernel<C, 2>), dim3(gx, (nrhs + 1) / 2), blk, 0, s, links, in, istride, out,
+                       ostride, nrhs, nullptr, nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
+                       lat.emmu);
+  } else {
+    hipLaunchKernelGGL((wilson_hw_kernel<C, 1>), dim3(gx, 1), blk, 0, s, links, in, istride, out, ostride, nrhs,
+                       nullptr, nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu);
+  }
+  SGN_HIP(hipGetLastError());
+  if (prof) {
+    const double b = (double)sizeof(C);
+    // per site: 24 spinor entries per RHS (read + write) and 36 link entries once per launch
+    prof->end(idx, (24.0 * nrhs + 36.0) * b * V, 1392.0 * V * nrhs);
+  }
+}
+
+void wilson_apply_multi(const Lattice& lat, const double2* links, const double2* in, size_t istride, double2* out,
+                        size_t ostride, int nrhs, hipStream_t s, Profiler* prof) {
+  wilson_multi<double2>(lat, links, in, istride, out, ostride, nrhs, s, prof);
+}
+
+void wilson_apply_multi32(const Lattice& lat, const float2* links, const float2* in, size_t istride, float2* out,
+                          size_t ostride, int nrhs, hipStream_t s, Profiler* prof) {
+  wilson_multi<float2>(lat, links, in, istride, out, ostride, nrhs, s, prof);
+}
+
+void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t s) {
+  const size_t n = (size_t)36 * V;
+  hipLaunchKernelGGL(links_to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, links, links32, n);
+  SGN_HIP(hipGetLastError());
 }

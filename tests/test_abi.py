@@ -68,3 +68,40 @@ def test_binding_refuses_host_tensors(sg):
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         sg._dptr(torch.zeros(4, dtype=torch.complex128))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (40, 3), (90, 4)])
+def test_host_eigensolver_matches_lapack(sg, n, seed):
+    # the small eigensolver of the deflation setup runs on the host: check it
+    # against LAPACK (numpy.linalg.eig) without a GPU
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Af = np.asfortranarray(A)
+    w = np.zeros(n, complex)
+    V = np.zeros((n, n), complex, order="F")
+    st = sg.lib.sgn_host_eig(n, Af.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
+                              V.ctypes.data_as(C.c_void_p))
+    assert st == 0
+    ref = np.linalg.eigvals(A)
+    d = np.abs(w[:, None] - ref[None, :])
+    assert d.min(axis=1).max() < 1e-10 * max(1, np.abs(ref).max())
+    assert np.linalg.norm(A @ V - V * w[None, :]) < 1e-10 * np.linalg.norm(A)
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0)
+
+
+def test_host_eigensolver_on_hessenberg_and_triangular(sg):
+    import numpy as np
+
+    rng = np.random.default_rng(9)
+    n = 30
+    for A in (np.triu(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)), -1),
+              np.triu(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))),
+              np.diag(np.arange(1, n + 1) * (1 + 0.5j))):
+        Af = np.asfortranarray(A)
+        w = np.zeros(n, complex)
+        V = np.zeros((n, n), complex, order="F")
+        assert sg.lib.sgn_host_eig(n, Af.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
+                                   V.ctypes.data_as(C.c_void_p)) == 0
+        assert np.linalg.norm(A @ V - V * w[None, :]) < 1e-10 * np.linalg.norm(A)

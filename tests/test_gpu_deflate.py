@@ -1,0 +1,71 @@
+"""GPU deflation setup (sgn_deflate) against the oracle's critical Schur pair."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import deflation, wilson
+
+pytestmark = pytest.mark.gpu
+M_W = -1.6
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0704_3486_amd as sg
+
+    return sg, torch
+
+
+def _check_pair(A, S, T, lam_ref, m):
+    # invariant subspace: A S = S T, S orthonormal, T upper triangular
+    assert np.abs(S.conj().T @ S - np.eye(m)).max() < 1e-12
+    assert np.abs(np.tril(T, -1)).max() == 0.0
+    res = np.linalg.norm(A @ S - S @ T)
+    assert res < 1e-10 * np.abs(lam_ref).max() + 1e-11
+    got = np.sort(np.abs(np.diag(T).real))
+    assert np.allclose(got, np.sort(np.abs(lam_ref.real)), atol=1e-10)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_deflate_small_matches_dense_oracle(env, mu):
+    sg, torch = env
+    dims = (3, 3, 3, 4)
+    links = synth.random_links(dims, 32)
+    A = wilson.hw_matrix(links, dims, mu, M_W)
+    Ad = A.toarray()
+    m = 12
+    S0, T0, lam0, _ = deflation.critical_from_dense(Ad, m)
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        sg.sgn_deflate(ctx, m)
+        print(sg.sgn_deflate_stats(ctx), flush=True)
+        S, T, ev = sg.sgn_deflate_export(ctx)
+        S = S.cpu().numpy()
+        _check_pair(A, S, T, lam0, m)
+        # same invariant subspace as the oracle
+        assert np.abs(S @ S.conj().T - S0 @ S0.conj().T).max() < 1e-9
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_deflate_6x6_matches_arpack(env):
+    sg, torch = env
+    dims, mu, m = (6, 6, 6, 6), 0.2, 20
+    links = synth.random_links(dims, synth.GAUGE_SEED)
+    A = wilson.hw_matrix(links, dims, mu, M_W)
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        sg.sgn_deflate(ctx, m)
+        stats = sg.sgn_deflate_stats(ctx)
+        print(stats, flush=True)
+        S, T, ev = sg.sgn_deflate_export(ctx)
+        S = S.cpu().numpy()
+        S0, T0, th0, _ = deflation.critical_from_arpack(A, m)
+        _check_pair(A, S, T, np.diag(T0), m)
+        assert stats["residual"] < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)

@@ -101,13 +101,18 @@ def small_problem():
     return dims, mu, links, A, S, T, x
 
 
+ORTH = [0, 1]  # SGN_ORTH_CGS2, SGN_ORTH_DELAYED
+
+
+@pytest.mark.parametrize("orth", ORTH)
 @pytest.mark.parametrize("m", [0, 12])
-@pytest.mark.parametrize("k", [2, 10, 40, 100])
-def test_fixed_k_matches_oracle_arnoldi(env, small_problem, m, k):
+@pytest.mark.parametrize("k", [1, 2, 10, 40, 100])
+def test_fixed_k_matches_oracle_arnoldi(env, small_problem, m, k, orth):
     sg, torch = env
     dims, mu, links, A, S, T, x = small_problem
-    print("fixed k", m, k, flush=True)
+    print("fixed k", m, k, orth, flush=True)
     ctx = sg.sgn_create(links, dims, mu, M_W)
+    sg.sgn_set_orthogonalization(ctx, orth)
     try:
         Sm, Tm = (S, T) if m else (None, None)
         if m:
@@ -123,11 +128,13 @@ def test_fixed_k_matches_oracle_arnoldi(env, small_problem, m, k):
         sg.sgn_destroy(ctx)
 
 
-def test_apply_converges_to_exact_small(env, small_problem):
+@pytest.mark.parametrize("orth", ORTH)
+def test_apply_converges_to_exact_small(env, small_problem, orth):
     sg, torch = env
     dims, mu, links, A, S, T, x = small_problem
     exact = matfunc.sgn_spectral_apply(A.toarray(), x)
     ctx = sg.sgn_create(links, dims, mu, M_W)
+    sg.sgn_set_orthogonalization(ctx, orth)
     try:
         sg.sgn_deflate_import(ctx, _dev(torch, S), T)
         y = torch.empty(x.size, dtype=torch.complex128, device="cuda")
@@ -135,6 +142,29 @@ def test_apply_converges_to_exact_small(env, small_problem):
         info = sg.sgn_last_info(ctx)
         print(info, flush=True)
         assert st == sg.SGN_OK and info["converged"] == 1
+        assert _rel(y.cpu().numpy(), exact) < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+@pytest.mark.parametrize("orth", ORTH)
+def test_full_grade_is_exact(env, orth):
+    # Eq. (interp): with k + m = N the composite space is everything and y is exact
+    sg, torch = env
+    dims, mu = (2, 2, 2, 4), 0.3
+    links = synth.random_links(dims, 31)
+    A = wilson.hw_matrix(links, dims, mu, M_W).toarray()
+    x = synth.gaussian_source(dims, 1000)
+    exact = matfunc.sgn_spectral_apply(A, x)
+    S, T, _, _ = deflation.critical_from_dense(A, 8)
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    sg.sgn_set_orthogonalization(ctx, orth)
+    try:
+        sg.sgn_deflate_import(ctx, _dev(torch, S), T)
+        y = torch.empty(x.size, dtype=torch.complex128, device="cuda")
+        sg.sgn_apply_fixed(ctx, _dev(torch, x), y, x.size - 8)
+        info = sg.sgn_last_info(ctx)
+        print(info, flush=True)
         assert _rel(y.cpu().numpy(), exact) < 1e-10
     finally:
         sg.sgn_destroy(ctx)
@@ -188,11 +218,13 @@ def test_c2_6x6_deflated_vs_exact(env, mu):
         sg.sgn_destroy(ctx)
 
 
-def test_edge_cases(env, small_problem):
+@pytest.mark.parametrize("orth", ORTH)
+def test_edge_cases(env, small_problem, orth):
     sg, torch = env
     dims, mu, links, A, S, T, x = small_problem
     N = x.size
     ctx = sg.sgn_create(links, dims, mu, M_W)
+    sg.sgn_set_orthogonalization(ctx, orth)
     try:
         sg.sgn_deflate_import(ctx, _dev(torch, S), T)
         y = torch.empty(N, dtype=torch.complex128, device="cuda")
@@ -234,10 +266,12 @@ def test_edge_cases(env, small_problem):
         sg.sgn_destroy(ctx)
 
 
-def test_deterministic_repeat(env, small_problem):
+@pytest.mark.parametrize("orth", ORTH)
+def test_deterministic_repeat(env, small_problem, orth):
     sg, torch = env
     dims, mu, links, A, S, T, x = small_problem
     ctx = sg.sgn_create(links, dims, mu, M_W)
+    sg.sgn_set_orthogonalization(ctx, orth)
     try:
         sg.sgn_deflate_import(ctx, _dev(torch, S), T)
         y1 = torch.empty(x.size, dtype=torch.complex128, device="cuda")
