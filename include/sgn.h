@@ -158,8 +158,25 @@ int sgn_apply_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
  * schedule).  x and y stay complex128 at the ABI. */
 int sgn_set_precision(sgn_ctx* ctx, int prec);
 
+/* Evaluation of sgn of the small composite matrix (step (v)):
+ *   SGN_SIGN_SCHULZ (default): inverse-free Newton-Schulz iteration
+ *     X <- X (3I - X^2)/2 from X_0 = H/|H|_1 (two complex GEMMs per step);
+ *     falls back to Roberts' iteration if it does not converge;
+ *   SGN_SIGN_ROBERTS: Roberts' iteration S <- (S + S^{-1})/2 (Eq. Roberts)
+ *     with determinantal scaling and Gauss-Jordan inverses. */
+enum { SGN_SIGN_SCHULZ = 0, SGN_SIGN_ROBERTS = 1 };
+int sgn_set_sign_method(sgn_ctx* ctx, int method);
+
 /* Select the orthogonalisation schedule (SGN_ORTH_*); default DELAYED. */
 int sgn_set_orthogonalization(sgn_ctx* ctx, int mode);
+
+/* Checkpoint placement of sgn_apply.  The small-matrix sign is evaluated at
+ * even checkpoints; the first successful sgn_apply on a field records the k
+ * at which convergence to tol was certified, and later applies with the same
+ * tol start checkpointing there (results then no longer depend on what ran
+ * before).  sgn_set_schedule sets that k explicitly (0: record it again on
+ * the next apply).  The stopping test is the same in every case. */
+int sgn_set_schedule(sgn_ctx* ctx, int k_first, double tol);
 
 /* Statistics of the last sgn_apply / sgn_apply_fixed. */
 int sgn_last_info(const sgn_ctx* ctx, sgn_info* info);
@@ -202,6 +219,12 @@ int sgn_profile_reset(sgn_ctx* ctx);
  * is the small eigensolver of the deflation setup.  SGN_ESINGULAR if the QR
  * iteration does not converge. */
 int sgn_host_eig(int n, const double* A, double* w, double* V);
+
+/* Copy the leading n x n block of the device composite matrix H of Eq.
+ * (eq:newH) from the last apply (before the final re-orthogonalisation of
+ * its last column in the delayed schedule) to host H (column-major), c0 =
+ * S^dag x (m entries) and beta = |x_perp|.  Any pointer may be NULL. */
+int sgn_debug_hessenberg(const sgn_ctx* ctx, int n, double* H, double* c0, double* beta);
 
 /* ---- errors ------------------------------------------------------------ */
 const char* sgn_strerror(int status);

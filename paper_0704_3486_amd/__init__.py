@@ -29,6 +29,8 @@ SGN_ENOCONV = -4
 SGN_ESINGULAR = -5
 SGN_ESTATE = -6
 SGN_EDEFL = -7
+SGN_SIGN_SCHULZ = 0
+SGN_SIGN_ROBERTS = 1
 SGN_ORTH_CGS2 = 0
 SGN_ORTH_DELAYED = 1
 SGN_PREC_FP64 = 0
@@ -86,8 +88,11 @@ def _load():
         "sgn_deflate": (i, [vp, i]),
         "sgn_set_orthogonalization": (i, [vp, i]),
         "sgn_set_precision": (i, [vp, i]),
+        "sgn_set_schedule": (i, [vp, i, d]),
+        "sgn_set_sign_method": (i, [vp, i]),
         "sgn_deflate_stats": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
         "sgn_host_eig": (i, [i, vp, vp, vp]),
+        "sgn_debug_hessenberg": (i, [vp, i, vp, vp, vp]),
         "sgn_strerror": (cp, [i]),
         "sgn_last_error": (cp, [vp]),
     }
@@ -235,6 +240,14 @@ def sgn_set_precision(ctx, prec):
     return _check(ctx, _lib.sgn_set_precision(ctx, int(prec)))
 
 
+def sgn_set_schedule(ctx, k_first, tol):
+    return _check(ctx, _lib.sgn_set_schedule(ctx, int(k_first), float(tol)))
+
+
+def sgn_set_sign_method(ctx, method):
+    return _check(ctx, _lib.sgn_set_sign_method(ctx, int(method)))
+
+
 def sgn_set_orthogonalization(ctx, mode):
     return _check(ctx, _lib.sgn_set_orthogonalization(ctx, int(mode)))
 
@@ -276,6 +289,16 @@ def sgn_profile_read(ctx):
 
 def sgn_profile_reset(ctx):
     return _check(ctx, _lib.sgn_profile_reset(ctx))
+
+
+def sgn_debug_hessenberg(ctx, n, m):
+    """(H[:n,:n], c0, beta) of the last apply, host numpy."""
+    H = np.zeros(n * n, dtype=np.complex128)
+    c0 = np.zeros(max(m, 1), dtype=np.complex128)
+    beta = C.c_double()
+    _check(ctx, _lib.sgn_debug_hessenberg(ctx, int(n), H.ctypes.data_as(C.c_void_p), c0.ctypes.data_as(C.c_void_p),
+                                          C.byref(beta)))
+    return H.reshape(n, n, order="F"), c0[:m], beta.value
 
 
 def sgn_strerror(status):

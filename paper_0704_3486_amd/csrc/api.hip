@@ -245,9 +245,15 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     breakdown = x_in_schur;
   } else {
     // Krylov loop (step (iv)) with checkpoints (step (v))
+    // First checkpoint: where the previous apply on this field certified
+    // convergence (its last-but-one checkpoint), else 32.  This only moves the
+    // checkpoints; the stopping test is the same.
     int next_ck;
+    const bool hinted = c->k_hint > 0 && c->tol_hint == tol;
     if (fixed_k >= 0) {
       next_ck = fixed_k;
+    } else if (hinted) {
+      next_ck = std::min(kmax, std::max(2, even_up(c->k_hint)));
     } else {
       next_ck = std::min(kmax, std::max(2, even_up(std::min(32, kmax / 2))));
     }
@@ -309,23 +315,35 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
         err = e;
         if (e <= tol) {
           converged = true;
+          // e ~ error at the previous checkpoint: remember where it was
+          // certified (once per field, so later applies share one schedule)
+          if (c->k_hint == 0) {
+            c->k_hint = prev_ck;
+            c->tol_hint = tol;
+          }
           break;
         }
         prev_ck = k;
-        // choose the next checkpoint
-        int nk;
+        // choose the next checkpoint from a geometric error model
+        // err(k) ~ e_b exp(r (k - k_b)), with r from the last two estimates or
+        // from the previous apply on this field
+        double rate = 0.0;
         if (hist.size() >= 2) {
           const auto& a = hist[hist.size() - 2];
           const auto& b = hist[hist.size() - 1];
-          const double rho_log = (std::log(b.second) - std::log(a.second)) / std::max(1, b.first - a.first);
-          if (rho_log < -1e-6) {
-            // err(k) ~ b.second * exp(rho_log (k - b.first)); want err <= tol / 2
-            const double steps = std::log(0.5 * tol / b.second) / rho_log;
-            const int target = b.first + (int)std::ceil(1.05 * steps);
-            nk = (target <= k) ? k + 4 : target;  // previous checkpoint should be below tol: confirm
-          } else {
-            nk = k + std::max(8, k / 2);
-          }
+          rate = (std::log(b.second) - std::log(a.second)) / std::max(1, b.first - a.first);
+          if (rate < -1e-6 && c->rate_hint == 0.0) c->rate_hint = rate;
+        } else if (c->rate_hint < 0.0) {
+          rate = c->rate_hint;
+        }
+        int nk;
+        if (hist.empty() && hinted) {
+          nk = k + 4;  // confirm the remembered k
+        } else if (!hist.empty() && rate < -1e-6) {
+          const auto& b = hist.back();
+          const double steps = std::log(0.5 * tol / b.second) / rate;
+          const int target = b.first + (int)std::ceil(1.05 * steps);
+          nk = (target <= k) ? k + 4 : target;  // previous checkpoint should be below tol: confirm
         } else {
           nk = k + std::max(8, k / 2);
         }
@@ -399,6 +417,8 @@ void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std:
   SGN_HIP(hipStreamSynchronize(s));
   c->T = std::move(Th);
   c->m = m;
+  c->k_hint = 0;
+  c->rate_hint = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +580,20 @@ int sgn_apply_fixed(sgn_ctx* c, const double* x, double* y, int k) {
   });
 }
 
+int sgn_debug_hessenberg(const sgn_ctx* cc, int n, double* H, double* c0, double* beta) {
+  sgn_ctx* c = const_cast<sgn_ctx*>(cc);
+  return guarded(c, [&] {
+    SGN_REQUIRE(c->Hc && n >= 0 && n <= c->ncap, SGN_EINVAL, "no Hessenberg of that size");
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    if (H && n)
+      SGN_HIP(hipMemcpy2D(H, sizeof(double2) * n, c->Hc, sizeof(double2) * c->ncap, sizeof(double2) * n, n,
+                          hipMemcpyDeviceToHost));
+    if (c0 && c->m) SGN_HIP(hipMemcpy(c0, c->c0, sizeof(double2) * c->m, hipMemcpyDeviceToHost));
+    if (beta) SGN_HIP(hipMemcpy(beta, &c->scal[0], sizeof(double), hipMemcpyDeviceToHost));
+    return SGN_OK;
+  });
+}
+
 int sgn_set_precision(sgn_ctx* c, int prec) {
   return guarded(c, [&] {
     SGN_REQUIRE(prec == SGN_PREC_FP64 || prec == SGN_PREC_MIXED, SGN_EINVAL, "unknown precision");
@@ -567,11 +601,31 @@ int sgn_set_precision(sgn_ctx* c, int prec) {
     if (prec == c->prec) return SGN_OK;
     c->release_workspace();
     c->prec = prec;
+    c->k_hint = 0;
+    c->rate_hint = 0.0;
     if (prec == SGN_PREC_MIXED && !c->links32) {
       SGN_HIP(hipMalloc(&c->links32, sizeof(float2) * 36 * (size_t)c->lat.V));
       wilson_links_f32(c->links, c->links32, c->lat.V, c->stream);
       SGN_HIP(hipStreamSynchronize(c->stream));
     }
+    return SGN_OK;
+  });
+}
+
+int sgn_set_schedule(sgn_ctx* c, int k_first, double tol) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(k_first >= 0, SGN_EINVAL, "k_first must be >= 0");
+    c->k_hint = k_first;
+    c->tol_hint = tol;
+    c->rate_hint = 0.0;
+    return SGN_OK;
+  });
+}
+
+int sgn_set_sign_method(sgn_ctx* c, int method) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(method == SGN_SIGN_SCHULZ || method == SGN_SIGN_ROBERTS, SGN_EINVAL, "unknown sign method");
+    c->dense.method = method;
     return SGN_OK;
   });
 }

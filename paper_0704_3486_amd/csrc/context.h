@@ -57,6 +57,10 @@ struct sgn_ctx {
   GsWork gs;
   KrylovWork kw;
   DenseWork dense;
+  // convergence history of previous applies on this field (checkpoint placement only)
+  int k_hint = 0;
+  double tol_hint = 0.0;
+  double rate_hint = 0.0;
   int orth = 1;  // 0: two classical Gram-Schmidt passes per step; 1: one reduction, delayed re-orthogonalisation
 
   ~sgn_ctx() { release(); }

@@ -26,8 +26,10 @@ namespace {
 constexpr int kGjThreads = 256;
 constexpr int kGjTile = 4;  // columns per workgroup in the trailing update
 
+// panel rows are padded to bp + 1 entries so that a column of the panel
+// (one entry per row) spreads over the LDS banks
 inline size_t gj_lds_bytes(int n, int bp) {
-  return sizeof(double2) * (size_t)n * bp + sizeof(int) * (size_t)(2 * n + (n & 1)) + sizeof(double2) * (size_t)n;
+  return sizeof(double2) * (size_t)n * (bp + 1) + sizeof(int) * (size_t)(2 * n + (n & 1)) + sizeof(double2) * (size_t)n;
 }
 
 __device__ inline void argmax_merge(double& v, int& i, double v2, int i2) {
@@ -41,10 +43,17 @@ __device__ inline void argmax_merge(double& v, int& i, double v2, int i2) {
 template <int BP>
 __global__ void __launch_bounds__(kGjThreads)
 gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int n, int p0,
-                int* __restrict__ rowpiv, double* __restrict__ logpiv, int* __restrict__ flag) {
+                int* __restrict__ rowpiv, double* __restrict__ logpiv, int* __restrict__ flag, size_t mstride) {
+  // blockIdx.y selects the matrix of a batch
+  Min += (size_t)blockIdx.y * mstride;
+  Mout += (size_t)blockIdx.y * mstride;
+  rowpiv += (size_t)blockIdx.y * n;
+  logpiv += (size_t)blockIdx.y * n;
+  flag += blockIdx.y;
+  constexpr int PS = BP + 1;  // padded row stride
   extern __shared__ double2 smem[];
-  double2* panel = smem;                                   // n * BP
-  int* used = reinterpret_cast<int*>(panel + (size_t)n * BP);  // n
+  double2* panel = smem;                                   // n * PS
+  int* used = reinterpret_cast<int*>(panel + (size_t)n * PS);  // n
   int* inR = used + n;                                     // n
   double2* fcol = reinterpret_cast<double2*>(inR + n + (n & 1));  // n (16-byte aligned)
   __shared__ int rp[BP];
@@ -55,8 +64,8 @@ gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int
   const int b = min(BP, n - p0);
 
   for (int idx = tid; idx < n * BP; idx += kGjThreads) {
-    const int row = idx / BP, col = idx - row * BP;
-    panel[idx] = (col < b) ? Min[(size_t)(p0 + col) * n + row] : make_double2(0.0, 0.0);
+    const int col = idx / n, row = idx - col * n;  // coalesced over rows of the global column
+    panel[row * PS + col] = (col < b) ? Min[(size_t)(p0 + col) * n + row] : make_double2(0.0, 0.0);
   }
   for (int i = tid; i < n; i += kGjThreads) {
     used[i] = 0;
@@ -71,7 +80,7 @@ gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int
     double bv = -1.0;
     int bi = n;
     for (int i = tid; i < n; i += kGjThreads)
-      if (!used[i]) argmax_merge(bv, bi, cabs2(panel[i * BP + t]), i);
+      if (!used[i]) argmax_merge(bv, bi, cabs2(panel[i * PS + t]), i);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const double v2 = __shfl_xor(bv, off, 64);
@@ -91,7 +100,7 @@ gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int
       rp[t] = i;
       used[i] = 1;
       inR[i] = 1;
-      double2 piv = panel[i * BP + t];
+      double2 piv = panel[i * PS + t];
       double a2 = cabs2(piv);
       if (!(a2 > 0.0) || !isfinite(a2)) {
         if (blockIdx.x == 0) *flag = 1;
@@ -109,18 +118,18 @@ gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int
     const double2 inv = pivinv;
     // scale the pivot row; the eliminated entry becomes 1/piv
     if (tid < BP) {
-      const double2 v = panel[r * BP + tid];
-      panel[r * BP + tid] = (tid == t) ? inv : cmul(v, inv);
+      const double2 v = panel[r * PS + tid];
+      panel[r * PS + tid] = (tid == t) ? inv : cmul(v, inv);
     }
     __syncthreads();
     // eliminate column t from every other row (multipliers staged first)
-    for (int i = tid; i < n; i += kGjThreads) fcol[i] = panel[i * BP + t];
+    for (int i = tid; i < n; i += kGjThreads) fcol[i] = panel[i * PS + t];
     __syncthreads();
     for (int idx = tid; idx < n * BP; idx += kGjThreads) {
       const int i = idx / BP, s = idx - i * BP;
       if (i == r) continue;
-      const double2 base = (s == t) ? make_double2(0.0, 0.0) : panel[idx];
-      panel[idx] = csub(base, cmul(fcol[i], panel[r * BP + s]));
+      const double2 base = (s == t) ? make_double2(0.0, 0.0) : panel[i * PS + s];
+      panel[i * PS + s] = csub(base, cmul(fcol[i], panel[r * PS + s]));
     }
     __syncthreads();
   }
@@ -129,7 +138,7 @@ gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int
   if (blockIdx.x == 0) {
     for (int idx = tid; idx < n * b; idx += kGjThreads) {
       const int col = idx / n, row = idx - col * n;
-      Mout[(size_t)(p0 + col) * n + row] = panel[row * BP + col];
+      Mout[(size_t)(p0 + col) * n + row] = panel[row * PS + col];
     }
   }
   // trailing update of this workgroup's column tile
@@ -150,7 +159,7 @@ gj_panel_kernel(const double2* __restrict__ Min, double2* __restrict__ Mout, int
       double2 acc = inR[i] ? make_double2(0.0, 0.0) : Min[(size_t)j * n + i];
 #pragma unroll
       for (int s = 0; s < BP; ++s)
-        if (s < b) acc = cfma(panel[i * BP + s], mr[jj][s], acc);
+        if (s < b) acc = cfma(panel[i * PS + s], mr[jj][s], acc);
       Mout[(size_t)j * n + i] = acc;
     }
   }
@@ -163,7 +172,15 @@ __global__ void __launch_bounds__(256)
 newton_combine_kernel(double2* __restrict__ S, const double2* __restrict__ M, int n,
                       const int* __restrict__ rowpiv, const double* __restrict__ logpiv,
                       double* __restrict__ scal, double* __restrict__ part, unsigned* __restrict__ counter,
-                      int nblk) {
+                      int nblk, size_t mstride) {
+  // blockIdx.y selects the matrix of a batch
+  S += (size_t)blockIdx.y * mstride;
+  M += (size_t)blockIdx.y * mstride;
+  rowpiv += (size_t)blockIdx.y * n;
+  logpiv += (size_t)blockIdx.y * n;
+  scal += (size_t)blockIdx.y * 8;
+  part += (size_t)blockIdx.y * 2 * nblk;
+  counter += blockIdx.y;
   extern __shared__ int rinv[];  // n
   __shared__ double red[2][256];
   __shared__ double mu_s;
@@ -252,12 +269,23 @@ __global__ void zero_kernel(double2* __restrict__ p, size_t n) {
   if (i < n) p[i] = make_double2(0.0, 0.0);
 }
 
-__global__ void set_scal_kernel(double* scal, int* flag) {
-  scal[0] = 1e30;
-  scal[1] = 0.0;
-  scal[2] = 1e30;
-  scal[3] = 1.0;
-  *flag = 0;
+__global__ void set_scal_kernel(double* scal, int* flag, int nb) {
+  for (int b = 0; b < nb; ++b) {
+    scal[8 * b + 0] = 1e30;
+    scal[8 * b + 1] = 0.0;
+    scal[8 * b + 2] = 1e30;
+    scal[8 * b + 3] = 1.0;
+    flag[b] = 0;
+  }
+}
+
+// batched strided copy: B_b = A_b (rows x cols), blockIdx.y = b
+__global__ void copy_mat_batched_kernel(const double2* __restrict__ A, int lda, size_t astride,
+                                        double2* __restrict__ B, int ldb, size_t bstride, int rows, int cols) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rows * cols) return;
+  const int c = (int)(e / rows), r = (int)(e - (size_t)c * rows);
+  B[(size_t)blockIdx.y * bstride + (size_t)c * ldb + r] = A[(size_t)blockIdx.y * astride + (size_t)c * lda + r];
 }
 
 // c[i] = sum_{q<m} F[i][q] c0[q] + beta F[i][m];  err = |c - [cprev; 0]| / |c|
@@ -310,7 +338,7 @@ __global__ void finite_kernel(const double2* __restrict__ v, size_t n, int* __re
 }
 
 template <int BP>
-void launch_panel(const double2* Min, double2* Mout, int n, int p0, DenseWork& d, hipStream_t s) {
+void launch_panel(const double2* Min, double2* Mout, int n, int p0, int nb, DenseWork& d, hipStream_t s) {
   const size_t lds = gj_lds_bytes(n, BP);
   static size_t configured = 0;
   if (lds > configured) {
@@ -319,8 +347,8 @@ void launch_panel(const double2* Min, double2* Mout, int n, int p0, DenseWork& d
     configured = lds;
   }
   const int nblk = (n + kGjTile - 1) / kGjTile;
-  hipLaunchKernelGGL(gj_panel_kernel<BP>, dim3(nblk), dim3(kGjThreads), lds, s, Min, Mout, n, p0, d.rowpiv,
-                     d.logpiv, d.flag);
+  hipLaunchKernelGGL(gj_panel_kernel<BP>, dim3(nblk, nb), dim3(kGjThreads), lds, s, Min, Mout, n, p0, d.rowpiv,
+                     d.logpiv, d.flag, (size_t)n * n);
 }
 
 }  // namespace
@@ -345,25 +373,30 @@ static int panel_width(int n) {
   return 0;
 }
 
-void dense_alloc(DenseWork& d, int n) {
-  if (n <= d.ncap) return;
+void dense_alloc(DenseWork& d, int n, int nb) {
+  if (n <= d.ncap && nb <= d.nbcap) return;
+  const int ncap = std::max(n, d.ncap), nbcap = std::max(nb, d.nbcap);
   dense_free(d);
-  d.ncap = n;
-  const size_t nn = (size_t)n * n;
+  d.ncap = ncap;
+  d.nbcap = nbcap;
+  const size_t nn = (size_t)ncap * ncap * nbcap;
   SGN_HIP(hipMalloc(&d.S, sizeof(double2) * nn));
   SGN_HIP(hipMalloc(&d.Ma, sizeof(double2) * nn));
   SGN_HIP(hipMalloc(&d.Mb, sizeof(double2) * nn));
-  SGN_HIP(hipMalloc(&d.rowpiv, sizeof(int) * (size_t)n));
-  SGN_HIP(hipMalloc(&d.logpiv, sizeof(double) * (size_t)n));
-  SGN_HIP(hipMalloc(&d.scal, sizeof(double) * 8));
-  SGN_HIP(hipHostMalloc(&d.host_scal, sizeof(double) * 8, hipHostMallocDefault));
-  SGN_HIP(hipMalloc(&d.flag, sizeof(int) * 2));
-  SGN_HIP(hipMalloc(&d.counters, sizeof(unsigned) * 4));
-  SGN_HIP(hipMemset(d.counters, 0, sizeof(unsigned) * 4));
+  SGN_HIP(hipMalloc(&d.rowpiv, sizeof(int) * (size_t)ncap * nbcap));
+  SGN_HIP(hipMalloc(&d.logpiv, sizeof(double) * (size_t)ncap * nbcap));
+  SGN_HIP(hipMalloc(&d.scal, sizeof(double) * 8 * (size_t)nbcap));
+  SGN_HIP(hipHostMalloc(&d.host_scal, sizeof(double) * 8 * (size_t)nbcap, hipHostMallocDefault));
+  SGN_HIP(hipHostMalloc(&d.host_flag, sizeof(int) * (size_t)nbcap, hipHostMallocDefault));
+  SGN_HIP(hipMalloc(&d.flag, sizeof(int) * (size_t)nbcap));
+  SGN_HIP(hipMalloc(&d.counters, sizeof(unsigned) * (size_t)nbcap));
+  SGN_HIP(hipMemset(d.counters, 0, sizeof(unsigned) * (size_t)nbcap));
   d.npart = 1024;
-  SGN_HIP(hipMalloc(&d.part, sizeof(double) * 2 * (size_t)d.npart));
+  SGN_HIP(hipMalloc(&d.part, sizeof(double) * 2 * (size_t)d.npart * nbcap));
   SGN_HIP(hipDeviceSynchronize());
 }
+
+void dense_alloc(DenseWork& d, int n) { dense_alloc(d, n, 1); }
 
 void dense_free(DenseWork& d) {
   if (d.S) (void)hipFree(d.S);
@@ -373,10 +406,15 @@ void dense_free(DenseWork& d) {
   if (d.logpiv) (void)hipFree(d.logpiv);
   if (d.scal) (void)hipFree(d.scal);
   if (d.host_scal) (void)hipHostFree(d.host_scal);
+  if (d.host_flag) (void)hipHostFree(d.host_flag);
   if (d.flag) (void)hipFree(d.flag);
   if (d.counters) (void)hipFree(d.counters);
   if (d.part) (void)hipFree(d.part);
+  if (d.spart) (void)hipFree(d.spart);
+  if (d.host_spart) (void)hipHostFree(d.host_spart);
+  const int method = d.method;
   d = DenseWork{};
+  d.method = method;
 }
 
 void dev_zero(double2* p, size_t n, hipStream_t s) {
@@ -417,20 +455,27 @@ void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, co
   SGN_HIP(hipGetLastError());
 }
 
-int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
-               Profiler* prof) {
-  SGN_REQUIRE(n >= 1, SGN_EINVAL, "dense_sign: n must be positive");
+static int dense_sign_newton_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride,
+                                     double2* F, int ldf, size_t fstride, hipStream_t s, Profiler* prof) {
+  SGN_REQUIRE(n >= 1 && nb >= 1, SGN_EINVAL, "dense_sign: n and the batch must be positive");
   const int bp = panel_width(n);
   SGN_REQUIRE(bp > 0, SGN_EINVAL, "dense_sign: matrix too large for the LDS panel");
-  dense_alloc(d, n);
-  dev_copy_mat(A, lda, d.S, n, n, n, s);
-  hipLaunchKernelGGL(set_scal_kernel, dim3(1), dim3(1), 0, s, d.scal, d.flag);
+  dense_alloc(d, n, nb);
+  const size_t nn = (size_t)n * n;
+  {
+    const size_t tot = nn;
+    hipLaunchKernelGGL(copy_mat_batched_kernel, dim3((unsigned)((tot + 255) / 256), nb), dim3(256), 0, s, A, lda,
+                       astride, d.S, n, nn, n, n);
+    SGN_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(set_scal_kernel, dim3(1), dim3(1), 0, s, d.scal, d.flag, nb);
   SGN_HIP(hipGetLastError());
   const int npanel = (n + bp - 1) / bp;
-  const int nblk_comb = (int)std::min<size_t>((size_t)d.npart, ((size_t)n * n + 255) / 256);
+  const int nblk_comb = (int)std::min<size_t>((size_t)d.npart, (nn + 255) / 256);
   const int maxit = 100;
-  double prev = 1e30;
-  int done_extra = -1;
+  std::vector<double> prev(nb, 1e30);
+  std::vector<char> done(nb, 0);
+  bool extra = false;
   for (int it = 1; it <= maxit; ++it) {
     const int idx = prof ? prof->begin(K_GJ_PANEL) : -1;
     const double2* Min = d.S;
@@ -438,35 +483,223 @@ int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int l
     for (int pi = 0; pi < npanel; ++pi) {
       double2* Mout = bufs[pi & 1];
       switch (bp) {
-        case 16: launch_panel<16>(Min, Mout, n, pi * bp, d, s); break;
-        case 8: launch_panel<8>(Min, Mout, n, pi * bp, d, s); break;
-        case 4: launch_panel<4>(Min, Mout, n, pi * bp, d, s); break;
-        default: launch_panel<2>(Min, Mout, n, pi * bp, d, s); break;
+        case 16: launch_panel<16>(Min, Mout, n, pi * bp, nb, d, s); break;
+        case 8: launch_panel<8>(Min, Mout, n, pi * bp, nb, d, s); break;
+        case 4: launch_panel<4>(Min, Mout, n, pi * bp, nb, d, s); break;
+        default: launch_panel<2>(Min, Mout, n, pi * bp, nb, d, s); break;
       }
       SGN_HIP(hipGetLastError());
       Min = Mout;
     }
-    if (prof) prof->end(idx, 2.0 * 16.0 * (double)n * n * npanel, 8.0 * (double)n * n * n);
+    if (prof) prof->end(idx, nb * 2.0 * 16.0 * (double)nn * npanel, nb * 8.0 * (double)nn * n);
     const int idx2 = prof ? prof->begin(K_NEWTON_COMBINE) : -1;
-    hipLaunchKernelGGL(newton_combine_kernel, dim3(nblk_comb), dim3(256), sizeof(int) * (size_t)n, s, d.S, Min, n,
-                       d.rowpiv, d.logpiv, d.scal, d.part, d.counters, nblk_comb);
+    hipLaunchKernelGGL(newton_combine_kernel, dim3(nblk_comb, nb), dim3(256), sizeof(int) * (size_t)n, s, d.S, Min,
+                       n, d.rowpiv, d.logpiv, d.scal, d.part, d.counters, nblk_comb, nn);
     SGN_HIP(hipGetLastError());
-    if (prof) prof->end(idx2, 3.0 * 16.0 * (double)n * n, 10.0 * (double)n * n);
-    SGN_HIP(hipMemcpyAsync(d.host_scal, d.scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
-    int hflag = 0;
-    SGN_HIP(hipMemcpyAsync(&d.host_scal[4], d.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (prof) prof->end(idx2, nb * 3.0 * 16.0 * (double)nn, nb * 10.0 * (double)nn);
+    SGN_HIP(hipMemcpyAsync(d.host_scal, d.scal, sizeof(double) * 8 * nb, hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipMemcpyAsync(d.host_flag, d.flag, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
     SGN_HIP(hipStreamSynchronize(s));
-    std::memcpy(&hflag, &d.host_scal[4], sizeof(int));
-    if (hflag) throw SgnError{SGN_ESINGULAR, "Roberts iteration met a singular iterate"};
-    const double ch = d.host_scal[0];
-    if (!std::isfinite(ch)) throw SgnError{SGN_ESINGULAR, "Roberts iteration diverged (non-finite iterate)"};
-    if (done_extra >= 0) {
-      dev_copy_mat(d.S, n, F, ldf, n, n, s);
+    for (int b = 0; b < nb; ++b) {
+      if (d.host_flag[b]) throw SgnError{SGN_ESINGULAR, "Roberts iteration met a singular iterate"};
+      if (!std::isfinite(d.host_scal[8 * b]))
+        throw SgnError{SGN_ESINGULAR, "Roberts iteration diverged (non-finite iterate)"};
+    }
+    if (extra) {
+      hipLaunchKernelGGL(copy_mat_batched_kernel, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, s, d.S, n,
+                         nn, F, ldf, fstride, n, n);
+      SGN_HIP(hipGetLastError());
       return it;
     }
     // converged (or stagnated at rounding level): one more step settles the last digits
-    if (ch <= 1e-13 || (it > 4 && ch < 1e-9 && ch > 0.5 * prev)) done_extra = it;
-    prev = ch;
+    bool all = true;
+    for (int b = 0; b < nb; ++b) {
+      const double ch = d.host_scal[8 * b];
+      if (ch <= 1e-13 || (it > 4 && ch < 1e-9 && ch > 0.5 * prev[b])) done[b] = 1;
+      prev[b] = ch;
+      all = all && done[b];
+    }
+    if (all) extra = true;
   }
   throw SgnError{SGN_ESINGULAR, "Roberts iteration did not converge in 100 steps"};
+}
+
+// ---------------------------------------------------------------------------
+// Inverse-free evaluation: Newton-Schulz iteration X <- X (3I - X^2) / 2 from
+// X_0 = A / |A|_1.  It converges to sgn(A) when every eigenvalue z of X_0
+// satisfies |1 - z^2| < 1, which holds for the composite Arnoldi matrices of
+// this method (their Ritz values have |Im| well below |Re| once the critical
+// eigenvalues are deflated); growth of the small eigenvalues is 3/2 per step,
+// then quadratic.  Each step is two complex GEMMs.  When the residual
+// |X^2 - I|_F / sqrt(n) does not fall below 1e-8 within 60 steps (or is not
+// finite), the caller falls back to Roberts' iteration with Gauss-Jordan
+// inverses, which converges for any matrix without eigenvalues on the
+// imaginary axis.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kGT = 32;  // output tile
+constexpr int kGK = 16;  // k chunk
+
+// C = alpha A B (MODE 0) or C = 3I - A B with part[tile] = sum |A B - I|^2 (MODE 1);
+// n x n column-major (ld n), blockIdx.z = matrix of the batch (stride nn)
+template <int MODE>
+__global__ void __launch_bounds__(256) zgemm_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                    double2* __restrict__ C, int n, double alpha,
+                                                    double* __restrict__ part, size_t nn) {
+  A += (size_t)blockIdx.z * nn;
+  B += (size_t)blockIdx.z * nn;
+  C += (size_t)blockIdx.z * nn;
+  __shared__ double2 As[kGT][kGK + 1];
+  __shared__ double2 Bs[kGK][kGT + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.x * kGT, j0 = blockIdx.y * kGT;
+  double2 c00 = make_double2(0, 0), c01 = c00, c10 = c00, c11 = c00;
+  for (int k0 = 0; k0 < n; k0 += kGK) {
+    for (int e = tid; e < kGT * kGK; e += 256) {
+      const int i = e & (kGT - 1), kk = e / kGT;  // A tile: coalesced over i
+      const int gi = i0 + i, gk = k0 + kk;
+      As[i][kk] = (gi < n && gk < n) ? A[(size_t)gk * n + gi] : make_double2(0, 0);
+      const int kb = e & (kGK - 1), jb = e / kGK;  // B tile: coalesced over k
+      const int gkb = k0 + kb, gj = j0 + jb;
+      Bs[kb][jb] = (gkb < n && gj < n) ? B[(size_t)gj * n + gkb] : make_double2(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; ++kk) {
+      const double2 a0 = As[tx][kk], a1 = As[tx + 16][kk];
+      const double2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
+      c00 = cfma(a0, b0, c00);
+      c01 = cfma(a0, b1, c01);
+      c10 = cfma(a1, b0, c10);
+      c11 = cfma(a1, b1, c11);
+    }
+    __syncthreads();
+  }
+  double2 cv[4] = {c00, c01, c10, c11};
+  double p = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gi = i0 + tx + 16 * (q >> 1), gj = j0 + ty + 16 * (q & 1);
+    if (gi < n && gj < n) {
+      double2 v = cv[q];
+      if (MODE == 0) {
+        v = cscale(v, alpha);
+      } else {
+        const double dI = (gi == gj) ? 1.0 : 0.0;
+        const double2 dv = make_double2(v.x - dI, v.y);
+        p += cabs2(dv);
+        v = make_double2(3.0 * dI - v.x, -v.y);
+      }
+      C[(size_t)gj * n + gi] = v;
+    }
+  }
+  if (MODE == 1) {
+    __shared__ double red[256];
+    red[tid] = p;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+  }
+}
+
+// X_b = A_b / |A_b|_1 (max column sum of |a_ij|); one workgroup per matrix
+__global__ void __launch_bounds__(256) norm1_scale_kernel(const double2* __restrict__ A, int lda, size_t astride,
+                                                          double2* __restrict__ X, int n, size_t nn) {
+  A += (size_t)blockIdx.x * astride;
+  X += (size_t)blockIdx.x * nn;
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double mx = 0.0;
+  for (int j = tid; j < n; j += 256) {
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum += sqrt(cabs2(A[(size_t)j * lda + i]));
+    mx = fmax(mx, sum);
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  const double inv = red[0] > 0.0 ? 1.0 / red[0] : 1.0;
+  for (size_t e = tid; e < (size_t)n * n; e += 256) {
+    const int j = (int)(e / n), i = (int)(e - (size_t)j * n);
+    X[e] = cscale(A[(size_t)j * lda + i], inv);
+  }
+}
+
+}  // namespace
+
+// returns iterations, or -1 if the iteration did not converge
+static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F,
+                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof) {
+  dense_alloc(d, n, nb);
+  const size_t nn = (size_t)n * n;
+  const int nt = (n + kGT - 1) / kGT;
+  const size_t nparts = (size_t)nt * nt * nb;
+  if (d.nspart < nparts) {
+    if (d.spart) (void)hipFree(d.spart);
+    if (d.host_spart) (void)hipHostFree(d.host_spart);
+    SGN_HIP(hipMalloc(&d.spart, sizeof(double) * nparts));
+    SGN_HIP(hipHostMalloc(&d.host_spart, sizeof(double) * nparts, hipHostMallocDefault));
+    d.nspart = nparts;
+  }
+  hipLaunchKernelGGL(norm1_scale_kernel, dim3(nb), dim3(256), 0, s, A, lda, astride, d.S, n, nn);
+  SGN_HIP(hipGetLastError());
+  double2* X = d.S;
+  double2* Y = d.Ma;
+  double2* Xn = d.Mb;
+  const dim3 grid(nt, nt, nb);
+  const int maxit = 60;
+  int iters = 0;
+  for (int it = 1; it <= maxit; ++it) {
+    const int idx = prof ? prof->begin(K_GJ_PANEL) : -1;
+    hipLaunchKernelGGL(zgemm_kernel<1>, grid, dim3(256), 0, s, X, X, Y, n, 1.0, d.spart, nn);
+    SGN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(zgemm_kernel<0>, grid, dim3(256), 0, s, X, Y, Xn, n, 0.5, nullptr, nn);
+    SGN_HIP(hipGetLastError());
+    if (prof) prof->end(idx, nb * 2.0 * 3.0 * 16.0 * (double)nn, nb * 2.0 * 8.0 * (double)nn * n);
+    std::swap(X, Xn);
+    iters = it;
+    if (it < 6) continue;  // growth phase: no need to look yet
+    SGN_HIP(hipMemcpyAsync(d.host_spart, d.spart, sizeof(double) * nparts, hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    double worst = 0.0;
+    bool ok = true;
+    for (int b = 0; b < nb; ++b) {
+      double sum = 0.0;
+      for (size_t t = 0; t < (size_t)nt * nt; ++t) sum += d.host_spart[(size_t)b * nt * nt + t];
+      const double r = std::sqrt(sum / n);  // |X^2 - I| of the iterate before this update
+      if (!std::isfinite(r) || r > 1e3) ok = false;
+      worst = std::max(worst, r);
+    }
+    if (!ok) return -1;
+    // error after the update ~ (3/2) (r/2)^2: below 1e-14 once r < 1e-7
+    if (worst < 1e-7) break;
+    if (it == maxit) return -1;
+  }
+  hipLaunchKernelGGL(copy_mat_batched_kernel, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, s, X, n, nn, F,
+                     ldf, fstride, n, n);
+  SGN_HIP(hipGetLastError());
+  return iters;
+}
+
+int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,
+                       size_t fstride, hipStream_t s, Profiler* prof) {
+  SGN_REQUIRE(n >= 1 && nb >= 1, SGN_EINVAL, "dense_sign: n and the batch must be positive");
+  if (d.method != 1) {
+    const int it = dense_sign_ns_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof);
+    if (it >= 0) return it;
+  }
+  return dense_sign_newton_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof);
+}
+
+int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
+               Profiler* prof) {
+  return dense_sign_batched(d, n, 1, A, lda, 0, F, ldf, 0, s, prof);
 }

@@ -153,7 +153,13 @@ void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t 
 
 // dense kernels (dense.hip)
 struct DenseWork {
+  int method = 0;         // 0: Newton-Schulz with Roberts/Gauss-Jordan fallback; 1: Roberts only
+  double* spart = nullptr;  // Newton-Schulz residual partials
+  double* host_spart = nullptr;
+  size_t nspart = 0;
   int ncap = 0;
+  int nbcap = 0;          // matrices per batch
+  int* host_flag = nullptr;
   double2* S = nullptr;   // n x n iterate
   double2* Ma = nullptr;  // Gauss-Jordan ping-pong
   double2* Mb = nullptr;
@@ -167,10 +173,14 @@ struct DenseWork {
   int npart = 0;
 };
 void dense_alloc(DenseWork& d, int n);
+void dense_alloc(DenseWork& d, int n, int nb);
 void dense_free(DenseWork& d);
 // F = sgn(A) (n x n, ld = lda); returns iterations; throws SGN_ESINGULAR
 int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
                Profiler* prof);
+// F_b = sgn(A_b) for nb matrices at strides astride / fstride; iterates until every matrix converged
+int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,
+                       size_t fstride, hipStream_t s, Profiler* prof);
 // c[i] = sum_{q<m} F[i][q] c0[q] + beta * F[i][m]  (i < n); err = |c - cprev_pad| / |c| if cprev
 void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, const double* beta, double2* c,
                   const double2* cprev, int nprev, double* err, hipStream_t s);

@@ -15,7 +15,9 @@ enum {
   kScGrRe,       // gam / rho
   kScGrIm,
   kScScale,      // |z| / rho: reference size of the next candidate
-  kScRef,        // reference size for this step's breakdown test
+  kScRef,        // reference size for the breakdown test of an even step (odd: kScRef + 1)
+  kScRefOdd,
+  kScRawC,       // raw sums of the dot pass: u^dag u, u^dag z (re, im), |z|^2 (4 slots)
   kScStride = 16
 };
 

@@ -30,7 +30,7 @@
 
 namespace {
 
-constexpr int kRpl = 16;                // dot: rows per lane
+constexpr int kRpl = 8;                 // dot: rows per lane
 constexpr int kCpw = 4;                 // dot: columns per wavefront
 constexpr int kDRows = 64 * kRpl;       // dot: rows per tile
 constexpr int kDCols = kCpw * 4;        // dot: columns per workgroup (4 wavefronts)
@@ -60,23 +60,6 @@ __device__ inline double wsum1(double v) {
   return v;
 }
 
-__device__ inline bool ticket_last(unsigned* counter, unsigned total) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == total - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = is_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-__device__ inline void ticket_reset(unsigned* counter) {
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // column c of Q for right-hand side slot r
 template <typename VT>
 __device__ inline double2 qload(const KrylovArgs& A, int r, int c, int i) {
@@ -88,8 +71,38 @@ __device__ inline double2 qload(const KrylovArgs& A, int r, int c, int i) {
 __device__ inline int slot_of(const KrylovArgs& A) { return A.act ? A.act[blockIdx.z] : (int)blockIdx.z; }
 
 // ---------------------------------------------------------------------------
+// dot pass: per (row tile, column group) partial sums of Q^dag u and Q^dag z,
+// plus |u|^2, u^dag z, |z|^2 per row tile.  No cross-workgroup communication:
+// the partials are reduced by kred_kernel in a fixed order.
 template <typename VT>
-__global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z, int flag_on) {
+__device__ inline void dot_cols(const double2* __restrict__ q, const double2 uv[kRpl], const double2 zv[kRpl],
+                                int row0, int lane, int N, double2& aa, double2& bb) {
+#pragma unroll
+  for (int t = 0; t < kRpl; ++t) {
+    const int i = row0 + t * 64 + lane;
+    if (i < N) {
+      const double2 qv = q[i];
+      aa = cfmac(qv, uv[t], aa);
+      bb = cfmac(qv, zv[t], bb);
+    }
+  }
+}
+template <typename VT>
+__device__ inline void dot_cols(const float2* __restrict__ q, const double2 uv[kRpl], const double2 zv[kRpl],
+                                int row0, int lane, int N, double2& aa, double2& bb) {
+#pragma unroll
+  for (int t = 0; t < kRpl; ++t) {
+    const int i = row0 + t * 64 + lane;
+    if (i < N) {
+      const double2 qv = ld2(q, i);
+      aa = cfmac(qv, uv[t], aa);
+      bb = cfmac(qv, zv[t], bb);
+    }
+  }
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
   const int r = slot_of(A);
   const int rt = blockIdx.x, cg = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -100,33 +113,24 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z, int
   double2* Pa = A.Pa + (size_t)r * A.pstride;
   double2* Pb = A.Pb + (size_t)r * A.pstride;
   double* Pcd = A.Pcd + (size_t)r * A.cdstride;
-  double2* av = A.a + (size_t)r * A.abstride;
-  double2* bv = A.b + (size_t)r * A.abstride;
-  double* sc = A.sc + (size_t)r * kScStride;
-  unsigned* cnt = A.cnt + (size_t)r * A.cntstride;
-  const int nrt = A.nrt_dot;
-  const int ngroups = gridDim.y;
 
   double2 uv[kRpl], zv[kRpl];
 #pragma unroll
-  for (int q = 0; q < kRpl; ++q) {
-    const int i = row0 + q * 64 + lane;
-    uv[q] = (i < N) ? u[i] : make_double2(0.0, 0.0);
-    zv[q] = (with_z && i < N) ? ld2(z, i) : make_double2(0.0, 0.0);
+  for (int t = 0; t < kRpl; ++t) {
+    const int i = row0 + t * 64 + lane;
+    uv[t] = (i < N) ? u[i] : make_double2(0.0, 0.0);
+    zv[t] = (with_z && i < N) ? ld2(z, i) : make_double2(0.0, 0.0);
   }
 #pragma unroll
   for (int cc = 0; cc < kCpw; ++cc) {
     const int c = cg * kDCols + wave * kCpw + cc;
     if (c < J) {
       double2 aa = make_double2(0.0, 0.0), bb = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int q = 0; q < kRpl; ++q) {
-        const int i = row0 + q * 64 + lane;
-        if (i < N) {
-          const double2 qv = qload<VT>(A, r, c, i);
-          aa = cfmac(qv, uv[q], aa);
-          bb = cfmac(qv, zv[q], bb);
-        }
+      if (c < A.m) {
+        dot_cols<VT>(A.S + (size_t)c * A.ldq, uv, zv, row0, lane, N, aa, bb);
+      } else {
+        const VT* q = static_cast<const VT*>(A.V) + (size_t)r * A.vstride + (size_t)(c - A.m) * A.ldq;
+        dot_cols<VT>(q, uv, zv, row0, lane, N, aa, bb);
       }
       aa = wsum2(aa);
       bb = wsum2(bb);
@@ -136,125 +140,124 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z, int
       }
     }
   }
-  if (cg == 0) {
+  if (cg == 0 && wave == 0) {
+    // |u|^2, u^dag z, |z|^2 of this row tile (the four wavefronts hold the
+    // same rows, so one of them accounts for the tile)
     double cs = 0.0, zs = 0.0;
     double2 ds = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int q = 0; q < kRpl; ++q) {
-      cs += cabs2(uv[q]);
-      zs += cabs2(zv[q]);
-      ds = cfmac(uv[q], zv[q], ds);
+    for (int t = 0; t < kRpl; ++t) {
+      cs += cabs2(uv[t]);
+      zs += cabs2(zv[t]);
+      ds = cfmac(uv[t], zv[t], ds);
     }
-    __shared__ double red4[4][4];
     cs = wsum1(cs);
     zs = wsum1(zs);
     ds = wsum2(ds);
     if (lane == 0) {
-      red4[wave][0] = cs;
-      red4[wave][1] = ds.x;
-      red4[wave][2] = ds.y;
-      red4[wave][3] = zs;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      const int q = threadIdx.x;
-      Pcd[4 * rt + q] = ((red4[0][q] + red4[1][q]) + red4[2][q]) + red4[3][q];
+      Pcd[4 * rt + 0] = cs;
+      Pcd[4 * rt + 1] = ds.x;
+      Pcd[4 * rt + 2] = ds.y;
+      Pcd[4 * rt + 3] = zs;
     }
   }
-  if (!ticket_last(&cnt[cg], (unsigned)nrt)) return;
-  {
-    __shared__ double2 ra[16][kDCols + 1], rb[16][kDCols + 1];
-    const int cc = threadIdx.x & 15, sub = threadIdx.x >> 4;
-    const int c = cg * kDCols + cc;
-    double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-    if (c < J)
-      for (int t = sub; t < nrt; t += 16) {
-        sa = cadd(sa, Pa[(size_t)t * A.ldp + c]);
-        sb = cadd(sb, Pb[(size_t)t * A.ldp + c]);
-      }
-    ra[sub][cc] = sa;
-    rb[sub][cc] = sb;
-    __syncthreads();
-    if (threadIdx.x < 16 && c < J) {
-      double2 s1 = ra[0][cc], s2 = rb[0][cc];
-      for (int k = 1; k < 16; ++k) {
-        s1 = cadd(s1, ra[k][cc]);
-        s2 = cadd(s2, rb[k][cc]);
-      }
-      av[c] = s1;
-      bv[c] = s2;
-    }
-  }
-  ticket_reset(&cnt[cg]);
-  if (!ticket_last(&cnt[A.cnt_all], (unsigned)ngroups)) return;
-  // last workgroup of this right-hand side: the step scalars
-  __shared__ double tr[7][256];
-  const int tid = threadIdx.x;
-  double s[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int t = tid; t < nrt; t += 256) {
-    s[0] += Pcd[4 * t];
-    s[1] += Pcd[4 * t + 1];
-    s[2] += Pcd[4 * t + 2];
-    s[3] += Pcd[4 * t + 3];
-  }
-  for (int c = tid; c < J; c += 256) {
-    const double2 x1 = av[c], x2 = bv[c];
-    s[4] += cabs2(x1);
-    const double2 ab = cmulc(x1, x2);
-    s[5] += ab.x;
-    s[6] += ab.y;
-  }
-  for (int q = 0; q < 7; ++q) tr[q][tid] = s[q];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off)
-      for (int q = 0; q < 7; ++q) tr[q][tid] += tr[q][tid + off];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double c = tr[0][0], aa = tr[4][0];
-    const double2 d = make_double2(tr[1][0], tr[2][0]);
-    const double2 ab = make_double2(tr[5][0], tr[6][0]);
-    const double rho2 = c - aa;
-    const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
-    const bool finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(tr[3][0]);
-    const bool brk = !(rho > 1e-14 * sc[kScRef]) || !finite;
-    const double inv = brk ? 0.0 : 1.0 / rho;
-    const double2 gam = cscale(csub(d, ab), inv);
-    sc[kScC] = c;
-    sc[kScRho] = brk ? 0.0 : rho;
-    sc[kScInv] = inv;
-    sc[kScGamRe] = gam.x;
-    sc[kScGamIm] = gam.y;
-    sc[kScGrRe] = gam.x * inv;
-    sc[kScGrIm] = gam.y * inv;
-    sc[kScScale] = sqrt(tr[3][0]) * inv;
-    if (flag_on && A.flag) {
-      int* f = A.flag + r;
-      if (!finite)
-        *f = -1;
-      else if (brk && *f == 0)
-        *f = A.j + 1;
-    }
-  }
-  ticket_reset(&cnt[A.cnt_all]);
 }
 
-// ---------------------------------------------------------------------------
-// Hessenberg column J (one row per thread) and the re-orthogonalisation of
-// column J-1; at j = 0 the correction goes to c0 instead.
-__device__ void hcol_row(const KrylovArgs& A, int r, int row) {
-  const int J = A.J;
+// reduce the dot partials over row tiles in a fixed order: a, b (one column
+// per thread) and, in workgroup 0, the scalars c, d, |z|^2 (to sc[kScC..])
+__global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
+  const int r = slot_of(A);
+  const int J = A.J, nrt = A.nrt_dot;
+  const double2* Pa = A.Pa + (size_t)r * A.pstride;
+  const double2* Pb = A.Pb + (size_t)r * A.pstride;
+  const double* Pcd = A.Pcd + (size_t)r * A.cdstride;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < J) {
+    double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+    for (int t = 0; t < nrt; ++t) {
+      sa = cadd(sa, Pa[(size_t)t * A.ldp + c]);
+      sb = cadd(sb, Pb[(size_t)t * A.ldp + c]);
+    }
+    A.a[(size_t)r * A.abstride + c] = sa;
+    A.b[(size_t)r * A.abstride + c] = sb;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 4) {
+    double s = 0.0;
+    for (int t = 0; t < nrt; ++t) s += Pcd[4 * t + threadIdx.x];
+    A.sc[(size_t)r * kScStride + kScRawC + threadIdx.x] = s;
+  }
+}
+
+// Step scalars from a, b and the raw sums; every workgroup of the update
+// computes them identically (fixed order), workgroup 0 also records them.
+struct StepScalars {
+  double rho, inv;
+  double2 gam, gr;
+  bool brk, finite;
+  double scale;
+};
+
+__device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* LDS [3][256] */) {
+  const int J = A.J, tid = threadIdx.x;
+  const double2* a = A.a + (size_t)r * A.abstride;
+  const double2* b = A.b + (size_t)r * A.abstride;
   const double* sc = A.sc + (size_t)r * kScStride;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int c = tid; c < J; c += 256) {
+    const double2 x1 = a[c], x2 = b[c];
+    s0 += cabs2(x1);
+    const double2 ab = cmulc(x1, x2);
+    s1 += ab.x;
+    s2 += ab.y;
+  }
+  red[tid] = s0;
+  red[256 + tid] = s1;
+  red[512 + tid] = s2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      red[tid] += red[tid + off];
+      red[256 + tid] += red[256 + tid + off];
+      red[512 + tid] += red[512 + tid + off];
+    }
+    __syncthreads();
+  }
+  StepScalars st;
+  const double c = sc[kScRawC];
+  const double2 d = make_double2(sc[kScRawC + 1], sc[kScRawC + 2]);
+  const double zz = sc[kScRawC + 3];
+  const double aa = red[0];
+  const double2 ab = make_double2(red[256], red[512]);
+  const double rho2 = c - aa;
+  const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+  st.finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(zz);
+  st.brk = !(rho > 1e-14 * sc[kScRef + (A.j & 1)]) || !st.finite;
+  st.inv = st.brk ? 0.0 : 1.0 / rho;
+  st.rho = st.brk ? 0.0 : rho;
+  st.gam = cscale(csub(d, ab), st.inv);
+  st.gr = cscale(st.gam, st.inv);
+  st.scale = sqrt(zz) * st.inv;
+  __syncthreads();  // red is reused by the caller
+  return st;
+}
+
+// Hessenberg column J and the re-orthogonalisation of column J-1, one row per
+// wavefront (the lanes split the sum over columns); at j = 0 the correction
+// goes to c0 instead.
+__device__ void hcol_row_wave(const KrylovArgs& A, int r, int row, int lane, const StepScalars& st) {
+  const int J = A.J;
   const double2* a = A.a + (size_t)r * A.abstride;
   const double2* b = A.b + (size_t)r * A.abstride;
   double2* H = A.H + (size_t)r * A.hstride;
   const int ldh = A.ldh;
-  const double rho = sc[kScRho], inv = sc[kScInv];
-  const double2 g = (row < J) ? b[row] : make_double2(sc[kScGamRe], sc[kScGamIm]);
-  double2 ha = make_double2(0.0, 0.0);
   const int lim = (A.j > 0) ? J - 1 : J;
-  for (int l = 0; l < lim; ++l) ha = cfma(H[(size_t)l * ldh + row], a[l], ha);
+  double2 ha = make_double2(0.0, 0.0);
+  if (row < J)  // row J of columns < J-1 is below the subdiagonal (zero)
+    for (int l = lane; l < lim; l += 64) ha = cfma(H[(size_t)l * ldh + row], a[l], ha);
+  ha = wsum2(ha);
+  if (lane != 0) return;
+  const double rho = st.rho, inv = st.inv;
+  const double2 g = (row < J) ? b[row] : st.gam;
   if (A.j > 0) {
     const double2 hl = (row < J) ? cadd(H[(size_t)(J - 1) * ldh + row], a[row]) : make_double2(rho, 0.0);
     ha = cfma(hl, a[J - 1], ha);
@@ -266,95 +269,95 @@ __device__ void hcol_row(const KrylovArgs& A, int r, int row) {
   H[(size_t)J * ldh + row] = cscale(csub(g, ha), inv);
 }
 
+// update pass: each workgroup owns 64 rows and all J columns; its four
+// wavefronts take interleaved quarters of the columns and are combined in LDS.
+template <typename VT>
+__device__ inline void upd_col(const double2* __restrict__ q, int i, bool ok, double2 ac, double2 ec, double2& sa,
+                               double2& se) {
+  if (ok) {
+    const double2 qv = q[i];
+    sa = cfma(qv, ac, sa);
+    se = cfma(qv, ec, se);
+  }
+}
+template <typename VT>
+__device__ inline void upd_col(const float2* __restrict__ q, int i, bool ok, double2 ac, double2 ec, double2& sa,
+                               double2& se) {
+  if (ok) {
+    const double2 qv = ld2(q, i);
+    sa = cfma(qv, ac, sa);
+    se = cfma(qv, ec, se);
+  }
+}
+
 template <typename VT>
 __global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
   const int r = slot_of(A);
-  const int rt = blockIdx.x, g = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = A.N, J = A.J;
-  const double* sc = A.sc + (size_t)r * kScStride;
+  __shared__ double red[3 * 256];
+  const StepScalars st = step_scalars(A, r, red);
+  // Hessenberg column J (one row per wavefront over the whole grid)
   {
-    const int lin = g * gridDim.x + rt;
-    const int row = lin * 256 + tid;
-    if (row <= J) hcol_row(A, r, row);
-    if (lin == 0 && tid == 0) {
-      double* scw = A.sc + (size_t)r * kScStride;
-      if (A.j == 0 && A.beta) A.beta[r] = sc[kScRho];
-      scw[kScRef] = sc[kScScale];
+    const int nwaves = gridDim.x * 4;
+    for (int row = blockIdx.x * 4 + wave; row <= J; row += nwaves) hcol_row_wave(A, r, row, lane, st);
+    if (blockIdx.x == 0 && tid == 0) {
+      double* sc = A.sc + (size_t)r * kScStride;
+      sc[kScRho] = st.rho;
+      sc[kScInv] = st.inv;
+      sc[kScGamRe] = st.gam.x;
+      sc[kScGamIm] = st.gam.y;
+      sc[kScGrRe] = st.gr.x;
+      sc[kScGrIm] = st.gr.y;
+      sc[kScScale] = st.scale;
+      // reference size for the next step's breakdown test (the other parity
+      // slot: this step's slot is still being read by other workgroups)
+      sc[kScRef + ((A.j + 1) & 1)] = st.scale;
+      if (A.j == 0 && A.beta) A.beta[r] = st.rho;
+      if (A.flag) {
+        int* f = A.flag + r;
+        if (!st.finite)
+          *f = -1;
+        else if (st.brk && *f == 0)
+          *f = A.j + 1;
+      }
     }
   }
-  const int ngroups = gridDim.y;
-  const int row0 = rt * kURows;
-  const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
-  const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
   const double2* av = A.a + (size_t)r * A.abstride;
   const double2* bv = A.b + (size_t)r * A.abstride;
-  __shared__ double2 as[kUCols], es[kUCols];
-  const int c0 = g * kUCols;
-  const int nc = min(kUCols, J - c0);
-  const double2 gr = make_double2(sc[kScGrRe], sc[kScGrIm]);
-  const double inv = sc[kScInv];
-  if (tid < nc) {
-    const double2 x1 = av[c0 + tid];
-    as[tid] = x1;
-    es[tid] = csub(bv[c0 + tid], cmul(gr, x1));
+  const int i = blockIdx.x * 64 + lane;
+  const bool ok = i < N;
+  double2 sa = make_double2(0.0, 0.0), se = make_double2(0.0, 0.0);
+  // S columns (FP64)
+  for (int c = wave; c < min(J, A.m); c += 4) {
+    const double2 ac = av[c];
+    upd_col<double2>(A.S + (size_t)c * A.ldq, i, ok, ac, csub(bv[c], cmul(st.gr, ac)), sa, se);
   }
+  // Krylov columns (VT)
+  const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride;
+  int c = A.m + ((wave - A.m % 4) + 4) % 4;  // first column >= m with c % 4 == wave
+  if (c < A.m) c += 4;
+#pragma unroll 4
+  for (; c < J; c += 4) {
+    const double2 ac = av[c];
+    upd_col<VT>(V + (size_t)(c - A.m) * A.ldq, i, ok, ac, csub(bv[c], cmul(st.gr, ac)), sa, se);
+  }
+  // combine the four wavefronts (fixed order)
+  __shared__ double2 ps[2][4][64];
+  ps[0][wave][lane] = sa;
+  ps[1][wave][lane] = se;
   __syncthreads();
-  double2 sa[kUpt], se[kUpt];
-#pragma unroll
-  for (int q = 0; q < kUpt; ++q) sa[q] = se[q] = make_double2(0.0, 0.0);
-  for (int c = 0; c < nc; ++c) {
-    const double2 ac = as[c], ec = es[c];
-#pragma unroll
-    for (int q = 0; q < kUpt; ++q) {
-      const int i = row0 + q * 256 + tid;
-      if (i < N) {
-        const double2 qv = qload<VT>(A, r, c0 + c, i);
-        sa[q] = cfma(qv, ac, sa[q]);
-        se[q] = cfma(qv, ec, se[q]);
-      }
-    }
-  }
-  if (ngroups > 1) {
-    double2* Upa = A.Upa + (size_t)r * A.upstride;
-    double2* Upe = A.Upe + (size_t)r * A.upstride;
-#pragma unroll
-    for (int q = 0; q < kUpt; ++q) {
-      const int i = row0 + q * 256 + tid;
-      if (i < N) {
-        Upa[(size_t)g * A.ldq + i] = sa[q];
-        Upe[(size_t)g * A.ldq + i] = se[q];
-      }
-    }
-    unsigned* cnt = A.cnt + (size_t)r * A.cntstride + A.cnt_rows;
-    if (!ticket_last(&cnt[rt], (unsigned)ngroups)) return;
-#pragma unroll
-    for (int q = 0; q < kUpt; ++q) {
-      const int i = row0 + q * 256 + tid;
-      double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
-      if (i < N)
-        for (int gg = 0; gg < ngroups; ++gg) {
-          s1 = cadd(s1, Upa[(size_t)gg * A.ldq + i]);
-          s2 = cadd(s2, Upe[(size_t)gg * A.ldq + i]);
-        }
-      sa[q] = s1;
-      se[q] = s2;
-    }
-    ticket_reset(&cnt[rt]);
-  }
-  VT* vout = static_cast<VT*>(A.V) + (size_t)r * A.vstride + (size_t)(J - A.m) * A.ldq;
-  double2* un = A.unext + (size_t)r * A.ustride;
-  VT* ulo = A.ulonext ? static_cast<VT*>(A.ulonext) + (size_t)r * A.zstride : nullptr;
-#pragma unroll
-  for (int q = 0; q < kUpt; ++q) {
-    const int i = row0 + q * 256 + tid;
-    if (i < N) {
-      const double2 ui = u[i];
-      st2(vout, i, cscale(csub(ui, sa[q]), inv));
-      const double2 nx = cscale(csub(csub(ld2(z, i), cmul(gr, ui)), se[q]), inv);
-      un[i] = nx;
-      if (ulo) st2(ulo, i, nx);
-    }
+  if (wave == 0 && ok) {
+    const double2 ta = cadd(cadd(ps[0][0][lane], ps[0][1][lane]), cadd(ps[0][2][lane], ps[0][3][lane]));
+    const double2 te = cadd(cadd(ps[1][0][lane], ps[1][1][lane]), cadd(ps[1][2][lane], ps[1][3][lane]));
+    const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
+    const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
+    VT* vout = static_cast<VT*>(A.V) + (size_t)r * A.vstride + (size_t)(J - A.m) * A.ldq;
+    const double2 ui = u[i];
+    st2(vout, i, cscale(csub(ui, ta), st.inv));
+    const double2 nx = cscale(csub(csub(ld2(z, i), cmul(st.gr, ui)), te), st.inv);
+    A.unext[(size_t)r * A.ustride + i] = nx;
+    if (A.ulonext) st2(static_cast<VT*>(A.ulonext) + (size_t)r * A.zstride, i, nx);
   }
 }
 
@@ -474,9 +477,11 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, int nb, bool with_z,
   krylov_bind(w, A);
   check_args(w, A, nb);
   const int ngroups = A.J > 0 ? (A.J + kDCols - 1) / kDCols : 1;
+  if (!flag_on) A.flag = nullptr;
   const int idx = prof ? prof->begin(K_GS_DOT) : -1;
-  hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, nb), dim3(256), 0, s, A, with_z ? 1 : 0,
-                     flag_on ? 1 : 0);
+  hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, nb), dim3(256), 0, s, A, with_z ? 1 : 0);
+  SGN_HIP(hipGetLastError());
+  hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (A.J + 255) / 256), 1, nb), dim3(256), 0, s, A);
   SGN_HIP(hipGetLastError());
   if (prof) {
     const double vb = (double)sizeof(VT);
@@ -490,12 +495,10 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, int nb, hipStream
   KrylovArgs A = Ain;
   krylov_bind(w, A);
   check_args(w, A, nb);
-  const int ngroups = A.J > 0 ? (A.J + kUCols - 1) / kUCols : 1;
-  SGN_REQUIRE((size_t)w.nrt_upd * ngroups * 256 >= (size_t)A.J + 1, SGN_EINVAL,
-              "krylov: grid too small for the Hessenberg column");
-  SGN_REQUIRE(A.J + 1 < A.ldh || A.J + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
+  SGN_REQUIRE(A.J + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
+  const int nblk = (A.N + 63) / 64;
   const int idx = prof ? prof->begin(K_GS_UPDATE) : -1;
-  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(w.nrt_upd, ngroups, nb), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(nblk, 1, nb), dim3(256), 0, s, A);
   SGN_HIP(hipGetLastError());
   if (prof) {
     const double vb = (double)sizeof(VT);
