@@ -267,7 +267,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
         ka.u = ucur;
         ka.unext = unext;
         if (mixed) {
-          wilson_apply_multi32(c->lat, c->links32, u32cur, 0, c->z32, 0, 1, s, prof);
+          wilson_apply_multi32(c->lat, c->links32, u32cur, 0, c->z32, 0, 1, true, s, prof);
           ka.z = c->z32;
           ka.ulonext = u32next;
           krylov_dot<float2>(c->kw, ka, 1, true, true, s, prof);

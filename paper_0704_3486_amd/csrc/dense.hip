@@ -608,29 +608,39 @@ __global__ void __launch_bounds__(256) zgemm_kernel(const double2* __restrict__ 
 }
 
 // X_b = A_b / |A_b|_1 (max column sum of |a_ij|); one workgroup per matrix
-__global__ void __launch_bounds__(256) norm1_scale_kernel(const double2* __restrict__ A, int lda, size_t astride,
-                                                          double2* __restrict__ X, int n, size_t nn) {
-  A += (size_t)blockIdx.x * astride;
-  X += (size_t)blockIdx.x * nn;
+// column sums of |A_ij| (one wavefront per column, lanes over rows)
+__global__ void __launch_bounds__(256) colsum_kernel(const double2* __restrict__ A, int lda, size_t astride,
+                                                     double* __restrict__ cs, int n) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const double2* col = A + (size_t)blockIdx.y * astride + (size_t)j * lda;
+  double sum = 0.0;
+  for (int i = lane; i < n; i += 64) sum += sqrt(cabs2(col[i]));
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane == 0) cs[(size_t)blockIdx.y * n + j] = sum;
+}
+
+// X = A / |A|_1 (the 1-norm as the largest column sum; every workgroup takes
+// the maximum itself)
+__global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __restrict__ A, int lda, size_t astride,
+                                                             const double* __restrict__ cs, double2* __restrict__ X,
+                                                             int n, size_t nn) {
+  const int b = blockIdx.y;
   __shared__ double red[256];
-  const int tid = threadIdx.x;
   double mx = 0.0;
-  for (int j = tid; j < n; j += 256) {
-    double sum = 0.0;
-    for (int i = 0; i < n; ++i) sum += sqrt(cabs2(A[(size_t)j * lda + i]));
-    mx = fmax(mx, sum);
-  }
-  red[tid] = mx;
+  for (int j = threadIdx.x; j < n; j += 256) mx = fmax(mx, cs[(size_t)b * n + j]);
+  red[threadIdx.x] = mx;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
   const double inv = red[0] > 0.0 ? 1.0 / red[0] : 1.0;
-  for (size_t e = tid; e < (size_t)n * n; e += 256) {
-    const int j = (int)(e / n), i = (int)(e - (size_t)j * n);
-    X[e] = cscale(A[(size_t)j * lda + i], inv);
-  }
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nn) return;
+  const int j = (int)(e / n), i = (int)(e - (size_t)j * n);
+  X[(size_t)b * nn + e] = cscale(A[(size_t)b * astride + (size_t)j * lda + i], inv);
 }
 
 }  // namespace
@@ -641,7 +651,7 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
   dense_alloc(d, n, nb);
   const size_t nn = (size_t)n * n;
   const int nt = (n + kGT - 1) / kGT;
-  const size_t nparts = (size_t)nt * nt * nb;
+  const size_t nparts = std::max((size_t)nt * nt, (size_t)n) * nb;
   if (d.nspart < nparts) {
     if (d.spart) (void)hipFree(d.spart);
     if (d.host_spart) (void)hipHostFree(d.host_spart);
@@ -649,7 +659,11 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
     SGN_HIP(hipHostMalloc(&d.host_spart, sizeof(double) * nparts, hipHostMallocDefault));
     d.nspart = nparts;
   }
-  hipLaunchKernelGGL(norm1_scale_kernel, dim3(nb), dim3(256), 0, s, A, lda, astride, d.S, n, nn);
+  // the column sums use the partial-sum buffer (sized above for both uses)
+  hipLaunchKernelGGL(colsum_kernel, dim3((n + 3) / 4, nb), dim3(256), 0, s, A, lda, astride, d.spart, n);
+  SGN_HIP(hipGetLastError());
+  hipLaunchKernelGGL(scale_by_norm1_kernel, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, s, A, lda, astride,
+                     d.spart, d.S, n, nn);
   SGN_HIP(hipGetLastError());
   double2* X = d.S;
   double2* Y = d.Ma;

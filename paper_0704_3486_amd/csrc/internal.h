@@ -143,12 +143,14 @@ void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStre
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);
 
-// Out_r = H_w(mu) In_r for nrhs vectors at fixed strides, one launch (links loaded once per hop)
+// Out_r = H_w(mu) In_r for nrhs vectors at fixed strides, one launch.  split: one
+// hop per thread for every right-hand side (each result bitwise independent of
+// nrhs); otherwise, for nrhs >= 2, one site per thread with the link shared.
 void wilson_apply_multi(const Lattice& lat, const double2* links, const double2* in, size_t istride, double2* out,
-                        size_t ostride, int nrhs, hipStream_t s, Profiler* prof);
+                        size_t ostride, int nrhs, bool split, hipStream_t s, Profiler* prof);
 // FP32 links and spinors (mixed precision)
 void wilson_apply_multi32(const Lattice& lat, const float2* links, const float2* in, size_t istride, float2* out,
-                          size_t ostride, int nrhs, hipStream_t s, Profiler* prof);
+                          size_t ostride, int nrhs, bool split, hipStream_t s, Profiler* prof);
 void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t s);
 
 // dense kernels (dense.hip)

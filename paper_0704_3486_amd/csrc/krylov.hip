@@ -163,28 +163,41 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
   }
 }
 
-// reduce the dot partials over row tiles in a fixed order: a, b (one column
-// per thread) and, in workgroup 0, the scalars c, d, |z|^2 (to sc[kScC..])
+// reduce the dot partials over row tiles in a fixed order: 32 columns per
+// workgroup, 8 threads per column (each sums every 8th row tile), then a
+// fixed-order combine; workgroup 0 also sums the scalars c, d, |z|^2
 __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
   const int r = slot_of(A);
   const int J = A.J, nrt = A.nrt_dot;
   const double2* Pa = A.Pa + (size_t)r * A.pstride;
   const double2* Pb = A.Pb + (size_t)r * A.pstride;
   const double* Pcd = A.Pcd + (size_t)r * A.cdstride;
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c < J) {
-    double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-    for (int t = 0; t < nrt; ++t) {
+  const int cl = threadIdx.x & 31, part = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + cl;
+  double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+  if (c < J)
+    for (int t = part; t < nrt; t += 8) {
       sa = cadd(sa, Pa[(size_t)t * A.ldp + c]);
       sb = cadd(sb, Pb[(size_t)t * A.ldp + c]);
     }
-    A.a[(size_t)r * A.abstride + c] = sa;
-    A.b[(size_t)r * A.abstride + c] = sb;
+  __shared__ double2 ra[8][33], rb[8][33];
+  ra[part][cl] = sa;
+  rb[part][cl] = sb;
+  __syncthreads();
+  if (part == 0 && c < J) {
+    double2 ta = ra[0][cl], tb = rb[0][cl];
+    for (int q = 1; q < 8; ++q) {
+      ta = cadd(ta, ra[q][cl]);
+      tb = cadd(tb, rb[q][cl]);
+    }
+    A.a[(size_t)r * A.abstride + c] = ta;
+    A.b[(size_t)r * A.abstride + c] = tb;
   }
-  if (blockIdx.x == 0 && threadIdx.x < 4) {
-    double s = 0.0;
-    for (int t = 0; t < nrt; ++t) s += Pcd[4 * t + threadIdx.x];
-    A.sc[(size_t)r * kScStride + kScRawC + threadIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x >= 64 && threadIdx.x < 68) {
+    const int q = threadIdx.x - 64;
+    double acc = 0.0;
+    for (int t = 0; t < nrt; ++t) acc += Pcd[4 * t + q];
+    A.sc[(size_t)r * kScStride + kScRawC + q] = acc;
   }
 }
 
@@ -272,31 +285,52 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int row, int lane, con
 // update pass: each workgroup owns 64 rows and all J columns; its four
 // wavefronts take interleaved quarters of the columns and are combined in LDS.
 template <typename VT>
-__device__ inline void upd_col(const double2* __restrict__ q, int i, bool ok, double2 ac, double2 ec, double2& sa,
-                               double2& se) {
-  if (ok) {
-    const double2 qv = q[i];
-    sa = cfma(qv, ac, sa);
-    se = cfma(qv, ec, se);
-  }
-}
-template <typename VT>
-__device__ inline void upd_col(const float2* __restrict__ q, int i, bool ok, double2 ac, double2 ec, double2& sa,
-                               double2& se) {
-  if (ok) {
-    const double2 qv = ld2(q, i);
-    sa = cfma(qv, ac, sa);
-    se = cfma(qv, ec, se);
-  }
-}
-
-template <typename VT>
 __global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
   const int r = slot_of(A);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = A.N, J = A.J;
+  const double2* av = A.a + (size_t)r * A.abstride;
+  const double2* bv = A.b + (size_t)r * A.abstride;
+  const int i = blockIdx.x * 64 + lane;
+  const bool ok = i < N;
+  // sweep: sa = Q a, sb = Q b (the step scalars enter only afterwards:
+  // Q (b - gr a) = sb - gr sa), wavefront w takes the columns c = w mod 4
+  double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+  const int ms = min(J, A.m);
+  for (int c = wave; c < ms; c += 4) {
+    if (ok) {
+      const double2 qv = A.S[(size_t)c * A.ldq + i];
+      sa = cfma(qv, av[c], sa);
+      sb = cfma(qv, bv[c], sb);
+    }
+  }
+  {
+    const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride;
+    int c = A.m + ((wave - A.m % 4) + 4) % 4;  // first column >= m with c = wave (mod 4)
+    // 8 columns per batch: their loads are issued before the arithmetic
+    for (; c + 28 < J; c += 32) {
+      double2 qv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) qv[t] = ok ? ld2(V + (size_t)(c + 4 * t - A.m) * A.ldq, i) : make_double2(0, 0);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        sa = cfma(qv[t], av[c + 4 * t], sa);
+        sb = cfma(qv[t], bv[c + 4 * t], sb);
+      }
+    }
+    for (; c < J; c += 4) {
+      if (ok) {
+        const double2 qv = ld2(V + (size_t)(c - A.m) * A.ldq, i);
+        sa = cfma(qv, av[c], sa);
+        sb = cfma(qv, bv[c], sb);
+      }
+    }
+  }
+  __shared__ double2 ps[2][4][64];
+  ps[0][wave][lane] = sa;
+  ps[1][wave][lane] = sb;
   __shared__ double red[3 * 256];
-  const StepScalars st = step_scalars(A, r, red);
+  const StepScalars st = step_scalars(A, r, red);  // contains __syncthreads
   // Hessenberg column J (one row per wavefront over the whole grid)
   {
     const int nwaves = gridDim.x * 4;
@@ -323,33 +357,11 @@ __global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
       }
     }
   }
-  const double2* av = A.a + (size_t)r * A.abstride;
-  const double2* bv = A.b + (size_t)r * A.abstride;
-  const int i = blockIdx.x * 64 + lane;
-  const bool ok = i < N;
-  double2 sa = make_double2(0.0, 0.0), se = make_double2(0.0, 0.0);
-  // S columns (FP64)
-  for (int c = wave; c < min(J, A.m); c += 4) {
-    const double2 ac = av[c];
-    upd_col<double2>(A.S + (size_t)c * A.ldq, i, ok, ac, csub(bv[c], cmul(st.gr, ac)), sa, se);
-  }
-  // Krylov columns (VT)
-  const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride;
-  int c = A.m + ((wave - A.m % 4) + 4) % 4;  // first column >= m with c % 4 == wave
-  if (c < A.m) c += 4;
-#pragma unroll 4
-  for (; c < J; c += 4) {
-    const double2 ac = av[c];
-    upd_col<VT>(V + (size_t)(c - A.m) * A.ldq, i, ok, ac, csub(bv[c], cmul(st.gr, ac)), sa, se);
-  }
-  // combine the four wavefronts (fixed order)
-  __shared__ double2 ps[2][4][64];
-  ps[0][wave][lane] = sa;
-  ps[1][wave][lane] = se;
-  __syncthreads();
+  // combine the four wavefronts (fixed order) and write v_J and u'
   if (wave == 0 && ok) {
     const double2 ta = cadd(cadd(ps[0][0][lane], ps[0][1][lane]), cadd(ps[0][2][lane], ps[0][3][lane]));
-    const double2 te = cadd(cadd(ps[1][0][lane], ps[1][1][lane]), cadd(ps[1][2][lane], ps[1][3][lane]));
+    const double2 tb = cadd(cadd(ps[1][0][lane], ps[1][1][lane]), cadd(ps[1][2][lane], ps[1][3][lane]));
+    const double2 te = csub(tb, cmul(st.gr, ta));
     const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
     const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
     VT* vout = static_cast<VT*>(A.V) + (size_t)r * A.vstride + (size_t)(J - A.m) * A.ldq;
@@ -361,31 +373,36 @@ __global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
   }
 }
 
-// y = S c_S + V c_V for slot r (coefficients c[0..m+k))
+// y = S c_S + V c_V for slot r (coefficients c[0..m+k)): 64 rows per
+// workgroup, wavefront w sums the columns c = w mod 4, fixed-order combine
 template <typename VT>
 __global__ void __launch_bounds__(256) kcombine_kernel(KrylovArgs A, const double2* __restrict__ coef, int cstride,
                                                        double2* __restrict__ y, size_t ystride, int ncol) {
   const int r = slot_of(A);
-  const int tid = threadIdx.x;
-  const int i0 = blockIdx.x * kURows;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const bool ok = i < A.N;
   const double2* cf = coef + (size_t)r * cstride;
-  double2 acc[kUpt];
+  double2 acc = make_double2(0.0, 0.0);
+  const int ms = min(ncol, A.m);
+  for (int c = wave; c < ms; c += 4)
+    if (ok) acc = cfma(A.S[(size_t)c * A.ldq + i], cf[c], acc);
+  const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride;
+  int c = A.m + ((wave - A.m % 4) + 4) % 4;
+  for (; c + 28 < ncol; c += 32) {
+    double2 qv[8];
 #pragma unroll
-  for (int q = 0; q < kUpt; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int c = 0; c < ncol; ++c) {
-    const double2 cc = cf[c];
+    for (int t = 0; t < 8; ++t) qv[t] = ok ? ld2(V + (size_t)(c + 4 * t - A.m) * A.ldq, i) : make_double2(0, 0);
 #pragma unroll
-    for (int q = 0; q < kUpt; ++q) {
-      const int i = i0 + q * 256 + tid;
-      if (i < A.N) acc[q] = cfma(qload<VT>(A, r, c, i), cc, acc[q]);
-    }
+    for (int t = 0; t < 8; ++t) acc = cfma(qv[t], cf[c + 4 * t], acc);
   }
-  double2* yr = y + (size_t)r * ystride;
-#pragma unroll
-  for (int q = 0; q < kUpt; ++q) {
-    const int i = i0 + q * 256 + tid;
-    if (i < A.N) yr[i] = acc[q];
-  }
+  for (; c < ncol; c += 4)
+    if (ok) acc = cfma(ld2(V + (size_t)(c - A.m) * A.ldq, i), cf[c], acc);
+  __shared__ double2 ps[4][64];
+  ps[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && ok)
+    y[(size_t)r * ystride + i] = cadd(cadd(ps[0][lane], ps[1][lane]), cadd(ps[2][lane], ps[3][lane]));
 }
 
 // dst = H[:n,:n] with column n-1 += a (slot r), dst dense n x n per slot
@@ -481,7 +498,7 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, int nb, bool with_z,
   const int idx = prof ? prof->begin(K_GS_DOT) : -1;
   hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, nb), dim3(256), 0, s, A, with_z ? 1 : 0);
   SGN_HIP(hipGetLastError());
-  hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (A.J + 255) / 256), 1, nb), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (A.J + 31) / 32), 1, nb), dim3(256), 0, s, A);
   SGN_HIP(hipGetLastError());
   if (prof) {
     const double vb = (double)sizeof(VT);
@@ -516,8 +533,8 @@ void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, int nb, const do
   krylov_bind(w, A);
   SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
   const int idx = prof ? prof->begin(K_MISC) : -1;
-  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3(w.nrt_upd, 1, nb), dim3(256), 0, s, A, coef, cstride, y, ystride,
-                     ncol);
+  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, nb), dim3(256), 0, s, A, coef, cstride, y,
+                     ystride, ncol);
   SGN_HIP(hipGetLastError());
   if (prof) prof->end(idx, nb * (double)A.N * (16.0 * ncol + 16.0), nb * 8.0 * (double)A.N * ncol);
 }

@@ -72,14 +72,72 @@ __device__ inline C unit_mul(int sr, int si, C v, typename Real<C>::type sg) {
   return mk<C>(sg * ((R)sr * v.x - (R)si * v.y), sg * ((R)sr * v.y + (R)si * v.x));
 }
 
-// Out_r = H_w(mu) In_r for RB right-hand sides per thread (blockIdx.y picks the
-// group of RB); the link of each hop is loaded once and applied to all RB.
-// Optional (single RHS): scale = *inv_beta on input and output, copy_out = In * scale.
+// contribution of hop d (nu = d/2, forward if d even) to the 12 components of
+// sum_hops at one site: the half-spinor of the neighbour m times the link
+// (U_{n,nu} forward, U_{m,nu}^dag backward), times e^{+-mu} on time hops,
+// expanded back to four spins
+template <typename C>
+__device__ inline void hop_term(const C u[9], const C* __restrict__ v, int V, int m, int d,
+                                typename Real<C>::type emu, typename Real<C>::type emmu, C o[4][3]) {
+  using R = typename Real<C>::type;
+  const int nu = d >> 1;
+  const bool fwd = (d & 1) == 0;
+  const R sg = fwd ? (R)1 : (R)-1;
+  const R phase = (nu == 3) ? (fwd ? emu : emmu) : (R)1;
+  const SpinProj P = spin_proj(nu);
+  C h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const C p0 = v[c * V + m];
+    const C p1 = v[(3 + c) * V + m];
+    const C pa = v[(3 * P.i0 + c) * V + m];
+    const C pb = v[(3 * P.i1 + c) * V + m];
+    h0[c] = tadd(p0, unit_mul(P.a0r, P.a0i, pa, sg));
+    h1[c] = tadd(p1, unit_mul(P.a1r, P.a1i, pb, sg));
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    C s0 = mk<C>(0, 0), s1 = mk<C>(0, 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (fwd) {
+        s0 = tfma(u[3 * r + c], h0[c], s0);
+        s1 = tfma(u[3 * r + c], h1[c], s1);
+      } else {
+        s0 = tfmac(u[3 * c + r], h0[c], s0);
+        s1 = tfmac(u[3 * c + r], h1[c], s1);
+      }
+    }
+    o[0][r] = tscale(s0, phase);
+    o[1][r] = tscale(s1, phase);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const C x0 = (P.j0 == 0) ? o[0][c] : o[1][c];
+    const C x1 = (P.j1 == 0) ? o[0][c] : o[1][c];
+    o[2][c] = unit_mul(P.b0r, P.b0i, x0, sg);
+    o[3][c] = unit_mul(P.b1r, P.b1i, x1, sg);
+  }
+}
+
+// neighbour of site n (coordinates x, y, z, t) along hop d, periodic wrap
+__device__ inline int hop_neighbour(int n, int d, int x, int y, int z, int t, int Lx, int Ly, int Lz, int Lt) {
+  const int nu = d >> 1;
+  const int L = nu == 0 ? Lx : nu == 1 ? Ly : nu == 2 ? Lz : Lt;
+  const int coord = nu == 0 ? x : nu == 1 ? y : nu == 2 ? z : t;
+  const int stride = nu == 0 ? 1 : nu == 1 ? Lx : nu == 2 ? Lx * Ly : Lx * Ly * Lz;
+  if ((d & 1) == 0) return (coord == L - 1) ? n - (L - 1) * stride : n + stride;
+  return (coord == 0) ? n + (L - 1) * stride : n - stride;
+}
+
+// Out_r = H_w(mu) In_r for RB right-hand sides per thread, one site per thread
+// (blockIdx.y picks the group of RB); the link of each hop is loaded once and
+// applied to all RB.  Used for several right-hand sides on large lattices.
 template <typename C, int RB>
 __global__ void __launch_bounds__(kWilsonBlock)
 wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
-                 size_t ostride, int nrhs, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx,
-                 int Ly, int Lz, int Lt, double kappa_d, double emu_d, double emmu_d) {
+                 size_t ostride, int nrhs, int Lx, int Ly, int Lz, int Lt, double kappa_d, double emu_d,
+                 double emmu_d) {
   using R = typename Real<C>::type;
   const int V = Lx * Ly * Lz * Lt;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,16 +147,6 @@ wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t i
   const int y = (n / Lx) % Ly;
   const int z = (n / (Lx * Ly)) % Lz;
   const int t = n / (Lx * Ly * Lz);
-  const int sy = Lx, sz = Lx * Ly, st = Lx * Ly * Lz;
-  int nb[8];
-  nb[0] = (x == Lx - 1) ? n - (Lx - 1) : n + 1;
-  nb[1] = (x == 0) ? n + (Lx - 1) : n - 1;
-  nb[2] = (y == Ly - 1) ? n - (Ly - 1) * sy : n + sy;
-  nb[3] = (y == 0) ? n + (Ly - 1) * sy : n - sy;
-  nb[4] = (z == Lz - 1) ? n - (Lz - 1) * sz : n + sz;
-  nb[5] = (z == 0) ? n + (Lz - 1) * sz : n - sz;
-  nb[6] = (t == Lt - 1) ? n - (Lt - 1) * st : n + st;
-  nb[7] = (t == 0) ? n + (Lt - 1) * st : n - st;
   const R kappa = (R)kappa_d, emu = (R)emu_d, emmu = (R)emmu_d;
 
   C acc[RB][4][3];
@@ -113,60 +161,23 @@ wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t i
   // spinors and link are live at a time (an unrolled body spills on gfx950).
 #pragma unroll 1
   for (int d = 0; d < 8; ++d) {
-    const int nu = d >> 1;
-    const bool fwd = (d & 1) == 0;  // forward hop: (1 + gamma) U_{n,nu} psi_{n+nu}
-    const int m = nb[d];
-    const R sg = fwd ? (R)1 : (R)-1;
-    const R phase = (nu == 3) ? (fwd ? emu : emmu) : (R)1;
-    const SpinProj P = spin_proj(nu);
-    const int ls = fwd ? n : m;  // site that owns the link
+    const int m = hop_neighbour(n, d, x, y, z, t, Lx, Ly, Lz, Lt);
+    const int ls = (d & 1) == 0 ? n : m;  // site that owns the link
     C u[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) u[e] = links[(nu * 9 + e) * V + ls];
+    for (int e = 0; e < 9; ++e) u[e] = links[((d >> 1) * 9 + e) * V + ls];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       if (rb0 + b >= nrhs) break;
-      const C* __restrict__ v = in + (size_t)(rb0 + b) * istride;
-      C h0[3], h1[3];
+      C o[4][3];
+      hop_term<C>(u, in + (size_t)(rb0 + b) * istride, V, m, d, emu, emmu, o);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const C p0 = v[c * V + m];
-        const C p1 = v[(3 + c) * V + m];
-        const C pa = v[(3 * P.i0 + c) * V + m];
-        const C pb = v[(3 * P.i1 + c) * V + m];
-        h0[c] = tadd(p0, unit_mul(P.a0r, P.a0i, pa, sg));
-        h1[c] = tadd(p1, unit_mul(P.a1r, P.a1i, pb, sg));
-      }
-      C c0[3], c1[3];
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        C s0 = mk<C>(0, 0), s1 = mk<C>(0, 0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (fwd) {
-            s0 = tfma(u[3 * r + c], h0[c], s0);
-            s1 = tfma(u[3 * r + c], h1[c], s1);
-          } else {
-            s0 = tfmac(u[3 * c + r], h0[c], s0);
-            s1 = tfmac(u[3 * c + r], h1[c], s1);
-          }
-        }
-        c0[r] = tscale(s0, phase);
-        c1[r] = tscale(s1, phase);
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        acc[b][0][c] = tadd(acc[b][0][c], c0[c]);
-        acc[b][1][c] = tadd(acc[b][1][c], c1[c]);
-        const C x0 = (P.j0 == 0) ? c0[c] : c1[c];
-        const C x1 = (P.j1 == 0) ? c0[c] : c1[c];
-        acc[b][2][c] = tadd(acc[b][2][c], unit_mul(P.b0r, P.b0i, x0, sg));
-        acc[b][3][c] = tadd(acc[b][3][c], unit_mul(P.b1r, P.b1i, x1, sg));
-      }
+        for (int c = 0; c < 3; ++c) acc[b][s][c] = tadd(acc[b][s][c], o[s][c]);
     }
   }
 
-  const R scale = inv_beta ? (R)(*inv_beta) : (R)1;
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
     if (rb0 + b >= nrhs) break;
@@ -178,13 +189,65 @@ wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t i
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int idx = (3 * s + c) * V + n;
-        const C self = v[idx];
-        // gamma5 (psi - kappa * hops), all times 1/beta
-        const C r = tsub(self, tscale(acc[b][s][c], kappa));
-        o[idx] = tscale(r, g5 * scale);
-        if (copy_out) copy_out[idx] = tscale(self, scale);
+        // gamma5 (psi - kappa * hops)
+        o[idx] = tscale(tsub(v[idx], tscale(acc[b][s][c], kappa)), g5);
       }
     }
+  }
+}
+
+// Out_r = H_w(mu) In_r with one hop per thread: a workgroup holds kSplitSites
+// sites x 8 hops, the per-hop terms meet in LDS and are summed in hop order.
+// Eight times the parallelism of one site per thread, for small lattices and
+// single right-hand sides (blockIdx.y = right-hand side).
+// Optional: scale = *inv_beta on input and output, copy_out = In * scale.
+constexpr int kSplitSites = 16;
+template <typename C>
+__global__ void __launch_bounds__(8 * kSplitSites)
+wilson_hw_split_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
+                       size_t ostride, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx, int Ly,
+                       int Lz, int Lt, double kappa_d, double emu_d, double emmu_d) {
+  using R = typename Real<C>::type;
+  const int V = Lx * Ly * Lz * Lt;
+  const int sl = threadIdx.x % kSplitSites, d = threadIdx.x / kSplitSites;
+  const int n0 = blockIdx.x * kSplitSites;
+  const int n = n0 + sl;
+  const C* __restrict__ v = in + (size_t)blockIdx.y * istride;
+  __shared__ C part[12][8][kSplitSites];
+  if (n < V) {
+    const int x = n % Lx;
+    const int y = (n / Lx) % Ly;
+    const int z = (n / (Lx * Ly)) % Lz;
+    const int t = n / (Lx * Ly * Lz);
+    const int m = hop_neighbour(n, d, x, y, z, t, Lx, Ly, Lz, Lt);
+    const int ls = (d & 1) == 0 ? n : m;
+    C u[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = links[((d >> 1) * 9 + e) * V + ls];
+    C o[4][3];
+    hop_term<C>(u, v, V, m, d, (R)emu_d, (R)emmu_d, o);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) part[3 * s + c][d][sl] = o[s][c];
+  }
+  __syncthreads();
+  const R kappa = (R)kappa_d;
+  const R scale = inv_beta ? (R)(*inv_beta) : (R)1;
+  C* __restrict__ w = out + (size_t)blockIdx.y * ostride;
+  for (int p = threadIdx.x; p < 12 * kSplitSites; p += 8 * kSplitSites) {
+    const int comp = p / kSplitSites, s2 = p % kSplitSites;
+    const int nn = n0 + s2;
+    if (nn >= V) continue;
+    C acc = mk<C>(0, 0);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) acc = tadd(acc, part[comp][h][s2]);
+    const size_t idx = (size_t)comp * V + nn;
+    const C self = v[idx];
+    // gamma5 (psi - kappa * hops), all times 1/beta
+    const R g5 = comp < 6 ? (R)1 : (R)-1;
+    w[idx] = tscale(tsub(self, tscale(acc, kappa)), g5 * scale);
+    if (copy_out) copy_out[idx] = tscale(self, scale);
   }
 }
 
@@ -243,8 +306,8 @@ void wilson_apply(const Lattice& lat, const double2* links, const double2* in, d
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof) {
   const int V = lat.V;
   const int idx = prof ? prof->begin(K_WILSON) : -1;
-  hipLaunchKernelGGL((wilson_hw_kernel<double2, 1>), dim3((V + kWilsonBlock - 1) / kWilsonBlock, 1),
-                     dim3(kWilsonBlock), 0, s, links, in, (size_t)0, out, (size_t)0, 1, inv_beta, copy_out, lat.L[0],
+  hipLaunchKernelGGL((wilson_hw_split_kernel<double2>), dim3((V + kSplitSites - 1) / kSplitSites, 1),
+                     dim3(8 * kSplitSites), 0, s, links, in, (size_t)0, out, (size_t)0, inv_beta, copy_out, lat.L[0],
                      lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu);
   SGN_HIP(hipGetLastError());
   if (prof) {
@@ -254,25 +317,28 @@ void wilson_apply(const Lattice& lat, const double2* links, const double2* in, d
   }
 }
 
+// several right-hand sides: one hop per thread (bitwise the single-RHS
+// result) unless the lattice is large enough that one site per thread fills
+// the chip, where the link is shared by up to four right-hand sides
 template <typename C>
 static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t istride, C* out, size_t ostride,
-                         int nrhs, hipStream_t s, Profiler* prof) {
+                         int nrhs, bool split, hipStream_t s, Profiler* prof) {
   const int V = lat.V;
   SGN_REQUIRE(nrhs >= 1, SGN_EINVAL, "wilson: nrhs must be positive");
   const int idx = prof ? prof->begin(K_WILSON) : -1;
   const dim3 blk(kWilsonBlock);
   const unsigned gx = (V + kWilsonBlock - 1) / kWilsonBlock;
-  if (nrhs >= 4 && sizeof(C) == 8) {
+  const int L0 = lat.L[0], L1 = lat.L[1], L2 = lat.L[2], L3 = lat.L[3];
+  if (split || nrhs == 1) {
+    hipLaunchKernelGGL((wilson_hw_split_kernel<C>), dim3((V + kSplitSites - 1) / kSplitSites, nrhs),
+                       dim3(8 * kSplitSites), 0, s, links, in, istride, out, ostride, nullptr, nullptr, L0, L1, L2,
+                       L3, lat.kappa, lat.emu, lat.emmu);
+  } else if (nrhs >= 4 && sizeof(C) == 8) {
     hipLaunchKernelGGL((wilson_hw_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), blk, 0, s, links, in, istride, out,
-                       ostride, nrhs, nullptr, nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
-                       lat.emmu);
-  } else if (nrhs >= 2) {
-    hipLaunchKernelGGL((wilson_hw_kernel<C, 2>), dim3(gx, (nrhs + 1) / 2), blk, 0, s, links, in, istride, out,
-                       ostride, nrhs, nullptr, nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
-                       lat.emmu);
+                       ostride, nrhs, L0, L1, L2, L3, lat.kappa, lat.emu, lat.emmu);
   } else {
-    hipLaunchKernelGGL((wilson_hw_kernel<C, 1>), dim3(gx, 1), blk, 0, s, links, in, istride, out, ostride, nrhs,
-                       nullptr, nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu);
+    hipLaunchKernelGGL((wilson_hw_kernel<C, 2>), dim3(gx, (nrhs + 1) / 2), blk, 0, s, links, in, istride, out,
+                       ostride, nrhs, L0, L1, L2, L3, lat.kappa, lat.emu, lat.emmu);
   }
   SGN_HIP(hipGetLastError());
   if (prof) {
@@ -283,13 +349,13 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
 }
 
 void wilson_apply_multi(const Lattice& lat, const double2* links, const double2* in, size_t istride, double2* out,
-                        size_t ostride, int nrhs, hipStream_t s, Profiler* prof) {
-  wilson_multi<double2>(lat, links, in, istride, out, ostride, nrhs, s, prof);
+                        size_t ostride, int nrhs, bool split, hipStream_t s, Profiler* prof) {
+  wilson_multi<double2>(lat, links, in, istride, out, ostride, nrhs, split, s, prof);
 }
 
 void wilson_apply_multi32(const Lattice& lat, const float2* links, const float2* in, size_t istride, float2* out,
-                          size_t ostride, int nrhs, hipStream_t s, Profiler* prof) {
-  wilson_multi<float2>(lat, links, in, istride, out, ostride, nrhs, s, prof);
+                          size_t ostride, int nrhs, bool split, hipStream_t s, Profiler* prof) {
+  wilson_multi<float2>(lat, links, in, istride, out, ostride, nrhs, split, s, prof);
 }
 
 void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t s) {
