@@ -88,10 +88,15 @@ Profiler::~Profiler() {
 static const char* kclass_name(int c) {
   switch (c) {
     case K_WILSON: return "wilson_hw";
-    case K_GS_DOT: return "gs_dot";
-    case K_GS_UPDATE: return "gs_update";
+    case K_KDOT: return "krylov_dot";
+    case K_KRED: return "krylov_reduce";
+    case K_KUPDATE: return "krylov_update";
+    case K_KCOMBINE: return "krylov_combine";
+    case K_NS_GEMM: return "ns_gemm";
     case K_GJ_PANEL: return "gj_inverse";
     case K_NEWTON_COMBINE: return "newton_combine";
+    case K_CGS_DOT: return "cgs_dot";
+    case K_CGS_UPDATE: return "cgs_update";
     default: return "misc";
   }
 }

@@ -672,12 +672,16 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
   const int maxit = 60;
   int iters = 0;
   for (int it = 1; it <= maxit; ++it) {
-    const int idx = prof ? prof->begin(K_GJ_PANEL) : -1;
+    // per product: read two n x n operands, write one; 8 n^3 real flops
+    const double gb = nb * 3.0 * 16.0 * (double)nn, gf = nb * 8.0 * (double)nn * n;
+    int idx = prof ? prof->begin(K_NS_GEMM) : -1;
     hipLaunchKernelGGL(zgemm_kernel<1>, grid, dim3(256), 0, s, X, X, Y, n, 1.0, d.spart, nn);
     SGN_HIP(hipGetLastError());
+    if (prof) prof->end(idx, gb, gf);
+    idx = prof ? prof->begin(K_NS_GEMM) : -1;
     hipLaunchKernelGGL(zgemm_kernel<0>, grid, dim3(256), 0, s, X, Y, Xn, n, 0.5, nullptr, nn);
     SGN_HIP(hipGetLastError());
-    if (prof) prof->end(idx, nb * 2.0 * 3.0 * 16.0 * (double)nn, nb * 2.0 * 8.0 * (double)nn * n);
+    if (prof) prof->end(idx, gb, gf);
     std::swap(X, Xn);
     iters = it;
     if (it < 6) continue;  // growth phase: no need to look yet

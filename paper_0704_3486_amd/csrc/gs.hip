@@ -250,7 +250,7 @@ void gs_dot(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, cons
   if (ncol <= 0) return;
   SGN_REQUIRE(ncol <= g.ncol_cap, SGN_EINVAL, "gs_dot: ncol exceeds workspace");
   const int ngroups = (ncol + kDotCols - 1) / kDotCols;
-  const int idx = prof ? prof->begin(K_GS_DOT) : -1;
+  const int idx = prof ? prof->begin(K_CGS_DOT) : -1;
   hipLaunchKernelGGL(gs_dot_kernel, dim3(g.nrt_dot, ngroups), dim3(256), 0, s, Q, ldq, N, ncol, w, g.P,
                      g.ncol_cap, h, g.counters, g.nrt_dot);
   SGN_HIP(hipGetLastError());
@@ -274,7 +274,7 @@ static void update_launch(const GsWork& g, const double2* Q, size_t ldq, int N, 
   const int ndotgroups = (g.ncol_cap + kDotCols - 1) / kDotCols;
   unsigned* cnt_rows = g.counters + ndotgroups;
   unsigned* cnt_norm = cnt_rows + g.nrt_upd;
-  const int idx = prof ? prof->begin(K_GS_UPDATE) : -1;
+  const int idx = prof ? prof->begin(K_CGS_UPDATE) : -1;
   hipLaunchKernelGGL(gs_update_kernel, dim3(g.nrt_upd, ngroups), dim3(256), 0, s, Q, ldq, N, ncol, h, sgn, w,
                      g.Upart, ngroups, cnt_rows, cnt_norm, g.nrt_upd, g.normpart, fd);
   SGN_HIP(hipGetLastError());

@@ -60,12 +60,19 @@ struct SgnError {
 // ----------------------------------------------------------------------------
 // kernel profiling (HIP events on the context stream)
 // ----------------------------------------------------------------------------
+// one class per kernel on the apply path, so that a class's average duration
+// is that kernel's (the Gauss-Jordan class brackets all panels of one inverse)
 enum KClass {
-  K_WILSON = 0,
-  K_GS_DOT,
-  K_GS_UPDATE,
-  K_GJ_PANEL,
-  K_NEWTON_COMBINE,
+  K_WILSON = 0,      // wilson_hw_*_kernel
+  K_KDOT,            // kdot_kernel
+  K_KRED,            // kred_kernel
+  K_KUPDATE,         // kupdate_kernel
+  K_KCOMBINE,        // kcombine_kernel
+  K_NS_GEMM,         // zgemm_kernel (Newton-Schulz)
+  K_GJ_PANEL,        // gj_panel_kernel x panels (Newton inverse)
+  K_NEWTON_COMBINE,  // newton_combine_kernel
+  K_CGS_DOT,         // gs_dot_kernel (deflation setup)
+  K_CGS_UPDATE,      // gs_update_kernel (deflation setup)
   K_MISC,
   K_NCLASS
 };

@@ -53,28 +53,23 @@ struct KrylovArgs {
   double* Pcd = nullptr;
   int ldp = 0;
   size_t pstride = 0, cdstride = 0;
-  double2 *Upa = nullptr, *Upe = nullptr;
-  size_t upstride = 0;
   double2 *a = nullptr, *b = nullptr;
   size_t abstride = 0;
   double* sc = nullptr;
-  unsigned* cnt = nullptr;
-  int cntstride = 0, cnt_all = 0, cnt_rows = 0;
   int nrt_dot = 0;
 };
 
+// partial sums of the dot pass [slot][row tile][column], the reduced
+// coefficients a, b [slot][column] and the step scalars [slot][kScStride]
 struct KrylovWork {
-  int nrt_dot = 0, nrt_upd = 0, ncol_cap = 0, nslots = 0;
-  int ngroups_dot_cap = 0, ngroups_upd_cap = 0;
+  int nrt_dot = 0, ncol_cap = 0, nslots = 0;
+  int ngroups_dot_cap = 0;
   int ldp = 0;
-  size_t pstride = 0, cdstride = 0, upstride = 0, abstride = 0;
-  int cnt_all = 0, cnt_rows = 0, cntstride = 0;
+  size_t pstride = 0, cdstride = 0, abstride = 0;
   double2 *Pa = nullptr, *Pb = nullptr;
   double* Pcd = nullptr;
-  double2 *Upa = nullptr, *Upe = nullptr;
   double2 *a = nullptr, *b = nullptr;
   double* sc = nullptr;
-  unsigned* cnt = nullptr;
 };
 
 void krylov_alloc(KrylovWork& w, int N, size_t ldq, int ncol_cap, int nslots);

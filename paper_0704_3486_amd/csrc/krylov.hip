@@ -34,9 +34,9 @@ constexpr int kRpl = 8;                 // dot: rows per lane
 constexpr int kCpw = 4;                 // dot: columns per wavefront
 constexpr int kDRows = 64 * kRpl;       // dot: rows per tile
 constexpr int kDCols = kCpw * 4;        // dot: columns per workgroup (4 wavefronts)
-constexpr int kUpt = 4;                 // update: rows per thread
-constexpr int kURows = 256 * kUpt;      // update: rows per tile
-constexpr int kUCols = 32;              // update: columns per workgroup
+constexpr int kUWaves = 8;              // update / combine: wavefronts per 64-row workgroup
+constexpr int kUThreads = 64 * kUWaves;
+constexpr int kUBatch = 8;              // update / combine: column loads issued together per lane
 
 __device__ inline double2 ld2(const double2* p, size_t i) { return p[i]; }
 __device__ inline double2 ld2(const float2* p, size_t i) {
@@ -74,30 +74,18 @@ __device__ inline int slot_of(const KrylovArgs& A) { return A.act ? A.act[blockI
 // dot pass: per (row tile, column group) partial sums of Q^dag u and Q^dag z,
 // plus |u|^2, u^dag z, |z|^2 per row tile.  No cross-workgroup communication:
 // the partials are reduced by kred_kernel in a fixed order.
-template <typename VT>
-__device__ inline void dot_cols(const double2* __restrict__ q, const double2 uv[kRpl], const double2 zv[kRpl],
-                                int row0, int lane, int N, double2& aa, double2& bb) {
+// the rows past N carry zero weights (uv = zv = 0 there) and load a valid
+// row instead: unconditional loads, all in flight together
+template <typename QT>
+__device__ inline void dot_cols(const QT* __restrict__ q, const double2 uv[kRpl], const double2 zv[kRpl], int row0,
+                                int lane, int N, double2& aa, double2& bb) {
+  double2 qv[kRpl];
+#pragma unroll
+  for (int t = 0; t < kRpl; ++t) qv[t] = ld2(q, min(row0 + t * 64 + lane, N - 1));
 #pragma unroll
   for (int t = 0; t < kRpl; ++t) {
-    const int i = row0 + t * 64 + lane;
-    if (i < N) {
-      const double2 qv = q[i];
-      aa = cfmac(qv, uv[t], aa);
-      bb = cfmac(qv, zv[t], bb);
-    }
-  }
-}
-template <typename VT>
-__device__ inline void dot_cols(const float2* __restrict__ q, const double2 uv[kRpl], const double2 zv[kRpl],
-                                int row0, int lane, int N, double2& aa, double2& bb) {
-#pragma unroll
-  for (int t = 0; t < kRpl; ++t) {
-    const int i = row0 + t * 64 + lane;
-    if (i < N) {
-      const double2 qv = ld2(q, i);
-      aa = cfmac(qv, uv[t], aa);
-      bb = cfmac(qv, zv[t], bb);
-    }
+    aa = cfmac(qv[t], uv[t], aa);
+    bb = cfmac(qv[t], zv[t], bb);
   }
 }
 
@@ -105,7 +93,7 @@ template <typename VT>
 __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
   const int r = slot_of(A);
   const int rt = blockIdx.x, cg = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int N = A.N, J = A.J;
   const int row0 = rt * kDRows;
   const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
@@ -127,7 +115,7 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
     if (c < J) {
       double2 aa = make_double2(0.0, 0.0), bb = make_double2(0.0, 0.0);
       if (c < A.m) {
-        dot_cols<VT>(A.S + (size_t)c * A.ldq, uv, zv, row0, lane, N, aa, bb);
+        dot_cols<double2>(A.S + (size_t)c * A.ldq, uv, zv, row0, lane, N, aa, bb);
       } else {
         const VT* q = static_cast<const VT*>(A.V) + (size_t)r * A.vstride + (size_t)(c - A.m) * A.ldq;
         dot_cols<VT>(q, uv, zv, row0, lane, N, aa, bb);
@@ -210,13 +198,14 @@ struct StepScalars {
   double scale;
 };
 
-__device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* LDS [3][256] */) {
+template <int NT>
+__device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* LDS [3][NT] */) {
   const int J = A.J, tid = threadIdx.x;
   const double2* a = A.a + (size_t)r * A.abstride;
   const double2* b = A.b + (size_t)r * A.abstride;
   const double* sc = A.sc + (size_t)r * kScStride;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int c = tid; c < J; c += 256) {
+  for (int c = tid; c < J; c += NT) {
     const double2 x1 = a[c], x2 = b[c];
     s0 += cabs2(x1);
     const double2 ab = cmulc(x1, x2);
@@ -224,14 +213,14 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
     s2 += ab.y;
   }
   red[tid] = s0;
-  red[256 + tid] = s1;
-  red[512 + tid] = s2;
+  red[NT + tid] = s1;
+  red[2 * NT + tid] = s2;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = NT / 2; off > 0; off >>= 1) {
     if (tid < off) {
       red[tid] += red[tid + off];
-      red[256 + tid] += red[256 + tid + off];
-      red[512 + tid] += red[512 + tid + off];
+      red[NT + tid] += red[NT + tid + off];
+      red[2 * NT + tid] += red[2 * NT + tid + off];
     }
     __syncthreads();
   }
@@ -240,7 +229,7 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
   const double2 d = make_double2(sc[kScRawC + 1], sc[kScRawC + 2]);
   const double zz = sc[kScRawC + 3];
   const double aa = red[0];
-  const double2 ab = make_double2(red[256], red[512]);
+  const double2 ab = make_double2(red[NT], red[2 * NT]);
   const double rho2 = c - aa;
   const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
   st.finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(zz);
@@ -282,59 +271,65 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int row, int lane, con
   H[(size_t)J * ldh + row] = cscale(csub(g, ha), inv);
 }
 
-// update pass: each workgroup owns 64 rows and all J columns; its four
-// wavefronts take interleaved quarters of the columns and are combined in LDS.
+// sa += sum_c q_c[i] a_c, sb += sum_c q_c[i] b_c over the columns c = c0,
+// c0 + kUWaves, ... < cend; column c sits at base + (c - cofs) ldq.  kUBatch
+// loads per lane are issued before their arithmetic.
+// (rows past N load row N-1 and are never written: unconditional loads; c
+// is wavefront-uniform, so the coefficients come through scalar loads)
+template <typename QT, bool HasB>
+__device__ inline void sweep_cols(const QT* __restrict__ base, int cofs, size_t ldq, int c, int cend, int i,
+                                  const double2* __restrict__ av, const double2* __restrict__ bv, double2& sa,
+                                  double2& sb) {
+  for (; c + (kUBatch - 1) * kUWaves < cend; c += kUBatch * kUWaves) {
+    double2 qv[kUBatch];
+#pragma unroll
+    for (int t = 0; t < kUBatch; ++t) qv[t] = ld2(base + (size_t)(c + t * kUWaves - cofs) * ldq, i);
+#pragma unroll
+    for (int t = 0; t < kUBatch; ++t) {
+      sa = cfma(qv[t], av[c + t * kUWaves], sa);
+      if constexpr (HasB) sb = cfma(qv[t], bv[c + t * kUWaves], sb);
+    }
+  }
+  for (; c < cend; c += kUWaves) {
+    const double2 qv = ld2(base + (size_t)(c - cofs) * ldq, i);
+    sa = cfma(qv, av[c], sa);
+    if constexpr (HasB) sb = cfma(qv, bv[c], sb);
+  }
+}
+
+// wavefront index as a scalar (uniform) value
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// first column >= m that wavefront w takes (c = w mod kUWaves)
+__device__ inline int first_col(int m, int w) { return m + ((w - m % kUWaves) + kUWaves) % kUWaves; }
+
+// update pass: each workgroup owns 64 rows and all J columns; its kUWaves
+// wavefronts take interleaved columns and are combined in LDS in fixed order.
 template <typename VT>
-__global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
+__global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
   const int r = slot_of(A);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int N = A.N, J = A.J;
   const double2* av = A.a + (size_t)r * A.abstride;
   const double2* bv = A.b + (size_t)r * A.abstride;
   const int i = blockIdx.x * 64 + lane;
   const bool ok = i < N;
   // sweep: sa = Q a, sb = Q b (the step scalars enter only afterwards:
-  // Q (b - gr a) = sb - gr sa), wavefront w takes the columns c = w mod 4
+  // Q (b - gr a) = sb - gr sa)
   double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-  const int ms = min(J, A.m);
-  for (int c = wave; c < ms; c += 4) {
-    if (ok) {
-      const double2 qv = A.S[(size_t)c * A.ldq + i];
-      sa = cfma(qv, av[c], sa);
-      sb = cfma(qv, bv[c], sb);
-    }
-  }
-  {
-    const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride;
-    int c = A.m + ((wave - A.m % 4) + 4) % 4;  // first column >= m with c = wave (mod 4)
-    // 8 columns per batch: their loads are issued before the arithmetic
-    for (; c + 28 < J; c += 32) {
-      double2 qv[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) qv[t] = ok ? ld2(V + (size_t)(c + 4 * t - A.m) * A.ldq, i) : make_double2(0, 0);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        sa = cfma(qv[t], av[c + 4 * t], sa);
-        sb = cfma(qv[t], bv[c + 4 * t], sb);
-      }
-    }
-    for (; c < J; c += 4) {
-      if (ok) {
-        const double2 qv = ld2(V + (size_t)(c - A.m) * A.ldq, i);
-        sa = cfma(qv, av[c], sa);
-        sb = cfma(qv, bv[c], sb);
-      }
-    }
-  }
-  __shared__ double2 ps[2][4][64];
+  const int il = ok ? i : N - 1;
+  sweep_cols<double2, true>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
+  sweep_cols<VT, true>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq, first_col(A.m, wave), J, il,
+                       av, bv, sa, sb);
+  __shared__ double2 ps[2][kUWaves][64];
   ps[0][wave][lane] = sa;
   ps[1][wave][lane] = sb;
-  __shared__ double red[3 * 256];
-  const StepScalars st = step_scalars(A, r, red);  // contains __syncthreads
+  __shared__ double red[3 * kUThreads];
+  const StepScalars st = step_scalars<kUThreads>(A, r, red);  // contains __syncthreads
   // Hessenberg column J (one row per wavefront over the whole grid)
   {
-    const int nwaves = gridDim.x * 4;
-    for (int row = blockIdx.x * 4 + wave; row <= J; row += nwaves) hcol_row_wave(A, r, row, lane, st);
+    const int nwaves = gridDim.x * kUWaves;
+    for (int row = blockIdx.x * kUWaves + wave; row <= J; row += nwaves) hcol_row_wave(A, r, row, lane, st);
     if (blockIdx.x == 0 && tid == 0) {
       double* sc = A.sc + (size_t)r * kScStride;
       sc[kScRho] = st.rho;
@@ -357,10 +352,14 @@ __global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
       }
     }
   }
-  // combine the four wavefronts (fixed order) and write v_J and u'
+  // combine the wavefronts (fixed order) and write v_J and u'
   if (wave == 0 && ok) {
-    const double2 ta = cadd(cadd(ps[0][0][lane], ps[0][1][lane]), cadd(ps[0][2][lane], ps[0][3][lane]));
-    const double2 tb = cadd(cadd(ps[1][0][lane], ps[1][1][lane]), cadd(ps[1][2][lane], ps[1][3][lane]));
+    double2 ta = ps[0][0][lane], tb = ps[1][0][lane];
+#pragma unroll
+    for (int w = 1; w < kUWaves; ++w) {
+      ta = cadd(ta, ps[0][w][lane]);
+      tb = cadd(tb, ps[1][w][lane]);
+    }
     const double2 te = csub(tb, cmul(st.gr, ta));
     const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
     const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
@@ -373,36 +372,31 @@ __global__ void __launch_bounds__(256) kupdate_kernel(KrylovArgs A) {
   }
 }
 
-// y = S c_S + V c_V for slot r (coefficients c[0..m+k)): 64 rows per
-// workgroup, wavefront w sums the columns c = w mod 4, fixed-order combine
+// y = S c_S + V c_V for slot r (coefficients c[0..ncol)): 64 rows per
+// workgroup, wavefront w sums the columns c = w mod kUWaves, fixed-order combine
 template <typename VT>
-__global__ void __launch_bounds__(256) kcombine_kernel(KrylovArgs A, const double2* __restrict__ coef, int cstride,
-                                                       double2* __restrict__ y, size_t ystride, int ncol) {
+__global__ void __launch_bounds__(kUThreads) kcombine_kernel(KrylovArgs A, const double2* __restrict__ coef,
+                                                             int cstride, double2* __restrict__ y, size_t ystride,
+                                                             int ncol) {
   const int r = slot_of(A);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int i = blockIdx.x * 64 + lane;
   const bool ok = i < A.N;
   const double2* cf = coef + (size_t)r * cstride;
-  double2 acc = make_double2(0.0, 0.0);
-  const int ms = min(ncol, A.m);
-  for (int c = wave; c < ms; c += 4)
-    if (ok) acc = cfma(A.S[(size_t)c * A.ldq + i], cf[c], acc);
-  const VT* V = static_cast<const VT*>(A.V) + (size_t)r * A.vstride;
-  int c = A.m + ((wave - A.m % 4) + 4) % 4;
-  for (; c + 28 < ncol; c += 32) {
-    double2 qv[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) qv[t] = ok ? ld2(V + (size_t)(c + 4 * t - A.m) * A.ldq, i) : make_double2(0, 0);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc = cfma(qv[t], cf[c + 4 * t], acc);
-  }
-  for (; c < ncol; c += 4)
-    if (ok) acc = cfma(ld2(V + (size_t)(c - A.m) * A.ldq, i), cf[c], acc);
-  __shared__ double2 ps[4][64];
+  double2 acc = make_double2(0.0, 0.0), unused = make_double2(0.0, 0.0);
+  const int il = ok ? i : A.N - 1;
+  sweep_cols<double2, false>(A.S, 0, A.ldq, wave, min(ncol, A.m), il, cf, nullptr, acc, unused);
+  sweep_cols<VT, false>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq, first_col(A.m, wave), ncol,
+                        il, cf, nullptr, acc, unused);
+  __shared__ double2 ps[kUWaves][64];
   ps[wave][lane] = acc;
   __syncthreads();
-  if (wave == 0 && ok)
-    y[(size_t)r * ystride + i] = cadd(cadd(ps[0][lane], ps[1][lane]), cadd(ps[2][lane], ps[3][lane]));
+  if (wave == 0 && ok) {
+    double2 t = ps[0][lane];
+#pragma unroll
+    for (int w = 1; w < kUWaves; ++w) t = cadd(t, ps[w][lane]);
+    y[(size_t)r * ystride + i] = t;
+  }
 }
 
 // dst = H[:n,:n] with column n-1 += a (slot r), dst dense n x n per slot
@@ -424,38 +418,28 @@ __global__ void kpatch_kernel(KrylovArgs A, int n, double2* __restrict__ dst, si
 // ---------------------------------------------------------------------------
 void krylov_alloc(KrylovWork& w, int N, size_t ldq, int ncol_cap, int nslots) {
   krylov_free(w);
+  (void)ldq;
   w.nrt_dot = (N + kDRows - 1) / kDRows;
-  w.nrt_upd = (N + kURows - 1) / kURows;
   w.ncol_cap = ncol_cap;
   w.nslots = nslots;
   w.ngroups_dot_cap = (ncol_cap + kDCols - 1) / kDCols;
-  w.ngroups_upd_cap = std::max(1, (ncol_cap + kUCols - 1) / kUCols);
   w.ldp = ncol_cap;
   w.pstride = (size_t)w.nrt_dot * ncol_cap;
   w.cdstride = (size_t)4 * w.nrt_dot;
-  w.upstride = ldq * (size_t)w.ngroups_upd_cap;
   w.abstride = (size_t)ncol_cap;
-  w.cnt_all = w.ngroups_dot_cap;
-  w.cnt_rows = w.ngroups_dot_cap + 1;
-  w.cntstride = w.ngroups_dot_cap + 1 + w.nrt_upd;
   const size_t S = (size_t)nslots;
   SGN_HIP(hipMalloc(&w.Pa, sizeof(double2) * w.pstride * S));
   SGN_HIP(hipMalloc(&w.Pb, sizeof(double2) * w.pstride * S));
   SGN_HIP(hipMalloc(&w.Pcd, sizeof(double) * w.cdstride * S));
-  SGN_HIP(hipMalloc(&w.Upa, sizeof(double2) * w.upstride * S));
-  SGN_HIP(hipMalloc(&w.Upe, sizeof(double2) * w.upstride * S));
   SGN_HIP(hipMalloc(&w.a, sizeof(double2) * w.abstride * S));
   SGN_HIP(hipMalloc(&w.b, sizeof(double2) * w.abstride * S));
   SGN_HIP(hipMalloc(&w.sc, sizeof(double) * kScStride * S));
   SGN_HIP(hipMemset(w.sc, 0, sizeof(double) * kScStride * S));
-  SGN_HIP(hipMalloc(&w.cnt, sizeof(unsigned) * (size_t)w.cntstride * S));
-  SGN_HIP(hipMemset(w.cnt, 0, sizeof(unsigned) * (size_t)w.cntstride * S));
   SGN_HIP(hipDeviceSynchronize());
 }
 
 void krylov_free(KrylovWork& w) {
-  for (void* p : {(void*)w.Pa, (void*)w.Pb, (void*)w.Pcd, (void*)w.Upa, (void*)w.Upe, (void*)w.a, (void*)w.b,
-                  (void*)w.sc, (void*)w.cnt})
+  for (void* p : {(void*)w.Pa, (void*)w.Pb, (void*)w.Pcd, (void*)w.a, (void*)w.b, (void*)w.sc})
     if (p) (void)hipFree(p);
   w = KrylovWork{};
 }
@@ -467,17 +451,10 @@ void krylov_bind(const KrylovWork& w, KrylovArgs& A) {
   A.ldp = w.ldp;
   A.pstride = w.pstride;
   A.cdstride = w.cdstride;
-  A.Upa = w.Upa;
-  A.Upe = w.Upe;
-  A.upstride = w.upstride;
   A.a = w.a;
   A.b = w.b;
   A.abstride = w.abstride;
   A.sc = w.sc;
-  A.cnt = w.cnt;
-  A.cntstride = w.cntstride;
-  A.cnt_all = w.cnt_all;
-  A.cnt_rows = w.cnt_rows;
   A.nrt_dot = w.nrt_dot;
 }
 
@@ -495,16 +472,19 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, int nb, bool with_z,
   check_args(w, A, nb);
   const int ngroups = A.J > 0 ? (A.J + kDCols - 1) / kDCols : 1;
   if (!flag_on) A.flag = nullptr;
-  const int idx = prof ? prof->begin(K_GS_DOT) : -1;
+  const double vb = (double)sizeof(VT);
+  const double qbytes = (double)A.N * (16.0 * A.m + vb * (A.J - A.m));
+  // algorithmic bytes: Q, u, z read once; a, b written
+  int idx = prof ? prof->begin(K_KDOT) : -1;
   hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, nb), dim3(256), 0, s, A, with_z ? 1 : 0);
   SGN_HIP(hipGetLastError());
+  if (prof)
+    prof->end(idx, nb * (qbytes + A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * A.J), nb * 16.0 * (double)A.N * A.J);
+  // partial sums of every row tile read, a, b written
+  idx = prof ? prof->begin(K_KRED) : -1;
   hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (A.J + 31) / 32), 1, nb), dim3(256), 0, s, A);
   SGN_HIP(hipGetLastError());
-  if (prof) {
-    const double vb = (double)sizeof(VT);
-    const double qbytes = (double)A.N * (16.0 * A.m + vb * (A.J - A.m));
-    prof->end(idx, nb * (qbytes + A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * A.J), nb * 16.0 * (double)A.N * A.J);
-  }
+  if (prof) prof->end(idx, nb * (32.0 * A.J * (w.nrt_dot + 1.0) + 32.0 * w.nrt_dot), nb * 4.0 * A.J * w.nrt_dot);
 }
 
 template <typename VT>
@@ -514,8 +494,8 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, int nb, hipStream
   check_args(w, A, nb);
   SGN_REQUIRE(A.J + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
   const int nblk = (A.N + 63) / 64;
-  const int idx = prof ? prof->begin(K_GS_UPDATE) : -1;
-  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(nblk, 1, nb), dim3(256), 0, s, A);
+  const int idx = prof ? prof->begin(K_KUPDATE) : -1;
+  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(nblk, 1, nb), dim3(kUThreads), 0, s, A);
   SGN_HIP(hipGetLastError());
   if (prof) {
     const double vb = (double)sizeof(VT);
@@ -532,8 +512,8 @@ void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, int nb, const do
   KrylovArgs A = Ain;
   krylov_bind(w, A);
   SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
-  const int idx = prof ? prof->begin(K_MISC) : -1;
-  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, nb), dim3(256), 0, s, A, coef, cstride, y,
+  const int idx = prof ? prof->begin(K_KCOMBINE) : -1;
+  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, nb), dim3(kUThreads), 0, s, A, coef, cstride, y,
                      ystride, ncol);
   SGN_HIP(hipGetLastError());
   if (prof) prof->end(idx, nb * (double)A.N * (16.0 * ncol + 16.0), nb * 8.0 * (double)A.N * ncol);
