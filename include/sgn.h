@@ -150,6 +150,24 @@ int sgn_apply(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
  * exact breakdown), then steps (v)-(vi) once.  k >= 0. */
 int sgn_apply_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
 
+/* Several sources of one field: Y_r = sgn(H_w(mu)) X_r for r < nrhs.
+ * X, Y: device complex128, nrhs x N (source r at X + 2 N r doubles); Y may
+ * alias X.  The sources advance together (one stencil, dot and update launch
+ * per Arnoldi step for all unfinished sources, at most 64 per launch; larger
+ * nrhs run in chunks of 64); each stops at the first shared even-k
+ * checkpoint where its own change is <= tol.  info: host array of nrhs
+ * entries (nullable).  Always the one-reduction schedule.  Per source the
+ * arithmetic is that of sgn_apply, so sgn_apply_batched_fixed returns
+ * bitwise the sgn_apply_fixed results; with a tolerance the shared
+ * checkpoints can stop a source at a later k than sgn_apply would.
+ * Returns SGN_ENOCONV if any source reached kmax unconverged (its Y_r holds
+ * the kmax approximation, info[r].converged = 0).  The workspace holds
+ * sgn_footprint_bytes(ctx, kmax, min(nrhs, 64)) bytes and is kept for reuse. */
+int sgn_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double tol, int kmax, sgn_info* info);
+
+/* Batched counterpart of sgn_apply_fixed: exactly k steps per source. */
+int sgn_apply_batched_fixed(sgn_ctx* ctx, int nrhs, const double* X, double* Y, int k, sgn_info* info);
+
 /* Arithmetic of the Krylov loop.  SGN_PREC_FP64 (default): everything FP64.
  * SGN_PREC_MIXED: the links, the stencil and the stored Krylov vectors v_j are
  * FP32; the Schur vectors S_m, the candidate vector being orthogonalised,
@@ -178,10 +196,14 @@ int sgn_set_orthogonalization(sgn_ctx* ctx, int mode);
  * the next apply).  The stopping test is the same in every case. */
 int sgn_set_schedule(sgn_ctx* ctx, int k_first, double tol);
 
-/* Statistics of the last sgn_apply / sgn_apply_fixed. */
+/* Statistics of the last sgn_apply / sgn_apply_fixed (after a batched
+ * apply: k_used and err_est are the largest over the sources, converged is 1
+ * only if all converged). */
 int sgn_last_info(const sgn_ctx* ctx, sgn_info* info);
 
-/* Device bytes an apply with this kmax needs beyond the resident field. */
+/* Device bytes an apply with this kmax needs beyond the resident field
+ * (nrhs = 1: sgn_apply; nrhs > 1: sgn_apply_batched with min(nrhs, 64)
+ * sources per chunk). */
 size_t sgn_footprint_bytes(const sgn_ctx* ctx, int kmax, int nrhs);
 
 /* ---- building blocks exposed for testing and measurement -------------- */

@@ -217,13 +217,13 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     if (n > 0) {
       if (delayed && kk > 0) {
         // finish the re-orthogonalisation of the last column, on a copy
-        ka.J = n;
+        ka.single(kk);
         ka.u = ucur;
         if (mixed)
-          krylov_dot<float2>(c->kw, ka, 1, false, false, s, prof);
+          krylov_dot<float2>(c->kw, ka, false, s, prof);
         else
-          krylov_dot<double2>(c->kw, ka, 1, false, false, s, prof);
-        krylov_patch(c->kw, ka, 1, n, c->F, 0, true, s);
+          krylov_dot<double2>(c->kw, ka, false, s, prof);
+        krylov_patch(c->kw, ka, n, c->F, 0, true, s);
         it = dense_sign(c->dense, n, c->F, n, c->F, n, s, prof);
       } else {
         it = dense_sign(c->dense, n, c->Hc, ncap, c->F, n, s, prof);
@@ -267,23 +267,22 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     for (int j = 0; j < kwant; ++j) {
       const int J = m + j;
       if (delayed) {
-        ka.J = J;
-        ka.j = j;
+        ka.single(j);
         ka.u = ucur;
         ka.unext = unext;
         if (mixed) {
           wilson_apply_multi32(c->lat, c->links32, u32cur, 0, c->z32, 0, 1, true, s, prof);
           ka.z = c->z32;
           ka.ulonext = u32next;
-          krylov_dot<float2>(c->kw, ka, 1, true, true, s, prof);
-          krylov_update<float2>(c->kw, ka, 1, s, prof);
+          krylov_dot<float2>(c->kw, ka, true, s, prof);
+          krylov_update<float2>(c->kw, ka, s, prof);
           std::swap(u32cur, u32next);
         } else {
           wilson_apply(c->lat, c->links, ucur, c->wB, nullptr, nullptr, s, prof);
           ka.z = c->wB;
           ka.ulonext = nullptr;
-          krylov_dot<double2>(c->kw, ka, 1, true, true, s, prof);
-          krylov_update<double2>(c->kw, ka, 1, s, prof);
+          krylov_dot<double2>(c->kw, ka, true, s, prof);
+          krylov_update<double2>(c->kw, ka, s, prof);
         }
         std::swap(ucur, unext);
       } else {
@@ -361,9 +360,9 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   const int n = m + k;
   if (delayed) {
     if (mixed)
-      krylov_combine<float2>(c->kw, ka, 1, c->cvec, 0, c->wB, 0, n, s, prof);
+      krylov_combine<float2>(c->kw, ka, c->cvec, 0, c->wB, 0, n, s, prof);
     else
-      krylov_combine<double2>(c->kw, ka, 1, c->cvec, 0, c->wB, 0, n, s, prof);
+      krylov_combine<double2>(c->kw, ka, c->cvec, 0, c->wB, 0, n, s, prof);
   } else {
     gs_combine(c->gs, c->Q, ldq, N, n, c->cvec, c->wB, nullptr, s, prof);
   }
@@ -403,8 +402,11 @@ void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std:
     SGN_REQUIRE(std::isfinite(d.x) && std::isfinite(d.y), SGN_EINVAL, "T has a non-finite diagonal");
     SGN_REQUIRE(d.x != 0.0, SGN_ESINGULAR, "T has an eigenvalue on the imaginary axis");
   }
-  // drop the old basis and the workspace (its layout depends on m)
+  // drop the old basis and the workspaces (their layout depends on m)
   c->release_workspace();
+  c->bw.release();
+  c->bw.k_hint = 0;
+  c->bw.rate_hint = 0.0;
   for (double2** p : {&c->S, &c->Tdev, &c->sgnT})
     if (*p) {
       SGN_HIP(hipFree(*p));
@@ -605,9 +607,12 @@ int sgn_set_precision(sgn_ctx* c, int prec) {
     SGN_HIP(hipStreamSynchronize(c->stream));
     if (prec == c->prec) return SGN_OK;
     c->release_workspace();
+    c->bw.release();
     c->prec = prec;
     c->k_hint = 0;
     c->rate_hint = 0.0;
+    c->bw.k_hint = 0;
+    c->bw.rate_hint = 0.0;
     if (prec == SGN_PREC_MIXED && !c->links32) {
       SGN_HIP(hipMalloc(&c->links32, sizeof(float2) * 36 * (size_t)c->lat.V));
       wilson_links_f32(c->links, c->links32, c->lat.V, c->stream);
@@ -623,6 +628,9 @@ int sgn_set_schedule(sgn_ctx* c, int k_first, double tol) {
     c->k_hint = k_first;
     c->tol_hint = tol;
     c->rate_hint = 0.0;
+    c->bw.k_hint = k_first;
+    c->bw.tol_hint = tol;
+    c->bw.rate_hint = 0.0;
     return SGN_OK;
   });
 }
@@ -652,11 +660,17 @@ int sgn_last_info(const sgn_ctx* c, sgn_info* info) {
 
 size_t sgn_footprint_bytes(const sgn_ctx* c, int kmax, int nrhs) {
   if (!c || kmax < 0 || nrhs < 1) return 0;
+  if (nrhs > 1) {
+    // sgn_apply_batched: per chunk of at most 64 sources
+    const size_t vt = c->prec == SGN_PREC_MIXED ? sizeof(float2) : sizeof(double2);
+    return BatchWork::bytes(c->ldq, c->m, std::max(kmax, 2), std::min(nrhs, kMaxBatch), vt) +
+           sizeof(double2) * c->ldq * (size_t)std::max(c->m, 1);
+  }
   const size_t ncap = (size_t)c->m + kmax + 1;
   const size_t per = sizeof(double2) * (c->ldq * (ncap + 3) + ncap * ncap + (ncap - 1) * (ncap - 1) + 4 * ncap) +
                      sizeof(double2) * c->ldq * ((ncap + 31) / 32);
   const size_t dense = 3 * sizeof(double2) * (ncap - 1) * (ncap - 1);
-  return per * (size_t)nrhs + dense;
+  return per + dense;
 }
 
 int sgn_matvec(sgn_ctx* c, const double* x, double* y) {

@@ -8,6 +8,68 @@
 #include "internal.h"
 #include "krylov.h"
 
+// Workspace of the batched apply (batch.hip): per slot r the Krylov columns,
+// candidates, stencil results, composite Hessenberg matrix and coefficients,
+// each at a fixed slot stride.  VT = FP64 (double2) or, in mixed precision,
+// FP32 (float2) for the Krylov columns and stencil operands.
+struct BatchWork {
+  int nslots = 0, kcap = 0, ncap = 0, prec = -1, m = -1;
+  size_t ldq = 0;
+  void* V = nullptr;         // [slot] ldq x (kcap + 1), VT
+  size_t vstride = 0;
+  double2* u = nullptr;      // [2][slot] ldq, FP64 candidates (ping-pong halves)
+  void* ulo = nullptr;       // [2][slot] ldq, VT copies of the candidates (mixed)
+  void* z = nullptr;         // [slot] ldq, VT stencil results
+  double2* xin = nullptr;    // [slot] ldq, packed sources
+  double2* y = nullptr;      // [slot] ldq, packed results
+  double2* H = nullptr;      // [slot] ncap x ncap
+  double2* F = nullptr;      // [launch slot] (m + kcap)^2, signs of one checkpoint
+  double2* c0 = nullptr;     // [slot] max(m, 1)
+  double2* cv = nullptr;     // [2][slot] ncap, coefficients (ping-pong halves)
+  double* beta = nullptr;    // [slot]
+  double* err = nullptr;     // [slot]
+  double* ref = nullptr;     // [slot] |x| (reference size of the first breakdown test)
+  double* inv = nullptr;     // [slot] scratch of the source normalisation
+  int* flag = nullptr;       // [slot] breakdown record
+  int* fin = nullptr;        // [slot] non-finite input flag
+  double* hpin = nullptr;    // pinned host mirror: err [slot], beta [slot], flag, fin [slot]
+  GsWork gs;
+  KrylovWork kw;
+  DenseWork dense;
+  // checkpoint placement learned by earlier batched applies (as k_hint, rate_hint)
+  int k_hint = 0;
+  double tol_hint = 0.0;
+  double rate_hint = 0.0;
+
+  size_t vt() const { return prec == SGN_PREC_MIXED ? sizeof(float2) : sizeof(double2); }
+  void release() {
+    for (void** p : {&V, (void**)&u, &ulo, &z, (void**)&xin, (void**)&y, (void**)&H, (void**)&F, (void**)&c0,
+                     (void**)&cv, (void**)&beta, (void**)&err, (void**)&ref, (void**)&inv, (void**)&flag,
+                     (void**)&fin})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = nullptr;
+    gs_free(gs);
+    krylov_free(kw);
+    dense_free(dense);
+    nslots = kcap = ncap = 0;
+    prec = m = -1;
+  }
+  // bytes ensure() allocates (kcap Krylov vectors for nslots right-hand sides)
+  static size_t bytes(size_t ldq, int m, int kcap, int nslots, size_t vt) {
+    const size_t ncap = (size_t)m + kcap + 1, n = (size_t)m + kcap, S = (size_t)nslots;
+    size_t b = S * ldq * (kcap + 1) * vt;                    // V
+    b += S * ldq * (2 * sizeof(double2) + 3 * vt + 2 * sizeof(double2));  // u, ulo, z, xin, y
+    b += S * sizeof(double2) * (ncap * ncap + n * n + (size_t)std::max(m, 1) + 2 * ncap);  // H, F, c0, cv
+    b += S * sizeof(double2) * 2 * (ncap + (ldq + 511) / 512 * ncap);  // dot partials, a, b
+    b += 3 * sizeof(double2) * n * n * S;                    // sign work matrices
+    return b;
+  }
+};
+
 struct sgn_ctx {
   Lattice lat{};
   int N = 0;
@@ -57,6 +119,7 @@ struct sgn_ctx {
   GsWork gs;
   KrylovWork kw;
   DenseWork dense;
+  BatchWork bw;
   // convergence history of previous applies on this field (checkpoint placement only)
   int k_hint = 0;
   double tol_hint = 0.0;
@@ -86,6 +149,7 @@ struct sgn_ctx {
     if (stream || true) (void)hipDeviceSynchronize();
     release_workspace();
     dense_free(dense);
+    bw.release();
     for (double2** p : {&links, &S, &Tdev, &sgnT})
       if (*p) {
         (void)hipFree(*p);

@@ -290,9 +290,17 @@ __global__ void copy_mat_batched_kernel(const double2* __restrict__ A, int lda, 
 
 // c[i] = sum_{q<m} F[i][q] c0[q] + beta F[i][m];  err = |c - [cprev; 0]| / |c|
 __global__ void __launch_bounds__(256)
-coeffs_kernel(int n, int m, const double2* __restrict__ F, int ldf, const double2* __restrict__ c0,
-              const double* __restrict__ beta, double2* __restrict__ c, const double2* __restrict__ cprev,
-              int nprev, double* __restrict__ err) {
+coeffs_kernel(int n, int m, const double2* __restrict__ F, int ldf, size_t fstride, const double2* __restrict__ c0,
+              int c0stride, const double* __restrict__ beta, double2* __restrict__ c,
+              const double2* __restrict__ cprev, int cstride, SlotMap map, double* __restrict__ err) {
+  const int z = blockIdx.x, r = map.slot[z], nprev = map.aux[z];
+  F += (size_t)z * fstride;
+  c0 += (size_t)r * c0stride;
+  beta += r;
+  c += (size_t)r * cstride;
+  if (nprev < 0) cprev = nullptr;
+  if (cprev) cprev += (size_t)r * cstride;
+  if (err) err += r;
   __shared__ double red[2][256];
   const int tid = threadIdx.x;
   const double b = *beta;
@@ -451,7 +459,18 @@ void dev_check_finite(const double2* v, size_t n, int* flag, hipStream_t s) {
 
 void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, const double* beta, double2* c,
                   const double2* cprev, int nprev, double* err, hipStream_t s) {
-  hipLaunchKernelGGL(coeffs_kernel, dim3(1), dim3(256), 0, s, n, m, F, ldf, c0, beta, c, cprev, nprev, err);
+  SlotMap one;
+  one.n = 1;
+  one.aux[0] = cprev ? nprev : -1;
+  dense_coeffs_batched(n, m, F, ldf, 0, c0, 0, beta, c, cprev, 0, one, err, s);
+}
+
+void dense_coeffs_batched(int n, int m, const double2* F, int ldf, size_t fstride, const double2* c0, int c0stride,
+                          const double* beta, double2* c, const double2* cprev, int cstride, const SlotMap& map,
+                          double* err, hipStream_t s) {
+  if (map.n <= 0) return;
+  hipLaunchKernelGGL(coeffs_kernel, dim3(map.n), dim3(256), 0, s, n, m, F, ldf, fstride, c0, c0stride, beta, c, cprev,
+                     cstride, map, err);
   SGN_HIP(hipGetLastError());
 }
 
@@ -546,7 +565,8 @@ constexpr int kGK = 16;  // k chunk
 template <int MODE>
 __global__ void __launch_bounds__(256) zgemm_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
                                                     double2* __restrict__ C, int n, double alpha,
-                                                    double* __restrict__ part, size_t nn) {
+                                                    double* __restrict__ part, size_t nn, unsigned long long skip) {
+  if ((skip >> blockIdx.z) & 1ull) return;  // this matrix has converged
   A += (size_t)blockIdx.z * nn;
   B += (size_t)blockIdx.z * nn;
   C += (size_t)blockIdx.z * nn;
@@ -645,9 +665,11 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
 
 }  // namespace
 
-// returns iterations, or -1 if the iteration did not converge
+// Newton-Schulz for nb matrices; returns the iterations run.  done marks the
+// matrices whose iteration met the stopping test (their F_b is written); the
+// others diverged or did not settle within the iteration limit.
 static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F,
-                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof) {
+                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done) {
   dense_alloc(d, n, nb);
   const size_t nn = (size_t)n * n;
   const int nt = (n + kGT - 1) / kGT;
@@ -671,15 +693,21 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
   const dim3 grid(nt, nt, nb);
   const int maxit = 60;
   int iters = 0;
-  for (int it = 1; it <= maxit; ++it) {
-    // per product: read two n x n operands, write one; 8 n^3 real flops
-    const double gb = nb * 3.0 * 16.0 * (double)nn, gf = nb * 8.0 * (double)nn * n;
+  SGN_REQUIRE(nb <= kMaxBatch, SGN_EINVAL, "dense_sign: batch too large");
+  done = 0;                      // matrices that met the stopping test (F written)
+  unsigned long long stop = 0;   // done, or left for the fallback
+  const unsigned long long all = nb == 64 ? ~0ull : ((1ull << nb) - 1);
+  for (int it = 1; it <= maxit && stop != all; ++it) {
+    // per product and matrix still iterating: read two n x n operands, write
+    // one; 8 n^3 real flops
+    const int nact = nb - __builtin_popcountll(stop);
+    const double gb = nact * 3.0 * 16.0 * (double)nn, gf = nact * 8.0 * (double)nn * n;
     int idx = prof ? prof->begin(K_NS_GEMM) : -1;
-    hipLaunchKernelGGL(zgemm_kernel<1>, grid, dim3(256), 0, s, X, X, Y, n, 1.0, d.spart, nn);
+    hipLaunchKernelGGL(zgemm_kernel<1>, grid, dim3(256), 0, s, X, X, Y, n, 1.0, d.spart, nn, stop);
     SGN_HIP(hipGetLastError());
     if (prof) prof->end(idx, gb, gf);
     idx = prof ? prof->begin(K_NS_GEMM) : -1;
-    hipLaunchKernelGGL(zgemm_kernel<0>, grid, dim3(256), 0, s, X, Y, Xn, n, 0.5, nullptr, nn);
+    hipLaunchKernelGGL(zgemm_kernel<0>, grid, dim3(256), 0, s, X, Y, Xn, n, 0.5, nullptr, nn, stop);
     SGN_HIP(hipGetLastError());
     if (prof) prof->end(idx, gb, gf);
     std::swap(X, Xn);
@@ -687,34 +715,39 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
     if (it < 6) continue;  // growth phase: no need to look yet
     SGN_HIP(hipMemcpyAsync(d.host_spart, d.spart, sizeof(double) * nparts, hipMemcpyDeviceToHost, s));
     SGN_HIP(hipStreamSynchronize(s));
-    double worst = 0.0;
-    bool ok = true;
     for (int b = 0; b < nb; ++b) {
+      if ((stop >> b) & 1ull) continue;
       double sum = 0.0;
       for (size_t t = 0; t < (size_t)nt * nt; ++t) sum += d.host_spart[(size_t)b * nt * nt + t];
       const double r = std::sqrt(sum / n);  // |X^2 - I| of the iterate before this update
-      if (!std::isfinite(r) || r > 1e3) ok = false;
-      worst = std::max(worst, r);
+      if (!std::isfinite(r) || r > 1e3) {
+        stop |= 1ull << b;  // diverging: left for the fallback
+      } else if (r < 1e-7) {
+        // error after the update ~ (3/2) (r/2)^2: below 1e-14 once r < 1e-7
+        hipLaunchKernelGGL(copy_mat_batched_kernel, dim3((unsigned)((nn + 255) / 256), 1), dim3(256), 0, s,
+                           X + (size_t)b * nn, n, nn, F + (size_t)b * fstride, ldf, fstride, n, n);
+        SGN_HIP(hipGetLastError());
+        done |= 1ull << b;
+        stop |= 1ull << b;
+      }
     }
-    if (!ok) return -1;
-    // error after the update ~ (3/2) (r/2)^2: below 1e-14 once r < 1e-7
-    if (worst < 1e-7) break;
-    if (it == maxit) return -1;
   }
-  hipLaunchKernelGGL(copy_mat_batched_kernel, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, s, X, n, nn, F,
-                     ldf, fstride, n, n);
-  SGN_HIP(hipGetLastError());
   return iters;
 }
 
 int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,
                        size_t fstride, hipStream_t s, Profiler* prof) {
   SGN_REQUIRE(n >= 1 && nb >= 1, SGN_EINVAL, "dense_sign: n and the batch must be positive");
-  if (d.method != 1) {
-    const int it = dense_sign_ns_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof);
-    if (it >= 0) return it;
-  }
-  return dense_sign_newton_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof);
+  if (d.method == 1) return dense_sign_newton_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof);
+  unsigned long long done = 0;
+  int it = dense_sign_ns_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof, done);
+  // Roberts' iteration for each matrix Newton-Schulz did not settle, one at a
+  // time (as it would run for that matrix alone)
+  for (int b = 0; b < nb; ++b)
+    if (!((done >> b) & 1ull))
+      it = std::max(it, dense_sign_newton_batched(d, n, 1, A + (size_t)b * astride, lda, astride,
+                                                  F + (size_t)b * fstride, ldf, fstride, s, prof));
+  return it;
 }
 
 int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,

@@ -150,6 +150,21 @@ void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStre
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);
 
+// most right-hand sides one launch carries; launch index z (blockIdx) works
+// on slot[z], aux[z] is a per-slot integer the caller defines
+constexpr int kMaxBatch = 64;
+struct SlotMap {
+  int n = 0;
+  int slot[kMaxBatch] = {};
+  int aux[kMaxBatch] = {};
+};
+
+// Out_slot = H_w(mu) In_slot for the slots of map (one hop per thread, the
+// same arithmetic per slot as wilson_apply), In/Out at fixed slot strides
+template <typename C>
+void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t istride, C* out, size_t ostride,
+                        const SlotMap& map, hipStream_t s, Profiler* prof);
+
 // Out_r = H_w(mu) In_r for nrhs vectors at fixed strides, one launch.  split: one
 // hop per thread for every right-hand side (each result bitwise independent of
 // nrhs); otherwise, for nrhs >= 2, one site per thread with the link shared.
@@ -187,12 +202,19 @@ void dense_free(DenseWork& d);
 // F = sgn(A) (n x n, ld = lda); returns iterations; throws SGN_ESINGULAR
 int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
                Profiler* prof);
-// F_b = sgn(A_b) for nb matrices at strides astride / fstride; iterates until every matrix converged
+// F_b = sgn(A_b) for nb <= kMaxBatch matrices at strides astride / fstride;
+// each matrix stops on its own test, so F_b is bitwise the single-matrix result
 int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,
                        size_t fstride, hipStream_t s, Profiler* prof);
 // c[i] = sum_{q<m} F[i][q] c0[q] + beta * F[i][m]  (i < n); err = |c - cprev_pad| / |c| if cprev
 void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, const double* beta, double2* c,
                   const double2* cprev, int nprev, double* err, hipStream_t s);
+// dense_coeffs for map.n matrices: F_z (stride fstride) belongs to slot
+// r = map.slot[z]; c0, beta, c, cprev, err are indexed by r; map.aux[z] is
+// that slot's nprev (< 0: no previous coefficients)
+void dense_coeffs_batched(int n, int m, const double2* F, int ldf, size_t fstride, const double2* c0, int c0stride,
+                          const double* beta, double2* c, const double2* cprev, int cstride, const SlotMap& map,
+                          double* err, hipStream_t s);
 // zero a device vector
 void dev_zero(double2* p, size_t n, hipStream_t s);
 void dev_copy_mat(const double2* A, int lda, double2* B, int ldb, int rows, int cols, hipStream_t s);

@@ -26,8 +26,11 @@ struct KrylovArgs {
   size_t ldq = 0;
   int m = 0;                    // Schur columns (FP64, shared by all slots)
   const double2* S = nullptr;   // ldq x m
-  int J = 0;                    // finished columns of Q
-  int j = 0;                    // step index (J = m + j)
+  // launch z (blockIdx.z < nb) works on slot act[z], whose step index is
+  // jv[z]: its basis has J = m + jv[z] finished columns
+  int nb = 1;
+  int act[kMaxBatch] = {};
+  int jv[kMaxBatch] = {};
   // Krylov columns: column c >= m of slot r at V + r*vstride + (c-m)*ldq (element type VT)
   void* V = nullptr;
   size_t vstride = 0;
@@ -47,7 +50,6 @@ struct KrylovArgs {
   int c0stride = 0;
   double* beta = nullptr;  // |x_perp| per slot (written at j = 0)
   int* flag = nullptr;     // breakdown record per slot: k_invariant + 1, or -1 for non-finite values
-  const int* act = nullptr;  // blockIdx.z -> slot (nullable: identity)
   // filled by krylov_bind from the workspace
   double2 *Pa = nullptr, *Pb = nullptr;
   double* Pcd = nullptr;
@@ -57,6 +59,18 @@ struct KrylovArgs {
   size_t abstride = 0;
   double* sc = nullptr;
   int nrt_dot = 0;
+
+  // host helpers
+  void single(int j) {  // one right-hand side in slot 0
+    nb = 1;
+    act[0] = 0;
+    jv[0] = j;
+  }
+  int jmax() const {
+    int x = 0;
+    for (int z = 0; z < nb; ++z) x = jv[z] > x ? jv[z] : x;
+    return x;
+  }
 };
 
 // partial sums of the dot pass [slot][row tile][column], the reduced
@@ -76,17 +90,17 @@ void krylov_alloc(KrylovWork& w, int N, size_t ldq, int ncol_cap, int nslots);
 void krylov_free(KrylovWork& w);
 void krylov_bind(const KrylovWork& w, KrylovArgs& A);
 
-// a = Q_J^dag u, b = Q_J^dag z (if with_z), step scalars; flag_on records breakdowns
+// a = Q_J^dag u, b = Q_J^dag z (if with_z), raw scalars; per launch slot
 template <typename VT>
-void krylov_dot(const KrylovWork& w, const KrylovArgs& A, int nb, bool with_z, bool flag_on, hipStream_t s,
-                Profiler* prof);
+void krylov_dot(const KrylovWork& w, const KrylovArgs& A, bool with_z, hipStream_t s, Profiler* prof);
 // v_J, next candidate, Hessenberg column J and re-orthogonalisation of column J-1
 template <typename VT>
-void krylov_update(const KrylovWork& w, const KrylovArgs& A, int nb, hipStream_t s, Profiler* prof);
-// y_r = Q_r coef_r over ncol columns
+void krylov_update(const KrylovWork& w, const KrylovArgs& A, hipStream_t s, Profiler* prof);
+// y_r = Q_r coef_r over ncol columns (the same ncol for every launch slot)
 template <typename VT>
-void krylov_combine(const KrylovWork& w, const KrylovArgs& A, int nb, const double2* coef, int cstride, double2* y,
+void krylov_combine(const KrylovWork& w, const KrylovArgs& A, const double2* coef, int cstride, double2* y,
                     size_t ystride, int ncol, hipStream_t s, Profiler* prof);
-// dst_r = H_r[:n,:n] (dense n x n at dstride) with column n-1 += a_r when with_a
-void krylov_patch(const KrylovWork& w, const KrylovArgs& A, int nb, int n, double2* dst, size_t dstride,
-                  bool with_a, hipStream_t s);
+// dst_z = H_r[:n,:n] (dense n x n at dstride, z = launch slot, r = act[z]) with
+// column n-1 += a_r when with_a
+void krylov_patch(const KrylovWork& w, const KrylovArgs& A, int n, double2* dst, size_t dstride, bool with_a,
+                  hipStream_t s);

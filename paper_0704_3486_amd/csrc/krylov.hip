@@ -68,7 +68,8 @@ __device__ inline double2 qload(const KrylovArgs& A, int r, int c, int i) {
   return ld2(V, i);
 }
 
-__device__ inline int slot_of(const KrylovArgs& A) { return A.act ? A.act[blockIdx.z] : (int)blockIdx.z; }
+__device__ inline int slot_of(const KrylovArgs& A) { return A.act[blockIdx.z]; }
+__device__ inline int step_of(const KrylovArgs& A) { return A.jv[blockIdx.z]; }
 
 // ---------------------------------------------------------------------------
 // dot pass: per (row tile, column group) partial sums of Q^dag u and Q^dag z,
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
   const int r = slot_of(A);
   const int rt = blockIdx.x, cg = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int N = A.N, J = A.J;
+  const int N = A.N, J = A.m + step_of(A);
   const int row0 = rt * kDRows;
   const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
   const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
 // fixed-order combine; workgroup 0 also sums the scalars c, d, |z|^2
 __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
   const int r = slot_of(A);
-  const int J = A.J, nrt = A.nrt_dot;
+  const int J = A.m + step_of(A), nrt = A.nrt_dot;
   const double2* Pa = A.Pa + (size_t)r * A.pstride;
   const double2* Pb = A.Pb + (size_t)r * A.pstride;
   const double* Pcd = A.Pcd + (size_t)r * A.cdstride;
@@ -200,7 +201,7 @@ struct StepScalars {
 
 template <int NT>
 __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* LDS [3][NT] */) {
-  const int J = A.J, tid = threadIdx.x;
+  const int J = A.m + step_of(A), tid = threadIdx.x;
   const double2* a = A.a + (size_t)r * A.abstride;
   const double2* b = A.b + (size_t)r * A.abstride;
   const double* sc = A.sc + (size_t)r * kScStride;
@@ -233,7 +234,7 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
   const double rho2 = c - aa;
   const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
   st.finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(zz);
-  st.brk = !(rho > 1e-14 * sc[kScRef + (A.j & 1)]) || !st.finite;
+  st.brk = !(rho > 1e-14 * sc[kScRef + (step_of(A) & 1)]) || !st.finite;
   st.inv = st.brk ? 0.0 : 1.0 / rho;
   st.rho = st.brk ? 0.0 : rho;
   st.gam = cscale(csub(d, ab), st.inv);
@@ -247,12 +248,12 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
 // wavefront (the lanes split the sum over columns); at j = 0 the correction
 // goes to c0 instead.
 __device__ void hcol_row_wave(const KrylovArgs& A, int r, int row, int lane, const StepScalars& st) {
-  const int J = A.J;
+  const int j = step_of(A), J = A.m + j;
   const double2* a = A.a + (size_t)r * A.abstride;
   const double2* b = A.b + (size_t)r * A.abstride;
   double2* H = A.H + (size_t)r * A.hstride;
   const int ldh = A.ldh;
-  const int lim = (A.j > 0) ? J - 1 : J;
+  const int lim = (j > 0) ? J - 1 : J;
   double2 ha = make_double2(0.0, 0.0);
   if (row < J)  // row J of columns < J-1 is below the subdiagonal (zero)
     for (int l = lane; l < lim; l += 64) ha = cfma(H[(size_t)l * ldh + row], a[l], ha);
@@ -260,7 +261,7 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int row, int lane, con
   if (lane != 0) return;
   const double rho = st.rho, inv = st.inv;
   const double2 g = (row < J) ? b[row] : st.gam;
-  if (A.j > 0) {
+  if (j > 0) {
     const double2 hl = (row < J) ? cadd(H[(size_t)(J - 1) * ldh + row], a[row]) : make_double2(rho, 0.0);
     ha = cfma(hl, a[J - 1], ha);
     H[(size_t)(J - 1) * ldh + row] = hl;
@@ -309,7 +310,7 @@ template <typename VT>
 __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
   const int r = slot_of(A);
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-  const int N = A.N, J = A.J;
+  const int N = A.N, j = step_of(A), J = A.m + j;
   const double2* av = A.a + (size_t)r * A.abstride;
   const double2* bv = A.b + (size_t)r * A.abstride;
   const int i = blockIdx.x * 64 + lane;
@@ -341,14 +342,14 @@ __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
       sc[kScScale] = st.scale;
       // reference size for the next step's breakdown test (the other parity
       // slot: this step's slot is still being read by other workgroups)
-      sc[kScRef + ((A.j + 1) & 1)] = st.scale;
-      if (A.j == 0 && A.beta) A.beta[r] = st.rho;
+      sc[kScRef + ((j + 1) & 1)] = st.scale;
+      if (j == 0 && A.beta) A.beta[r] = st.rho;
       if (A.flag) {
         int* f = A.flag + r;
         if (!st.finite)
           *f = -1;
         else if (st.brk && *f == 0)
-          *f = A.j + 1;
+          *f = j + 1;
       }
     }
   }
@@ -408,7 +409,7 @@ __global__ void kpatch_kernel(KrylovArgs A, int n, double2* __restrict__ dst, si
   const double2* H = A.H + (size_t)r * A.hstride;
   double2 v = H[(size_t)c * A.ldh + row];
   if (with_a && c == n - 1) v = cadd(v, A.a[(size_t)r * A.abstride + row]);
-  dst[(size_t)r * dstride + e] = v;
+  dst[(size_t)blockIdx.z * dstride + e] = v;
 }
 
 }  // namespace
@@ -458,83 +459,107 @@ void krylov_bind(const KrylovWork& w, KrylovArgs& A) {
   A.nrt_dot = w.nrt_dot;
 }
 
-static void check_args(const KrylovWork& w, const KrylovArgs& A, int nb) {
-  SGN_REQUIRE(A.J >= 0 && A.J <= w.ncol_cap, SGN_EINVAL, "krylov: J exceeds workspace");
-  SGN_REQUIRE(nb >= 1 && nb <= w.nslots, SGN_EINVAL, "krylov: batch exceeds workspace");
-  SGN_REQUIRE(A.J >= A.m, SGN_EINVAL, "krylov: J < m");
+static void check_args(const KrylovWork& w, const KrylovArgs& A) {
+  SGN_REQUIRE(A.nb >= 1 && A.nb <= w.nslots && A.nb <= kMaxBatch, SGN_EINVAL, "krylov: batch exceeds workspace");
+  for (int z = 0; z < A.nb; ++z) {
+    SGN_REQUIRE(A.act[z] >= 0 && A.act[z] < w.nslots, SGN_EINVAL, "krylov: slot out of range");
+    SGN_REQUIRE(A.jv[z] >= 0 && A.m + A.jv[z] <= w.ncol_cap, SGN_EINVAL, "krylov: J exceeds workspace");
+  }
 }
 
-template <typename VT>
-void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, int nb, bool with_z, bool flag_on, hipStream_t s,
-                Profiler* prof) {
-  KrylovArgs A = Ain;
-  krylov_bind(w, A);
-  check_args(w, A, nb);
-  const int ngroups = A.J > 0 ? (A.J + kDCols - 1) / kDCols : 1;
-  if (!flag_on) A.flag = nullptr;
-  const double vb = (double)sizeof(VT);
-  const double qbytes = (double)A.N * (16.0 * A.m + vb * (A.J - A.m));
-  // algorithmic bytes: Q, u, z read once; a, b written
-  int idx = prof ? prof->begin(K_KDOT) : -1;
-  hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, nb), dim3(256), 0, s, A, with_z ? 1 : 0);
-  SGN_HIP(hipGetLastError());
-  if (prof)
-    prof->end(idx, nb * (qbytes + A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * A.J), nb * 16.0 * (double)A.N * A.J);
-  // partial sums of every row tile read, a, b written
-  idx = prof ? prof->begin(K_KRED) : -1;
-  hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (A.J + 31) / 32), 1, nb), dim3(256), 0, s, A);
-  SGN_HIP(hipGetLastError());
-  if (prof) prof->end(idx, nb * (32.0 * A.J * (w.nrt_dot + 1.0) + 32.0 * w.nrt_dot), nb * 4.0 * A.J * w.nrt_dot);
-}
-
-template <typename VT>
-void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, int nb, hipStream_t s, Profiler* prof) {
-  KrylovArgs A = Ain;
-  krylov_bind(w, A);
-  check_args(w, A, nb);
-  SGN_REQUIRE(A.J + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
-  const int nblk = (A.N + 63) / 64;
-  const int idx = prof ? prof->begin(K_KUPDATE) : -1;
-  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(nblk, 1, nb), dim3(kUThreads), 0, s, A);
-  SGN_HIP(hipGetLastError());
-  if (prof) {
-    const double vb = (double)sizeof(VT);
-    const double qbytes = (double)A.N * (16.0 * A.m + vb * (A.J - A.m));
-    // read Q, u, z; write v_J, u' (+ its low-precision copy)
-    const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
-    prof->end(idx, nb * (qbytes + vec + 32.0 * A.J), nb * 16.0 * (double)A.N * A.J);
+// sum over the launch slots of the finished columns J, split into the FP64
+// Schur part and the Krylov part (for the algorithmic byte counts)
+static void col_sums(const KrylovArgs& A, double& sum_m, double& sum_k) {
+  sum_m = 0.0;
+  sum_k = 0.0;
+  for (int z = 0; z < A.nb; ++z) {
+    sum_m += A.m;
+    sum_k += A.jv[z];
   }
 }
 
 template <typename VT>
-void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, int nb, const double2* coef, int cstride,
-                    double2* y, size_t ystride, int ncol, hipStream_t s, Profiler* prof) {
+void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStream_t s, Profiler* prof) {
   KrylovArgs A = Ain;
   krylov_bind(w, A);
-  SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
-  const int idx = prof ? prof->begin(K_KCOMBINE) : -1;
-  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, nb), dim3(kUThreads), 0, s, A, coef, cstride, y,
-                     ystride, ncol);
+  check_args(w, A);
+  const int Jmax = A.m + A.jmax();
+  const int ngroups = Jmax > 0 ? (Jmax + kDCols - 1) / kDCols : 1;
+  const double vb = (double)sizeof(VT);
+  double sm, sk;
+  col_sums(A, sm, sk);
+  const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
+  // algorithmic bytes: Q, u, z read once; a, b written
+  int idx = prof ? prof->begin(K_KDOT) : -1;
+  hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, A.nb), dim3(256), 0, s, A, with_z ? 1 : 0);
   SGN_HIP(hipGetLastError());
-  if (prof) prof->end(idx, nb * (double)A.N * (16.0 * ncol + 16.0), nb * 8.0 * (double)A.N * ncol);
+  if (prof)
+    prof->end(idx, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * (sm + sk),
+              16.0 * (double)A.N * (sm + sk));
+  // partial sums of every row tile read, a, b written
+  idx = prof ? prof->begin(K_KRED) : -1;
+  hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (Jmax + 31) / 32), 1, A.nb), dim3(256), 0, s, A);
+  SGN_HIP(hipGetLastError());
+  if (prof)
+    prof->end(idx, 32.0 * (sm + sk) * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot, 4.0 * (sm + sk) * w.nrt_dot);
 }
 
-void krylov_patch(const KrylovWork& w, const KrylovArgs& Ain, int nb, int n, double2* dst, size_t dstride,
-                  bool with_a, hipStream_t s) {
+template <typename VT>
+void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Profiler* prof) {
   KrylovArgs A = Ain;
   krylov_bind(w, A);
+  check_args(w, A);
+  SGN_REQUIRE(A.m + A.jmax() + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
+  const int nblk = (A.N + 63) / 64;
+  const int idx = prof ? prof->begin(K_KUPDATE) : -1;
+  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(nblk, 1, A.nb), dim3(kUThreads), 0, s, A);
+  SGN_HIP(hipGetLastError());
+  if (prof) {
+    const double vb = (double)sizeof(VT);
+    double sm, sk;
+    col_sums(A, sm, sk);
+    const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
+    // read Q, u, z; write v_J, u' (+ its low-precision copy)
+    const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
+    prof->end(idx, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk));
+  }
+}
+
+template <typename VT>
+void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, const double2* coef, int cstride, double2* y,
+                    size_t ystride, int ncol, hipStream_t s, Profiler* prof) {
+  KrylovArgs A = Ain;
+  krylov_bind(w, A);
+  check_args(w, A);
+  SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
+  const int idx = prof ? prof->begin(K_KCOMBINE) : -1;
+  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, A.nb), dim3(kUThreads), 0, s, A, coef, cstride,
+                     y, ystride, ncol);
+  SGN_HIP(hipGetLastError());
+  if (prof) {
+    const double vb = (double)sizeof(VT);
+    const int nm = std::min(ncol, A.m);
+    prof->end(idx, A.nb * (double)A.N * (16.0 * nm + vb * (ncol - nm) + 16.0), A.nb * 8.0 * (double)A.N * ncol);
+  }
+}
+
+void krylov_patch(const KrylovWork& w, const KrylovArgs& Ain, int n, double2* dst, size_t dstride, bool with_a,
+                  hipStream_t s) {
+  KrylovArgs A = Ain;
+  krylov_bind(w, A);
+  check_args(w, A);
   const size_t tot = (size_t)n * n;
   if (tot == 0) return;
-  hipLaunchKernelGGL(kpatch_kernel, dim3((unsigned)((tot + 255) / 256), 1, nb), dim3(256), 0, s, A, n, dst,
+  hipLaunchKernelGGL(kpatch_kernel, dim3((unsigned)((tot + 255) / 256), 1, A.nb), dim3(256), 0, s, A, n, dst,
                      dstride, with_a ? 1 : 0);
   SGN_HIP(hipGetLastError());
 }
 
-template void krylov_dot<double2>(const KrylovWork&, const KrylovArgs&, int, bool, bool, hipStream_t, Profiler*);
-template void krylov_dot<float2>(const KrylovWork&, const KrylovArgs&, int, bool, bool, hipStream_t, Profiler*);
-template void krylov_update<double2>(const KrylovWork&, const KrylovArgs&, int, hipStream_t, Profiler*);
-template void krylov_update<float2>(const KrylovWork&, const KrylovArgs&, int, hipStream_t, Profiler*);
-template void krylov_combine<double2>(const KrylovWork&, const KrylovArgs&, int, const double2*, int, double2*,
-                                      size_t, int, hipStream_t, Profiler*);
-template void krylov_combine<float2>(const KrylovWork&, const KrylovArgs&, int, const double2*, int, double2*,
-                                     size_t, int, hipStream_t, Profiler*);
+template void krylov_dot<double2>(const KrylovWork&, const KrylovArgs&, bool, hipStream_t, Profiler*);
+template void krylov_dot<float2>(const KrylovWork&, const KrylovArgs&, bool, hipStream_t, Profiler*);
+template void krylov_update<double2>(const KrylovWork&, const KrylovArgs&, hipStream_t, Profiler*);
+template void krylov_update<float2>(const KrylovWork&, const KrylovArgs&, hipStream_t, Profiler*);
+template void krylov_combine<double2>(const KrylovWork&, const KrylovArgs&, const double2*, int, double2*, size_t,
+                                      int, hipStream_t, Profiler*);
+template void krylov_combine<float2>(const KrylovWork&, const KrylovArgs&, const double2*, int, double2*, size_t, int,
+                                     hipStream_t, Profiler*);

@@ -206,13 +206,14 @@ template <typename C>
 __global__ void __launch_bounds__(8 * kSplitSites)
 wilson_hw_split_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
                        size_t ostride, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx, int Ly,
-                       int Lz, int Lt, double kappa_d, double emu_d, double emmu_d) {
+                       int Lz, int Lt, double kappa_d, double emu_d, double emmu_d, SlotMap map) {
   using R = typename Real<C>::type;
   const int V = Lx * Ly * Lz * Lt;
   const int sl = threadIdx.x % kSplitSites, d = threadIdx.x / kSplitSites;
   const int n0 = blockIdx.x * kSplitSites;
   const int n = n0 + sl;
-  const C* __restrict__ v = in + (size_t)blockIdx.y * istride;
+  const int slot = map.n > 0 ? map.slot[blockIdx.y] : (int)blockIdx.y;
+  const C* __restrict__ v = in + (size_t)slot * istride;
   __shared__ C part[12][8][kSplitSites];
   if (n < V) {
     const int x = n % Lx;
@@ -234,7 +235,7 @@ wilson_hw_split_kernel(const C* __restrict__ links, const C* __restrict__ in, si
   __syncthreads();
   const R kappa = (R)kappa_d;
   const R scale = inv_beta ? (R)(*inv_beta) : (R)1;
-  C* __restrict__ w = out + (size_t)blockIdx.y * ostride;
+  C* __restrict__ w = out + (size_t)slot * ostride;
   for (int p = threadIdx.x; p < 12 * kSplitSites; p += 8 * kSplitSites) {
     const int comp = p / kSplitSites, s2 = p % kSplitSites;
     const int nn = n0 + s2;
@@ -308,7 +309,7 @@ void wilson_apply(const Lattice& lat, const double2* links, const double2* in, d
   const int idx = prof ? prof->begin(K_WILSON) : -1;
   hipLaunchKernelGGL((wilson_hw_split_kernel<double2>), dim3((V + kSplitSites - 1) / kSplitSites, 1),
                      dim3(8 * kSplitSites), 0, s, links, in, (size_t)0, out, (size_t)0, inv_beta, copy_out, lat.L[0],
-                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu);
+                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{});
   SGN_HIP(hipGetLastError());
   if (prof) {
     // algorithmic bytes: read v (12), write w (12), 4 links of 9 (36) per site; + copy (12)
@@ -332,7 +333,7 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
   if (split || nrhs == 1) {
     hipLaunchKernelGGL((wilson_hw_split_kernel<C>), dim3((V + kSplitSites - 1) / kSplitSites, nrhs),
                        dim3(8 * kSplitSites), 0, s, links, in, istride, out, ostride, nullptr, nullptr, L0, L1, L2,
-                       L3, lat.kappa, lat.emu, lat.emmu);
+                       L3, lat.kappa, lat.emu, lat.emmu, SlotMap{});
   } else if (nrhs >= 4 && sizeof(C) == 8) {
     hipLaunchKernelGGL((wilson_hw_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), blk, 0, s, links, in, istride, out,
                        ostride, nrhs, L0, L1, L2, L3, lat.kappa, lat.emu, lat.emmu);
@@ -347,6 +348,27 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
     prof->end(idx, (24.0 * nrhs + 36.0) * b * V, 1392.0 * V * nrhs);
   }
 }
+
+template <typename C>
+void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t istride, C* out, size_t ostride,
+                        const SlotMap& map, hipStream_t s, Profiler* prof) {
+  SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
+  const int V = lat.V;
+  const int idx = prof ? prof->begin(K_WILSON) : -1;
+  hipLaunchKernelGGL((wilson_hw_split_kernel<C>), dim3((V + kSplitSites - 1) / kSplitSites, map.n),
+                     dim3(8 * kSplitSites), 0, s, links, in, istride, out, ostride, nullptr, nullptr, lat.L[0],
+                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, map);
+  SGN_HIP(hipGetLastError());
+  if (prof) {
+    const double b = (double)sizeof(C);
+    // per site and slot: read v (12), write w (12), the links (36)
+    prof->end(idx, 60.0 * b * V * map.n, 1392.0 * V * map.n);
+  }
+}
+template void wilson_apply_slots<double2>(const Lattice&, const double2*, const double2*, size_t, double2*, size_t,
+                                          const SlotMap&, hipStream_t, Profiler*);
+template void wilson_apply_slots<float2>(const Lattice&, const float2*, const float2*, size_t, float2*, size_t,
+                                         const SlotMap&, hipStream_t, Profiler*);
 
 void wilson_apply_multi(const Lattice& lat, const double2* links, const double2* in, size_t istride, double2* out,
                         size_t ostride, int nrhs, bool split, hipStream_t s, Profiler* prof) {
