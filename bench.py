@@ -223,10 +223,17 @@ def calibrate_copy(torch):
     n = 1 << 29  # float32 elements
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(3):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+    ms = e0.elapsed_time(e1) / 3
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 4,
+                      "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}))
 
 
 def cpu_baseline(ctxs, xs, ks, sg, torch, links):

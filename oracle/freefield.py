@@ -49,6 +49,27 @@ def momentum_matrices(dims, mu: float, m_w: float):
     return H, c
 
 
+def _momentum_apply(x: np.ndarray, dims, M: np.ndarray) -> np.ndarray:
+    """Apply the per-momentum 4x4 spin matrices M(p) to x (colour untouched).
+
+    The antiperiodic time direction enters as the phase e^{-i pi t / L_t}
+    before the FFT (momenta p_4 = (2 n_4 + 1) pi / L_t) and its inverse after.
+    """
+    lx, ly, lz, lt = (int(d) for d in dims)
+    psi = x.reshape(lt, lz, ly, lx, 4, 3)
+    tph = np.exp(-1j * np.pi * np.arange(lt) / lt)[:, None, None, None, None, None]
+    f = np.fft.fftn(psi * tph, axes=(0, 1, 2, 3))
+    f = np.einsum("...ab,...bc->...ac", M, f)
+    out = np.fft.ifftn(f, axes=(0, 1, 2, 3)) / tph
+    return out.reshape(-1)
+
+
+def h_free_apply(x: np.ndarray, dims, mu: float, m_w: float) -> np.ndarray:
+    """H_w(mu) x for U = 1 (Eq. Dw times gamma5), by FFT: H(p) per momentum."""
+    H, _ = momentum_matrices(dims, mu, m_w)
+    return _momentum_apply(x, dims, H)
+
+
 def sgn_free_apply(x: np.ndarray, dims, mu: float, m_w: float) -> np.ndarray:
     """sgn(H_w(mu)) x for U = 1, by FFT and the closed form H(p)/sqrt(c(p))."""
     lx, ly, lz, lt = (int(d) for d in dims)
@@ -59,12 +80,7 @@ def sgn_free_apply(x: np.ndarray, dims, mu: float, m_w: float) -> np.ndarray:
     H2 = np.einsum("...ab,...bc->...ac", H, H)
     assert np.allclose(H2, c[..., None, None] * np.eye(4), atol=1e-12)
     M = H / np.sqrt(c)[..., None, None]
-    psi = x.reshape(lt, lz, ly, lx, 4, 3)
-    tph = np.exp(-1j * np.pi * np.arange(lt) / lt)[:, None, None, None, None, None]
-    f = np.fft.fftn(psi * tph, axes=(0, 1, 2, 3))
-    f = np.einsum("...ab,...bc->...ac", M, f)
-    out = np.fft.ifftn(f, axes=(0, 1, 2, 3)) / tph
-    return out.reshape(-1)
+    return _momentum_apply(x, dims, M)
 
 
 def free_eigenvalues(dims, mu: float, m_w: float) -> np.ndarray:

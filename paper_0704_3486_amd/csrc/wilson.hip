@@ -196,59 +196,161 @@ wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t i
   }
 }
 
-// Out_r = H_w(mu) In_r with one hop per thread: a workgroup holds kSplitSites
-// sites x 8 hops, the per-hop terms meet in LDS and are summed in hop order.
-// Eight times the parallelism of one site per thread, for small lattices and
-// single right-hand sides (blockIdx.y = right-hand side).
-// Optional: scale = *inv_beta on input and output, copy_out = In * scale.
-constexpr int kSplitSites = 16;
+// Workgroup b runs on XCD b mod 8, each XCD with its own L2.  Renumber the
+// blocks so that XCD x works through one contiguous range of sites (about
+// 1/8 of the lattice): the neighbour spinors and backward-hop links a block
+// reads were then mostly fetched into the same L2 by the blocks just before
+// it.  A bijection on [0, nblk).
+constexpr int kXcds = 8;
+constexpr int kSiteGroup = 32;  // sites per workgroup of the stencil
+__device__ inline int xcd_block(int b, int nblk) {
+  const int x = b % kXcds, i = b / kXcds, q = nblk / kXcds, r = nblk % kXcds;
+  return x * q + min(x, r) + i;
+}
+
+// Order in which the workgroups (16 lexicographically consecutive sites
+// each) visit the lattice.  Lexicographic order puts the t-neighbours of a
+// site a whole time slice of work away, beyond L2 on large lattices.  The
+// blocked order walks 4D blocks of Lx x By x Bz x Bt sites (inside a block:
+// 16-site segments of By rows, then z, then t; the blocks with t fastest), so
+// every neighbour of a site is touched within about Lx By Bz sites of work.
+// on = 0: lexicographic (lattices the blocks do not tile, or too small to care).
+struct SiteOrder {
+  int on = 0;
+  int By = 1, Bz = 1, Bt = 1;
+  int segw = 1;  // workgroups per segment: Lx By / kSiteGroup
+};
+
+// first site of logical workgroup w
+__device__ inline int order_site(int w, const SiteOrder& o, int Lx, int Ly, int Lz, int Lt, int sites_per_wg) {
+  if (!o.on) return w * sites_per_wg;
+  const int wpb = o.segw * o.Bz * o.Bt;
+  const int blk = w / wpb, in = w - blk * wpb;
+  const int seg = in % o.segw, zi = (in / o.segw) % o.Bz, ti = in / (o.segw * o.Bz);
+  const int ntb = Lt / o.Bt, nzb = Lz / o.Bz;
+  const int tb = blk % ntb, zb = (blk / ntb) % nzb, yb = blk / (ntb * nzb);
+  const int t = tb * o.Bt + ti, z = zb * o.Bz + zi, y0 = yb * o.By;
+  return ((t * Lz + z) * Ly + y0) * Lx + seg * sites_per_wg;
+}
+
 template <typename C>
-__global__ void __launch_bounds__(8 * kSplitSites)
-wilson_hw_split_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
-                       size_t ostride, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx, int Ly,
-                       int Lz, int Lt, double kappa_d, double emu_d, double emmu_d, SlotMap map) {
+__device__ inline C shfl_xor_c(C v, int mask) {
+  return mk<C>(__shfl_xor(v.x, mask, 64), __shfl_xor(v.y, mask, 64));
+}
+
+// Out_r = H_w(mu) In_r.  A workgroup holds kSiteGroup = 32 sites and four
+// wavefronts, wavefront nu taking direction nu for all 32 sites: lanes 0..31
+// the forward hop, lanes 32..63 the backward hop of the same sites.  The
+// direction, its link array, spin projector and phase are then uniform over
+// the wavefront; the backward lanes turn U_{m,nu} into U_{m,nu}^dag with
+// selects, so both halves run one instruction stream.  One butterfly shuffle
+// (xor 32) adds the two hops, p_nu = fwd_nu + bwd_nu (the same bits in both
+// halves: addition is commutative); the four p_nu meet in LDS and are summed
+// in direction order.  The site's own spinor entries for the second phase
+// are loaded with the hop operands, so a workgroup waits on memory once.
+// blockIdx.y = right-hand side (slot map).  Optional: scale = *inv_beta on
+// input and output, copy_out = In * scale.
+template <typename C>
+__global__ void __launch_bounds__(256)
+wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
+                     size_t ostride, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx, int Ly,
+                     int Lz, int Lt, double kappa_d, double emu_d, double emmu_d, SlotMap map, SiteOrder order) {
   using R = typename Real<C>::type;
+  constexpr int kThreads = 256, kOut = 12 * kSiteGroup;
   const int V = Lx * Ly * Lz * Lt;
-  const int sl = threadIdx.x % kSplitSites, d = threadIdx.x / kSplitSites;
-  const int n0 = blockIdx.x * kSplitSites;
+  const int lane = threadIdx.x & 63;
+  const int nu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sl = lane & (kSiteGroup - 1);
+  const bool fwd = lane < kSiteGroup;
+  const int n0 = order_site(xcd_block(blockIdx.x, gridDim.x), order, Lx, Ly, Lz, Lt, kSiteGroup);
   const int n = n0 + sl;
+  const int nc = n < V ? n : V - 1;  // lanes past the lattice work on a valid site, never written out
   const int slot = map.n > 0 ? map.slot[blockIdx.y] : (int)blockIdx.y;
   const C* __restrict__ v = in + (size_t)slot * istride;
-  __shared__ C part[12][8][kSplitSites];
-  if (n < V) {
-    const int x = n % Lx;
-    const int y = (n / Lx) % Ly;
-    const int z = (n / (Lx * Ly)) % Lz;
-    const int t = n / (Lx * Ly * Lz);
-    const int m = hop_neighbour(n, d, x, y, z, t, Lx, Ly, Lz, Lt);
-    const int ls = (d & 1) == 0 ? n : m;
-    C u[9];
+  // second-phase outputs of this thread: p = tid + q kThreads < kOut, i.e.
+  // component p / kSiteGroup of site n0 + p % kSiteGroup
+  C self[2];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) u[e] = links[((d >> 1) * 9 + e) * V + ls];
-    C o[4][3];
-    hop_term<C>(u, v, V, m, d, (R)emu_d, (R)emmu_d, o);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) part[3 * s + c][d][sl] = o[s][c];
+  for (int q = 0; q < 2; ++q) {
+    const int p = threadIdx.x + q * kThreads, nn = n0 + p % kSiteGroup;
+    self[q] = (p < kOut && nn < V) ? v[(size_t)(p / kSiteGroup) * V + nn] : mk<C>(0, 0);
   }
+  const int x = nc % Lx;
+  const int y = (nc / Lx) % Ly;
+  const int z = (nc / (Lx * Ly)) % Lz;
+  const int t = nc / (Lx * Ly * Lz);
+  const int m = hop_neighbour(nc, 2 * nu + (fwd ? 0 : 1), x, y, z, t, Lx, Ly, Lz, Lt);
+  const int ls = fwd ? nc : m;  // site that owns the link
+  const C* __restrict__ lp = links + (size_t)nu * 9 * V;
+  C u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = lp[(size_t)e * V + ls];
+  // the matrix applied to the half spinor: U (forward) or U^dag (backward)
+  C w9[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C a = u[3 * r + c], b = u[3 * c + r];
+      w9[3 * r + c] = fwd ? a : mk<C>(b.x, -b.y);
+    }
+  const SpinProj P = spin_proj(nu);
+  const R sg = fwd ? (R)1 : (R)-1;
+  const R phase = (nu == 3) ? (fwd ? (R)emu_d : (R)emmu_d) : (R)1;
+  C h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const C p0 = v[(size_t)c * V + m];
+    const C p1 = v[(size_t)(3 + c) * V + m];
+    const C pa = v[(size_t)(3 * P.i0 + c) * V + m];
+    const C pb = v[(size_t)(3 * P.i1 + c) * V + m];
+    h0[c] = tadd(p0, unit_mul(P.a0r, P.a0i, pa, sg));
+    h1[c] = tadd(p1, unit_mul(P.a1r, P.a1i, pb, sg));
+  }
+  C o[4][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    C s0 = mk<C>(0, 0), s1 = mk<C>(0, 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s0 = tfma(w9[3 * r + c], h0[c], s0);
+      s1 = tfma(w9[3 * r + c], h1[c], s1);
+    }
+    o[0][r] = tscale(s0, phase);
+    o[1][r] = tscale(s1, phase);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const C x0 = (P.j0 == 0) ? o[0][c] : o[1][c];
+    const C x1 = (P.j1 == 0) ? o[0][c] : o[1][c];
+    o[2][c] = unit_mul(P.b0r, P.b0i, x0, sg);
+    o[3][c] = unit_mul(P.b1r, P.b1i, x1, sg);
+  }
+  __shared__ C part[12][4][kSiteGroup];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C pnu = tadd(o[s][c], shfl_xor_c(o[s][c], 32));
+      if (fwd) part[3 * s + c][nu][sl] = pnu;
+    }
   __syncthreads();
   const R kappa = (R)kappa_d;
   const R scale = inv_beta ? (R)(*inv_beta) : (R)1;
   C* __restrict__ w = out + (size_t)slot * ostride;
-  for (int p = threadIdx.x; p < 12 * kSplitSites; p += 8 * kSplitSites) {
-    const int comp = p / kSplitSites, s2 = p % kSplitSites;
-    const int nn = n0 + s2;
-    if (nn >= V) continue;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = threadIdx.x + q * kThreads;
+    const int comp = p / kSiteGroup, s2 = p % kSiteGroup, nn = n0 + s2;
+    if (p >= kOut || nn >= V) continue;
     C acc = mk<C>(0, 0);
 #pragma unroll
-    for (int h = 0; h < 8; ++h) acc = tadd(acc, part[comp][h][s2]);
+    for (int k = 0; k < 4; ++k) acc = tadd(acc, part[comp][k][s2]);
     const size_t idx = (size_t)comp * V + nn;
-    const C self = v[idx];
     // gamma5 (psi - kappa * hops), all times 1/beta
     const R g5 = comp < 6 ? (R)1 : (R)-1;
-    w[idx] = tscale(tsub(self, tscale(acc, kappa)), g5 * scale);
-    if (copy_out) copy_out[idx] = tscale(self, scale);
+    w[idx] = tscale(tsub(self[q], tscale(acc, kappa)), g5 * scale);
+    if (copy_out) copy_out[idx] = tscale(self[q], scale);
   }
 }
 
@@ -303,13 +405,33 @@ void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStre
   SGN_HIP(hipGetLastError());
 }
 
+// the blocked order when the lattice is large enough to leave L2 and its
+// extents admit the blocks (Lx By a multiple of the workgroup's 16 sites)
+static SiteOrder site_order(const Lattice& lat) {
+  SiteOrder o;
+  const int Lx = lat.L[0], Ly = lat.L[1], Lz = lat.L[2], Lt = lat.L[3];
+  if (lat.V < 65536) return o;
+  auto pick = [](int L, int cap, auto ok) {
+    for (int b = cap; b >= 1; b /= 2)
+      if (L % b == 0 && ok(b)) return b;
+    return 0;
+  };
+  o.By = pick(Ly, 8, [&](int b) { return (Lx * b) % kSiteGroup == 0; });
+  o.Bz = pick(Lz, 8, [](int) { return true; });
+  o.Bt = pick(Lt, 4, [](int) { return true; });
+  if (o.By == 0 || o.Bz == 0 || o.Bt == 0) return SiteOrder{};
+  o.segw = Lx * o.By / kSiteGroup;
+  o.on = 1;
+  return o;
+}
+
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof) {
   const int V = lat.V;
   const int idx = prof ? prof->begin(K_WILSON) : -1;
-  hipLaunchKernelGGL((wilson_hw_split_kernel<double2>), dim3((V + kSplitSites - 1) / kSplitSites, 1),
-                     dim3(8 * kSplitSites), 0, s, links, in, (size_t)0, out, (size_t)0, inv_beta, copy_out, lat.L[0],
-                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{});
+  hipLaunchKernelGGL((wilson_hw_dir_kernel<double2>), dim3((V + kSiteGroup - 1) / kSiteGroup, 1),
+                     dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0, inv_beta, copy_out, lat.L[0],
+                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{}, site_order(lat));
   SGN_HIP(hipGetLastError());
   if (prof) {
     // algorithmic bytes: read v (12), write w (12), 4 links of 9 (36) per site; + copy (12)
@@ -331,9 +453,9 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
   const unsigned gx = (V + kWilsonBlock - 1) / kWilsonBlock;
   const int L0 = lat.L[0], L1 = lat.L[1], L2 = lat.L[2], L3 = lat.L[3];
   if (split || nrhs == 1) {
-    hipLaunchKernelGGL((wilson_hw_split_kernel<C>), dim3((V + kSplitSites - 1) / kSplitSites, nrhs),
-                       dim3(8 * kSplitSites), 0, s, links, in, istride, out, ostride, nullptr, nullptr, L0, L1, L2,
-                       L3, lat.kappa, lat.emu, lat.emmu, SlotMap{});
+    hipLaunchKernelGGL((wilson_hw_dir_kernel<C>), dim3((V + kSiteGroup - 1) / kSiteGroup, nrhs),
+                       dim3(256), 0, s, links, in, istride, out, ostride, nullptr, nullptr, L0, L1, L2,
+                       L3, lat.kappa, lat.emu, lat.emmu, SlotMap{}, site_order(lat));
   } else if (nrhs >= 4 && sizeof(C) == 8) {
     hipLaunchKernelGGL((wilson_hw_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), blk, 0, s, links, in, istride, out,
                        ostride, nrhs, L0, L1, L2, L3, lat.kappa, lat.emu, lat.emmu);
@@ -355,9 +477,9 @@ void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t 
   SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
   const int V = lat.V;
   const int idx = prof ? prof->begin(K_WILSON) : -1;
-  hipLaunchKernelGGL((wilson_hw_split_kernel<C>), dim3((V + kSplitSites - 1) / kSplitSites, map.n),
-                     dim3(8 * kSplitSites), 0, s, links, in, istride, out, ostride, nullptr, nullptr, lat.L[0],
-                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, map);
+  hipLaunchKernelGGL((wilson_hw_dir_kernel<C>), dim3((V + kSiteGroup - 1) / kSiteGroup, map.n),
+                     dim3(256), 0, s, links, in, istride, out, ostride, nullptr, nullptr, lat.L[0],
+                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, map, site_order(lat));
   SGN_HIP(hipGetLastError());
   if (prof) {
     const double b = (double)sizeof(C);

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import arnoldi, deflation, matfunc, wilson
+from oracle import arnoldi, deflation, freefield, matfunc, wilson
 
 pytestmark = pytest.mark.gpu
 
@@ -55,6 +55,25 @@ def test_matvec_matches_oracle(env, dims, mu):
         sg.sgn_matvec(ctx, _dev(torch, x), y)
         ref = wilson.hw_matrix(links, dims, mu, M_W) @ x
         assert _rel(y.cpu().numpy(), ref) < 1e-14
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (20, 16, 16, 16), (16, 8, 32, 16)])
+def test_matvec_large_pure_gauge(env, dims):
+    """Lattices large enough for the blocked site order of the stencil: no
+    dense oracle fits, so the exact relation H[U] (Omega x) = Omega H[1] x for
+    pure-gauge links U = Omega_n Omega_{n+nu}^dag (H[1] by FFT) is checked."""
+    sg, torch = env
+    print("matvec pure gauge", dims, flush=True)
+    om = synth.random_su3_field(dims, 11)
+    ctx = sg.sgn_create(synth.pure_gauge_links(om), dims, 0.3, M_W)
+    try:
+        x = synth.gaussian_source(dims, 4)
+        y = torch.empty(x.size, dtype=torch.complex128, device="cuda")
+        sg.sgn_matvec(ctx, _dev(torch, synth.gauge_transform_spinor(om, x)), y)
+        ref = synth.gauge_transform_spinor(om, freefield.h_free_apply(x, dims, 0.3, M_W))
+        assert _rel(y.cpu().numpy(), ref) < 1e-13
     finally:
         sg.sgn_destroy(ctx)
 

@@ -116,6 +116,27 @@ def test_free_field_closed_form_matches_dense(mu):
     assert np.linalg.norm(y_dense - y_free) < 1e-12 * np.linalg.norm(y_dense)
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 2, 4), (3, 2, 4, 2)])
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_free_field_operator_matches_dense(dims, mu):
+    # H(p) by FFT vs the literal Eq. (Dw) matrix (every hop, the boundary sign)
+    H = wilson.hw_matrix(_unit_links(dims), dims, mu, M_W)
+    x = synth.gaussian_source(dims, 5)
+    y = freefield.h_free_apply(x, dims, mu, M_W)
+    assert np.linalg.norm(H @ x - y) < 1e-13 * np.linalg.norm(y)
+
+
+def test_pure_gauge_operator_is_rotated_free_operator():
+    # H[U] (Omega x) = Omega H[1] x for U_{n,nu} = Omega_n Omega_{n+nu}^dag
+    dims = (2, 3, 2, 4)
+    om = synth.random_su3_field(dims, 8)
+    U = synth.pure_gauge_links(om)
+    x = synth.gaussian_source(dims, 6)
+    lhs = wilson.hw_matrix(U, dims, 0.2, M_W) @ synth.gauge_transform_spinor(om, x)
+    rhs = synth.gauge_transform_spinor(om, freefield.h_free_apply(x, dims, 0.2, M_W))
+    assert np.linalg.norm(lhs - rhs) < 1e-13 * np.linalg.norm(rhs)
+
+
 def test_free_field_spectrum():
     dims = (2, 2, 2, 4)
     H = wilson.hw_matrix(_unit_links(dims), dims, 0.3, M_W).toarray()
