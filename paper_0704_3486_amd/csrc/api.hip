@@ -367,9 +367,10 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     gs_combine(c->gs, c->Q, ldq, N, n, c->cvec, c->wB, nullptr, s, prof);
   }
   wilson_unpack(c->lat, c->wB, y_abi, s);
+  SGN_HIP(hipMemcpyAsync(&c->hpin[6], &c->scal[0], sizeof(double), hipMemcpyDeviceToHost, s));
   SGN_HIP(hipStreamSynchronize(s));
   if (prof) c->prof.flush();
-  SGN_HIP(hipMemcpy(&info.beta, &c->scal[0], sizeof(double), hipMemcpyDeviceToHost));
+  info.beta = c->hpin[6];
 
   info.k_used = k;
   info.converged = converged ? 1 : 0;

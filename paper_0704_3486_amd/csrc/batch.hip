@@ -63,6 +63,7 @@ void batch_ensure(sgn_ctx* c, int nslots, int kcap) {
   SGN_HIP(hipHostMalloc(&b.hpin, sizeof(double) * 4 * S, hipHostMallocDefault));
   gs_alloc(b.gs, c->N, ldq, (int)mm);
   krylov_alloc(b.kw, c->N, ldq, b.ncap, nslots);
+  dense_reserve(b.dense, (int)n, nslots);
   // the Schur block T_m of every slot's composite matrix never changes
   SGN_HIP(hipMemset(b.H, 0, sizeof(double2) * ncap * ncap * S));
   for (int r = 0; r < nslots && m > 0; ++r) dev_copy_mat(c->Tdev, m, b.H + (size_t)r * ncap * ncap, b.ncap, m, m, nullptr);

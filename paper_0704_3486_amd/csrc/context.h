@@ -194,6 +194,7 @@ struct sgn_ctx {
     SGN_HIP(hipMalloc(&cprev, sizeof(double2) * (size_t)ncap));
     gs_alloc(gs, N, ldq, ncap);
     krylov_alloc(kw, N, ldq, ncap, 1);
+    dense_reserve(dense, m + kcap, 1);
     // the Schur block of Q and of H never changes between applies
     if (m > 0) {
       SGN_HIP(hipMemcpy2D(Q, ldq * sizeof(double2), S, ldq * sizeof(double2), ldq * sizeof(double2), m,

@@ -345,15 +345,19 @@ __global__ void finite_kernel(const double2* __restrict__ v, size_t n, int* __re
   }
 }
 
+size_t lds_budget();
+
 template <int BP>
 void launch_panel(const double2* Min, double2* Mout, int n, int p0, int nb, DenseWork& d, hipStream_t s) {
   const size_t lds = gj_lds_bytes(n, BP);
-  static size_t configured = 0;
-  if (lds > configured) {
+  // allow the kernel the whole budget once (thread-safe: contexts may run on
+  // several host threads)
+  static const bool configured = [] {
     SGN_HIP(hipFuncSetAttribute((const void*)gj_panel_kernel<BP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    configured = lds;
-  }
+                                (int)lds_budget()));
+    return true;
+  }();
+  (void)configured;
   const int nblk = (n + kGjTile - 1) / kGjTile;
   hipLaunchKernelGGL(gj_panel_kernel<BP>, dim3(nblk, nb), dim3(kGjThreads), lds, s, Min, Mout, n, p0, d.rowpiv,
                      d.logpiv, d.flag, (size_t)n * n);
@@ -361,17 +365,18 @@ void launch_panel(const double2* Min, double2* Mout, int n, int p0, int nb, Dens
 
 }  // namespace
 
-static size_t lds_budget() {
-  static size_t cached = 0;
-  if (!cached) {
+namespace {
+size_t lds_budget() {
+  static const size_t cached = [] {
     int dev = 0, v = 0;
     SGN_HIP(hipGetDevice(&dev));
     SGN_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     // leave room for the kernel's static LDS arrays
-    cached = (size_t)std::max(v, 16384) - 2048;
-  }
+    return (size_t)std::max(v, 16384) - 2048;
+  }();
   return cached;
 }
+}  // namespace
 
 static int panel_width(int n) {
   const size_t budget = lds_budget();
@@ -405,6 +410,8 @@ void dense_alloc(DenseWork& d, int n, int nb) {
 }
 
 void dense_alloc(DenseWork& d, int n) { dense_alloc(d, n, 1); }
+
+
 
 void dense_free(DenseWork& d) {
   if (d.S) (void)hipFree(d.S);
@@ -665,13 +672,9 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
 
 }  // namespace
 
-// Newton-Schulz for nb matrices; returns the iterations run.  done marks the
-// matrices whose iteration met the stopping test (their F_b is written); the
-// others diverged or did not settle within the iteration limit.
-static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F,
-                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done) {
-  dense_alloc(d, n, nb);
-  const size_t nn = (size_t)n * n;
+// partial sums of |X^2 - I| per 32 x 32 tile (and the column sums of the
+// 1-norm) for nb matrices of order n; returns the entries in use
+static size_t ns_reserve(DenseWork& d, int n, int nb) {
   const int nt = (n + kGT - 1) / kGT;
   const size_t nparts = std::max((size_t)nt * nt, (size_t)n) * nb;
   if (d.nspart < nparts) {
@@ -681,6 +684,18 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
     SGN_HIP(hipHostMalloc(&d.host_spart, sizeof(double) * nparts, hipHostMallocDefault));
     d.nspart = nparts;
   }
+  return nparts;
+}
+
+// Newton-Schulz for nb matrices; returns the iterations run.  done marks the
+// matrices whose iteration met the stopping test (their F_b is written); the
+// others diverged or did not settle within the iteration limit.
+static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F,
+                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done) {
+  dense_alloc(d, n, nb);
+  const size_t nn = (size_t)n * n;
+  const int nt = (n + kGT - 1) / kGT;
+  const size_t nparts = ns_reserve(d, n, nb);
   // the column sums use the partial-sum buffer (sized above for both uses)
   hipLaunchKernelGGL(colsum_kernel, dim3((n + 3) / 4, nb), dim3(256), 0, s, A, lda, astride, d.spart, n);
   SGN_HIP(hipGetLastError());
@@ -733,6 +748,11 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
     }
   }
   return iters;
+}
+
+void dense_reserve(DenseWork& d, int n, int nb) {
+  dense_alloc(d, n, nb);
+  ns_reserve(d, n, nb);
 }
 
 int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,

@@ -199,6 +199,9 @@ struct DenseWork {
 void dense_alloc(DenseWork& d, int n);
 void dense_alloc(DenseWork& d, int n, int nb);
 void dense_free(DenseWork& d);
+// allocate everything dense_sign_batched needs up to order n and batch nb,
+// so that later calls of at most that size allocate nothing
+void dense_reserve(DenseWork& d, int n, int nb);
 // F = sgn(A) (n x n, ld = lda); returns iterations; throws SGN_ESINGULAR
 int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
                Profiler* prof);
