@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true", help="skip the 32^4 stencil measurement")
+    ap.add_argument("--serial", action="store_true",
+                    help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
+                         "whose per-kernel averages then compare with the HIP-event ones)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 2 GiB three times (the reference for the "
                          "HBM traffic counters) and exit")
@@ -147,15 +150,17 @@ def main():
                 field_steps(f, r, 1, ks)
         return ks
 
-    run_concurrent(0, args.warmup)
+    runner = run_serial if args.serial else run_concurrent
+    runner(0, args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ks = run_concurrent(args.warmup, args.steps)
+    ks = runner(args.warmup, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     applies = args.steps * len(MUS)
     value = applies / elapsed
-    log(f"timed (3 streams): {applies} applies in {elapsed:.3f} s -> {value:.2f} applies/s, mean k {np.mean(ks):.1f}")
+    mode = "serial" if args.serial else "3 streams"
+    log(f"timed ({mode}): {applies} applies in {elapsed:.3f} s -> {value:.2f} applies/s, mean k {np.mean(ks):.1f}")
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,7 +243,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sgn(H_w(mu))x, 6^4 lattice (N=15552), m_w=-1.6, mu in {0.0,0.2,0.5}, "
                                "m=20 Schur deflation, kmax=500, tol=1e-10, FP64, 1 RHS per apply, "
-                               "3 applies per step (one per field, fields on separate streams)",
+                               "3 applies per step (one per field"
+                               + (", one at a time)" if args.serial else ", fields on separate streams)"),
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
                    "mean_k": round(float(np.mean(ks)), 1)},
         "accuracy": acc,

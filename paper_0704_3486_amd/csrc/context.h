@@ -54,7 +54,7 @@ struct BatchWork {
     hpin = nullptr;
     gs_free(gs);
     krylov_free(kw);
-    dense_free(dense);
+    dense_destroy(dense);
     nslots = kcap = ncap = 0;
     prec = m = -1;
   }
@@ -148,7 +148,7 @@ struct sgn_ctx {
   void release() {
     if (stream || true) (void)hipDeviceSynchronize();
     release_workspace();
-    dense_free(dense);
+    dense_destroy(dense);
     bw.release();
     for (double2** p : {&links, &S, &Tdev, &sgnT})
       if (*p) {

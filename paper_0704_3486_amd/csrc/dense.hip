@@ -19,6 +19,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <rocblas/rocblas.h>
+
 #include "internal.h"
 
 namespace {
@@ -428,8 +430,16 @@ void dense_free(DenseWork& d) {
   if (d.spart) (void)hipFree(d.spart);
   if (d.host_spart) (void)hipHostFree(d.host_spart);
   const int method = d.method;
+  void* blas = d.blas;
   d = DenseWork{};
   d.method = method;
+  d.blas = blas;
+}
+
+void dense_destroy(DenseWork& d) {
+  dense_free(d);
+  if (d.blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(d.blas));
+  d.blas = nullptr;
 }
 
 void dev_zero(double2* p, size_t n, hipStream_t s) {
@@ -564,74 +574,53 @@ static int dense_sign_newton_batched(DenseWork& d, int n, int nb, const double2*
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kGT = 32;  // output tile
-constexpr int kGK = 16;  // k chunk
+constexpr int kEpi = 256;  // entries per workgroup of the epilogue
 
-// C = alpha A B (MODE 0) or C = 3I - A B with part[tile] = sum |A B - I|^2 (MODE 1);
-// n x n column-major (ld n), blockIdx.z = matrix of the batch (stride nn)
-template <int MODE>
-__global__ void __launch_bounds__(256) zgemm_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
-                                                    double2* __restrict__ C, int n, double alpha,
-                                                    double* __restrict__ part, size_t nn, unsigned long long skip) {
-  if ((skip >> blockIdx.z) & 1ull) return;  // this matrix has converged
-  A += (size_t)blockIdx.z * nn;
-  B += (size_t)blockIdx.z * nn;
-  C += (size_t)blockIdx.z * nn;
-  __shared__ double2 As[kGT][kGK + 1];
-  __shared__ double2 Bs[kGK][kGT + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.x * kGT, j0 = blockIdx.y * kGT;
-  double2 c00 = make_double2(0, 0), c01 = c00, c10 = c00, c11 = c00;
-  for (int k0 = 0; k0 < n; k0 += kGK) {
-    for (int e = tid; e < kGT * kGK; e += 256) {
-      const int i = e & (kGT - 1), kk = e / kGT;  // A tile: coalesced over i
-      const int gi = i0 + i, gk = k0 + kk;
-      As[i][kk] = (gi < n && gk < n) ? A[(size_t)gk * n + gi] : make_double2(0, 0);
-      const int kb = e & (kGK - 1), jb = e / kGK;  // B tile: coalesced over k
-      const int gkb = k0 + kb, gj = j0 + jb;
-      Bs[kb][jb] = (gkb < n && gj < n) ? B[(size_t)gj * n + gkb] : make_double2(0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kGK; ++kk) {
-      const double2 a0 = As[tx][kk], a1 = As[tx + 16][kk];
-      const double2 b0 = Bs[kk][ty], b1 = Bs[kk][ty + 16];
-      c00 = cfma(a0, b0, c00);
-      c01 = cfma(a0, b1, c01);
-      c10 = cfma(a1, b0, c10);
-      c11 = cfma(a1, b1, c11);
-    }
-    __syncthreads();
+void blas_check(rocblas_status st) {
+  if (st != rocblas_status_success)
+    throw SgnError{SGN_EHIP, std::string("rocBLAS: ") + rocblas_status_to_string(st)};
+}
+
+// the context's rocBLAS handle on stream s: host scalars, no atomics in the
+// GEMM kernels (results reproducible run to run)
+rocblas_handle blas_handle(DenseWork& d, hipStream_t s) {
+  if (!d.blas) {
+    rocblas_handle h = nullptr;
+    blas_check(rocblas_create_handle(&h));
+    d.blas = h;
+    blas_check(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+    blas_check(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));
   }
-  double2 cv[4] = {c00, c01, c10, c11};
+  rocblas_handle h = static_cast<rocblas_handle>(d.blas);
+  blas_check(rocblas_set_stream(h, s));
+  return h;
+}
+
+// Y = 3I - P in place, P = X^2 from the GEMM, and per kEpi entries the
+// partial sum of |P - I|^2 (fixed-order tree); blockIdx.y = matrix of the
+// batch (stride nn), skipped once it has stopped
+__global__ void __launch_bounds__(kEpi) ns_epilogue_kernel(double2* __restrict__ Y, int n, size_t nn,
+                                                           double* __restrict__ part, int nblk,
+                                                           unsigned long long skip) {
+  const int b = blockIdx.y;
+  if ((skip >> b) & 1ull) return;
+  const size_t e = (size_t)blockIdx.x * kEpi + threadIdx.x;
   double p = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gi = i0 + tx + 16 * (q >> 1), gj = j0 + ty + 16 * (q & 1);
-    if (gi < n && gj < n) {
-      double2 v = cv[q];
-      if (MODE == 0) {
-        v = cscale(v, alpha);
-      } else {
-        const double dI = (gi == gj) ? 1.0 : 0.0;
-        const double2 dv = make_double2(v.x - dI, v.y);
-        p += cabs2(dv);
-        v = make_double2(3.0 * dI - v.x, -v.y);
-      }
-      C[(size_t)gj * n + gi] = v;
-    }
+  if (e < nn) {
+    const int j = (int)(e / n), i = (int)(e - (size_t)j * n);
+    const double2 v = Y[(size_t)b * nn + e];
+    const double dI = (i == j) ? 1.0 : 0.0;
+    p = (v.x - dI) * (v.x - dI) + v.y * v.y;
+    Y[(size_t)b * nn + e] = make_double2(3.0 * dI - v.x, -v.y);
   }
-  if (MODE == 1) {
-    __shared__ double red[256];
-    red[tid] = p;
+  __shared__ double red[kEpi];
+  red[threadIdx.x] = p;
+  __syncthreads();
+  for (int off = kEpi / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) red[tid] += red[tid + off];
-      __syncthreads();
-    }
-    if (tid == 0) part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
   }
+  if (threadIdx.x == 0) part[(size_t)b * nblk + blockIdx.x] = red[0];
 }
 
 // X_b = A_b / |A_b|_1 (max column sum of |a_ij|); one workgroup per matrix
@@ -672,11 +661,11 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
 
 }  // namespace
 
-// partial sums of |X^2 - I| per 32 x 32 tile (and the column sums of the
+// partial sums of |X^2 - I| per kEpi entries (and the column sums of the
 // 1-norm) for nb matrices of order n; returns the entries in use
 static size_t ns_reserve(DenseWork& d, int n, int nb) {
-  const int nt = (n + kGT - 1) / kGT;
-  const size_t nparts = std::max((size_t)nt * nt, (size_t)n) * nb;
+  const size_t nblk = ((size_t)n * n + kEpi - 1) / kEpi;
+  const size_t nparts = std::max(nblk, (size_t)n) * nb;
   if (d.nspart < nparts) {
     if (d.spart) (void)hipFree(d.spart);
     if (d.host_spart) (void)hipHostFree(d.host_spart);
@@ -694,8 +683,7 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
                                  int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done) {
   dense_alloc(d, n, nb);
   const size_t nn = (size_t)n * n;
-  const int nt = (n + kGT - 1) / kGT;
-  const size_t nparts = ns_reserve(d, n, nb);
+  ns_reserve(d, n, nb);
   // the column sums use the partial-sum buffer (sized above for both uses)
   hipLaunchKernelGGL(colsum_kernel, dim3((n + 3) / 4, nb), dim3(256), 0, s, A, lda, astride, d.spart, n);
   SGN_HIP(hipGetLastError());
@@ -705,35 +693,46 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
   double2* X = d.S;
   double2* Y = d.Ma;
   double2* Xn = d.Mb;
-  const dim3 grid(nt, nt, nb);
+  const int nblk = (int)((nn + kEpi - 1) / kEpi);
   const int maxit = 60;
   int iters = 0;
   SGN_REQUIRE(nb <= kMaxBatch, SGN_EINVAL, "dense_sign: batch too large");
   done = 0;                      // matrices that met the stopping test (F written)
   unsigned long long stop = 0;   // done, or left for the fallback
   const unsigned long long all = nb == 64 ? ~0ull : ((1ull << nb) - 1);
+  rocblas_handle h = blas_handle(d, s);
+  const rocblas_double_complex one(1.0, 0.0), half(0.5, 0.0), zero(0.0, 0.0);
+  auto rc = [](const double2* p) { return reinterpret_cast<const rocblas_double_complex*>(p); };
+  auto rw = [](double2* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
   for (int it = 1; it <= maxit && stop != all; ++it) {
     // per product and matrix still iterating: read two n x n operands, write
-    // one; 8 n^3 real flops
-    const int nact = nb - __builtin_popcountll(stop);
-    const double gb = nact * 3.0 * 16.0 * (double)nn, gf = nact * 8.0 * (double)nn * n;
-    int idx = prof ? prof->begin(K_NS_GEMM) : -1;
-    hipLaunchKernelGGL(zgemm_kernel<1>, grid, dim3(256), 0, s, X, X, Y, n, 1.0, d.spart, nn, stop);
+    // one; 8 n^3 real flops.  One GEMM call per matrix, so a matrix gets the
+    // same arithmetic in any batch.
+    for (int b = 0; b < nb; ++b) {
+      if ((stop >> b) & 1ull) continue;
+      const int idx = prof ? prof->begin(K_NS_GEMM) : -1;
+      blas_check(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, rc(X + b * nn), n,
+                               rc(X + b * nn), n, &zero, rw(Y + b * nn), n));
+      if (prof) prof->end(idx, 3.0 * 16.0 * (double)nn, 8.0 * (double)nn * n);
+    }
+    hipLaunchKernelGGL(ns_epilogue_kernel, dim3(nblk, nb), dim3(kEpi), 0, s, Y, n, nn, d.spart, nblk, stop);
     SGN_HIP(hipGetLastError());
-    if (prof) prof->end(idx, gb, gf);
-    idx = prof ? prof->begin(K_NS_GEMM) : -1;
-    hipLaunchKernelGGL(zgemm_kernel<0>, grid, dim3(256), 0, s, X, Y, Xn, n, 0.5, nullptr, nn, stop);
-    SGN_HIP(hipGetLastError());
-    if (prof) prof->end(idx, gb, gf);
+    for (int b = 0; b < nb; ++b) {
+      if ((stop >> b) & 1ull) continue;
+      const int idx = prof ? prof->begin(K_NS_GEMM) : -1;
+      blas_check(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &half, rc(X + b * nn), n,
+                               rc(Y + b * nn), n, &zero, rw(Xn + b * nn), n));
+      if (prof) prof->end(idx, 3.0 * 16.0 * (double)nn, 8.0 * (double)nn * n);
+    }
     std::swap(X, Xn);
     iters = it;
     if (it < 6) continue;  // growth phase: no need to look yet
-    SGN_HIP(hipMemcpyAsync(d.host_spart, d.spart, sizeof(double) * nparts, hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipMemcpyAsync(d.host_spart, d.spart, sizeof(double) * (size_t)nblk * nb, hipMemcpyDeviceToHost, s));
     SGN_HIP(hipStreamSynchronize(s));
     for (int b = 0; b < nb; ++b) {
       if ((stop >> b) & 1ull) continue;
       double sum = 0.0;
-      for (size_t t = 0; t < (size_t)nt * nt; ++t) sum += d.host_spart[(size_t)b * nt * nt + t];
+      for (int t = 0; t < nblk; ++t) sum += d.host_spart[(size_t)b * nblk + t];
       const double r = std::sqrt(sum / n);  // |X^2 - I| of the iterate before this update
       if (!std::isfinite(r) || r > 1e3) {
         stop |= 1ull << b;  // diverging: left for the fallback

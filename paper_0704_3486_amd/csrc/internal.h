@@ -195,10 +195,14 @@ struct DenseWork {
   unsigned* counters = nullptr;
   double* part = nullptr;  // reduction partials
   int npart = 0;
+  void* blas = nullptr;    // rocBLAS handle (Newton-Schulz GEMMs), created on first use
 };
 void dense_alloc(DenseWork& d, int n);
 void dense_alloc(DenseWork& d, int n, int nb);
+// free the buffers (the rocBLAS handle stays for reuse)
 void dense_free(DenseWork& d);
+// free everything, the rocBLAS handle included
+void dense_destroy(DenseWork& d);
 // allocate everything dense_sign_batched needs up to order n and batch nb,
 // so that later calls of at most that size allocate nothing
 void dense_reserve(DenseWork& d, int n, int nb);

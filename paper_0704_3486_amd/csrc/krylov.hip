@@ -110,9 +110,10 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
     uv[t] = (i < N) ? u[i] : make_double2(0.0, 0.0);
     zv[t] = (with_z && i < N) ? ld2(z, i) : make_double2(0.0, 0.0);
   }
+  const int cw = cg * kDCols + wave * kCpw;  // first column of this wavefront
 #pragma unroll
   for (int cc = 0; cc < kCpw; ++cc) {
-    const int c = cg * kDCols + wave * kCpw + cc;
+    const int c = cw + cc;
     if (c < J) {
       double2 aa = make_double2(0.0, 0.0), bb = make_double2(0.0, 0.0);
       if (c < A.m) {
@@ -182,11 +183,14 @@ __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
     A.a[(size_t)r * A.abstride + c] = ta;
     A.b[(size_t)r * A.abstride + c] = tb;
   }
-  if (blockIdx.x == 0 && threadIdx.x >= 64 && threadIdx.x < 68) {
-    const int q = threadIdx.x - 64;
+  if (blockIdx.x == 0) {
+    // wavefront q sums scalar q over the row tiles: lane partials (tiles
+    // lane, lane + 64, ...) then a fixed butterfly
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double acc = 0.0;
-    for (int t = 0; t < nrt; ++t) acc += Pcd[4 * t + q];
-    A.sc[(size_t)r * kScStride + kScRawC + q] = acc;
+    for (int t = lane; t < nrt; t += 64) acc += Pcd[4 * t + q];
+    acc = wsum1(acc);
+    if (lane == 0) A.sc[(size_t)r * kScStride + kScRawC + q] = acc;
   }
 }
 
