@@ -494,18 +494,13 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStre
   col_sums(A, sm, sk);
   const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
   // algorithmic bytes: Q, u, z read once; a, b written
-  int idx = prof ? prof->begin(K_KDOT) : -1;
-  hipLaunchKernelGGL(kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, A.nb), dim3(256), 0, s, A, with_z ? 1 : 0);
-  SGN_HIP(hipGetLastError());
-  if (prof)
-    prof->end(idx, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * (sm + sk),
-              16.0 * (double)A.N * (sm + sk));
+  prof_launch(prof, K_KDOT, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * (sm + sk),
+              16.0 * (double)A.N * (sm + sk), kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, A.nb), dim3(256), 0, s, A,
+              with_z ? 1 : 0);
   // partial sums of every row tile read, a, b written
-  idx = prof ? prof->begin(K_KRED) : -1;
-  hipLaunchKernelGGL(kred_kernel, dim3(std::max(1, (Jmax + 31) / 32), 1, A.nb), dim3(256), 0, s, A);
-  SGN_HIP(hipGetLastError());
-  if (prof)
-    prof->end(idx, 32.0 * (sm + sk) * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot, 4.0 * (sm + sk) * w.nrt_dot);
+  prof_launch(prof, K_KRED, 32.0 * (sm + sk) * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot,
+              4.0 * (sm + sk) * w.nrt_dot, kred_kernel, dim3(std::max(1, (Jmax + 31) / 32), 1, A.nb), dim3(256), 0, s,
+              A);
 }
 
 template <typename VT>
@@ -515,18 +510,14 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   check_args(w, A);
   SGN_REQUIRE(A.m + A.jmax() + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
   const int nblk = (A.N + 63) / 64;
-  const int idx = prof ? prof->begin(K_KUPDATE) : -1;
-  hipLaunchKernelGGL(kupdate_kernel<VT>, dim3(nblk, 1, A.nb), dim3(kUThreads), 0, s, A);
-  SGN_HIP(hipGetLastError());
-  if (prof) {
-    const double vb = (double)sizeof(VT);
-    double sm, sk;
-    col_sums(A, sm, sk);
-    const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
-    // read Q, u, z; write v_J, u' (+ its low-precision copy)
-    const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
-    prof->end(idx, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk));
-  }
+  const double vb = (double)sizeof(VT);
+  double sm, sk;
+  col_sums(A, sm, sk);
+  const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
+  // read Q, u, z; write v_J, u' (+ its low-precision copy)
+  const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
+  prof_launch(prof, K_KUPDATE, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk),
+              kupdate_kernel<VT>, dim3(nblk, 1, A.nb), dim3(kUThreads), 0, s, A);
 }
 
 template <typename VT>
@@ -536,15 +527,11 @@ void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, const double2* c
   krylov_bind(w, A);
   check_args(w, A);
   SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
-  const int idx = prof ? prof->begin(K_KCOMBINE) : -1;
-  hipLaunchKernelGGL(kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, A.nb), dim3(kUThreads), 0, s, A, coef, cstride,
-                     y, ystride, ncol);
-  SGN_HIP(hipGetLastError());
-  if (prof) {
-    const double vb = (double)sizeof(VT);
-    const int nm = std::min(ncol, A.m);
-    prof->end(idx, A.nb * (double)A.N * (16.0 * nm + vb * (ncol - nm) + 16.0), A.nb * 8.0 * (double)A.N * ncol);
-  }
+  const double vb = (double)sizeof(VT);
+  const int nm = std::min(ncol, A.m);
+  prof_launch(prof, K_KCOMBINE, A.nb * (double)A.N * (16.0 * nm + vb * (ncol - nm) + 16.0),
+              A.nb * 8.0 * (double)A.N * ncol, kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, A.nb), dim3(kUThreads),
+              0, s, A, coef, cstride, y, ystride, ncol);
 }
 
 void krylov_patch(const KrylovWork& w, const KrylovArgs& Ain, int n, double2* dst, size_t dstride, bool with_a,

@@ -428,16 +428,12 @@ static SiteOrder site_order(const Lattice& lat) {
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof) {
   const int V = lat.V;
-  const int idx = prof ? prof->begin(K_WILSON) : -1;
-  hipLaunchKernelGGL((wilson_hw_dir_kernel<double2>), dim3((V + kSiteGroup - 1) / kSiteGroup, 1),
-                     dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0, inv_beta, copy_out, lat.L[0],
-                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{}, site_order(lat));
-  SGN_HIP(hipGetLastError());
-  if (prof) {
-    // algorithmic bytes: read v (12), write w (12), 4 links of 9 (36) per site; + copy (12)
-    const double per_site = (60.0 + (copy_out ? 12.0 : 0.0)) * 16.0;
-    prof->end(idx, per_site * V, 1392.0 * V);
-  }
+  // algorithmic bytes: read v (12), write w (12), 4 links of 9 (36) per site; + copy (12)
+  const double per_site = (60.0 + (copy_out ? 12.0 : 0.0)) * 16.0;
+  prof_launch(prof, K_WILSON, per_site * V, 1392.0 * V, wilson_hw_dir_kernel<double2>,
+              dim3((V + kSiteGroup - 1) / kSiteGroup, 1), dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0,
+              inv_beta, copy_out, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{},
+              site_order(lat));
 }
 
 // several right-hand sides: one hop per thread (bitwise the single-RHS
@@ -476,16 +472,12 @@ void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t 
                         const SlotMap& map, hipStream_t s, Profiler* prof) {
   SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
   const int V = lat.V;
-  const int idx = prof ? prof->begin(K_WILSON) : -1;
-  hipLaunchKernelGGL((wilson_hw_dir_kernel<C>), dim3((V + kSiteGroup - 1) / kSiteGroup, map.n),
-                     dim3(256), 0, s, links, in, istride, out, ostride, nullptr, nullptr, lat.L[0],
-                     lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, map, site_order(lat));
-  SGN_HIP(hipGetLastError());
-  if (prof) {
-    const double b = (double)sizeof(C);
-    // per site and slot: read v (12), write w (12), the links (36)
-    prof->end(idx, 60.0 * b * V * map.n, 1392.0 * V * map.n);
-  }
+  // per site and slot: read v (12), write w (12), the links (36)
+  const double b = (double)sizeof(C);
+  prof_launch(prof, K_WILSON, 60.0 * b * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
+              dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
+              (const double*)nullptr, (C*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
+              lat.emmu, map, site_order(lat));
 }
 template void wilson_apply_slots<double2>(const Lattice&, const double2*, const double2*, size_t, double2*, size_t,
                                           const SlotMap&, hipStream_t, Profiler*);
