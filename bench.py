@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sgn(H_w(mu))·x applies/sec at 1e-10 rel err; stencil HBM GB/s vs peak"
 HBM_PEAK_GBPS = 8000.0
-FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP64_MFMA_PEAK_TFLOPS = 78.6
 # profiling class -> kernel symbol (as rocprofv3 lists it)
 HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_kernel<double2>",
                "krylov_reduce": "kred_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stencil", action="store_true", help="skip the 32^4 stencil measurement")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only run the 32^4 stencil measurement and print its JSON object")
     ap.add_argument("--serial", action="store_true",
                     help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
                          "whose per-kernel averages then compare with the HIP-event ones)")
@@ -89,6 +91,10 @@ def main():
 
     import paper_0704_3486_amd as sg
     import synth
+
+    if args.stencil_only:
+        print(json.dumps(stencil_leg(sg, synth, torch)))
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -204,9 +210,9 @@ def main():
     if "ns_gemm" in kstats and kstats["ns_gemm"]["ms"] > 0:
         s = kstats["ns_gemm"]
         tf = s["flops"] / (s["ms"] * 1e-3) / 1e12
-        sign = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4), "avg_launch_us": kern["ns_gemm"]["avg_us"],
-                "kernel": "zgemm_kernel"}
+        sign = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4), "avg_launch_us": kern["ns_gemm"]["avg_us"],
+                "kernel": "rocBLAS ZGEMM (Tensile Cijk_..._ZB_MI16x16x4, FP64 MFMA), Newton-Schulz products"}
     stencil_6 = None
     if "wilson_hw" in kstats and kstats["wilson_hw"]["ms"] > 0:
         s = kstats["wilson_hw"]

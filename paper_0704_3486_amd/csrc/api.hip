@@ -42,22 +42,16 @@ hipEvent_t Profiler::get_event() {
 
 int Profiler::begin(int cls) {
   if (!on) return -1;
-  Pending p{get_event(), get_event(), cls, false};
+  Pending p{get_event(), get_event(), cls};
   SGN_HIP(hipEventRecord(p.a, stream));
   pending.push_back(p);
-  return (int)pending.size() - 1;
-}
-
-int Profiler::open(int cls) {
-  if (!on) return -1;
-  pending.push_back(Pending{get_event(), get_event(), cls, true});
   return (int)pending.size() - 1;
 }
 
 void Profiler::end(int idx, double nbytes, double nflops) {
   if (!on || idx < 0) return;
   Pending& p = pending[idx];
-  if (!p.self_timed) SGN_HIP(hipEventRecord(p.b, stream));
+  SGN_HIP(hipEventRecord(p.b, stream));
   launches[p.cls] += 1;
   bytes[p.cls] += nbytes;
   flops[p.cls] += nflops;

@@ -1,7 +1,6 @@
 // Internal declarations shared by the HIP translation units of libsgn.
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -88,32 +87,27 @@ struct Profiler {
   struct Pending {
     hipEvent_t a, b;
     int cls;
-    bool self_timed;  // events set by the launch itself (open)
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t get_event();
   // bracket a launch: returns index of pending record or -1
   int begin(int cls);
-  // a launch that timestamps its own events (hipExtLaunchKernelGGL): the
-  // events measure the kernel alone, as a kernel trace does
-  int open(int cls);
-  hipEvent_t start_event(int idx) const { return idx < 0 ? nullptr : pending[idx].a; }
-  hipEvent_t stop_event(int idx) const { return idx < 0 ? nullptr : pending[idx].b; }
+
   void end(int idx, double nbytes, double nflops);
   void flush();  // synchronise and accumulate the pending durations
   void reset();
   ~Profiler();
 };
 
-// Launch kernel<<<grid, block, shm, s>>>(args...); with profiling on, the
-// dispatch itself timestamps the class's start and stop events.
+// Launch kernel<<<grid, block, shm, s>>>(args...); with profiling on, bracket
+// it with events on s (recorded in stream order, so the interval never covers
+// earlier work; it includes the launch gap, about 2 us on the 6^4 workload).
 template <typename F, typename... Args>
 inline void prof_launch(Profiler* prof, int cls, double nbytes, double nflops, F kernel, dim3 grid, dim3 block,
                         uint32_t shm, hipStream_t s, Args... args) {
-  const int idx = prof ? prof->open(cls) : -1;
-  hipExtLaunchKernelGGL(kernel, grid, block, shm, s, prof ? prof->start_event(idx) : nullptr,
-                        prof ? prof->stop_event(idx) : nullptr, 0, args...);
+  const int idx = prof ? prof->begin(cls) : -1;
+  hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
   SGN_HIP(hipGetLastError());
   if (prof) prof->end(idx, nbytes, nflops);
 }
