@@ -1,21 +1,27 @@
 // C ABI of libsgn: context management and the deflated modified Arnoldi
-// driver (Section 5.2, steps (iii)-(vi)).
+// driver (Section 5.2, steps (iii)-(vi)) for one source.
 //
-// Per source x (step (iii)):  pack x, two classical Gram-Schmidt passes
-// against S_m give c0 = S^dag x and x_perp, beta = |x_perp|.
-// Per Krylov step j (step (iv), Eq. eq:modArnoldi), all on the device:
-//     w  = H_w(mu) v_j             (stencil; also stores v_j = w_prev / beta)
-//     h1 = Q^dag w, w -= Q h1      (pass 1 against Q = (S_m, v_1..v_j))
-//     h2 = Q^dag w, w -= Q h2      (pass 2, re-orthogonalisation)
-//     column j of H = h1 + h2, H_{j+1,j} = |w|
-// so X = S_m^dag A V_k and H_k accumulate in one composite matrix
-// H = [[T_m, X], [0, H_k]] (Eq. eq:newH).  At even checkpoints k (step (v))
-// the device computes sgn(H) by Roberts' iteration on the composite matrix,
-// which yields sgn(T_m), sgn(H_k) and the Sylvester block Y of Eq. (eq:f_H)
-// at once, and the coefficient vector c = sgn(H) Q^dag x with
+// Step (iii): pack x, one classical Gram-Schmidt pass against S_m gives
+// c0 = S^dag x and x - S c0; its re-orthogonalisation is folded into Arnoldi
+// step 0.  Step (iv) (Eq. eq:modArnoldi), per Krylov step j on the device,
+// with u the unnormalised candidate of step j (krylov.hip):
+//     z = H_w(mu) u                           (stencil)
+//     a = Q^dag u, b = Q^dag z, |u|^2, u^dag z (one reduction pass over Q)
+//     v_j = (u - Q a) / rho,  u' = (z - g u - Q (b - g a)) / rho
+//     column j of H, and a folded into column j-1 (its re-orthogonalisation)
+// with Q = (S_m, v_1..v_{j-1}) and rho = |u - Q a|: every new vector is
+// orthogonalised twice against all of Q (classical Gram-Schmidt with one
+// re-orthogonalisation), in two sweeps over Q per step.  X = S_m^dag A V_k
+// and H_k accumulate in one composite matrix H = [[T_m, X], [0, H_k]]
+// (Eq. eq:newH).  At even checkpoints k (step (v)) the device evaluates the
+// sign of the composite matrix (Newton-Schulz on rocBLAS ZGEMM, Roberts'
+// iteration of Eq. Roberts as the fallback), which holds sgn(T_m), sgn(H_k)
+// and the Sylvester block Y of Eq. (eq:f_H), then c = sgn(H) Q^dag x with
 // Q^dag x = [c0; beta e_1].  Step (vi) is y = Q c (Eq. eq:formula).
 // Convergence: ||c_k - [c_k'; 0]|| / ||c_k|| <= tol between checkpoints;
 // because Q has orthonormal columns this is exactly the relative change of y.
+// The two-pass schedule (SGN_ORTH_CGS2: gs.hip, four sweeps per step) is kept
+// as an option.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
