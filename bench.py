@@ -19,6 +19,9 @@ synchronisations; value = applies per second.  Also reported:
   * stencil: H_w(mu) on a 32^4 lattice (1 GB of operands, beyond the 256 MB
     Infinity Cache), algorithmic GB/s against the HBM peak, beside a plain
     device copy timed the same way;
+  * batched_mixed_12x12x12x12: 32 sources of a 12^4 field (m = 40) in one
+    mixed-precision batched apply (tol 1e-7) against FP64 single-source
+    applies (tol 1e-10) on the same field, with the mixed error;
   * cpu_baseline: the oracle's plain Arnoldi (numpy/scipy, FP64) on a bounded
     sample, one apply per field at the Krylov dimension the GPU used.
 
@@ -69,6 +72,9 @@ def main():
     ap.add_argument("--no-stencil", action="store_true", help="skip the 32^4 stencil measurement")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only run the 32^4 stencil measurement and print its JSON object")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 12^4 x 32-source mixed batch")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 12^4 x 32-source mixed-precision batch and print its JSON object")
     ap.add_argument("--serial", action="store_true",
                     help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
                          "whose per-kernel averages then compare with the HIP-event ones)")
@@ -94,6 +100,9 @@ def main():
 
     if args.stencil_only:
         print(json.dumps(stencil_leg(sg, synth, torch)))
+        return
+    if args.batched_only:
+        print(json.dumps(batched_leg(sg, synth, torch)))
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -227,6 +236,7 @@ def main():
         sg.sgn_destroy(c)
 
     stencil = None if args.no_stencil else stencil_leg(sg, synth, torch)
+    batched = None if args.no_batched else batched_leg(sg, synth, torch)
     if stencil is not None and stencil_6 is not None:
         stencil["in_apply_6x6x6x6"] = stencil_6
 
@@ -258,6 +268,7 @@ def main():
         "setup": setup,
         "roofline": roofline,
         "stencil": stencil,
+        "batched_mixed_12x12x12x12": batched,
         "small_sign": sign,
         "kernels": kern,
         "profiled_pass_seconds": round(elapsed_prof, 4),
@@ -331,6 +342,60 @@ def stencil_leg(sg, synth, torch):
            "bytes_per_launch": s["bytes"] / s["launches"], "plain_copy_GBps": copy,
            "frac_of_plain_copy": round(gb / copy, 4)}
     log(f"stencil: {out}")
+    return out
+
+
+BATCH_DIMS = (12, 12, 12, 12)
+BATCH_M = 40
+BATCH_NRHS = 32
+BATCH_KMAX = 400
+BATCH_TOL = 1e-7
+
+
+def batched_leg(sg, synth, torch):
+    """32 sources of one 12^4 field (mu = 0.3, m = 40) in one mixed-precision
+    batched apply, against FP64 single-source applies on the same field; the
+    mixed results of two sources are compared with their FP64 results."""
+    dims = BATCH_DIMS
+    N = 12 * int(np.prod(dims))
+    links = synth.random_links(dims, synth.GAUGE_SEED)
+    ctx = sg.sgn_create(links, dims, 0.3, M_W)
+    try:
+        t0 = time.perf_counter()
+        sg.sgn_deflate(ctx, BATCH_M)
+        torch.cuda.synchronize()
+        t_defl = time.perf_counter() - t0
+        X = torch.from_numpy(np.stack([synth.gaussian_source(dims, 1000 + r) for r in range(BATCH_NRHS)])).cuda()
+        # FP64, one source at a time (tol 1e-10)
+        y64 = torch.empty((2, N), dtype=torch.complex128, device="cuda")
+        sg.sgn_apply(ctx, X[0], y64[0], TOL, BATCH_KMAX)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ks64 = []
+        for r in range(2):
+            sg.sgn_apply(ctx, X[r], y64[r], TOL, BATCH_KMAX)
+            ks64.append(sg.sgn_last_info(ctx)["k_used"])
+        torch.cuda.synchronize()
+        fp64_rate = 2 / (time.perf_counter() - t0)
+        # mixed precision, all sources in one batched call (one untimed call first)
+        sg.sgn_set_precision(ctx, sg.SGN_PREC_MIXED)
+        Y = torch.empty_like(X)
+        sg.sgn_apply_batched(ctx, X, Y, BATCH_TOL, BATCH_KMAX)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos = sg.sgn_apply_batched(ctx, X, Y, BATCH_TOL, BATCH_KMAX)
+        torch.cuda.synchronize()
+        mixed_rate = BATCH_NRHS / (time.perf_counter() - t0)
+        err = [float(torch.linalg.vector_norm(Y[r] - y64[r]) / torch.linalg.vector_norm(y64[r])) for r in range(2)]
+    finally:
+        sg.sgn_destroy(ctx)
+    out = {"workload": f"12^4 (N={N}), mu=0.3, m={BATCH_M} (sgn_deflate), {BATCH_NRHS} Gaussian sources, "
+                       f"kmax={BATCH_KMAX}",
+           "mixed_batched_applies_per_s": round(mixed_rate, 3), "mixed_tol": BATCH_TOL, "status": st,
+           "mixed_k": [i["k_used"] for i in infos], "fp64_single_applies_per_s": round(fp64_rate, 3),
+           "fp64_tol": TOL, "fp64_k": ks64, "speedup": round(mixed_rate / fp64_rate, 3),
+           "mixed_rel_err_vs_fp64": err, "deflation_seconds": round(t_defl, 2)}
+    log(f"batched: {out}")
     return out
 
 

@@ -77,7 +77,9 @@ typedef struct sgn_info {
   int newton_iters;   /* Roberts iterations summed over all checkpoints */
   int n_matvec;       /* applications of H_w(mu) */
   int n_checkpoints;  /* evaluations of the small-matrix sign */
-  int breakdown;      /* 1 if the Krylov space became invariant (exact result) */
+  int breakdown;      /* 1 if the Krylov space became invariant (exact result): the
+                       * orthogonalised candidate fell below 1e-12 (FP64) or 1e-6
+                       * (mixed: FP32 basis) of its size before orthogonalisation */
   double err_est;     /* ||c_k - c_k'|| / ||c_k|| at the last checkpoint */
   double beta;        /* |x_perp| = |(1 - S S^dag) x| */
   double ms_arnoldi;  /* wall time of the Arnoldi steps (device-synchronous) */

@@ -165,6 +165,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   ka.c0 = c->c0;
   ka.beta = &c->scal[0];
   ka.flag = c->flag;
+  ka.brk_tol = mixed ? 1e-6 : 1e-12;
   double2* ucur = c->wA;   // FP64 candidate
   double2* unext = c->wC;
   float2* u32cur = c->u32a;

@@ -136,6 +136,7 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
   base.c0stride = (int)mm;
   base.beta = b.beta;
   base.flag = b.flag;
+  base.brk_tol = mixed ? 1e-6 : 1e-12;
   auto half_u = [&](int p) { return b.u + (size_t)(p & 1) * ns * ldq; };
   auto half_lo = [&](int p) { return static_cast<float2*>(b.ulo) + (size_t)(p & 1) * ns * ldq; };
   auto fill = [&](KrylovArgs& ka, const std::vector<int>& slots, int j) {

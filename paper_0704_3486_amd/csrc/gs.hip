@@ -205,7 +205,9 @@ gs_update_kernel(const double2* __restrict__ Q, size_t ldq, int N, int ncol, con
   if (tid == 0) {
     const double hnorm = sqrt(hn2[0]);
     const bool finite = isfinite(beta) && isfinite(hnorm);
-    const bool brk = !(beta > 1e-14 * fmax(hnorm, 1e-300)) || beta == 0.0;
+    // invariant Krylov space: the new vector is at the rounding level of the
+    // coefficients removed from it
+    const bool brk = !(beta > 1e-12 * fmax(hnorm, 1e-300)) || beta == 0.0;
     if (fin.hout) fin.hout[ncol] = make_double2(finite ? beta : 0.0, 0.0);
     if (fin.beta) *fin.beta = beta;
     if (fin.inv_beta) *fin.inv_beta = (finite && !brk) ? 1.0 / beta : 0.0;

@@ -50,6 +50,10 @@ struct KrylovArgs {
   int c0stride = 0;
   double* beta = nullptr;  // |x_perp| per slot (written at j = 0)
   int* flag = nullptr;     // breakdown record per slot: k_invariant + 1, or -1 for non-finite values
+  // the Krylov space counts as invariant when the new candidate's norm after
+  // orthogonalisation is below brk_tol times its reference size: about the
+  // rounding level of the stored basis (FP64: 1e-12; FP32 columns: 1e-6)
+  double brk_tol = 1e-12;
   // filled by krylov_bind from the workspace
   double2 *Pa = nullptr, *Pb = nullptr;
   double* Pcd = nullptr;

@@ -238,7 +238,7 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
   const double rho2 = c - aa;
   const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
   st.finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(zz);
-  st.brk = !(rho > 1e-14 * sc[kScRef + (step_of(A) & 1)]) || !st.finite;
+  st.brk = !(rho > A.brk_tol * sc[kScRef + (step_of(A) & 1)]) || !st.finite;
   st.inv = st.brk ? 0.0 : 1.0 / rho;
   st.rho = st.brk ? 0.0 : rho;
   st.gam = cscale(csub(d, ab), st.inv);
