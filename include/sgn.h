@@ -170,6 +170,44 @@ int sgn_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double
 /* Batched counterpart of sgn_apply_fixed: exactly k steps per source. */
 int sgn_apply_batched_fixed(sgn_ctx* ctx, int nrhs, const double* X, double* Y, int k, sgn_info* info);
 
+/* ---- serving: continuous batching on one resident field ---------------- */
+
+/* A session keeps up to max_slots (1..64) requests of one context in flight,
+ * each with its own Krylov workspace of kmax vectors (device bytes:
+ * sgn_footprint_bytes(ctx, kmax, max_slots)).  sgn_session_submit admits a
+ * request into a free slot (source projection, step (iii)); each
+ * sgn_session_step runs one Arnoldi step (step (iv)) for every occupied slot,
+ * all in one stencil, dot and update launch, each request at its own Krylov
+ * dimension; a request reaching one of its checkpoints evaluates the small
+ * sign (step (v)) and, once its change is <= tol (or its space is invariant,
+ * or it reached its kmax), writes y (step (vi)) and frees its slot.  The
+ * checkpoint schedule depends on the request alone, so y is bitwise the same
+ * whatever else is in flight (and equal to sgn_apply on a fresh context).
+ * x, y: device complex128, N entries, caller-owned; x is read during submit
+ * only, y must stay valid until poll reports the request done.  The context
+ * keeps its Schur pair and precision while sessions are open (sgn_deflate,
+ * sgn_deflate_import, sgn_set_precision return SGN_ESTATE); a session uses
+ * the context's stream and is not thread-safe; destroy sessions before their
+ * context. */
+typedef struct sgn_session sgn_session;
+/* NULL on failure (sgn_last_error(ctx) says why). */
+sgn_session* sgn_session_create(sgn_ctx* ctx, int max_slots, int kmax);
+/* Admit a request; *req receives its handle.  SGN_ENOMEM if every slot is
+ * busy (the request is not admitted), SGN_EINVAL for NaN/Inf in x, tol <= 0
+ * or kmax outside [2, session kmax]. */
+int sgn_session_submit(sgn_session* s, const double* x, double* y, double tol, int kmax, int* req);
+/* Advance every occupied slot by up to nsteps Arnoldi steps (stops early when
+ * no slot is occupied); returns the number of requests finished (>= 0). */
+int sgn_session_step(sgn_session* s, int nsteps);
+/* 1: request done, y written, info filled (nullable; the handle is then
+ * forgotten; info.converged = 0 if it stopped at its kmax); 0: running;
+ * < 0: the request failed (SGN_EINVAL: non-finite values) or the handle is
+ * unknown. */
+int sgn_session_poll(sgn_session* s, int req, sgn_info* info);
+/* Occupied slots. */
+int sgn_session_active(const sgn_session* s);
+void sgn_session_destroy(sgn_session* s);
+
 /* Arithmetic of the Krylov loop.  SGN_PREC_FP64 (default): everything FP64.
  * SGN_PREC_MIXED: the links, the stencil and the stored Krylov vectors v_j are
  * FP32; the Schur vectors S_m, the candidate vector being orthogonalised,

@@ -79,6 +79,12 @@ def _load():
         "sgn_apply": (i, [vp, vp, vp, d, i]),
         "sgn_apply_fixed": (i, [vp, vp, vp, i]),
         "sgn_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
+        "sgn_session_create": (vp, [vp, i, i]),
+        "sgn_session_submit": (i, [vp, vp, vp, d, i, C.POINTER(C.c_int)]),
+        "sgn_session_step": (i, [vp, i]),
+        "sgn_session_poll": (i, [vp, i, C.POINTER(sgn_info)]),
+        "sgn_session_active": (i, [vp]),
+        "sgn_session_destroy": (None, [vp]),
         "sgn_apply_batched_fixed": (i, [vp, i, vp, vp, i, C.POINTER(sgn_info)]),
         "sgn_last_info": (i, [vp, C.POINTER(sgn_info)]),
         "sgn_footprint_bytes": (C.c_size_t, [vp, i, i]),
@@ -257,6 +263,57 @@ def sgn_apply_batched_fixed(ctx, X, Y, k):
     _check(ctx, _lib.sgn_apply_batched_fixed(ctx, int(nrhs), _dptr(X, nrhs * N, "X"), _dptr(Y, nrhs * N, "Y"),
                                              int(k), infos))
     return [infos[r].as_dict() for r in range(nrhs)]
+
+
+class Session:
+    """Serving session on one context (continuous batching; see sgn_session_*
+    in include/sgn.h).  Keeps the caller's tensors alive until polled."""
+
+    def __init__(self, ctx, max_slots, kmax):
+        self.ctx = ctx
+        self.h = _lib.sgn_session_create(ctx, int(max_slots), int(kmax))
+        if not self.h:
+            raise SgnError(SGN_ESTATE, "sgn_session_create failed: " + (_lib.sgn_last_error(ctx) or b"").decode())
+        self._live = {}
+
+    def submit(self, x, y, tol, kmax):
+        """Admit a request; returns its handle, or None when no slot is free."""
+        _, N = sgn_get_dims(self.ctx)
+        req = C.c_int(-1)
+        st = _lib.sgn_session_submit(self.h, _dptr(x, N, "x"), _dptr(y, N, "y"), float(tol), int(kmax),
+                                     C.byref(req))
+        if st == SGN_ENOMEM:
+            return None
+        _check(self.ctx, st)
+        self._live[req.value] = (x, y)
+        return req.value
+
+    def step(self, nsteps=1):
+        """Advance every occupied slot by up to nsteps steps; returns the
+        number of requests finished."""
+        st = _lib.sgn_session_step(self.h, int(nsteps))
+        if st < 0:
+            _check(self.ctx, st)
+        return st
+
+    def poll(self, req):
+        """None while running, else the request's info dict."""
+        info = sgn_info()
+        st = _lib.sgn_session_poll(self.h, int(req), C.byref(info))
+        if st == 0:
+            return None
+        self._live.pop(req, None)
+        _check(self.ctx, st if st < 0 else SGN_OK)
+        return info.as_dict()
+
+    def active(self):
+        return _lib.sgn_session_active(self.h)
+
+    def destroy(self):
+        if self.h:
+            _lib.sgn_session_destroy(self.h)
+            self.h = None
+            self._live.clear()
 
 
 def sgn_set_precision(ctx, prec):

@@ -400,6 +400,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
 }  // namespace
 
 void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std::vector<double2>& Tin) {
+  SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session holds this field's Schur pair");
   hipStream_t s = c->stream;
   SGN_HIP(hipStreamSynchronize(s));
   std::vector<double2> Th(Tin);
@@ -612,6 +613,7 @@ int sgn_debug_hessenberg(const sgn_ctx* cc, int n, double* H, double* c0, double
 int sgn_set_precision(sgn_ctx* c, int prec) {
   return guarded(c, [&] {
     SGN_REQUIRE(prec == SGN_PREC_FP64 || prec == SGN_PREC_MIXED, SGN_EINVAL, "unknown precision");
+    SGN_REQUIRE(c->sessions == 0 || prec == c->prec, SGN_ESTATE, "a serving session holds this field's precision");
     SGN_HIP(hipStreamSynchronize(c->stream));
     if (prec == c->prec) return SGN_OK;
     c->release_workspace();

@@ -125,6 +125,7 @@ struct sgn_ctx {
   double tol_hint = 0.0;
   double rate_hint = 0.0;
   int orth = 1;  // 0: two classical Gram-Schmidt passes per step; 1: one reduction, delayed re-orthogonalisation
+  int sessions = 0;  // open serving sessions (they hold the Schur pair and the precision fixed)
 
   ~sgn_ctx() { release(); }
 

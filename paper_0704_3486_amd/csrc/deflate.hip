@@ -316,6 +316,7 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
 extern "C" int sgn_deflate(sgn_ctx* c, int m) {
   return guarded(c, [&] {
     SGN_REQUIRE(m >= 0 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 0 <= m <= N/4");
+    SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session holds this field's Schur pair");
     if (m == 0) {
       install_schur_pair(c, 0, nullptr, {});
       return SGN_OK;

@@ -34,7 +34,8 @@ struct KrylovArgs {
   // Krylov columns: column c >= m of slot r at V + r*vstride + (c-m)*ldq (element type VT)
   void* V = nullptr;
   size_t vstride = 0;
-  // FP64 candidate u (read) and next candidate (written), per slot at ustride
+  // FP64 candidate u (read) and next candidate (written; may equal u), per
+  // slot at ustride
   double2* u = nullptr;
   double2* unext = nullptr;
   size_t ustride = 0;

@@ -366,7 +366,9 @@ __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
       tb = cadd(tb, ps[1][w][lane]);
     }
     const double2 te = csub(tb, cmul(st.gr, ta));
-    const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
+    // u may be updated in place (unext == u): each lane reads its u[i]
+    // before writing u'[i], and no other thread of the step touches row i of u
+    const double2* u = A.u + (size_t)r * A.ustride;
     const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
     VT* vout = static_cast<VT*>(A.V) + (size_t)r * A.vstride + (size_t)(J - A.m) * A.ldq;
     const double2 ui = u[i];
