@@ -73,6 +73,14 @@ def main():
     ap.add_argument("--stencil-only", action="store_true",
                     help="only run the 32^4 stencil measurement and print its JSON object")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12^4 x 32-source mixed batch")
+    ap.add_argument("--serving", action="store_true",
+                    help="only run the serving stream (Poisson arrivals over four resident fields) and print its "
+                         "JSON object")
+    ap.add_argument("--serving-rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--serving-requests", type=int, default=2000, help="arrivals at the offered rate")
+    ap.add_argument("--serving-sustained", type=int, default=400,
+                    help="arrivals of the second stream, at 70%% of the served rate")
+    ap.add_argument("--serving-mixed", action="store_true", help="serve in mixed precision")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 12^4 x 32-source mixed-precision batch and print its JSON object")
     ap.add_argument("--serial", action="store_true",
@@ -103,6 +111,10 @@ def main():
         return
     if args.batched_only:
         print(json.dumps(batched_leg(sg, synth, torch)))
+        return
+    if args.serving:
+        print(json.dumps(serving_leg(sg, synth, torch, args.serving_rate, args.serving_requests, args.serving_sustained,
+                                     sg.SGN_PREC_MIXED if args.serving_mixed else sg.SGN_PREC_FP64)))
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -396,6 +408,108 @@ def batched_leg(sg, synth, torch):
            "fp64_tol": TOL, "fp64_k": ks64, "speedup": round(mixed_rate / fp64_rate, 3),
            "mixed_rel_err_vs_fp64": err, "deflation_seconds": round(t_defl, 2)}
     log(f"batched: {out}")
+    return out
+
+
+# serving stream: lattice, deflation m, session kmax, arrival weight, share of
+# the HBM budget for its Krylov workspaces.  The 12^4 and 16^4 fields draw
+# mu = 0.5, where a 40-60 vector basis from H_w^2 takes minutes to tens of
+# minutes to converge; they are served without deflation (kmax 600).
+SERVE_FIELDS = [((6, 6, 6, 6), 20, 500, 0.4, 0.05), ((8, 8, 8, 8), 30, 500, 0.3, 0.10),
+                ((12, 12, 12, 12), 0, 600, 0.2, 0.35), ((16, 16, 16, 16), 0, 600, 0.1, 0.50)]
+SERVE_TOL = 1e-8
+SERVE_BUDGET = 150e9
+
+
+def serving_leg(sg, synth, torch, rate, nreq, nreq_sustained, prec):
+    """Poisson arrivals of sgn(H)x requests over four resident fields (6^4,
+    8^4, 12^4, 16^4 with weights 0.4/0.3/0.2/0.1; field seeds G+1..G+4, mu per
+    field drawn once from {0.1, 0.3, 0.5} with default_rng(G+100)), tol 1e-8,
+    served by one continuous-batching session per field.
+
+    Two streams over the same resident fields: `nreq` arrivals at the offered
+    `rate` (inter-arrival times from default_rng(7)), which exceeds what one
+    device serves, so its served rate is the device's capacity for this mix;
+    then `nreq_sustained` arrivals at 70 % of that served rate
+    (default_rng(8)), whose latencies are those of a stable queue.  Latency =
+    host time from a request's arrival to its completion."""
+    from paper_0704_3486_amd.serving import Server
+
+    G = synth.GAUGE_SEED
+    mus = np.random.default_rng(G + 100).choice([0.1, 0.3, 0.5], size=len(SERVE_FIELDS))
+    srv = Server(SERVE_BUDGET, nsteps=4)
+    setup = {}
+    names = []
+    for i, (dims, m, kmax, _, share) in enumerate(SERVE_FIELDS):
+        name = "x".join(str(d) for d in dims)
+        links = synth.random_links(dims, G + 1 + i)
+        setup[name] = {"mu": float(mus[i]),
+                       **srv.add_field(name, links, dims, float(mus[i]), M_W, m, kmax, share, prec)}
+        log(f"serving setup {name}: {setup[name]}")
+        names.append(name)
+    try:
+        offered = _serve_stream(srv, names, synth, torch, rate, nreq, 7, 1000)
+        rate2 = round(0.7 * offered["served_applies_per_s"], 3)
+        sustained = _serve_stream(srv, names, synth, torch, rate2, nreq_sustained, 8, 1000 + nreq)
+    finally:
+        srv.close()
+    out = {"workload": "Poisson arrivals over 6^4/8^4/12^4/16^4 (0.4/0.3/0.2/0.1), tol "
+                       + f"{SERVE_TOL}, " + ("mixed precision" if prec == sg.SGN_PREC_MIXED else "FP64"),
+           "served_applies_per_s": offered["served_applies_per_s"], "offered": offered,
+           "at_70pct_of_served": sustained, "setup": setup}
+    log(f"serving: {out}")
+    return out
+
+
+def _serve_stream(srv, names, synth, torch, rate, nreq, arrival_seed, source_seed):
+    """One bounded Poisson stream through the running server; returns its
+    served rate and latency percentiles, overall and per field."""
+    from paper_0704_3486_amd.serving import Request
+
+    rng = np.random.default_rng(arrival_seed)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    which = rng.choice(len(SERVE_FIELDS), size=nreq, p=[f[3] for f in SERVE_FIELDS])
+    reqs = []
+    for q in range(nreq):
+        dims, _, kmax, _, _ = SERVE_FIELDS[which[q]]
+        x = torch.from_numpy(synth.gaussian_source(dims, source_seed + q)).cuda()
+        reqs.append(Request(names[which[q]], x, torch.empty_like(x), SERVE_TOL, kmax))
+    torch.cuda.synchronize()
+    srv.start()
+    t0 = time.perf_counter()
+    log(f"serving: {nreq} arrivals at {rate}/s")
+    for q, req in enumerate(reqs):
+        delay = t0 + arrive[q] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        srv.submit(req)
+    log(f"serving: {nreq} requests submitted in {time.perf_counter() - t0:.2f} s")
+    mark = max(1, nreq // 10)
+    for q, req in enumerate(reqs):
+        req.done.wait()
+        if (q + 1) % mark == 0:
+            log(f"serving: first {q + 1} requests done at {time.perf_counter() - t0:.2f} s")
+    srv.stop()
+    t_end = max(r.t_done for r in reqs)
+    lat = np.array([r.latency for r in reqs])
+    fails = sum(1 for r in reqs if r.error is not None or r.info is None or not r.info["converged"])
+    per = {}
+    for name in names:
+        sel = [r for r in reqs if r.field == name]
+        if not sel:
+            continue
+        lf = np.array([r.latency for r in sel])
+        per[name] = {"requests": len(sel), "p50_ms": round(1e3 * float(np.percentile(lf, 50)), 2),
+                     "p99_ms": round(1e3 * float(np.percentile(lf, 99)), 2),
+                     "mean_k": round(float(np.mean([r.info["k_used"] for r in sel if r.info])), 1)}
+    out = {"offered_per_s": rate, "requests": nreq, "served_applies_per_s": round(nreq / (t_end - t0), 3),
+           "arrival_span_s": round(float(arrive[-1]), 3), "makespan_s": round(t_end - t0, 3),
+           "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+           "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2), "not_converged_or_failed": fails,
+           "per_field": per}
+    log(f"serving stream: {out}")
+    del reqs
+    torch.cuda.empty_cache()
     return out
 
 
