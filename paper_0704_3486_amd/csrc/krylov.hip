@@ -22,9 +22,12 @@
 // Krylov columns v_j and the stencil operand/result (z) are stored as VT
 // (double2, or float2 in mixed precision).
 //
-// Batching: blockIdx.z selects a right-hand side; per-RHS buffers are laid
-// out at fixed strides.  All reductions are combined in a fixed order by the
-// last workgroup to finish, so results are bitwise independent of the batch.
+// Batching: each workgroup serves one right-hand side; per-RHS buffers are
+// laid out at fixed strides.  The dot and update passes number their
+// workgroups with the right-hand side varying fastest, so the workgroups of
+// all right-hand sides that read the same rows of the shared Schur block S run
+// together and S comes from cache after the first of them.  Every reduction
+// has a fixed order, so results are bitwise independent of the batch.
 #include "internal.h"
 #include "krylov.h"
 
@@ -68,8 +71,9 @@ __device__ inline double2 qload(const KrylovArgs& A, int r, int c, int i) {
   return ld2(V, i);
 }
 
-__device__ inline int slot_of(const KrylovArgs& A) { return A.act[blockIdx.z]; }
-__device__ inline int step_of(const KrylovArgs& A) { return A.jv[blockIdx.z]; }
+// launch position z (an index into the batch) -> buffer slot and step
+__device__ inline int slot_of(const KrylovArgs& A, int z) { return A.act[z]; }
+__device__ inline int step_of(const KrylovArgs& A, int z) { return A.jv[z]; }
 
 // ---------------------------------------------------------------------------
 // dot pass: per (row tile, column group) partial sums of Q^dag u and Q^dag z,
@@ -90,12 +94,14 @@ __device__ inline void dot_cols(const QT* __restrict__ q, const double2 uv[kRpl]
   }
 }
 
+// workgroup id = z + nb (rt + nrt cg): batch position fastest, then row tile
 template <typename VT>
 __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
-  const int r = slot_of(A);
-  const int rt = blockIdx.x, cg = blockIdx.y;
+  const int zb = blockIdx.x % A.nb, rest = blockIdx.x / A.nb;
+  const int rt = rest % A.nrt_dot, cg = rest / A.nrt_dot;
+  const int r = slot_of(A, zb);
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int N = A.N, J = A.m + step_of(A);
+  const int N = A.N, J = A.m + step_of(A, zb);
   const int row0 = rt * kDRows;
   const double2* __restrict__ u = A.u + (size_t)r * A.ustride;
   const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
@@ -157,8 +163,8 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
 // workgroup, 8 threads per column (each sums every 8th row tile), then a
 // fixed-order combine; workgroup 0 also sums the scalars c, d, |z|^2
 __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
-  const int r = slot_of(A);
-  const int J = A.m + step_of(A), nrt = A.nrt_dot;
+  const int r = slot_of(A, blockIdx.z);
+  const int J = A.m + step_of(A, blockIdx.z), nrt = A.nrt_dot;
   const double2* Pa = A.Pa + (size_t)r * A.pstride;
   const double2* Pb = A.Pb + (size_t)r * A.pstride;
   const double* Pcd = A.Pcd + (size_t)r * A.cdstride;
@@ -204,8 +210,8 @@ struct StepScalars {
 };
 
 template <int NT>
-__device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* LDS [3][NT] */) {
-  const int J = A.m + step_of(A), tid = threadIdx.x;
+__device__ StepScalars step_scalars(const KrylovArgs& A, int r, int j, double* red /* LDS [3][NT] */) {
+  const int J = A.m + j, tid = threadIdx.x;
   const double2* a = A.a + (size_t)r * A.abstride;
   const double2* b = A.b + (size_t)r * A.abstride;
   const double* sc = A.sc + (size_t)r * kScStride;
@@ -238,7 +244,7 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
   const double rho2 = c - aa;
   const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
   st.finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(zz);
-  st.brk = !(rho > A.brk_tol * sc[kScRef + (step_of(A) & 1)]) || !st.finite;
+  st.brk = !(rho > A.brk_tol * sc[kScRef + (j & 1)]) || !st.finite;
   st.inv = st.brk ? 0.0 : 1.0 / rho;
   st.rho = st.brk ? 0.0 : rho;
   st.gam = cscale(csub(d, ab), st.inv);
@@ -251,8 +257,8 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, double* red /* L
 // Hessenberg column J and the re-orthogonalisation of column J-1, one row per
 // wavefront (the lanes split the sum over columns); at j = 0 the correction
 // goes to c0 instead.
-__device__ void hcol_row_wave(const KrylovArgs& A, int r, int row, int lane, const StepScalars& st) {
-  const int j = step_of(A), J = A.m + j;
+__device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int lane, const StepScalars& st) {
+  const int J = A.m + j;
   const double2* a = A.a + (size_t)r * A.abstride;
   const double2* b = A.b + (size_t)r * A.abstride;
   double2* H = A.H + (size_t)r * A.hstride;
@@ -310,14 +316,16 @@ __device__ inline int first_col(int m, int w) { return m + ((w - m % kUWaves) + 
 
 // update pass: each workgroup owns 64 rows and all J columns; its kUWaves
 // wavefronts take interleaved columns and are combined in LDS in fixed order.
+// Workgroup id = z + nb blk (batch position fastest, then the 64-row block).
 template <typename VT>
 __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
-  const int r = slot_of(A);
+  const int zb = blockIdx.x % A.nb, blk = blockIdx.x / A.nb, nblk = gridDim.x / A.nb;
+  const int r = slot_of(A, zb);
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-  const int N = A.N, j = step_of(A), J = A.m + j;
+  const int N = A.N, j = step_of(A, zb), J = A.m + j;
   const double2* av = A.a + (size_t)r * A.abstride;
   const double2* bv = A.b + (size_t)r * A.abstride;
-  const int i = blockIdx.x * 64 + lane;
+  const int i = blk * 64 + lane;
   const bool ok = i < N;
   // sweep: sa = Q a, sb = Q b (the step scalars enter only afterwards:
   // Q (b - gr a) = sb - gr sa)
@@ -330,12 +338,12 @@ __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
   ps[0][wave][lane] = sa;
   ps[1][wave][lane] = sb;
   __shared__ double red[3 * kUThreads];
-  const StepScalars st = step_scalars<kUThreads>(A, r, red);  // contains __syncthreads
-  // Hessenberg column J (one row per wavefront over the whole grid)
+  const StepScalars st = step_scalars<kUThreads>(A, r, j, red);  // contains __syncthreads
+  // Hessenberg column J (one row per wavefront over this slot's workgroups)
   {
-    const int nwaves = gridDim.x * kUWaves;
-    for (int row = blockIdx.x * kUWaves + wave; row <= J; row += nwaves) hcol_row_wave(A, r, row, lane, st);
-    if (blockIdx.x == 0 && tid == 0) {
+    const int nwaves = nblk * kUWaves;
+    for (int row = blk * kUWaves + wave; row <= J; row += nwaves) hcol_row_wave(A, r, j, row, lane, st);
+    if (blk == 0 && tid == 0) {
       double* sc = A.sc + (size_t)r * kScStride;
       sc[kScRho] = st.rho;
       sc[kScInv] = st.inv;
@@ -385,7 +393,7 @@ template <typename VT>
 __global__ void __launch_bounds__(kUThreads) kcombine_kernel(KrylovArgs A, const double2* __restrict__ coef,
                                                              int cstride, double2* __restrict__ y, size_t ystride,
                                                              int ncol) {
-  const int r = slot_of(A);
+  const int r = slot_of(A, blockIdx.z);
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int i = blockIdx.x * 64 + lane;
   const bool ok = i < A.N;
@@ -408,7 +416,7 @@ __global__ void __launch_bounds__(kUThreads) kcombine_kernel(KrylovArgs A, const
 
 // dst = H[:n,:n] with column n-1 += a (slot r), dst dense n x n per slot
 __global__ void kpatch_kernel(KrylovArgs A, int n, double2* __restrict__ dst, size_t dstride, int with_a) {
-  const int r = slot_of(A);
+  const int r = slot_of(A, blockIdx.z);
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)n * n) return;
   const int c = (int)(e / n), row = (int)(e - (size_t)c * n);
@@ -496,8 +504,10 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStre
   col_sums(A, sm, sk);
   const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
   // algorithmic bytes: Q, u, z read once; a, b written
+  const size_t nwg = (size_t)w.nrt_dot * ngroups * A.nb;
+  SGN_REQUIRE(nwg * 256 < (size_t(1) << 32), SGN_EINVAL, "krylov: dot grid too large");
   prof_launch(prof, K_KDOT, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * (sm + sk),
-              16.0 * (double)A.N * (sm + sk), kdot_kernel<VT>, dim3(w.nrt_dot, ngroups, A.nb), dim3(256), 0, s, A,
+              16.0 * (double)A.N * (sm + sk), kdot_kernel<VT>, dim3((unsigned)nwg), dim3(256), 0, s, A,
               with_z ? 1 : 0);
   // partial sums of every row tile read, a, b written
   prof_launch(prof, K_KRED, 32.0 * (sm + sk) * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot,
@@ -511,7 +521,8 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   krylov_bind(w, A);
   check_args(w, A);
   SGN_REQUIRE(A.m + A.jmax() + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
-  const int nblk = (A.N + 63) / 64;
+  const size_t nwg = (size_t)((A.N + 63) / 64) * A.nb;
+  SGN_REQUIRE(nwg * kUThreads < (size_t(1) << 32), SGN_EINVAL, "krylov: update grid too large");
   const double vb = (double)sizeof(VT);
   double sm, sk;
   col_sums(A, sm, sk);
@@ -519,7 +530,7 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   // read Q, u, z; write v_J, u' (+ its low-precision copy)
   const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
   prof_launch(prof, K_KUPDATE, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk),
-              kupdate_kernel<VT>, dim3(nblk, 1, A.nb), dim3(kUThreads), 0, s, A);
+              kupdate_kernel<VT>, dim3((unsigned)nwg), dim3(kUThreads), 0, s, A);
 }
 
 template <typename VT>
