@@ -8,22 +8,23 @@
 // For a single right-hand side these are matrix-vector products (0.5 flop
 // per byte), so they are written as streaming kernels, not MFMA tiles.
 //
-// Reductions are deterministic: partial sums are combined in a fixed order by
-// the last workgroup to finish (atomic ticket + device-scope fences), so a
-// result is bitwise reproducible for a given problem shape.
+// Reductions are deterministic: partial sums are written per row tile and
+// combined in a fixed order by a separate small kernel, so a result is
+// bitwise reproducible for a given problem shape.  No kernel synchronises
+// with another workgroup.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace {
 
-constexpr int kDotRpl = 16;                 // rows per lane
-constexpr int kDotCpw = 4;                  // columns per wavefront
-constexpr int kDotWaves = 4;                // wavefronts per workgroup
-constexpr int kDotRows = 64 * kDotRpl;      // rows per tile (1024)
-constexpr int kDotCols = kDotCpw * kDotWaves;  // columns per workgroup (16)
-
-constexpr int kUpdRpt = 4;                  // rows per thread
-constexpr int kUpdRows = 256 * kUpdRpt;     // rows per tile (1024)
-constexpr int kUpdCols = 32;                // columns per workgroup
+constexpr int kDotRpl = 8;                     // dot: rows per lane
+constexpr int kDotRows = 64 * kDotRpl;         // dot: rows per tile (512)
+constexpr int kDotCpw = 4;                     // dot: columns per wavefront
+constexpr int kDotCols = 4 * kDotCpw;          // dot: columns per workgroup (4 wavefronts)
+constexpr int kUpdWaves = 8;                   // update: wavefronts per 64-row workgroup
+constexpr int kUpdThreads = 64 * kUpdWaves;
+constexpr int kUpdBatch = 8;                   // update: column loads issued together per lane
 
 __device__ inline double2 wave_sum(double2 v) {
 #pragma unroll
@@ -40,69 +41,55 @@ __device__ inline double wave_sum1(double v) {
   return v;
 }
 
-// Atomic ticket: returns true in every thread of the workgroup that finished last.
-__device__ inline bool last_block(unsigned* counter, unsigned total) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == total - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = is_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-__device__ inline void reset_counter(unsigned* counter) {
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// partial sums P[rt][c] = sum over the rows of tile rt of conj(Q[c][i]) w[i];
+// workgroup id = rt + nrt cg, column group cg = 16 columns (4 per wavefront).
+// Rows past N carry zero weight and load row N-1 (unconditional loads).
 __global__ void __launch_bounds__(256)
-gs_dot_kernel(const double2* __restrict__ Q, size_t ldq, int N, int ncol, const double2* __restrict__ w,
-              double2* __restrict__ P, int ldp, double2* __restrict__ h, unsigned* __restrict__ counters,
-              int nrt) {
-  const int rt = blockIdx.x, cg = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+gs_dot_part_kernel(const double2* __restrict__ Q, size_t ldq, int N, int ncol, const double2* __restrict__ w,
+                   double2* __restrict__ P, int ldp, int nrt) {
+  const int rt = blockIdx.x % nrt, cg = blockIdx.x / nrt;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row0 = rt * kDotRows;
   double2 wv[kDotRpl];
 #pragma unroll
-  for (int r = 0; r < kDotRpl; ++r) {
-    const int i = row0 + r * 64 + lane;
-    wv[r] = (i < N) ? w[i] : make_double2(0.0, 0.0);
+  for (int t = 0; t < kDotRpl; ++t) {
+    const int i = row0 + t * 64 + lane;
+    wv[t] = (i < N) ? w[i] : make_double2(0.0, 0.0);
   }
 #pragma unroll
   for (int cc = 0; cc < kDotCpw; ++cc) {
-    const int c = cg * kDotCols + wave * kDotCpw + cc;
+    const int c = (cg * 4 + wave) * kDotCpw + cc;
     if (c < ncol) {
       const double2* __restrict__ q = Q + (size_t)c * ldq;
+      double2 qv[kDotRpl];
+#pragma unroll
+      for (int t = 0; t < kDotRpl; ++t) qv[t] = q[min(row0 + t * 64 + lane, N - 1)];
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int r = 0; r < kDotRpl; ++r) {
-        const int i = row0 + r * 64 + lane;
-        if (i < N) acc = cfmac(q[i], wv[r], acc);
-      }
+      for (int t = 0; t < kDotRpl; ++t) acc = cfmac(qv[t], wv[t], acc);
       acc = wave_sum(acc);
       if (lane == 0) P[(size_t)rt * ldp + c] = acc;
     }
   }
-  if (!last_block(&counters[cg], (unsigned)nrt)) return;
-  // fixed-order reduction over row tiles: 16 columns x 16 interleaved subsets
-  __shared__ double2 red[16][kDotCols + 1];
-  const int cc = threadIdx.x & 15, sub = threadIdx.x >> 4;
-  const int c = cg * kDotCols + cc;
+}
+
+// h[c] = sum over row tiles of P[rt][c] in a fixed order: 32 columns per
+// workgroup, 8 threads per column (each sums every 8th tile), then in order
+__global__ void __launch_bounds__(256)
+gs_dot_red_kernel(const double2* __restrict__ P, int ldp, int nrt, int ncol, double2* __restrict__ h) {
+  const int cl = threadIdx.x & 31, part = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + cl;
   double2 acc = make_double2(0.0, 0.0);
   if (c < ncol)
-    for (int r = sub; r < nrt; r += 16) acc = cadd(acc, P[(size_t)r * ldp + c]);
-  red[sub][cc] = acc;
+    for (int t = part; t < nrt; t += 8) acc = cadd(acc, P[(size_t)t * ldp + c]);
+  __shared__ double2 red[8][33];
+  red[part][cl] = acc;
   __syncthreads();
-  if (threadIdx.x < 16 && c < ncol) {
-    double2 s = red[0][cc];
-    for (int k = 1; k < 16; ++k) s = cadd(s, red[k][cc]);
-    h[c] = s;
+  if (part == 0 && c < ncol) {
+    double2 sum = red[0][cl];
+    for (int q = 1; q < 8; ++q) sum = cadd(sum, red[q][cl]);
+    h[c] = sum;
   }
-  reset_counter(&counters[cg]);
 }
 
 struct FinDev {
@@ -115,69 +102,59 @@ struct FinDev {
   int active;
 };
 
-__global__ void __launch_bounds__(256)
+// w += sgn Q h: each workgroup owns 64 rows and all columns; its wavefronts
+// take the columns c = wave, wave + 8, ... (batches of kUpdBatch loads in
+// flight; past ncol, column ncol-1 is reloaded with weight zero) and are
+// combined in LDS in a fixed order.  With want_norm, normpart[blk] = |w|^2
+// over the block's rows.
+__global__ void __launch_bounds__(kUpdThreads)
 gs_update_kernel(const double2* __restrict__ Q, size_t ldq, int N, int ncol, const double2* __restrict__ h,
-                 double sgn, double2* __restrict__ w, double2* __restrict__ Upart, int ngroups,
-                 unsigned* __restrict__ cnt_rows, unsigned* __restrict__ cnt_norm, int nrt,
-                 double* __restrict__ normpart, FinDev fin) {
-  const int rt = blockIdx.x, g = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int row0 = rt * kUpdRows;
-  __shared__ double2 hs[kUpdCols];
-  const int c0 = g * kUpdCols;
-  const int nc = min(kUpdCols, ncol - c0);
-  if (tid < nc) hs[tid] = h[c0 + tid];
+                 double sgn, double2* __restrict__ w, double* __restrict__ normpart, int want_norm) {
+  const int blk = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = blk * 64 + lane;
+  const bool ok = i < N;
+  const int il = ok ? i : N - 1;
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 acc = zero;
+  for (int c = wave; c < ncol; c += kUpdBatch * kUpdWaves) {
+    double2 qv[kUpdBatch], hv[kUpdBatch];
+#pragma unroll
+    for (int t = 0; t < kUpdBatch; ++t) {
+      const int cc = c + t * kUpdWaves, cl = min(cc, ncol - 1);
+      qv[t] = Q[(size_t)cl * ldq + il];
+      hv[t] = (cc < ncol) ? h[cl] : zero;
+    }
+#pragma unroll
+    for (int t = 0; t < kUpdBatch; ++t) acc = cfma(qv[t], hv[t], acc);
+  }
+  __shared__ double2 ps[kUpdWaves][64];
+  ps[wave][lane] = acc;
   __syncthreads();
-  double2 u[kUpdRpt];
+  if (wave != 0) return;
+  double2 sum = ps[0][lane];
 #pragma unroll
-  for (int r = 0; r < kUpdRpt; ++r) u[r] = make_double2(0.0, 0.0);
-  for (int c = 0; c < nc; ++c) {
-    const double2* __restrict__ q = Q + (size_t)(c0 + c) * ldq;
-    const double2 hc = hs[c];
-#pragma unroll
-    for (int r = 0; r < kUpdRpt; ++r) {
-      const int i = row0 + r * 256 + tid;
-      if (i < N) u[r] = cfma(q[i], hc, u[r]);
-    }
-  }
-  if (ngroups > 1) {
-#pragma unroll
-    for (int r = 0; r < kUpdRpt; ++r) {
-      const int i = row0 + r * 256 + tid;
-      if (i < N) Upart[(size_t)g * ldq + i] = u[r];
-    }
-    if (!last_block(&cnt_rows[rt], (unsigned)ngroups)) return;
-#pragma unroll
-    for (int r = 0; r < kUpdRpt; ++r) {
-      const int i = row0 + r * 256 + tid;
-      double2 s = make_double2(0.0, 0.0);
-      if (i < N)
-        for (int gg = 0; gg < ngroups; ++gg) s = cadd(s, Upart[(size_t)gg * ldq + i]);
-      u[r] = s;
-    }
-    reset_counter(&cnt_rows[rt]);
-  }
+  for (int q = 1; q < kUpdWaves; ++q) sum = cadd(sum, ps[q][lane]);
   double nrm = 0.0;
-#pragma unroll
-  for (int r = 0; r < kUpdRpt; ++r) {
-    const int i = row0 + r * 256 + tid;
-    if (i < N) {
-      const double2 wi = make_double2(w[i].x + sgn * u[r].x, w[i].y + sgn * u[r].y);
-      w[i] = wi;
-      nrm += cabs2(wi);
-    }
+  if (ok) {
+    const double2 wi = make_double2(w[i].x + sgn * sum.x, w[i].y + sgn * sum.y);
+    w[i] = wi;
+    nrm = cabs2(wi);
   }
-  if (!fin.active) return;
-  // workgroup sum of |w|^2 over this row tile, fixed order
-  __shared__ double wred[4];
-  nrm = wave_sum1(nrm);
-  if ((tid & 63) == 0) wred[tid >> 6] = nrm;
-  __syncthreads();
-  if (tid == 0) normpart[rt] = ((wred[0] + wred[1]) + wred[2]) + wred[3];
-  if (!last_block(cnt_norm, (unsigned)nrt)) return;
+  if (want_norm) {
+    nrm = wave_sum1(nrm);
+    if (lane == 0) normpart[blk] = nrm;
+  }
+}
+
+// beta = |w| from the block partials (fixed order), then the coefficient
+// column hout = h1 + h with beta appended, 1/beta and the breakdown record
+__global__ void __launch_bounds__(256)
+gs_final_kernel(const double* __restrict__ normpart, int nblk, int ncol, const double2* __restrict__ h, FinDev fin) {
+  const int tid = threadIdx.x;
   __shared__ double tred[256];
   double s = 0.0;
-  for (int r = tid; r < nrt; r += 256) s += normpart[r];
+  for (int r = tid; r < nblk; r += 256) s += normpart[r];
   tred[tid] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -185,7 +162,6 @@ gs_update_kernel(const double2* __restrict__ Q, size_t ldq, int N, int ncol, con
     __syncthreads();
   }
   const double beta = sqrt(tred[0]);
-  // coefficient column: hout = h1 + h, then beta (as a complex entry)
   __shared__ double hn2[256];
   double hsum = 0.0;
   if (fin.hout) {
@@ -218,32 +194,23 @@ gs_update_kernel(const double2* __restrict__ Q, size_t ldq, int N, int ncol, con
         *fin.flag = fin.kval + 1;
     }
   }
-  reset_counter(cnt_norm);
 }
 
 }  // namespace
 
 void gs_alloc(GsWork& g, int N, size_t ldq, int ncol_cap) {
   gs_free(g);
+  (void)ldq;
   g.nrt_dot = (N + kDotRows - 1) / kDotRows;
-  g.nrt_upd = (N + kUpdRows - 1) / kUpdRows;
+  g.nblk_upd = (N + 63) / 64;
   g.ncol_cap = ncol_cap;
-  g.ngroups_cap = (ncol_cap + kUpdCols - 1) / kUpdCols;
-  const int ndotgroups = (ncol_cap + kDotCols - 1) / kDotCols;
-  g.ncounters = ndotgroups + g.nrt_upd + 1;
-  SGN_HIP(hipMalloc(&g.P, sizeof(double2) * (size_t)g.nrt_dot * ncol_cap));
-  SGN_HIP(hipMalloc(&g.Upart, sizeof(double2) * ldq * (size_t)(g.ngroups_cap > 1 ? g.ngroups_cap : 1)));
-  SGN_HIP(hipMalloc(&g.normpart, sizeof(double) * (size_t)g.nrt_upd));
-  SGN_HIP(hipMalloc(&g.counters, sizeof(unsigned) * (size_t)g.ncounters));
-  SGN_HIP(hipMemset(g.counters, 0, sizeof(unsigned) * (size_t)g.ncounters));
-  SGN_HIP(hipDeviceSynchronize());
+  SGN_HIP(hipMalloc(&g.P, sizeof(double2) * (size_t)g.nrt_dot * std::max(ncol_cap, 1)));
+  SGN_HIP(hipMalloc(&g.normpart, sizeof(double) * (size_t)g.nblk_upd));
 }
 
 void gs_free(GsWork& g) {
   if (g.P) (void)hipFree(g.P);
-  if (g.Upart) (void)hipFree(g.Upart);
   if (g.normpart) (void)hipFree(g.normpart);
-  if (g.counters) (void)hipFree(g.counters);
   g = GsWork{};
 }
 
@@ -251,10 +218,14 @@ void gs_dot(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, cons
             hipStream_t s, Profiler* prof) {
   if (ncol <= 0) return;
   SGN_REQUIRE(ncol <= g.ncol_cap, SGN_EINVAL, "gs_dot: ncol exceeds workspace");
-  const int ngroups = (ncol + kDotCols - 1) / kDotCols;
+  const size_t nwg = (size_t)g.nrt_dot * ((ncol + kDotCols - 1) / kDotCols);
+  SGN_REQUIRE(nwg * 256 < (size_t(1) << 32), SGN_EINVAL, "gs_dot: grid too large");
   const int idx = prof ? prof->begin(K_CGS_DOT) : -1;
-  hipLaunchKernelGGL(gs_dot_kernel, dim3(g.nrt_dot, ngroups), dim3(256), 0, s, Q, ldq, N, ncol, w, g.P,
-                     g.ncol_cap, h, g.counters, g.nrt_dot);
+  hipLaunchKernelGGL(gs_dot_part_kernel, dim3((unsigned)nwg), dim3(256), 0, s, Q, ldq, N, ncol, w, g.P,
+                     g.ncol_cap, g.nrt_dot);
+  SGN_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gs_dot_red_kernel, dim3((unsigned)((ncol + 31) / 32)), dim3(256), 0, s, g.P, g.ncol_cap,
+                     g.nrt_dot, ncol, h);
   SGN_HIP(hipGetLastError());
   if (prof) prof->end(idx, 16.0 * ((double)N * ncol + N + ncol), 8.0 * (double)N * ncol);
 }
@@ -262,9 +233,13 @@ void gs_dot(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, cons
 static void update_launch(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* h,
                           double sgn, double2* w, const GsFinal* fin, int kval, hipStream_t s, Profiler* prof) {
   SGN_REQUIRE(ncol >= 0 && ncol <= g.ncol_cap, SGN_EINVAL, "gs_update: ncol exceeds workspace");
-  const int ngroups = ncol > 0 ? (ncol + kUpdCols - 1) / kUpdCols : 1;
-  FinDev fd{};
+  SGN_REQUIRE((size_t)g.nblk_upd * kUpdThreads < (size_t(1) << 32), SGN_EINVAL, "gs_update: grid too large");
+  const int idx = prof ? prof->begin(K_CGS_UPDATE) : -1;
+  hipLaunchKernelGGL(gs_update_kernel, dim3(g.nblk_upd), dim3(kUpdThreads), 0, s, Q, ldq, N, ncol, h, sgn, w,
+                     g.normpart, fin ? 1 : 0);
+  SGN_HIP(hipGetLastError());
   if (fin) {
+    FinDev fd{};
     fd.h1 = fin->h1;
     fd.hout = fin->hout;
     fd.beta = fin->beta;
@@ -272,19 +247,14 @@ static void update_launch(const GsWork& g, const double2* Q, size_t ldq, int N, 
     fd.flag = fin->flag;
     fd.kval = kval;
     fd.active = 1;
+    hipLaunchKernelGGL(gs_final_kernel, dim3(1), dim3(256), 0, s, g.normpart, g.nblk_upd, ncol, h, fd);
+    SGN_HIP(hipGetLastError());
   }
-  const int ndotgroups = (g.ncol_cap + kDotCols - 1) / kDotCols;
-  unsigned* cnt_rows = g.counters + ndotgroups;
-  unsigned* cnt_norm = cnt_rows + g.nrt_upd;
-  const int idx = prof ? prof->begin(K_CGS_UPDATE) : -1;
-  hipLaunchKernelGGL(gs_update_kernel, dim3(g.nrt_upd, ngroups), dim3(256), 0, s, Q, ldq, N, ncol, h, sgn, w,
-                     g.Upart, ngroups, cnt_rows, cnt_norm, g.nrt_upd, g.normpart, fd);
-  SGN_HIP(hipGetLastError());
   if (prof) prof->end(idx, 16.0 * ((double)N * ncol + 2.0 * N + ncol), 8.0 * (double)N * ncol);
 }
 
 void gs_update(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* h, double2* w,
-                 const GsFinal* fin, int kval, hipStream_t s, Profiler* prof) {
+               const GsFinal* fin, int kval, hipStream_t s, Profiler* prof) {
   update_launch(g, Q, ldq, N, ncol, h, -1.0, w, fin, kval, s, prof);
 }
 
@@ -299,4 +269,3 @@ void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, 
   dev_zero(y, (size_t)N, s);
   update_launch(g, Q, ldq, N, ncol, coef, +1.0, y, nullptr, 0, s, prof);
 }
-

@@ -117,14 +117,10 @@ inline void prof_launch(Profiler* prof, int cls, double nbytes, double nflops, F
 // ----------------------------------------------------------------------------
 struct GsWork {
   int nrt_dot = 0;      // row tiles of the dot kernel
-  int nrt_upd = 0;      // row tiles of the update kernel
+  int nblk_upd = 0;     // 64-row blocks of the update kernel
   int ncol_cap = 0;     // max columns
-  double2* P = nullptr;      // dot partials [nrt_dot][ncol_cap]
-  double2* Upart = nullptr;  // update partials [ngroups][ldq]
-  int ngroups_cap = 0;
-  double* normpart = nullptr;  // [nrt_upd]
-  unsigned* counters = nullptr;  // zero-initialised, reset by the kernels
-  int ncounters = 0;
+  double2* P = nullptr;        // dot partials [nrt_dot][ncol_cap]
+  double* normpart = nullptr;  // |w|^2 per update block [nblk_upd]
 };
 
 // GS kernels (gs.hip)
