@@ -228,6 +228,17 @@ int sgn_set_sign_method(sgn_ctx* ctx, int method);
 /* Select the orthogonalisation schedule (SGN_ORTH_*); default DELAYED. */
 int sgn_set_orthogonalization(sgn_ctx* ctx, int mode);
 
+/* Launch shape of the Arnoldi step's two sweeps over the basis (Eq.
+ * eq:modArnoldi; the Gram-Schmidt dot and update passes of step (iv)):
+ * update_batch (4, 8 or 16) basis columns whose loads each lane of the
+ * update pass issues before their arithmetic, and dot_cols (1, 2 or 4)
+ * basis columns per wavefront of the dot pass.  Every choice forms every sum
+ * in the same order, so results are bitwise the same; only the time
+ * differs.  Defaults 8 and 4.  Applies to later applies, batched applies and
+ * session steps on this context.  SGN_EINVAL for other values. */
+int sgn_set_tuning(sgn_ctx* ctx, int update_batch, int dot_cols);
+int sgn_get_tuning(const sgn_ctx* ctx, int* update_batch, int* dot_cols);
+
 /* Checkpoint placement of sgn_apply.  The small-matrix sign is evaluated at
  * even checkpoints; the first successful sgn_apply on a field records the k
  * at which convergence to tol was certified, and later applies with the same

@@ -95,6 +95,8 @@ def _load():
         "sgn_profile_reset": (i, [vp]),
         "sgn_deflate": (i, [vp, i]),
         "sgn_set_orthogonalization": (i, [vp, i]),
+        "sgn_set_tuning": (i, [vp, i, i]),
+        "sgn_get_tuning": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "sgn_set_precision": (i, [vp, i]),
         "sgn_set_schedule": (i, [vp, i, d]),
         "sgn_set_sign_method": (i, [vp, i]),
@@ -330,6 +332,18 @@ def sgn_set_sign_method(ctx, method):
 
 def sgn_set_orthogonalization(ctx, mode):
     return _check(ctx, _lib.sgn_set_orthogonalization(ctx, int(mode)))
+
+
+def sgn_set_tuning(ctx, update_batch, dot_cols):
+    """Launch shape of the Arnoldi step's dot and update passes (results
+    are bitwise the same for every choice)."""
+    return _check(ctx, _lib.sgn_set_tuning(ctx, int(update_batch), int(dot_cols)))
+
+
+def sgn_get_tuning(ctx):
+    ub, cpw = C.c_int(), C.c_int()
+    _check(ctx, _lib.sgn_get_tuning(ctx, C.byref(ub), C.byref(cpw)))
+    return ub.value, cpw.value
 
 
 def sgn_last_info(ctx):

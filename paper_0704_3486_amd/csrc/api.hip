@@ -155,6 +155,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
 
   // argument block of the one-reduction step (krylov.hip)
   KrylovArgs ka;
+  ka.tune = c->tune;
   ka.N = N;
   ka.ldq = ldq;
   ka.m = m;
@@ -659,6 +660,25 @@ int sgn_set_orthogonalization(sgn_ctx* c, int mode) {
     c->orth = mode;
     return SGN_OK;
   });
+}
+
+int sgn_set_tuning(sgn_ctx* c, int update_batch, int dot_cols) {
+  return guarded(c, [&] {
+    KrylovTune t;
+    t.ub = update_batch;
+    t.cpw = dot_cols;
+    SGN_REQUIRE(krylov_tune_valid(t), SGN_EINVAL, "update_batch must be 4, 8 or 16 and dot_cols 1, 2 or 4");
+    c->tune = t;
+    return SGN_OK;
+  });
+}
+
+int sgn_get_tuning(const sgn_ctx* c, int* update_batch, int* dot_cols) {
+  if (!c) return SGN_ESTATE;
+  if (!update_batch || !dot_cols) return SGN_EINVAL;
+  *update_batch = c->tune.ub;
+  *dot_cols = c->tune.cpw;
+  return SGN_OK;
 }
 
 int sgn_last_info(const sgn_ctx* c, sgn_info* info) {

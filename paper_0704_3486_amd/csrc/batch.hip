@@ -120,6 +120,7 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
     if (h_fin[r] != 0) throw SgnError{SGN_EINVAL, "x contains NaN or Inf"};
 
   KrylovArgs base;
+  base.tune = c->tune;
   base.N = N;
   base.ldq = ldq;
   base.m = m;

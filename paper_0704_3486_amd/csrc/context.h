@@ -124,6 +124,7 @@ struct sgn_ctx {
   int k_hint = 0;
   double tol_hint = 0.0;
   double rate_hint = 0.0;
+  KrylovTune tune;  // launch shape of the Krylov dot/update passes (results do not depend on it)
   int orth = 1;  // 0: two classical Gram-Schmidt passes per step; 1: one reduction, delayed re-orthogonalisation
   int sessions = 0;  // open serving sessions (they hold the Schur pair and the precision fixed)
 

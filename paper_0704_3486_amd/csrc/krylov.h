@@ -21,6 +21,18 @@ enum {
   kScStride = 16
 };
 
+// Launch shape of the dot and update passes.  Every choice computes every
+// sum in the same order, so results do not depend on it; only the time does.
+//   ub:  update pass, column loads per lane issued before their arithmetic (4, 8, 16)
+//   cpw: dot pass, columns per wavefront (1, 2, 4): fewer columns per
+//        wavefront means more workgroups, shorter chains of dependent loads,
+//        and more re-reads of u and z from cache
+struct KrylovTune {
+  int ub = 8;
+  int cpw = 4;
+};
+bool krylov_tune_valid(const KrylovTune& t);
+
 struct KrylovArgs {
   int N = 0;
   size_t ldq = 0;
@@ -55,6 +67,7 @@ struct KrylovArgs {
   // orthogonalisation is below brk_tol times its reference size: about the
   // rounding level of the stored basis (FP64: 1e-12; FP32 columns: 1e-6)
   double brk_tol = 1e-12;
+  KrylovTune tune;  // host side only (selects the kernel instance)
   // filled by krylov_bind from the workspace
   double2 *Pa = nullptr, *Pb = nullptr;
   double* Pcd = nullptr;
@@ -82,7 +95,6 @@ struct KrylovArgs {
 // coefficients a, b [slot][column] and the step scalars [slot][kScStride]
 struct KrylovWork {
   int nrt_dot = 0, ncol_cap = 0, nslots = 0;
-  int ngroups_dot_cap = 0;
   int ldp = 0;
   size_t pstride = 0, cdstride = 0, abstride = 0;
   double2 *Pa = nullptr, *Pb = nullptr;

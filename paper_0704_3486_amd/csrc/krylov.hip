@@ -34,12 +34,10 @@
 namespace {
 
 constexpr int kRpl = 8;                 // dot: rows per lane
-constexpr int kCpw = 4;                 // dot: columns per wavefront
-constexpr int kDRows = 64 * kRpl;       // dot: rows per tile
-constexpr int kDCols = kCpw * 4;        // dot: columns per workgroup (4 wavefronts)
+constexpr int kDRows = 64 * kRpl;       // dot: rows per tile (4 wavefronts of CPW columns each)
 constexpr int kUWaves = 8;              // update / combine: wavefronts per 64-row workgroup
 constexpr int kUThreads = 64 * kUWaves;
-constexpr int kUBatch = 8;              // update / combine: column loads issued together per lane
+constexpr int kCBatch = 8;              // combine: column loads issued together per lane
 
 __device__ inline double2 ld2(const double2* p, size_t i) { return p[i]; }
 __device__ inline double2 ld2(const float2* p, size_t i) {
@@ -94,8 +92,9 @@ __device__ inline void dot_cols(const QT* __restrict__ q, const double2 uv[kRpl]
   }
 }
 
-// workgroup id = z + nb (rt + nrt cg): batch position fastest, then row tile
-template <typename VT>
+// workgroup id = z + nb (rt + nrt cg): batch position fastest, then row
+// tile; column group cg holds columns [4 CPW cg, 4 CPW (cg + 1)), CPW per wavefront
+template <typename VT, int CPW>
 __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
   const int zb = blockIdx.x % A.nb, rest = blockIdx.x / A.nb;
   const int rt = rest % A.nrt_dot, cg = rest / A.nrt_dot;
@@ -116,9 +115,9 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
     uv[t] = (i < N) ? u[i] : make_double2(0.0, 0.0);
     zv[t] = (with_z && i < N) ? ld2(z, i) : make_double2(0.0, 0.0);
   }
-  const int cw = cg * kDCols + wave * kCpw;  // first column of this wavefront
+  const int cw = (cg * 4 + wave) * CPW;  // first column of this wavefront
 #pragma unroll
-  for (int cc = 0; cc < kCpw; ++cc) {
+  for (int cc = 0; cc < CPW; ++cc) {
     const int c = cw + cc;
     if (c < J) {
       double2 aa = make_double2(0.0, 0.0), bb = make_double2(0.0, 0.0);
@@ -266,7 +265,21 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int la
   const int lim = (j > 0) ? J - 1 : J;
   double2 ha = make_double2(0.0, 0.0);
   if (row < J)  // row J of columns < J-1 is below the subdiagonal (zero)
-    for (int l = lane; l < lim; l += 64) ha = cfma(H[(size_t)l * ldh + row], a[l], ha);
+    // columns l = lane, lane + 64, ... in order, 8 loads in flight per lane
+    for (int l0 = 0; l0 < lim; l0 += 8 * 64) {
+      double2 hv[8], xv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int l = l0 + t * 64 + lane;
+        if (l < lim) {
+          hv[t] = H[(size_t)l * ldh + row];
+          xv[t] = a[l];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (l0 + t * 64 + lane < lim) ha = cfma(hv[t], xv[t], ha);
+    }
   ha = wsum2(ha);
   if (lane != 0) return;
   const double rho = st.rho, inv = st.inv;
@@ -283,28 +296,37 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int la
 }
 
 // sa += sum_c q_c[i] a_c, sb += sum_c q_c[i] b_c over the columns c = c0,
-// c0 + kUWaves, ... < cend; column c sits at base + (c - cofs) ldq.  kUBatch
-// loads per lane are issued before their arithmetic.
+// c0 + kUWaves, ... < cend, in that order; column c sits at base + (c - cofs)
+// ldq.  Each batch of KB column loads (and their coefficients) is issued
+// before its arithmetic, the last, partial batch too, so a sweep costs
+// ceil(ncols / KB) memory round trips: a slot past cend reloads column
+// cend - 1 (a cache hit) and adds it with coefficient zero, which leaves the
+// sums unchanged since basis vectors are finite.
 // (rows past N load row N-1 and are never written: unconditional loads; c
 // is wavefront-uniform, so the coefficients come through scalar loads)
-template <typename QT, bool HasB>
+template <typename QT, bool HasB, int KB>
 __device__ inline void sweep_cols(const QT* __restrict__ base, int cofs, size_t ldq, int c, int cend, int i,
                                   const double2* __restrict__ av, const double2* __restrict__ bv, double2& sa,
                                   double2& sb) {
-  for (; c + (kUBatch - 1) * kUWaves < cend; c += kUBatch * kUWaves) {
-    double2 qv[kUBatch];
+  const double2 zero = make_double2(0.0, 0.0);
+  for (; c < cend; c += KB * kUWaves) {
+    double2 qv[KB], ca[KB], cb[KB];
 #pragma unroll
-    for (int t = 0; t < kUBatch; ++t) qv[t] = ld2(base + (size_t)(c + t * kUWaves - cofs) * ldq, i);
-#pragma unroll
-    for (int t = 0; t < kUBatch; ++t) {
-      sa = cfma(qv[t], av[c + t * kUWaves], sa);
-      if constexpr (HasB) sb = cfma(qv[t], bv[c + t * kUWaves], sb);
+    for (int t = 0; t < KB; ++t) {
+      const int cc = c + t * kUWaves, cl = min(cc, cend - 1);
+      qv[t] = ld2(base + (size_t)(cl - cofs) * ldq, i);
+      ca[t] = av[cl];
+      if constexpr (HasB) cb[t] = bv[cl];
+      if (cc >= cend) {
+        ca[t] = zero;
+        if constexpr (HasB) cb[t] = zero;
+      }
     }
-  }
-  for (; c < cend; c += kUWaves) {
-    const double2 qv = ld2(base + (size_t)(c - cofs) * ldq, i);
-    sa = cfma(qv, av[c], sa);
-    if constexpr (HasB) sb = cfma(qv, bv[c], sb);
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+      sa = cfma(qv[t], ca[t], sa);
+      if constexpr (HasB) sb = cfma(qv[t], cb[t], sb);
+    }
   }
 }
 
@@ -317,7 +339,7 @@ __device__ inline int first_col(int m, int w) { return m + ((w - m % kUWaves) + 
 // update pass: each workgroup owns 64 rows and all J columns; its kUWaves
 // wavefronts take interleaved columns and are combined in LDS in fixed order.
 // Workgroup id = z + nb blk (batch position fastest, then the 64-row block).
-template <typename VT>
+template <typename VT, int KB>
 __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
   const int zb = blockIdx.x % A.nb, blk = blockIdx.x / A.nb, nblk = gridDim.x / A.nb;
   const int r = slot_of(A, zb);
@@ -331,9 +353,9 @@ __global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
   // Q (b - gr a) = sb - gr sa)
   double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
   const int il = ok ? i : N - 1;
-  sweep_cols<double2, true>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
-  sweep_cols<VT, true>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq, first_col(A.m, wave), J, il,
-                       av, bv, sa, sb);
+  sweep_cols<double2, true, KB>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
+  sweep_cols<VT, true, KB>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq, first_col(A.m, wave), J,
+                           il, av, bv, sa, sb);
   __shared__ double2 ps[2][kUWaves][64];
   ps[0][wave][lane] = sa;
   ps[1][wave][lane] = sb;
@@ -400,9 +422,9 @@ __global__ void __launch_bounds__(kUThreads) kcombine_kernel(KrylovArgs A, const
   const double2* cf = coef + (size_t)r * cstride;
   double2 acc = make_double2(0.0, 0.0), unused = make_double2(0.0, 0.0);
   const int il = ok ? i : A.N - 1;
-  sweep_cols<double2, false>(A.S, 0, A.ldq, wave, min(ncol, A.m), il, cf, nullptr, acc, unused);
-  sweep_cols<VT, false>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq, first_col(A.m, wave), ncol,
-                        il, cf, nullptr, acc, unused);
+  sweep_cols<double2, false, kCBatch>(A.S, 0, A.ldq, wave, min(ncol, A.m), il, cf, nullptr, acc, unused);
+  sweep_cols<VT, false, kCBatch>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
+                                 first_col(A.m, wave), ncol, il, cf, nullptr, acc, unused);
   __shared__ double2 ps[kUWaves][64];
   ps[wave][lane] = acc;
   __syncthreads();
@@ -437,7 +459,6 @@ void krylov_alloc(KrylovWork& w, int N, size_t ldq, int ncol_cap, int nslots) {
   w.nrt_dot = (N + kDRows - 1) / kDRows;
   w.ncol_cap = ncol_cap;
   w.nslots = nslots;
-  w.ngroups_dot_cap = (ncol_cap + kDCols - 1) / kDCols;
   w.ldp = ncol_cap;
   w.pstride = (size_t)w.nrt_dot * ncol_cap;
   w.cdstride = (size_t)4 * w.nrt_dot;
@@ -492,13 +513,37 @@ static void col_sums(const KrylovArgs& A, double& sum_m, double& sum_k) {
   }
 }
 
+bool krylov_tune_valid(const KrylovTune& t) {
+  return (t.ub == 4 || t.ub == 8 || t.ub == 16) && (t.cpw == 1 || t.cpw == 2 || t.cpw == 4);
+}
+
+template <typename VT>
+static auto dot_kernel_for(int cpw) {
+  switch (cpw) {
+    case 1: return kdot_kernel<VT, 1>;
+    case 2: return kdot_kernel<VT, 2>;
+    default: return kdot_kernel<VT, 4>;
+  }
+}
+
+template <typename VT>
+static auto update_kernel_for(int ub) {
+  switch (ub) {
+    case 4: return kupdate_kernel<VT, 4>;
+    case 16: return kupdate_kernel<VT, 16>;
+    default: return kupdate_kernel<VT, 8>;
+  }
+}
+
 template <typename VT>
 void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStream_t s, Profiler* prof) {
   KrylovArgs A = Ain;
   krylov_bind(w, A);
   check_args(w, A);
+  SGN_REQUIRE(krylov_tune_valid(A.tune), SGN_EINVAL, "krylov: invalid launch shape");
   const int Jmax = A.m + A.jmax();
-  const int ngroups = Jmax > 0 ? (Jmax + kDCols - 1) / kDCols : 1;
+  const int gcols = 4 * A.tune.cpw;
+  const int ngroups = Jmax > 0 ? (Jmax + gcols - 1) / gcols : 1;
   const double vb = (double)sizeof(VT);
   double sm, sk;
   col_sums(A, sm, sk);
@@ -507,8 +552,8 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStre
   const size_t nwg = (size_t)w.nrt_dot * ngroups * A.nb;
   SGN_REQUIRE(nwg * 256 < (size_t(1) << 32), SGN_EINVAL, "krylov: dot grid too large");
   prof_launch(prof, K_KDOT, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * (sm + sk),
-              16.0 * (double)A.N * (sm + sk), kdot_kernel<VT>, dim3((unsigned)nwg), dim3(256), 0, s, A,
-              with_z ? 1 : 0);
+              16.0 * (double)A.N * (sm + sk), dot_kernel_for<VT>(A.tune.cpw), dim3((unsigned)nwg), dim3(256), 0, s,
+              A, with_z ? 1 : 0);
   // partial sums of every row tile read, a, b written
   prof_launch(prof, K_KRED, 32.0 * (sm + sk) * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot,
               4.0 * (sm + sk) * w.nrt_dot, kred_kernel, dim3(std::max(1, (Jmax + 31) / 32), 1, A.nb), dim3(256), 0, s,
@@ -521,6 +566,7 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   krylov_bind(w, A);
   check_args(w, A);
   SGN_REQUIRE(A.m + A.jmax() + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
+  SGN_REQUIRE(krylov_tune_valid(A.tune), SGN_EINVAL, "krylov: invalid launch shape");
   const size_t nwg = (size_t)((A.N + 63) / 64) * A.nb;
   SGN_REQUIRE(nwg * kUThreads < (size_t(1) << 32), SGN_EINVAL, "krylov: update grid too large");
   const double vb = (double)sizeof(VT);
@@ -530,7 +576,7 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   // read Q, u, z; write v_J, u' (+ its low-precision copy)
   const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
   prof_launch(prof, K_KUPDATE, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk),
-              kupdate_kernel<VT>, dim3((unsigned)nwg), dim3(kUThreads), 0, s, A);
+              update_kernel_for<VT>(A.tune.ub), dim3((unsigned)nwg), dim3(kUThreads), 0, s, A);
 }
 
 template <typename VT>

@@ -124,6 +124,7 @@ struct sgn_session {
 
   KrylovArgs base() const {
     KrylovArgs a;
+    a.tune = c->tune;
     a.N = c->N;
     a.ldq = ldq;
     a.m = m;
