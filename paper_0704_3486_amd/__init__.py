@@ -96,6 +96,7 @@ def _load():
         "sgn_deflate": (i, [vp, i]),
         "sgn_set_orthogonalization": (i, [vp, i]),
         "sgn_set_tuning": (i, [vp, i, i]),
+        "sgn_set_step_graphs": (i, [vp, i]),
         "sgn_get_tuning": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "sgn_set_precision": (i, [vp, i]),
         "sgn_set_schedule": (i, [vp, i, d]),
@@ -338,6 +339,11 @@ def sgn_set_tuning(ctx, update_batch, dot_cols):
     """Launch shape of the Arnoldi step's dot and update passes (results
     are bitwise the same for every choice)."""
     return _check(ctx, _lib.sgn_set_tuning(ctx, int(update_batch), int(dot_cols)))
+
+
+def sgn_set_step_graphs(ctx, steps):
+    """Replay runs of `steps` Arnoldi steps as captured graphs (0: off)."""
+    return _check(ctx, _lib.sgn_set_step_graphs(ctx, int(steps)))
 
 
 def sgn_get_tuning(ctx):

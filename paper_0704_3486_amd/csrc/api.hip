@@ -136,6 +136,59 @@ struct ApplyResult {
   int status = SGN_OK;
 };
 
+// One step of the one-reduction Arnoldi recurrence (step (iv)): z = H_w u,
+// then the dot and update passes of the argument block.
+static void arnoldi_step(sgn_ctx* c, const KrylovArgs& ka, bool mixed, hipStream_t s, Profiler* prof) {
+  if (mixed) {
+    wilson_apply_multi32(c->lat, c->links32, static_cast<const float2*>(ka.ulonext), 0, c->z32, 0, 1, true, s,
+                         prof);
+    krylov_dot<float2>(c->kw, ka, true, s, prof);
+    krylov_update<float2>(c->kw, ka, s, prof);
+  } else {
+    wilson_apply(c->lat, c->links, ka.u, c->wB, nullptr, nullptr, s, prof);
+    krylov_dot<double2>(c->kw, ka, true, s, prof);
+    krylov_update<double2>(c->kw, ka, s, prof);
+  }
+}
+
+// The graph of L consecutive Arnoldi steps whose step index comes from
+// c->jdev (advanced by L at its end), valid for chunks starting at any j in
+// the same 32-column bucket of j + L - 1; captured on first use.  It holds
+// only kernel launches.
+static hipGraphExec_t step_graph(sgn_ctx* c, const KrylovArgs& ka0, bool mixed, int j, int L) {
+  const int b = (j + L - 1) / 32;
+  if ((int)c->graphs.size() <= b) c->graphs.resize(b + 1, nullptr);
+  if (c->graphs[b]) return c->graphs[b];
+  // grids sized for the largest step of the bucket
+  const int jcap = std::min(32 * (b + 1) - 1, c->kcap - 1);
+  SGN_REQUIRE(j + L - 1 <= jcap, SGN_EINVAL, "captured steps exceed the workspace");
+  if (!c->cap_stream) SGN_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = c->cap_stream;
+  KrylovArgs ka = ka0;
+  ka.single(jcap);
+  ka.jdev = c->jdev;
+  hipGraph_t g = nullptr;
+  SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int t = 0; t < L; ++t) {
+      ka.joff = t;
+      arnoldi_step(c, ka, mixed, cs, nullptr);
+    }
+    krylov_set_index(c->jdev, L, true, cs);
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  SGN_HIP(hipStreamEndCapture(cs, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  SGN_HIP(e);
+  c->graphs[b] = ex;
+  return ex;
+}
+
 // Steps (iii)-(vi).  fixed_k >= 0: exactly that many steps, no convergence test.
 int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int kmax, int fixed_k) {
   const auto t_start = std::chrono::steady_clock::now();
@@ -167,10 +220,10 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   ka.beta = &c->scal[0];
   ka.flag = c->flag;
   ka.brk_tol = mixed ? 1e-6 : 1e-12;
-  double2* ucur = c->wA;   // FP64 candidate
-  double2* unext = c->wC;
-  float2* u32cur = c->u32a;
-  float2* u32next = c->u32b;
+  // the candidate is updated in place by each step (FP64, and its FP32 copy
+  // in mixed precision), so every step's launch arguments are the same
+  double2* const ucur = c->wA;
+  float2* const u32cur = c->u32a;
 
   // step (iii): x_perp = (1 - S S^dag) x, beta = |x_perp|
   SGN_HIP(hipMemsetAsync(c->flag, 0, sizeof(int) * 2, s));
@@ -272,27 +325,27 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     }
     double2* wprev = c->wA;  // two-pass schedule: x_perp (unnormalised) for j = 0
     double2* wcur = c->wB;
-    for (int j = 0; j < kwant; ++j) {
+    ka.u = ucur;
+    ka.unext = ucur;
+    ka.z = mixed ? (const void*)c->z32 : (const void*)c->wB;
+    ka.ulonext = mixed ? (void*)u32cur : nullptr;
+    for (int j = 0; j < kwant;) {
       const int J = m + j;
-      if (delayed) {
-        ka.single(j);
-        ka.u = ucur;
-        ka.unext = unext;
-        if (mixed) {
-          wilson_apply_multi32(c->lat, c->links32, u32cur, 0, c->z32, 0, 1, true, s, prof);
-          ka.z = c->z32;
-          ka.ulonext = u32next;
-          krylov_dot<float2>(c->kw, ka, true, s, prof);
-          krylov_update<float2>(c->kw, ka, s, prof);
-          std::swap(u32cur, u32next);
-        } else {
-          wilson_apply(c->lat, c->links, ucur, c->wB, nullptr, nullptr, s, prof);
-          ka.z = c->wB;
-          ka.ulonext = nullptr;
-          krylov_dot<double2>(c->kw, ka, true, s, prof);
-          krylov_update<double2>(c->kw, ka, s, prof);
+      const int seg_end = std::min(next_ck, kwant);  // the next checkpoint
+      const int L = c->graph_steps;
+      if (delayed && !prof && L > 0 && j + L <= seg_end) {
+        // whole captured chunks of L steps up to the checkpoint
+        krylov_set_index(c->jdev, j, false, s);
+        while (j + L <= seg_end) {
+          SGN_HIP(hipGraphLaunch(step_graph(c, ka, mixed, j, L), s));
+          j += L;
+          info.n_matvec += L;
         }
-        std::swap(ucur, unext);
+      } else if (delayed) {
+        ka.single(j);
+        arnoldi_step(c, ka, mixed, s, prof);
+        ++j;
+        info.n_matvec += 1;
       } else {
         double2* vcol = c->Q + (size_t)J * ldq;
         wilson_apply(c->lat, c->links, wprev, wcur, &c->scal[1], vcol, s, prof);
@@ -303,9 +356,10 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
         GsFinal fin{c->hbuf1, c->Hc + (size_t)J * ncap, nullptr, &c->scal[1], c->flag};
         gs_update(c->gs, c->Q, ldq, N, ncol, c->hbuf2, wcur, &fin, j + 1, s, prof);
         std::swap(wprev, wcur);
+        ++j;
+        info.n_matvec += 1;
       }
-      k = j + 1;
-      info.n_matvec += 1;
+      k = j;
       if (k == next_ck || k == kwant) {
         // breakdown check (flag = k_invariant + 1)
         SGN_HIP(hipMemcpyAsync(&c->hpin[4], c->flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -668,7 +722,19 @@ int sgn_set_tuning(sgn_ctx* c, int update_batch, int dot_cols) {
     t.ub = update_batch;
     t.cpw = dot_cols;
     SGN_REQUIRE(krylov_tune_valid(t), SGN_EINVAL, "update_batch must be 4, 8 or 16 and dot_cols 1, 2 or 4");
+    SGN_HIP(hipStreamSynchronize(c->stream));
     c->tune = t;
+    c->drop_graphs();  // they hold the previous kernel instances
+    return SGN_OK;
+  });
+}
+
+int sgn_set_step_graphs(sgn_ctx* c, int steps) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(steps == 0 || (steps >= 2 && steps <= 64), SGN_EINVAL, "steps must be 0 or 2..64");
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    if (steps != c->graph_steps) c->drop_graphs();
+    c->graph_steps = steps;
     return SGN_OK;
   });
 }

@@ -125,6 +125,14 @@ struct sgn_ctx {
   double tol_hint = 0.0;
   double rate_hint = 0.0;
   KrylovTune tune;  // launch shape of the Krylov dot/update passes (results do not depend on it)
+  // captured Arnoldi steps: graph_steps consecutive steps of sgn_apply per
+  // replay (0: direct launches), one graph per 32-column bucket of the basis
+  // size, captured on cap_stream when first needed; they hold the workspace's
+  // addresses and are dropped with it
+  int graph_steps = 0;
+  hipStream_t cap_stream = nullptr;
+  int* jdev = nullptr;  // device step index read by the captured steps
+  std::vector<hipGraphExec_t> graphs;
   int orth = 1;  // 0: two classical Gram-Schmidt passes per step; 1: one reduction, delayed re-orthogonalisation
   int sessions = 0;  // open serving sessions (they hold the Schur pair and the precision fixed)
 
@@ -143,8 +151,17 @@ struct sgn_ctx {
       }
     gs_free(gs);
     krylov_free(kw);
+    drop_graphs();
+    if (jdev) (void)hipFree(jdev);
+    jdev = nullptr;
     kcap = 0;
     ncap = 0;
+  }
+
+  void drop_graphs() {
+    for (hipGraphExec_t& g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    graphs.clear();
   }
 
   void release() {
@@ -162,6 +179,8 @@ struct sgn_ctx {
     if (scal) (void)hipFree(scal);
     if (flag) (void)hipFree(flag);
     if (hpin) (void)hipHostFree(hpin);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
     scal = nullptr;
     flag = nullptr;
     hpin = nullptr;
@@ -194,6 +213,7 @@ struct sgn_ctx {
     SGN_HIP(hipMalloc(&c0, sizeof(double2) * (size_t)(m > 0 ? m : 1)));
     SGN_HIP(hipMalloc(&cvec, sizeof(double2) * (size_t)ncap));
     SGN_HIP(hipMalloc(&cprev, sizeof(double2) * (size_t)ncap));
+    SGN_HIP(hipMalloc(&jdev, sizeof(int)));
     gs_alloc(gs, N, ldq, ncap);
     krylov_alloc(kw, N, ldq, ncap, 1);
     dense_reserve(dense, m + kcap, 1);

@@ -43,6 +43,10 @@ struct KrylovArgs {
   int nb = 1;
   int act[kMaxBatch] = {};
   int jv[kMaxBatch] = {};
+  // replayable launches (nb == 1): the step index is *jdev + joff, read on
+  // the device; jv[0] then only sizes the grids (an upper bound on the step)
+  const int* jdev = nullptr;
+  int joff = 0;
   // Krylov columns: column c >= m of slot r at V + r*vstride + (c-m)*ldq (element type VT)
   void* V = nullptr;
   size_t vstride = 0;
@@ -113,6 +117,8 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& A, bool with_z, hipStream
 // v_J, next candidate, Hessenberg column J and re-orthogonalisation of column J-1
 template <typename VT>
 void krylov_update(const KrylovWork& w, const KrylovArgs& A, hipStream_t s, Profiler* prof);
+// *p = v, or *p += v (stream-ordered; for the device step index of replayed steps)
+void krylov_set_index(int* p, int v, bool add, hipStream_t s);
 // y_r = Q_r coef_r over ncol columns (the same ncol for every launch slot)
 template <typename VT>
 void krylov_combine(const KrylovWork& w, const KrylovArgs& A, const double2* coef, int cstride, double2* y,

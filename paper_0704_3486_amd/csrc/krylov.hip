@@ -71,7 +71,7 @@ __device__ inline double2 qload(const KrylovArgs& A, int r, int c, int i) {
 
 // launch position z (an index into the batch) -> buffer slot and step
 __device__ inline int slot_of(const KrylovArgs& A, int z) { return A.act[z]; }
-__device__ inline int step_of(const KrylovArgs& A, int z) { return A.jv[z]; }
+__device__ inline int step_of(const KrylovArgs& A, int z) { return A.jdev ? *A.jdev + A.joff : A.jv[z]; }
 
 // ---------------------------------------------------------------------------
 // dot pass: per (row tile, column group) partial sums of Q^dag u and Q^dag z,
@@ -436,6 +436,10 @@ __global__ void __launch_bounds__(kUThreads) kcombine_kernel(KrylovArgs A, const
   }
 }
 
+__global__ void set_index_kernel(int* p, int v, int add) {
+  if (threadIdx.x == 0) *p = add ? *p + v : v;
+}
+
 // dst = H[:n,:n] with column n-1 += a (slot r), dst dense n x n per slot
 __global__ void kpatch_kernel(KrylovArgs A, int n, double2* __restrict__ dst, size_t dstride, int with_a) {
   const int r = slot_of(A, blockIdx.z);
@@ -496,6 +500,7 @@ void krylov_bind(const KrylovWork& w, KrylovArgs& A) {
 
 static void check_args(const KrylovWork& w, const KrylovArgs& A) {
   SGN_REQUIRE(A.nb >= 1 && A.nb <= w.nslots && A.nb <= kMaxBatch, SGN_EINVAL, "krylov: batch exceeds workspace");
+  SGN_REQUIRE(!A.jdev || (A.nb == 1 && A.joff >= 0), SGN_EINVAL, "krylov: device step index needs one slot");
   for (int z = 0; z < A.nb; ++z) {
     SGN_REQUIRE(A.act[z] >= 0 && A.act[z] < w.nslots, SGN_EINVAL, "krylov: slot out of range");
     SGN_REQUIRE(A.jv[z] >= 0 && A.m + A.jv[z] <= w.ncol_cap, SGN_EINVAL, "krylov: J exceeds workspace");
@@ -591,6 +596,11 @@ void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, const double2* c
   prof_launch(prof, K_KCOMBINE, A.nb * (double)A.N * (16.0 * nm + vb * (ncol - nm) + 16.0),
               A.nb * 8.0 * (double)A.N * ncol, kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, A.nb), dim3(kUThreads),
               0, s, A, coef, cstride, y, ystride, ncol);
+}
+
+void krylov_set_index(int* p, int v, bool add, hipStream_t s) {
+  hipLaunchKernelGGL(set_index_kernel, dim3(1), dim3(64), 0, s, p, v, add ? 1 : 0);
+  SGN_HIP(hipGetLastError());
 }
 
 void krylov_patch(const KrylovWork& w, const KrylovArgs& Ain, int n, double2* dst, size_t dstride, bool with_a,
