@@ -231,13 +231,17 @@ int sgn_set_orthogonalization(sgn_ctx* ctx, int mode);
 /* Launch shape of the Arnoldi step's two sweeps over the basis (Eq.
  * eq:modArnoldi; the Gram-Schmidt dot and update passes of step (iv)):
  * update_batch (4, 8 or 16) basis columns whose loads each lane of the
- * update pass issues before their arithmetic, and dot_cols (1, 2 or 4)
- * basis columns per wavefront of the dot pass.  Every choice forms every sum
- * in the same order, so results are bitwise the same; only the time
- * differs.  Defaults 8 and 4.  Applies to later applies, batched applies and
- * session steps on this context.  SGN_EINVAL for other values. */
-int sgn_set_tuning(sgn_ctx* ctx, int update_batch, int dot_cols);
-int sgn_get_tuning(const sgn_ctx* ctx, int* update_batch, int* dot_cols);
+ * update pass issues before their arithmetic, dot_cols (1, 2 or 4) basis
+ * columns per wavefront of the dot pass, and update_waves (8 or 16)
+ * wavefronts per 64-row workgroup of the update pass.  update_batch and
+ * dot_cols form every sum in the same order, so results are bitwise the
+ * same for all their values; update_waves changes which columns each
+ * wavefront sums, so results differ between its values at the rounding
+ * level.  Defaults 8, 4, 8.  Applies to later applies, batched applies and
+ * session steps on this context (which all use the same shape, so they stay
+ * bitwise consistent with each other).  SGN_EINVAL for other values. */
+int sgn_set_tuning(sgn_ctx* ctx, int update_batch, int dot_cols, int update_waves);
+int sgn_get_tuning(const sgn_ctx* ctx, int* update_batch, int* dot_cols, int* update_waves);
 
 /* Captured Arnoldi steps of sgn_apply / sgn_apply_fixed (step (iv)): runs
  * of `steps` consecutive steps between two checkpoints are replayed as one

@@ -95,9 +95,9 @@ def _load():
         "sgn_profile_reset": (i, [vp]),
         "sgn_deflate": (i, [vp, i]),
         "sgn_set_orthogonalization": (i, [vp, i]),
-        "sgn_set_tuning": (i, [vp, i, i]),
+        "sgn_set_tuning": (i, [vp, i, i, i]),
         "sgn_set_step_graphs": (i, [vp, i]),
-        "sgn_get_tuning": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "sgn_get_tuning": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "sgn_set_precision": (i, [vp, i]),
         "sgn_set_schedule": (i, [vp, i, d]),
         "sgn_set_sign_method": (i, [vp, i]),
@@ -335,10 +335,11 @@ def sgn_set_orthogonalization(ctx, mode):
     return _check(ctx, _lib.sgn_set_orthogonalization(ctx, int(mode)))
 
 
-def sgn_set_tuning(ctx, update_batch, dot_cols):
-    """Launch shape of the Arnoldi step's dot and update passes (results
-    are bitwise the same for every choice)."""
-    return _check(ctx, _lib.sgn_set_tuning(ctx, int(update_batch), int(dot_cols)))
+def sgn_set_tuning(ctx, update_batch=8, dot_cols=4, update_waves=8):
+    """Launch shape of the Arnoldi step's dot and update passes (results are
+    bitwise the same for every update_batch and dot_cols; update_waves
+    changes them at the rounding level)."""
+    return _check(ctx, _lib.sgn_set_tuning(ctx, int(update_batch), int(dot_cols), int(update_waves)))
 
 
 def sgn_set_step_graphs(ctx, steps):
@@ -347,9 +348,9 @@ def sgn_set_step_graphs(ctx, steps):
 
 
 def sgn_get_tuning(ctx):
-    ub, cpw = C.c_int(), C.c_int()
-    _check(ctx, _lib.sgn_get_tuning(ctx, C.byref(ub), C.byref(cpw)))
-    return ub.value, cpw.value
+    ub, cpw, uw = C.c_int(), C.c_int(), C.c_int()
+    _check(ctx, _lib.sgn_get_tuning(ctx, C.byref(ub), C.byref(cpw), C.byref(uw)))
+    return ub.value, cpw.value, uw.value
 
 
 def sgn_last_info(ctx):

@@ -716,12 +716,14 @@ int sgn_set_orthogonalization(sgn_ctx* c, int mode) {
   });
 }
 
-int sgn_set_tuning(sgn_ctx* c, int update_batch, int dot_cols) {
+int sgn_set_tuning(sgn_ctx* c, int update_batch, int dot_cols, int update_waves) {
   return guarded(c, [&] {
     KrylovTune t;
     t.ub = update_batch;
     t.cpw = dot_cols;
-    SGN_REQUIRE(krylov_tune_valid(t), SGN_EINVAL, "update_batch must be 4, 8 or 16 and dot_cols 1, 2 or 4");
+    t.uw = update_waves;
+    SGN_REQUIRE(krylov_tune_valid(t), SGN_EINVAL,
+                "update_batch must be 4, 8 or 16, dot_cols 1, 2 or 4 and update_waves 8 or 16");
     SGN_HIP(hipStreamSynchronize(c->stream));
     c->tune = t;
     c->drop_graphs();  // they hold the previous kernel instances
@@ -739,11 +741,12 @@ int sgn_set_step_graphs(sgn_ctx* c, int steps) {
   });
 }
 
-int sgn_get_tuning(const sgn_ctx* c, int* update_batch, int* dot_cols) {
+int sgn_get_tuning(const sgn_ctx* c, int* update_batch, int* dot_cols, int* update_waves) {
   if (!c) return SGN_ESTATE;
-  if (!update_batch || !dot_cols) return SGN_EINVAL;
+  if (!update_batch || !dot_cols || !update_waves) return SGN_EINVAL;
   *update_batch = c->tune.ub;
   *dot_cols = c->tune.cpw;
+  *update_waves = c->tune.uw;
   return SGN_OK;
 }
 

@@ -21,15 +21,21 @@ enum {
   kScStride = 16
 };
 
-// Launch shape of the dot and update passes.  Every choice computes every
-// sum in the same order, so results do not depend on it; only the time does.
+// Launch shape of the dot and update passes.  Every choice of ub and cpw
+// forms every sum in the same order, so results do not depend on them; only
+// the time does.
 //   ub:  update pass, column loads per lane issued before their arithmetic (4, 8, 16)
 //   cpw: dot pass, columns per wavefront (1, 2, 4): fewer columns per
 //        wavefront means more workgroups, shorter chains of dependent loads,
 //        and more re-reads of u and z from cache
+//   uw:  update pass, wavefronts per 64-row workgroup (8, 16).  Unlike ub and
+//        cpw this changes which columns each wavefront sums, so results
+//        differ at the rounding level between its values (every path of a
+//        context uses the same value, so they stay bitwise consistent).
 struct KrylovTune {
   int ub = 8;
   int cpw = 4;
+  int uw = 8;
 };
 bool krylov_tune_valid(const KrylovTune& t);
 

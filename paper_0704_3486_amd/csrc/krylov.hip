@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kRpl = 8;                 // dot: rows per lane
 constexpr int kDRows = 64 * kRpl;       // dot: rows per tile (4 wavefronts of CPW columns each)
-constexpr int kUWaves = 8;              // update / combine: wavefronts per 64-row workgroup
+constexpr int kUWaves = 8;              // combine (and the default update): wavefronts per 64-row workgroup
 constexpr int kUThreads = 64 * kUWaves;
 constexpr int kCBatch = 8;              // combine: column loads issued together per lane
 
@@ -60,6 +60,9 @@ __device__ inline double wsum1(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// wavefront index as a scalar (uniform) value
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // column c of Q for right-hand side slot r
 template <typename VT>
@@ -199,8 +202,10 @@ __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
   }
 }
 
-// Step scalars from a, b and the raw sums; every workgroup of the update
-// computes them identically (fixed order), workgroup 0 also records them.
+// Step scalars from a, b and the raw sums.  Each thread brings its partial
+// sums over the columns c = tid, tid + NT, ... (|a_c|^2 and conj(a_c) b_c);
+// they are combined by wavefront butterflies and then over the wavefronts in
+// a fixed order, so every workgroup computes them identically.
 struct StepScalars {
   double rho, inv;
   double2 gam, gr;
@@ -208,38 +213,45 @@ struct StepScalars {
   double scale;
 };
 
+// this thread's columns of a and b: the first two are loaded by the caller
+// (early, so their latency overlaps other work), the rest here
 template <int NT>
-__device__ StepScalars step_scalars(const KrylovArgs& A, int r, int j, double* red /* LDS [3][NT] */) {
-  const int J = A.m + j, tid = threadIdx.x;
-  const double2* a = A.a + (size_t)r * A.abstride;
-  const double2* b = A.b + (size_t)r * A.abstride;
-  const double* sc = A.sc + (size_t)r * kScStride;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int c = tid; c < J; c += NT) {
-    const double2 x1 = a[c], x2 = b[c];
+__device__ inline void scalar_partials(const double2* av, const double2* bv, int J, double2 a0, double2 b0,
+                                       double2 a1, double2 b1, double& s0, double2& s12) {
+  const int tid = threadIdx.x;
+  s0 = cabs2(a0) + cabs2(a1);
+  s12 = cadd(cmulc(a0, b0), cmulc(a1, b1));
+  for (int c = tid + 2 * NT; c < J; c += NT) {
+    const double2 x1 = av[c], x2 = bv[c];
     s0 += cabs2(x1);
-    const double2 ab = cmulc(x1, x2);
-    s1 += ab.x;
-    s2 += ab.y;
+    s12 = cadd(s12, cmulc(x1, x2));
   }
-  red[tid] = s0;
-  red[NT + tid] = s1;
-  red[2 * NT + tid] = s2;
+}
+
+template <int NW>
+__device__ StepScalars step_scalars(const KrylovArgs& A, int r, int j, double s0, double2 s12,
+                                    double* red /* LDS [3][NW] */) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  s0 = wsum1(s0);
+  s12 = wsum2(s12);
+  if (lane == 0) {
+    red[wave] = s0;
+    red[NW + wave] = s12.x;
+    red[2 * NW + wave] = s12.y;
+  }
   __syncthreads();
-  for (int off = NT / 2; off > 0; off >>= 1) {
-    if (tid < off) {
-      red[tid] += red[tid + off];
-      red[NT + tid] += red[NT + tid + off];
-      red[2 * NT + tid] += red[2 * NT + tid + off];
-    }
-    __syncthreads();
+  double aa = red[0];
+  double2 ab = make_double2(red[NW], red[2 * NW]);
+  for (int w = 1; w < NW; ++w) {
+    aa += red[w];
+    ab.x += red[NW + w];
+    ab.y += red[2 * NW + w];
   }
+  const double* sc = A.sc + (size_t)r * kScStride;
   StepScalars st;
   const double c = sc[kScRawC];
   const double2 d = make_double2(sc[kScRawC + 1], sc[kScRawC + 2]);
   const double zz = sc[kScRawC + 3];
-  const double aa = red[0];
-  const double2 ab = make_double2(red[NT], red[2 * NT]);
   const double rho2 = c - aa;
   const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
   st.finite = isfinite(c) && isfinite(d.x) && isfinite(d.y) && isfinite(zz);
@@ -249,7 +261,6 @@ __device__ StepScalars step_scalars(const KrylovArgs& A, int r, int j, double* r
   st.gam = cscale(csub(d, ab), st.inv);
   st.gr = cscale(st.gam, st.inv);
   st.scale = sqrt(zz) * st.inv;
-  __syncthreads();  // red is reused by the caller
   return st;
 }
 
@@ -265,11 +276,13 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int la
   const int lim = (j > 0) ? J - 1 : J;
   double2 ha = make_double2(0.0, 0.0);
   if (row < J)  // row J of columns < J-1 is below the subdiagonal (zero)
-    // columns l = lane, lane + 64, ... in order, 8 loads in flight per lane
-    for (int l0 = 0; l0 < lim; l0 += 8 * 64) {
-      double2 hv[8], xv[8];
+    // columns l = lane, lane + 64, ... in order, 4 loads of each operand in
+    // flight per lane (deeper batches raise the kernel's register count, and
+    // with it lower the occupancy of the sweep workgroups)
+    for (int l0 = 0; l0 < lim; l0 += 4 * 64) {
+      double2 hv[4], xv[4];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < 4; ++t) {
         const int l = l0 + t * 64 + lane;
         if (l < lim) {
           hv[t] = H[(size_t)l * ldh + row];
@@ -277,7 +290,7 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int la
         }
       }
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
+      for (int t = 0; t < 4; ++t)
         if (l0 + t * 64 + lane < lim) ha = cfma(hv[t], xv[t], ha);
     }
   ha = wsum2(ha);
@@ -296,7 +309,7 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int la
 }
 
 // sa += sum_c q_c[i] a_c, sb += sum_c q_c[i] b_c over the columns c = c0,
-// c0 + kUWaves, ... < cend, in that order; column c sits at base + (c - cofs)
+// c0 + NW, ... < cend, in that order; column c sits at base + (c - cofs)
 // ldq.  Each batch of KB column loads (and their coefficients) is issued
 // before its arithmetic, the last, partial batch too, so a sweep costs
 // ceil(ncols / KB) memory round trips: a slot past cend reloads column
@@ -304,16 +317,16 @@ __device__ void hcol_row_wave(const KrylovArgs& A, int r, int j, int row, int la
 // sums unchanged since basis vectors are finite.
 // (rows past N load row N-1 and are never written: unconditional loads; c
 // is wavefront-uniform, so the coefficients come through scalar loads)
-template <typename QT, bool HasB, int KB>
+template <typename QT, bool HasB, int KB, int NW>
 __device__ inline void sweep_cols(const QT* __restrict__ base, int cofs, size_t ldq, int c, int cend, int i,
                                   const double2* __restrict__ av, const double2* __restrict__ bv, double2& sa,
                                   double2& sb) {
   const double2 zero = make_double2(0.0, 0.0);
-  for (; c < cend; c += KB * kUWaves) {
+  for (; c < cend; c += KB * NW) {
     double2 qv[KB], ca[KB], cb[KB];
 #pragma unroll
     for (int t = 0; t < KB; ++t) {
-      const int cc = c + t * kUWaves, cl = min(cc, cend - 1);
+      const int cc = c + t * NW, cl = min(cc, cend - 1);
       qv[t] = ld2(base + (size_t)(cl - cofs) * ldq, i);
       ca[t] = av[cl];
       if constexpr (HasB) cb[t] = bv[cl];
@@ -330,68 +343,93 @@ __device__ inline void sweep_cols(const QT* __restrict__ base, int cofs, size_t 
   }
 }
 
-// wavefront index as a scalar (uniform) value
-__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// first column >= m that wavefront w takes (c = w mod kUWaves)
-__device__ inline int first_col(int m, int w) { return m + ((w - m % kUWaves) + kUWaves) % kUWaves; }
+// first column >= m that wavefront w of NW takes (c = w mod NW)
+template <int NW>
+__device__ inline int first_col(int m, int w) { return m + ((w - m % NW) + NW) % NW; }
 
-// update pass: each workgroup owns 64 rows and all J columns; its kUWaves
-// wavefronts take interleaved columns and are combined in LDS in fixed order.
-// Workgroup id = z + nb blk (batch position fastest, then the 64-row block).
-template <typename VT, int KB>
-__global__ void __launch_bounds__(kUThreads) kupdate_kernel(KrylovArgs A) {
-  const int zb = blockIdx.x % A.nb, blk = blockIdx.x / A.nb, nblk = gridDim.x / A.nb;
+// update pass.  Per slot, the first nh workgroups compute the Hessenberg
+// column J (one row per wavefront), the next nblk each own 64 rows and all J
+// columns: their NW wavefronts take interleaved columns, combined in LDS in a
+// fixed order.  Workgroup id = z + nb b (batch position fastest).  Both kinds
+// compute the step scalars; the Hessenberg rows, a strided gather, so run
+// beside the sweeps instead of after them.
+template <typename VT, int KB, int NW>
+__global__ void __launch_bounds__(64 * NW) kupdate_kernel(KrylovArgs A, int nh) {
+  constexpr int NT = 64 * NW;
+  const int zb = blockIdx.x % A.nb, bb = blockIdx.x / A.nb;
   const int r = slot_of(A, zb);
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int N = A.N, j = step_of(A, zb), J = A.m + j;
   const double2* av = A.a + (size_t)r * A.abstride;
   const double2* bv = A.b + (size_t)r * A.abstride;
+  const double2 zero = make_double2(0.0, 0.0);
+  // this thread's first two coefficients for the step scalars (loaded after
+  // the sweep in the sweep workgroups, whose registers the sweep needs)
+  double2 a0 = zero, b0 = zero, a1 = zero, b1 = zero;
+  auto load_coef = [&]() {
+    if (tid < J) {
+      a0 = av[tid];
+      b0 = bv[tid];
+    }
+    if (tid + NT < J) {
+      a1 = av[tid + NT];
+      b1 = bv[tid + NT];
+    }
+  };
+  __shared__ double red[3 * NW];
+  double s0;
+  double2 s12;
+  if (bb < nh) {
+    load_coef();
+    scalar_partials<NT>(av, bv, J, a0, b0, a1, b1, s0, s12);
+    const StepScalars st = step_scalars<NW>(A, r, j, s0, s12, red);
+    const int row = bb * NW + wave;
+    if (row <= J) hcol_row_wave(A, r, j, row, lane, st);
+    return;
+  }
+  const int blk = bb - nh;
   const int i = blk * 64 + lane;
   const bool ok = i < N;
   // sweep: sa = Q a, sb = Q b (the step scalars enter only afterwards:
   // Q (b - gr a) = sb - gr sa)
-  double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+  double2 sa = zero, sb = zero;
   const int il = ok ? i : N - 1;
-  sweep_cols<double2, true, KB>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
-  sweep_cols<VT, true, KB>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq, first_col(A.m, wave), J,
-                           il, av, bv, sa, sb);
-  __shared__ double2 ps[2][kUWaves][64];
+  sweep_cols<double2, true, KB, NW>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
+  sweep_cols<VT, true, KB, NW>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
+                               first_col<NW>(A.m, wave), J, il, av, bv, sa, sb);
+  __shared__ double2 ps[2][NW][64];
   ps[0][wave][lane] = sa;
   ps[1][wave][lane] = sb;
-  __shared__ double red[3 * kUThreads];
-  const StepScalars st = step_scalars<kUThreads>(A, r, j, red);  // contains __syncthreads
-  // Hessenberg column J (one row per wavefront over this slot's workgroups)
-  {
-    const int nwaves = nblk * kUWaves;
-    for (int row = blk * kUWaves + wave; row <= J; row += nwaves) hcol_row_wave(A, r, j, row, lane, st);
-    if (blk == 0 && tid == 0) {
-      double* sc = A.sc + (size_t)r * kScStride;
-      sc[kScRho] = st.rho;
-      sc[kScInv] = st.inv;
-      sc[kScGamRe] = st.gam.x;
-      sc[kScGamIm] = st.gam.y;
-      sc[kScGrRe] = st.gr.x;
-      sc[kScGrIm] = st.gr.y;
-      sc[kScScale] = st.scale;
-      // reference size for the next step's breakdown test (the other parity
-      // slot: this step's slot is still being read by other workgroups)
-      sc[kScRef + ((j + 1) & 1)] = st.scale;
-      if (j == 0 && A.beta) A.beta[r] = st.rho;
-      if (A.flag) {
-        int* f = A.flag + r;
-        if (!st.finite)
-          *f = -1;
-        else if (st.brk && *f == 0)
-          *f = j + 1;
-      }
+  load_coef();
+  scalar_partials<NT>(av, bv, J, a0, b0, a1, b1, s0, s12);
+  const StepScalars st = step_scalars<NW>(A, r, j, s0, s12, red);  // contains __syncthreads
+  if (blk == 0 && tid == 0) {
+    double* sc = A.sc + (size_t)r * kScStride;
+    sc[kScRho] = st.rho;
+    sc[kScInv] = st.inv;
+    sc[kScGamRe] = st.gam.x;
+    sc[kScGamIm] = st.gam.y;
+    sc[kScGrRe] = st.gr.x;
+    sc[kScGrIm] = st.gr.y;
+    sc[kScScale] = st.scale;
+    // reference size for the next step's breakdown test (the other parity
+    // slot: this step's slot is still being read by other workgroups)
+    sc[kScRef + ((j + 1) & 1)] = st.scale;
+    if (j == 0 && A.beta) A.beta[r] = st.rho;
+    if (A.flag) {
+      int* f = A.flag + r;
+      if (!st.finite)
+        *f = -1;
+      else if (st.brk && *f == 0)
+        *f = j + 1;
     }
   }
   // combine the wavefronts (fixed order) and write v_J and u'
   if (wave == 0 && ok) {
     double2 ta = ps[0][0][lane], tb = ps[1][0][lane];
 #pragma unroll
-    for (int w = 1; w < kUWaves; ++w) {
+    for (int w = 1; w < NW; ++w) {
       ta = cadd(ta, ps[0][w][lane]);
       tb = cadd(tb, ps[1][w][lane]);
     }
@@ -422,9 +460,9 @@ __global__ void __launch_bounds__(kUThreads) kcombine_kernel(KrylovArgs A, const
   const double2* cf = coef + (size_t)r * cstride;
   double2 acc = make_double2(0.0, 0.0), unused = make_double2(0.0, 0.0);
   const int il = ok ? i : A.N - 1;
-  sweep_cols<double2, false, kCBatch>(A.S, 0, A.ldq, wave, min(ncol, A.m), il, cf, nullptr, acc, unused);
-  sweep_cols<VT, false, kCBatch>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
-                                 first_col(A.m, wave), ncol, il, cf, nullptr, acc, unused);
+  sweep_cols<double2, false, kCBatch, kUWaves>(A.S, 0, A.ldq, wave, min(ncol, A.m), il, cf, nullptr, acc, unused);
+  sweep_cols<VT, false, kCBatch, kUWaves>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
+                                          first_col<kUWaves>(A.m, wave), ncol, il, cf, nullptr, acc, unused);
   __shared__ double2 ps[kUWaves][64];
   ps[wave][lane] = acc;
   __syncthreads();
@@ -519,7 +557,8 @@ static void col_sums(const KrylovArgs& A, double& sum_m, double& sum_k) {
 }
 
 bool krylov_tune_valid(const KrylovTune& t) {
-  return (t.ub == 4 || t.ub == 8 || t.ub == 16) && (t.cpw == 1 || t.cpw == 2 || t.cpw == 4);
+  return (t.ub == 4 || t.ub == 8 || t.ub == 16) && (t.cpw == 1 || t.cpw == 2 || t.cpw == 4) &&
+         (t.uw == 8 || t.uw == 16);
 }
 
 template <typename VT>
@@ -531,13 +570,18 @@ static auto dot_kernel_for(int cpw) {
   }
 }
 
-template <typename VT>
-static auto update_kernel_for(int ub) {
+template <typename VT, int NW>
+static auto update_kernel_nw(int ub) {
   switch (ub) {
-    case 4: return kupdate_kernel<VT, 4>;
-    case 16: return kupdate_kernel<VT, 16>;
-    default: return kupdate_kernel<VT, 8>;
+    case 4: return kupdate_kernel<VT, 4, NW>;
+    case 16: return kupdate_kernel<VT, 16, NW>;
+    default: return kupdate_kernel<VT, 8, NW>;
   }
+}
+
+template <typename VT>
+static auto update_kernel_for(const KrylovTune& t) {
+  return t.uw == 16 ? update_kernel_nw<VT, 16>(t.ub) : update_kernel_nw<VT, 8>(t.ub);
 }
 
 template <typename VT>
@@ -572,8 +616,11 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   check_args(w, A);
   SGN_REQUIRE(A.m + A.jmax() + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
   SGN_REQUIRE(krylov_tune_valid(A.tune), SGN_EINVAL, "krylov: invalid launch shape");
-  const size_t nwg = (size_t)((A.N + 63) / 64) * A.nb;
-  SGN_REQUIRE(nwg * kUThreads < (size_t(1) << 32), SGN_EINVAL, "krylov: update grid too large");
+  // per slot: Hessenberg-row workgroups for rows 0..m+jmax, then the 64-row blocks
+  const int nh = (A.m + A.jmax() + 1 + A.tune.uw - 1) / A.tune.uw;
+  const size_t nwg = ((size_t)((A.N + 63) / 64) + nh) * A.nb;
+  const int nthr = 64 * A.tune.uw;
+  SGN_REQUIRE(nwg * nthr < (size_t(1) << 32), SGN_EINVAL, "krylov: update grid too large");
   const double vb = (double)sizeof(VT);
   double sm, sk;
   col_sums(A, sm, sk);
@@ -581,7 +628,7 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   // read Q, u, z; write v_J, u' (+ its low-precision copy)
   const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
   prof_launch(prof, K_KUPDATE, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk),
-              update_kernel_for<VT>(A.tune.ub), dim3((unsigned)nwg), dim3(kUThreads), 0, s, A);
+              update_kernel_for<VT>(A.tune), dim3((unsigned)nwg), dim3(nthr), 0, s, A, nh);
 }
 
 template <typename VT>
