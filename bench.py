@@ -56,6 +56,7 @@ M_W = -1.6
 M_DEFL = 20
 KMAX = 500
 TOL = 1e-10
+AUTOTUNE_K = 300  # about the k these fields reach at TOL (248-428)
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -69,6 +70,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape of the Arnoldi passes instead of timing the nine")
     ap.add_argument("--no-stencil", action="store_true", help="skip the 32^4 stencil measurement")
     ap.add_argument("--stencil-only", action="store_true",
                     help="only run the 32^4 stencil measurement and print its JSON object")
@@ -105,6 +108,7 @@ def main():
 
     import paper_0704_3486_amd as sg
     import synth
+    from paper_0704_3486_amd.autotune import autotune
 
     if args.stencil_only:
         print(json.dumps(stencil_leg(sg, synth, torch)))
@@ -133,6 +137,10 @@ def main():
         sg.sgn_deflate(ctx, M_DEFL)
         torch.cuda.synchronize()
         setup[str(mu)] = {"seconds": round(time.perf_counter() - t0, 3), **sg.sgn_deflate_stats(ctx)}
+        if not args.no_autotune:
+            # launch shape of the Arnoldi passes (results are bitwise the same for every shape)
+            tuned = autotune(ctx, k=AUTOTUNE_K)
+            setup[str(mu)]["launch_shape"] = [tuned["update_batch"], tuned["dot_cols"]]
         log(f"setup mu={mu}: {setup[str(mu)]}")
         ctxs.append(ctx)
         streams.append(st)

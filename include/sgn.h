@@ -215,6 +215,8 @@ void sgn_session_destroy(sgn_session* s);
  * sign (Roberts) and the assembly of y stay FP64 (always the delayed
  * schedule).  x and y stay complex128 at the ABI. */
 int sgn_set_precision(sgn_ctx* ctx, int prec);
+/* The context's precision (SGN_PREC_*), or SGN_ESTATE for a NULL context. */
+int sgn_get_precision(const sgn_ctx* ctx);
 
 /* Evaluation of sgn of the small composite matrix (step (v)):
  *   SGN_SIGN_SCHULZ (default): inverse-free Newton-Schulz iteration

@@ -99,6 +99,7 @@ def _load():
         "sgn_set_step_graphs": (i, [vp, i]),
         "sgn_get_tuning": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "sgn_set_precision": (i, [vp, i]),
+        "sgn_get_precision": (i, [vp]),
         "sgn_set_schedule": (i, [vp, i, d]),
         "sgn_set_sign_method": (i, [vp, i]),
         "sgn_deflate_stats": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(d)]),
@@ -325,6 +326,12 @@ def sgn_set_precision(ctx, prec):
 
 def sgn_set_schedule(ctx, k_first, tol):
     return _check(ctx, _lib.sgn_set_schedule(ctx, int(k_first), float(tol)))
+
+
+def sgn_get_precision(ctx):
+    p = _lib.sgn_get_precision(ctx)
+    _check(ctx, p if p < 0 else SGN_OK)
+    return p
 
 
 def sgn_set_sign_method(ctx, method):

@@ -687,6 +687,8 @@ int sgn_set_precision(sgn_ctx* c, int prec) {
   });
 }
 
+int sgn_get_precision(const sgn_ctx* c) { return c ? c->prec : SGN_ESTATE; }
+
 int sgn_set_schedule(sgn_ctx* c, int k_first, double tol) {
   return guarded(c, [&] {
     SGN_REQUIRE(k_first >= 0, SGN_EINVAL, "k_first must be >= 0");
