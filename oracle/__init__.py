@@ -18,6 +18,8 @@ Contents, each following the paper (Bloch, Frommer, Lang, Wettig 2007):
                    eq:formula) and the undeflated Arnoldi (Eq. yproj3)
   * deflation   -- partial Schur pair (S_m, T_m) from critical eigenvectors
                    (Eq. pSd), from a dense eigendecomposition or from ARPACK
+  * overlap     -- the overlap operator D_ov(mu) = 1 + gamma5 sgn(H_w(mu))
+                   (Eq. Dov) and its Ginsparg-Wilson defect (Eq. GW:eq)
                    on H_w^2 as in the Results section
 
 Parity status: every function listed above is pinned by the CPU tests in
