@@ -249,6 +249,8 @@ def main():
         stencil_6 = {"workload": "6^4 FP64 (inside the applies)", "achieved": round(gb, 1), "unit": "GB/s",
                      "frac": round(gb / HBM_PEAK_GBPS, 4), "avg_launch_us": kern["wilson_hw"]["avg_us"]}
 
+    ov = overlap_leg(sg, torch, ctxs[1], MUS[1], xs)
+
     pairs = []  # the Schur pairs, for the oracle baseline
     for c in ctxs:
         S, T, _ = sg.sgn_deflate_export(c)
@@ -290,11 +292,46 @@ def main():
         "stencil": stencil,
         "batched_mixed_12x12x12x12": batched,
         "small_sign": sign,
+        "overlap": ov,
         "kernels": kern,
         "profiled_pass_seconds": round(elapsed_prof, 4),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def overlap_leg(sg, torch, ctx, mu, xs, reps=10):
+    """D_ov(mu) x = x + gamma5 sgn(H_w(mu)) x on one 6^4 field: the error on
+    the source with a stored exact sign, the Ginsparg-Wilson defect
+    ||D g5 D x - (g5 D x + D g5 x)|| / ||x|| from three applies, and the rate
+    of one apply at a time."""
+    N = xs[0].numel()
+    g5 = torch.from_numpy(np.tile(np.repeat([1.0, 1.0, -1.0, -1.0], 3), N // 12)).to(xs[0].device)
+    y = torch.empty_like(xs[0])
+    out = {"workload": f"6^4, mu={mu}, m={M_DEFL}, tol={TOL}, FP64, 1 RHS per apply, one at a time"}
+    path = os.path.join(GOLDEN, f"c6_mu{mu}.npy")
+    sg.sgn_overlap_apply(ctx, xs[0], y, TOL, KMAX)
+    if os.path.exists(path):
+        x0 = xs[0].cpu().numpy()
+        exact = x0 + g5.cpu().numpy() * np.load(path, allow_pickle=False)
+        out["rel_err_vs_exact"] = float(np.linalg.norm(y.cpu().numpy() - exact) / np.linalg.norm(exact))
+
+    def D(v):
+        w = torch.empty_like(v)
+        sg.sgn_overlap_apply(ctx, v.contiguous(), w, TOL, KMAX)
+        return w
+
+    dx = D(xs[1])
+    defect = (D(g5 * dx) - g5 * dx - D(g5 * xs[1])).norm() / xs[1].norm()
+    out["gw_defect"] = float(defect)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        sg.sgn_overlap_apply(ctx, xs[r % len(xs)], y, TOL, KMAX)
+    torch.cuda.synchronize()
+    out["applies_per_s_one_at_a_time"] = round(reps / (time.perf_counter() - t0), 3)
+    log(f"overlap: {out}")
+    return out
 
 
 def kernel_table(kstats):

@@ -170,6 +170,17 @@ int sgn_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double
 /* Batched counterpart of sgn_apply_fixed: exactly k steps per source. */
 int sgn_apply_batched_fixed(sgn_ctx* ctx, int nrhs, const double* X, double* Y, int k, sgn_info* info);
 
+/* The overlap Dirac operator at nonzero chemical potential (Section 2, Eq.
+ * Dov): y = D_ov(mu) x = x + gamma5 sgn(H_w(mu)) x, gamma5 = diag(1, 1, -1,
+ * -1) in spin.  The sign is applied exactly as by sgn_apply (same tol, kmax,
+ * status, sgn_last_info); the batched form as by sgn_apply_batched, with
+ * the same info array.  x, y (X, Y: nrhs x N): device complex128 in the
+ * interface layout; they must not overlap (SGN_EINVAL), since x is read
+ * again after the sign is formed.  Complete on return. */
+int sgn_overlap_apply(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
+int sgn_overlap_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double tol, int kmax,
+                              sgn_info* info);
+
 /* ---- serving: continuous batching on one resident field ---------------- */
 
 /* A session keeps up to max_slots (1..64) requests of one context in flight,

@@ -79,6 +79,8 @@ def _load():
         "sgn_apply": (i, [vp, vp, vp, d, i]),
         "sgn_apply_fixed": (i, [vp, vp, vp, i]),
         "sgn_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
+        "sgn_overlap_apply": (i, [vp, vp, vp, d, i]),
+        "sgn_overlap_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
         "sgn_session_create": (vp, [vp, i, i]),
         "sgn_session_submit": (i, [vp, vp, vp, d, i, C.POINTER(C.c_int)]),
         "sgn_session_step": (i, [vp, i]),
@@ -256,6 +258,23 @@ def sgn_apply_batched(ctx, X, Y, tol, kmax):
     infos = (sgn_info * nrhs)()
     st = _lib.sgn_apply_batched(ctx, int(nrhs), _dptr(X, nrhs * N, "X"), _dptr(Y, nrhs * N, "Y"), float(tol),
                                 int(kmax), infos)
+    return _check(ctx, st, soft=(SGN_ENOCONV,)), [infos[r].as_dict() for r in range(nrhs)]
+
+
+def sgn_overlap_apply(ctx, x, y, tol, kmax):
+    """y = D_ov(mu) x = x + gamma5 sgn(H_w(mu)) x; returns SGN_OK or SGN_ENOCONV (soft)."""
+    _, N = sgn_get_dims(ctx)
+    st = _lib.sgn_overlap_apply(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), float(tol), int(kmax))
+    return _check(ctx, st, soft=(SGN_ENOCONV,))
+
+
+def sgn_overlap_apply_batched(ctx, X, Y, tol, kmax):
+    """Y[r] = D_ov(mu) X[r]; returns (status, [info dict per source])."""
+    _, N = sgn_get_dims(ctx)
+    nrhs = X.shape[0] if X.dim() == 2 else X.numel() // N
+    infos = (sgn_info * nrhs)()
+    st = _lib.sgn_overlap_apply_batched(ctx, int(nrhs), _dptr(X, nrhs * N, "X"), _dptr(Y, nrhs * N, "Y"),
+                                        float(tol), int(kmax), infos)
     return _check(ctx, st, soft=(SGN_ENOCONV,)), [infos[r].as_dict() for r in range(nrhs)]
 
 

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -640,6 +641,26 @@ int sgn_apply(sgn_ctx* c, const double* x, double* y, double tol, int kmax) {
     SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
     SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
     return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), tol, kmax, -1);
+  });
+}
+
+// [a, a + n) and [b, b + n) (complex entries) share memory
+static bool overlapping(const double* a, const double* b, size_t n) {
+  const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  const uintptr_t len = n * sizeof(double2);
+  return pa < pb + len && pb < pa + len;
+}
+
+int sgn_overlap_apply(sgn_ctx* c, const double* x, double* y, double tol, int kmax) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
+    SGN_REQUIRE(!overlapping(x, y, (size_t)c->N), SGN_EINVAL, "x and y must not overlap");
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    const int st = run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), tol, kmax, -1);
+    overlap_finish(reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), (size_t)c->N, c->stream);
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    return st;
   });
 }
 

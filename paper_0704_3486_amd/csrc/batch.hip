@@ -377,6 +377,23 @@ int sgn_apply_batched(sgn_ctx* c, int nrhs, const double* X, double* Y, double t
   });
 }
 
+int sgn_overlap_apply_batched(sgn_ctx* c, int nrhs, const double* X, double* Y, double tol, int kmax,
+                              sgn_info* info) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    SGN_REQUIRE(X && Y && nrhs >= 1, SGN_EINVAL, "X and Y must not be NULL and nrhs >= 1");
+    const size_t n = (size_t)nrhs * c->N;
+    const auto px = reinterpret_cast<uintptr_t>(X), py = reinterpret_cast<uintptr_t>(Y);
+    SGN_REQUIRE(px + n * sizeof(double2) <= py || py + n * sizeof(double2) <= px, SGN_EINVAL,
+                "X and Y must not overlap");
+    const int st = batched_entry(c, nrhs, X, Y, tol, kmax, -1, info);
+    overlap_finish(reinterpret_cast<const double2*>(X), reinterpret_cast<double2*>(Y), n, c->stream);
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    return st;
+  });
+}
+
 int sgn_apply_batched_fixed(sgn_ctx* c, int nrhs, const double* X, double* Y, int k, sgn_info* info) {
   return guarded(c, [&] {
     SGN_REQUIRE(k >= 0 && k <= c->N, SGN_EINVAL, "k must satisfy 0 <= k <= N");

@@ -155,6 +155,8 @@ struct Lattice {
 void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, hipStream_t s);
 void wilson_pack(const Lattice& lat, const double2* x_abi, double2* v, hipStream_t s);
 void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStream_t s);
+// y = x + gamma5 y over n entries in the interface layout (n a multiple of 12)
+void overlap_finish(const double2* x, double2* y, size_t n, hipStream_t s);
 // out = H_w(mu) (in * scale), optional copy_out = in * scale; scale = *inv_beta (or 1 if null)
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);

@@ -405,6 +405,21 @@ void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStre
   SGN_HIP(hipGetLastError());
 }
 
+// y = x + gamma5 y in the interface layout (component 12 n + 3 spin + colour;
+// gamma5 = diag(1, 1, -1, -1) in spin): the last step of D_ov(mu) x
+__global__ void overlap_finish_kernel(const double2* __restrict__ x, double2* __restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 xi = x[i], si = y[i];
+  y[i] = (i % 12 < 6) ? make_double2(xi.x + si.x, xi.y + si.y) : make_double2(xi.x - si.x, xi.y - si.y);
+}
+
+void overlap_finish(const double2* x, double2* y, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(overlap_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+  SGN_HIP(hipGetLastError());
+}
+
 // the blocked order when the lattice is large enough to leave L2 and its
 // extents admit the blocks (Lx By a multiple of the workgroup's 16 sites)
 static SiteOrder site_order(const Lattice& lat) {
