@@ -136,8 +136,32 @@ int sgn_deflate_import(sgn_ctx* ctx, int m, const double* S, const double* T);
  * evals to host (m complex = diag T).  Any pointer may be NULL. */
 int sgn_deflate_export(const sgn_ctx* ctx, double* S, double* T, double* evals);
 
-/* Number of installed deflation vectors (0 if none, <0 on error). */
+/* Number of installed deflation vectors, Schur or LR (0 if none, <0 on error). */
 int sgn_deflation_size(const sgn_ctx* ctx);
+
+/* LR-deflation (the LR-deflation subsection; Eqs. Rev, Lev, xdec, fARLx,
+ * LRArnoldi, fAxLRArn): with right eigenvectors R (A R = R Lambda) and left
+ * eigenvectors L (L^dag A = Lambda L^dag) of the m critical eigenvalues,
+ * L^dag R = I, an apply computes R sgn(Lambda) L^dag x + beta V_k sgn(H_k) e1
+ * with the plain Arnoldi method on x_- = (1 - R L^dag) x (no projection
+ * inside the Krylov steps).  An LR pair replaces any Schur pair and vice
+ * versa; sgn_apply, sgn_apply_fixed and sgn_overlap_apply use it, batched
+ * applies and sessions return SGN_ESTATE while it is installed.
+ * sgn_deflate_lr computes it on the device: the critical Schur pairs of
+ * H_w(mu) and of H_w(-mu) = H_w(mu)^dag (same method as sgn_deflate; its
+ * left eigenvectors are the right ones of H_w(-mu) for conj(lambda)), their
+ * eigenvectors, paired by eigenvalue and rescaled to L^dag R = I
+ * (SGN_EDEFL if the eigenvalues do not pair up or L^dag R deviates from I by
+ * more than 1e-8); 1 <= m <= N/4.  sgn_deflate_lr_import takes R and L
+ * (device, interface layout, N x m column-major) and the eigenvalues (host,
+ * m complex); SGN_EINVAL unless L^dag R = I to 1e-8.  sgn_deflate_lr_export
+ * copies them out (any pointer may be NULL; SGN_ESTATE without an LR pair).
+ * sgn_deflation_mode: SGN_DEFL_NONE, SGN_DEFL_SCHUR or SGN_DEFL_LR. */
+enum { SGN_DEFL_NONE = 0, SGN_DEFL_SCHUR = 1, SGN_DEFL_LR = 2 };
+int sgn_deflate_lr(sgn_ctx* ctx, int m);
+int sgn_deflate_lr_import(sgn_ctx* ctx, int m, const double* R, const double* L, const double* lam);
+int sgn_deflate_lr_export(const sgn_ctx* ctx, double* R, double* L, double* lam);
+int sgn_deflation_mode(const sgn_ctx* ctx);
 
 /* ---- the hot path (Section 5.2, steps (iii)-(vi)) ---------------------- */
 

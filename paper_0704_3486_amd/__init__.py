@@ -29,6 +29,9 @@ SGN_ENOCONV = -4
 SGN_ESINGULAR = -5
 SGN_ESTATE = -6
 SGN_EDEFL = -7
+SGN_DEFL_NONE = 0
+SGN_DEFL_SCHUR = 1
+SGN_DEFL_LR = 2
 SGN_SIGN_SCHULZ = 0
 SGN_SIGN_ROBERTS = 1
 SGN_ORTH_CGS2 = 0
@@ -96,6 +99,10 @@ def _load():
         "sgn_profile_read": (i, [vp, C.POINTER(sgn_kstat), i]),
         "sgn_profile_reset": (i, [vp]),
         "sgn_deflate": (i, [vp, i]),
+        "sgn_deflate_lr": (i, [vp, i]),
+        "sgn_deflate_lr_import": (i, [vp, i, vp, vp, vp]),
+        "sgn_deflate_lr_export": (i, [vp, vp, vp, vp]),
+        "sgn_deflation_mode": (i, [vp]),
         "sgn_set_orthogonalization": (i, [vp, i]),
         "sgn_set_tuning": (i, [vp, i, i, i]),
         "sgn_set_step_graphs": (i, [vp, i]),
@@ -236,6 +243,53 @@ def sgn_deflate_export(ctx):
 
 def sgn_deflation_size(ctx):
     return _lib.sgn_deflation_size(ctx)
+
+
+def sgn_deflation_mode(ctx):
+    """SGN_DEFL_NONE, SGN_DEFL_SCHUR or SGN_DEFL_LR."""
+    mode = _lib.sgn_deflation_mode(ctx)
+    _check(ctx, mode if mode < 0 else SGN_OK)
+    return mode
+
+
+def sgn_deflate_lr(ctx, m):
+    """LR-deflation pair (right and left critical eigenvectors) computed on the device."""
+    return _check(ctx, _lib.sgn_deflate_lr(ctx, int(m)))
+
+
+def sgn_deflate_lr_import(ctx, R, L, lam):
+    """Install R, L (N x m complex128 device tensors, interface layout, L^dag R = I)
+    and the eigenvalues lam (m complex, host)."""
+    import torch
+
+    _, N = sgn_get_dims(ctx)
+    m = int(R.shape[1])
+    if R.shape != (N, m) or L.shape != (N, m):
+        raise ValueError("R and L must have shape (N, m)")
+    Rc = R.t().contiguous()  # column-major N x m = row-major m x N
+    Lc = L.t().contiguous()
+    lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128).ravel())
+    if lam.size != m:
+        raise ValueError("lam must have m entries")
+    torch.cuda.synchronize()  # the library reads Rc, Lc on the context's stream
+    return _check(ctx, _lib.sgn_deflate_lr_import(ctx, m, _dptr(Rc, N * m, "R"), _dptr(Lc, N * m, "L"),
+                                                  lam.ctypes.data_as(C.c_void_p)))
+
+
+def sgn_deflate_lr_export(ctx):
+    """(R, L, lam): R, L device tensors N x m, lam numpy (m,)."""
+    import torch
+
+    _, N = sgn_get_dims(ctx)
+    m = sgn_deflation_size(ctx)
+    if sgn_deflation_mode(ctx) != SGN_DEFL_LR:
+        raise SgnError(SGN_ESTATE, "no LR-deflation pair installed")
+    R = torch.empty(m, N, dtype=torch.complex128, device="cuda")
+    L = torch.empty(m, N, dtype=torch.complex128, device="cuda")
+    lam = np.zeros(m, dtype=np.complex128)
+    _check(ctx, _lib.sgn_deflate_lr_export(ctx, _dptr(R, N * m, "R"), _dptr(L, N * m, "L"),
+                                           lam.ctypes.data_as(C.c_void_p)))
+    return R.t(), L.t(), lam
 
 
 def sgn_apply(ctx, x, y, tol, kmax):

@@ -231,6 +231,12 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   wilson_pack(c->lat, x_abi, c->xin, s);
   dev_check_finite(c->xin, (size_t)N, c->flag + 1, s);
   SGN_HIP(hipMemcpyAsync(c->wA, c->xin, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+  const int lrm = c->lr_m;
+  if (lrm > 0) {
+    // LR-deflation, step (iii): L^dag x, and x_- = (1 - R L^dag) x in place of x
+    gs_dot(c->gs, c->lrL, ldq, N, lrm, c->wA, c->lrC, s, prof);
+    gs_update(c->gs, c->lrR, ldq, N, lrm, c->lrC, c->wA, nullptr, 0, s, prof);
+  }
   if (delayed) {
     // one pass against S now; its re-orthogonalisation is folded into step 0
     gs_norm(c->gs, N, c->xin, &c->scal[5], &c->scal[6], nullptr, s, prof);
@@ -429,6 +435,11 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   } else {
     gs_combine(c->gs, c->Q, ldq, N, n, c->cvec, c->wB, nullptr, s, prof);
   }
+  if (lrm > 0) {
+    // LR-deflation, step (vi): y += R sgn(Lambda) L^dag x
+    dev_cmul(c->lrSgn, c->lrC, lrm, s);
+    gs_add(c->gs, c->lrR, ldq, N, lrm, c->lrC, c->wB, s, prof);
+  }
   wilson_unpack(c->lat, c->wB, y_abi, s);
   SGN_HIP(hipMemcpyAsync(&c->hpin[6], &c->scal[0], sizeof(double), hipMemcpyDeviceToHost, s));
   SGN_HIP(hipStreamSynchronize(s));
@@ -467,7 +478,8 @@ void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std:
     SGN_REQUIRE(std::isfinite(d.x) && std::isfinite(d.y), SGN_EINVAL, "T has a non-finite diagonal");
     SGN_REQUIRE(d.x != 0.0, SGN_ESINGULAR, "T has an eigenvalue on the imaginary axis");
   }
-  // drop the old basis and the workspaces (their layout depends on m)
+  // drop the old basis (Schur or LR) and the workspaces (their layout depends on m)
+  c->drop_lr();
   c->release_workspace();
   c->bw.release();
   c->bw.k_hint = 0;
@@ -491,6 +503,38 @@ void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std:
   c->m = m;
   c->k_hint = 0;
   c->rate_hint = 0.0;
+}
+
+// Install an LR-deflation pair (the LR-deflation subsection, steps (i)-(ii)):
+// right and left eigenvectors in the internal layout (device, ldq x m) with
+// L^dag R = I, and the eigenvalues (host).  Replaces any Schur pair (m = 0
+// for the Krylov part).
+void install_lr_pair(sgn_ctx* c, int m, const double2* R_internal, const double2* L_internal,
+                     const std::vector<double2>& lam) {
+  install_schur_pair(c, 0, nullptr, {});
+  if (m == 0) return;
+  hipStream_t s = c->stream;
+  std::vector<double2> sg((size_t)m);
+  for (int i = 0; i < m; ++i) {
+    SGN_REQUIRE(std::isfinite(lam[i].x) && std::isfinite(lam[i].y), SGN_EINVAL, "non-finite eigenvalue");
+    SGN_REQUIRE(lam[i].x != 0.0, SGN_ESINGULAR, "an eigenvalue lies on the imaginary axis");
+    sg[i] = make_double2(lam[i].x > 0.0 ? 1.0 : -1.0, 0.0);  // step (ii): sgn(lambda_i) = sgn(Re lambda_i)
+  }
+  try {
+    SGN_HIP(hipMalloc(&c->lrR, sizeof(double2) * c->ldq * (size_t)m));
+    SGN_HIP(hipMalloc(&c->lrL, sizeof(double2) * c->ldq * (size_t)m));
+    SGN_HIP(hipMalloc(&c->lrSgn, sizeof(double2) * (size_t)m));
+    SGN_HIP(hipMalloc(&c->lrC, sizeof(double2) * (size_t)m));
+    SGN_HIP(hipMemcpyAsync(c->lrR, R_internal, sizeof(double2) * c->ldq * (size_t)m, hipMemcpyDeviceToDevice, s));
+    SGN_HIP(hipMemcpyAsync(c->lrL, L_internal, sizeof(double2) * c->ldq * (size_t)m, hipMemcpyDeviceToDevice, s));
+    SGN_HIP(hipMemcpyAsync(c->lrSgn, sg.data(), sizeof(double2) * (size_t)m, hipMemcpyHostToDevice, s));
+    SGN_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    c->drop_lr();
+    throw;
+  }
+  c->lrLam = lam;
+  c->lr_m = m;
 }
 
 // ---------------------------------------------------------------------------
@@ -589,7 +633,80 @@ int sgn_get_dims(const sgn_ctx* c, int dims[4], long long* n) {
   return SGN_OK;
 }
 
-int sgn_deflation_size(const sgn_ctx* c) { return c ? c->m : SGN_ESTATE; }
+int sgn_deflation_size(const sgn_ctx* c) { return c ? (c->lr_m > 0 ? c->lr_m : c->m) : SGN_ESTATE; }
+
+int sgn_deflation_mode(const sgn_ctx* c) {
+  if (!c) return SGN_ESTATE;
+  return c->lr_m > 0 ? SGN_DEFL_LR : (c->m > 0 ? SGN_DEFL_SCHUR : SGN_DEFL_NONE);
+}
+
+int sgn_deflate_lr_import(sgn_ctx* c, int m, const double* R_abi, const double* L_abi, const double* lam_host) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(m >= 1 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 1 <= m <= N/4");
+    SGN_REQUIRE(R_abi && L_abi && lam_host, SGN_EINVAL, "R, L and lam must not be NULL");
+    SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session holds this field's deflation");
+    hipStream_t s = c->stream;
+    const size_t ldq = c->ldq;
+    std::vector<double2> lam((size_t)m);
+    std::memcpy(lam.data(), lam_host, sizeof(double2) * (size_t)m);
+    double2 *Rint = nullptr, *Lint = nullptr, *G = nullptr;
+    GsWork g;
+    try {
+      SGN_HIP(hipMalloc(&Rint, sizeof(double2) * ldq * (size_t)m));
+      SGN_HIP(hipMalloc(&Lint, sizeof(double2) * ldq * (size_t)m));
+      SGN_HIP(hipMalloc(&G, sizeof(double2) * (size_t)m * m));
+      SGN_HIP(hipMemsetAsync(Rint, 0, sizeof(double2) * ldq * (size_t)m, s));
+      SGN_HIP(hipMemsetAsync(Lint, 0, sizeof(double2) * ldq * (size_t)m, s));
+      for (int j = 0; j < m; ++j) {
+        wilson_pack(c->lat, reinterpret_cast<const double2*>(R_abi) + (size_t)j * c->N, Rint + (size_t)j * ldq, s);
+        wilson_pack(c->lat, reinterpret_cast<const double2*>(L_abi) + (size_t)j * c->N, Lint + (size_t)j * ldq, s);
+      }
+      // L^dag R = I is required (the oblique projector R L^dag)
+      gs_alloc(g, c->N, ldq, m);
+      for (int j = 0; j < m; ++j) gs_dot(g, Lint, ldq, c->N, m, Rint + (size_t)j * ldq, G + (size_t)j * m, s, nullptr);
+      std::vector<double2> Gh((size_t)m * m);
+      SGN_HIP(hipMemcpyAsync(Gh.data(), G, sizeof(double2) * Gh.size(), hipMemcpyDeviceToHost, s));
+      SGN_HIP(hipStreamSynchronize(s));
+      double dev = 0.0;
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+          const double2 e = Gh[(size_t)j * m + i];
+          dev = std::max(dev, std::hypot(e.x - (i == j ? 1.0 : 0.0), e.y));
+        }
+      SGN_REQUIRE(std::isfinite(dev) && dev <= 1e-8, SGN_EINVAL, "L^dag R must equal I (deviation " +
+                                                                     std::to_string(dev) + ")");
+      install_lr_pair(c, m, Rint, Lint, lam);
+    } catch (...) {
+      gs_free(g);
+      for (double2* p : {Rint, Lint, G})
+        if (p) (void)hipFree(p);
+      throw;
+    }
+    gs_free(g);
+    for (double2* p : {Rint, Lint, G})
+      if (p) SGN_HIP(hipFree(p));
+    return SGN_OK;
+  });
+}
+
+int sgn_deflate_lr_export(const sgn_ctx* cc, double* R_abi, double* L_abi, double* lam_host) {
+  sgn_ctx* c = const_cast<sgn_ctx*>(cc);
+  return guarded(c, [&] {
+    const int m = c->lr_m;
+    SGN_REQUIRE(m > 0, SGN_ESTATE, "no LR-deflation pair installed");
+    for (int j = 0; j < m; ++j) {
+      if (R_abi)
+        wilson_unpack(c->lat, c->lrR + (size_t)j * c->ldq, reinterpret_cast<double2*>(R_abi) + (size_t)j * c->N,
+                      c->stream);
+      if (L_abi)
+        wilson_unpack(c->lat, c->lrL + (size_t)j * c->ldq, reinterpret_cast<double2*>(L_abi) + (size_t)j * c->N,
+                      c->stream);
+    }
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    if (lam_host) std::memcpy(lam_host, c->lrLam.data(), sizeof(double2) * (size_t)m);
+    return SGN_OK;
+  });
+}
 
 int sgn_deflate_import(sgn_ctx* c, int m, const double* S_abi, const double* T_host) {
   return guarded(c, [&] {

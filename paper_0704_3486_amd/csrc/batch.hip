@@ -353,6 +353,7 @@ int batched_entry(sgn_ctx* c, int nrhs, const double* X, double* Y, double tol, 
                   sgn_info* info) {
   SGN_REQUIRE(nrhs >= 1, SGN_EINVAL, "nrhs must be positive");
   SGN_REQUIRE(X && Y, SGN_EINVAL, "X and Y must not be NULL");
+  SGN_REQUIRE(c->lr_m == 0, SGN_ESTATE, "an LR-deflation pair is installed: batched applies use a Schur pair");
   const double2* Xc = reinterpret_cast<const double2*>(X);
   double2* Yc = reinterpret_cast<double2*>(Y);
   int status = SGN_OK;

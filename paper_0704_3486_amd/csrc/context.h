@@ -90,6 +90,16 @@ struct sgn_ctx {
   std::vector<double2> T;     // host m x m (column-major, upper triangular)
   double2* Tdev = nullptr;    // m x m
   double2* sgnT = nullptr;    // m x m
+  // LR-deflation pair, installed in place of a Schur pair (then m = 0 and
+  // the Krylov part is the plain Arnoldi method): right and left critical
+  // eigenvectors in the internal layout (ldq x lr_m, L^dag R = I), sgn of
+  // their eigenvalues, and the per-apply coefficients L^dag x
+  int lr_m = 0;
+  double2* lrR = nullptr;
+  double2* lrL = nullptr;
+  double2* lrSgn = nullptr;       // lr_m entries (sgn Re lambda_i, 0)
+  double2* lrC = nullptr;         // lr_m entries
+  std::vector<double2> lrLam;     // host eigenvalues
 
   // Krylov workspace
   int kcap = 0;               // capacity in Krylov vectors
@@ -158,6 +168,16 @@ struct sgn_ctx {
     ncap = 0;
   }
 
+  void drop_lr() {
+    for (double2** p : {&lrR, &lrL, &lrSgn, &lrC})
+      if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+      }
+    lrLam.clear();
+    lr_m = 0;
+  }
+
   void drop_graphs() {
     for (hipGraphExec_t& g : graphs)
       if (g) (void)hipGraphExecDestroy(g);
@@ -169,6 +189,7 @@ struct sgn_ctx {
     release_workspace();
     dense_destroy(dense);
     bw.release();
+    drop_lr();
     for (double2** p : {&links, &S, &Tdev, &sgnT})
       if (*p) {
         (void)hipFree(*p);
@@ -214,7 +235,7 @@ struct sgn_ctx {
     SGN_HIP(hipMalloc(&cvec, sizeof(double2) * (size_t)ncap));
     SGN_HIP(hipMalloc(&cprev, sizeof(double2) * (size_t)ncap));
     SGN_HIP(hipMalloc(&jdev, sizeof(int)));
-    gs_alloc(gs, N, ldq, ncap);
+    gs_alloc(gs, N, ldq, std::max(ncap, lr_m));
     krylov_alloc(kw, N, ldq, ncap, 1);
     dense_reserve(dense, m + kcap, 1);
     // the Schur block of Q and of H never changes between applies
@@ -252,3 +273,7 @@ inline int guarded(sgn_ctx* c, F&& f) {
 // Install a partial Schur pair (S in the internal layout, device, ldq x m;
 // T host column-major m x m, upper triangular) and compute sgn(T) on the device.
 void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std::vector<double2>& T);
+// Install an LR-deflation pair (R, L internal layout ldq x m, L^dag R = I;
+// eigenvalues on the host) in place of any Schur pair.
+void install_lr_pair(sgn_ctx* c, int m, const double2* R_internal, const double2* L_internal,
+                     const std::vector<double2>& lam);

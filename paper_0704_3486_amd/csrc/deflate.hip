@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <random>
 
@@ -80,8 +81,11 @@ struct DeflateStats {
   double lower = 0.0;     // ||tril(T, -1)||_F before it is dropped
 };
 
+// The critical Schur pair of the context's operator: S (device, internal
+// layout, ldq x m) and T (host, m x m column-major, upper triangular).
 static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_restarts, double tol,
-                                unsigned long long seed) {
+                                unsigned long long seed, std::unique_ptr<DevBuf>& S_out,
+                                std::vector<double2>& T_out) {
   hipStream_t s = c->stream;
   const int N = c->N;
   const size_t ldq = c->ldq;
@@ -281,8 +285,8 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
   st.lower = std::sqrt(low);
 
   // S = Z Rq (device, internal layout) and the residual ||A S - S T||_F
-  DevBuf bS(sizeof(double2) * ldq * (size_t)m);
-  double2* Sd = bS.as<double2>();
+  auto bS = std::make_unique<DevBuf>(sizeof(double2) * ldq * (size_t)m);
+  double2* Sd = bS->as<double2>();
   SGN_HIP(hipMemsetAsync(Sd, 0, sizeof(double2) * ldq * (size_t)m, s));
   std::vector<double2> cf((size_t)nev * m), cf2((size_t)m * m);
   for (size_t e = 0; e < cf.size(); ++e) cf[e] = to_d2(Rq[e]);
@@ -308,10 +312,68 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
   st.residual = std::sqrt(res2) / anorm;
   SGN_REQUIRE(st.residual <= 1e-10, SGN_EDEFL,
               "deflation basis not accurate enough: ||AS - ST||_F / ||A|| = " + std::to_string(st.residual));
-  std::vector<double2> Th(Tkeep);
-  install_schur_pair(c, m, Sd, Th);
+  S_out = std::move(bS);
+  T_out = std::move(Tkeep);
   return st;
 }
+
+namespace {
+
+// in-place inverse of a column-major n x n complex matrix (Gauss-Jordan with
+// partial pivoting); false if singular
+bool invert(int n, std::vector<cplx>& A) {
+  std::vector<int> piv(n);
+  std::vector<cplx> I((size_t)n * n, cplx(0.0, 0.0));
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  auto at = [n](std::vector<cplx>& M, int r, int c) -> cplx& { return M[(size_t)c * n + r]; };
+  for (int col = 0; col < n; ++col) {
+    int p = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::abs(at(A, r, col)) > std::abs(at(A, p, col))) p = r;
+    if (std::abs(at(A, p, col)) == 0.0) return false;
+    if (p != col)
+      for (int c2 = 0; c2 < n; ++c2) {
+        std::swap(at(A, p, c2), at(A, col, c2));
+        std::swap(at(I, p, c2), at(I, col, c2));
+      }
+    const cplx d = 1.0 / at(A, col, col);
+    for (int c2 = 0; c2 < n; ++c2) {
+      at(A, col, c2) *= d;
+      at(I, col, c2) *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const cplx f = at(A, r, col);
+      if (f == cplx(0.0, 0.0)) continue;
+      for (int c2 = 0; c2 < n; ++c2) {
+        at(A, r, c2) -= f * at(A, col, c2);
+        at(I, r, c2) -= f * at(I, col, c2);
+      }
+    }
+  }
+  A.swap(I);
+  return true;
+}
+
+// eigenvalues and eigenvectors (columns) of a host m x m column-major matrix
+void host_eigvecs(int m, const std::vector<double2>& T, std::vector<cplx>& lam, std::vector<cplx>& W) {
+  std::vector<cplx> A((size_t)m * m);
+  for (size_t e = 0; e < A.size(); ++e) A[e] = to_c(T[e]);
+  lam.assign(m, cplx(0.0, 0.0));
+  W.assign((size_t)m * m, cplx(0.0, 0.0));
+  SGN_REQUIRE(hostla::eig(m, A.data(), lam.data(), W.data()), SGN_EDEFL,
+              "LR deflation: eigenproblem of T did not converge");
+}
+
+// the time-hop factors e^{+mu}, e^{-mu} exchanged while alive: the operator
+// becomes H_w(-mu) = H_w(mu)^dag
+struct MinusMu {
+  Lattice& lat;
+  explicit MinusMu(Lattice& l) : lat(l) { std::swap(lat.emu, lat.emmu); }
+  ~MinusMu() { std::swap(lat.emu, lat.emmu); }
+};
+
+}  // namespace
 
 extern "C" int sgn_deflate(sgn_ctx* c, int m) {
   return guarded(c, [&] {
@@ -324,7 +386,10 @@ extern "C" int sgn_deflate(sgn_ctx* c, int m) {
     const int nev = std::min(m + std::max(10, m / 2), c->N / 2);
     const int ncv = std::min(std::max(3 * nev, nev + 40), c->N - 1);
     SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
-    const DeflateStats st = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull);
+    std::unique_ptr<DevBuf> S;
+    std::vector<double2> T;
+    const DeflateStats st = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull, S, T);
+    install_schur_pair(c, m, S->as<double2>(), T);
     c->defl_restarts = st.restarts;
     c->defl_matvecs = st.matvecs;
     c->defl_residual = st.residual;
@@ -338,4 +403,103 @@ extern "C" int sgn_deflate_stats(const sgn_ctx* c, int* restarts, int* matvecs, 
   if (matvecs) *matvecs = c->defl_matvecs;
   if (residual) *residual = c->defl_residual;
   return SGN_OK;
+}
+
+// LR-deflation setup (the LR-deflation subsection, steps (i)-(ii)): right
+// eigenvectors R = S W of the critical Schur pair of H_w(mu) (T W = W Lambda),
+// left eigenvectors from the critical Schur pair of H_w(-mu) = H_w(mu)^dag
+// (a left eigenvector of H_w(mu) for lambda is a right eigenvector of
+// H_w(-mu) for conj(lambda)), paired by eigenvalue and rescaled to
+// L^dag R = I.
+extern "C" int sgn_deflate_lr(sgn_ctx* c, int m) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(m >= 1 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 1 <= m <= N/4");
+    SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session holds this field's deflation");
+    const int nev = std::min(m + std::max(10, m / 2), c->N / 2);
+    const int ncv = std::min(std::max(3 * nev, nev + 40), c->N - 1);
+    SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
+    hipStream_t s = c->stream;
+    const size_t ldq = c->ldq;
+    const int N = c->N;
+    std::unique_ptr<DevBuf> S1, S2;
+    std::vector<double2> T1, T2;
+    const DeflateStats st1 = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull, S1, T1);
+    DeflateStats st2;
+    {
+      MinusMu flip(c->lat);
+      st2 = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull, S2, T2);
+    }
+    std::vector<cplx> lam1, W1, lam2, W2;
+    host_eigvecs(m, T1, lam1, W1);
+    host_eigvecs(m, T2, lam2, W2);
+    // pair lambda_i with the eigenvalue conj(lambda_i) of H_w(-mu)
+    std::vector<int> perm(m, -1);
+    std::vector<char> used(m, 0);
+    for (int i = 0; i < m; ++i) {
+      int best = -1;
+      double bd = 0.0;
+      for (int j = 0; j < m; ++j) {
+        const double d = std::abs(lam2[j] - std::conj(lam1[i]));
+        if (!used[j] && (best < 0 || d < bd)) best = j, bd = d;
+      }
+      SGN_REQUIRE(best >= 0 && bd <= 1e-8 * std::max(1.0, std::abs(lam1[i])), SGN_EDEFL,
+                  "LR deflation: the critical eigenvalues of H_w(mu) and H_w(-mu) do not pair up");
+      used[best] = 1;
+      perm[i] = best;
+    }
+    GsWork g;
+    gs_alloc(g, N, ldq, m);
+    struct GsGuard {
+      GsWork& g;
+      ~GsGuard() { gs_free(g); }
+    } guard{g};
+    DevBuf bR(sizeof(double2) * ldq * (size_t)m), bL0(sizeof(double2) * ldq * (size_t)m),
+        bL(sizeof(double2) * ldq * (size_t)m), bcoef(sizeof(double2) * (size_t)m * m);
+    double2* R = bR.as<double2>();
+    double2* L0 = bL0.as<double2>();
+    double2* L = bL.as<double2>();
+    double2* coef = bcoef.as<double2>();
+    SGN_HIP(hipMemsetAsync(R, 0, sizeof(double2) * ldq * (size_t)m, s));
+    SGN_HIP(hipMemsetAsync(L0, 0, sizeof(double2) * ldq * (size_t)m, s));
+    SGN_HIP(hipMemsetAsync(L, 0, sizeof(double2) * ldq * (size_t)m, s));
+    std::vector<double2> hc((size_t)m * m);
+    auto combine = [&](const double2* Q, const std::vector<cplx>& C, double2* out) {
+      for (size_t e = 0; e < hc.size(); ++e) hc[e] = to_d2(C[e]);
+      SGN_HIP(hipMemcpyAsync(coef, hc.data(), sizeof(double2) * hc.size(), hipMemcpyHostToDevice, s));
+      for (int j = 0; j < m; ++j) gs_combine(g, Q, ldq, N, m, coef + (size_t)j * m, out + (size_t)j * ldq, nullptr, s, nullptr);
+      SGN_HIP(hipStreamSynchronize(s));
+    };
+    auto gram = [&](const double2* A, const double2* B) {  // A^dag B, host column-major
+      for (int j = 0; j < m; ++j) gs_dot(g, A, ldq, N, m, B + (size_t)j * ldq, coef + (size_t)j * m, s, nullptr);
+      SGN_HIP(hipMemcpyAsync(hc.data(), coef, sizeof(double2) * hc.size(), hipMemcpyDeviceToHost, s));
+      SGN_HIP(hipStreamSynchronize(s));
+      std::vector<cplx> G(hc.size());
+      for (size_t e = 0; e < G.size(); ++e) G[e] = to_c(hc[e]);
+      return G;
+    };
+    combine(S1->as<double2>(), W1, R);
+    std::vector<cplx> W2p((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int r = 0; r < m; ++r) W2p[(size_t)i * m + r] = W2[(size_t)perm[i] * m + r];
+    combine(S2->as<double2>(), W2p, L0);
+    // L = L0 (L0^dag R)^{-dag}, so that L^dag R = I
+    std::vector<cplx> M = gram(L0, R);
+    SGN_REQUIRE(invert(m, M), SGN_EDEFL, "LR deflation: left and right eigenvectors are not independent");
+    std::vector<cplx> X((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) X[(size_t)j * m + i] = std::conj(M[(size_t)i * m + j]);
+    combine(L0, X, L);
+    const std::vector<cplx> B = gram(L, R);
+    double dev = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) dev = std::max(dev, std::abs(B[(size_t)j * m + i] - (i == j ? 1.0 : 0.0)));
+    SGN_REQUIRE(dev <= 1e-8, SGN_EDEFL, "LR deflation: L^dag R deviates from I by " + std::to_string(dev));
+    std::vector<double2> lam(m);
+    for (int i = 0; i < m; ++i) lam[i] = to_d2(lam1[i]);
+    install_lr_pair(c, m, R, L, lam);
+    c->defl_restarts = st1.restarts + st2.restarts;
+    c->defl_matvecs = st1.matvecs + st2.matvecs;
+    c->defl_residual = std::max(st1.residual, st2.residual);
+    return SGN_OK;
+  });
 }

@@ -334,6 +334,11 @@ __global__ void negate_kernel(const double2* __restrict__ in, double2* __restric
   if (i < n) out[i] = cneg(in[i]);
 }
 
+__global__ void cmul_kernel(const double2* __restrict__ a, double2* __restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = cmul(a[i], x[i]);
+}
+
 __global__ void to_f32_kernel(const double2* __restrict__ in, float2* __restrict__ out, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -459,6 +464,12 @@ void dev_copy_mat(const double2* A, int lda, double2* B, int ldb, int rows, int 
 void dev_negate(const double2* in, double2* out, int n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(negate_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+  SGN_HIP(hipGetLastError());
+}
+
+void dev_cmul(const double2* a, double2* x, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(cmul_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, x, n);
   SGN_HIP(hipGetLastError());
 }
 

@@ -258,6 +258,11 @@ void gs_update(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, c
   update_launch(g, Q, ldq, N, ncol, h, -1.0, w, fin, kval, s, prof);
 }
 
+void gs_add(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* h, double2* w,
+            hipStream_t s, Profiler* prof) {
+  update_launch(g, Q, ldq, N, ncol, h, +1.0, w, nullptr, 0, s, prof);
+}
+
 void gs_norm(const GsWork& g, int N, const double2* w, double* beta, double* inv_beta, int* flag,
              hipStream_t s, Profiler* prof) {
   GsFinal fin{nullptr, nullptr, beta, inv_beta, flag};

@@ -236,11 +236,16 @@ void dense_coeffs_batched(int n, int m, const double2* F, int ldf, size_t fstrid
 // zero a device vector
 void dev_zero(double2* p, size_t n, hipStream_t s);
 void dev_copy_mat(const double2* A, int lda, double2* B, int ldb, int rows, int cols, hipStream_t s);
+// w += sum_c Q[c] h[c]
+void gs_add(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* h, double2* w,
+            hipStream_t s, Profiler* prof);
 // y = sum_c Q[c] coef[c]  (fresh output)
 void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, const double2* coef,
                 double2* y, double2* scratch_neg, hipStream_t s, Profiler* prof);
-// vector scale in place: v[i] *= a (device scalar pointer)
+// out = -in
 void dev_negate(const double2* in, double2* out, int n, hipStream_t s);
+// x[i] = a[i] x[i] (complex, n entries)
+void dev_cmul(const double2* a, double2* x, int n, hipStream_t s);
 // precision conversion
 void dev_to_f32(const double2* in, float2* out, size_t n, hipStream_t s);
 // any non-finite entry -> flag = 1

@@ -390,6 +390,7 @@ sgn_session* sgn_session_create(sgn_ctx* c, int max_slots, int kmax) {
   const int st = guarded(c, [&] {
     SGN_REQUIRE(max_slots >= 1 && max_slots <= kMaxBatch, SGN_EINVAL, "max_slots must satisfy 1 <= max_slots <= 64");
     SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    SGN_REQUIRE(c->lr_m == 0, SGN_ESTATE, "an LR-deflation pair is installed: sessions use a Schur pair");
     std::unique_ptr<sgn_session> p(new sgn_session);
     p->c = c;
     p->max_slots = max_slots;

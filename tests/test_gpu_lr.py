@@ -1,0 +1,195 @@
+"""LR-deflation through the C ABI (the LR-deflation subsection): fixed-k
+parity with the oracle's algorithm, the exact critical components, the k = 0
+case, the device setup (left and right eigenvectors) against the oracle's
+eigenvalues and relations, mixed precision, the overlap operator, and the
+paths that refuse an LR pair."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lr, matfunc, overlap, wilson
+
+pytestmark = pytest.mark.gpu
+
+M_W = -1.6
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0704_3486_amd as sg
+
+    return sg, torch
+
+
+@pytest.fixture(scope="module")
+def case():
+    dims, mu, m = (4, 4, 4, 4), 0.3, 8
+    links = synth.random_links(dims, 93)
+    A = wilson.hw_matrix(links, dims, mu, M_W).toarray()
+    R, L, lam = lr.lr_pair_from_dense(A, m)
+    Sgn = matfunc.sgn_spectral(A)
+    X = np.stack([synth.gaussian_source(dims, 9300 + r) for r in range(2)])
+    return dims, mu, links, A, R, L, lam, Sgn, X
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _lr_ctx(sg, torch, case, prec=0):
+    dims, mu, links, A, R, L, lam, Sgn, X = case
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    sg.sgn_set_precision(ctx, prec)
+    sg.sgn_deflate_lr_import(ctx, torch.from_numpy(R).cuda(), torch.from_numpy(L).cuda(), lam)
+    assert sg.sgn_deflation_mode(ctx) == sg.SGN_DEFL_LR and sg.sgn_deflation_size(ctx) == R.shape[1]
+    return ctx
+
+
+def test_lr_fixed_k_matches_oracle(env, case):
+    sg, torch = env
+    A, R, L, lam, X = case[3], case[4], case[5], case[6], case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        for k in (10, 60):
+            x = torch.from_numpy(X[0]).cuda()
+            y = torch.empty_like(x)
+            sg.sgn_apply_fixed(ctx, x, y, k)
+            ref = lr.sgn_lr_deflated(A, X[0], k, R, L, lam)
+            print("k", k, _rel(y.cpu().numpy(), ref), flush=True)
+            assert _rel(y.cpu().numpy(), ref) < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_converged_and_critical_components_exact(env, case):
+    sg, torch = env
+    R, L, lam, Sgn, X = case[4], case[5], case[6], case[7], case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        x = torch.from_numpy(X[1]).cuda()
+        y = torch.empty_like(x)
+        assert sg.sgn_apply(ctx, x, y, 1e-11, 600) == sg.SGN_OK
+        exact = Sgn @ X[1]
+        got = y.cpu().numpy()
+        assert _rel(got, exact) < 1e-9
+        # L^dag y = sgn(Lambda) L^dag x, exactly in the method
+        crit = L.conj().T @ got - matfunc.sgn_scalar(lam) * (L.conj().T @ X[1])
+        assert np.abs(crit).max() < 1e-11 * np.linalg.norm(X[1])
+        # the overlap operator on the LR pair
+        yo = torch.empty_like(x)
+        assert sg.sgn_overlap_apply(ctx, x, yo, 1e-11, 600) == sg.SGN_OK
+        g5 = overlap.gamma5_vector(X.shape[1] // 12)
+        assert _rel(yo.cpu().numpy(), X[1] + g5 * exact) < 1e-9
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_source_in_span_r_exact(env, case):
+    sg, torch = env
+    R, lam, Sgn = case[4], case[6], case[7]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        a = np.arange(1, R.shape[1] + 1) * (0.5 + 1.0j)
+        xs = R @ a
+        x = torch.from_numpy(xs).cuda()
+        y = torch.empty_like(x)
+        sg.sgn_apply(ctx, x, y, 1e-10, 100)
+        info = sg.sgn_last_info(ctx)
+        assert info["k_used"] == 0 and info["breakdown"] == 1
+        assert _rel(y.cpu().numpy(), Sgn @ xs) < 1e-12
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_mixed_precision(env, case):
+    sg, torch = env
+    Sgn, X = case[7], case[8]
+    ctx = _lr_ctx(sg, torch, case, prec=1)
+    try:
+        x = torch.from_numpy(X[0]).cuda()
+        y = torch.empty_like(x)
+        assert sg.sgn_apply(ctx, x, y, 1e-7, 600) == sg.SGN_OK
+        assert _rel(y.cpu().numpy(), Sgn @ X[0]) < 1e-6
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_device_setup(env, case):
+    sg, torch = env
+    dims, mu, links, A, R, L, lam = case[:7]
+    Sgn, X = case[7], case[8]
+    m = R.shape[1]
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        sg.sgn_deflate_lr(ctx, m)
+        assert sg.sgn_deflation_mode(ctx) == sg.SGN_DEFL_LR
+        Rd, Ld, lamd = sg.sgn_deflate_lr_export(ctx)
+        Rd, Ld = Rd.cpu().numpy(), Ld.cpu().numpy()
+        # the same critical eigenvalues as the dense oracle (as sets)
+        for z in lam:
+            assert np.min(np.abs(lamd - z)) < 1e-10 * max(1.0, abs(z))
+        assert np.abs(Ld.conj().T @ Rd - np.eye(m)).max() < 1e-9
+        assert np.linalg.norm(A @ Rd - Rd * lamd) / np.linalg.norm(Rd) < 1e-9
+        assert np.linalg.norm(Ld.conj().T @ A - lamd[:, None] * Ld.conj().T) / np.linalg.norm(Ld) < 1e-9
+        # the oblique projector does not depend on the eigenvector scaling
+        assert np.abs(Rd @ Ld.conj().T - R @ L.conj().T).max() < 1e-9
+        x = torch.from_numpy(X[0]).cuda()
+        y = torch.empty_like(x)
+        assert sg.sgn_apply(ctx, x, y, 1e-11, 600) == sg.SGN_OK
+        assert _rel(y.cpu().numpy(), Sgn @ X[0]) < 1e-9
+        stats = sg.sgn_deflate_stats(ctx)
+        assert stats["residual"] < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_refused_by_batched_and_sessions_then_schur_again(env, case):
+    sg, torch = env
+    X = case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        Xd = torch.from_numpy(X).cuda()
+        Y = torch.empty_like(Xd)
+        with pytest.raises(sg.SgnError) as e:
+            sg.sgn_apply_batched(ctx, Xd, Y, 1e-10, 200)
+        assert e.value.status == sg.SGN_ESTATE
+        with pytest.raises(sg.SgnError) as e:
+            sg.Session(ctx, 2, 100)
+        assert e.value.status == sg.SGN_ESTATE
+        bad = torch.from_numpy(case[4]).cuda()
+        with pytest.raises(sg.SgnError) as e:  # L^dag R != I
+            sg.sgn_deflate_lr_import(ctx, bad, bad, case[6])
+        assert e.value.status == sg.SGN_EINVAL
+        sg.sgn_deflate(ctx, 8)  # a Schur pair replaces the LR pair
+        assert sg.sgn_deflation_mode(ctx) == sg.SGN_DEFL_SCHUR
+        st, _ = sg.sgn_apply_batched(ctx, Xd, Y, 1e-10, 600)
+        assert st == sg.SGN_OK
+        assert _rel(Y[0].cpu().numpy(), case[7] @ X[0]) < 1e-8
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_c2_field_vs_stored_exact(env):
+    sg, torch = env
+    path = os.path.join(GOLDEN, "c6_mu0.2.npy")
+    if not os.path.exists(path):
+        pytest.skip("stored exact result missing")
+    dims, mu = (6, 6, 6, 6), 0.2
+    exact = np.load(path, allow_pickle=False)
+    ctx = sg.sgn_create(synth.random_links(dims, synth.GAUGE_SEED), dims, mu, M_W)
+    try:
+        sg.sgn_deflate_lr(ctx, 20)
+        x = torch.from_numpy(synth.gaussian_source(dims, 1000)).cuda()
+        y = torch.empty_like(x)
+        assert sg.sgn_apply(ctx, x, y, 1e-11, 500) == sg.SGN_OK
+        print("LR 6^4", sg.sgn_last_info(ctx), flush=True)
+        assert _rel(y.cpu().numpy(), exact) < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)
