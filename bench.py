@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lr", action="store_true", help="skip the LR-deflation comparison on the mu=0.2 field")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape of the Arnoldi passes instead of timing the nine")
     ap.add_argument("--no-stencil", action="store_true", help="skip the 32^4 stencil measurement")
@@ -250,6 +251,8 @@ def main():
                      "frac": round(gb / HBM_PEAK_GBPS, 4), "avg_launch_us": kern["wilson_hw"]["avg_us"]}
 
     ov = overlap_leg(sg, torch, ctxs[1], MUS[1], xs)
+    lrd = None if args.no_lr else lr_leg(sg, synth, torch, MUS[1], xs, latency_schur(sg, torch, ctxs[1], xs),
+                                         tune=not args.no_autotune)
 
     pairs = []  # the Schur pairs, for the oracle baseline
     for c in ctxs:
@@ -293,11 +296,56 @@ def main():
         "batched_mixed_12x12x12x12": batched,
         "small_sign": sign,
         "overlap": ov,
+        "lr_deflation": lrd,
         "kernels": kern,
         "profiled_pass_seconds": round(elapsed_prof, 4),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def latency_schur(sg, torch, ctx, xs, reps=10):
+    """ms per apply, one at a time, and mean k of the Schur-deflated field."""
+    y = torch.empty_like(xs[0])
+    ks = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        sg.sgn_apply(ctx, xs[r % len(xs)], y, TOL, KMAX)
+        ks.append(sg.sgn_last_info(ctx)["k_used"])
+    torch.cuda.synchronize()
+    return {"ms_per_apply": round(1e3 * (time.perf_counter() - t0) / reps, 3), "mean_k": float(np.mean(ks))}
+
+
+def lr_leg(sg, synth, torch, mu, xs, schur, reps=10, tune=True):
+    """LR-deflation (right and left critical eigenvectors, m = M_DEFL) on the
+    same 6^4 field against its Schur deflation: setup time, error on the
+    source with a stored exact result, ms per apply and k, one at a time."""
+    t0 = time.perf_counter()
+    ctx = sg.sgn_create(synth.random_links(DIMS, synth.GAUGE_SEED), DIMS, mu, M_W)
+    try:
+        sg.sgn_deflate_lr(ctx, M_DEFL)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        if tune:
+            from paper_0704_3486_amd.autotune import autotune
+
+            autotune(ctx, k=AUTOTUNE_K)
+        y = torch.empty_like(xs[0])
+        out = {"workload": f"6^4, mu={mu}, m={M_DEFL} (LR), tol={TOL}, FP64, 1 RHS per apply, one at a time",
+               "setup_seconds": round(setup_s, 3), **sg.sgn_deflate_stats(ctx)}
+        sg.sgn_apply(ctx, xs[0], y, TOL, KMAX)
+        path = os.path.join(GOLDEN, f"c6_mu{mu}.npy")
+        if os.path.exists(path):
+            exact = np.load(path, allow_pickle=False)
+            out["rel_err_vs_exact"] = float(np.linalg.norm(y.cpu().numpy() - exact) / np.linalg.norm(exact))
+        lat = latency_schur(sg, torch, ctx, xs, reps)
+        out["ms_per_apply"], out["mean_k"] = lat["ms_per_apply"], lat["mean_k"]
+        out["schur_same_field"] = schur
+    finally:
+        sg.sgn_destroy(ctx)
+    log(f"lr: {out}")
+    return out
 
 
 def overlap_leg(sg, torch, ctx, mu, xs, reps=10):
