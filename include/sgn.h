@@ -136,6 +136,14 @@ int sgn_deflate_import(sgn_ctx* ctx, int m, const double* S, const double* T);
  * evals to host (m complex = diag T).  Any pointer may be NULL. */
 int sgn_deflate_export(const sgn_ctx* ctx, double* S, double* T, double* evals);
 
+/* Krylov subspace size of the deflation eigensolver (sgn_deflate,
+ * sgn_deflate_lr: thick-restart Arnoldi on H_w^2): ncv basis vectors per
+ * cycle, of which about (ncv + nev) / 2 are kept at a restart; nev =
+ * m + max(10, m / 2).  0 restores the default max(3 nev, nev + 40); values
+ * below nev + 3 are raised to it, above N - 1 lowered to it.  SGN_EINVAL for
+ * ncv < 0.  Device memory grows by 2 ncv N complex128 during the setup. */
+int sgn_set_deflation_krylov(sgn_ctx* ctx, int ncv);
+
 /* Number of installed deflation vectors, Schur or LR (0 if none, <0 on error). */
 int sgn_deflation_size(const sgn_ctx* ctx);
 

@@ -100,6 +100,7 @@ def _load():
         "sgn_profile_reset": (i, [vp]),
         "sgn_deflate": (i, [vp, i]),
         "sgn_deflate_lr": (i, [vp, i]),
+        "sgn_set_deflation_krylov": (i, [vp, i]),
         "sgn_deflate_lr_import": (i, [vp, i, vp, vp, vp]),
         "sgn_deflate_lr_export": (i, [vp, vp, vp, vp]),
         "sgn_deflation_mode": (i, [vp]),
@@ -250,6 +251,11 @@ def sgn_deflation_mode(ctx):
     mode = _lib.sgn_deflation_mode(ctx)
     _check(ctx, mode if mode < 0 else SGN_OK)
     return mode
+
+
+def sgn_set_deflation_krylov(ctx, ncv):
+    """Krylov subspace size of the deflation eigensolver (0: default rule)."""
+    return _check(ctx, _lib.sgn_set_deflation_krylov(ctx, int(ncv)))
 
 
 def sgn_deflate_lr(ctx, m):

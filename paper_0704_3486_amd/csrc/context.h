@@ -85,6 +85,7 @@ struct sgn_ctx {
   // deflation
   int m = 0;
   int defl_restarts = 0, defl_matvecs = 0;
+  int defl_ncv = 0;  // Krylov subspace size of the deflation eigensolver (0: default rule)
   double defl_residual = 0.0;
   double2* S = nullptr;       // internal layout, ldq x m
   std::vector<double2> T;     // host m x m (column-major, upper triangular)

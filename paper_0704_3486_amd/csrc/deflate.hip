@@ -74,7 +74,20 @@ std::vector<int> select_critical(const std::vector<cplx>& lam, int m) {
 
 }  // namespace
 
+// thrown by deflate_run when the Ritz pairs have not converged within its restarts
+struct NotConverged {
+  int matvecs;
+};
+
+// Krylov subspace size of the deflation eigensolver: the context's setting,
+// else max(3 nev, nev + 40); at most N - 1
+static int deflation_ncv(const sgn_ctx* c, int nev) {
+  const int want = c->defl_ncv > 0 ? std::max(c->defl_ncv, nev + 3) : std::max(3 * nev, nev + 40);
+  return std::min(want, c->N - 1);
+}
+
 struct DeflateStats {
+  int ncv = 0;            // Krylov subspace size of the run that converged
   int restarts = 0;
   int matvecs = 0;
   double residual = 0.0;  // ||A S - S T||_F / ||A||
@@ -179,8 +192,7 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
       for (int i = 0; i < nev; ++i)
         for (int r = 0; r < ncv; ++r) cf[(size_t)i * ncv + r] = to_d2(Y[(size_t)ord[i] * ncv + r]);
       SGN_HIP(hipMemcpyAsync(coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, s));
-      for (int i = 0; i < nev; ++i)
-        gs_combine(g, V, ldq, N, ncv, coef + (size_t)i * ncv, Vt + (size_t)i * ldq, nullptr, s, nullptr);
+      dev_zgemm_nn(c->dense, N, nev, ncv, V, (int)ldq, coef, ncv, Vt, (int)ldq, s);  // one pass over V
       SGN_HIP(hipStreamSynchronize(s));  // cf is pageable host memory
       break;
     }
@@ -224,8 +236,7 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
     std::vector<double2> cf((size_t)ncv * kk);
     for (size_t e = 0; e < cf.size(); ++e) cf[e] = to_d2(Yq[e]);
     SGN_HIP(hipMemcpyAsync(coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, s));
-    for (int i = 0; i < kk; ++i)
-      gs_combine(g, V, ldq, N, ncv, coef + (size_t)i * ncv, Vt + (size_t)i * ldq, nullptr, s, nullptr);
+    dev_zgemm_nn(c->dense, N, kk, ncv, V, (int)ldq, coef, ncv, Vt, (int)ldq, s);  // one pass over V
     SGN_HIP(hipMemcpyAsync(Vt + (size_t)kk * ldq, V + (size_t)ncv * ldq, sizeof(double2) * ldq,
                            hipMemcpyDeviceToDevice, s));
     std::swap(V, Vt);
@@ -233,7 +244,7 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
     SGN_HIP(hipStreamSynchronize(s));
     k = kk;
   }
-  SGN_REQUIRE(converged, SGN_EDEFL, "deflation: Arnoldi on A^2 did not converge");
+  if (!converged) throw NotConverged{st.matvecs};
 
   // Z = orth(U) on the device (classical Gram-Schmidt, two passes), in Vt
   for (int i = 0; i < nev; ++i) {
@@ -317,6 +328,32 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
   return st;
 }
 
+// deflate_run with a growing Krylov subspace: unless the context fixes ncv,
+// a run that has not converged after 400 restarts is repeated with twice the
+// subspace (the restart count is very sensitive to ncv on clustered spectra),
+// up to N - 1; the last size gets 3000 restarts.
+static DeflateStats deflate_escalating(sgn_ctx* c, int m, int nev, unsigned long long seed,
+                                       std::unique_ptr<DevBuf>& S_out, std::vector<double2>& T_out) {
+  int ncv = deflation_ncv(c, nev);
+  SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
+  int spent_restarts = 0, spent_matvecs = 0;
+  for (;;) {
+    const bool last = c->defl_ncv > 0 || ncv >= c->N - 1;
+    try {
+      DeflateStats st = deflate_run(c, m, nev, ncv, last ? 3000 : 400, 1e-13, seed, S_out, T_out);
+      st.ncv = ncv;
+      st.restarts += spent_restarts;
+      st.matvecs += spent_matvecs;
+      return st;
+    } catch (const NotConverged& e) {
+      SGN_REQUIRE(!last, SGN_EDEFL, "deflation: Arnoldi on A^2 did not converge");
+      spent_restarts += 400;
+      spent_matvecs += e.matvecs;
+      ncv = std::min(2 * ncv, c->N - 1);
+    }
+  }
+}
+
 namespace {
 
 // in-place inverse of a column-major n x n complex matrix (Gauss-Jordan with
@@ -384,11 +421,9 @@ extern "C" int sgn_deflate(sgn_ctx* c, int m) {
       return SGN_OK;
     }
     const int nev = std::min(m + std::max(10, m / 2), c->N / 2);
-    const int ncv = std::min(std::max(3 * nev, nev + 40), c->N - 1);
-    SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
     std::unique_ptr<DevBuf> S;
     std::vector<double2> T;
-    const DeflateStats st = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull, S, T);
+    const DeflateStats st = deflate_escalating(c, m, nev, 0x5151ull, S, T);
     install_schur_pair(c, m, S->as<double2>(), T);
     c->defl_restarts = st.restarts;
     c->defl_matvecs = st.matvecs;
@@ -416,18 +451,16 @@ extern "C" int sgn_deflate_lr(sgn_ctx* c, int m) {
     SGN_REQUIRE(m >= 1 && m <= c->N / 4, SGN_EINVAL, "m must satisfy 1 <= m <= N/4");
     SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session holds this field's deflation");
     const int nev = std::min(m + std::max(10, m / 2), c->N / 2);
-    const int ncv = std::min(std::max(3 * nev, nev + 40), c->N - 1);
-    SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
     hipStream_t s = c->stream;
     const size_t ldq = c->ldq;
     const int N = c->N;
     std::unique_ptr<DevBuf> S1, S2;
     std::vector<double2> T1, T2;
-    const DeflateStats st1 = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull, S1, T1);
+    const DeflateStats st1 = deflate_escalating(c, m, nev, 0x5151ull, S1, T1);
     DeflateStats st2;
     {
       MinusMu flip(c->lat);
-      st2 = deflate_run(c, m, nev, ncv, 3000, 1e-13, 0x5151ull, S2, T2);
+      st2 = deflate_escalating(c, m, nev, 0x5151ull, S2, T2);
     }
     std::vector<cplx> lam1, W1, lam2, W2;
     host_eigvecs(m, T1, lam1, W1);
@@ -500,6 +533,14 @@ extern "C" int sgn_deflate_lr(sgn_ctx* c, int m) {
     c->defl_restarts = st1.restarts + st2.restarts;
     c->defl_matvecs = st1.matvecs + st2.matvecs;
     c->defl_residual = std::max(st1.residual, st2.residual);
+    return SGN_OK;
+  });
+}
+
+extern "C" int sgn_set_deflation_krylov(sgn_ctx* c, int ncv) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(ncv >= 0, SGN_EINVAL, "ncv must be >= 0 (0: default)");
+    c->defl_ncv = ncv;
     return SGN_OK;
   });
 }

@@ -607,6 +607,7 @@ rocblas_handle blas_handle(DenseWork& d, hipStream_t s) {
   return h;
 }
 
+
 // Y = 3I - P in place, P = X^2 from the GEMM, and per kEpi entries the
 // partial sum of |P - I|^2 (fixed-order tree); blockIdx.y = matrix of the
 // batch (stride nn), skipped once it has stopped
@@ -674,6 +675,17 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
 
 // partial sums of |X^2 - I| per kEpi entries (and the column sums of the
 // 1-norm) for nb matrices of order n; returns the entries in use
+void dev_zgemm_nn(DenseWork& d, int M, int N, int K, const double2* A, int lda, const double2* B, int ldb,
+                  double2* C, int ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  rocblas_handle h = blas_handle(d, s);
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  blas_check(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, M, N, K, &one,
+                           reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                           reinterpret_cast<const rocblas_double_complex*>(B), ldb, &zero,
+                           reinterpret_cast<rocblas_double_complex*>(C), ldc));
+}
+
 static size_t ns_reserve(DenseWork& d, int n, int nb) {
   const size_t nblk = ((size_t)n * n + kEpi - 1) / kEpi;
   const size_t nparts = std::max(nblk, (size_t)n) * nb;

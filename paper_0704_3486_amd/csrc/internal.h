@@ -244,6 +244,9 @@ void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, 
                 double2* y, double2* scratch_neg, hipStream_t s, Profiler* prof);
 // out = -in
 void dev_negate(const double2* in, double2* out, int n, hipStream_t s);
+// C = A B (column-major, complex; rocBLAS with atomics off, deterministic)
+void dev_zgemm_nn(DenseWork& d, int M, int N, int K, const double2* A, int lda, const double2* B, int ldb,
+                  double2* C, int ldc, hipStream_t s);
 // x[i] = a[i] x[i] (complex, n entries)
 void dev_cmul(const double2* a, double2* x, int n, hipStream_t s);
 // precision conversion
