@@ -506,10 +506,11 @@ def batched_leg(sg, synth, torch):
 
 # serving stream: lattice, deflation m, session kmax, arrival weight, share of
 # the HBM budget for its Krylov workspaces.  The 12^4 and 16^4 fields draw
-# mu = 0.5, where a 40-60 vector basis from H_w^2 takes minutes to tens of
-# minutes to converge; they are served without deflation (kmax 600).
+# mu = 0.5, where the deflation basis converges slowly (12^4, m = 40: about
+# 46 s); the 16^4 field (m = 60 would take minutes) is served without
+# deflation (kmax 600).
 SERVE_FIELDS = [((6, 6, 6, 6), 20, 500, 0.4, 0.05), ((8, 8, 8, 8), 30, 500, 0.3, 0.10),
-                ((12, 12, 12, 12), 0, 600, 0.2, 0.35), ((16, 16, 16, 16), 0, 600, 0.1, 0.50)]
+                ((12, 12, 12, 12), 40, 500, 0.2, 0.35), ((16, 16, 16, 16), 0, 600, 0.1, 0.50)]
 SERVE_TOL = 1e-8
 SERVE_BUDGET = 150e9
 
