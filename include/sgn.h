@@ -153,8 +153,8 @@ int sgn_deflation_size(const sgn_ctx* ctx);
  * L^dag R = I, an apply computes R sgn(Lambda) L^dag x + beta V_k sgn(H_k) e1
  * with the plain Arnoldi method on x_- = (1 - R L^dag) x (no projection
  * inside the Krylov steps).  An LR pair replaces any Schur pair and vice
- * versa; sgn_apply, sgn_apply_fixed and sgn_overlap_apply use it, batched
- * applies and sessions return SGN_ESTATE while it is installed.
+ * versa; every apply (single, batched, overlap, serving sessions) uses the
+ * installed one.
  * sgn_deflate_lr computes it on the device: the critical Schur pairs of
  * H_w(mu) and of H_w(-mu) = H_w(mu)^dag (same method as sgn_deflate; its
  * left eigenvectors are the right ones of H_w(-mu) for conj(lambda)), their

@@ -30,7 +30,7 @@ int even_k(int k) { return (k + 1) & ~1; }
 // (re)allocate the batch workspace for nslots sources and kcap Krylov vectors
 void batch_ensure(sgn_ctx* c, int nslots, int kcap) {
   BatchWork& b = c->bw;
-  const bool same_layout = b.V && b.prec == c->prec && b.m == c->m;
+  const bool same_layout = b.V && b.prec == c->prec && b.m == c->m && b.lrm == c->lr_m;
   if (same_layout && b.nslots >= nslots && b.kcap >= kcap) return;
   if (same_layout) {
     nslots = std::max(nslots, b.nslots);
@@ -42,6 +42,7 @@ void batch_ensure(sgn_ctx* c, int nslots, int kcap) {
   b.nslots = nslots;
   b.kcap = kcap;
   b.m = m;
+  b.lrm = c->lr_m;
   b.prec = c->prec;
   b.ldq = ldq;
   b.ncap = m + kcap + 1;
@@ -57,11 +58,12 @@ void batch_ensure(sgn_ctx* c, int nslots, int kcap) {
   // two n x n blocks per slot: the patched composite matrix and its sign
   SGN_HIP(hipMalloc(&b.F, sizeof(double2) * n * n * 2 * S));
   SGN_HIP(hipMalloc(&b.c0, sizeof(double2) * mm * S));
+  SGN_HIP(hipMalloc(&b.lrc, sizeof(double2) * (size_t)std::max(c->lr_m, 1) * S));
   SGN_HIP(hipMalloc(&b.cv, sizeof(double2) * ncap * 2 * S));
   for (double** p : {&b.beta, &b.err, &b.ref, &b.inv}) SGN_HIP(hipMalloc(p, sizeof(double) * S));
   for (int** p : {&b.flag, &b.fin}) SGN_HIP(hipMalloc(p, sizeof(int) * S));
   SGN_HIP(hipHostMalloc(&b.hpin, sizeof(double) * 4 * S, hipHostMallocDefault));
-  gs_alloc(b.gs, c->N, ldq, (int)mm);
+  gs_alloc(b.gs, c->N, ldq, std::max((int)mm, c->lr_m));
   krylov_alloc(b.kw, c->N, ldq, b.ncap, nslots);
   dense_reserve(b.dense, (int)n, nslots);
   // the Schur block T_m of every slot's composite matrix never changes
@@ -111,6 +113,11 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
     if (m > 0) {
       gs_dot(b.gs, c->S, ldq, N, m, u0, b.c0 + (size_t)r * mm, s, prof);
       gs_update(b.gs, c->S, ldq, N, m, b.c0 + (size_t)r * mm, u0, nullptr, 0, s, prof);
+    }
+    if (c->lr_m > 0) {  // LR-deflation, step (iii): L^dag x, x_- = (1 - R L^dag) x
+      double2* lc = b.lrc + (size_t)r * c->lr_m;
+      gs_dot(b.gs, c->lrL, ldq, N, c->lr_m, u0, lc, s, prof);
+      gs_update(b.gs, c->lrR, ldq, N, c->lr_m, lc, u0, nullptr, 0, s, prof);
     }
     if (mixed) dev_to_f32(u0, static_cast<float2*>(b.ulo) + (size_t)r * ldq, (size_t)N, s);
   }
@@ -176,7 +183,14 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
         krylov_combine<float2>(b.kw, kf, cvcur, (int)ncap, b.y, ldq, g.first, s, prof);
       else
         krylov_combine<double2>(b.kw, kf, cvcur, (int)ncap, b.y, ldq, g.first, s, prof);
-      for (int r : g.second) wilson_unpack(c->lat, b.y + (size_t)r * ldq, Y_abi + (size_t)r * N, s);
+      for (int r : g.second) {
+        if (c->lr_m > 0) {  // LR-deflation, step (vi): y += R sgn(Lambda) L^dag x
+          double2* lc = b.lrc + (size_t)r * c->lr_m;
+          dev_cmul(c->lrSgn, lc, c->lr_m, s);
+          gs_add(b.gs, c->lrR, ldq, N, c->lr_m, lc, b.y + (size_t)r * ldq, s, prof);
+        }
+        wilson_unpack(c->lat, b.y + (size_t)r * ldq, Y_abi + (size_t)r * N, s);
+      }
     }
   };
 
@@ -353,7 +367,6 @@ int batched_entry(sgn_ctx* c, int nrhs, const double* X, double* Y, double tol, 
                   sgn_info* info) {
   SGN_REQUIRE(nrhs >= 1, SGN_EINVAL, "nrhs must be positive");
   SGN_REQUIRE(X && Y, SGN_EINVAL, "X and Y must not be NULL");
-  SGN_REQUIRE(c->lr_m == 0, SGN_ESTATE, "an LR-deflation pair is installed: batched applies use a Schur pair");
   const double2* Xc = reinterpret_cast<const double2*>(X);
   double2* Yc = reinterpret_cast<double2*>(Y);
   int status = SGN_OK;

@@ -13,7 +13,7 @@
 // each at a fixed slot stride.  VT = FP64 (double2) or, in mixed precision,
 // FP32 (float2) for the Krylov columns and stencil operands.
 struct BatchWork {
-  int nslots = 0, kcap = 0, ncap = 0, prec = -1, m = -1;
+  int nslots = 0, kcap = 0, ncap = 0, prec = -1, m = -1, lrm = -1;
   size_t ldq = 0;
   void* V = nullptr;         // [slot] ldq x (kcap + 1), VT
   size_t vstride = 0;
@@ -25,6 +25,7 @@ struct BatchWork {
   double2* H = nullptr;      // [slot] ncap x ncap
   double2* F = nullptr;      // [launch slot] (m + kcap)^2, signs of one checkpoint
   double2* c0 = nullptr;     // [slot] max(m, 1)
+  double2* lrc = nullptr;    // [slot] max(lr_m, 1): L^dag x of the LR-deflation
   double2* cv = nullptr;     // [2][slot] ncap, coefficients (ping-pong halves)
   double* beta = nullptr;    // [slot]
   double* err = nullptr;     // [slot]
@@ -44,8 +45,8 @@ struct BatchWork {
   size_t vt() const { return prec == SGN_PREC_MIXED ? sizeof(float2) : sizeof(double2); }
   void release() {
     for (void** p : {&V, (void**)&u, &ulo, &z, (void**)&xin, (void**)&y, (void**)&H, (void**)&F, (void**)&c0,
-                     (void**)&cv, (void**)&beta, (void**)&err, (void**)&ref, (void**)&inv, (void**)&flag,
-                     (void**)&fin})
+                     (void**)&lrc, (void**)&cv, (void**)&beta, (void**)&err, (void**)&ref, (void**)&inv,
+                     (void**)&flag, (void**)&fin})
       if (*p) {
         (void)hipFree(*p);
         *p = nullptr;
@@ -56,7 +57,7 @@ struct BatchWork {
     krylov_free(kw);
     dense_destroy(dense);
     nslots = kcap = ncap = 0;
-    prec = m = -1;
+    prec = m = lrm = -1;
   }
   // bytes ensure() allocates (kcap Krylov vectors for nslots right-hand sides)
   static size_t bytes(size_t ldq, int m, int kcap, int nslots, size_t vt) {

@@ -67,6 +67,7 @@ struct sgn_session {
   double2* H = nullptr;     // ncap x ncap composite Hessenberg
   double2* F = nullptr;     // 2 x (m + kmax)^2: patched composite, its sign
   double2* c0 = nullptr;    // max(m, 1)
+  double2* lrc = nullptr;   // max(lr_m, 1): L^dag x of the LR-deflation
   double2* cv = nullptr;    // ncap, coefficients of the last checkpoint
   double2* cp = nullptr;    // ncap, coefficients of the one before
   double *beta = nullptr, *err = nullptr, *ref = nullptr, *inv = nullptr;
@@ -93,12 +94,13 @@ struct sgn_session {
     SGN_HIP(hipMalloc(&H, sizeof(double2) * nc * nc * S));
     SGN_HIP(hipMalloc(&F, sizeof(double2) * n * n * 2 * S));
     SGN_HIP(hipMalloc(&c0, sizeof(double2) * mm * S));
+    SGN_HIP(hipMalloc(&lrc, sizeof(double2) * (size_t)std::max(c->lr_m, 1) * S));
     SGN_HIP(hipMalloc(&cv, sizeof(double2) * nc * S));
     SGN_HIP(hipMalloc(&cp, sizeof(double2) * nc * S));
     for (double** p : {&beta, &err, &ref, &inv}) SGN_HIP(hipMalloc(p, sizeof(double) * S));
     for (int** p : {&flag, &fin}) SGN_HIP(hipMalloc(p, sizeof(int) * S));
     SGN_HIP(hipHostMalloc(&hpin, sizeof(double) * 4 * S, hipHostMallocDefault));
-    gs_alloc(gs, c->N, ldq, (int)mm);
+    gs_alloc(gs, c->N, ldq, std::max((int)mm, c->lr_m));
     krylov_alloc(kw, c->N, ldq, ncap, max_slots);
     dense_reserve(dense, (int)n, max_slots);
     SGN_HIP(hipMemset(H, 0, sizeof(double2) * nc * nc * S));
@@ -109,8 +111,8 @@ struct sgn_session {
   void release() {
     (void)hipDeviceSynchronize();
     for (void** p : {&V, (void**)&u, &ulo, &z, (void**)&xin, (void**)&y, (void**)&H, (void**)&F, (void**)&c0,
-                     (void**)&cv, (void**)&cp, (void**)&beta, (void**)&err, (void**)&ref, (void**)&inv,
-                     (void**)&flag, (void**)&fin})
+                     (void**)&lrc, (void**)&cv, (void**)&cp, (void**)&beta, (void**)&err, (void**)&ref,
+                     (void**)&inv, (void**)&flag, (void**)&fin})
       if (*p) {
         (void)hipFree(*p);
         *p = nullptr;
@@ -182,6 +184,11 @@ struct sgn_session {
     if (m > 0) {
       gs_dot(gs, c->S, ldq, N, m, ur, c0 + (size_t)r * mm, s, prof);
       gs_update(gs, c->S, ldq, N, m, c0 + (size_t)r * mm, ur, nullptr, 0, s, prof);
+    }
+    if (c->lr_m > 0) {  // LR-deflation, step (iii): L^dag x, x_- = (1 - R L^dag) x
+      double2* lc = lrc + (size_t)r * c->lr_m;
+      gs_dot(gs, c->lrL, ldq, N, c->lr_m, ur, lc, s, prof);
+      gs_update(gs, c->lrR, ldq, N, c->lr_m, lc, ur, nullptr, 0, s, prof);
     }
     if (prec == SGN_PREC_MIXED) dev_to_f32(ur, static_cast<float2*>(ulo) + (size_t)r * ldq, (size_t)N, s);
     int* h_fin = reinterpret_cast<int*>(hpin + max_slots) + max_slots;
@@ -331,6 +338,11 @@ struct sgn_session {
       else
         krylov_combine<double2>(kw, kf, cv, (int)nc, y, ldq, g.first, s, prof);
       for (int r : g.second) {
+        if (c->lr_m > 0) {  // LR-deflation, step (vi): y += R sgn(Lambda) L^dag x
+          double2* lc = lrc + (size_t)r * c->lr_m;
+          dev_cmul(c->lrSgn, lc, c->lr_m, s);
+          gs_add(gs, c->lrR, ldq, c->N, c->lr_m, lc, y + (size_t)r * ldq, s, prof);
+        }
         wilson_unpack(c->lat, y + (size_t)r * ldq, slots[r].y, s);
         slots[r].busy = false;
       }
@@ -390,7 +402,6 @@ sgn_session* sgn_session_create(sgn_ctx* c, int max_slots, int kmax) {
   const int st = guarded(c, [&] {
     SGN_REQUIRE(max_slots >= 1 && max_slots <= kMaxBatch, SGN_EINVAL, "max_slots must satisfy 1 <= max_slots <= 64");
     SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
-    SGN_REQUIRE(c->lr_m == 0, SGN_ESTATE, "an LR-deflation pair is installed: sessions use a Schur pair");
     std::unique_ptr<sgn_session> p(new sgn_session);
     p->c = c;
     p->max_slots = max_slots;

@@ -1,8 +1,8 @@
 """LR-deflation through the C ABI (the LR-deflation subsection): fixed-k
 parity with the oracle's algorithm, the exact critical components, the k = 0
 case, the device setup (left and right eigenvectors) against the oracle's
-eigenvalues and relations, mixed precision, the overlap operator, and the
-paths that refuse an LR pair."""
+eigenvalues and relations, mixed precision, the overlap operator, batched
+applies and serving sessions on an LR pair, and the import checks."""
 import os
 
 import numpy as np
@@ -150,28 +150,67 @@ def test_lr_device_setup(env, case):
         sg.sgn_destroy(ctx)
 
 
-def test_lr_refused_by_batched_and_sessions_then_schur_again(env, case):
+def test_lr_batched_and_session(env, case):
+    # batched at fixed k: bitwise the single-source result; a session: the
+    # same result alone and among other requests, near the exact sign
     sg, torch = env
-    X = case[8]
+    X, Sgn = case[8], case[7]
     ctx = _lr_ctx(sg, torch, case)
     try:
         Xd = torch.from_numpy(X).cuda()
         Y = torch.empty_like(Xd)
-        with pytest.raises(sg.SgnError) as e:
-            sg.sgn_apply_batched(ctx, Xd, Y, 1e-10, 200)
-        assert e.value.status == sg.SGN_ESTATE
-        with pytest.raises(sg.SgnError) as e:
-            sg.Session(ctx, 2, 100)
-        assert e.value.status == sg.SGN_ESTATE
+        sg.sgn_apply_batched_fixed(ctx, Xd, Y, 60)
+        for r in range(X.shape[0]):
+            y = torch.empty_like(Xd[r])
+            sg.sgn_apply_fixed(ctx, Xd[r].contiguous(), y, 60)
+            assert torch.equal(y, Y[r])
+
+        def run_session(rows, slots):
+            ses = sg.Session(ctx, slots, 500)
+            out = {}
+            try:
+                hs = {}
+                for r in rows:
+                    out[r] = torch.empty_like(Xd[r])
+                    hs[ses.submit(Xd[r].contiguous(), out[r], 1e-11, 500)] = r
+                    ses.step(7)  # the next request joins a running one
+                while ses.active():
+                    ses.step(5)
+                for h in hs:
+                    assert ses.poll(h)["converged"] == 1
+            finally:
+                ses.destroy()
+            return out
+
+        alone = run_session([1], 1)
+        mixed = run_session([0, 1], 2)
+        assert torch.equal(alone[1], mixed[1])
+        assert _rel(mixed[1].cpu().numpy(), Sgn @ X[1]) < 1e-9
+        st, _ = sg.sgn_overlap_apply_batched(ctx, Xd, Y, 1e-11, 500)
+        assert st == sg.SGN_OK
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_import_checks_then_schur_again(env, case):
+    sg, torch = env
+    X = case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
         bad = torch.from_numpy(case[4]).cuda()
         with pytest.raises(sg.SgnError) as e:  # L^dag R != I
             sg.sgn_deflate_lr_import(ctx, bad, bad, case[6])
         assert e.value.status == sg.SGN_EINVAL
+        assert sg.sgn_deflation_mode(ctx) == sg.SGN_DEFL_LR  # the failed import left the pair
         sg.sgn_deflate(ctx, 8)  # a Schur pair replaces the LR pair
         assert sg.sgn_deflation_mode(ctx) == sg.SGN_DEFL_SCHUR
+        Xd = torch.from_numpy(X).cuda()
+        Y = torch.empty_like(Xd)
         st, _ = sg.sgn_apply_batched(ctx, Xd, Y, 1e-10, 600)
         assert st == sg.SGN_OK
         assert _rel(Y[0].cpu().numpy(), case[7] @ X[0]) < 1e-8
+        with pytest.raises(sg.SgnError):
+            sg.sgn_deflate_lr_export(ctx)
     finally:
         sg.sgn_destroy(ctx)
 
