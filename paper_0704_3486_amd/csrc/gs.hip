@@ -79,9 +79,17 @@ __global__ void __launch_bounds__(256)
 gs_dot_red_kernel(const double2* __restrict__ P, int ldp, int nrt, int ncol, double2* __restrict__ h) {
   const int cl = threadIdx.x & 31, part = threadIdx.x >> 5;
   const int c = blockIdx.x * 32 + cl;
-  double2 acc = make_double2(0.0, 0.0);
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 acc = zero;
+  // tiles t = part, part + 8, ... in that order, eight loads in flight
   if (c < ncol)
-    for (int t = part; t < nrt; t += 8) acc = cadd(acc, P[(size_t)t * ldp + c]);
+    for (int t0 = part; t0 < nrt; t0 += 64) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (t0 + 8 * u < nrt) ? P[(size_t)(t0 + 8 * u) * ldp + c] : zero;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
+    }
   __shared__ double2 red[8][33];
   red[part][cl] = acc;
   __syncthreads();

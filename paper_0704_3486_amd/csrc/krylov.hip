@@ -172,11 +172,23 @@ __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
   const double* Pcd = A.Pcd + (size_t)r * A.cdstride;
   const int cl = threadIdx.x & 31, part = threadIdx.x >> 5;
   const int c = blockIdx.x * 32 + cl;
-  double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 sa = zero, sb = zero;
+  // tiles t = part, part + 8, ... in that order, eight loads in flight
   if (c < J)
-    for (int t = part; t < nrt; t += 8) {
-      sa = cadd(sa, Pa[(size_t)t * A.ldp + c]);
-      sb = cadd(sb, Pb[(size_t)t * A.ldp + c]);
+    for (int t0 = part; t0 < nrt; t0 += 64) {
+      double2 va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + 8 * u;
+        va[u] = t < nrt ? Pa[(size_t)t * A.ldp + c] : zero;
+        vb[u] = t < nrt ? Pb[(size_t)t * A.ldp + c] : zero;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sa = cadd(sa, va[u]);
+        sb = cadd(sb, vb[u]);
+      }
     }
   __shared__ double2 ra[8][33], rb[8][33];
   ra[part][cl] = sa;
@@ -196,7 +208,13 @@ __global__ void __launch_bounds__(256) kred_kernel(KrylovArgs A) {
     // lane, lane + 64, ...) then a fixed butterfly
     const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double acc = 0.0;
-    for (int t = lane; t < nrt; t += 64) acc += Pcd[4 * t + q];
+    for (int t0 = lane; t0 < nrt; t0 += 64 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (t0 + 64 * u < nrt) ? Pcd[4 * (t0 + 64 * u) + q] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
     acc = wsum1(acc);
     if (lane == 0) A.sc[(size_t)r * kScStride + kScRawC + q] = acc;
   }
