@@ -427,6 +427,9 @@ def stencil_leg(sg, synth, torch):
     ctx = sg.sgn_create(links, dims, 0.3, M_W)
     del links
     try:
+        from paper_0704_3486_amd.autotune import autotune_stencil
+
+        walk = autotune_stencil(ctx)  # the walk order only (results bitwise the same)
         x = torch.from_numpy(synth.gaussian_source(dims, 1000)).cuda()
         y = torch.empty_like(x)
         for _ in range(3):
@@ -446,7 +449,7 @@ def stencil_leg(sg, synth, torch):
            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(gb / HBM_PEAK_GBPS, 4),
            "avg_launch_us": round(1e3 * s["ms"] / s["launches"], 2), "kernel": HBM_KERNELS["wilson_hw"],
            "bytes_per_launch": s["bytes"] / s["launches"], "plain_copy_GBps": copy,
-           "frac_of_plain_copy": round(gb / copy, 4)}
+           "frac_of_plain_copy": round(gb / copy, 4), "walk_blocks": list(walk["blocks"])}
     log(f"stencil: {out}")
     return out
 

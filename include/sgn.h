@@ -301,6 +301,16 @@ int sgn_get_tuning(const sgn_ctx* ctx, int* update_batch, int* dot_cols, int* up
  * and replay measured no faster).  SGN_EINVAL for other values. */
 int sgn_set_step_graphs(sgn_ctx* ctx, int steps);
 
+/* Order in which the stencil's workgroups walk the lattice (Eq. Dw; results
+ * are bitwise the same for every order): 4D blocks of Lx x By x Bz x Bt
+ * sites, walked block by block so that neighbour spinors and links are
+ * reused from cache.  By, Bz, Bt must divide Ly, Lz, Lt with Lx*By a
+ * multiple of 32; (0, 0, 0) restores the default (on lattices of 65536
+ * sites or more the first of By = 4, 8, 2, 16, 1, Bz = 16, 8, 4, 2, 1,
+ * Bt = 4, 8, 2, 1 that fits; natural order below); By < 0 selects the
+ * natural order.  SGN_EINVAL otherwise. */
+int sgn_set_stencil_blocks(sgn_ctx* ctx, int By, int Bz, int Bt);
+
 /* Checkpoint placement of sgn_apply.  The small-matrix sign is evaluated at
  * even checkpoints; the first successful sgn_apply on a field records the k
  * at which convergence to tol was certified, and later applies with the same

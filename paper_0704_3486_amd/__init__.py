@@ -107,6 +107,7 @@ def _load():
         "sgn_set_orthogonalization": (i, [vp, i]),
         "sgn_set_tuning": (i, [vp, i, i, i]),
         "sgn_set_step_graphs": (i, [vp, i]),
+        "sgn_set_stencil_blocks": (i, [vp, i, i, i]),
         "sgn_get_tuning": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "sgn_set_precision": (i, [vp, i]),
         "sgn_get_precision": (i, [vp]),
@@ -431,6 +432,11 @@ def sgn_set_tuning(ctx, update_batch=8, dot_cols=4, update_waves=8):
 def sgn_set_step_graphs(ctx, steps):
     """Replay runs of `steps` Arnoldi steps as captured graphs (0: off)."""
     return _check(ctx, _lib.sgn_set_step_graphs(ctx, int(steps)))
+
+
+def sgn_set_stencil_blocks(ctx, By=0, Bz=0, Bt=0):
+    """Stencil walk blocks (0, 0, 0: default; By < 0: natural order); results are bitwise the same."""
+    return _check(ctx, _lib.sgn_set_stencil_blocks(ctx, int(By), int(Bz), int(Bt)))
 
 
 def sgn_get_tuning(ctx):

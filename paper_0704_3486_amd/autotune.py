@@ -21,10 +21,14 @@ import os
 import time
 
 from . import (sgn_apply_batched_fixed, sgn_apply_fixed, sgn_deflation_size, sgn_get_dims, sgn_get_precision,
-               sgn_get_tuning, sgn_set_tuning)
+               sgn_get_tuning, sgn_matvec, sgn_set_stencil_blocks, sgn_set_tuning)
 
 UPDATE_BATCH = (4, 8, 16)
 DOT_COLS = (1, 2, 4)
+# stencil walk blocks (By, Bz, Bt) tried by autotune_stencil: the default
+# rule, the natural order and blocks around the default
+STENCIL_BLOCKS = ((0, 0, 0), (-1, 0, 0), (4, 16, 2), (4, 16, 8), (4, 8, 8), (8, 8, 2), (8, 8, 4), (2, 8, 4),
+                  (8, 4, 4))
 
 
 def _key(ctx, nrhs, k, device):
@@ -90,3 +94,36 @@ def autotune(ctx, k=256, nrhs=1, cache=None, reps=3):
             json.dump(table, f, indent=1, sort_keys=True)
         os.replace(tmp, cache)
     return {"update_batch": ub, "dot_cols": cpw, "ms": round(1e3 * t, 4), "cached": False}
+
+
+def autotune_stencil(ctx, reps=10):
+    """Pick the fastest stencil walk (sgn_set_stencil_blocks; results are
+    bitwise the same for every walk) by timing sgn_matvec on this context's
+    lattice; shapes that do not fit the lattice are skipped.  Returns
+    {"blocks": (By, Bz, Bt), "us": per matvec}."""
+    import torch
+
+    from . import SgnError
+
+    _, n = sgn_get_dims(ctx)
+    gen = torch.Generator(device="cuda").manual_seed(4321)
+    x = torch.randn(n, dtype=torch.complex128, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    best = None
+    for blocks in STENCIL_BLOCKS:
+        try:
+            sgn_set_stencil_blocks(ctx, *blocks)
+        except SgnError:
+            continue
+        sgn_matvec(ctx, x, y)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sgn_matvec(ctx, x, y)
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t0) / reps
+        if best is None or us < best[0]:
+            best = (us, blocks)
+    sgn_set_stencil_blocks(ctx, *best[1])
+    return {"blocks": best[1], "us": round(best[0], 2)}

@@ -871,6 +871,19 @@ int sgn_set_tuning(sgn_ctx* c, int update_batch, int dot_cols, int update_waves)
   });
 }
 
+int sgn_set_stencil_blocks(sgn_ctx* c, int By, int Bz, int Bt) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(wilson_blocks_valid(c->lat, By, Bz, Bt), SGN_EINVAL,
+                "blocks must divide Ly, Lz, Lt with Lx*By a multiple of 32 (0,0,0: default; -1: natural order)");
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    c->lat.blk[0] = By < 0 ? -1 : By;
+    c->lat.blk[1] = By < 0 ? 0 : Bz;
+    c->lat.blk[2] = By < 0 ? 0 : Bt;
+    c->drop_graphs();  // captured stencil launches hold the old order
+    return SGN_OK;
+  });
+}
+
 int sgn_set_step_graphs(sgn_ctx* c, int steps) {
   return guarded(c, [&] {
     SGN_REQUIRE(steps == 0 || (steps >= 2 && steps <= 64), SGN_EINVAL, "steps must be 0 or 2..64");

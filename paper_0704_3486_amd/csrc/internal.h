@@ -151,10 +151,15 @@ struct Lattice {
   int V;
   double kappa;
   double emu, emmu;  // e^{+mu}, e^{-mu}
+  // stencil walk blocks (By, Bz, Bt): {0,0,0} the default rule, {-1,...} the
+  // natural site order; otherwise these extents (results do not depend on it)
+  int blk[3] = {0, 0, 0};
 };
 void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, hipStream_t s);
 void wilson_pack(const Lattice& lat, const double2* x_abi, double2* v, hipStream_t s);
 void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStream_t s);
+// walk blocks acceptable for this lattice (0,0,0: default; negative By: natural order)
+bool wilson_blocks_valid(const Lattice& lat, int By, int Bz, int Bt);
 // y = x + gamma5 y over n entries in the interface layout (n a multiple of 12)
 void overlap_finish(const double2* x, double2* y, size_t n, hipStream_t s);
 // out = H_w(mu) (in * scale), optional copy_out = in * scale; scale = *inv_beta (or 1 if null)

@@ -18,6 +18,8 @@
 //   (1 + g3): h = (p0 - i p2, p1 + i p3),   lower = ( i h0, -i h1)
 //   (1 + g4): h = (p0 + p2,   p1 + p3),     lower = ( h0,    h1)
 // and (1 - g_nu) flips the sign of every gamma term (lower = -(same map)).
+#include <initializer_list>
+
 #include "internal.h"
 
 namespace {
@@ -425,19 +427,37 @@ void overlap_finish(const double2* x, double2* y, size_t n, hipStream_t s) {
 static SiteOrder site_order(const Lattice& lat) {
   SiteOrder o;
   const int Lx = lat.L[0], Ly = lat.L[1], Lz = lat.L[2], Lt = lat.L[3];
+  if (lat.blk[0] < 0) return o;
+  if (lat.blk[0] > 0) {  // set by sgn_set_stencil_blocks (validated there)
+    o.By = lat.blk[0];
+    o.Bz = lat.blk[1];
+    o.Bt = lat.blk[2];
+    o.segw = Lx * o.By / kSiteGroup;
+    o.on = 1;
+    return o;
+  }
   if (lat.V < 65536) return o;
-  auto pick = [](int L, int cap, auto ok) {
-    for (int b = cap; b >= 1; b /= 2)
+  // preferred extents first (at 32^4, Lx x 4 x 16 x 4 walked 6 % faster than
+  // Lx x 8 x 8 x 4 and 14 % faster than the natural order)
+  auto pick = [](int L, std::initializer_list<int> pref, auto ok) {
+    for (int b : pref)
       if (L % b == 0 && ok(b)) return b;
     return 0;
   };
-  o.By = pick(Ly, 8, [&](int b) { return (Lx * b) % kSiteGroup == 0; });
-  o.Bz = pick(Lz, 8, [](int) { return true; });
-  o.Bt = pick(Lt, 4, [](int) { return true; });
+  o.By = pick(Ly, {4, 8, 2, 16, 1}, [&](int b) { return (Lx * b) % kSiteGroup == 0; });
+  o.Bz = pick(Lz, {16, 8, 4, 2, 1}, [](int) { return true; });
+  o.Bt = pick(Lt, {4, 8, 2, 1}, [](int) { return true; });
   if (o.By == 0 || o.Bz == 0 || o.Bt == 0) return SiteOrder{};
   o.segw = Lx * o.By / kSiteGroup;
   o.on = 1;
   return o;
+}
+
+bool wilson_blocks_valid(const Lattice& lat, int By, int Bz, int Bt) {
+  if (By == 0 && Bz == 0 && Bt == 0) return true;
+  if (By < 0) return Bz <= 0 && Bt <= 0;
+  return By >= 1 && Bz >= 1 && Bt >= 1 && lat.L[1] % By == 0 && lat.L[2] % Bz == 0 && lat.L[3] % Bt == 0 &&
+         (lat.L[0] * By) % kSiteGroup == 0;
 }
 
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,

@@ -61,3 +61,38 @@ def test_autotune_sets_cached_neutral_shape(env, tmp_path):
         assert np.isfinite(y1.abs().sum().item())
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_stencil_walks_bitwise_equal(env):
+    sg, torch = env
+    from paper_0704_3486_amd.autotune import autotune_stencil
+
+    dims = (8, 8, 8, 16)
+    ctx = sg.sgn_create(synth.random_links(dims, 82), dims, 0.3, M_W)
+    try:
+        x = torch.from_numpy(synth.gaussian_source(dims, 8200)).cuda()
+        ref = torch.empty_like(x)
+        sg.sgn_matvec(ctx, x, ref)  # default order (natural at this size)
+        for blocks in ((4, 8, 4), (8, 4, 2), (4, 2, 16), (-1, 0, 0), (0, 0, 0)):
+            sg.sgn_set_stencil_blocks(ctx, *blocks)
+            y = torch.empty_like(x)
+            sg.sgn_matvec(ctx, x, y)
+            assert torch.equal(y, ref), blocks
+        for bad in ((3, 1, 1), (2, 8, 4), (4, 3, 4), (4, 8, 0)):  # 8*2 not a multiple of 32; not divisors
+            with pytest.raises(sg.SgnError) as e:
+                sg.sgn_set_stencil_blocks(ctx, *bad)
+            assert e.value.status == sg.SGN_EINVAL
+        r = autotune_stencil(ctx, reps=2)
+        print("stencil walk", r, flush=True)
+        y = torch.empty_like(x)
+        sg.sgn_matvec(ctx, x, y)
+        assert torch.equal(y, ref)
+        # an apply is unchanged by the walk
+        sg.sgn_deflate(ctx, 0)
+        y1, y2 = torch.empty_like(x), torch.empty_like(x)
+        sg.sgn_apply_fixed(ctx, x, y1, 40)
+        sg.sgn_set_stencil_blocks(ctx, -1)
+        sg.sgn_apply_fixed(ctx, x, y2, 40)
+        assert torch.equal(y1, y2)
+    finally:
+        sg.sgn_destroy(ctx)
