@@ -113,7 +113,7 @@ def main():
     from paper_0704_3486_amd.autotune import autotune
 
     if args.stencil_only:
-        print(json.dumps(stencil_leg(sg, synth, torch)))
+        print(json.dumps(stencil_leg(sg, synth, torch, tune=not args.no_autotune)))
         return
     if args.batched_only:
         print(json.dumps(batched_leg(sg, synth, torch)))
@@ -261,7 +261,7 @@ def main():
         pairs.append((S.cpu().numpy(), T))
         sg.sgn_destroy(c)
 
-    stencil = None if args.no_stencil else stencil_leg(sg, synth, torch)
+    stencil = None if args.no_stencil else stencil_leg(sg, synth, torch, tune=not args.no_autotune)
     batched = None if args.no_batched else batched_leg(sg, synth, torch)
     if stencil is not None and stencil_6 is not None:
         stencil["in_apply_6x6x6x6"] = stencil_6
@@ -418,7 +418,7 @@ def stored_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
-def stencil_leg(sg, synth, torch):
+def stencil_leg(sg, synth, torch, tune=True):
     """H_w(mu) x on a 32^4 lattice, FP64, one right-hand side: average kernel
     time from the library's HIP events and algorithmic GB/s (60 V 16 bytes:
     read v, write w, four links per site), beside a plain 2 GiB copy."""
@@ -429,7 +429,8 @@ def stencil_leg(sg, synth, torch):
     try:
         from paper_0704_3486_amd.autotune import autotune_stencil
 
-        walk = autotune_stencil(ctx)  # the walk order only (results bitwise the same)
+        # the walk order only (results bitwise the same); else the default walk
+        walk = autotune_stencil(ctx) if tune else {"blocks": (0, 0, 0)}
         x = torch.from_numpy(synth.gaussian_source(dims, 1000)).cuda()
         y = torch.empty_like(x)
         for _ in range(3):
