@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lr", action="store_true", help="skip the LR-deflation comparison on the mu=0.2 field")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 8^4 mixed-precision figures")
     ap.add_argument("--no-overlap", action="store_true", help="skip the overlap-operator figures on the mu=0.2 field")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape of the Arnoldi passes instead of timing the nine")
@@ -263,6 +264,7 @@ def main():
 
     stencil = None if args.no_stencil else stencil_leg(sg, synth, torch, tune=not args.no_autotune)
     batched = None if args.no_batched else batched_leg(sg, synth, torch)
+    mixed8 = None if args.no_mixed else mixed_leg(sg, synth, torch, tune=not args.no_autotune)
     if stencil is not None and stencil_6 is not None:
         stencil["in_apply_6x6x6x6"] = stencil_6
 
@@ -295,6 +297,7 @@ def main():
         "roofline": roofline,
         "stencil": stencil,
         "batched_mixed_12x12x12x12": batched,
+        "mixed_8x8x8x8": mixed8,
         "small_sign": sign,
         "overlap": ov,
         "lr_deflation": lrd,
@@ -316,6 +319,54 @@ def latency_schur(sg, torch, ctx, xs, reps=10):
         ks.append(sg.sgn_last_info(ctx)["k_used"])
     torch.cuda.synchronize()
     return {"ms_per_apply": round(1e3 * (time.perf_counter() - t0) / reps, 3), "mean_k": float(np.mean(ks))}
+
+
+def mixed_leg(sg, synth, torch, tune=True, reps=5):
+    """8^4, mu = 0.3, m = 30 Schur vectors: mixed precision (FP32 stencil and
+    Krylov basis, tol 1e-7) against FP64 (tol 1e-10), one source per apply,
+    one at a time on the same field and Schur pair: error of the seed-1000
+    source against the stored FP64 oracle result (k = 800), k and rate."""
+    from paper_0704_3486_amd.autotune import autotune
+
+    dims, mu, m = (8, 8, 8, 8), 0.3, 30
+    links = synth.random_links(dims, synth.GAUGE_SEED)
+    xs = [torch.from_numpy(synth.gaussian_source(dims, 1000 + r)).cuda() for r in range(reps)]
+    path = os.path.join(GOLDEN, "c8_mu0.3.npy")
+    ref = np.load(path, allow_pickle=False) if os.path.exists(path) else None
+    out = {"workload": f"8^4 (N={12 * 8 ** 4}), mu={mu}, m={m}, 1 RHS per apply, one at a time"}
+    ctxs = {}
+    try:
+        t0 = time.perf_counter()
+        for prec, tol in ((sg.SGN_PREC_MIXED, 1e-7), (sg.SGN_PREC_FP64, 1e-10)):
+            ctx = sg.sgn_create(links, dims, mu, M_W)
+            ctxs[prec] = ctx
+            sg.sgn_set_precision(ctx, prec)
+            if prec == sg.SGN_PREC_MIXED:
+                sg.sgn_deflate(ctx, m)
+                out["deflation_seconds"] = round(time.perf_counter() - t0, 2)
+                S, T, _ = sg.sgn_deflate_export(ctx)
+            else:
+                sg.sgn_deflate_import(ctx, S, T)
+            if tune:
+                autotune(ctx, k=300)
+            y = torch.empty_like(xs[0])
+            sg.sgn_apply(ctx, xs[0], y, tol, 800)
+            name = "mixed" if prec == sg.SGN_PREC_MIXED else "fp64"
+            entry = {"tol": tol, "k": sg.sgn_last_info(ctx)["k_used"]}
+            if ref is not None:
+                entry["rel_err_vs_fp64_oracle"] = float(np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for x in xs:
+                sg.sgn_apply(ctx, x, y, tol, 800)
+            torch.cuda.synchronize()
+            entry["applies_per_s"] = round(len(xs) / (time.perf_counter() - t1), 3)
+            out[name] = entry
+    finally:
+        for c in ctxs.values():
+            sg.sgn_destroy(c)
+    log(f"mixed 8^4: {out}")
+    return out
 
 
 def lr_leg(sg, synth, torch, mu, xs, schur, reps=10, tune=True):
