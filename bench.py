@@ -265,6 +265,7 @@ def main():
     stencil = None if args.no_stencil else stencil_leg(sg, synth, torch, tune=not args.no_autotune)
     batched = None if args.no_batched else batched_leg(sg, synth, torch)
     mixed8 = None if args.no_mixed else mixed_leg(sg, synth, torch, tune=not args.no_autotune)
+    small4 = None if args.no_mixed else c1_leg(sg, synth, torch)
     if stencil is not None and stencil_6 is not None:
         stencil["in_apply_6x6x6x6"] = stencil_6
 
@@ -298,6 +299,7 @@ def main():
         "stencil": stencil,
         "batched_mixed_12x12x12x12": batched,
         "mixed_8x8x8x8": mixed8,
+        "undeflated_4x4x4x4": small4,
         "small_sign": sign,
         "overlap": ov,
         "lr_deflation": lrd,
@@ -319,6 +321,33 @@ def latency_schur(sg, torch, ctx, xs, reps=10):
         ks.append(sg.sgn_last_info(ctx)["k_used"])
     torch.cuda.synchronize()
     return {"ms_per_apply": round(1e3 * (time.perf_counter() - t0) / reps, 3), "mean_k": float(np.mean(ks))}
+
+
+def c1_leg(sg, synth, torch, reps=20):
+    """4^4, mu = 0.3, no deflation, exactly k = 300 Arnoldi steps (FP64), one
+    source per apply: error of the seed-1000 source against its stored exact
+    sign (full diagonalisation) and the rate, one at a time."""
+    dims, mu, k = (4, 4, 4, 4), 0.3, 300
+    ctx = sg.sgn_create(synth.random_links(dims, synth.GAUGE_SEED), dims, mu, M_W)
+    try:
+        x = torch.from_numpy(synth.gaussian_source(dims, 1000)).cuda()
+        y = torch.empty_like(x)
+        sg.sgn_apply_fixed(ctx, x, y, k)
+        out = {"workload": f"4^4 (N=3072), mu={mu}, m=0, k={k} fixed, FP64, 1 RHS per apply, one at a time"}
+        path = os.path.join(GOLDEN, "c4_mu0.3.npy")
+        if os.path.exists(path):
+            exact = np.load(path, allow_pickle=False)
+            out["rel_err_vs_exact"] = float(np.linalg.norm(y.cpu().numpy() - exact) / np.linalg.norm(exact))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sg.sgn_apply_fixed(ctx, x, y, k)
+        torch.cuda.synchronize()
+        out["applies_per_s"] = round(reps / (time.perf_counter() - t0), 3)
+    finally:
+        sg.sgn_destroy(ctx)
+    log(f"4^4: {out}")
+    return out
 
 
 def mixed_leg(sg, synth, torch, tune=True, reps=5):
