@@ -69,3 +69,35 @@ def test_deflate_6x6_matches_arpack(env):
         assert stats["residual"] < 1e-10
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_deflation_krylov_size(env):
+    # the eigensolver's basis size changes the iteration, not the result: a
+    # narrow basis (about 2 nev), a wide one and the default all find the
+    # oracle's critical subspace; a negative size is rejected.  (The smallest
+    # basis, nev + 3, adds two vectors per restart and does not reach the
+    # 1e-13 residual within its restart limit on this lattice.)
+    sg, torch = env
+    dims, mu, m = (3, 3, 3, 4), 0.2, 6
+    links = synth.random_links(dims, 33)
+    A = wilson.hw_matrix(links, dims, mu, M_W)
+    S0, T0, lam0, _ = deflation.critical_from_dense(A.toarray(), m)
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        with pytest.raises(sg.SgnError) as e:
+            sg.sgn_set_deflation_krylov(ctx, -1)
+        assert e.value.status == sg.SGN_EINVAL
+        seen = []
+        for ncv in (32, 80, 0):
+            sg.sgn_set_deflation_krylov(ctx, ncv)
+            sg.sgn_deflate(ctx, m)
+            stats = sg.sgn_deflate_stats(ctx)
+            print("ncv", ncv, stats, flush=True)
+            S, T, _ = sg.sgn_deflate_export(ctx)
+            S = S.cpu().numpy()
+            _check_pair(A, S, T, lam0, m)
+            assert np.abs(S @ S.conj().T - S0 @ S0.conj().T).max() < 1e-9
+            seen.append(stats["matvecs"])
+        assert len(set(seen)) > 1  # the basis size took effect
+    finally:
+        sg.sgn_destroy(ctx)
