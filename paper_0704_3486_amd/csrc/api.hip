@@ -420,6 +420,11 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
         } else {
           nk = k + std::max(8, k / 2);
         }
+        // the model is fitted on early checkpoints, where the error often
+        // falls more slowly than later: extrapolate at most as far again as
+        // the steps already taken, so that a late checkpoint below the
+        // tolerance is followed by one that can certify it before kmax
+        nk = std::min(nk, 2 * k + 8);
         next_ck = std::min(kmax, even_up(std::max(nk, k + 2)));
       }
     }
