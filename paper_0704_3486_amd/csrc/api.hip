@@ -421,10 +421,10 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
           nk = k + std::max(8, k / 2);
         }
         // the model is fitted on early checkpoints, where the error often
-        // falls more slowly than later: extrapolate at most as far again as
-        // the steps already taken, so that a late checkpoint below the
-        // tolerance is followed by one that can certify it before kmax
-        nk = std::min(nk, 2 * k + 8);
+        // falls more slowly than later; a jump that would land on kmax
+        // leaves no later checkpoint to certify the result against, so
+        // such a jump goes at most as far again as the steps already taken
+        if (nk >= kmax) nk = std::min(nk, 2 * k + 8);
         next_ck = std::min(kmax, even_up(std::max(nk, k + 2)));
       }
     }

@@ -290,7 +290,7 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
     } else {
       nk = k + std::max(8, k / 2);
     }
-    nk = std::min(nk, 2 * k + 8);  // bounded extrapolation, as in sgn_apply
+    if (nk >= kwant) nk = std::min(nk, 2 * k + 8);  // bounded jump towards kmax, as in sgn_apply
     next_ck = std::min(kwant, even_k(std::max(nk, k + 2)));
     return true;
   };

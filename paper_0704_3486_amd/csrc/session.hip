@@ -227,7 +227,7 @@ struct sgn_session {
     } else {
       nk = k + std::max(8, k / 2);
     }
-    nk = std::min(nk, 2 * k + 8);  // bounded extrapolation, as in sgn_apply
+    if (nk >= sl.kreq) nk = std::min(nk, 2 * k + 8);  // bounded jump towards kmax, as in sgn_apply
     return std::min(sl.kreq, even_up2(std::max(nk, k + 2)));
   }
 
