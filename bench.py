@@ -6,10 +6,11 @@ ensembles), m_w = -1.6, three fields mu in {0.0, 0.2, 0.5}, m = 20 critical
 Schur vectors computed once per field by the library's own deflation setup,
 single right-hand side per apply, FP64, kmax = 500, tolerance 1e-10.
 
-A step is one sgn(H_w(mu)) x per field (three applies, distinct Gaussian
-sources).  The three fields are independent problems: each context runs on
-its own HIP stream, driven by its own host thread, so their latency-bound
-kernels overlap on the device.  The timed region covers exactly --steps
+A step is --per-field (default 2) sgn(H_w(mu)) x per field, each a
+single-source FP64 apply on a distinct Gaussian source.  The applies are
+independent: every field has that many contexts, each holding the field's
+links and Schur pair, on its own HIP stream and driven by its own host
+thread, so their latency-bound kernels overlap on the device.  The timed region covers exactly --steps
 steps with inputs resident in device memory, bracketed by device
 synchronisations; value = applies per second.  Also reported:
   * latency: the same steps run one apply at a time (ms per apply);
@@ -89,6 +90,9 @@ def main():
     ap.add_argument("--serving-mixed", action="store_true", help="serve in mixed precision")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 12^4 x 32-source mixed-precision batch and print its JSON object")
+    ap.add_argument("--per-field", type=int, default=2,
+                    help="applies in flight per field in the timed steps: one context and stream each, all "
+                         "holding the field's Schur pair")
     ap.add_argument("--serial", action="store_true",
                     help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
                          "whose per-kernel averages then compare with the HIP-event ones)")
@@ -148,7 +152,8 @@ def main():
         ctxs.append(ctx)
         streams.append(st)
 
-    nsrc = args.steps + args.warmup
+    P = 1 if args.serial else max(1, args.per_field)
+    nsrc = (args.steps + args.warmup) * P
     xs = [torch.from_numpy(synth.gaussian_source(DIMS, 1000 + r)).to(dev) for r in range(max(nsrc, 2))]
     ys = [torch.empty(N, dtype=torch.complex128, device=dev) for _ in MUS]
     torch.cuda.synchronize()
@@ -167,19 +172,49 @@ def main():
         acc[str(mu)] = entry
         log(f"accuracy mu={mu}: {entry}")
 
+    # further contexts per field (P applies of a field in flight): the same
+    # links and Schur pair, their own stream and output; the launch shape of
+    # the field's first context; one untimed apply of the seed-1000 source
+    # (the first context's accuracy apply) so every context starts from the
+    # same remembered checkpoint
+    lanes = [(ctxs[f], ys[f]) for f in range(len(MUS))]
+    extra = []
+    for p in range(1, P):
+        for f, mu in enumerate(MUS):
+            c = sg.sgn_create(links, DIMS, mu, M_W)
+            extra.append(c)
+            st = torch.cuda.Stream(device=dev)
+            streams.append(st)
+            sg.sgn_set_stream(c, st.cuda_stream)
+            S, T, _ = sg.sgn_deflate_export(ctxs[f])
+            sg.sgn_deflate_import(c, S, T)
+            sg.sgn_set_tuning(c, *sg.sgn_get_tuning(ctxs[f]))
+            y = torch.empty(N, dtype=torch.complex128, device=dev)
+            sg.sgn_apply(c, xs[0], y, TOL, KMAX)
+            lanes.append((c, y))
+    torch.cuda.synchronize()
+
     def field_steps(f, first, count, ks):
         for r in range(first, first + count):
             sg.sgn_apply(ctxs[f], xs[r % len(xs)], ys[f], TOL, KMAX)
             ks.append(sg.sgn_last_info(ctxs[f])["k_used"])
 
+    def lane_steps(q, first, count, ks):
+        # lane q = p * len(MUS) + f takes source r * P + p of step r
+        c, y = lanes[q]
+        p = q // len(MUS)
+        for r in range(first, first + count):
+            sg.sgn_apply(c, xs[(r * P + p) % len(xs)], y, TOL, KMAX)
+            ks.append(sg.sgn_last_info(c)["k_used"])
+
     def run_concurrent(first, count):
-        ks = [[] for _ in MUS]
-        th = [threading.Thread(target=field_steps, args=(f, first, count, ks[f])) for f in range(len(MUS))]
+        ks = [[] for _ in lanes]
+        th = [threading.Thread(target=lane_steps, args=(q, first, count, ks[q])) for q in range(len(lanes))]
         for t in th:
             t.start()
         for t in th:
             t.join()
-        return [k for kf in ks for k in kf]
+        return [k for kq in ks for k in kq]
 
     def run_serial(first, count):
         ks = []
@@ -195,9 +230,9 @@ def main():
     ks = runner(args.warmup, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    applies = args.steps * len(MUS)
+    applies = args.steps * len(lanes)
     value = applies / elapsed
-    mode = "serial" if args.serial else "3 streams"
+    mode = "serial" if args.serial else f"{len(lanes)} streams"
     log(f"timed ({mode}): {applies} applies in {elapsed:.3f} s -> {value:.2f} applies/s, mean k {np.mean(ks):.1f}")
 
     torch.cuda.synchronize()
@@ -205,9 +240,12 @@ def main():
     run_serial(args.warmup, args.steps)
     torch.cuda.synchronize()
     elapsed_serial = time.perf_counter() - t0
-    latency = {"ms_per_apply": round(1e3 * elapsed_serial / applies, 3),
-               "applies_per_s_one_at_a_time": round(applies / elapsed_serial, 3)}
+    n_serial = args.steps * len(MUS)
+    latency = {"ms_per_apply": round(1e3 * elapsed_serial / n_serial, 3),
+               "applies_per_s_one_at_a_time": round(n_serial / elapsed_serial, 3)}
     log(f"serial: {latency}")
+    for c in extra:
+        sg.sgn_destroy(c)
 
     # profiled pass over the same steps, one apply at a time (HIP events on
     # each context's stream)
@@ -288,8 +326,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sgn(H_w(mu))x, 6^4 lattice (N=15552), m_w=-1.6, mu in {0.0,0.2,0.5}, "
                                "m=20 Schur deflation, kmax=500, tol=1e-10, FP64, 1 RHS per apply, "
-                               "3 applies per step (one per field"
-                               + (", one at a time)" if args.serial else ", fields on separate streams)"),
+                               + ("3 applies per step (one per field, one at a time)" if args.serial else
+                                  f"{len(lanes)} applies per step ({P} per field in flight, one context and "
+                                  "stream each)"),
+                   "applies_in_flight_per_field": P,
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
                    "mean_k": round(float(np.mean(ks)), 1)},
         "accuracy": acc,
