@@ -141,7 +141,10 @@ int sgn_deflate_export(const sgn_ctx* ctx, double* S, double* T, double* evals);
  * cycle, of which about (ncv + nev) / 2 are kept at a restart; nev =
  * m + max(10, m / 2).  0 restores the default max(3 nev, nev + 40); values
  * below nev + 3 are raised to it, above N - 1 lowered to it.  SGN_EINVAL for
- * ncv < 0.  Device memory grows by 2 ncv N complex128 during the setup. */
+ * ncv < 0.  A fixed ncv is not enlarged when the solver stalls: a basis of
+ * only a few vectors more than nev gains little per restart and can end in
+ * SGN_EDEFL (no convergence within 3000 restarts); about 2 nev or more is
+ * safe.  Device memory grows by 2 ncv N complex128 during the setup. */
 int sgn_set_deflation_krylov(sgn_ctx* ctx, int ncv);
 
 /* Number of installed deflation vectors, Schur or LR (0 if none, <0 on error). */
