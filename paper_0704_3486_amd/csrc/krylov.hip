@@ -47,6 +47,24 @@ __device__ inline double2 ld2(const float2* p, size_t i) {
 __device__ inline void st2(double2* p, size_t i, double2 v) { p[i] = v; }
 __device__ inline void st2(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
 
+// two adjacent rows il, il + 1 of one column (il even): FP32 columns in one
+// 16-byte load per lane, FP64 columns in two
+__device__ inline void ld_pair(const double2* __restrict__ p, int il, double2& q0, double2& q1) {
+  q0 = p[il];
+  q1 = p[il + 1];
+}
+__device__ inline void ld_pair(const float2* __restrict__ p, int il, double2& q0, double2& q1) {
+  const float4 v = *reinterpret_cast<const float4*>(p + il);
+  q0 = make_double2((double)v.x, (double)v.y);
+  q1 = make_double2((double)v.z, (double)v.w);
+}
+
+// Rows per lane group of the dot and update passes: 1 with FP64 Krylov
+// columns, 2 with FP32 columns, whose lanes then take adjacent row pairs so
+// that a column load is 16 bytes per lane
+template <typename VT>
+constexpr int rows_per_lane() { return sizeof(VT) == 8 ? 2 : 1; }
+
 __device__ inline double2 wsum2(double2 v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -82,12 +100,25 @@ __device__ inline int step_of(const KrylovArgs& A, int z) { return A.jdev ? *A.j
 // the partials are reduced by kred_kernel in a fixed order.
 // the rows past N carry zero weights (uv = zv = 0 there) and load a valid
 // row instead: unconditional loads, all in flight together
-template <typename QT>
+// Row of a lane's slot t in a tile: R = 1, row0 + 64 t + lane; R = 2 (FP32
+// columns), the pair row0 + 128 (t / 2) + 2 lane + {0, 1}
+template <int R>
+__device__ inline int dot_row(int row0, int t, int lane) {
+  return R == 1 ? row0 + t * 64 + lane : row0 + (t >> 1) * 128 + 2 * lane + (t & 1);
+}
+
+template <typename QT, int R>
 __device__ inline void dot_cols(const QT* __restrict__ q, const double2 uv[kRpl], const double2 zv[kRpl], int row0,
                                 int lane, int N, double2& aa, double2& bb) {
   double2 qv[kRpl];
+  if constexpr (R == 1) {
 #pragma unroll
-  for (int t = 0; t < kRpl; ++t) qv[t] = ld2(q, min(row0 + t * 64 + lane, N - 1));
+    for (int t = 0; t < kRpl; ++t) qv[t] = ld2(q, min(dot_row<1>(row0, t, lane), N - 1));
+  } else {
+    // N is even, so a pair lies wholly below N or wholly at or above it
+#pragma unroll
+    for (int t = 0; t < kRpl; t += 2) ld_pair(q, min(dot_row<2>(row0, t, lane), N - 2), qv[t], qv[t + 1]);
+  }
 #pragma unroll
   for (int t = 0; t < kRpl; ++t) {
     aa = cfmac(qv[t], uv[t], aa);
@@ -99,6 +130,7 @@ __device__ inline void dot_cols(const QT* __restrict__ q, const double2 uv[kRpl]
 // tile; column group cg holds columns [4 CPW cg, 4 CPW (cg + 1)), CPW per wavefront
 template <typename VT, int CPW>
 __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
+  constexpr int R = rows_per_lane<VT>();
   const int zb = blockIdx.x % A.nb, rest = blockIdx.x / A.nb;
   const int rt = rest % A.nrt_dot, cg = rest / A.nrt_dot;
   const int r = slot_of(A, zb);
@@ -114,7 +146,7 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
   double2 uv[kRpl], zv[kRpl];
 #pragma unroll
   for (int t = 0; t < kRpl; ++t) {
-    const int i = row0 + t * 64 + lane;
+    const int i = dot_row<R>(row0, t, lane);
     uv[t] = (i < N) ? u[i] : make_double2(0.0, 0.0);
     zv[t] = (with_z && i < N) ? ld2(z, i) : make_double2(0.0, 0.0);
   }
@@ -125,10 +157,10 @@ __global__ void __launch_bounds__(256) kdot_kernel(KrylovArgs A, int with_z) {
     if (c < J) {
       double2 aa = make_double2(0.0, 0.0), bb = make_double2(0.0, 0.0);
       if (c < A.m) {
-        dot_cols<double2>(A.S + (size_t)c * A.ldq, uv, zv, row0, lane, N, aa, bb);
+        dot_cols<double2, R>(A.S + (size_t)c * A.ldq, uv, zv, row0, lane, N, aa, bb);
       } else {
         const VT* q = static_cast<const VT*>(A.V) + (size_t)r * A.vstride + (size_t)(c - A.m) * A.ldq;
-        dot_cols<VT>(q, uv, zv, row0, lane, N, aa, bb);
+        dot_cols<VT, R>(q, uv, zv, row0, lane, N, aa, bb);
       }
       aa = wsum2(aa);
       bb = wsum2(bb);
@@ -362,19 +394,54 @@ __device__ inline void sweep_cols(const QT* __restrict__ base, int cofs, size_t 
 }
 
 
+// sweep_cols for two adjacent rows per lane: each row's sums take the same
+// columns in the same order as sweep_cols, so the results are bitwise those
+// of one row per lane
+template <typename QT, int KB, int NW>
+__device__ inline void sweep_cols_pair(const QT* __restrict__ base, int cofs, size_t ldq, int c, int cend, int il,
+                                       const double2* __restrict__ av, const double2* __restrict__ bv,
+                                       double2 (&sa)[2], double2 (&sb)[2]) {
+  const double2 zero = make_double2(0.0, 0.0);
+  for (; c < cend; c += KB * NW) {
+    double2 q0[KB], q1[KB], ca[KB], cb[KB];
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+      const int cc = c + t * NW, cl = min(cc, cend - 1);
+      ld_pair(base + (size_t)(cl - cofs) * ldq, il, q0[t], q1[t]);
+      ca[t] = av[cl];
+      cb[t] = bv[cl];
+      if (cc >= cend) {
+        ca[t] = zero;
+        cb[t] = zero;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+      sa[0] = cfma(q0[t], ca[t], sa[0]);
+      sb[0] = cfma(q0[t], cb[t], sb[0]);
+      sa[1] = cfma(q1[t], ca[t], sa[1]);
+      sb[1] = cfma(q1[t], cb[t], sb[1]);
+    }
+  }
+}
+
 // first column >= m that wavefront w of NW takes (c = w mod NW)
 template <int NW>
 __device__ inline int first_col(int m, int w) { return m + ((w - m % NW) + NW) % NW; }
 
 // update pass.  Per slot, the first nh workgroups compute the Hessenberg
-// column J (one row per wavefront), the next nblk each own 64 rows and all J
-// columns: their NW wavefronts take interleaved columns, combined in LDS in a
-// fixed order.  Workgroup id = z + nb b (batch position fastest).  Both kinds
-// compute the step scalars; the Hessenberg rows, a strided gather, so run
-// beside the sweeps instead of after them.
+// column J (one row per wavefront), the next nblk each own 64 R rows and all
+// J columns: their NW wavefronts take interleaved columns, combined in LDS in
+// a fixed order.  R = 1 for FP64 columns; R = 2 for FP32 columns, whose lanes
+// then take two adjacent rows each, so that a column load is 16 bytes per
+// lane (every row's sums are the same as with R = 1).  Workgroup id = z + nb b
+// (batch position fastest).  Both kinds compute the step scalars; the
+// Hessenberg rows, a strided gather, so run beside the sweeps instead of
+// after them.
 template <typename VT, int KB, int NW>
 __global__ void __launch_bounds__(64 * NW) kupdate_kernel(KrylovArgs A, int nh) {
   constexpr int NT = 64 * NW;
+  constexpr int R = rows_per_lane<VT>();
   const int zb = blockIdx.x % A.nb, bb = blockIdx.x / A.nb;
   const int r = slot_of(A, zb);
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
@@ -407,18 +474,31 @@ __global__ void __launch_bounds__(64 * NW) kupdate_kernel(KrylovArgs A, int nh) 
     return;
   }
   const int blk = bb - nh;
-  const int i = blk * 64 + lane;
-  const bool ok = i < N;
+  const int i = blk * 64 * R + R * lane;  // this lane's first row
+  const bool ok = i < N;                  // N is even: with R = 2, row i + 1 < N too
   // sweep: sa = Q a, sb = Q b (the step scalars enter only afterwards:
   // Q (b - gr a) = sb - gr sa)
-  double2 sa = zero, sb = zero;
-  const int il = ok ? i : N - 1;
-  sweep_cols<double2, true, KB, NW>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
-  sweep_cols<VT, true, KB, NW>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
-                               first_col<NW>(A.m, wave), J, il, av, bv, sa, sb);
-  __shared__ double2 ps[2][NW][64];
-  ps[0][wave][lane] = sa;
-  ps[1][wave][lane] = sb;
+  __shared__ double2 ps[2][NW][64 * R];
+  const int il = ok ? i : N - R;
+  if constexpr (R == 1) {
+    double2 sa = zero, sb = zero;
+    sweep_cols<double2, true, KB, NW>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
+    sweep_cols<VT, true, KB, NW>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
+                                 first_col<NW>(A.m, wave), J, il, av, bv, sa, sb);
+    ps[0][wave][lane] = sa;
+    ps[1][wave][lane] = sb;
+  } else {
+    // FP64 Schur columns take two loads per lane: half the batch keeps the
+    // bytes in flight (the batch size does not change any sum)
+    double2 sa[2] = {zero, zero}, sb[2] = {zero, zero};
+    sweep_cols_pair<double2, (KB > 4 ? KB / 2 : 2), NW>(A.S, 0, A.ldq, wave, min(J, A.m), il, av, bv, sa, sb);
+    sweep_cols_pair<VT, KB, NW>(static_cast<const VT*>(A.V) + (size_t)r * A.vstride, A.m, A.ldq,
+                                first_col<NW>(A.m, wave), J, il, av, bv, sa, sb);
+    ps[0][wave][2 * lane] = sa[0];
+    ps[0][wave][2 * lane + 1] = sa[1];
+    ps[1][wave][2 * lane] = sb[0];
+    ps[1][wave][2 * lane + 1] = sb[1];
+  }
   load_coef();
   scalar_partials<NT>(av, bv, J, a0, b0, a1, b1, s0, s12);
   const StepScalars st = step_scalars<NW>(A, r, j, s0, s12, red);  // contains __syncthreads
@@ -445,23 +525,32 @@ __global__ void __launch_bounds__(64 * NW) kupdate_kernel(KrylovArgs A, int nh) 
   }
   // combine the wavefronts (fixed order) and write v_J and u'
   if (wave == 0 && ok) {
-    double2 ta = ps[0][0][lane], tb = ps[1][0][lane];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      ta = cadd(ta, ps[0][w][lane]);
-      tb = cadd(tb, ps[1][w][lane]);
-    }
-    const double2 te = csub(tb, cmul(st.gr, ta));
     // u may be updated in place (unext == u): each lane reads its u[i]
     // before writing u'[i], and no other thread of the step touches row i of u
     const double2* u = A.u + (size_t)r * A.ustride;
     const VT* __restrict__ z = static_cast<const VT*>(A.z) + (size_t)r * A.zstride;
     VT* vout = static_cast<VT*>(A.V) + (size_t)r * A.vstride + (size_t)(J - A.m) * A.ldq;
-    const double2 ui = u[i];
-    st2(vout, i, cscale(csub(ui, ta), st.inv));
-    const double2 nx = cscale(csub(csub(ld2(z, i), cmul(st.gr, ui)), te), st.inv);
-    A.unext[(size_t)r * A.ustride + i] = nx;
-    if (A.ulonext) st2(static_cast<VT*>(A.ulonext) + (size_t)r * A.zstride, i, nx);
+    double2 vo[R], nx[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = R * lane + q;
+      double2 ta = ps[0][0][row], tb = ps[1][0][row];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        ta = cadd(ta, ps[0][w][row]);
+        tb = cadd(tb, ps[1][w][row]);
+      }
+      const double2 te = csub(tb, cmul(st.gr, ta));
+      const double2 ui = u[i + q];
+      vo[q] = cscale(csub(ui, ta), st.inv);
+      nx[q] = cscale(csub(csub(ld2(z, i + q), cmul(st.gr, ui)), te), st.inv);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      st2(vout, i + q, vo[q]);
+      A.unext[(size_t)r * A.ustride + i + q] = nx[q];
+      if (A.ulonext) st2(static_cast<VT*>(A.ulonext) + (size_t)r * A.zstride, i + q, nx[q]);
+    }
   }
 }
 
@@ -602,11 +691,22 @@ static auto update_kernel_for(const KrylovTune& t) {
   return t.uw == 16 ? update_kernel_nw<VT, 16>(t.ub) : update_kernel_nw<VT, 8>(t.ub);
 }
 
+// 16-byte loads of row pairs of the FP32 columns (dot and update passes)
+template <typename VT>
+static void check_pairs(const KrylovArgs& A) {
+  static_assert(kRpl % 2 == 0, "dot tiles hold whole row pairs");
+  if (rows_per_lane<VT>() == 2) {
+    SGN_REQUIRE(A.N % 2 == 0 && A.ldq % 2 == 0 && A.vstride % 2 == 0 && (reinterpret_cast<uintptr_t>(A.V) & 15) == 0,
+                SGN_EINVAL, "krylov: FP32 basis needs an even row count and strides and a 16-byte aligned base");
+  }
+}
+
 template <typename VT>
 void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStream_t s, Profiler* prof) {
   KrylovArgs A = Ain;
   krylov_bind(w, A);
   check_args(w, A);
+  check_pairs<VT>(A);
   SGN_REQUIRE(krylov_tune_valid(A.tune), SGN_EINVAL, "krylov: invalid launch shape");
   const int Jmax = A.m + A.jmax();
   const int gcols = 4 * A.tune.cpw;
@@ -634,9 +734,12 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   check_args(w, A);
   SGN_REQUIRE(A.m + A.jmax() + 1 <= A.ldh, SGN_EINVAL, "krylov: H too small");
   SGN_REQUIRE(krylov_tune_valid(A.tune), SGN_EINVAL, "krylov: invalid launch shape");
-  // per slot: Hessenberg-row workgroups for rows 0..m+jmax, then the 64-row blocks
+  // per slot: Hessenberg-row workgroups for rows 0..m+jmax, then the blocks
+  // of 64 R rows
   const int nh = (A.m + A.jmax() + 1 + A.tune.uw - 1) / A.tune.uw;
-  const size_t nwg = ((size_t)((A.N + 63) / 64) + nh) * A.nb;
+  const int rows = 64 * rows_per_lane<VT>();
+  check_pairs<VT>(A);
+  const size_t nwg = ((size_t)((A.N + rows - 1) / rows) + nh) * A.nb;
   const int nthr = 64 * A.tune.uw;
   SGN_REQUIRE(nwg * nthr < (size_t(1) << 32), SGN_EINVAL, "krylov: update grid too large");
   const double vb = (double)sizeof(VT);
