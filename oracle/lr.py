@@ -13,6 +13,10 @@ K_k(A, x_-):  f(A) x ~ R f(Lambda) L^dag x + beta V_k f(H_k) e_1.
 The algorithm's steps, as the paper lists them: (i) left and right
 eigenvectors of the critical eigenvalues, (ii) f(lambda_i), (iii) x_-,
 (iv) the Arnoldi basis V_k and H_k = V_k^dag A V_k, (v) f(H_k), (vi) the sum.
+
+The same pair serves the adjoint f(A)^dag x = f(A^dag) x (the remark closing
+the subsection): A^dag L = L conj(Lambda) and R^dag A^dag = conj(Lambda) R^dag,
+so L and R exchange roles, with R^dag L = I.
 """
 from __future__ import annotations
 
@@ -47,3 +51,11 @@ def sgn_lr_deflated(A, x: np.ndarray, k: int, R: np.ndarray, L: np.ndarray, lam:
         fH = sgn_spectral(st.Hbar[: st.k, : st.k])
         y = y + st.V[:, : st.k] @ (st.beta * fH[:, 0])         # Eq. (fAxLRArn)
     return y
+
+
+def sgn_lr_adjoint(A, x: np.ndarray, k: int, R: np.ndarray, L: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """sgn(A)^dag x by the LR-deflated method on A^dag: the left eigenvectors
+    L are A^dag's right eigenvectors and R its left ones, for the eigenvalues
+    conj(Lambda); the Krylov space is K_k(A^dag, (1 - L R^dag) x)."""
+    Ah = A.conj().T
+    return sgn_lr_deflated(Ah, x, k, L, R, np.conj(lam))

@@ -80,3 +80,29 @@ def test_dropping_the_projection_is_detected(case):
     st = modified_arnoldi(lambda v: A @ v, x, None, 40)
     y = R @ (matfunc.sgn_scalar(lam) * c) + st.V[:, :40] @ (st.beta * matfunc.sgn_spectral(st.Hbar[:40, :40])[:, 0])
     assert np.abs(L.conj().T @ y - L.conj().T @ exact).max() > 1e-3 * np.linalg.norm(x)
+
+
+def test_adjoint_full_grade_and_inner_products(case):
+    # the adjoint by LR-deflation on A^dag (roles of L and R exchanged): at
+    # full grade it is sgn(A)^dag x exactly, and <y, sgn(A) x> = <sgn(A)^dag y, x>
+    A, Am, R, L, lam, x, exact = case
+    N = A.shape[0]
+    y = synth.gaussian_source((2, 2, 2, 4), 4101)
+    Sgn = matfunc.sgn_spectral(A)
+    ya = lr.sgn_lr_adjoint(A, y, N - M, R, L, lam)
+    assert _rel(ya, Sgn.conj().T @ y) < 1e-10
+    lhs = np.vdot(y, Sgn @ x)
+    rhs = np.vdot(ya, x)
+    assert abs(lhs - rhs) < 1e-10 * np.linalg.norm(x) * np.linalg.norm(y)
+    # A^dag is H_w(-mu): the adjoint is the sign of the -mu operator
+    assert _rel(ya, matfunc.sgn_spectral(Am) @ y) < 1e-10
+
+
+def test_adjoint_critical_components_exact_for_every_k(case):
+    # R^dag sgn(A)^dag y = sgn(conj Lambda) R^dag y exactly, whatever k
+    A, _, R, L, lam, _, _ = case
+    y = synth.gaussian_source((2, 2, 2, 4), 4102)
+    for k in (0, 5, 40):
+        ya = lr.sgn_lr_adjoint(A, y, k, R, L, lam)
+        crit = R.conj().T @ ya - matfunc.sgn_scalar(np.conj(lam)) * (R.conj().T @ y)
+        assert np.abs(crit).max() < 1e-11 * np.linalg.norm(y)
