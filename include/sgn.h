@@ -216,6 +216,18 @@ int sgn_overlap_apply(sgn_ctx* ctx, const double* x, double* y, double tol, int 
 int sgn_overlap_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double tol, int kmax,
                               sgn_info* info);
 
+/* The adjoint y = sgn(H_w(mu))^dag x = sgn(H_w(-mu)) x (the LR-deflation
+ * subsection's closing remark: the left and right eigenvectors exchange
+ * roles).  Runs the method on A^dag = H_w(-mu) with the installed LR pair
+ * (sgn_deflate_lr or sgn_deflate_lr_import), L as A^dag's right and R as its
+ * left eigenvectors for conj(Lambda), or with no deflation; tol, kmax,
+ * status and sgn_last_info as for sgn_apply, and the fixed form as
+ * sgn_apply_fixed.  SGN_ESTATE with a Schur pair installed (a Schur basis of
+ * A is none of A^dag) or while a serving session is open on the context.
+ * Captured step graphs (sgn_set_step_graphs) are not used by these calls. */
+int sgn_apply_adjoint(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
+int sgn_apply_adjoint_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
+
 /* ---- serving: continuous batching on one resident field ---------------- */
 
 /* A session keeps up to max_slots (1..64) requests of one context in flight,

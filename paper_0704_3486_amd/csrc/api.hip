@@ -794,6 +794,52 @@ int sgn_apply_fixed(sgn_ctx* c, const double* x, double* y, int k) {
   });
 }
 
+// The adjoint problem on this context, for the duration of one apply:
+// A^dag = H_w(mu)^dag = H_w(-mu) (the time hops' e^{+mu} and e^{-mu}
+// exchanged), with the LR pair's roles exchanged (L holds A^dag's right
+// eigenvectors and R its left ones, for conj(Lambda), whose signs are those of
+// Lambda).  Captured step graphs hold the forward phases among their kernel
+// arguments, so none are replayed meanwhile.
+struct AdjointScope {
+  sgn_ctx* c;
+  int graph_steps;
+  explicit AdjointScope(sgn_ctx* cc) : c(cc), graph_steps(cc->graph_steps) {
+    std::swap(c->lat.emu, c->lat.emmu);
+    std::swap(c->lrR, c->lrL);
+    c->graph_steps = 0;
+  }
+  ~AdjointScope() {
+    std::swap(c->lat.emu, c->lat.emmu);
+    std::swap(c->lrR, c->lrL);
+    c->graph_steps = graph_steps;
+  }
+};
+
+static int run_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int kmax, int fixed_k) {
+  SGN_REQUIRE(c->m == 0, SGN_ESTATE,
+              "the adjoint needs an LR pair (sgn_deflate_lr) or no deflation: a Schur basis of A is none of A^dag");
+  SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session runs on this field");
+  AdjointScope scope(c);
+  return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), tol, kmax, fixed_k);
+}
+
+int sgn_apply_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int kmax) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    return run_adjoint(c, x, y, tol, kmax, -1);
+  });
+}
+
+int sgn_apply_adjoint_fixed(sgn_ctx* c, const double* x, double* y, int k) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
+    SGN_REQUIRE(k >= 0 && k <= c->N - c->m, SGN_EINVAL, "k must satisfy 0 <= k <= N - m");
+    return run_adjoint(c, x, y, 1.0, k, k);
+  });
+}
+
 int sgn_debug_hessenberg(const sgn_ctx* cc, int n, double* H, double* c0, double* beta) {
   sgn_ctx* c = const_cast<sgn_ctx*>(cc);
   return guarded(c, [&] {

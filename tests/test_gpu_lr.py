@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import lr, matfunc, overlap, wilson
+from oracle import deflation, lr, matfunc, overlap, wilson
 
 pytestmark = pytest.mark.gpu
 
@@ -230,5 +230,86 @@ def test_lr_c2_field_vs_stored_exact(env):
         assert sg.sgn_apply(ctx, x, y, 1e-11, 500) == sg.SGN_OK
         print("LR 6^4", sg.sgn_last_info(ctx), flush=True)
         assert _rel(y.cpu().numpy(), exact) < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_adjoint_matches_oracle_and_exact(env, case):
+    # sgn(A)^dag x with the same LR pair, L and R exchanged, on A^dag = H_w(-mu)
+    sg, torch = env
+    A, R, L, lam, Sgn, X = case[3], case[4], case[5], case[6], case[7], case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        x = torch.from_numpy(X[0]).cuda()
+        y = torch.empty_like(x)
+        for k in (10, 60):
+            sg.sgn_apply_adjoint_fixed(ctx, x, y, k)
+            ref = lr.sgn_lr_adjoint(A, X[0], k, R, L, lam)
+            print("adjoint k", k, _rel(y.cpu().numpy(), ref), flush=True)
+            assert _rel(y.cpu().numpy(), ref) < 1e-10
+        assert sg.sgn_apply_adjoint(ctx, x, y, 1e-11, 600) == sg.SGN_OK
+        ya = y.cpu().numpy()
+        assert _rel(ya, Sgn.conj().T @ X[0]) < 1e-9
+        # <w, sgn(A) x> = <sgn(A)^dag w, x>, both sides through the GPU
+        w = torch.from_numpy(X[1]).cuda()
+        sw = torch.empty_like(w)
+        assert sg.sgn_apply(ctx, w, sw, 1e-11, 600) == sg.SGN_OK
+        lhs = np.vdot(X[0], sw.cpu().numpy())
+        rhs = np.vdot(ya, X[1])
+        assert abs(lhs - rhs) < 1e-9 * np.linalg.norm(X[0]) * np.linalg.norm(X[1])
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_adjoint_leaves_the_forward_problem_and_ignores_graphs(env, case):
+    sg, torch = env
+    X = case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        x = torch.from_numpy(X[0]).cuda()
+        f0, f1, a0, a1 = (torch.empty_like(x) for _ in range(4))
+        sg.sgn_apply_fixed(ctx, x, f0, 40)
+        sg.sgn_apply_adjoint_fixed(ctx, x, a0, 40)
+        sg.sgn_set_step_graphs(ctx, 8)  # captured steps hold the forward phases
+        sg.sgn_apply_fixed(ctx, x, f1, 40)
+        sg.sgn_apply_adjoint_fixed(ctx, x, a1, 40)
+        assert torch.equal(a0, a1)
+        sg.sgn_apply_fixed(ctx, x, a1, 40)
+        assert torch.equal(f0, f1) and torch.equal(f0, a1)
+        assert not torch.equal(f0, a0)
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_adjoint_states(env, case):
+    # a Schur pair is refused; no deflation runs the plain method on H_w(-mu)
+    sg, torch = env
+    dims, mu, links, A, R, L, lam, Sgn, X = case
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        x = torch.from_numpy(X[0]).cuda()
+        y = torch.empty_like(x)
+        assert sg.sgn_apply_adjoint(ctx, x, y, 1e-11, x.numel()) == sg.SGN_OK
+        assert _rel(y.cpu().numpy(), Sgn.conj().T @ X[0]) < 1e-9
+        Am = wilson.hw_matrix(links, dims, -mu, M_W).toarray()
+        assert np.abs(Am - A.conj().T).max() < 1e-14  # the operator the adjoint runs on
+        S, T, _, _ = deflation.critical_from_dense(A, 8)
+        sg.sgn_deflate_import(ctx, torch.from_numpy(S).cuda(), T)
+        with pytest.raises(sg.SgnError) as e:
+            sg.sgn_apply_adjoint(ctx, x, y, 1e-10, 300)
+        assert e.value.status == sg.SGN_ESTATE
+    finally:
+        sg.sgn_destroy(ctx)
+
+
+def test_lr_adjoint_mixed_precision(env, case):
+    sg, torch = env
+    Sgn, X = case[7], case[8]
+    ctx = _lr_ctx(sg, torch, case, prec=1)
+    try:
+        x = torch.from_numpy(X[1]).cuda()
+        y = torch.empty_like(x)
+        assert sg.sgn_apply_adjoint(ctx, x, y, 1e-7, 600) == sg.SGN_OK
+        assert _rel(y.cpu().numpy(), Sgn.conj().T @ X[1]) < 1e-6
     finally:
         sg.sgn_destroy(ctx)
