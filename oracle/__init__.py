@@ -22,7 +22,8 @@ Contents, each following the paper (Bloch, Frommer, Lang, Wettig 2007):
                    (Eq. Dov) and its Ginsparg-Wilson defect (Eq. GW:eq)
   * lr          -- LR-deflation: left/right critical eigenvectors and the
                    approximation R f(Lambda) L^dag x + beta V_k f(H_k) e_1
-                   (Eqs. Rev, Lev, xdec, fARLx, LRArnoldi, fAxLRArn)
+                   (Eqs. Rev, Lev, xdec, fARLx, LRArnoldi, fAxLRArn), and
+                   the adjoint sgn(A)^dag x from the same pair
                    on H_w^2 as in the Results section
 
 Parity status: every function listed above is pinned by the CPU tests in
