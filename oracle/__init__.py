@@ -18,13 +18,13 @@ Contents, each following the paper (Bloch, Frommer, Lang, Wettig 2007):
                    eq:formula) and the undeflated Arnoldi (Eq. yproj3)
   * deflation   -- partial Schur pair (S_m, T_m) from critical eigenvectors
                    (Eq. pSd), from a dense eigendecomposition or from ARPACK
+                   on H_w^2 as in the Results section
   * overlap     -- the overlap operator D_ov(mu) = 1 + gamma5 sgn(H_w(mu))
                    (Eq. Dov) and its Ginsparg-Wilson defect (Eq. GW:eq)
   * lr          -- LR-deflation: left/right critical eigenvectors and the
                    approximation R f(Lambda) L^dag x + beta V_k f(H_k) e_1
                    (Eqs. Rev, Lev, xdec, fARLx, LRArnoldi, fAxLRArn), and
                    the adjoint sgn(A)^dag x from the same pair
-                   on H_w^2 as in the Results section
 
 Parity status: every function listed above is pinned by the CPU tests in
 tests/test_oracle_*.py against facts the paper and the mathematics fix
