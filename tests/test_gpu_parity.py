@@ -59,7 +59,7 @@ def test_matvec_matches_oracle(env, dims, mu):
         sg.sgn_destroy(ctx)
 
 
-@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (20, 16, 16, 16), (16, 8, 32, 16)])
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (20, 16, 16, 16), (16, 8, 32, 16), (24, 24, 24, 28)])
 def test_matvec_large_pure_gauge(env, dims):
     """Lattices large enough for the blocked site order of the stencil: no
     dense oracle fits, so the exact relation H[U] (Omega x) = Omega H[1] x for
