@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--serving-sustained", type=int, default=400,
                     help="arrivals of the second stream, at 70%% of the served rate")
     ap.add_argument("--serving-mixed", action="store_true", help="serve in mixed precision")
+    ap.add_argument("--m-scan", action="store_true",
+                    help="only the deflation-size scan (setup time, k and time per apply against m) and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 12^4 x 32-source mixed-precision batch and print its JSON object")
     ap.add_argument("--per-field", type=int, default=2,
@@ -126,6 +128,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps(batched_leg(sg, synth, torch)))
+        return
+    if args.m_scan:
+        print(json.dumps(m_scan_leg(sg, synth, torch)))
         return
     if args.serving:
         print(json.dumps(serving_leg(sg, synth, torch, args.serving_rate, args.serving_requests, args.serving_sustained,
@@ -376,6 +381,53 @@ def latency_schur(sg, torch, ctx, xs, reps=10):
         ks.append(sg.sgn_last_info(ctx)["k_used"])
     torch.cuda.synchronize()
     return {"ms_per_apply": round(1e3 * (time.perf_counter() - t0) / reps, 3), "mean_k": float(np.mean(ks))}
+
+
+M_SCAN = ((DIMS, 0.2, (0, 10, 20, 30, 40)), ((8, 8, 8, 8), 0.3, (0, 15, 30, 45, 60)))
+
+
+def m_scan_leg(sg, synth, torch, reps=6):
+    """Deflation size against cost (the paper's closing question: how the
+    best m and the setup time depend on the volume).  Per lattice and m: the
+    Schur setup time (sgn_deflate), the mean k and ms per apply at tol 1e-10
+    (FP64, one at a time, kmax 1200), and the number of applies after which
+    the setup has paid for itself against m = 0."""
+    out = []
+    for dims, mu, ms in M_SCAN:
+        links = synth.random_links(dims, synth.GAUGE_SEED)
+        xs = [torch.from_numpy(synth.gaussian_source(dims, 1000 + r)).cuda() for r in range(reps)]
+        y = torch.empty_like(xs[0])
+        rows = []
+        for m in ms:
+            ctx = sg.sgn_create(links, dims, mu, M_W)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if m:
+                    sg.sgn_deflate(ctx, m)
+                torch.cuda.synchronize()
+                setup = time.perf_counter() - t0
+                sg.sgn_apply(ctx, xs[0], y, TOL, 1200)  # first apply: places the checkpoints
+                ks = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for x in xs:
+                    st = sg.sgn_apply(ctx, x, y, TOL, 1200)
+                    ks.append(sg.sgn_last_info(ctx)["k_used"] if st == sg.SGN_OK else None)
+                torch.cuda.synchronize()
+                ms_apply = 1e3 * (time.perf_counter() - t0) / len(xs)
+            finally:
+                sg.sgn_destroy(ctx)
+            row = {"m": m, "setup_s": round(setup, 3), "mean_k": (float(np.mean(ks)) if None not in ks else None),
+                   "ms_per_apply": round(ms_apply, 3)}
+            rows.append(row)
+            log(f"m-scan {dims} mu={mu}: {row}")
+        base = rows[0]["ms_per_apply"]
+        for row in rows[1:]:
+            gain = base - row["ms_per_apply"]
+            row["break_even_applies"] = round(1e3 * row["setup_s"] / gain, 1) if gain > 0 else None
+        out.append({"lattice": list(dims), "N": 12 * int(np.prod(dims)), "mu": mu, "tol": TOL, "rows": rows})
+    return {"workload": "deflation size scan, FP64, one source per apply, one at a time", "scan": out}
 
 
 def c1_leg(sg, synth, torch, reps=20):
