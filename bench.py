@@ -127,7 +127,7 @@ def main():
         print(json.dumps(stencil_leg(sg, synth, torch, tune=not args.no_autotune)))
         return
     if args.batched_only:
-        print(json.dumps(batched_leg(sg, synth, torch)))
+        print(json.dumps(batched_leg(sg, synth, torch, tune=not args.no_autotune)))
         return
     if args.m_scan:
         print(json.dumps(m_scan_leg(sg, synth, torch)))
@@ -320,7 +320,7 @@ def main():
         sg.sgn_destroy(c)
 
     stencil = None if args.no_stencil else stencil_leg(sg, synth, torch, tune=not args.no_autotune)
-    batched = None if args.no_batched else batched_leg(sg, synth, torch)
+    batched = None if args.no_batched else batched_leg(sg, synth, torch, tune=not args.no_autotune)
     mixed8 = None if args.no_mixed else mixed_leg(sg, synth, torch, tune=not args.no_autotune)
     small4 = None if args.no_mixed else c1_leg(sg, synth, torch)
     if stencil is not None and stencil_6 is not None:
@@ -649,10 +649,15 @@ BATCH_KMAX = 400
 BATCH_TOL = 1e-7
 
 
-def batched_leg(sg, synth, torch):
+def batched_leg(sg, synth, torch, tune=True):
     """32 sources of one 12^4 field (mu = 0.3, m = 40) in one mixed-precision
     batched apply, against FP64 single-source applies on the same field; the
-    mixed results of two sources are compared with their FP64 results."""
+    mixed results of two sources are compared with their FP64 results.  With
+    tune, each precision's launch shape is autotuned first (FP64 single
+    source at k = 200; mixed, 32 sources at k = 120; one timed call per
+    shape, since the shapes give bitwise the same results)."""
+    from paper_0704_3486_amd.autotune import autotune
+
     dims = BATCH_DIMS
     N = 12 * int(np.prod(dims))
     links = synth.random_links(dims, synth.GAUGE_SEED)
@@ -663,6 +668,10 @@ def batched_leg(sg, synth, torch):
         torch.cuda.synchronize()
         t_defl = time.perf_counter() - t0
         X = torch.from_numpy(np.stack([synth.gaussian_source(dims, 1000 + r) for r in range(BATCH_NRHS)])).cuda()
+        shapes = {}
+        if tune:
+            t = autotune(ctx, k=200, nrhs=1, reps=1)
+            shapes["fp64"] = [t["update_batch"], t["dot_cols"]]
         # FP64, one source at a time (tol 1e-10)
         y64 = torch.empty((2, N), dtype=torch.complex128, device="cuda")
         sg.sgn_apply(ctx, X[0], y64[0], TOL, BATCH_KMAX)
@@ -676,6 +685,9 @@ def batched_leg(sg, synth, torch):
         fp64_rate = 2 / (time.perf_counter() - t0)
         # mixed precision, all sources in one batched call (one untimed call first)
         sg.sgn_set_precision(ctx, sg.SGN_PREC_MIXED)
+        if tune:
+            t = autotune(ctx, k=120, nrhs=BATCH_NRHS, reps=1)
+            shapes["mixed_batched"] = [t["update_batch"], t["dot_cols"]]
         Y = torch.empty_like(X)
         sg.sgn_apply_batched(ctx, X, Y, BATCH_TOL, BATCH_KMAX)
         torch.cuda.synchronize()
@@ -691,7 +703,8 @@ def batched_leg(sg, synth, torch):
            "mixed_batched_applies_per_s": round(mixed_rate, 3), "mixed_tol": BATCH_TOL, "status": st,
            "mixed_k": [i["k_used"] for i in infos], "fp64_single_applies_per_s": round(fp64_rate, 3),
            "fp64_tol": TOL, "fp64_k": ks64, "speedup": round(mixed_rate / fp64_rate, 3),
-           "mixed_rel_err_vs_fp64": err, "deflation_seconds": round(t_defl, 2)}
+           "mixed_rel_err_vs_fp64": err, "deflation_seconds": round(t_defl, 2),
+           "launch_shapes": shapes or None}
     log(f"batched: {out}")
     return out
 
