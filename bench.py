@@ -322,7 +322,7 @@ def main():
     stencil = None if args.no_stencil else stencil_leg(sg, synth, torch, tune=not args.no_autotune)
     batched = None if args.no_batched else batched_leg(sg, synth, torch, tune=not args.no_autotune)
     mixed8 = None if args.no_mixed else mixed_leg(sg, synth, torch, tune=not args.no_autotune)
-    small4 = None if args.no_mixed else c1_leg(sg, synth, torch)
+    small4 = None if args.no_mixed else undeflated_4x4_leg(sg, synth, torch)
     if stencil is not None and stencil_6 is not None:
         stencil["in_apply_6x6x6x6"] = stencil_6
 
@@ -430,7 +430,7 @@ def m_scan_leg(sg, synth, torch, reps=6):
     return {"workload": "deflation size scan, FP64, one source per apply, one at a time", "scan": out}
 
 
-def c1_leg(sg, synth, torch, reps=20):
+def undeflated_4x4_leg(sg, synth, torch, reps=20):
     """4^4, mu = 0.3, no deflation, exactly k = 300 Arnoldi steps (FP64), one
     source per apply: error of the seed-1000 source against its stored exact
     sign (full diagonalisation) and the rate, one at a time."""

@@ -64,7 +64,7 @@ def test_fp64_apply_12x12_pure_gauge(env, pure_gauge):
 
 
 def test_batched_mixed_12x12_pure_gauge(env, pure_gauge):
-    """The C4 path (mixed precision, several sources per launch) at 12^4:
+    """The batched mixed-precision path (several sources per launch) at 12^4:
     every source within the 1e-6 mixed-precision target of the exact result."""
     sg, torch = env
     links, Xg, exact = pure_gauge

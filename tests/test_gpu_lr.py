@@ -215,7 +215,7 @@ def test_lr_import_checks_then_schur_again(env, case):
         sg.sgn_destroy(ctx)
 
 
-def test_lr_c2_field_vs_stored_exact(env):
+def test_lr_6x6_field_vs_stored_exact(env):
     sg, torch = env
     path = os.path.join(GOLDEN, "c6_mu0.2.npy")
     if not os.path.exists(path):

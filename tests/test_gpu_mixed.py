@@ -77,7 +77,7 @@ def test_mixed_apply_vs_exact_small(env, m):
         sg.sgn_destroy(ctx)
 
 
-def test_mixed_c3_8x8_vs_fp64_oracle_arnoldi(env):
+def test_mixed_8x8_vs_fp64_oracle_arnoldi(env):
     # 8^4, mu = 0.3, m = 30: against the oracle's FP64 Arnoldi at k = 800
     # (self-converged: |y_800 - y_700| / |y_800| <= 1e-8, stored by make_golden.py)
     sg, torch = env

@@ -132,7 +132,7 @@ def test_overlap_argument_checks(env, field):
         sg.sgn_destroy(ctx)
 
 
-def test_overlap_c2_field_vs_stored_exact(env):
+def test_overlap_6x6_field_vs_stored_exact(env):
     sg, torch = env
     path = os.path.join(GOLDEN, "c6_mu0.2.npy")
     if not os.path.exists(path):

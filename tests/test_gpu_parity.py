@@ -201,7 +201,7 @@ def _golden(name):
     return np.load(path, allow_pickle=False)
 
 
-def test_c1_4x4_no_deflation_vs_exact(env):
+def test_4x4_no_deflation_vs_exact(env):
     # 4^4, mu = 0.3, m = 0, k <= 300 per the workload; at k = 300 the error is ~1e-10,
     # so the apply is allowed kmax = 400 and held to 1e-10 against the exact result.
     sg, torch = env
@@ -221,7 +221,7 @@ def test_c1_4x4_no_deflation_vs_exact(env):
 
 
 @pytest.mark.parametrize("mu", [0.0, 0.2, 0.5])
-def test_c2_6x6_deflated_vs_exact(env, mu):
+def test_6x6_deflated_vs_exact(env, mu):
     sg, torch = env
     dims = (6, 6, 6, 6)
     exact = _golden(f"c6_mu{mu}")
