@@ -228,6 +228,13 @@ int sgn_overlap_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y
 int sgn_apply_adjoint(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
 int sgn_apply_adjoint_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
 
+/* The adjoint of the overlap operator (Eq. Dov): y = D_ov(mu)^dag x =
+ * x + sgn(H_w(mu))^dag gamma5 x, the sign applied as by sgn_apply_adjoint
+ * (same requirements and status) to gamma5 x.  At mu != 0 this is not
+ * gamma5 D_ov gamma5.  x, y: device complex128 in the interface layout; they
+ * must not overlap (SGN_EINVAL).  Complete on return. */
+int sgn_overlap_apply_adjoint(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
+
 /* ---- serving: continuous batching on one resident field ---------------- */
 
 /* A session keeps up to max_slots (1..64) requests of one context in flight,

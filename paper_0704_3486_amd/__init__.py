@@ -83,6 +83,7 @@ def _load():
         "sgn_apply_fixed": (i, [vp, vp, vp, i]),
         "sgn_apply_adjoint": (i, [vp, vp, vp, d, i]),
         "sgn_apply_adjoint_fixed": (i, [vp, vp, vp, i]),
+        "sgn_overlap_apply_adjoint": (i, [vp, vp, vp, d, i]),
         "sgn_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
         "sgn_overlap_apply": (i, [vp, vp, vp, d, i]),
         "sgn_overlap_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
@@ -324,6 +325,13 @@ def sgn_apply_adjoint(ctx, x, y, tol, kmax):
 def sgn_apply_adjoint_fixed(ctx, x, y, k):
     _, N = sgn_get_dims(ctx)
     return _check(ctx, _lib.sgn_apply_adjoint_fixed(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), int(k)))
+
+
+def sgn_overlap_apply_adjoint(ctx, x, y, tol, kmax):
+    """y = D_ov(mu)^dag x = x + sgn(H_w(mu))^dag gamma5 x; returns SGN_OK or SGN_ENOCONV (soft)."""
+    _, N = sgn_get_dims(ctx)
+    st = _lib.sgn_overlap_apply_adjoint(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), float(tol), int(kmax))
+    return _check(ctx, st, soft=(SGN_ENOCONV,))
 
 
 def sgn_apply_batched(ctx, X, Y, tol, kmax):

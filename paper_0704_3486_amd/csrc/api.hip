@@ -815,10 +815,14 @@ struct AdjointScope {
   }
 };
 
-static int run_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int kmax, int fixed_k) {
+static void check_adjoint(const sgn_ctx* c) {
   SGN_REQUIRE(c->m == 0, SGN_ESTATE,
               "the adjoint needs an LR pair (sgn_deflate_lr) or no deflation: a Schur basis of A is none of A^dag");
   SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session runs on this field");
+}
+
+static int run_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int kmax, int fixed_k) {
+  check_adjoint(c);
   AdjointScope scope(c);
   return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), tol, kmax, fixed_k);
 }
@@ -837,6 +841,23 @@ int sgn_apply_adjoint_fixed(sgn_ctx* c, const double* x, double* y, int k) {
     SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
     SGN_REQUIRE(k >= 0 && k <= c->N - c->m, SGN_EINVAL, "k must satisfy 0 <= k <= N - m");
     return run_adjoint(c, x, y, 1.0, k, k);
+  });
+}
+
+int sgn_overlap_apply_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int kmax) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
+    SGN_REQUIRE(!overlapping(x, y, (size_t)c->N), SGN_EINVAL, "x and y must not overlap");
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    check_adjoint(c);  // before y is written
+    const auto x2 = reinterpret_cast<const double2*>(x);
+    const auto y2 = reinterpret_cast<double2*>(y);
+    overlap_adjoint_start(x2, y2, (size_t)c->N, c->stream);  // y = gamma5 x
+    const int st = run_adjoint(c, y, y, tol, kmax, -1);      // y = sgn^dag y (in place)
+    overlap_adjoint_finish(x2, y2, (size_t)c->N, c->stream);
+    SGN_HIP(hipStreamSynchronize(c->stream));
+    return st;
   });
 }
 

@@ -422,6 +422,34 @@ void overlap_finish(const double2* x, double2* y, size_t n, hipStream_t s) {
   SGN_HIP(hipGetLastError());
 }
 
+// the adjoint D_ov(mu)^dag x = x + sgn(H_w(mu))^dag gamma5 x, in the interface
+// layout: y = gamma5 x before the sign, y = x + y after it
+__global__ void gamma5_abi_kernel(const double2* __restrict__ x, double2* __restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 xi = x[i];
+  y[i] = (i % 12 < 6) ? xi : make_double2(-xi.x, -xi.y);
+}
+
+__global__ void add_abi_kernel(const double2* __restrict__ x, double2* __restrict__ y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 xi = x[i], si = y[i];
+  y[i] = make_double2(xi.x + si.x, xi.y + si.y);
+}
+
+void overlap_adjoint_start(const double2* x, double2* y, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(gamma5_abi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+  SGN_HIP(hipGetLastError());
+}
+
+void overlap_adjoint_finish(const double2* x, double2* y, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(add_abi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+  SGN_HIP(hipGetLastError());
+}
+
 // the blocked order when the lattice is large enough to leave L2 and its
 // extents admit the blocks (Lx By a multiple of the workgroup's 16 sites)
 static SiteOrder site_order(const Lattice& lat) {

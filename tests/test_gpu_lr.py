@@ -313,3 +313,27 @@ def test_lr_adjoint_mixed_precision(env, case):
         assert _rel(y.cpu().numpy(), Sgn.conj().T @ X[1]) < 1e-6
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_overlap_adjoint(env, case):
+    # D_ov(mu)^dag x = x + sgn(H_w(mu))^dag gamma5 x against the dense oracle,
+    # and <w, D_ov x> = <D_ov^dag w, x> with both sides on the GPU
+    sg, torch = env
+    A, X = case[3], case[8]
+    Dov = overlap.overlap_dense(A)
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        x = torch.from_numpy(X[0]).cuda()
+        w = torch.from_numpy(X[1]).cuda()
+        ya, yd = torch.empty_like(x), torch.empty_like(x)
+        assert sg.sgn_overlap_apply_adjoint(ctx, w, ya, 1e-11, 600) == sg.SGN_OK
+        assert _rel(ya.cpu().numpy(), Dov.conj().T @ X[1]) < 1e-9
+        assert sg.sgn_overlap_apply(ctx, x, yd, 1e-11, 600) == sg.SGN_OK
+        lhs = np.vdot(X[1], yd.cpu().numpy())
+        rhs = np.vdot(ya.cpu().numpy(), X[0])
+        assert abs(lhs - rhs) < 1e-9 * np.linalg.norm(X[0]) * np.linalg.norm(X[1])
+        with pytest.raises(sg.SgnError) as e:
+            sg.sgn_overlap_apply_adjoint(ctx, x, x, 1e-10, 100)  # y aliases x
+        assert e.value.status == sg.SGN_EINVAL
+    finally:
+        sg.sgn_destroy(ctx)
