@@ -203,9 +203,12 @@ def main():
             lanes.append((c, y))
     torch.cuda.synchronize()
 
+    unconverged = []  # applies that ended without reaching TOL (SGN_ENOCONV)
+
     def field_steps(f, first, count, ks):
         for r in range(first, first + count):
-            sg.sgn_apply(ctxs[f], xs[r % len(xs)], ys[f], TOL, KMAX)
+            if sg.sgn_apply(ctxs[f], xs[r % len(xs)], ys[f], TOL, KMAX) != sg.SGN_OK:
+                unconverged.append(f)
             ks.append(sg.sgn_last_info(ctxs[f])["k_used"])
 
     def lane_steps(q, first, count, ks):
@@ -213,7 +216,8 @@ def main():
         c, y = lanes[q]
         p = q // len(MUS)
         for r in range(first, first + count):
-            sg.sgn_apply(c, xs[(r * P + p) % len(xs)], y, TOL, KMAX)
+            if sg.sgn_apply(c, xs[(r * P + p) % len(xs)], y, TOL, KMAX) != sg.SGN_OK:
+                unconverged.append(q)
             ks.append(sg.sgn_last_info(c)["k_used"])
 
     def run_concurrent(first, count):
@@ -235,10 +239,12 @@ def main():
     runner = run_serial if args.serial else run_concurrent
     runner(0, args.warmup)
     torch.cuda.synchronize()
+    unconverged.clear()
     t0 = time.perf_counter()
     ks = runner(args.warmup, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    timed_unconverged = len(unconverged)
     applies = args.steps * len(lanes)
     value = applies / elapsed
     mode = "serial" if args.serial else f"{len(lanes)} streams"
@@ -350,7 +356,7 @@ def main():
                                   "stream each)"),
                    "applies_in_flight_per_field": P,
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
-                   "mean_k": round(float(np.mean(ks)), 1)},
+                   "mean_k": round(float(np.mean(ks)), 1), "timed_unconverged": timed_unconverged},
         "accuracy": acc,
         "latency": latency,
         "setup": setup,
