@@ -227,6 +227,12 @@ int sgn_overlap_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y
  * Captured step graphs (sgn_set_step_graphs) are not used by these calls. */
 int sgn_apply_adjoint(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
 int sgn_apply_adjoint_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
+/* Several sources, as sgn_apply_batched / sgn_apply_batched_fixed: Y_r =
+ * sgn(H_w(mu))^dag X_r, per source bitwise the single-source adjoint at
+ * fixed k; the same requirements as sgn_apply_adjoint. */
+int sgn_apply_adjoint_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double tol, int kmax,
+                              sgn_info* info);
+int sgn_apply_adjoint_batched_fixed(sgn_ctx* ctx, int nrhs, const double* X, double* Y, int k, sgn_info* info);
 
 /* The adjoint of the overlap operator (Eq. Dov): y = D_ov(mu)^dag x =
  * x + sgn(H_w(mu))^dag gamma5 x, the sign applied as by sgn_apply_adjoint

@@ -94,6 +94,8 @@ def _load():
         "sgn_session_active": (i, [vp]),
         "sgn_session_destroy": (None, [vp]),
         "sgn_apply_batched_fixed": (i, [vp, i, vp, vp, i, C.POINTER(sgn_info)]),
+        "sgn_apply_adjoint_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
+        "sgn_apply_adjoint_batched_fixed": (i, [vp, i, vp, vp, i, C.POINTER(sgn_info)]),
         "sgn_last_info": (i, [vp, C.POINTER(sgn_info)]),
         "sgn_footprint_bytes": (C.c_size_t, [vp, i, i]),
         "sgn_matvec": (i, [vp, vp, vp]),
@@ -369,6 +371,26 @@ def sgn_apply_batched_fixed(ctx, X, Y, k):
     infos = (sgn_info * nrhs)()
     _check(ctx, _lib.sgn_apply_batched_fixed(ctx, int(nrhs), _dptr(X, nrhs * N, "X"), _dptr(Y, nrhs * N, "Y"),
                                              int(k), infos))
+    return [infos[r].as_dict() for r in range(nrhs)]
+
+
+def sgn_apply_adjoint_batched(ctx, X, Y, tol, kmax):
+    """Y[r] = sgn(H_w(mu))^dag X[r]; returns (status, [info dict per source])."""
+    _, N = sgn_get_dims(ctx)
+    nrhs = X.shape[0] if X.dim() == 2 else X.numel() // N
+    infos = (sgn_info * nrhs)()
+    st = _lib.sgn_apply_adjoint_batched(ctx, int(nrhs), _dptr(X, nrhs * N, "X"), _dptr(Y, nrhs * N, "Y"),
+                                        float(tol), int(kmax), infos)
+    return _check(ctx, st, soft=(SGN_ENOCONV,)), [infos[r].as_dict() for r in range(nrhs)]
+
+
+def sgn_apply_adjoint_batched_fixed(ctx, X, Y, k):
+    """Exactly k Arnoldi steps per source of the adjoint; returns [info dict per source]."""
+    _, N = sgn_get_dims(ctx)
+    nrhs = X.shape[0] if X.dim() == 2 else X.numel() // N
+    infos = (sgn_info * nrhs)()
+    _check(ctx, _lib.sgn_apply_adjoint_batched_fixed(ctx, int(nrhs), _dptr(X, nrhs * N, "X"),
+                                                     _dptr(Y, nrhs * N, "Y"), int(k), infos))
     return [infos[r].as_dict() for r in range(nrhs)]
 
 

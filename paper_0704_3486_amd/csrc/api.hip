@@ -794,33 +794,6 @@ int sgn_apply_fixed(sgn_ctx* c, const double* x, double* y, int k) {
   });
 }
 
-// The adjoint problem on this context, for the duration of one apply:
-// A^dag = H_w(mu)^dag = H_w(-mu) (the time hops' e^{+mu} and e^{-mu}
-// exchanged), with the LR pair's roles exchanged (L holds A^dag's right
-// eigenvectors and R its left ones, for conj(Lambda), whose signs are those of
-// Lambda).  Captured step graphs hold the forward phases among their kernel
-// arguments, so none are replayed meanwhile.
-struct AdjointScope {
-  sgn_ctx* c;
-  int graph_steps;
-  explicit AdjointScope(sgn_ctx* cc) : c(cc), graph_steps(cc->graph_steps) {
-    std::swap(c->lat.emu, c->lat.emmu);
-    std::swap(c->lrR, c->lrL);
-    c->graph_steps = 0;
-  }
-  ~AdjointScope() {
-    std::swap(c->lat.emu, c->lat.emmu);
-    std::swap(c->lrR, c->lrL);
-    c->graph_steps = graph_steps;
-  }
-};
-
-static void check_adjoint(const sgn_ctx* c) {
-  SGN_REQUIRE(c->m == 0, SGN_ESTATE,
-              "the adjoint needs an LR pair (sgn_deflate_lr) or no deflation: a Schur basis of A is none of A^dag");
-  SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session runs on this field");
-}
-
 static int run_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int kmax, int fixed_k) {
   check_adjoint(c);
   AdjointScope scope(c);

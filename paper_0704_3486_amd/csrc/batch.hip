@@ -416,4 +416,24 @@ int sgn_apply_batched_fixed(sgn_ctx* c, int nrhs, const double* X, double* Y, in
   });
 }
 
+int sgn_apply_adjoint_batched(sgn_ctx* c, int nrhs, const double* X, double* Y, double tol, int kmax,
+                              sgn_info* info) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(kmax >= 2 && kmax <= c->N, SGN_EINVAL, "kmax must satisfy 2 <= kmax <= N");
+    check_adjoint(c);
+    AdjointScope scope(c);
+    return batched_entry(c, nrhs, X, Y, tol, kmax, -1, info);
+  });
+}
+
+int sgn_apply_adjoint_batched_fixed(sgn_ctx* c, int nrhs, const double* X, double* Y, int k, sgn_info* info) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(k >= 0 && k <= c->N, SGN_EINVAL, "k must satisfy 0 <= k <= N");
+    check_adjoint(c);
+    AdjointScope scope(c);
+    return batched_entry(c, nrhs, X, Y, 1.0, std::max(k, 2), k, info);
+  });
+}
+
 }  // extern "C"

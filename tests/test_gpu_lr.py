@@ -337,3 +337,31 @@ def test_overlap_adjoint(env, case):
         assert e.value.status == sg.SGN_EINVAL
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_lr_adjoint_batched(env, case):
+    # at fixed k each source is bitwise its single-source adjoint; with a
+    # tolerance every source is near the exact sgn(A)^dag x
+    sg, torch = env
+    Sgn, X = case[7], case[8]
+    ctx = _lr_ctx(sg, torch, case)
+    try:
+        Xd = torch.from_numpy(X).cuda()
+        Y = torch.empty_like(Xd)
+        sg.sgn_apply_adjoint_batched_fixed(ctx, Xd, Y, 40)
+        for r in range(X.shape[0]):
+            y = torch.empty_like(Xd[r])
+            sg.sgn_apply_adjoint_fixed(ctx, Xd[r].contiguous(), y, 40)
+            assert torch.equal(y, Y[r])
+        st, infos = sg.sgn_apply_adjoint_batched(ctx, Xd, Y, 1e-11, 600)
+        assert st == sg.SGN_OK and all(i["converged"] for i in infos)
+        for r in range(X.shape[0]):
+            assert _rel(Y[r].cpu().numpy(), Sgn.conj().T @ X[r]) < 1e-9
+        # the forward batched apply afterwards is unchanged
+        Y2 = torch.empty_like(Xd)
+        sg.sgn_apply_batched_fixed(ctx, Xd, Y2, 40)
+        y = torch.empty_like(Xd[0])
+        sg.sgn_apply_fixed(ctx, Xd[0].contiguous(), y, 40)
+        assert torch.equal(y, Y2[0])
+    finally:
+        sg.sgn_destroy(ctx)
