@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--per-field", type=int, default=2,
                     help="applies in flight per field in the timed steps: one context and stream each, all "
                          "holding the field's Schur pair")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="replay runs of this many Arnoldi steps as captured HIP graphs in the timed applies "
+                         "(sgn_set_step_graphs; bitwise the same results; 0: direct launches)")
     ap.add_argument("--serial", action="store_true",
                     help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
                          "whose per-kernel averages then compare with the HIP-event ones)")
@@ -201,6 +204,9 @@ def main():
             y = torch.empty(N, dtype=torch.complex128, device=dev)
             sg.sgn_apply(c, xs[0], y, TOL, KMAX)
             lanes.append((c, y))
+    if args.graph_steps:
+        for c, _ in lanes:
+            sg.sgn_set_step_graphs(c, args.graph_steps)
     torch.cuda.synchronize()
 
     unconverged = []  # applies that ended without reaching TOL (SGN_ENOCONV)
@@ -261,6 +267,8 @@ def main():
     log(f"serial: {latency}")
     for c in extra:
         sg.sgn_destroy(c)
+    for c in ctxs:
+        sg.sgn_set_step_graphs(c, 0)  # the profiled pass times direct launches
 
     # profiled pass over the same steps, one apply at a time (HIP events on
     # each context's stream)
@@ -354,7 +362,7 @@ def main():
                                + ("3 applies per step (one per field, one at a time)" if args.serial else
                                   f"{len(lanes)} applies per step ({P} per field in flight, one context and "
                                   "stream each)"),
-                   "applies_in_flight_per_field": P,
+                   "applies_in_flight_per_field": P, "graph_steps": args.graph_steps,
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
                    "mean_k": round(float(np.mean(ks)), 1), "timed_unconverged": timed_unconverged},
         "accuracy": acc,
