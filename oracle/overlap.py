@@ -52,3 +52,17 @@ def gw_defect(D: np.ndarray) -> float:
     lhs = D * g5[None, :] + g5[:, None] * D
     rhs = (D * g5[None, :]) @ D
     return float(np.linalg.norm(lhs - rhs) / np.linalg.norm(D))
+
+
+def massive_overlap_dense(A_hw: np.ndarray, mass: float) -> np.ndarray:
+    """The massive overlap operator, a reading (the paper leaves the inversion
+    of D_ov to future work and names no mass term): the usual
+    D(m) = (1 - m/2) D_ov(mu) + m = (1 + m/2) + (1 - m/2) gamma5 sgn(H_w(mu)),
+    which is D_ov at m = 0 and 2 at m = 2."""
+    n = A_hw.shape[0]
+    return (1.0 - 0.5 * mass) * overlap_dense(A_hw) + mass * np.eye(n, dtype=complex)
+
+
+def massive_overlap_solve(A_hw: np.ndarray, b: np.ndarray, mass: float) -> np.ndarray:
+    """x with D(m) x = b, by a dense LU solve."""
+    return np.linalg.solve(massive_overlap_dense(A_hw, mass), np.asarray(b, dtype=np.complex128))

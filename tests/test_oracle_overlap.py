@@ -73,3 +73,29 @@ def test_apply_matches_dense(fields):
     H = fields[2][0.3]
     x = synth.gaussian_source(fields[0], 3200)
     assert np.allclose(overlap.overlap_apply(H, x), overlap.overlap_dense(H) @ x, atol=1e-12)
+
+
+def test_massive_overlap_reading_and_solve():
+    # D(m) = (1 - m/2) D_ov + m: D(0) = D_ov, D(2) = 2 (so x = b/2), the
+    # expanded form (1 + m/2) + (1 - m/2) gamma5 sgn, at mu = 0 a spectrum on
+    # |lambda - (1 + m/2)| = 1 - m/2, and the solve's residual
+    dims = (2, 2, 2, 2)
+    U = synth.random_links(dims, 61)
+    b = synth.gaussian_source(dims, 6100)
+    n = b.size
+    for mu in (0.0, 0.3):
+        A = wilson.hw_matrix(U, dims, mu, M_W).toarray()
+        D = overlap.overlap_dense(A)
+        assert np.abs(overlap.massive_overlap_dense(A, 0.0) - D).max() < 1e-14
+        assert np.abs(overlap.massive_overlap_dense(A, 2.0) - 2.0 * np.eye(n)).max() < 1e-14
+        assert np.abs(overlap.massive_overlap_solve(A, b, 2.0) - 0.5 * b).max() < 1e-14
+        m = 0.2
+        g5 = overlap.gamma5_vector(n // 12)
+        expanded = (1 + m / 2) * np.eye(n) + (1 - m / 2) * g5[:, None] * matfunc.sgn_spectral(A)
+        Dm = overlap.massive_overlap_dense(A, m)
+        assert np.abs(Dm - expanded).max() < 1e-13
+        x = overlap.massive_overlap_solve(A, b, m)
+        assert np.linalg.norm(Dm @ x - b) < 1e-12 * np.linalg.norm(b)
+        if mu == 0.0:
+            ev = np.linalg.eigvals(Dm)
+            assert np.abs(np.abs(ev - (1 + m / 2)) - (1 - m / 2)).max() < 1e-12
