@@ -324,6 +324,7 @@ def main():
                      "frac": round(gb / HBM_PEAK_GBPS, 4), "avg_launch_us": kern["wilson_hw"]["avg_us"]}
 
     ov = None if args.no_overlap else overlap_leg(sg, torch, ctxs[1], MUS[1], xs)
+    ovs = None if args.no_overlap else overlap_solve_leg(sg, torch, ctxs[1], MUS[1], xs)
     lrd = None if args.no_lr else lr_leg(sg, synth, torch, MUS[1], xs, latency_schur(sg, torch, ctxs[1], xs),
                                          tune=not args.no_autotune)
 
@@ -376,6 +377,7 @@ def main():
         "undeflated_4x4x4x4": small4,
         "small_sign": sign,
         "overlap": ov,
+        "overlap_solve": ovs,
         "lr_deflation": lrd,
         "kernels": kern,
         "profiled_pass_seconds": round(elapsed_prof, 4),
@@ -547,6 +549,31 @@ def lr_leg(sg, synth, torch, mu, xs, schur, reps=10, tune=True):
     finally:
         sg.sgn_destroy(ctx)
     log(f"lr: {out}")
+    return out
+
+
+OVS_MASSES = (0.5, 0.1)
+
+
+def overlap_solve_leg(sg, torch, ctx, mu, xs):
+    """D(m) x = b for the massive overlap operator (1 - m/2) D_ov + m on the
+    6^4 field with its m = 20 Schur pair: restarted GMRES (50) over sign
+    applies (inner tol 1e-10), outer tol 1e-8, the seed-1000 source as b;
+    outer steps, seconds and the true relative residual per mass."""
+    b = xs[0]
+    x = torch.empty_like(b)
+    out = {"workload": f"6^4, mu={mu}, m={M_DEFL} Schur, D(m) = (1 - m/2) D_ov + m, GMRES(50), tol 1e-8, "
+                       "inner sign tol 1e-10, FP64", "solves": []}
+    for mass in OVS_MASSES:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, res = sg.sgn_overlap_solve(ctx, b, x, mass, 1e-8, max_iter=2000, restart=50, inner_tol=1e-10,
+                                           inner_kmax=KMAX)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out["solves"].append({"mass": mass, "status": st, "outer_steps": it, "rel_residual": res,
+                              "seconds": round(sec, 3), "ms_per_outer_step": round(1e3 * sec / max(it, 1), 3)})
+    log(f"overlap solve: {out}")
     return out
 
 

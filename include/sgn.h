@@ -241,6 +241,24 @@ int sgn_apply_adjoint_batched_fixed(sgn_ctx* ctx, int nrhs, const double* X, dou
  * must not overlap (SGN_EINVAL).  Complete on return. */
 int sgn_overlap_apply_adjoint(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
 
+/* Solve D(m) x = b for the massive overlap operator
+ *   D(m) = (1 - m/2) D_ov(mu) + m = (1 + m/2) + (1 - m/2) gamma5 sgn(H_w(mu)),
+ * a reading: the paper leaves the inversion of D_ov to future work (each
+ * outer step needs one sign apply, which is where deflation's one-off cost
+ * pays) and names no mass term; this is the usual one, D_ov at m = 0.
+ * Restarted GMRES (restart outer vectors, 1..500) with the sign applied as
+ * by sgn_apply(inner_tol, inner_kmax) on the installed deflation; the outer
+ * basis is orthogonalised twice with classical Gram-Schmidt on the device.
+ * Stops when the true relative residual |b - D x| / |b| <= tol (checked at
+ * every restart) or after max_iter outer steps (then SGN_ENOCONV, x the
+ * last iterate).  The operator is only as accurate as inner_tol, so choose
+ * inner_tol well below tol.  b, x: device complex128, N entries, not
+ * overlapping.  iters, rel_res (host, nullable): outer steps taken and the
+ * final true relative residual.  SGN_ENOCONV also when an inner apply
+ * misses inner_tol.  Allocates (restart + 2) N complex128 per call. */
+int sgn_overlap_solve(sgn_ctx* ctx, const double* b, double* x, double mass, double tol, int max_iter, int restart,
+                      double inner_tol, int inner_kmax, int* iters, double* rel_res);
+
 /* ---- serving: continuous batching on one resident field ---------------- */
 
 /* A session keeps up to max_slots (1..64) requests of one context in flight,

@@ -20,7 +20,9 @@ Contents, each following the paper (Bloch, Frommer, Lang, Wettig 2007):
                    (Eq. pSd), from a dense eigendecomposition or from ARPACK
                    on H_w^2 as in the Results section
   * overlap     -- the overlap operator D_ov(mu) = 1 + gamma5 sgn(H_w(mu))
-                   (Eq. Dov) and its Ginsparg-Wilson defect (Eq. GW:eq)
+                   (Eq. Dov), its Ginsparg-Wilson defect (Eq. GW:eq), and
+                   the massive operator (1 - m/2) D_ov + m with its dense
+                   solve (a reading: the paper leaves the inversion open)
   * lr          -- LR-deflation: left/right critical eigenvectors and the
                    approximation R f(Lambda) L^dag x + beta V_k f(H_k) e_1
                    (Eqs. Rev, Lev, xdec, fARLx, LRArnoldi, fAxLRArn), and

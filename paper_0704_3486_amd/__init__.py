@@ -84,6 +84,7 @@ def _load():
         "sgn_apply_adjoint": (i, [vp, vp, vp, d, i]),
         "sgn_apply_adjoint_fixed": (i, [vp, vp, vp, i]),
         "sgn_overlap_apply_adjoint": (i, [vp, vp, vp, d, i]),
+        "sgn_overlap_solve": (i, [vp, vp, vp, d, d, i, i, d, i, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
         "sgn_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
         "sgn_overlap_apply": (i, [vp, vp, vp, d, i]),
         "sgn_overlap_apply_batched": (i, [vp, i, vp, vp, d, i, C.POINTER(sgn_info)]),
@@ -334,6 +335,19 @@ def sgn_overlap_apply_adjoint(ctx, x, y, tol, kmax):
     _, N = sgn_get_dims(ctx)
     st = _lib.sgn_overlap_apply_adjoint(ctx, _dptr(x, N, "x"), _dptr(y, N, "y"), float(tol), int(kmax))
     return _check(ctx, st, soft=(SGN_ENOCONV,))
+
+
+def sgn_overlap_solve(ctx, b, x, mass, tol, max_iter=500, restart=50, inner_tol=None, inner_kmax=None):
+    """x with D(m) x = b, D(m) = (1 - m/2) D_ov(mu) + m, by restarted GMRES
+    over sign applies (inner_tol default tol / 100, inner_kmax default
+    min(N, 1000)); returns (status, outer steps, true relative residual)."""
+    _, N = sgn_get_dims(ctx)
+    it, res = C.c_int(0), C.c_double(0.0)
+    st = _lib.sgn_overlap_solve(ctx, _dptr(b, N, "b"), _dptr(x, N, "x"), float(mass), float(tol), int(max_iter),
+                                int(restart), float(inner_tol if inner_tol is not None else tol / 100.0),
+                                int(inner_kmax if inner_kmax is not None else min(N, 1000)), C.byref(it),
+                                C.byref(res))
+    return _check(ctx, st, soft=(SGN_ENOCONV,)), it.value, res.value
 
 
 def sgn_apply_batched(ctx, X, Y, tol, kmax):

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -831,6 +832,156 @@ int sgn_overlap_apply_adjoint(sgn_ctx* c, const double* x, double* y, double tol
     overlap_adjoint_finish(x2, y2, (size_t)c->N, c->stream);
     SGN_HIP(hipStreamSynchronize(c->stream));
     return st;
+  });
+}
+
+// Device buffer owned by one call
+struct CallBuf {
+  void* p = nullptr;
+  explicit CallBuf(size_t bytes) { SGN_HIP(hipMalloc(&p, bytes)); }
+  ~CallBuf() {
+    if (p) (void)hipFree(p);
+  }
+  CallBuf(const CallBuf&) = delete;
+  CallBuf& operator=(const CallBuf&) = delete;
+  double2* c2() const { return static_cast<double2*>(p); }
+  double* d() const { return static_cast<double*>(p); }
+};
+
+// D(m) x = b for D(m) = (1 - m/2) D_ov(mu) + m = (1 + m/2) + (1 - m/2) gamma5
+// sgn(H_w(mu)) (a reading: the paper leaves the inversion of the overlap
+// operator to future work, where every outer step needs one sign apply) by
+// restarted GMRES.  The outer basis W is orthogonalised with classical
+// Gram-Schmidt and one re-orthogonalisation on the device; the small least
+// squares problem (Givens rotations) is solved on the host; at each restart
+// the true residual b - D x is formed.
+int sgn_overlap_solve(sgn_ctx* c, const double* b, double* x, double mass, double tol, int max_iter, int restart,
+                      double inner_tol, int inner_kmax, int* iters, double* rel_res) {
+  return guarded(c, [&] {
+    using cplx = std::complex<double>;
+    const int N = c->N;
+    SGN_REQUIRE(b && x, SGN_EINVAL, "b and x must not be NULL");
+    SGN_REQUIRE(!overlapping(b, x, (size_t)N), SGN_EINVAL, "b and x must not overlap");
+    SGN_REQUIRE(mass >= 0.0 && std::isfinite(mass), SGN_EINVAL, "mass must be finite and >= 0");
+    SGN_REQUIRE(tol > 0.0 && std::isfinite(tol), SGN_EINVAL, "tol must be positive");
+    SGN_REQUIRE(max_iter >= 1, SGN_EINVAL, "max_iter must be >= 1");
+    SGN_REQUIRE(restart >= 1 && restart <= 500, SGN_EINVAL, "restart must satisfy 1 <= restart <= 500");
+    SGN_REQUIRE(inner_tol > 0.0 && std::isfinite(inner_tol), SGN_EINVAL, "inner_tol must be positive");
+    SGN_REQUIRE(inner_kmax >= 2 && inner_kmax <= N, SGN_EINVAL, "inner_kmax must satisfy 2 <= inner_kmax <= N");
+    hipStream_t s = c->stream;
+    const size_t ld = c->ldq;
+    const int R = restart;
+    CallBuf bW(sizeof(double2) * ld * (size_t)(R + 1)), bt(sizeof(double2) * ld);
+    CallBuf bh(sizeof(double2) * 3 * (size_t)(R + 2)), bsc(sizeof(double) * 4);
+    double2* W = bW.c2();
+    double2* t = bt.c2();
+    double2* h1 = bh.c2();
+    double2* h2 = h1 + (R + 2);
+    double2* hout = h2 + (R + 2);  // also the solution coefficients y
+    double* sc = bsc.d();
+    GsWork g;
+    gs_alloc(g, N, ld, R + 1);
+    struct GsGuard {
+      GsWork& g;
+      ~GsGuard() { gs_free(g); }
+    } guard{g};
+    const auto b2 = reinterpret_cast<const double2*>(b);
+    const auto x2 = reinterpret_cast<double2*>(x);
+    const double ca = 1.0 + 0.5 * mass, cb = 1.0 - 0.5 * mass;
+    auto apply_D = [&](const double2* v, double2* out) {  // out = D(m) v, out != v
+      const int st = run_apply(c, v, out, inner_tol, inner_kmax, -1);
+      SGN_REQUIRE(st == SGN_OK, SGN_ENOCONV, "overlap solve: a sign apply did not reach inner_tol within inner_kmax");
+      axpby_abi(v, out, ca, cb, true, (size_t)N, s);
+    };
+    auto norm = [&](const double2* v) {
+      gs_norm(g, N, v, &sc[0], &sc[1], nullptr, s, nullptr);
+      double r = 0.0;
+      SGN_HIP(hipMemcpyAsync(&r, &sc[0], sizeof(double), hipMemcpyDeviceToHost, s));
+      SGN_HIP(hipStreamSynchronize(s));
+      return r;
+    };
+    dev_zero(x2, (size_t)N, s);
+    const double bnorm = norm(b2);
+    SGN_REQUIRE(std::isfinite(bnorm), SGN_EINVAL, "b contains NaN or Inf");
+    int it = 0;
+    double res = 0.0;
+    if (bnorm > 0.0) {
+      std::vector<cplx> H((size_t)(R + 1) * R), sn(R), gv(R + 1), y(R);
+      std::vector<double> cs(R);
+      std::vector<double2> hh(R + 2);
+      for (bool first = true;; first = false) {
+        // true residual r = b - D x in W_0
+        if (first) {
+          SGN_HIP(hipMemcpyAsync(W, b2, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+        } else {
+          apply_D(x2, t);
+          axpby_abi(b2, t, 1.0, -1.0, false, (size_t)N, s);
+          SGN_HIP(hipMemcpyAsync(W, t, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+        }
+        const double beta = norm(W);
+        res = beta / bnorm;
+        if (res <= tol || it >= max_iter) break;
+        axpby_abi(W, W, 0.0, 1.0 / beta, false, (size_t)N, s);
+        std::fill(gv.begin(), gv.end(), cplx(0.0, 0.0));
+        gv[0] = beta;
+        int j = 0;
+        while (j < R && it < max_iter) {
+          double2* w = W + (size_t)(j + 1) * ld;
+          apply_D(W + (size_t)j * ld, w);
+          ++it;
+          gs_dot(g, W, ld, N, j + 1, w, h1, s, nullptr);
+          gs_update(g, W, ld, N, j + 1, h1, w, nullptr, 0, s, nullptr);
+          gs_dot(g, W, ld, N, j + 1, w, h2, s, nullptr);
+          GsFinal fin{h1, hout, nullptr, nullptr, nullptr};
+          gs_update(g, W, ld, N, j + 1, h2, w, &fin, 0, s, nullptr);
+          SGN_HIP(hipMemcpyAsync(hh.data(), hout, sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, s));
+          SGN_HIP(hipStreamSynchronize(s));
+          const double hn = hh[j + 1].x;
+          SGN_REQUIRE(std::isfinite(hn), SGN_EINVAL, "overlap solve: non-finite value");
+          cplx* Hj = &H[(size_t)j * (R + 1)];
+          for (int i = 0; i <= j; ++i) Hj[i] = cplx(hh[i].x, hh[i].y);
+          Hj[j + 1] = hn;
+          for (int i = 0; i < j; ++i) {  // earlier rotations
+            const cplx u = Hj[i], v = Hj[i + 1];
+            Hj[i] = cs[i] * u + sn[i] * v;
+            Hj[i + 1] = -std::conj(sn[i]) * u + cs[i] * v;
+          }
+          const double r = std::hypot(std::abs(Hj[j]), hn);
+          if (std::abs(Hj[j]) == 0.0) {
+            cs[j] = 0.0;
+            sn[j] = 1.0;
+          } else {
+            const cplx ph = Hj[j] / std::abs(Hj[j]);
+            cs[j] = std::abs(Hj[j]) / r;
+            sn[j] = ph * hn / r;
+          }
+          Hj[j] = cs[j] * Hj[j] + sn[j] * Hj[j + 1];
+          Hj[j + 1] = 0.0;
+          gv[j + 1] = -std::conj(sn[j]) * gv[j];
+          gv[j] = cs[j] * gv[j];
+          ++j;
+          if (hn > 0.0) axpby_abi(w, w, 0.0, 1.0 / hn, false, (size_t)N, s);
+          if (std::abs(gv[j]) <= tol * bnorm || hn == 0.0) break;
+        }
+        // x += W y with R y = g (upper triangular j x j)
+        for (int i = j - 1; i >= 0; --i) {
+          cplx acc = gv[i];
+          for (int k = i + 1; k < j; ++k) acc -= H[(size_t)k * (R + 1) + i] * y[k];
+          y[i] = acc / H[(size_t)i * (R + 1) + i];
+        }
+        for (int i = 0; i < j; ++i) hh[i] = make_double2(y[i].real(), y[i].imag());
+        SGN_HIP(hipMemcpyAsync(hout, hh.data(), sizeof(double2) * j, hipMemcpyHostToDevice, s));
+        gs_add(g, W, ld, N, j, hout, x2, s, nullptr);
+        SGN_HIP(hipStreamSynchronize(s));  // hh is pageable host memory
+      }
+    }
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = res;
+    if (res > tol) {
+      c->last_error = "overlap solve: max_iter reached before the requested tolerance";
+      return SGN_ENOCONV;
+    }
+    return SGN_OK;
   });
 }
 

@@ -165,6 +165,8 @@ void overlap_finish(const double2* x, double2* y, size_t n, hipStream_t s);
 // D_ov^dag x = x + sgn^dag (gamma5 x): y = gamma5 x, then (after the sign) y = x + y
 void overlap_adjoint_start(const double2* x, double2* y, size_t n, hipStream_t s);
 void overlap_adjoint_finish(const double2* x, double2* y, size_t n, hipStream_t s);
+// y = a x + b g y with g = gamma5 (g5) or 1, interface layout, n entries; x may be y
+void axpby_abi(const double2* x, double2* y, double a, double b, bool g5, size_t n, hipStream_t s);
 // out = H_w(mu) (in * scale), optional copy_out = in * scale; scale = *inv_beta (or 1 if null)
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);

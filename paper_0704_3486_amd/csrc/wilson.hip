@@ -438,6 +438,22 @@ __global__ void add_abi_kernel(const double2* __restrict__ x, double2* __restric
   y[i] = make_double2(xi.x + si.x, xi.y + si.y);
 }
 
+// y = a x + b g y, g = gamma5 (if g5) or 1, in the interface layout; x may be y
+__global__ void axpby_abi_kernel(const double2* x, double2* y, double a, double b, int g5, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 xi = x[i], yi = y[i];
+  const double bb = (g5 && i % 12 >= 6) ? -b : b;
+  y[i] = make_double2(a * xi.x + bb * yi.x, a * xi.y + bb * yi.y);
+}
+
+void axpby_abi(const double2* x, double2* y, double a, double b, bool g5, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(axpby_abi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, a, b, g5 ? 1 : 0,
+                     n);
+  SGN_HIP(hipGetLastError());
+}
+
 void overlap_adjoint_start(const double2* x, double2* y, size_t n, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(gamma5_abi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);

@@ -150,3 +150,34 @@ def test_overlap_6x6_field_vs_stored_exact(env):
         assert _rel(y.cpu().numpy(), exact) < 1e-10
     finally:
         sg.sgn_destroy(ctx)
+
+
+@pytest.mark.parametrize("mass", [0.2, 2.0])
+def test_massive_overlap_solve(env, field, mass):
+    # D(m) x = b by GMRES over GPU sign applies, against the oracle's dense
+    # solve; m = 2 is 2 times the identity (one outer step)
+    sg, torch = env
+    dims, mu, links, _, S, T, X = field
+    A = wilson.hw_matrix(links, dims, mu, M_W).toarray()
+    ref = overlap.massive_overlap_solve(A, X[2], mass)
+    ctx = _ctx(sg, torch, field)
+    try:
+        b = torch.from_numpy(X[2]).cuda()
+        x = torch.empty_like(b)
+        st, it, res = sg.sgn_overlap_solve(ctx, b, x, mass, 1e-9, max_iter=300, restart=40, inner_tol=1e-12,
+                                           inner_kmax=600)
+        print("overlap solve", mass, st, it, res, flush=True)
+        assert st == sg.SGN_OK and res <= 1e-9
+        assert _rel(x.cpu().numpy(), ref) < 1e-7
+        if mass == 2.0:
+            assert it == 1
+        # the residual through the GPU operator: D(m) x = (1 - m/2) D_ov x + m x
+        dx = torch.empty_like(x)
+        assert sg.sgn_overlap_apply(ctx, x, dx, 1e-12, 600) == sg.SGN_OK
+        r = (1 - mass / 2) * dx + mass * x - b
+        assert float(r.norm() / b.norm()) < 1e-8
+        with pytest.raises(sg.SgnError) as e:
+            sg.sgn_overlap_solve(ctx, b, b, mass, 1e-9)  # x aliases b
+        assert e.value.status == sg.SGN_EINVAL
+    finally:
+        sg.sgn_destroy(ctx)
