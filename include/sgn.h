@@ -252,7 +252,9 @@ int sgn_overlap_apply_adjoint(sgn_ctx* ctx, const double* x, double* y, double t
  * Stops when the true relative residual |b - D x| / |b| <= tol (checked at
  * every restart) or after max_iter outer steps (then SGN_ENOCONV, x the
  * last iterate).  The operator is only as accurate as inner_tol, so choose
- * inner_tol well below tol.  b, x: device complex128, N entries, not
+ * inner_tol well below tol; in mixed precision (sgn_set_precision) the
+ * inner applies run on the FP32 basis, which bounds inner_tol at about
+ * 1e-7.  b, x: device complex128, N entries, not
  * overlapping.  iters, rel_res (host, nullable): outer steps taken and the
  * final true relative residual.  SGN_ENOCONV also when an inner apply
  * misses inner_tol.  Allocates (restart + 2) N complex128 per call. */

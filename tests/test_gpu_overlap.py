@@ -181,3 +181,22 @@ def test_massive_overlap_solve(env, field, mass):
         assert e.value.status == sg.SGN_EINVAL
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_massive_overlap_solve_mixed_precision(env, field):
+    sg, torch = env
+    dims, mu, links, _, S, T, X = field
+    A = wilson.hw_matrix(links, dims, mu, M_W).toarray()
+    ref = overlap.massive_overlap_solve(A, X[3], 0.3)
+    ctx = _ctx(sg, torch, field)
+    try:
+        sg.sgn_set_precision(ctx, sg.SGN_PREC_MIXED)
+        b = torch.from_numpy(X[3]).cuda()
+        x = torch.empty_like(b)
+        st, it, res = sg.sgn_overlap_solve(ctx, b, x, 0.3, 1e-5, max_iter=300, restart=40, inner_tol=1e-7,
+                                           inner_kmax=600)
+        print("mixed overlap solve", st, it, res, flush=True)
+        assert st == sg.SGN_OK and res <= 1e-5
+        assert _rel(x.cpu().numpy(), ref) < 1e-4
+    finally:
+        sg.sgn_destroy(ctx)
