@@ -141,15 +141,3 @@ def sgn_arnoldi(A, x, k: int, S=None, T=None, how: str = "definition") -> np.nda
         return approx_definition(S, T, st)
     return approx_paper(S, T, st)
 
-
-def coefficient_vector(S, T, st: ArnoldiState) -> np.ndarray:
-    """c = sgn(H) Q^dag x, so that y = Q c (used for fixed-k comparisons)."""
-    N = st.V.shape[0]
-    S = np.zeros((N, 0), dtype=np.complex128) if S is None else S
-    T = np.zeros((0, 0), dtype=np.complex128) if T is None else T
-    m = S.shape[1]
-    g = np.zeros(m + st.k, dtype=np.complex128)
-    g[:m] = st.c0
-    if st.k:
-        g[m] = st.beta
-    return sgn_spectral(composite_h(T, st)) @ g

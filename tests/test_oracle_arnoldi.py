@@ -55,7 +55,8 @@ def test_source_inside_schur_space_is_exact_at_k0(tiny):
     S, T, lam, low = deflation.critical_from_dense(Ad, 6)
     xs = S @ np.arange(1, 7)
     st = arnoldi.modified_arnoldi(lambda v: A @ v, xs, S, 10)
-    assert st.k == 0 and st.beta < 1e-12 or st.beta < 1e-12
+    # two Gram-Schmidt passes leave rounding noise of x's size at most
+    assert st.beta < 1e-12 * np.linalg.norm(xs)
     ys = arnoldi.approx_definition(S, T, arnoldi.modified_arnoldi(lambda v: A @ v, xs, S, 0))
     assert _rel(ys, matfunc.sgn_spectral_apply(Ad, xs)) < 1e-11
 
