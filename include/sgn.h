@@ -73,8 +73,8 @@ enum { SGN_ORTH_CGS2 = 0, SGN_ORTH_DELAYED = 1 };
 /* Per-apply statistics (sgn_last_info). */
 typedef struct sgn_info {
   int k_used;         /* Krylov dimension of the returned approximation */
-  int converged;      /* 1 if the change between checkpoints fell below tol */
-  int newton_iters;   /* Roberts iterations summed over all checkpoints */
+  int converged;      /* 1 if the stopping rule (sgn_apply) certified tol */
+  int newton_iters;   /* small-matrix sign iterations summed over all checkpoints */
   int n_matvec;       /* applications of H_w(mu) */
   int n_checkpoints;  /* evaluations of the small-matrix sign */
   int breakdown;      /* 1 if the Krylov space became invariant (exact result): the
@@ -115,7 +115,8 @@ int sgn_get_dims(const sgn_ctx* ctx, int dims[4], long long* n);
  * Results section): Arnoldi on H_w^2 for its smallest-magnitude eigenvalues
  * with thick restarts, a Rayleigh-Ritz step with H_w on the converged span,
  * selection by |Re lambda|, S_m = orthonormalised eigenvectors, T_m =
- * S_m^dag A S_m, then sgn(T_m) by Roberts' iteration.  m = 0 removes
+ * S_m^dag A S_m, then sgn(T_m) on the device (the small-matrix sign of
+ * sgn_set_sign_method: Newton-Schulz by default).  m = 0 removes
  * deflation.  SGN_EDEFL if ||A S - S T||_F / ||A|| > 1e-10 or the eigensolver
  * does not converge.  Requires 0 <= m <= N/4. */
 int sgn_deflate(sgn_ctx* ctx, int m);
@@ -127,8 +128,8 @@ int sgn_deflate_stats(const sgn_ctx* ctx, int* restarts, int* matvecs, double* r
 /* Install a partial Schur pair A S = S T (Eq. pSd) computed elsewhere.
  * S: device complex128, column-major N x m, orthonormal columns;
  * T: host complex128, column-major m x m, upper triangular (the strictly
- * lower part is ignored).  Computes sgn(T) with Roberts' iteration (Eq.
- * Roberts) on the device.  m = 0 removes deflation.  Returns SGN_EINVAL if
+ * lower part is ignored).  Computes sgn(T) on the device with the
+ * small-matrix sign of sgn_set_sign_method.  m = 0 removes deflation.  Returns SGN_EINVAL if
  * m < 0 or m > N/4, SGN_ESINGULAR if T has a diagonal entry with Re = 0. */
 int sgn_deflate_import(sgn_ctx* ctx, int m, const double* S, const double* T);
 
@@ -176,15 +177,23 @@ int sgn_deflation_mode(const sgn_ctx* ctx);
 
 /* ---- the hot path (Section 5.2, steps (iii)-(vi)) ---------------------- */
 
-/* y = sgn(H_w(mu)) x by the deflated modified Arnoldi method.  Krylov steps
- * continue until the change of the coefficient vector between two even-k
- * checkpoints is <= tol (relative), or until k = kmax (then SGN_ENOCONV with
- * y holding the kmax approximation).  x, y: device complex128, N entries.
- * Requires tol > 0, 2 <= kmax <= N.  Returns SGN_EINVAL for NaN/Inf in x. */
+/* y = sgn(H_w(mu)) x by the deflated modified Arnoldi method.  The small
+ * sign is evaluated at even-k checkpoints (Section 4); the relative change e
+ * of y between two checkpoints k' < k is exact (Q has orthonormal columns).
+ * Stopping rule (not in the paper, which measures only against the exact y):
+ * the changes fit a geometric error model err(k) ~ exp(r k), under which
+ * e / (1 - exp(r (k - k'))) estimates the error of y_k'; the apply stops
+ * once that estimate is <= tol and returns y_k (a factor exp(r (k - k')),
+ * at most 1/2 for a confirming checkpoint, more accurate), or at k = kmax
+ * (then SGN_ENOCONV with y holding the kmax approximation).  x, y: device
+ * complex128, N entries.  Requires tol > 0, 2 <= kmax <= N.  Returns
+ * SGN_EINVAL for NaN/Inf in x. */
 int sgn_apply(sgn_ctx* ctx, const double* x, double* y, double tol, int kmax);
 
 /* Fixed Krylov dimension: exactly k modified Arnoldi steps (fewer only on an
- * exact breakdown), then steps (v)-(vi) once.  k >= 0. */
+ * exact breakdown), then steps (v)-(vi) once.  0 <= k <= N - d, d the
+ * installed deflation size (Schur m or the LR pair's m), else SGN_EINVAL:
+ * the composite basis holds at most N orthonormal columns. */
 int sgn_apply_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
 
 /* Several sources of one field: Y_r = sgn(H_w(mu)) X_r for r < nrhs.
@@ -202,7 +211,8 @@ int sgn_apply_fixed(sgn_ctx* ctx, const double* x, double* y, int k);
  * sgn_footprint_bytes(ctx, kmax, min(nrhs, 64)) bytes and is kept for reuse. */
 int sgn_apply_batched(sgn_ctx* ctx, int nrhs, const double* X, double* Y, double tol, int kmax, sgn_info* info);
 
-/* Batched counterpart of sgn_apply_fixed: exactly k steps per source. */
+/* Batched counterpart of sgn_apply_fixed: exactly k steps per source, with
+ * the same bound 0 <= k <= N - d. */
 int sgn_apply_batched_fixed(sgn_ctx* ctx, int nrhs, const double* X, double* Y, int k, sgn_info* info);
 
 /* The overlap Dirac operator at nonzero chemical potential (Section 2, Eq.

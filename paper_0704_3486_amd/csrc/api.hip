@@ -18,8 +18,10 @@
 // iteration of Eq. Roberts as the fallback), which holds sgn(T_m), sgn(H_k)
 // and the Sylvester block Y of Eq. (eq:f_H), then c = sgn(H) Q^dag x with
 // Q^dag x = [c0; beta e_1].  Step (vi) is y = Q c (Eq. eq:formula).
-// Convergence: ||c_k - [c_k'; 0]|| / ||c_k|| <= tol between checkpoints;
-// because Q has orthonormal columns this is exactly the relative change of y.
+// Convergence: ||c_k - [c_k'; 0]|| / ||c_k|| between checkpoints is exactly
+// the relative change of y (Q has orthonormal columns); the stopping rule
+// (ckpt.h) divides it by the model's 1 - exp(r (k - k')) and certifies the
+// earlier checkpoint against tol.
 // The two-pass schedule (SGN_ORTH_CGS2: gs.hip, four sweeps per step) is kept
 // as an option.
 #include <algorithm>
@@ -32,6 +34,7 @@
 #include <string>
 #include <vector>
 
+#include "ckpt.h"
 #include "context.h"
 
 // ---------------------------------------------------------------------------
@@ -275,7 +278,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   double err = 1e30;
   int ncheck = 0;
   int newton_total = 0;
-  std::vector<std::pair<int, double>> hist;  // (k of the earlier checkpoint, change)
+  CkModel model;  // changes between checkpoints (placement and stopping rule)
   int prev_ck = -1;
 
   auto checkpoint = [&](int kk) -> double {
@@ -385,12 +388,16 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
           converged = true;
           break;
         }
-        if (prev_ck >= 0 && e < 1e29) hist.emplace_back(prev_ck, e);
+        if (prev_ck >= 0 && e < 1e29) model.hist.push_back(CkSpan{prev_ck, k, e});
         err = e;
-        if (e <= tol) {
+        // rate of the geometric error model: from this apply's last two
+        // spans, else from the first apply on this field
+        const double rate = model.rate(c->rate_hint < 0.0 ? c->rate_hint : 0.0);
+        if (model.hist.size() >= 2 && CkModel::usable(rate) && c->rate_hint == 0.0) c->rate_hint = rate;
+        if (prev_ck >= 0 && e < 1e29 && CkModel::bound(e, k - prev_ck, rate) <= tol) {
           converged = true;
-          // e ~ error at the previous checkpoint: remember where it was
-          // certified (once per field, so later applies share one schedule)
+          // the previous checkpoint is certified: remember it (once per
+          // field, so later applies share one schedule)
           if (c->k_hint == 0) {
             c->k_hint = prev_ck;
             c->tol_hint = tol;
@@ -398,35 +405,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
           break;
         }
         prev_ck = k;
-        // choose the next checkpoint from a geometric error model
-        // err(k) ~ e_b exp(r (k - k_b)), with r from the last two estimates or
-        // from the previous apply on this field
-        double rate = 0.0;
-        if (hist.size() >= 2) {
-          const auto& a = hist[hist.size() - 2];
-          const auto& b = hist[hist.size() - 1];
-          rate = (std::log(b.second) - std::log(a.second)) / std::max(1, b.first - a.first);
-          if (rate < -1e-6 && c->rate_hint == 0.0) c->rate_hint = rate;
-        } else if (c->rate_hint < 0.0) {
-          rate = c->rate_hint;
-        }
-        int nk;
-        if (hist.empty() && hinted) {
-          nk = k + 4;  // confirm the remembered k
-        } else if (!hist.empty() && rate < -1e-6) {
-          const auto& b = hist.back();
-          const double steps = std::log(0.5 * tol / b.second) / rate;
-          const int target = b.first + (int)std::ceil(1.05 * steps);
-          nk = (target <= k) ? k + 4 : target;  // previous checkpoint should be below tol: confirm
-        } else {
-          nk = k + std::max(8, k / 2);
-        }
-        // the model is fitted on early checkpoints, where the error often
-        // falls more slowly than later; a jump that would land on kmax
-        // leaves no later checkpoint to certify the result against, so
-        // such a jump goes at most as far again as the steps already taken
-        if (nk >= kmax) nk = std::min(nk, 2 * k + 8);
-        next_ck = std::min(kmax, even_up(std::max(nk, k + 2)));
+        next_ck = model.next(k, kmax, tol, rate, hinted && model.hist.empty());
       }
     }
   }
@@ -503,7 +482,7 @@ void install_schur_pair(sgn_ctx* c, int m, const double2* S_internal, const std:
   SGN_HIP(hipMalloc(&c->Tdev, sizeof(double2) * (size_t)m * m));
   SGN_HIP(hipMalloc(&c->sgnT, sizeof(double2) * (size_t)m * m));
   SGN_HIP(hipMemcpyAsync(c->Tdev, Th.data(), sizeof(double2) * Th.size(), hipMemcpyHostToDevice, s));
-  dense_sign(c->dense, m, c->Tdev, m, c->sgnT, m, s, nullptr);  // step (ii): sgn(T_m) by Eq. (Roberts)
+  dense_sign(c->dense, m, c->Tdev, m, c->sgnT, m, s, nullptr);  // step (ii): sgn(T_m)
   SGN_HIP(hipStreamSynchronize(s));
   c->T = std::move(Th);
   c->m = m;
@@ -790,7 +769,8 @@ int sgn_overlap_apply(sgn_ctx* c, const double* x, double* y, double tol, int km
 int sgn_apply_fixed(sgn_ctx* c, const double* x, double* y, int k) {
   return guarded(c, [&] {
     SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
-    SGN_REQUIRE(k >= 0 && k <= c->N - c->m, SGN_EINVAL, "k must satisfy 0 <= k <= N - m");
+    SGN_REQUIRE(k >= 0 && k <= c->N - c->m - c->lr_m, SGN_EINVAL,
+                "k must satisfy 0 <= k <= N - (deflation size)");
     return run_apply(c, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), 1.0, k, k);
   });
 }
@@ -813,7 +793,8 @@ int sgn_apply_adjoint(sgn_ctx* c, const double* x, double* y, double tol, int km
 int sgn_apply_adjoint_fixed(sgn_ctx* c, const double* x, double* y, int k) {
   return guarded(c, [&] {
     SGN_REQUIRE(x && y, SGN_EINVAL, "x and y must not be NULL");
-    SGN_REQUIRE(k >= 0 && k <= c->N - c->m, SGN_EINVAL, "k must satisfy 0 <= k <= N - m");
+    SGN_REQUIRE(k >= 0 && k <= c->N - c->m - c->lr_m, SGN_EINVAL,
+                "k must satisfy 0 <= k <= N - (deflation size)");
     return run_adjoint(c, x, y, 1.0, k, k);
   });
 }
@@ -879,6 +860,7 @@ int sgn_overlap_solve(sgn_ctx* c, const double* b, double* x, double mass, doubl
     double2* h2 = h1 + (R + 2);
     double2* hout = h2 + (R + 2);  // also the solution coefficients y
     double* sc = bsc.d();
+    int* dflag = reinterpret_cast<int*>(sc + 2);  // non-finite record of the outer Gram-Schmidt
     GsWork g;
     gs_alloc(g, N, ld, R + 1);
     struct GsGuard {
@@ -932,12 +914,19 @@ int sgn_overlap_solve(sgn_ctx* c, const double* b, double* x, double mass, doubl
           gs_dot(g, W, ld, N, j + 1, w, h1, s, nullptr);
           gs_update(g, W, ld, N, j + 1, h1, w, nullptr, 0, s, nullptr);
           gs_dot(g, W, ld, N, j + 1, w, h2, s, nullptr);
-          GsFinal fin{h1, hout, nullptr, nullptr, nullptr};
+          SGN_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+          GsFinal fin{h1, hout, nullptr, nullptr, dflag};
           gs_update(g, W, ld, N, j + 1, h2, w, &fin, 0, s, nullptr);
+          int hflag = 0;
           SGN_HIP(hipMemcpyAsync(hh.data(), hout, sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, s));
+          SGN_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
           SGN_HIP(hipStreamSynchronize(s));
+          // the update kernel writes 0 in place of a non-finite norm; its flag
+          // (-1) and the coefficients tell a NaN column from a lucky breakdown
+          bool finite = hflag >= 0;
+          for (int i = 0; i <= j + 1; ++i) finite = finite && std::isfinite(hh[i].x) && std::isfinite(hh[i].y);
+          SGN_REQUIRE(finite, SGN_EINVAL, "overlap solve: non-finite value in the outer Arnoldi basis");
           const double hn = hh[j + 1].x;
-          SGN_REQUIRE(std::isfinite(hn), SGN_EINVAL, "overlap solve: non-finite value");
           cplx* Hj = &H[(size_t)j * (R + 1)];
           for (int i = 0; i <= j; ++i) Hj[i] = cplx(hh[i].x, hh[i].y);
           Hj[j + 1] = hn;

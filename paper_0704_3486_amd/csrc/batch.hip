@@ -21,6 +21,7 @@
 #include <map>
 #include <vector>
 
+#include "ckpt.h"
 #include "context.h"
 
 namespace {
@@ -161,7 +162,7 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
   for (int r = 0; r < nr; ++r) active[r] = r;
   int ncheck = 0, newton_total = 0, n_matvec = 0;
   double ms_sign = 0.0;
-  std::vector<std::pair<int, double>> hist;
+  CkModel model;  // largest change among the running slots, per span
   int prev_ck = -1;
   int next_ck;
   const bool hinted = b.k_hint > 0 && b.tol_hint == tol;
@@ -244,11 +245,24 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
     ++ncheck;
     std::vector<int> done_now, still;
     double worst = 0.0;
+    // rate of the error model: the batch's spans so far (the worst change of
+    // each) or the first batched apply on this field; this span's own change
+    // per slot
+    double rate = model.rate(b.rate_hint < 0.0 ? b.rate_hint : 0.0);
+    if (prev_ck >= 0) {
+      double w = 0.0;
+      for (int r : active) w = std::max(w, h_err[r]);
+      if (w < 1e29) {
+        CkModel probe = model;
+        probe.hist.push_back(CkSpan{prev_ck, k, w});
+        rate = probe.rate(rate);
+      }
+    }
     for (int r : active) {
       const double e = h_err[r];
       res[r].err = e;
       nprev[r] = m + res[r].k;
-      const bool ok = e <= tol;
+      const bool ok = prev_ck >= 0 && e < 1e29 && CkModel::bound(e, k - prev_ck, rate) <= tol;
       if (fixed_k >= 0 || res[r].breakdown || ok || k == kwant) {
         res[r].done = true;
         res[r].converged = fixed_k >= 0 || res[r].breakdown || ok;
@@ -268,30 +282,11 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
     if (active.empty()) return false;
     // next checkpoint from the geometric error model of sgn_apply, on the
     // largest change among the slots still running
-    if (prev_ck >= 0 && worst < 1e29) hist.emplace_back(prev_ck, worst);
+    if (prev_ck >= 0 && worst < 1e29) model.hist.push_back(CkSpan{prev_ck, k, worst});
     prev_ck = k;
-    double rate = 0.0;
-    if (hist.size() >= 2) {
-      const auto& a = hist[hist.size() - 2];
-      const auto& bb = hist[hist.size() - 1];
-      rate = (std::log(bb.second) - std::log(a.second)) / std::max(1, bb.first - a.first);
-      if (rate < -1e-6 && b.rate_hint == 0.0) b.rate_hint = rate;
-    } else if (b.rate_hint < 0.0) {
-      rate = b.rate_hint;
-    }
-    int nk;
-    if (hist.empty() && hinted) {
-      nk = k + 4;
-    } else if (!hist.empty() && rate < -1e-6) {
-      const auto& bb = hist.back();
-      const double steps = std::log(0.5 * tol / bb.second) / rate;
-      const int target = bb.first + (int)std::ceil(1.05 * steps);
-      nk = (target <= k) ? k + 4 : target;
-    } else {
-      nk = k + std::max(8, k / 2);
-    }
-    if (nk >= kwant) nk = std::min(nk, 2 * k + 8);  // bounded jump towards kmax, as in sgn_apply
-    next_ck = std::min(kwant, even_k(std::max(nk, k + 2)));
+    rate = model.rate(b.rate_hint < 0.0 ? b.rate_hint : 0.0);
+    if (model.hist.size() >= 2 && CkModel::usable(rate) && b.rate_hint == 0.0) b.rate_hint = rate;
+    next_ck = model.next(k, kwant, tol, rate, hinted && model.hist.empty());
     return true;
   };
 
@@ -411,7 +406,8 @@ int sgn_overlap_apply_batched(sgn_ctx* c, int nrhs, const double* X, double* Y, 
 
 int sgn_apply_batched_fixed(sgn_ctx* c, int nrhs, const double* X, double* Y, int k, sgn_info* info) {
   return guarded(c, [&] {
-    SGN_REQUIRE(k >= 0 && k <= c->N, SGN_EINVAL, "k must satisfy 0 <= k <= N");
+    SGN_REQUIRE(k >= 0 && k <= c->N - c->m - c->lr_m, SGN_EINVAL,
+                "k must satisfy 0 <= k <= N - (deflation size)");
     return batched_entry(c, nrhs, X, Y, 1.0, std::max(k, 2), k, info);
   });
 }
@@ -429,7 +425,8 @@ int sgn_apply_adjoint_batched(sgn_ctx* c, int nrhs, const double* X, double* Y, 
 
 int sgn_apply_adjoint_batched_fixed(sgn_ctx* c, int nrhs, const double* X, double* Y, int k, sgn_info* info) {
   return guarded(c, [&] {
-    SGN_REQUIRE(k >= 0 && k <= c->N, SGN_EINVAL, "k must satisfy 0 <= k <= N");
+    SGN_REQUIRE(k >= 0 && k <= c->N - c->m - c->lr_m, SGN_EINVAL,
+                "k must satisfy 0 <= k <= N - (deflation size)");
     check_adjoint(c);
     AdjointScope scope(c);
     return batched_entry(c, nrhs, X, Y, 1.0, std::max(k, 2), k, info);

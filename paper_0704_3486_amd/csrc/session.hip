@@ -26,6 +26,7 @@
 #include <string>
 #include <vector>
 
+#include "ckpt.h"
 #include "context.h"
 
 namespace {
@@ -40,7 +41,7 @@ struct Slot {
   double tol = 0.0;
   double2* y = nullptr;  // caller's output (device, ABI layout)
   int next_ck = 0, prev_ck = -1, nprev = -1, ncheck = 0, newton = 0;
-  std::vector<std::pair<int, double>> hist;
+  CkModel model;  // this request's changes between checkpoints
   double err = 1e30;
   double ms_sign = 0.0;
   std::chrono::steady_clock::time_point t0;
@@ -207,28 +208,16 @@ struct sgn_session {
     return sl.req;
   }
 
-  // next checkpoint of a running slot from its own change history (the
-  // geometric model of sgn_apply, without field-level hints)
-  static int next_checkpoint(Slot& sl, int k) {
-    if (sl.prev_ck >= 0 && sl.err < 1e29) sl.hist.emplace_back(sl.prev_ck, sl.err);
+  // stopping test and next checkpoint of a running slot from its own change
+  // history (the rule of sgn_apply, without field-level hints): records the
+  // span that ends at k and returns the model's rate
+  static double record_span(Slot& sl, int k) {
+    if (sl.prev_ck >= 0 && sl.err < 1e29) sl.model.hist.push_back(CkSpan{sl.prev_ck, k, sl.err});
+    return sl.model.rate(0.0);
+  }
+  static int next_checkpoint(Slot& sl, int k, double rate) {
     sl.prev_ck = k;
-    double rate = 0.0;
-    if (sl.hist.size() >= 2) {
-      const auto& a = sl.hist[sl.hist.size() - 2];
-      const auto& b = sl.hist[sl.hist.size() - 1];
-      rate = (std::log(b.second) - std::log(a.second)) / std::max(1, b.first - a.first);
-    }
-    int nk;
-    if (!sl.hist.empty() && rate < -1e-6) {
-      const auto& b = sl.hist.back();
-      const double steps = std::log(0.5 * sl.tol / b.second) / rate;
-      const int target = b.first + (int)std::ceil(1.05 * steps);
-      nk = (target <= k) ? k + 4 : target;
-    } else {
-      nk = k + std::max(8, k / 2);
-    }
-    if (nk >= sl.kreq) nk = std::min(nk, 2 * k + 8);  // bounded jump towards kmax, as in sgn_apply
-    return std::min(sl.kreq, even_up2(std::max(nk, k + 2)));
+    return sl.model.next(k, sl.kreq, sl.tol, rate, false);
   }
 
   // checkpoint (step (v)) for the slots in `due`; finished requests are
@@ -304,7 +293,8 @@ struct sgn_session {
       ++sl.ncheck;
       sl.err = h_err[r];
       sl.nprev = m + kk[r];
-      const bool ok = sl.err <= sl.tol;
+      const double rate = record_span(sl, sl.j);
+      const bool ok = sl.prev_ck >= 0 && sl.err < 1e29 && CkModel::bound(sl.err, sl.j - sl.prev_ck, rate) <= sl.tol;
       if (brk[r] || ok || sl.j >= sl.kreq) {
         finish[m + kk[r]].push_back(r);
         Done d;
@@ -326,7 +316,7 @@ struct sgn_session {
       } else {
         SGN_HIP(hipMemcpyAsync(cp + (size_t)r * nc, cv + (size_t)r * nc, sizeof(double2) * sl.nprev,
                                hipMemcpyDeviceToDevice, s));
-        sl.next_ck = next_checkpoint(sl, sl.j);
+        sl.next_ck = next_checkpoint(sl, sl.j, rate);
       }
     }
     // step (vi) for the finished requests: y = Q c into the caller's buffer

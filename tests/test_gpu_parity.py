@@ -308,3 +308,32 @@ def test_deterministic_repeat(env, small_problem, orth):
         assert torch.equal(y1, y2)
     finally:
         sg.sgn_destroy(ctx)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.2, 0.5])
+def test_6x6_sources_at_tol_1e10_vs_exact(env, mu):
+    # the headline configuration: the library's own m = 20 Schur pair, tol
+    # 1e-10.  The first apply places the checkpoints; the later sources start
+    # where it was certified, and each must still land within 1e-10 of the
+    # exact result (stored for sources 1000..1015 by the oracle's dense
+    # Roberts sign)
+    sg, torch = env
+    dims = (6, 6, 6, 6)
+    Y = _golden(f"c6_mu{mu}_sources")
+    links = synth.random_links(dims, synth.GAUGE_SEED)
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        assert sg.sgn_deflate(ctx, 20) == sg.SGN_OK
+        y = torch.empty(Y.shape[1], dtype=torch.complex128, device="cuda")
+        errs = []
+        for r in range(Y.shape[0]):
+            x = synth.gaussian_source(dims, 1000 + r)
+            st = sg.sgn_apply(ctx, _dev(torch, x), y, 1e-10, 500)
+            info = sg.sgn_last_info(ctx)
+            e = _rel(y.cpu().numpy(), Y[r])
+            errs.append(e)
+            print(mu, r, info["k_used"], info["n_checkpoints"], f"{e:.3e}", flush=True)
+            assert st == sg.SGN_OK
+        assert max(errs) < 1e-10, errs
+    finally:
+        sg.sgn_destroy(ctx)
