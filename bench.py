@@ -165,8 +165,17 @@ def main():
         streams.append(st)
 
     P = 1 if args.serial else max(1, args.per_field)
-    nsrc = (args.steps + args.warmup) * P
-    xs = [torch.from_numpy(synth.gaussian_source(DIMS, 1000 + r)).to(dev) for r in range(max(nsrc, 2))]
+    # sources: the seeds whose exact results are stored for every field
+    # (1000 .. 1000 + n - 1, dense Roberts sign of the oracle), cycled; so
+    # every timed apply is checked against the exact y
+    gold = {}
+    for f, mu in enumerate(MUS):
+        path = os.path.join(GOLDEN, f"c6_mu{mu}_sources.npy")
+        if os.path.exists(path):
+            gold[f] = torch.from_numpy(np.load(path, allow_pickle=False)).to(dev)
+    nstored = min(g.shape[0] for g in gold.values()) if len(gold) == len(MUS) else 0
+    nsrc = nstored if nstored else max((args.steps + args.warmup) * P, 2)
+    xs = [torch.from_numpy(synth.gaussian_source(DIMS, 1000 + r)).to(dev) for r in range(nsrc)]
     ys = [torch.empty(N, dtype=torch.complex128, device=dev) for _ in MUS]
     torch.cuda.synchronize()
 
@@ -217,25 +226,30 @@ def main():
                 unconverged.append(f)
             ks.append(sg.sgn_last_info(ctxs[f])["k_used"])
 
-    def lane_steps(q, first, count, ks):
+    # one output buffer per timed apply and lane (the results are checked
+    # after the timed region)
+    outs = [[torch.empty(N, dtype=torch.complex128, device=dev) for _ in range(args.steps)] for _ in lanes]
+
+    def lane_steps(q, first, count, ks, timed):
         # lane q = p * len(MUS) + f takes source r * P + p of step r
         c, y = lanes[q]
         p = q // len(MUS)
         for r in range(first, first + count):
-            if sg.sgn_apply(c, xs[(r * P + p) % len(xs)], y, TOL, KMAX) != sg.SGN_OK:
+            out = outs[q][r - first] if timed else y
+            if sg.sgn_apply(c, xs[(r * P + p) % len(xs)], out, TOL, KMAX) != sg.SGN_OK:
                 unconverged.append(q)
             ks.append(sg.sgn_last_info(c)["k_used"])
 
-    def run_concurrent(first, count):
+    def run_concurrent(first, count, timed=False):
         ks = [[] for _ in lanes]
-        th = [threading.Thread(target=lane_steps, args=(q, first, count, ks[q])) for q in range(len(lanes))]
+        th = [threading.Thread(target=lane_steps, args=(q, first, count, ks[q], timed)) for q in range(len(lanes))]
         for t in th:
             t.start()
         for t in th:
             t.join()
         return [k for kq in ks for k in kq]
 
-    def run_serial(first, count):
+    def run_serial(first, count, timed=False):
         ks = []
         for r in range(first, first + count):
             for f in range(len(MUS)):
@@ -247,7 +261,7 @@ def main():
     torch.cuda.synchronize()
     unconverged.clear()
     t0 = time.perf_counter()
-    ks = runner(args.warmup, args.steps)
+    ks = runner(args.warmup, args.steps, timed=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timed_unconverged = len(unconverged)
@@ -255,6 +269,8 @@ def main():
     value = applies / elapsed
     mode = "serial" if args.serial else f"{len(lanes)} streams"
     log(f"timed ({mode}): {applies} applies in {elapsed:.3f} s -> {value:.2f} applies/s, mean k {np.mean(ks):.1f}")
+    timed_acc = timed_accuracy(torch, outs if not args.serial else None, gold, nstored, P, args.warmup, args.steps)
+    log(f"timed applies vs exact: {timed_acc}")
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -366,7 +382,7 @@ def main():
                    "applies_in_flight_per_field": P, "graph_steps": args.graph_steps,
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
                    "mean_k": round(float(np.mean(ks)), 1), "timed_unconverged": timed_unconverged},
-        "accuracy": acc,
+        "accuracy": {"timed_applies": timed_acc, "seed_1000": acc},
         "latency": latency,
         "setup": setup,
         "roofline": roofline,
@@ -384,6 +400,26 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def timed_accuracy(torch, outs, gold, nstored, P, warmup, steps):
+    """Relative error |y - y_exact| / |y_exact| of every timed apply (the
+    Results section's measure), against the stored exact results."""
+    if outs is None or not nstored:
+        return None
+    errs, per_mu = [], {}
+    for q, lane in enumerate(outs):
+        f, p = q % len(MUS), q // len(MUS)
+        for i, y in enumerate(lane):
+            r = warmup + i
+            ref = gold[f][(r * P + p) % nstored]
+            e = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
+            errs.append(e)
+            per_mu.setdefault(str(MUS[f]), []).append(e)
+    return {"applies": len(errs), "max_rel_err": max(errs), "median_rel_err": float(np.median(errs)),
+            "max_rel_err_per_mu": {k: max(v) for k, v in per_mu.items()},
+            "sources": f"Gaussian seeds 1000..{1000 + nstored - 1}, cycled",
+            "reference": "oracle dense Roberts sign of H_w(mu) (stored exact y per source and field)"}
 
 
 def latency_schur(sg, torch, ctx, xs, reps=10):
