@@ -150,9 +150,9 @@ class Server:
                     req.t_done = time.perf_counter()
                     req.done.set()
                     continue
-                if h is None:  # cannot happen with the slot count above; requeue
+                if h is None:  # cannot happen with the slot count above; requeue in order
                     with f.cv:
-                        f.queue.appendleft(req)
+                        f.queue.extendleft(reversed(admit[admit.index(req):]))
                     break
                 running[h] = req
             if not running:

@@ -168,3 +168,24 @@ def test_batched_rejects_bad_input(env, problem):
         assert st == sg.SGN_OK
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_fixed_k_bound_is_the_single_source_bound(env, problem):
+    # the composite basis (S V_k) holds at most N columns: k <= N - m for the
+    # single and the batched fixed-k entries alike
+    sg, torch = env
+    dims, mu, links, A, S, T, X = problem
+    N, m = X.shape[1], S.shape[1]
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        sg.sgn_deflate_import(ctx, _dev(torch, S), T)
+        Xd = _dev(torch, X[:2])
+        Y = torch.empty_like(Xd)
+        y = torch.empty_like(Xd[0])
+        for call in (lambda k: sg.sgn_apply_fixed(ctx, Xd[0], y, k),
+                     lambda k: sg.sgn_apply_batched_fixed(ctx, Xd, Y, k)):
+            with pytest.raises(sg.SgnError) as e:
+                call(N - m + 1)
+            assert e.value.status == sg.SGN_EINVAL
+    finally:
+        sg.sgn_destroy(ctx)

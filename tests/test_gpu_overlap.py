@@ -63,7 +63,7 @@ def test_overlap_matches_oracle_and_sign_apply(env, field):
         # same sign arithmetic, then one IEEE add per entry
         assert torch.equal(yo, x + g5 * ys)
         exact = field[3] @ X[0]
-        assert _rel(yo.cpu().numpy(), exact) < 1e-9
+        assert _rel(yo.cpu().numpy(), exact) < 1e-10
     finally:
         sg.sgn_destroy(c1)
         sg.sgn_destroy(c2)
@@ -104,7 +104,7 @@ def test_overlap_batched(env, field):
         assert st == sg.SGN_OK and all(i["converged"] for i in infos)
         for r in range(X.shape[0]):
             exact = field[3] @ X[r]
-            assert _rel(Y[r].cpu().numpy(), exact) < 1e-9
+            assert _rel(Y[r].cpu().numpy(), exact) < 1e-10
     finally:
         sg.sgn_destroy(ctx)
 
@@ -193,10 +193,12 @@ def test_massive_overlap_solve_mixed_precision(env, field):
         sg.sgn_set_precision(ctx, sg.SGN_PREC_MIXED)
         b = torch.from_numpy(X[3]).cuda()
         x = torch.empty_like(b)
-        st, it, res = sg.sgn_overlap_solve(ctx, b, x, 0.3, 1e-5, max_iter=300, restart=40, inner_tol=1e-7,
+        # inner_tol a decade above the FP32 floor of the inner applies (about
+        # 1.4e-7 on this lattice), the outer tolerance a decade above that
+        st, it, res = sg.sgn_overlap_solve(ctx, b, x, 0.3, 1e-4, max_iter=300, restart=40, inner_tol=1e-6,
                                            inner_kmax=600)
         print("mixed overlap solve", st, it, res, flush=True)
-        assert st == sg.SGN_OK and res <= 1e-5
-        assert _rel(x.cpu().numpy(), ref) < 1e-4
+        assert st == sg.SGN_OK and res <= 1e-4
+        assert _rel(x.cpu().numpy(), ref) < 1e-3
     finally:
         sg.sgn_destroy(ctx)

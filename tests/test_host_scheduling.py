@@ -140,3 +140,31 @@ def test_autotune_cache_hit_sets_the_stored_shape(tmp_path, monkeypatch):
     # another Krylov dimension or source count is another entry
     assert at._key(None, 1, 200, "TestGPU") not in json.loads(cache.read_text())
     assert at._key(None, 32, 300, "TestGPU") != key
+
+
+def test_serving_requeues_every_unsubmitted_request_in_order():
+    # a session that turns one request away once (no free slot reported):
+    # that request and every one admitted after it return to the queue in
+    # order, and all of them finish
+    work = {f"r{i}": 2 for i in range(8)}
+    srv, ses, serving = _server(max_slots=4, work=work)
+    inner = ses.submit
+    refused = []
+
+    def submit_refusing_once(x, y, tol, kmax):
+        if x == "r1" and not refused:
+            refused.append(x)
+            return None
+        return inner(x, y, tol, kmax)
+
+    ses.submit = submit_refusing_once
+    reqs = [serving.Request("f", f"r{i}", None, 1e-8, 100) for i in range(8)]
+    for r in reqs:
+        srv.submit(r)
+    srv.start()
+    for r in reqs:
+        assert r.done.wait(10), r.x
+    srv.stop()
+    assert refused == ["r1"]
+    assert ses.admitted == [f"r{i}" for i in range(8)]
+    assert all(r.info is not None and r.error is None for r in reqs)
