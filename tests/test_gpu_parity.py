@@ -233,7 +233,9 @@ def test_6x6_deflated_vs_exact(env, mu):
     try:
         sg.sgn_deflate_import(ctx, _dev(torch, S), T)
         y = torch.empty(x.size, dtype=torch.complex128, device="cuda")
-        st = sg.sgn_apply(ctx, _dev(torch, x), y, 1e-11, 500)
+        # the stopping rule certifies tol on the result before the last
+        # checkpoint, so the stated tolerance is the asserted one
+        st = sg.sgn_apply(ctx, _dev(torch, x), y, 1e-10, 500)
         info = sg.sgn_last_info(ctx)
         print(mu, info, flush=True)
         assert st == sg.SGN_OK
