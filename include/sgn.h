@@ -393,6 +393,19 @@ size_t sgn_footprint_bytes(const sgn_ctx* ctx, int kmax, int nrhs);
  * y must not alias x. */
 int sgn_matvec(sgn_ctx* ctx, const double* x, double* y);
 
+/* sgn_matvec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same y = H_w(mu) x, bitwise, with the two staging vectors (packed x and its
+ * image) in a static per-device buffer of 64 MiB instead of per-call
+ * allocations.  The call allocates nothing.  Limit: 2 * 16 * ceil(12 V / 64)
+ * * 64 bytes <= 64 MiB, i.e. at most 174762 lattice sites (20^4 fits, 24^4
+ * does not); larger lattices give SGN_EINVAL.  The context's device must be
+ * current (SGN_ESTATE otherwise).  Every call on one GPU shares that GPU's
+ * buffer: calls that overlap in time on one GPU (several host threads, or
+ * contexts on different streams) race, so serialise them.  Synchronous like
+ * every call of this library.  x, y: device, N entries, distinct. */
+int sgn_matvec_noalloc(sgn_ctx* ctx, const double* x, double* y);
+
 /* F = sgn(A) for a dense n x n complex128 column-major device matrix, by
  * scaled Roberts/Newton iteration (Eq. Roberts) with a Gauss-Jordan inverse.
  * Uses the context's stream and workspace.  iters (nullable) receives the

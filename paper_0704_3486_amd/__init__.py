@@ -100,6 +100,7 @@ def _load():
         "sgn_last_info": (i, [vp, C.POINTER(sgn_info)]),
         "sgn_footprint_bytes": (C.c_size_t, [vp, i, i]),
         "sgn_matvec": (i, [vp, vp, vp]),
+        "sgn_matvec_noalloc": (i, [vp, vp, vp]),
         "sgn_dense_sign": (i, [vp, i, vp, vp, C.POINTER(C.c_int)]),
         "sgn_set_profiling": (i, [vp, i]),
         "sgn_profile_read": (i, [vp, C.POINTER(sgn_kstat), i]),
@@ -517,6 +518,11 @@ def sgn_footprint_bytes(ctx, kmax, nrhs=1):
 def sgn_matvec(ctx, x, y):
     _, N = sgn_get_dims(ctx)
     return _check(ctx, _lib.sgn_matvec(ctx, _dptr(x, N, "x"), _dptr(y, N, "y")))
+
+
+def sgn_matvec_noalloc(ctx, x, y):
+    _, N = sgn_get_dims(ctx)
+    return _check(ctx, _lib.sgn_matvec_noalloc(ctx, _dptr(x, N, "x"), _dptr(y, N, "y")))
 
 
 def sgn_dense_sign(ctx, A, F):

@@ -31,6 +31,7 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -112,7 +113,45 @@ static const char* kclass_name(int c) {
   }
 }
 
+// Staging of sgn_matvec_noalloc (the packed source and H_w(mu) of it, two
+// vectors of the internal layout), for callers that cannot allocate device
+// memory.  A file-scope device array: each GPU the library runs on holds its
+// own copy until the process ends.  Host code never uses the array's name as
+// an address: sgn_create looks up each device's copy once, with that device
+// current, and every launch takes the looked-up pointer.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device, null until looked up
+std::vector<hipError_t> g_scratch_err;
+
+// look up the device copy of `scratch` for device dev (current); once per device
+void scratch_lookup(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) {
+    g_scratch_ptr.resize(dev + 1, nullptr);
+    g_scratch_err.resize(dev + 1, hipSuccess);
+  }
+  if (g_scratch_ptr[dev] || g_scratch_err[dev] != hipSuccess) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p)
+    g_scratch_ptr[dev] = p;
+  else
+    g_scratch_err[dev] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
+void* scratch_device_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  SGN_REQUIRE(dev >= 0 && dev < (int)g_scratch_ptr.size() && g_scratch_ptr[dev], SGN_EHIP,
+              std::string("static staging buffer unavailable on this device: ") +
+                  (dev >= 0 && dev < (int)g_scratch_err.size() ? hipGetErrorString(g_scratch_err[dev])
+                                                               : "no context was created on it"));
+  return g_scratch_ptr[dev];
+}
 
 thread_local std::string g_create_error;
 
@@ -580,6 +619,8 @@ sgn_ctx* sgn_create(const double* gauge, const int dims[4], double mu, double m_
     c->m_w = m_w;
     c->N = (int)(12 * V);
     c->ldq = ((size_t)c->N + 63) / 64 * 64;
+    SGN_HIP(hipGetDevice(&c->device));
+    scratch_lookup(c->device);  // once per device (sgn_matvec_noalloc)
     SGN_HIP(hipMalloc(&c->links, sizeof(double2) * 36 * (size_t)V));
     double2* graw = nullptr;
     SGN_HIP(hipMalloc(&graw, sizeof(double2) * 36 * (size_t)V));
@@ -1129,6 +1170,27 @@ int sgn_matvec(sgn_ctx* c, const double* x, double* y) {
     }
     SGN_HIP(hipFree(a));
     SGN_HIP(hipFree(b));
+    return SGN_OK;
+  });
+}
+
+int sgn_matvec_noalloc(sgn_ctx* c, const double* x, double* y) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(x && y && x != y, SGN_EINVAL, "x and y must be distinct non-NULL buffers");
+    const size_t need = 2 * sizeof(double2) * c->ldq;
+    SGN_REQUIRE(need <= kScratchBytes, SGN_EINVAL,
+                "lattice too large for the static staging buffer (2 * 16 * ceil(12 V / 64) * 64 bytes must be "
+                "<= 64 MiB, i.e. at most 174762 sites)");
+    int dev = -1;
+    SGN_HIP(hipGetDevice(&dev));
+    SGN_REQUIRE(dev == c->device, SGN_ESTATE, "the context's device must be current");
+    auto* base = static_cast<double2*>(scratch_device_ptr(dev));
+    double2* a = base;
+    double2* b = base + c->ldq;
+    wilson_pack(c->lat, reinterpret_cast<const double2*>(x), a, c->stream);
+    wilson_apply(c->lat, c->links, a, b, nullptr, nullptr, c->stream, nullptr);
+    wilson_unpack(c->lat, b, reinterpret_cast<double2*>(y), c->stream);
+    SGN_HIP(hipStreamSynchronize(c->stream));
     return SGN_OK;
   });
 }

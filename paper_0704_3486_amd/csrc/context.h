@@ -73,6 +73,7 @@ struct BatchWork {
 };
 
 struct sgn_ctx {
+  int device = -1;  // HIP device current at sgn_create
   Lattice lat{};
   int N = 0;
   size_t ldq = 0;
