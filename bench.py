@@ -331,7 +331,8 @@ def main():
         tf = s["flops"] / (s["ms"] * 1e-3) / 1e12
         sign = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4), "avg_launch_us": kern["ns_gemm"]["avg_us"],
-                "kernel": "rocBLAS ZGEMM (Tensile Cijk_..._ZB_MI16x16x4, FP64 MFMA), Newton-Schulz products"}
+                "kernel": "zgemm_splitk_kernel / zgemm_kernel (hand-written, v_mfma_f64_16x16x4f64), "
+                          "Newton-Schulz products X^2 and X Y / 2 with their epilogues"}
     stencil_6 = None
     if "wilson_hw" in kstats and kstats["wilson_hw"]["ms"] > 0:
         s = kstats["wilson_hw"]

@@ -412,6 +412,14 @@ int sgn_matvec_noalloc(sgn_ctx* ctx, const double* x, double* y);
  * iteration count.  SGN_ESINGULAR on a singular iterate. */
 int sgn_dense_sign(sgn_ctx* ctx, int n, const double* A, double* F, int* iters);
 
+/* C = A B for complex128 column-major device matrices (A: M x K, ld lda;
+ * B: K x N, ld ldb; C: M x N, ld ldc), on the matrix cores with the kernel
+ * of the small-matrix sign's Newton-Schulz products (FP64 MFMA).  Uses the
+ * context's stream.  SGN_EINVAL for negative sizes or short leading
+ * dimensions. */
+int sgn_zgemm(sgn_ctx* ctx, int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C,
+              int ldc);
+
 /* Kernel-level timing with HIP events on the context's stream.  When on,
  * every launch of the instrumented kernels is bracketed by events and its
  * duration and algorithmic bytes are accumulated per kernel class. */

@@ -101,6 +101,7 @@ def _load():
         "sgn_footprint_bytes": (C.c_size_t, [vp, i, i]),
         "sgn_matvec": (i, [vp, vp, vp]),
         "sgn_matvec_noalloc": (i, [vp, vp, vp]),
+        "sgn_zgemm": (i, [vp, i, i, i, vp, i, vp, i, vp, i]),
         "sgn_dense_sign": (i, [vp, i, vp, vp, C.POINTER(C.c_int)]),
         "sgn_set_profiling": (i, [vp, i]),
         "sgn_profile_read": (i, [vp, C.POINTER(sgn_kstat), i]),
@@ -523,6 +524,17 @@ def sgn_matvec(ctx, x, y):
 def sgn_matvec_noalloc(ctx, x, y):
     _, N = sgn_get_dims(ctx)
     return _check(ctx, _lib.sgn_matvec_noalloc(ctx, _dptr(x, N, "x"), _dptr(y, N, "y")))
+
+
+def sgn_zgemm(ctx, A, B, C):
+    """C = A B for GPU complex128 tensors given as column-major matrices: pass
+    each matrix M as M.T.contiguous() (shape (cols, rows)); C likewise."""
+    K, M = A.shape
+    N, K2 = B.shape
+    if K2 != K or tuple(C.shape) != (N, M):
+        raise ValueError("shapes do not match")
+    return _check(ctx, _lib.sgn_zgemm(ctx, M, N, K, _dptr(A, A.numel(), "A"), max(M, 1), _dptr(B, B.numel(), "B"),
+                                      max(K, 1), _dptr(C, C.numel(), "C"), max(M, 1)))
 
 
 def sgn_dense_sign(ctx, A, F):

@@ -14,7 +14,7 @@
 // re-orthogonalisation), in two sweeps over Q per step.  X = S_m^dag A V_k
 // and H_k accumulate in one composite matrix H = [[T_m, X], [0, H_k]]
 // (Eq. eq:newH).  At even checkpoints k (step (v)) the device evaluates the
-// sign of the composite matrix (Newton-Schulz on rocBLAS ZGEMM, Roberts'
+// sign of the composite matrix (Newton-Schulz on the matrix cores, Roberts'
 // iteration of Eq. Roberts as the fallback), which holds sgn(T_m), sgn(H_k)
 // and the Sylvester block Y of Eq. (eq:f_H), then c = sgn(H) Q^dag x with
 // Q^dag x = [c0; beta e_1].  Step (vi) is y = Q c (Eq. eq:formula).
@@ -60,11 +60,11 @@ int Profiler::begin(int cls) {
   return (int)pending.size() - 1;
 }
 
-void Profiler::end(int idx, double nbytes, double nflops) {
+void Profiler::end(int idx, double nbytes, double nflops, int count) {
   if (!on || idx < 0) return;
   Pending& p = pending[idx];
   SGN_HIP(hipEventRecord(p.b, stream));
-  launches[p.cls] += 1;
+  launches[p.cls] += count;
   bytes[p.cls] += nbytes;
   flops[p.cls] += nflops;
 }
@@ -1204,6 +1204,25 @@ int sgn_dense_sign(sgn_ctx* c, int n, const double* A, double* F, int* iters) {
     SGN_HIP(hipStreamSynchronize(c->stream));
     if (c->prof.on) c->prof.flush();
     if (iters) *iters = it;
+    return SGN_OK;
+  });
+}
+
+int sgn_zgemm(sgn_ctx* c, int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C,
+              int ldc) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(M >= 0 && N >= 0 && K >= 0, SGN_EINVAL, "sizes must be >= 0");
+    SGN_REQUIRE(lda >= std::max(M, 1) && ldb >= std::max(K, 1) && ldc >= std::max(M, 1), SGN_EINVAL,
+                "leading dimensions too small");
+    if (M == 0 || N == 0) return SGN_OK;
+    SGN_REQUIRE(C && ((A && B) || K == 0), SGN_EINVAL, "NULL matrix");
+    if (K == 0) {
+      for (int j = 0; j < N; ++j) dev_zero(reinterpret_cast<double2*>(C) + (size_t)j * ldc, (size_t)M, c->stream);
+    } else {
+      zgemm(M, N, K, 1.0, reinterpret_cast<const double2*>(A), lda, 0, reinterpret_cast<const double2*>(B), ldb, 0,
+            reinterpret_cast<double2*>(C), ldc, 0, 1, c->stream);
+    }
+    SGN_HIP(hipStreamSynchronize(c->stream));
     return SGN_OK;
   });
 }

@@ -19,8 +19,6 @@
 #include <cmath>
 #include <cstring>
 
-#include <rocblas/rocblas.h>
-
 #include "internal.h"
 
 namespace {
@@ -433,19 +431,16 @@ void dense_free(DenseWork& d) {
   if (d.counters) (void)hipFree(d.counters);
   if (d.part) (void)hipFree(d.part);
   if (d.spart) (void)hipFree(d.spart);
-  if (d.host_spart) (void)hipHostFree(d.host_spart);
+  if (d.ns_state) (void)hipFree(d.ns_state);
+  if (d.host_state) (void)hipHostFree(d.host_state);
   const int method = d.method;
-  void* blas = d.blas;
+  const int last_iters = d.last_iters;
   d = DenseWork{};
   d.method = method;
-  d.blas = blas;
+  d.last_iters = last_iters;
 }
 
-void dense_destroy(DenseWork& d) {
-  dense_free(d);
-  if (d.blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(d.blas));
-  d.blas = nullptr;
-}
+void dense_destroy(DenseWork& d) { dense_free(d); }
 
 void dev_zero(double2* p, size_t n, hipStream_t s) {
   if (n == 0) return;
@@ -577,63 +572,18 @@ static int dense_sign_newton_batched(DenseWork& d, int n, int nb, const double2*
 // satisfies |1 - z^2| < 1, which holds for the composite Arnoldi matrices of
 // this method (their Ritz values have |Im| well below |Re| once the critical
 // eigenvalues are deflated); growth of the small eigenvalues is 3/2 per step,
-// then quadratic.  Each step is two complex GEMMs.  When the residual
-// |X^2 - I|_F / sqrt(n) does not fall below 1e-8 within 60 steps (or is not
-// finite), the caller falls back to Roberts' iteration with Gauss-Jordan
-// inverses, which converges for any matrix without eigenvalues on the
-// imaginary axis.
+// then quadratic.  Each step is two complex products on the matrix cores
+// (zgemm.hip), one launch each for the whole batch, and a per-matrix check
+// of |X^2 - I|_F / sqrt(n) on the device; a matrix stops once it is below
+// 1e-7 (the next iterate is then at rounding level), or when it diverges or
+// has not settled within 60 steps (then the caller falls back to Roberts'
+// iteration with Gauss-Jordan inverses, which converges for any matrix
+// without eigenvalues on the imaginary axis).  The host reads the per-matrix
+// states only every other step from the step where the previous call
+// settled, so launches run back to back in between; a finished matrix's
+// later launches return at once.
 // ---------------------------------------------------------------------------
 namespace {
-
-constexpr int kEpi = 256;  // entries per workgroup of the epilogue
-
-void blas_check(rocblas_status st) {
-  if (st != rocblas_status_success)
-    throw SgnError{SGN_EHIP, std::string("rocBLAS: ") + rocblas_status_to_string(st)};
-}
-
-// the context's rocBLAS handle on stream s: host scalars, no atomics in the
-// GEMM kernels (results reproducible run to run)
-rocblas_handle blas_handle(DenseWork& d, hipStream_t s) {
-  if (!d.blas) {
-    rocblas_handle h = nullptr;
-    blas_check(rocblas_create_handle(&h));
-    d.blas = h;
-    blas_check(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
-    blas_check(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));
-  }
-  rocblas_handle h = static_cast<rocblas_handle>(d.blas);
-  blas_check(rocblas_set_stream(h, s));
-  return h;
-}
-
-
-// Y = 3I - P in place, P = X^2 from the GEMM, and per kEpi entries the
-// partial sum of |P - I|^2 (fixed-order tree); blockIdx.y = matrix of the
-// batch (stride nn), skipped once it has stopped
-__global__ void __launch_bounds__(kEpi) ns_epilogue_kernel(double2* __restrict__ Y, int n, size_t nn,
-                                                           double* __restrict__ part, int nblk,
-                                                           unsigned long long skip) {
-  const int b = blockIdx.y;
-  if ((skip >> b) & 1ull) return;
-  const size_t e = (size_t)blockIdx.x * kEpi + threadIdx.x;
-  double p = 0.0;
-  if (e < nn) {
-    const int j = (int)(e / n), i = (int)(e - (size_t)j * n);
-    const double2 v = Y[(size_t)b * nn + e];
-    const double dI = (i == j) ? 1.0 : 0.0;
-    p = (v.x - dI) * (v.x - dI) + v.y * v.y;
-    Y[(size_t)b * nn + e] = make_double2(3.0 * dI - v.x, -v.y);
-  }
-  __shared__ double red[kEpi];
-  red[threadIdx.x] = p;
-  __syncthreads();
-  for (int off = kEpi / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(size_t)b * nblk + blockIdx.x] = red[0];
-}
 
 // X_b = A_b / |A_b|_1 (max column sum of |a_ij|); one workgroup per matrix
 // column sums of |A_ij| (one wavefront per column, lanes over rows)
@@ -671,32 +621,38 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
   X[(size_t)b * nn + e] = cscale(A[(size_t)b * astride + (size_t)j * lda + i], inv);
 }
 
-}  // namespace
-
-// partial sums of |X^2 - I| per kEpi entries (and the column sums of the
-// 1-norm) for nb matrices of order n; returns the entries in use
-void dev_zgemm_nn(DenseWork& d, int M, int N, int K, const double2* A, int lda, const double2* B, int ldb,
-                  double2* C, int ldc, hipStream_t s) {
-  if (M <= 0 || N <= 0) return;
-  rocblas_handle h = blas_handle(d, s);
-  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-  blas_check(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, M, N, K, &one,
-                           reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                           reinterpret_cast<const rocblas_double_complex*>(B), ldb, &zero,
-                           reinterpret_cast<rocblas_double_complex*>(C), ldc));
+__global__ void ns_init_kernel(int* state, int* iters, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) {
+    state[b] = 0;
+    iters[b] = 0;
+  }
 }
 
-static size_t ns_reserve(DenseWork& d, int n, int nb) {
-  const size_t nblk = ((size_t)n * n + kEpi - 1) / kEpi;
-  const size_t nparts = std::max(nblk, (size_t)n) * nb;
+}  // namespace
+
+// C = A B (column-major, complex) on the matrix cores
+void dev_zgemm_nn(DenseWork& d, int M, int N, int K, const double2* A, int lda, const double2* B, int ldb,
+                  double2* C, int ldc, hipStream_t s) {
+  (void)d;
+  zgemm(M, N, K, 1.0, A, lda, 0, B, ldb, 0, C, ldc, 0, 1, s);
+}
+
+static void ns_reserve(DenseWork& d, int n, int nb) {
+  // residual partials of the squaring launches; also the column sums (n per matrix)
+  const size_t nparts = (size_t)std::max(zgemm_ns_parts(n, nb), n) * nb;
   if (d.nspart < nparts) {
     if (d.spart) (void)hipFree(d.spart);
-    if (d.host_spart) (void)hipHostFree(d.host_spart);
     SGN_HIP(hipMalloc(&d.spart, sizeof(double) * nparts));
-    SGN_HIP(hipHostMalloc(&d.host_spart, sizeof(double) * nparts, hipHostMallocDefault));
     d.nspart = nparts;
   }
-  return nparts;
+  if (d.nstate < nb) {
+    if (d.ns_state) (void)hipFree(d.ns_state);
+    if (d.host_state) (void)hipHostFree(d.host_state);
+    SGN_HIP(hipMalloc(&d.ns_state, sizeof(int) * 2 * (size_t)nb));
+    SGN_HIP(hipHostMalloc(&d.host_state, sizeof(int) * 2 * (size_t)nb, hipHostMallocDefault));
+    d.nstate = nb;
+  }
 }
 
 // Newton-Schulz for nb matrices; returns the iterations run.  done marks the
@@ -704,72 +660,69 @@ static size_t ns_reserve(DenseWork& d, int n, int nb) {
 // others diverged or did not settle within the iteration limit.
 static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F,
                                  int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done) {
+  SGN_REQUIRE(nb <= kMaxBatch, SGN_EINVAL, "dense_sign: batch too large");
   dense_alloc(d, n, nb);
   const size_t nn = (size_t)n * n;
   ns_reserve(d, n, nb);
+  int* state = d.ns_state;
+  int* iters = d.ns_state + nb;
   // the column sums use the partial-sum buffer (sized above for both uses)
   hipLaunchKernelGGL(colsum_kernel, dim3((n + 3) / 4, nb), dim3(256), 0, s, A, lda, astride, d.spart, n);
   SGN_HIP(hipGetLastError());
   hipLaunchKernelGGL(scale_by_norm1_kernel, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, s, A, lda, astride,
                      d.spart, d.S, n, nn);
   SGN_HIP(hipGetLastError());
+  hipLaunchKernelGGL(ns_init_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, state, iters, nb);
+  SGN_HIP(hipGetLastError());
   double2* X = d.S;
   double2* Y = d.Ma;
   double2* Xn = d.Mb;
-  const int nblk = (int)((nn + kEpi - 1) / kEpi);
+  const int nparts = zgemm_ns_parts(n, nb);
   const int maxit = 60;
-  int iters = 0;
-  SGN_REQUIRE(nb <= kMaxBatch, SGN_EINVAL, "dense_sign: batch too large");
-  done = 0;                      // matrices that met the stopping test (F written)
-  unsigned long long stop = 0;   // done, or left for the fallback
-  const unsigned long long all = nb == 64 ? ~0ull : ((1ull << nb) - 1);
-  rocblas_handle h = blas_handle(d, s);
-  const rocblas_double_complex one(1.0, 0.0), half(0.5, 0.0), zero(0.0, 0.0);
-  auto rc = [](const double2* p) { return reinterpret_cast<const rocblas_double_complex*>(p); };
-  auto rw = [](double2* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
-  for (int it = 1; it <= maxit && stop != all; ++it) {
-    // per product and matrix still iterating: read two n x n operands, write
-    // one; 8 n^3 real flops.  One GEMM call per matrix, so a matrix gets the
-    // same arithmetic in any batch.
-    for (int b = 0; b < nb; ++b) {
-      if ((stop >> b) & 1ull) continue;
-      const int idx = prof ? prof->begin(K_NS_GEMM) : -1;
-      blas_check(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, rc(X + b * nn), n,
-                               rc(X + b * nn), n, &zero, rw(Y + b * nn), n));
-      if (prof) prof->end(idx, 3.0 * 16.0 * (double)nn, 8.0 * (double)nn * n);
-    }
-    hipLaunchKernelGGL(ns_epilogue_kernel, dim3(nblk, nb), dim3(kEpi), 0, s, Y, n, nn, d.spart, nblk, stop);
-    SGN_HIP(hipGetLastError());
-    for (int b = 0; b < nb; ++b) {
-      if ((stop >> b) & 1ull) continue;
-      const int idx = prof ? prof->begin(K_NS_GEMM) : -1;
-      blas_check(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &half, rc(X + b * nn), n,
-                               rc(Y + b * nn), n, &zero, rw(Xn + b * nn), n));
-      if (prof) prof->end(idx, 3.0 * 16.0 * (double)nn, 8.0 * (double)nn * n);
-    }
+  const int first_look = std::max(6, std::min(d.last_iters, maxit));
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    int idx = prof ? prof->begin(K_NS_GEMM) : -1;
+    zgemm_ns_square(n, X, Y, nn, nb, state, d.spart, s);
+    if (prof) prof->end(idx, 0.0, 0.0, 0);
+    ns_check(d.spart, nparts, n, state, iters, it, maxit, nb, s);
+    idx = prof ? prof->begin(K_NS_GEMM) : -1;
+    zgemm_ns_update(n, X, Y, Xn, nn, nb, state, F, ldf, fstride, s);
+    if (prof) prof->end(idx, 0.0, 0.0, 0);
     std::swap(X, Xn);
-    iters = it;
-    if (it < 6) continue;  // growth phase: no need to look yet
-    SGN_HIP(hipMemcpyAsync(d.host_spart, d.spart, sizeof(double) * (size_t)nblk * nb, hipMemcpyDeviceToHost, s));
-    SGN_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < nb; ++b) {
-      if ((stop >> b) & 1ull) continue;
-      double sum = 0.0;
-      for (int t = 0; t < nblk; ++t) sum += d.host_spart[(size_t)b * nblk + t];
-      const double r = std::sqrt(sum / n);  // |X^2 - I| of the iterate before this update
-      if (!std::isfinite(r) || r > 1e3) {
-        stop |= 1ull << b;  // diverging: left for the fallback
-      } else if (r < 1e-7) {
-        // error after the update ~ (3/2) (r/2)^2: below 1e-14 once r < 1e-7
-        hipLaunchKernelGGL(copy_mat_batched_kernel, dim3((unsigned)((nn + 255) / 256), 1), dim3(256), 0, s,
-                           X + (size_t)b * nn, n, nn, F + (size_t)b * fstride, ldf, fstride, n, n);
-        SGN_HIP(hipGetLastError());
-        done |= 1ull << b;
-        stop |= 1ull << b;
-      }
+    if (it >= first_look && ((it - first_look) % 2 == 0 || it == maxit)) {
+      SGN_HIP(hipMemcpyAsync(d.host_state, state, sizeof(int) * 2 * (size_t)nb, hipMemcpyDeviceToHost, s));
+      SGN_HIP(hipStreamSynchronize(s));
+      bool all = true;
+      for (int b = 0; b < nb; ++b) all = all && d.host_state[b] != 0;
+      if (all) break;
     }
   }
-  return iters;
+  it = std::min(it, maxit);
+  // a final read (the loop may have ended at maxit without one)
+  SGN_HIP(hipMemcpyAsync(d.host_state, state, sizeof(int) * 2 * (size_t)nb, hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipStreamSynchronize(s));
+  done = 0;
+  int most = 0;
+  double gemm_matrices = 0.0;  // matrix products that did work
+  for (int b = 0; b < nb; ++b) {
+    const int st = d.host_state[b];
+    if (st == 1 || st == 2) {
+      done |= 1ull << b;
+      most = std::max(most, d.host_state[nb + b]);
+      gemm_matrices += 2.0 * d.host_state[nb + b];
+    } else {
+      gemm_matrices += 2.0 * it;
+    }
+  }
+  if (most > 0) d.last_iters = most;
+  if (prof) {
+    // per product: read two n x n operands, write one; 8 n^3 real flops
+    prof->bytes[K_NS_GEMM] += gemm_matrices * 3.0 * 16.0 * (double)nn;
+    prof->flops[K_NS_GEMM] += gemm_matrices * 8.0 * (double)nn * n;
+    prof->launches[K_NS_GEMM] += 2 * (long long)std::max(most, done == 0 ? it : most);
+  }
+  return done ? most : it;
 }
 
 void dense_reserve(DenseWork& d, int n, int nb) {

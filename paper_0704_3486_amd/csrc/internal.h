@@ -94,7 +94,8 @@ struct Profiler {
   // bracket a launch: returns index of pending record or -1
   int begin(int cls);
 
-  void end(int idx, double nbytes, double nflops);
+  // count: launches the interval counts as (0: accounted by the caller)
+  void end(int idx, double nbytes, double nflops, int count = 1);
   void flush();  // synchronise and accumulate the pending durations
   void reset();
   ~Profiler();
@@ -200,8 +201,11 @@ void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t 
 struct DenseWork {
   int method = 0;         // 0: Newton-Schulz with Roberts/Gauss-Jordan fallback; 1: Roberts only
   double* spart = nullptr;  // Newton-Schulz residual partials
-  double* host_spart = nullptr;
   size_t nspart = 0;
+  int* ns_state = nullptr;  // Newton-Schulz per-matrix state [nb] and iterations [nb]
+  int* host_state = nullptr;  // pinned mirror
+  int nstate = 0;
+  int last_iters = 0;       // iterations the previous call needed (when the host first looks)
   int ncap = 0;
   int nbcap = 0;          // matrices per batch
   int* host_flag = nullptr;
@@ -216,13 +220,11 @@ struct DenseWork {
   unsigned* counters = nullptr;
   double* part = nullptr;  // reduction partials
   int npart = 0;
-  void* blas = nullptr;    // rocBLAS handle (Newton-Schulz GEMMs), created on first use
 };
 void dense_alloc(DenseWork& d, int n);
 void dense_alloc(DenseWork& d, int n, int nb);
-// free the buffers (the rocBLAS handle stays for reuse)
+// free the buffers
 void dense_free(DenseWork& d);
-// free everything, the rocBLAS handle included
 void dense_destroy(DenseWork& d);
 // allocate everything dense_sign_batched needs up to order n and batch nb,
 // so that later calls of at most that size allocate nothing
@@ -254,7 +256,7 @@ void gs_combine(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, 
                 double2* y, double2* scratch_neg, hipStream_t s, Profiler* prof);
 // out = -in
 void dev_negate(const double2* in, double2* out, int n, hipStream_t s);
-// C = A B (column-major, complex; rocBLAS with atomics off, deterministic)
+// C = A B (column-major, complex; matrix-core kernel of zgemm.hip, deterministic)
 void dev_zgemm_nn(DenseWork& d, int M, int N, int K, const double2* A, int lda, const double2* B, int ldb,
                   double2* C, int ldc, hipStream_t s);
 // x[i] = a[i] x[i] (complex, n entries)
@@ -263,3 +265,21 @@ void dev_cmul(const double2* a, double2* x, int n, hipStream_t s);
 void dev_to_f32(const double2* in, float2* out, size_t n, hipStream_t s);
 // any non-finite entry -> flag = 1
 void dev_check_finite(const double2* v, size_t n, int* flag, hipStream_t s);
+
+// complex FP64 products on the matrix cores (zgemm.hip)
+// C_b = alpha A_b B_b (M x K times K x N, column-major) for nb matrices at strides
+void zgemm(int M, int N, int K, double alpha, const double2* A, int lda, size_t astride, const double2* B, int ldb,
+           size_t bstride, double2* C, int ldc, size_t cstride, int nb, hipStream_t s);
+// Newton-Schulz step of nb n x n matrices at stride `stride`: Y = 3I - X X with
+// per-wavefront partials of |X X - I|^2 (zgemm_ns_parts(n, nb) per matrix),
+// skipped for matrices whose state is not 0
+void zgemm_ns_square(int n, const double2* X, double2* Y, size_t stride, int nb, const int* state, double* part,
+                     hipStream_t s);
+// Xn = X Y / 2, also into F_b (ld ldf, stride fstride) where state == 1;
+// skipped where state > 1
+void zgemm_ns_update(int n, const double2* X, const double2* Y, double2* Xn, size_t stride, int nb, const int* state,
+                     double2* F, int ldf, size_t fstride, hipStream_t s);
+int zgemm_ns_parts(int n, int nb);
+// per matrix: residual from the partials and the state transition of iteration it
+void ns_check(const double* part, int nparts, int n, int* state, int* iters, int it, int maxit, int nb,
+              hipStream_t s);
