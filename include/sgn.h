@@ -148,6 +148,28 @@ int sgn_deflate_export(const sgn_ctx* ctx, double* S, double* T, double* evals);
  * safe.  Device memory grows by 2 ncv N complex128 during the setup. */
 int sgn_set_deflation_krylov(sgn_ctx* ctx, int ncv);
 
+/* Chebyshev filter of the deflation eigensolver (sgn_deflate, sgn_deflate_lr;
+ * the faster setup the Results section's ARPACK run on H_w^2 asks for): the
+ * thick-restart Arnoldi method runs on p(H_w^2) = T_d((H_w^2 - c) / e), the
+ * degree-d Chebyshev polynomial of the interval [alpha, beta] = [c - e,
+ * c + e] = [cut rho, rho] of H_w^2's spectrum (rho its spectral radius,
+ * estimated by a 40-step Arnoldi run, with 10 % margin).  p stays within
+ * [-1, 1] on that interval and grows fast below it, so the smallest-
+ * magnitude eigenvalues of H_w^2 become the largest of p(H_w^2), found in few
+ * restarts; the eigenvectors are the same, and the Rayleigh-Ritz step with
+ * H_w, the selection and the Schur-residual test follow as without the
+ * filter.  Each Arnoldi step costs 2 d stencil applications instead of 2, so
+ * the filter pays where orthogonalisation and restarts dominate (large
+ * lattices, clustered spectra).  If the filtered run has not converged within
+ * 300 restarts (for instance when fewer than m + max(10, m/2) eigenvalues lie
+ * below alpha), the unfiltered solver runs.  degree 0 disables the filter;
+ * cut 0 selects the default 1/16.  Default degree 16.  SGN_EINVAL for degree
+ * outside [0, 200] or cut outside (0, 1). */
+int sgn_set_deflation_filter(sgn_ctx* ctx, int degree, double cut);
+/* Of the last sgn_deflate / sgn_deflate_lr: the filter degree of the run that
+ * converged (0: unfiltered) and its interval [alpha, beta]. */
+int sgn_deflate_filter_stats(const sgn_ctx* ctx, int* degree, double* alpha, double* beta);
+
 /* Number of installed deflation vectors, Schur or LR (0 if none, <0 on error). */
 int sgn_deflation_size(const sgn_ctx* ctx);
 

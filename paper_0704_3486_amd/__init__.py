@@ -109,6 +109,8 @@ def _load():
         "sgn_deflate": (i, [vp, i]),
         "sgn_deflate_lr": (i, [vp, i]),
         "sgn_set_deflation_krylov": (i, [vp, i]),
+        "sgn_set_deflation_filter": (i, [vp, i, d]),
+        "sgn_deflate_filter_stats": (i, [vp, C.POINTER(C.c_int), C.POINTER(d), C.POINTER(d)]),
         "sgn_deflate_lr_import": (i, [vp, i, vp, vp, vp]),
         "sgn_deflate_lr_export": (i, [vp, vp, vp, vp]),
         "sgn_deflation_mode": (i, [vp]),
@@ -214,7 +216,15 @@ def sgn_deflate(ctx, m):
 def sgn_deflate_stats(ctx):
     r, mv, res = C.c_int(), C.c_int(), C.c_double()
     _check(ctx, _lib.sgn_deflate_stats(ctx, C.byref(r), C.byref(mv), C.byref(res)))
-    return {"restarts": r.value, "matvecs": mv.value, "residual": res.value}
+    out = {"restarts": r.value, "matvecs": mv.value, "residual": res.value}
+    out.update(sgn_deflate_filter_stats(ctx))
+    return out
+
+
+def sgn_deflate_filter_stats(ctx):
+    deg, a, b = C.c_int(), C.c_double(), C.c_double()
+    _check(ctx, _lib.sgn_deflate_filter_stats(ctx, C.byref(deg), C.byref(a), C.byref(b)))
+    return {"filter_degree": deg.value, "filter_interval": [a.value, b.value]}
 
 
 def sgn_deflate_import(ctx, S, T):
@@ -260,6 +270,10 @@ def sgn_deflation_mode(ctx):
     mode = _lib.sgn_deflation_mode(ctx)
     _check(ctx, mode if mode < 0 else SGN_OK)
     return mode
+
+
+def sgn_set_deflation_filter(ctx, degree, cut=0.0):
+    return _check(ctx, _lib.sgn_set_deflation_filter(ctx, int(degree), float(cut)))
 
 
 def sgn_set_deflation_krylov(ctx, ncv):

@@ -72,6 +72,10 @@ struct BatchWork {
   }
 };
 
+// default filter of the deflation eigensolver (sgn_set_deflation_filter)
+constexpr int kDefaultFilterDegree = 16;
+constexpr double kDefaultFilterCut = 1.0 / 16.0;
+
 struct sgn_ctx {
   int device = -1;  // HIP device current at sgn_create
   Lattice lat{};
@@ -89,6 +93,12 @@ struct sgn_ctx {
   int m = 0;
   int defl_restarts = 0, defl_matvecs = 0;
   int defl_ncv = 0;  // Krylov subspace size of the deflation eigensolver (0: default rule)
+  // Chebyshev filter of the deflation eigensolver: degree (0: A^2 itself) and
+  // the damped interval's lower end as a fraction of A^2's spectral radius
+  int defl_degree = kDefaultFilterDegree;
+  double defl_cut = kDefaultFilterCut;
+  int defl_used_degree = 0;  // last sgn_deflate: degree of the run that converged (0: unfiltered)
+  double defl_alpha = 0.0, defl_beta = 0.0;
   double defl_residual = 0.0;
   double2* S = nullptr;       // internal layout, ldq x m
   std::vector<double2> T;     // host m x m (column-major, upper triangular)

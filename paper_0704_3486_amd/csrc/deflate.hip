@@ -41,6 +41,28 @@ void dev_scale(const double2* in, double2* out, int n, const double* inv, hipStr
   SGN_HIP(hipGetLastError());
 }
 
+// one step of the Chebyshev recurrence on L = (A^2 - c) / e:
+// out = a (hy - c y) - b yp, with hy = A^2 y (out may alias yp)
+__global__ void cheb_step_kernel(const double2* hy, const double2* y, const double2* yp, double2* out, double a,
+                                 double c, double b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 h = hy[i], v = y[i];
+  double2 r = make_double2(a * (h.x - c * v.x), a * (h.y - c * v.y));
+  if (b != 0.0) {
+    const double2 q = yp[i];
+    r.x -= b * q.x;
+    r.y -= b * q.y;
+  }
+  out[i] = r;
+}
+
+void dev_cheb_step(const double2* hy, const double2* y, const double2* yp, double2* out, double a, double c, double b,
+                   int n, hipStream_t s) {
+  hipLaunchKernelGGL(cheb_step_kernel, dim3((n + 255) / 256), dim3(256), 0, s, hy, y, yp, out, a, c, b, n);
+  SGN_HIP(hipGetLastError());
+}
+
 struct DevBuf {
   void* p = nullptr;
   explicit DevBuf(size_t bytes) { SGN_HIP(hipMalloc(&p, bytes)); }
@@ -92,12 +114,24 @@ struct DeflateStats {
   int matvecs = 0;
   double residual = 0.0;  // ||A S - S T||_F / ||A||
   double lower = 0.0;     // ||tril(T, -1)||_F before it is dropped
+  int degree = 0;         // Chebyshev degree of the operator of the run that converged (0: A^2)
+  double alpha = 0.0, beta = 0.0;  // its damped interval [alpha, beta] of A^2
+};
+
+// Operator of the eigensolver: A^2 (degree 0) or the Chebyshev polynomial
+// T_d((A^2 - c) / e) of degree d, which stays within [-1, 1] on the real
+// interval [alpha, beta] = [c - e, c + e] of A^2's spectrum and grows fast
+// below alpha, so that the smallest-magnitude eigenvalues of A^2 become the
+// largest-magnitude ones of the operator.
+struct OpSpec {
+  int degree = 0;
+  double c = 0.0, e = 1.0;
 };
 
 // The critical Schur pair of the context's operator: S (device, internal
 // layout, ldq x m) and T (host, m x m column-major, upper triangular).
 static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_restarts, double tol,
-                                unsigned long long seed, std::unique_ptr<DevBuf>& S_out,
+                                unsigned long long seed, const OpSpec& op, std::unique_ptr<DevBuf>& S_out,
                                 std::vector<double2>& T_out) {
   hipStream_t s = c->stream;
   const int N = c->N;
@@ -107,6 +141,11 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
 
   DevBuf bV(sizeof(double2) * ldq * (size_t)(ncv + 1)), bVt(sizeof(double2) * ldq * (size_t)(ncv + 1));
   DevBuf bt(sizeof(double2) * ldq), bw(sizeof(double2) * ldq);
+  std::unique_ptr<DevBuf> bya, byb;  // Chebyshev recurrence
+  if (op.degree > 0) {
+    bya = std::make_unique<DevBuf>(sizeof(double2) * ldq);
+    byb = std::make_unique<DevBuf>(sizeof(double2) * ldq);
+  }
   DevBuf bH(sizeof(double2) * (size_t)ldh * ldh), bcoef(sizeof(double2) * (size_t)ldh * ldh);
   DevBuf bh1(sizeof(double2) * ldh), bh2(sizeof(double2) * ldh);
   DevBuf bsc(sizeof(double) * 8), bflag(sizeof(int) * 4);
@@ -142,6 +181,38 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
     dev_scale(w, V, N, &sc[1], s);
   }
 
+  // w = operator(v): A^2 v, or T_d((A^2 - c) / e) v by the three-term
+  // recurrence y_{j+1} = 2 L y_j - y_{j-1}, y_1 = L v, y_0 = v
+  auto apply_op = [&](const double2* v) {
+    auto sq = [&](const double2* in, double2* out) {
+      wilson_apply(c->lat, c->links, in, t1, nullptr, nullptr, s, nullptr);
+      wilson_apply(c->lat, c->links, t1, out, nullptr, nullptr, s, nullptr);
+      st.matvecs += 2;
+    };
+    if (op.degree == 0) {
+      sq(v, w);
+      return;
+    }
+    double2* ya = bya->as<double2>();
+    double2* yb = byb->as<double2>();
+    const double ie = 1.0 / op.e;
+    sq(v, w);
+    if (op.degree == 1) {
+      dev_cheb_step(w, v, v, w, ie, op.c, 0.0, N, s);
+      return;
+    }
+    dev_cheb_step(w, v, v, ya, ie, op.c, 0.0, N, s);  // y_1
+    const double2* prev = v;
+    double2* cur = ya;
+    for (int d = 2; d <= op.degree; ++d) {
+      sq(cur, w);
+      double2* out = (d == op.degree) ? w : (prev == v ? yb : const_cast<double2*>(prev));
+      dev_cheb_step(w, cur, prev, out, 2.0 * ie, op.c, 1.0, N, s);
+      prev = cur;
+      cur = out;
+    }
+  };
+
   std::vector<double2> Hh((size_t)ldh * ldh);
   std::vector<cplx> Hn((size_t)ncv * ncv), theta(ncv), Y((size_t)ncv * ncv);
   int k = 0;
@@ -151,9 +222,7 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
     // Arnoldi extension k -> ncv on A^2 (Eq. Arnoldi with A^2 in place of A)
     for (int j = k; j < ncv; ++j) {
       double2* vj = V + (size_t)j * ldq;
-      wilson_apply(c->lat, c->links, vj, t1, nullptr, nullptr, s, nullptr);
-      wilson_apply(c->lat, c->links, t1, w, nullptr, nullptr, s, nullptr);
-      st.matvecs += 2;
+      apply_op(vj);
       const int ncol = j + 1;
       gs_dot(g, V, ldq, N, ncol, w, bh1.as<double2>(), s, nullptr);
       gs_update(g, V, ldq, N, ncol, bh1.as<double2>(), w, nullptr, 0, s, nullptr);
@@ -170,18 +239,25 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
     SGN_REQUIRE(std::isfinite(beta), SGN_EDEFL, "deflation: non-finite Arnoldi coefficient");
     SGN_REQUIRE(hostla::eig(ncv, Hn.data(), theta.data(), Y.data()), SGN_EDEFL,
                 "deflation: small eigenproblem did not converge");
-    // order by |theta| (wanted: smallest magnitude of lambda^2)
+    // order by |theta|: wanted the smallest magnitude of lambda^2 (A^2), or
+    // the largest of the filter polynomial
     std::vector<int> ord(ncv);
     std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(theta[a]) < std::abs(theta[b]); });
+    if (op.degree == 0)
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(theta[a]) < std::abs(theta[b]); });
+    else
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::abs(theta[a]) > std::abs(theta[b]); });
     bnorm = 0.0;
     for (auto& t : theta) bnorm = std::max(bnorm, std::abs(t));
     int nconv = 0;
     double worst = 0.0;
     for (int i = 0; i < nev; ++i) {
       const double r = std::abs(beta) * std::abs(Y[(size_t)ord[i] * ncv + (ncv - 1)]);
-      worst = std::max(worst, r / bnorm);
-      if (r <= tol * bnorm) ++nconv;
+      // A^2: relative to its spectral radius; the filter: relative to the
+      // Ritz value itself (the wanted ones are the large ones)
+      const double scale = op.degree == 0 ? bnorm : std::abs(theta[ord[i]]);
+      worst = std::max(worst, r / scale);
+      if (r <= tol * scale) ++nconv;
     }
     st.restarts = rst;
     const bool last = (rst == max_restarts);
@@ -319,8 +395,13 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
     SGN_HIP(hipStreamSynchronize(s));
     res2 += r * r;
   }
-  const double anorm = std::sqrt(bnorm);
+  // ||A||: from the spectral radius of A^2 (its Ritz values), or, with the
+  // filter, from the interval the filter was built on
+  const double anorm = std::sqrt(op.degree == 0 ? bnorm : op.c + op.e);
   st.residual = std::sqrt(res2) / anorm;
+  st.degree = op.degree;
+  st.alpha = op.degree ? op.c - op.e : 0.0;
+  st.beta = op.degree ? op.c + op.e : 0.0;
   SGN_REQUIRE(st.residual <= 1e-10, SGN_EDEFL,
               "deflation basis not accurate enough: ||AS - ST||_F / ||A|| = " + std::to_string(st.residual));
   S_out = std::move(bS);
@@ -328,19 +409,107 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
   return st;
 }
 
+// Spectral radius of A^2 from a short Arnoldi run (the largest-magnitude Ritz
+// values converge first): the upper end of the filter's damped interval,
+// with a 10 % margin (eigenvalues above it would be amplified too).
+static double sq_radius_estimate(sgn_ctx* c, int steps, unsigned long long seed) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const size_t ldq = c->ldq;
+  steps = std::max(2, std::min(steps, N - 1));
+  const int ldh = steps + 1;
+  DevBuf bV(sizeof(double2) * ldq * (size_t)(steps + 1)), bt(sizeof(double2) * ldq), bw(sizeof(double2) * ldq);
+  DevBuf bH(sizeof(double2) * (size_t)ldh * ldh), bh1(sizeof(double2) * ldh), bh2(sizeof(double2) * ldh),
+      bsc(sizeof(double) * 4);
+  double2* V = bV.as<double2>();
+  double2* t1 = bt.as<double2>();
+  double2* w = bw.as<double2>();
+  double2* Hd = bH.as<double2>();
+  double* sc = bsc.as<double>();
+  GsWork g;
+  gs_alloc(g, N, ldq, ldh);
+  struct GsGuard {
+    GsWork& g;
+    ~GsGuard() { gs_free(g); }
+  } guard{g};
+  SGN_HIP(hipMemsetAsync(Hd, 0, sizeof(double2) * (size_t)ldh * ldh, s));
+  {
+    std::vector<double2> v0((size_t)N);
+    std::mt19937_64 rng(seed ^ 0x9e3779b97f4a7c15ull);
+    std::normal_distribution<double> nd;
+    for (auto& z : v0) z = make_double2(nd(rng), nd(rng));
+    SGN_HIP(hipMemcpyAsync(w, v0.data(), sizeof(double2) * N, hipMemcpyHostToDevice, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    gs_norm(g, N, w, &sc[0], &sc[1], nullptr, s, nullptr);
+    dev_scale(w, V, N, &sc[1], s);
+  }
+  for (int j = 0; j < steps; ++j) {
+    double2* vj = V + (size_t)j * ldq;
+    wilson_apply(c->lat, c->links, vj, t1, nullptr, nullptr, s, nullptr);
+    wilson_apply(c->lat, c->links, t1, w, nullptr, nullptr, s, nullptr);
+    gs_dot(g, V, ldq, N, j + 1, w, bh1.as<double2>(), s, nullptr);
+    gs_update(g, V, ldq, N, j + 1, bh1.as<double2>(), w, nullptr, 0, s, nullptr);
+    gs_dot(g, V, ldq, N, j + 1, w, bh2.as<double2>(), s, nullptr);
+    GsFinal fin{bh1.as<double2>(), Hd + (size_t)j * ldh, nullptr, &sc[1], nullptr};
+    gs_update(g, V, ldq, N, j + 1, bh2.as<double2>(), w, &fin, j + 1, s, nullptr);
+    dev_scale(w, V + (size_t)(j + 1) * ldq, N, &sc[1], s);
+  }
+  std::vector<double2> Hh((size_t)ldh * ldh);
+  SGN_HIP(hipMemcpyAsync(Hh.data(), Hd, sizeof(double2) * Hh.size(), hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipStreamSynchronize(s));
+  std::vector<cplx> Hn((size_t)steps * steps), theta(steps), Y((size_t)steps * steps);
+  for (int j = 0; j < steps; ++j)
+    for (int i = 0; i < steps; ++i) Hn[(size_t)j * steps + i] = to_c(Hh[(size_t)j * ldh + i]);
+  SGN_REQUIRE(hostla::eig(steps, Hn.data(), theta.data(), Y.data()), SGN_EDEFL,
+              "deflation: spectral estimate did not converge");
+  double r = 0.0;
+  for (auto& t : theta) r = std::max(r, std::abs(t));
+  SGN_REQUIRE(std::isfinite(r) && r > 0.0, SGN_EDEFL, "deflation: non-finite spectral estimate");
+  return 1.1 * r;
+}
+
 // deflate_run with a growing Krylov subspace: unless the context fixes ncv,
 // a run that has not converged after 400 restarts is repeated with twice the
 // subspace (the restart count is very sensitive to ncv on clustered spectra),
 // up to N - 1; the last size gets 3000 restarts.
+//
+// With a filter degree set (sgn_set_deflation_filter), a filtered run comes
+// first: the operator is T_d((A^2 - c) / e) on the interval [alpha, beta] =
+// [cut rho, rho] of A^2's spectrum (rho its spectral radius, estimated), whose
+// largest-magnitude Ritz values are sought.  It keeps the Krylov subspace
+// small, so it replaces most of the restarts (each of which orthogonalises
+// against the whole basis and solves a small eigenproblem on the host) by
+// stencil applications.  If it has not converged within its restarts, or
+// its basis fails the Schur-residual test, the unfiltered solver runs.
 static DeflateStats deflate_escalating(sgn_ctx* c, int m, int nev, unsigned long long seed,
                                        std::unique_ptr<DevBuf>& S_out, std::vector<double2>& T_out) {
   int ncv = deflation_ncv(c, nev);
   SGN_REQUIRE(ncv > nev + 2, SGN_EINVAL, "lattice too small for this m");
   int spent_restarts = 0, spent_matvecs = 0;
+  if (c->defl_degree > 0) {
+    const double rho = sq_radius_estimate(c, 40, seed);
+    spent_matvecs += 2 * std::min(40, c->N - 1);
+    OpSpec op;
+    op.degree = c->defl_degree;
+    const double alpha = c->defl_cut * rho;
+    op.c = 0.5 * (rho + alpha);
+    op.e = 0.5 * (rho - alpha);
+    try {
+      DeflateStats st = deflate_run(c, m, nev, ncv, 300, 1e-13, seed, op, S_out, T_out);
+      st.ncv = ncv;
+      st.matvecs += spent_matvecs;
+      return st;
+    } catch (const NotConverged& e) {
+      spent_restarts += 300;
+      spent_matvecs += e.matvecs;
+    } catch (const SgnError& e) {
+      if (e.status != SGN_EDEFL) throw;
+    }
+  }
   for (;;) {
     const bool last = c->defl_ncv > 0 || ncv >= c->N - 1;
     try {
-      DeflateStats st = deflate_run(c, m, nev, ncv, last ? 3000 : 400, 1e-13, seed, S_out, T_out);
+      DeflateStats st = deflate_run(c, m, nev, ncv, last ? 3000 : 400, 1e-13, seed, OpSpec{}, S_out, T_out);
       st.ncv = ncv;
       st.restarts += spent_restarts;
       st.matvecs += spent_matvecs;
@@ -428,8 +597,29 @@ extern "C" int sgn_deflate(sgn_ctx* c, int m) {
     c->defl_restarts = st.restarts;
     c->defl_matvecs = st.matvecs;
     c->defl_residual = st.residual;
+    c->defl_used_degree = st.degree;
+    c->defl_alpha = st.alpha;
+    c->defl_beta = st.beta;
     return SGN_OK;
   });
+}
+
+extern "C" int sgn_set_deflation_filter(sgn_ctx* c, int degree, double cut) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(degree >= 0 && degree <= 200, SGN_EINVAL, "degree must satisfy 0 <= degree <= 200");
+    SGN_REQUIRE(cut == 0.0 || (cut > 0.0 && cut < 1.0), SGN_EINVAL, "cut must be 0 (default) or in (0, 1)");
+    c->defl_degree = degree;
+    c->defl_cut = cut > 0.0 ? cut : kDefaultFilterCut;
+    return SGN_OK;
+  });
+}
+
+extern "C" int sgn_deflate_filter_stats(const sgn_ctx* c, int* degree, double* alpha, double* beta) {
+  if (!c) return SGN_ESTATE;
+  if (degree) *degree = c->defl_used_degree;
+  if (alpha) *alpha = c->defl_alpha;
+  if (beta) *beta = c->defl_beta;
+  return SGN_OK;
 }
 
 extern "C" int sgn_deflate_stats(const sgn_ctx* c, int* restarts, int* matvecs, double* residual) {
@@ -533,6 +723,9 @@ extern "C" int sgn_deflate_lr(sgn_ctx* c, int m) {
     c->defl_restarts = st1.restarts + st2.restarts;
     c->defl_matvecs = st1.matvecs + st2.matvecs;
     c->defl_residual = std::max(st1.residual, st2.residual);
+    c->defl_used_degree = std::min(st1.degree, st2.degree);
+    c->defl_alpha = st1.alpha;
+    c->defl_beta = st1.beta;
     return SGN_OK;
   });
 }
