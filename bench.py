@@ -92,6 +92,11 @@ def main():
     ap.add_argument("--serving-sustained", type=int, default=400,
                     help="arrivals of the second stream, at 70%% of the served rate")
     ap.add_argument("--serving-mixed", action="store_true", help="serve in mixed precision")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the bounded serving leg of the default run")
+    ap.add_argument("--no-setup", action="store_true", help="skip the deflation-setup timings")
+    ap.add_argument("--setup-scan", action="store_true",
+                    help="only time the deflation setup, filtered and unfiltered, on more lattices and degrees")
     ap.add_argument("--m-scan", action="store_true",
                     help="only the deflation-size scan (setup time, k and time per apply against m) and exit")
     ap.add_argument("--batched-only", action="store_true",
@@ -134,6 +139,9 @@ def main():
         return
     if args.m_scan:
         print(json.dumps(m_scan_leg(sg, synth, torch)))
+        return
+    if args.setup_scan:
+        print(json.dumps(setup_leg(sg, synth, torch, SETUP_SCAN_FULL)))
         return
     if args.serving:
         print(json.dumps(serving_leg(sg, synth, torch, args.serving_rate, args.serving_requests, args.serving_sustained,
@@ -358,6 +366,11 @@ def main():
     if stencil is not None and stencil_6 is not None:
         stencil["in_apply_6x6x6x6"] = stencil_6
 
+    setup_times = None if args.no_setup else setup_leg(sg, synth, torch, SETUP_SCAN)
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(sg, synth, torch, *SERVE_DEFAULT, sg.SGN_PREC_FP64)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pairs, xs[0].cpu().numpy(), [acc[str(mu)]["k"] for mu in MUS], links)
@@ -396,6 +409,8 @@ def main():
         "overlap": ov,
         "overlap_solve": ovs,
         "lr_deflation": lrd,
+        "deflation_setup": setup_times,
+        "serving": serving,
         "kernels": kern,
         "profiled_pass_seconds": round(elapsed_prof, 4),
         "cpu_baseline": cpu,
@@ -481,6 +496,38 @@ def m_scan_leg(sg, synth, torch, reps=6):
             row["break_even_applies"] = round(1e3 * row["setup_s"] / gain, 1) if gain > 0 else None
         out.append({"lattice": list(dims), "N": 12 * int(np.prod(dims)), "mu": mu, "tol": TOL, "rows": rows})
     return {"workload": "deflation size scan, FP64, one source per apply, one at a time", "scan": out}
+
+
+# deflation setup (sgn_deflate): lattice, mu, m, filter degrees timed (0 = the
+# unfiltered thick-restart Arnoldi on H_w^2)
+SETUP_SCAN = (((8, 8, 8, 8), 0.5, 30, (16, 0)), ((12, 12, 12, 12), 0.5, 40, (16,)),
+              ((16, 16, 16, 16), 0.5, 60, (16,)))
+SETUP_SCAN_FULL = (((6, 6, 6, 6), 0.2, 20, (16, 0)), ((8, 8, 8, 8), 0.5, 30, (8, 16, 24, 0)),
+                   ((12, 12, 12, 12), 0.5, 40, (16, 24, 0)), ((16, 16, 16, 16), 0.5, 60, (16, 32)))
+
+
+def setup_leg(sg, synth, torch, scan):
+    """Deflation setup time (the Results section's initialisation cost) with
+    the Chebyshev-filtered eigensolver against the unfiltered one, on the
+    serving stream's mu = 0.5 fields."""
+    rows = []
+    for dims, mu, m, degrees in scan:
+        links = synth.random_links(dims, synth.GAUGE_SEED)
+        for deg in degrees:
+            ctx = sg.sgn_create(links, dims, mu, M_W)
+            try:
+                sg.sgn_set_deflation_filter(ctx, deg)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sg.sgn_deflate(ctx, m)
+                torch.cuda.synchronize()
+                row = {"lattice": list(dims), "mu": mu, "m": m, "degree": deg,
+                       "seconds": round(time.perf_counter() - t0, 3), **sg.sgn_deflate_stats(ctx)}
+            finally:
+                sg.sgn_destroy(ctx)
+            rows.append(row)
+            log(f"setup {dims} mu={mu} m={m} degree={deg}: {row}")
+    return {"workload": "sgn_deflate (critical Schur pair), FP64", "rows": rows}
 
 
 def undeflated_4x4_leg(sg, synth, torch, reps=20):
@@ -789,11 +836,12 @@ def batched_leg(sg, synth, torch, tune=True):
 
 # serving stream: lattice, deflation m, session kmax, arrival weight, share of
 # the HBM budget for its Krylov workspaces.  The 12^4 and 16^4 fields draw
-# mu = 0.5, where the deflation basis converges slowly (12^4, m = 40: about
-# 46 s); the 16^4 field (m = 60 would take minutes) is served without
-# deflation (kmax 600).
+# mu = 0.5; their deflation bases (m = 40, 60) come from the filtered setup.
 SERVE_FIELDS = [((6, 6, 6, 6), 20, 500, 0.4, 0.05), ((8, 8, 8, 8), 30, 500, 0.3, 0.10),
-                ((12, 12, 12, 12), 40, 500, 0.2, 0.35), ((16, 16, 16, 16), 0, 600, 0.1, 0.50)]
+                ((12, 12, 12, 12), 40, 600, 0.2, 0.35), ((16, 16, 16, 16), 60, 600, 0.1, 0.50)]
+# the bounded serving leg of the default run: arrivals at the offered rate,
+# then at 70 % of the rate served
+SERVE_DEFAULT = (200.0, 200, 120)
 SERVE_TOL = 1e-8
 SERVE_BUDGET = 150e9
 
