@@ -821,6 +821,17 @@ def batched_leg(sg, synth, torch, tune=True):
         torch.cuda.synchronize()
         mixed_rate = BATCH_NRHS / (time.perf_counter() - t0)
         err = [float(torch.linalg.vector_norm(Y[r] - y64[r]) / torch.linalg.vector_norm(y64[r])) for r in range(2)]
+        # the same batch with captured runs of 16 steps (bitwise the same results)
+        sg.sgn_set_step_graphs(ctx, 16)
+        Yg = torch.empty_like(X)
+        sg.sgn_apply_batched(ctx, X, Yg, BATCH_TOL, BATCH_KMAX)  # captures
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sg.sgn_apply_batched(ctx, X, Yg, BATCH_TOL, BATCH_KMAX)
+        torch.cuda.synchronize()
+        graph_rate = BATCH_NRHS / (time.perf_counter() - t0)
+        graph_same = bool(torch.equal(Yg, Y))
+        sg.sgn_set_step_graphs(ctx, 0)
     finally:
         sg.sgn_destroy(ctx)
     out = {"workload": f"12^4 (N={N}), mu=0.3, m={BATCH_M} (sgn_deflate), {BATCH_NRHS} Gaussian sources, "
@@ -829,6 +840,7 @@ def batched_leg(sg, synth, torch, tune=True):
            "mixed_k": [i["k_used"] for i in infos], "fp64_single_applies_per_s": round(fp64_rate, 3),
            "fp64_tol": TOL, "fp64_k": ks64, "speedup": round(mixed_rate / fp64_rate, 3),
            "mixed_rel_err_vs_fp64": err, "deflation_seconds": round(t_defl, 2),
+           "mixed_batched_graph16_applies_per_s": round(graph_rate, 3), "graph16_bitwise_same": graph_same,
            "launch_shapes": shapes or None}
     log(f"batched: {out}")
     return out

@@ -368,17 +368,20 @@ int sgn_set_orthogonalization(sgn_ctx* ctx, int mode);
 int sgn_set_tuning(sgn_ctx* ctx, int update_batch, int dot_cols, int update_waves);
 int sgn_get_tuning(const sgn_ctx* ctx, int* update_batch, int* dot_cols, int* update_waves);
 
-/* Captured Arnoldi steps of sgn_apply / sgn_apply_fixed (step (iv)): runs
- * of `steps` consecutive steps between two checkpoints are replayed as one
- * HIP graph, whose kernels read the step index from device memory; shorter
- * runs, profiled applies and the two-pass schedule launch each kernel
- * directly.  The graphs (one per 32 columns of basis size, captured on first
- * use on a stream the context owns) hold the workspace's addresses and are
- * dropped when it, the Schur pair, the precision, the launch shape or
- * `steps` changes.  The kernels and their arguments are the same in both
- * modes, so results are bitwise the same.  steps: 0 (off) or 2..64;
- * default 0 (off: on MI355X the step's kernels already run back to back,
- * and replay measured no faster).  SGN_EINVAL for other values. */
+/* Captured Arnoldi steps of sgn_apply / sgn_apply_fixed and of the batched
+ * applies (step (iv)): runs of `steps` consecutive steps between two
+ * checkpoints are replayed as one HIP graph, whose kernels read the step
+ * index from device memory; shorter runs, profiled applies, the adjoint
+ * applies and the two-pass schedule launch each kernel directly.  A batch
+ * replays runs of an even number of steps (steps rounded down) that start
+ * at an even step, one graph per set of running sources.  The graphs (one
+ * per 32 columns of basis size, captured on first use on a stream the
+ * context owns) hold the workspace's addresses and are dropped when it, the
+ * Schur pair, the precision, the launch shape or `steps` changes.  The
+ * kernels and their arguments are the same in both modes, so results are
+ * bitwise the same.  steps: 0 (off) or 2..64; default 0 (off: on MI355X the
+ * step's kernels already run back to back, and replay measured no faster).
+ * SGN_EINVAL for other values. */
 int sgn_set_step_graphs(sgn_ctx* ctx, int steps);
 
 /* Order in which the stencil's workgroups walk the lattice (Eq. Dw; results

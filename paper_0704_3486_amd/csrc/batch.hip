@@ -64,6 +64,7 @@ void batch_ensure(sgn_ctx* c, int nslots, int kcap) {
   for (double** p : {&b.beta, &b.err, &b.ref, &b.inv}) SGN_HIP(hipMalloc(p, sizeof(double) * S));
   for (int** p : {&b.flag, &b.fin}) SGN_HIP(hipMalloc(p, sizeof(int) * S));
   SGN_HIP(hipHostMalloc(&b.hpin, sizeof(double) * 4 * S, hipHostMallocDefault));
+  SGN_HIP(hipMalloc(&b.jdev, sizeof(int)));
   gs_alloc(b.gs, c->N, ldq, std::max((int)mm, c->lr_m));
   krylov_alloc(b.kw, c->N, ldq, b.ncap, nslots);
   dense_reserve(b.dense, (int)n, nslots);
@@ -295,26 +296,82 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
     SGN_HIP(hipMemsetAsync(b.beta, 0, sizeof(double) * ns, s));
     checkpoint(0);
   }
-  for (int j = 0; j < kwant && !active.empty(); ++j) {
-    KrylovArgs ka = base;
-    fill(ka, active, j);
+  // one Arnoldi step for the running slots at step j (step (iv)); with
+  // jdev set, the launch slots read the step index from the device
+  auto step = [&](KrylovArgs ka, int j, hipStream_t st, Profiler* pf) {
     SlotMap map;
     map.n = ka.nb;
-    for (int z = 0; z < map.n; ++z) map.slot[z] = active[z];
+    for (int z = 0; z < map.n; ++z) map.slot[z] = ka.act[z];
     ka.u = half_u(j);
     ka.unext = half_u(j + 1);
     if (mixed) {
-      wilson_apply_slots<float2>(c->lat, c->links32, half_lo(j), ldq, static_cast<float2*>(b.z), ldq, map, s, prof);
+      wilson_apply_slots<float2>(c->lat, c->links32, half_lo(j), ldq, static_cast<float2*>(b.z), ldq, map, st, pf);
       ka.ulonext = half_lo(j + 1);
-      krylov_dot<float2>(b.kw, ka, true, s, prof);
-      krylov_update<float2>(b.kw, ka, s, prof);
+      krylov_dot<float2>(b.kw, ka, true, st, pf);
+      krylov_update<float2>(b.kw, ka, st, pf);
     } else {
-      wilson_apply_slots<double2>(c->lat, c->links, half_u(j), ldq, static_cast<double2*>(b.z), ldq, map, s, prof);
+      wilson_apply_slots<double2>(c->lat, c->links, half_u(j), ldq, static_cast<double2*>(b.z), ldq, map, st, pf);
       ka.ulonext = nullptr;
-      krylov_dot<double2>(b.kw, ka, true, s, prof);
-      krylov_update<double2>(b.kw, ka, s, prof);
+      krylov_dot<double2>(b.kw, ka, true, st, pf);
+      krylov_update<double2>(b.kw, ka, st, pf);
     }
-    const int k = j + 1;
+  };
+  // captured run of L steps (L even) from any even step j of the same
+  // 32-column bucket, for the current set of running slots: the same kernels
+  // and arguments as direct launches (the candidate halves alternate with the
+  // step's parity, which an even start fixes), so results are bitwise the same
+  auto graph_for = [&](int j, int L) -> hipGraphExec_t {
+    const int bucket = (j + L - 1) / 32;
+    auto key = std::make_pair(active, bucket);
+    auto it = b.graphs.find(key);
+    if (it != b.graphs.end()) return it->second;
+    const int jcap = std::min(32 * (bucket + 1) - 1, b.kcap - 1);
+    SGN_REQUIRE(j + L - 1 <= jcap, SGN_EINVAL, "captured steps exceed the workspace");
+    if (!c->cap_stream) SGN_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->cap_stream;
+    KrylovArgs ka = base;
+    fill(ka, active, jcap);
+    ka.jdev = b.jdev;
+    hipGraph_t g = nullptr;
+    SGN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int t = 0; t < L; ++t) {
+        ka.joff = t;
+        step(ka, t, cs, nullptr);
+      }
+      krylov_set_index(b.jdev, L, true, cs);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SGN_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    SGN_HIP(e);
+    b.graphs[key] = ex;
+    return ex;
+  };
+  const int L = c->graph_steps & ~1;
+  for (int j = 0; j < kwant && !active.empty();) {
+    const int seg_end = std::min(next_ck, kwant);
+    if (L > 0 && !prof && (j & 1) == 0 && j + L <= seg_end) {
+      // whole captured runs up to the checkpoint
+      krylov_set_index(b.jdev, j, false, s);
+      while (j + L <= seg_end) {
+        SGN_HIP(hipGraphLaunch(graph_for(j, L), s));
+        j += L;
+        n_matvec += L * (int)active.size();
+      }
+      if (j == next_ck || j == kwant)
+        if (!checkpoint(j)) break;
+      continue;
+    }
+    KrylovArgs ka = base;
+    fill(ka, active, j);
+    step(ka, j, s, prof);
+    const int k = ++j;
     n_matvec += (int)active.size();
     if (k == next_ck || k == kwant)
       if (!checkpoint(k)) break;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -42,12 +43,24 @@ struct BatchWork {
   int k_hint = 0;
   double tol_hint = 0.0;
   double rate_hint = 0.0;
+  // captured runs of Arnoldi steps (sgn_set_step_graphs): the step index comes
+  // from jdev; one graph per set of running slots and 32-column bucket of the
+  // step index; they hold the workspace's addresses
+  int* jdev = nullptr;
+  std::map<std::pair<std::vector<int>, int>, hipGraphExec_t> graphs;
+
+  void drop_graphs() {
+    for (auto& g : graphs)
+      if (g.second) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
 
   size_t vt() const { return prec == SGN_PREC_MIXED ? sizeof(float2) : sizeof(double2); }
   void release() {
+    drop_graphs();
     for (void** p : {&V, (void**)&u, &ulo, &z, (void**)&xin, (void**)&y, (void**)&H, (void**)&F, (void**)&c0,
                      (void**)&lrc, (void**)&cv, (void**)&beta, (void**)&err, (void**)&ref, (void**)&inv,
-                     (void**)&flag, (void**)&fin})
+                     (void**)&flag, (void**)&fin, (void**)&jdev})
       if (*p) {
         (void)hipFree(*p);
         *p = nullptr;
@@ -196,6 +209,7 @@ struct sgn_ctx {
     for (hipGraphExec_t& g : graphs)
       if (g) (void)hipGraphExecDestroy(g);
     graphs.clear();
+    bw.drop_graphs();
   }
 
   void release() {

@@ -49,8 +49,8 @@ struct KrylovArgs {
   int nb = 1;
   int act[kMaxBatch] = {};
   int jv[kMaxBatch] = {};
-  // replayable launches (nb == 1): the step index is *jdev + joff, read on
-  // the device; jv[0] then only sizes the grids (an upper bound on the step)
+  // replayable launches: the step index of every launch slot is *jdev + joff,
+  // read on the device; jv[] then only sizes the grids (an upper bound)
   const int* jdev = nullptr;
   int joff = 0;
   // Krylov columns: column c >= m of slot r at V + r*vstride + (c-m)*ldq (element type VT)

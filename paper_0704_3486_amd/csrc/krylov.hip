@@ -645,7 +645,8 @@ void krylov_bind(const KrylovWork& w, KrylovArgs& A) {
 
 static void check_args(const KrylovWork& w, const KrylovArgs& A) {
   SGN_REQUIRE(A.nb >= 1 && A.nb <= w.nslots && A.nb <= kMaxBatch, SGN_EINVAL, "krylov: batch exceeds workspace");
-  SGN_REQUIRE(!A.jdev || (A.nb == 1 && A.joff >= 0), SGN_EINVAL, "krylov: device step index needs one slot");
+  // a device step index is shared by every launch slot (all at the same step)
+  SGN_REQUIRE(!A.jdev || A.joff >= 0, SGN_EINVAL, "krylov: negative step offset");
   for (int z = 0; z < A.nb; ++z) {
     SGN_REQUIRE(A.act[z] >= 0 && A.act[z] < w.nslots, SGN_EINVAL, "krylov: slot out of range");
     SGN_REQUIRE(A.jv[z] >= 0 && A.m + A.jv[z] <= w.ncol_cap, SGN_EINVAL, "krylov: J exceeds workspace");

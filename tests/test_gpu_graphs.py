@@ -104,3 +104,42 @@ def test_graph_setting_errors_and_reuse(env, small):
         assert not torch.equal(y1, y3)
     finally:
         sg.sgn_destroy(ctx)
+
+
+def _run_batched(sg, torch, small, prec, steps, tol):
+    dims, mu, links, A, S, T, X = small
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    out, ks = [], []
+    try:
+        sg.sgn_set_precision(ctx, prec)
+        sg.sgn_deflate_import(ctx, torch.from_numpy(S.astype(np.complex128)).cuda(), T)
+        sg.sgn_set_step_graphs(ctx, steps)
+        Xd = torch.from_numpy(X).cuda()
+        for rep in range(2):
+            Y = torch.empty_like(Xd)
+            st, infos = sg.sgn_apply_batched(ctx, Xd, Y, tol, 400)
+            assert st == sg.SGN_OK
+            ks.append([i["k_used"] for i in infos])
+            _ = (Y * 2.0).abs().sum().item()  # other GPU work and a synchronisation
+            out.append(Y)
+            # two of the three sources: another set of running slots
+            Y2 = torch.empty_like(Xd[:2])
+            sg.sgn_apply_batched_fixed(ctx, Xd[:2].contiguous(), Y2, 70 + 2 * rep)
+            out.append(Y2)
+        torch.cuda.synchronize()
+    finally:
+        sg.sgn_destroy(ctx)
+    return torch.cat([o.reshape(-1) for o in out]), ks
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_graph_replay_bitwise_equal_direct(env, small, prec):
+    sg, torch = env
+    tol = 1e-10 if prec == 0 else 1e-7
+    print("batched graphs vs direct, precision", prec, flush=True)
+    Yd, kd = _run_batched(sg, torch, small, prec, 0, tol)
+    for steps in (2, 8, 17):  # 17: runs of 16
+        print("  steps per graph", steps, flush=True)
+        Yg, kg = _run_batched(sg, torch, small, prec, steps, tol)
+        assert torch.equal(Yg, Yd), steps
+        assert kg == kd
