@@ -90,9 +90,11 @@ typedef struct sgn_info {
 /* ---- context ---------------------------------------------------------- */
 
 /* Create a context for one gauge field (Eq. Dw).  gauge: host complex128
- * U[V][4][3][3]; dims: {Lx,Ly,Lz,Lt}, each >= 2; requires 8 + 2 m_w > 0.
- * The context uses the null stream until sgn_set_stream is called.
- * Returns NULL on failure (see sgn_create_error). */
+ * U[V][4][3][3] of SU(3) matrices (unitary with determinant 1 to 1e-10: the
+ * stencil keeps two rows of each link and rebuilds the third, so other
+ * matrices are refused); dims: {Lx,Ly,Lz,Lt}, each >= 2; requires
+ * 8 + 2 m_w > 0.  The context uses the null stream until sgn_set_stream is
+ * called.  Returns NULL on failure (see sgn_create_error). */
 sgn_ctx* sgn_create(const double* gauge, const int dims[4], double mu, double m_w);
 
 /* Message of the last failed sgn_create on this thread ("" if none). */

@@ -621,18 +621,25 @@ sgn_ctx* sgn_create(const double* gauge, const int dims[4], double mu, double m_
     c->ldq = ((size_t)c->N + 63) / 64 * 64;
     SGN_HIP(hipGetDevice(&c->device));
     scratch_lookup(c->device);  // once per device (sgn_matvec_noalloc)
-    SGN_HIP(hipMalloc(&c->links, sizeof(double2) * 36 * (size_t)V));
-    double2* graw = nullptr;
-    SGN_HIP(hipMalloc(&graw, sizeof(double2) * 36 * (size_t)V));
-    SGN_HIP(hipMemcpy(graw, gauge, sizeof(double2) * 36 * (size_t)V, hipMemcpyHostToDevice));
-    wilson_pack_links(c->lat, graw, c->links, nullptr);
-    SGN_HIP(hipDeviceSynchronize());
-    SGN_HIP(hipFree(graw));
+    SGN_HIP(hipMalloc(&c->links, sizeof(double2) * wilson_link_entries((int)V)));
     SGN_HIP(hipMalloc(&c->scal, sizeof(double) * 8));
     SGN_HIP(hipMalloc(&c->flag, sizeof(int) * 4));
     SGN_HIP(hipHostMalloc(&c->hpin, sizeof(double) * 8, hipHostMallocDefault));
     SGN_HIP(hipMemset(c->scal, 0, sizeof(double) * 8));
     SGN_HIP(hipMemset(c->flag, 0, sizeof(int) * 4));
+    double2* graw = nullptr;
+    SGN_HIP(hipMalloc(&graw, sizeof(double2) * 36 * (size_t)V));
+    SGN_HIP(hipMemcpy(graw, gauge, sizeof(double2) * 36 * (size_t)V, hipMemcpyHostToDevice));
+    wilson_pack_links(c->lat, graw, c->links, c->flag, nullptr);
+    SGN_HIP(hipDeviceSynchronize());
+    SGN_HIP(hipFree(graw));
+    int bad = 0;
+    SGN_HIP(hipMemcpy(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+    SGN_HIP(hipMemset(c->flag, 0, sizeof(int) * 4));
+    if (bad) {
+      g_create_error = "gauge links must be SU(3) (unitary with determinant 1, to 1e-10)";
+      return nullptr;
+    }
   } catch (const SgnError& e) {
     g_create_error = e.msg;
     return nullptr;
@@ -1043,7 +1050,7 @@ int sgn_set_precision(sgn_ctx* c, int prec) {
     c->bw.k_hint = 0;
     c->bw.rate_hint = 0.0;
     if (prec == SGN_PREC_MIXED && !c->links32) {
-      SGN_HIP(hipMalloc(&c->links32, sizeof(float2) * 36 * (size_t)c->lat.V));
+      SGN_HIP(hipMalloc(&c->links32, sizeof(float2) * wilson_link_entries(c->lat.V)));
       wilson_links_f32(c->links, c->links32, c->lat.V, c->stream);
       SGN_HIP(hipStreamSynchronize(c->stream));
     }

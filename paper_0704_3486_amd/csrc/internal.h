@@ -156,7 +156,10 @@ struct Lattice {
   // natural site order; otherwise these extents (results do not depend on it)
   int blk[3] = {0, 0, 0};
 };
-void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, hipStream_t s);
+// links in the internal layout (rows 0, 1 of each SU(3) link; wilson_link_entries(V)
+// complex entries); *bad = 1 (device) for a link that is not SU(3) to 1e-10
+void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, int* bad, hipStream_t s);
+size_t wilson_link_entries(int V);
 void wilson_pack(const Lattice& lat, const double2* x_abi, double2* v, hipStream_t s);
 void wilson_unpack(const Lattice& lat, const double2* v, double2* y_abi, hipStream_t s);
 // walk blocks acceptable for this lattice (0,0,0: default; negative By: natural order)

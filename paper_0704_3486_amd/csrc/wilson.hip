@@ -2,12 +2,17 @@
 //
 // Internal layout (structure of arrays, one coalesced stream per component):
 //   spinor  v[c * V + n],        c = 3 spin + colour, n = site index
-//   links   U[(nu * 9 + 3 row + col) * V + n]
+//   links   U[(nu * 6 + 3 row + col) * V + n],  rows 0 and 1 only
 // so that the 64 lanes of a wavefront, which own 64 consecutive sites, read
 // every component with one fully coalesced 1 KiB load.  Neighbour spinors
 // (8 per site) are re-read through L2 / MALL; each link is used by two sites.
-// The antiperiodic time boundary is folded into U_{n,t} of the last time
-// slice, the hopping factor kappa and e^{+-mu} stay scalars.
+// A link is an SU(3) matrix, so its third row is the complex conjugate of
+// the cross product of the first two (unitarity and det U = 1; sgn_create
+// checks both): the stencil stores 12 of the 18 reals and rebuilds the third
+// row in registers, 24 instead of 36 link entries per site (the stencil's
+// bytes fall from 60 to 48 complex numbers per site).  The antiperiodic time
+// boundary is then a sign on the hops that cross it (folded into the link it
+// would change the determinant); kappa and e^{+-mu} stay scalars.
 //
 // Spin structure (chiral basis): (1 +- gamma_nu) has rank 2, so each hop
 // projects the 4-spinor onto a 2-spinor ("half spinor"), multiplies the two
@@ -80,12 +85,13 @@ __device__ inline C unit_mul(int sr, int si, C v, typename Real<C>::type sg) {
 // expanded back to four spins
 template <typename C>
 __device__ inline void hop_term(const C u[9], const C* __restrict__ v, int V, int m, int d,
-                                typename Real<C>::type emu, typename Real<C>::type emmu, C o[4][3]) {
+                                typename Real<C>::type emu, typename Real<C>::type emmu, typename Real<C>::type bc,
+                                C o[4][3]) {
   using R = typename Real<C>::type;
   const int nu = d >> 1;
   const bool fwd = (d & 1) == 0;
   const R sg = fwd ? (R)1 : (R)-1;
-  const R phase = (nu == 3) ? (fwd ? emu : emmu) : (R)1;
+  const R phase = (nu == 3) ? (fwd ? emu : emmu) * bc : (R)1;
   const SpinProj P = spin_proj(nu);
   C h0[3], h1[3];
 #pragma unroll
@@ -120,6 +126,25 @@ __device__ inline void hop_term(const C u[9], const C* __restrict__ v, int V, in
     o[2][c] = unit_mul(P.b0r, P.b0i, x0, sg);
     o[3][c] = unit_mul(P.b1r, P.b1i, x1, sg);
   }
+}
+
+constexpr int kLinkRows = 2;               // rows of an SU(3) link held in memory
+constexpr int kLinkEntries = 3 * kLinkRows;  // complex entries per link and site
+
+// the link of site ls in direction nu: rows 0 and 1 from memory, row 2 =
+// conj(row 0 x row 1)
+template <typename C>
+__device__ inline void load_link(const C* __restrict__ links, int V, int nu, int ls, C u[9]) {
+  const C* __restrict__ lp = links + (size_t)nu * kLinkEntries * V;
+#pragma unroll
+  for (int e = 0; e < kLinkEntries; ++e) u[e] = lp[(size_t)e * V + ls];
+  // cross product of the first two rows, conjugated
+  const C c0 = tsub(tmul(u[1], u[5]), tmul(u[2], u[4]));
+  const C c1 = tsub(tmul(u[2], u[3]), tmul(u[0], u[5]));
+  const C c2 = tsub(tmul(u[0], u[4]), tmul(u[1], u[3]));
+  u[6] = mk<C>(c0.x, -c0.y);
+  u[7] = mk<C>(c1.x, -c1.y);
+  u[8] = mk<C>(c2.x, -c2.y);
 }
 
 // neighbour of site n (coordinates x, y, z, t) along hop d, periodic wrap
@@ -166,13 +191,14 @@ wilson_hw_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t i
     const int m = hop_neighbour(n, d, x, y, z, t, Lx, Ly, Lz, Lt);
     const int ls = (d & 1) == 0 ? n : m;  // site that owns the link
     C u[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) u[e] = links[((d >> 1) * 9 + e) * V + ls];
+    load_link<C>(links, V, d >> 1, ls, u);
+    // antiperiodic in time: the hops across the time boundary
+    const R bc = ((d == 6 && t == Lt - 1) || (d == 7 && t == 0)) ? (R)-1 : (R)1;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       if (rb0 + b >= nrhs) break;
       C o[4][3];
-      hop_term<C>(u, in + (size_t)(rb0 + b) * istride, V, m, d, emu, emmu, o);
+      hop_term<C>(u, in + (size_t)(rb0 + b) * istride, V, m, d, emu, emmu, bc, o);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -283,10 +309,8 @@ wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size
   const int t = nc / (Lx * Ly * Lz);
   const int m = hop_neighbour(nc, 2 * nu + (fwd ? 0 : 1), x, y, z, t, Lx, Ly, Lz, Lt);
   const int ls = fwd ? nc : m;  // site that owns the link
-  const C* __restrict__ lp = links + (size_t)nu * 9 * V;
   C u[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = lp[(size_t)e * V + ls];
+  load_link<C>(links, V, nu, ls, u);
   // the matrix applied to the half spinor: U (forward) or U^dag (backward)
   C w9[9];
 #pragma unroll
@@ -298,7 +322,10 @@ wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size
     }
   const SpinProj P = spin_proj(nu);
   const R sg = fwd ? (R)1 : (R)-1;
-  const R phase = (nu == 3) ? (fwd ? (R)emu_d : (R)emmu_d) : (R)1;
+  // e^{+-mu} on time hops, and the antiperiodic sign on the two hops across
+  // the time boundary (forward from the last slice, backward from the first)
+  const bool across = nu == 3 && (fwd ? t == Lt - 1 : t == 0);
+  const R phase = (nu == 3) ? (fwd ? (R)emu_d : (R)emmu_d) * (across ? (R)-1 : (R)1) : (R)1;
   C h0[3], h1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -361,15 +388,32 @@ __global__ void links_to_f32_kernel(const double2* __restrict__ a, float2* __res
   if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
-__global__ void pack_links_kernel(const double2* __restrict__ g, double2* __restrict__ U, int V, int Lt,
-                                  int st) {
+// rows 0 and 1 of every link into the internal layout; bad = 1 if some link
+// is not SU(3) to 1e-10 (|U U^dag - I|, |det U - 1|), since row 2 is rebuilt
+__global__ void pack_links_kernel(const double2* __restrict__ g, double2* __restrict__ U, int V, int* bad) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= V) return;
-  const int t = n / st;
+  bool ok = true;
   for (int nu = 0; nu < 4; ++nu) {
-    const double bc = (nu == 3 && t == Lt - 1) ? -1.0 : 1.0;
-    for (int e = 0; e < 9; ++e) U[(nu * 9 + e) * V + n] = cscale(g[(n * 4 + nu) * 9 + e], bc);
+    double2 a[9];
+    for (int e = 0; e < 9; ++e) a[e] = g[((size_t)n * 4 + nu) * 9 + e];
+    for (int e = 0; e < kLinkEntries; ++e) U[((size_t)nu * kLinkEntries + e) * V + n] = a[e];
+    double dev = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = 0; k < 3; ++k) acc = cfma(a[3 * i + k], make_double2(a[3 * j + k].x, -a[3 * j + k].y), acc);
+        dev = fmax(dev, fabs(acc.x - (i == j ? 1.0 : 0.0)) + fabs(acc.y));
+      }
+    // det = row 2 . (row 0 x row 1)
+    const double2 c0 = csub(cmul(a[1], a[5]), cmul(a[2], a[4]));
+    const double2 c1 = csub(cmul(a[2], a[3]), cmul(a[0], a[5]));
+    const double2 c2 = csub(cmul(a[0], a[4]), cmul(a[1], a[3]));
+    const double2 det = cadd(cadd(cmul(a[6], c0), cmul(a[7], c1)), cmul(a[8], c2));
+    dev = fmax(dev, fabs(det.x - 1.0) + fabs(det.y));
+    if (!(dev <= 1e-10)) ok = false;
   }
+  if (!ok) *bad = 1;
 }
 
 __global__ void pack_kernel(const double2* __restrict__ x, double2* __restrict__ v, int V) {
@@ -388,12 +432,13 @@ __global__ void unpack_kernel(const double2* __restrict__ v, double2* __restrict
 
 }  // namespace
 
-void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, hipStream_t s) {
+void wilson_pack_links(const Lattice& lat, const double2* gauge_abi, double2* links, int* bad, hipStream_t s) {
   const int V = lat.V;
-  hipLaunchKernelGGL(pack_links_kernel, dim3((V + 255) / 256), dim3(256), 0, s, gauge_abi, links, V, lat.L[3],
-                     lat.L[0] * lat.L[1] * lat.L[2]);
+  hipLaunchKernelGGL(pack_links_kernel, dim3((V + 255) / 256), dim3(256), 0, s, gauge_abi, links, V, bad);
   SGN_HIP(hipGetLastError());
 }
+
+size_t wilson_link_entries(int V) { return (size_t)4 * kLinkEntries * V; }
 
 void wilson_pack(const Lattice& lat, const double2* x_abi, double2* v, hipStream_t s) {
   const int n = 12 * lat.V;
@@ -507,8 +552,9 @@ bool wilson_blocks_valid(const Lattice& lat, int By, int Bz, int Bt) {
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof) {
   const int V = lat.V;
-  // algorithmic bytes: read v (12), write w (12), 4 links of 9 (36) per site; + copy (12)
-  const double per_site = (60.0 + (copy_out ? 12.0 : 0.0)) * 16.0;
+  // algorithmic bytes: read v (12), write w (12), 4 links of 6 stored entries
+  // (24) per site; + copy (12)
+  const double per_site = (48.0 + (copy_out ? 12.0 : 0.0)) * 16.0;
   prof_launch(prof, K_WILSON, per_site * V, 1392.0 * V, wilson_hw_dir_kernel<double2>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, 1), dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0,
               inv_beta, copy_out, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{},
@@ -542,7 +588,7 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
   if (prof) {
     const double b = (double)sizeof(C);
     // per site: 24 spinor entries per RHS (read + write) and 36 link entries once per launch
-    prof->end(idx, (24.0 * nrhs + 36.0) * b * V, 1392.0 * V * nrhs);
+    prof->end(idx, (24.0 * nrhs + 24.0) * b * V, 1392.0 * V * nrhs);
   }
 }
 
@@ -551,9 +597,9 @@ void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t 
                         const SlotMap& map, hipStream_t s, Profiler* prof) {
   SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
   const int V = lat.V;
-  // per site and slot: read v (12), write w (12), the links (36)
+  // per site and slot: read v (12), write w (12), the links (24 stored entries)
   const double b = (double)sizeof(C);
-  prof_launch(prof, K_WILSON, 60.0 * b * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
+  prof_launch(prof, K_WILSON, 48.0 * b * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
               (const double*)nullptr, (C*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
               lat.emmu, map, site_order(lat));
@@ -574,7 +620,7 @@ void wilson_apply_multi32(const Lattice& lat, const float2* links, const float2*
 }
 
 void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t s) {
-  const size_t n = (size_t)36 * V;
+  const size_t n = wilson_link_entries(V);
   hipLaunchKernelGGL(links_to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, links, links32, n);
   SGN_HIP(hipGetLastError());
 }

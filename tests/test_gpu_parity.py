@@ -339,3 +339,18 @@ def test_6x6_sources_at_tol_1e10_vs_exact(env, mu):
         assert max(errs) < 1e-10, errs
     finally:
         sg.sgn_destroy(ctx)
+
+
+def test_create_refuses_non_su3_links(env):
+    # the stencil rebuilds the third row of each link from the first two
+    sg, torch = env
+    dims = (2, 2, 2, 4)
+    links = synth.random_links(dims, 9).copy()
+    links[1, 0, 1, 0, 2] *= 1.01  # one link no longer unitary
+    with pytest.raises(sg.SgnError) as e:
+        sg.sgn_create(links, dims, 0.3, M_W)
+    assert "SU(3)" in str(e.value)
+    links = synth.random_links(dims, 9).copy()
+    links[0, 1, 0, 1, 3] *= np.exp(2j * np.pi / 3 + 0.1j)  # unitary, det != 1
+    with pytest.raises(sg.SgnError):
+        sg.sgn_create(links, dims, 0.3, M_W)
