@@ -416,11 +416,14 @@ __global__ void pack_links_kernel(const double2* __restrict__ g, double2* __rest
   if (!ok) *bad = 1;
 }
 
+// threads run over the interface layout, so the reads are contiguous; the
+// writes go to 12 streams (one per component), each contiguous across the
+// lanes that share a component (as in unpack_kernel, the other way round)
 __global__ void pack_kernel(const double2* __restrict__ x, double2* __restrict__ v, int V) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // internal index c * V + n
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // ABI index 12 n + c
   if (i >= 12 * V) return;
-  const int c = i / V, n = i - c * V;
-  v[i] = x[12 * n + c];
+  const int n = i / 12, c = i - 12 * n;
+  v[(size_t)c * V + n] = x[i];
 }
 
 __global__ void unpack_kernel(const double2* __restrict__ v, double2* __restrict__ y, int V) {
