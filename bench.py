@@ -1008,10 +1008,25 @@ def cpu_baseline(pairs, x, ks, links):
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     cores = len(os.sched_getaffinity(0))
     log(f"cpu baseline: {len(MUS)} applies in {t_total:.2f} s")
+    # the same oracle on one core (BLAS limited to one thread): the mu = 0.2 field
+    from threadpoolctl import threadpool_limits
+
+    f1 = 1
+    A = wilson.hw_matrix(links, DIMS, MUS[f1], M_W)
+    S, T = pairs[f1]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        st = arnoldi.modified_arnoldi(lambda v: A @ v, x, S, int(ks[f1]))
+        arnoldi.approx_paper(S, T, st)
+        t_one = time.perf_counter() - t0
+    log(f"cpu baseline, one core: 1 apply in {t_one:.2f} s")
     return {"value": round(len(MUS) / t_total, 4), "unit": "applies/s", "cores": int(min(threads, cores)),
             "kind": "oracle",
             "sample": f"one apply per field (mu 0.0, 0.2, 0.5) on the seed-1000 source at the GPU's k {list(ks)}, "
-                      f"6^4, m=20, MGS x2 Arnoldi + Roberts + Appendix A Sylvester, {t_total:.1f} s total"}
+                      f"6^4, m=20, MGS x2 Arnoldi + Roberts + Appendix A Sylvester, {t_total:.1f} s total",
+            "one_core": {"value": round(1.0 / t_one, 4), "unit": "applies/s", "cores": 1,
+                         "sample": f"one apply on the mu = {MUS[f1]} field at k {int(ks[f1])}, BLAS on one "
+                                   f"thread, {t_one:.1f} s"}}
 
 
 if __name__ == "__main__":
