@@ -826,6 +826,15 @@ def batched_leg(sg, synth, torch, tune=True):
         torch.cuda.synchronize()
         mixed_rate = BATCH_NRHS / (time.perf_counter() - t0)
         err = [float(torch.linalg.vector_norm(Y[r] - y64[r]) / torch.linalg.vector_norm(y64[r])) for r in range(2)]
+        # sources 1000, 1001 against the oracle's FP64 deflated Arnoldi at k = 800
+        gpath = os.path.join(GOLDEN, "c12_mu0.3_sources.npy")
+        err_oracle = None
+        if os.path.exists(gpath):
+            gold = torch.from_numpy(np.load(gpath, allow_pickle=False)).cuda()
+            err_oracle = {"mixed_batched": [float(torch.linalg.vector_norm(Y[r] - gold[r]) /
+                                                  torch.linalg.vector_norm(gold[r])) for r in range(gold.shape[0])],
+                          "fp64_single": [float(torch.linalg.vector_norm(y64[r] - gold[r]) /
+                                                torch.linalg.vector_norm(gold[r])) for r in range(gold.shape[0])]}
         # the same batch with captured runs of 16 steps (bitwise the same results)
         sg.sgn_set_step_graphs(ctx, 16)
         Yg = torch.empty_like(X)
@@ -844,7 +853,7 @@ def batched_leg(sg, synth, torch, tune=True):
            "mixed_batched_applies_per_s": round(mixed_rate, 3), "mixed_tol": BATCH_TOL, "status": st,
            "mixed_k": [i["k_used"] for i in infos], "fp64_single_applies_per_s": round(fp64_rate, 3),
            "fp64_tol": TOL, "fp64_k": ks64, "speedup": round(mixed_rate / fp64_rate, 3),
-           "mixed_rel_err_vs_fp64": err, "deflation_seconds": round(t_defl, 2),
+           "mixed_rel_err_vs_fp64": err, "rel_err_vs_oracle_k800": err_oracle, "deflation_seconds": round(t_defl, 2),
            "mixed_batched_graph16_applies_per_s": round(graph_rate, 3), "graph16_bitwise_same": graph_same,
            "launch_shapes": shapes or None}
     log(f"batched: {out}")
