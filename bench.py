@@ -50,6 +50,10 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # profiling class -> kernel symbol (as rocprofv3 lists it)
 HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_kernel<double2>",
                "krylov_reduce": "kred_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
+# the same for the block (s-step) process
+HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
+                     "block_factor": "bsmall_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
+BLOCK_STEPS = 8  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
 STENCIL_DIMS = (32, 32, 32, 32)
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs, stored with the hash of the source it was measured on (stale -> null)
@@ -104,6 +108,9 @@ def main():
     ap.add_argument("--per-field", type=int, default=2,
                     help="applies in flight per field in the timed steps: one context and stream each, all "
                          "holding the field's Schur pair")
+    ap.add_argument("--block-steps", type=int, default=BLOCK_STEPS,
+                    help="Arnoldi steps per block of the headline applies (sgn_set_block_steps; 0: the one-vector "
+                         "process with its delayed re-orthogonalisation)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay runs of this many Arnoldi steps as captured HIP graphs in the timed applies "
                          "(sgn_set_step_graphs; bitwise the same results; 0: direct launches)")
@@ -164,7 +171,9 @@ def main():
         sg.sgn_deflate(ctx, M_DEFL)
         torch.cuda.synchronize()
         setup[str(mu)] = {"seconds": round(time.perf_counter() - t0, 3), **sg.sgn_deflate_stats(ctx)}
-        if not args.no_autotune:
+        if args.block_steps:
+            sg.sgn_set_block_steps(ctx, args.block_steps)
+        elif not args.no_autotune:
             # launch shape of the Arnoldi passes (results are bitwise the same for every shape)
             tuned = autotune(ctx, k=AUTOTUNE_K)
             setup[str(mu)]["launch_shape"] = [tuned["update_batch"], tuned["dot_cols"]]
@@ -218,6 +227,7 @@ def main():
             S, T, _ = sg.sgn_deflate_export(ctxs[f])
             sg.sgn_deflate_import(c, S, T)
             sg.sgn_set_tuning(c, *sg.sgn_get_tuning(ctxs[f]))
+            sg.sgn_set_block_steps(c, args.block_steps)
             y = torch.empty(N, dtype=torch.complex128, device=dev)
             sg.sgn_apply(c, xs[0], y, TOL, KMAX)
             lanes.append((c, y))
@@ -313,26 +323,27 @@ def main():
         sg.sgn_set_profiling(c, False)
     kern = kernel_table(kstats)
     log("kernels: " + json.dumps(kern))
-    hbm_kernels = {k: v for k, v in kern.items() if k in HBM_KERNELS}
+    kmap = HBM_KERNELS_BLOCK if args.block_steps else HBM_KERNELS
+    hbm_kernels = {k: v for k, v in kern.items() if k in kmap}
     dom = max(hbm_kernels, key=lambda k: hbm_kernels[k]["total_ms"]) if hbm_kernels else None
     roofline = None
     if dom:
         s = kstats[dom]
         achieved = s["bytes"] / (s["ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(HBM_KERNELS[dom]),
-                    "kernel": HBM_KERNELS[dom], "avg_launch_us": kern[dom]["avg_us"],
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(kmap[dom]),
+                    "kernel": kmap[dom], "avg_launch_us": kern[dom]["avg_us"],
                     "bytes_per_launch": round(s["bytes"] / s["launches"], 1)}
     # the timed region's aggregate rate: the Krylov passes' and the stencil's
     # algorithmic bytes per apply (from the profiled pass) times applies per second
     aggregate = None
     nprof = len(ks_prof)
-    if nprof and all(k in kstats for k in HBM_KERNELS):
-        per_apply = sum(kstats[k]["bytes"] for k in HBM_KERNELS) / nprof
+    if nprof and all(k in kstats for k in kmap):
+        per_apply = sum(kstats[k]["bytes"] for k in kmap) / nprof
         gbs = per_apply * value / 1e9
         aggregate = {"GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBPS, 4),
                      "bytes_per_apply": round(per_apply), "mean_k_profiled": round(float(np.mean(ks_prof)), 1),
-                     "kernels": sorted(HBM_KERNELS)}
+                     "kernels": sorted(kmap)}
     sign = None
     if "ns_gemm" in kstats and kstats["ns_gemm"]["ms"] > 0:
         s = kstats["ns_gemm"]
@@ -394,6 +405,7 @@ def main():
                                   f"{len(lanes)} applies per step ({P} per field in flight, one context and "
                                   "stream each)"),
                    "applies_in_flight_per_field": P, "graph_steps": args.graph_steps,
+                   "block_steps": args.block_steps,
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
                    "mean_k": round(float(np.mean(ks)), 1), "timed_unconverged": timed_unconverged},
         "accuracy": {"timed_applies": timed_acc, "seed_1000": acc},

@@ -115,6 +115,8 @@ def _load():
         "sgn_deflate_lr_export": (i, [vp, vp, vp, vp]),
         "sgn_deflation_mode": (i, [vp]),
         "sgn_set_orthogonalization": (i, [vp, i]),
+        "sgn_set_block_steps": (i, [vp, i]),
+        "sgn_get_block_steps": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
         "sgn_set_tuning": (i, [vp, i, i, i]),
         "sgn_set_step_graphs": (i, [vp, i]),
         "sgn_set_stencil_blocks": (i, [vp, i, i, i]),
@@ -497,6 +499,18 @@ def sgn_set_orthogonalization(ctx, mode):
     return _check(ctx, _lib.sgn_set_orthogonalization(ctx, int(mode)))
 
 
+def sgn_set_block_steps(ctx, s):
+    """Block (s-step) Arnoldi process for FP64 applies: s steps per block (0: off)."""
+    return _check(ctx, _lib.sgn_set_block_steps(ctx, int(s)))
+
+
+def sgn_get_block_steps(ctx):
+    """(block size, Chebyshev interval half-width in use)."""
+    sb, e = C.c_int(), C.c_double()
+    _check(ctx, _lib.sgn_get_block_steps(ctx, C.byref(sb), C.byref(e)))
+    return sb.value, e.value
+
+
 def sgn_set_tuning(ctx, update_batch=8, dot_cols=4, update_waves=8):
     """Launch shape of the Arnoldi step's dot and update passes (results are
     bitwise the same for every update_batch and dot_cols; update_waves
@@ -564,8 +578,8 @@ def sgn_set_profiling(ctx, on):
 
 
 def sgn_profile_read(ctx):
-    arr = (sgn_kstat * 16)()
-    n = _lib.sgn_profile_read(ctx, arr, 16)
+    arr = (sgn_kstat * 32)()
+    n = _lib.sgn_profile_read(ctx, arr, 32)
     _check(ctx, n if n < 0 else SGN_OK)
     return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "bytes": arr[i].bytes,
                                    "flops": arr[i].flops} for i in range(n)}

@@ -109,6 +109,10 @@ static const char* kclass_name(int c) {
     case K_NEWTON_COMBINE: return "newton_combine";
     case K_CGS_DOT: return "cgs_dot";
     case K_CGS_UPDATE: return "cgs_update";
+    case K_BDOT: return "block_dot";
+    case K_BRED: return "block_reduce";
+    case K_BUPDATE: return "block_update";
+    case K_BSMALL: return "block_factor";
     default: return "misc";
   }
 }
@@ -233,8 +237,24 @@ static hipGraphExec_t step_graph(sgn_ctx* c, const KrylovArgs& ka0, bool mixed, 
   return ex;
 }
 
+// A block of the block Arnoldi process was not of full rank: the apply is
+// repeated with one-vector steps.
+struct BlockFallback {};
+
+static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int kmax, int fixed_k,
+                          bool allow_block);
+
 // Steps (iii)-(vi).  fixed_k >= 0: exactly that many steps, no convergence test.
 int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int kmax, int fixed_k) {
+  try {
+    return run_apply_impl(c, x_abi, y_abi, tol, kmax, fixed_k, true);
+  } catch (const BlockFallback&) {
+    return run_apply_impl(c, x_abi, y_abi, tol, kmax, fixed_k, false);
+  }
+}
+
+static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int kmax, int fixed_k,
+                          bool allow_block) {
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = c->stream;
   Profiler* prof = c->prof.on ? &c->prof : nullptr;
@@ -246,7 +266,17 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
   c->ensure_workspace(std::max(kwant, 2));
   const int ncap = c->ncap;
   const bool mixed = (c->prec == SGN_PREC_MIXED);
-  const bool delayed = mixed || (c->orth == SGN_ORTH_DELAYED);
+  // block Arnoldi process (FP64 only); else one vector per step
+  const bool block = allow_block && !mixed && c->block_s > 0;
+  const int sblk = block ? c->block_s : 1;
+  const bool delayed = !block && (mixed || c->orth == SGN_ORTH_DELAYED);
+  if (block) {
+    if (c->blk.ncap < c->ncap) block_alloc(c->blk, N, ldq, c->ncap);
+    if (!(c->cheb_e > 0.0)) c->cheb_e = std::sqrt(sq_radius_estimate(c, 40, 0x5eedull));
+    SGN_HIP(hipMemsetAsync(c->blk.flag, 0, sizeof(int), s));
+  }
+  // checkpoints of the block process fall on whole blocks
+  auto align = [&](int kk) { return block ? std::min(kmax, (kk + sblk - 1) / sblk * sblk) : kk; };
   sgn_info info{};
   double ms_sign = 0.0;
 
@@ -369,9 +399,9 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
     if (fixed_k >= 0) {
       next_ck = fixed_k;
     } else if (hinted) {
-      next_ck = std::min(kmax, std::max(2, even_up(c->k_hint)));
+      next_ck = align(std::min(kmax, std::max(2, even_up(c->k_hint))));
     } else {
-      next_ck = std::min(kmax, std::max(2, even_up(std::min(32, kmax / 2))));
+      next_ck = align(std::min(kmax, std::max(2, even_up(std::min(32, kmax / 2)))));
     }
     double2* wprev = c->wA;  // two-pass schedule: x_perp (unnormalised) for j = 0
     double2* wcur = c->wB;
@@ -396,6 +426,11 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
         arnoldi_step(c, ka, mixed, s, prof);
         ++j;
         info.n_matvec += 1;
+      } else if (block) {
+        const int sb = std::min(sblk, seg_end - j);
+        block_step(c, j, sb, c->cheb_e, s, prof);
+        j += sb;
+        info.n_matvec += sb;
       } else {
         double2* vcol = c->Q + (size_t)J * ldq;
         wilson_apply(c->lat, c->links, wprev, wcur, &c->scal[1], vcol, s, prof);
@@ -416,6 +451,13 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
         SGN_HIP(hipStreamSynchronize(s));
         int f0;
         std::memcpy(&f0, &c->hpin[4], sizeof(int));
+        if (block) {
+          SGN_HIP(hipMemcpyAsync(&c->hpin[4], c->blk.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+          SGN_HIP(hipStreamSynchronize(s));
+          int bf;
+          std::memcpy(&bf, &c->hpin[4], sizeof(int));
+          if (bf != 0) throw BlockFallback{};
+        }
         if (f0 < 0) throw SgnError{SGN_EINVAL, "non-finite value in the Krylov basis"};
         if (f0 > 0) {
           k = f0 - 1;
@@ -444,7 +486,7 @@ int run_apply(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int 
           break;
         }
         prev_ck = k;
-        next_ck = model.next(k, kmax, tol, rate, hinted && model.hist.empty());
+        next_ck = align(model.next(k, kmax, tol, rate, hinted && model.hist.empty()));
       }
     }
   }
@@ -1085,6 +1127,23 @@ int sgn_set_orthogonalization(sgn_ctx* c, int mode) {
   return guarded(c, [&] {
     SGN_REQUIRE(mode == SGN_ORTH_CGS2 || mode == SGN_ORTH_DELAYED, SGN_EINVAL, "unknown orthogonalisation mode");
     c->orth = mode;
+    return SGN_OK;
+  });
+}
+
+int sgn_set_block_steps(sgn_ctx* c, int sb) {
+  return guarded(c, [&] {
+    SGN_REQUIRE(sb >= 0 && sb <= kBlockMax, SGN_EINVAL, "block steps must be 0 (off) or 1..8");
+    c->block_s = sb;
+    return SGN_OK;
+  });
+}
+
+int sgn_get_block_steps(const sgn_ctx* cc, int* sb, double* e_out) {
+  sgn_ctx* c = const_cast<sgn_ctx*>(cc);
+  return guarded(c, [&] {
+    if (sb) *sb = c->block_s;
+    if (e_out) *e_out = c->cheb_e;
     return SGN_OK;
   });
 }

@@ -171,6 +171,11 @@ struct sgn_ctx {
   int* jdev = nullptr;  // device step index read by the captured steps
   std::vector<hipGraphExec_t> graphs;
   int orth = 1;  // 0: two classical Gram-Schmidt passes per step; 1: one reduction, delayed re-orthogonalisation
+  // block (s-step) Arnoldi process for FP64 applies: block size (0: off) and
+  // the half-width of its Chebyshev interval (estimated on first use)
+  int block_s = 0;
+  double cheb_e = 0.0;
+  BlockWork blk;
   int sessions = 0;  // open serving sessions (they hold the Schur pair and the precision fixed)
 
   ~sgn_ctx() { release(); }
@@ -188,6 +193,7 @@ struct sgn_ctx {
       }
     gs_free(gs);
     krylov_free(kw);
+    block_free(blk);
     drop_graphs();
     if (jdev) (void)hipFree(jdev);
     jdev = nullptr;
@@ -305,6 +311,15 @@ inline void check_adjoint(const sgn_ctx* c) {
   SGN_REQUIRE(c->sessions == 0, SGN_ESTATE, "a serving session runs on this field");
 }
 
+
+// One block of sb <= kBlockMax Arnoldi steps from k finished steps (block.hip):
+// Q columns m + k + 1 .. m + k + sb and H columns m + k .. m + k + sb - 1; at
+// k = 0 it also writes v_1 = wA * scal[1].  e: half-width of the Chebyshev
+// interval.  A block that is not of full rank raises blk.flag.
+void block_step(sgn_ctx* c, int k, int sb, double e, hipStream_t s, Profiler* prof);
+// 1.1 x the spectral radius of A^2 from an Arnoldi run of `steps` steps on A^2
+// (deflate.hip)
+double sq_radius_estimate(sgn_ctx* c, int steps, unsigned long long seed);
 
 inline int fail(sgn_ctx* c, const SgnError& e) {
   if (c) c->last_error = e.msg;

@@ -412,7 +412,7 @@ static DeflateStats deflate_run(sgn_ctx* c, int m, int nev, int ncv, int max_res
 // Spectral radius of A^2 from a short Arnoldi run (the largest-magnitude Ritz
 // values converge first): the upper end of the filter's damped interval,
 // with a 10 % margin (eigenvalues above it would be amplified too).
-static double sq_radius_estimate(sgn_ctx* c, int steps, unsigned long long seed) {
+double sq_radius_estimate(sgn_ctx* c, int steps, unsigned long long seed) {
   hipStream_t s = c->stream;
   const int N = c->N;
   const size_t ldq = c->ldq;

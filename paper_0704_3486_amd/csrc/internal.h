@@ -73,6 +73,10 @@ enum KClass {
   K_NEWTON_COMBINE,  // newton_combine_kernel
   K_CGS_DOT,         // gs_dot_kernel (deflation setup)
   K_CGS_UPDATE,      // gs_update_kernel (deflation setup)
+  K_BDOT,            // bdot_kernel (block steps: Q^dag W)
+  K_BRED,            // bred_kernel (block steps: sum of the dot partials)
+  K_BUPDATE,         // bupdate_kernel (block steps: W - Q C)
+  K_BSMALL,          // bsmall_kernel (block steps: Cholesky factor and H times the coefficients)
   K_MISC,
   K_NCLASS
 };
@@ -146,6 +150,25 @@ void gs_update(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, c
 void gs_norm(const GsWork& g, int N, const double2* w, double* beta, double* inv_beta, int* flag,
              hipStream_t s, Profiler* prof);
 
+// workspace of the block (s-step) Arnoldi process (block.hip)
+constexpr int kBlockMax = 8;  // largest block
+struct BlockWork {
+  int ncap = 0;               // Q columns the buffers serve
+  double2* W = nullptr;       // ldq x kBlockMax block vectors
+  double2* part = nullptr;    // dot partials [chunk][column][kBlockMax]
+  double2* C1 = nullptr;      // [ncap][kBlockMax] first-pass coefficients
+  double2* C2 = nullptr;      // [ncap][kBlockMax] second-pass coefficients
+  double2* Ct = nullptr;      // [ncap][kBlockMax] their sum
+  double2* P = nullptr;       // [kBlockMax][ncap] H times Ct
+  double2* G = nullptr;       // [kBlockMax][kBlockMax] Gram matrix of the projected block
+  double2* R = nullptr;       // [3][kBlockMax][kBlockMax]: Cholesky factor R, R^-1, Rb^-1
+  double2* Rinv = nullptr;
+  double2* Rbi = nullptr;
+  int* flag = nullptr;        // set when a block is not of full rank
+};
+void block_alloc(BlockWork& b, int N, size_t ldq, int ncap);
+void block_free(BlockWork& b);
+
 // Wilson kernels (wilson.hip)
 struct Lattice {
   int L[4];
@@ -174,6 +197,12 @@ void axpby_abi(const double2* x, double2* y, double a, double b, bool g5, size_t
 // out = H_w(mu) (in * scale), optional copy_out = in * scale; scale = *inv_beta (or 1 if null)
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);
+
+// out = ca H_w(mu) (in * scale) + cb prev (prev nullable), optional copy_out =
+// in * scale: one step of a three-term polynomial recurrence in the stencil
+void wilson_apply_cheb(const Lattice& lat, const double2* links, const double2* in, double2* out,
+                       const double* inv_beta, double2* copy_out, const double2* prev, double ca, double cb,
+                       hipStream_t s, Profiler* prof);
 
 // most right-hand sides one launch carries; launch index z (blockIdx) works
 // on slot[z], aux[z] is a per-slot integer the caller defines
