@@ -54,6 +54,7 @@ HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_k
 HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
                      "block_factor": "bsmall_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
 BLOCK_STEPS = 8  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
+BATCH = 8  # sources per batched apply call of each context in the timed region
 STENCIL_DIMS = (32, 32, 32, 32)
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs, stored with the hash of the source it was measured on (stale -> null)
@@ -105,9 +106,12 @@ def main():
                     help="only the deflation-size scan (setup time, k and time per apply against m) and exit")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 12^4 x 32-source mixed-precision batch and print its JSON object")
-    ap.add_argument("--per-field", type=int, default=2,
-                    help="applies in flight per field in the timed steps: one context and stream each, all "
-                         "holding the field's Schur pair")
+    ap.add_argument("--per-field", type=int, default=1,
+                    help="contexts per field in the timed steps: one stream each, all holding the field's Schur "
+                         "pair")
+    ap.add_argument("--batch", type=int, default=BATCH,
+                    help="sources per apply call of each context in the timed region (1: sgn_apply; more: one "
+                         "sgn_apply_batched call on that many sources)")
     ap.add_argument("--block-steps", type=int, default=BLOCK_STEPS,
                     help="Arnoldi steps per block of the headline applies (sgn_set_block_steps; 0: the one-vector "
                          "process with its delayed re-orthogonalisation)")
@@ -182,6 +186,7 @@ def main():
         streams.append(st)
 
     P = 1 if args.serial else max(1, args.per_field)
+    B = 1 if args.serial else max(1, args.batch)
     # sources: the seeds whose exact results are stored for every field
     # (1000 .. 1000 + n - 1, dense Roberts sign of the oracle), cycled; so
     # every timed apply is checked against the exact y
@@ -191,7 +196,7 @@ def main():
         if os.path.exists(path):
             gold[f] = torch.from_numpy(np.load(path, allow_pickle=False)).to(dev)
     nstored = min(g.shape[0] for g in gold.values()) if len(gold) == len(MUS) else 0
-    nsrc = nstored if nstored else max((args.steps + args.warmup) * P, 2)
+    nsrc = nstored if nstored else max((args.steps + args.warmup) * P * B, 2)
     xs = [torch.from_numpy(synth.gaussian_source(DIMS, 1000 + r)).to(dev) for r in range(nsrc)]
     ys = [torch.empty(N, dtype=torch.complex128, device=dev) for _ in MUS]
     torch.cuda.synchronize()
@@ -244,19 +249,32 @@ def main():
                 unconverged.append(f)
             ks.append(sg.sgn_last_info(ctxs[f])["k_used"])
 
-    # one output buffer per timed apply and lane (the results are checked
-    # after the timed region)
-    outs = [[torch.empty(N, dtype=torch.complex128, device=dev) for _ in range(args.steps)] for _ in lanes]
+    # one output buffer per timed step and lane (the results are checked
+    # after the timed region); lane q = p * len(MUS) + f takes sources
+    # (r * P + p) * B + i, i < B, of step r, as one batched call when B > 1
+    outs = [[torch.empty(B, N, dtype=torch.complex128, device=dev) for _ in range(args.steps)] for _ in lanes]
+    src = lambda q, r: [((r * P + q // len(MUS)) * B + i) % len(xs) for i in range(B)]
+    batches = {}
+    if B > 1:
+        for q in range(len(lanes)):
+            for r in range(args.warmup + args.steps):
+                batches[(q, r)] = torch.stack([xs[i] for i in src(q, r)]).contiguous()
+    ybuf = [torch.empty(B, N, dtype=torch.complex128, device=dev) for _ in lanes]
+    torch.cuda.synchronize()
 
     def lane_steps(q, first, count, ks, timed):
-        # lane q = p * len(MUS) + f takes source r * P + p of step r
-        c, y = lanes[q]
-        p = q // len(MUS)
+        c = lanes[q][0]
         for r in range(first, first + count):
-            out = outs[q][r - first] if timed else y
-            if sg.sgn_apply(c, xs[(r * P + p) % len(xs)], out, TOL, KMAX) != sg.SGN_OK:
-                unconverged.append(q)
-            ks.append(sg.sgn_last_info(c)["k_used"])
+            out = outs[q][r - first] if timed else ybuf[q]
+            if B == 1:
+                if sg.sgn_apply(c, xs[src(q, r)[0]], out[0], TOL, KMAX) != sg.SGN_OK:
+                    unconverged.append(q)
+                ks.append(sg.sgn_last_info(c)["k_used"])
+            else:
+                st, infos = sg.sgn_apply_batched(c, batches[(q, r)], out, TOL, KMAX)
+                if st != sg.SGN_OK:
+                    unconverged.append(q)
+                ks.extend(i["k_used"] for i in infos)
 
     def run_concurrent(first, count, timed=False):
         ks = [[] for _ in lanes]
@@ -283,11 +301,12 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timed_unconverged = len(unconverged)
-    applies = args.steps * len(lanes)
+    applies = args.steps * len(lanes) * B
     value = applies / elapsed
     mode = "serial" if args.serial else f"{len(lanes)} streams"
     log(f"timed ({mode}): {applies} applies in {elapsed:.3f} s -> {value:.2f} applies/s, mean k {np.mean(ks):.1f}")
-    timed_acc = timed_accuracy(torch, outs if not args.serial else None, gold, nstored, P, args.warmup, args.steps)
+    timed_acc = timed_accuracy(torch, outs if not args.serial else None, gold, nstored, P, B, args.warmup,
+                               args.steps)
     log(f"timed applies vs exact: {timed_acc}")
 
     torch.cuda.synchronize()
@@ -402,9 +421,10 @@ def main():
         "config": {"workload": "sgn(H_w(mu))x, 6^4 lattice (N=15552), m_w=-1.6, mu in {0.0,0.2,0.5}, "
                                "m=20 Schur deflation, kmax=500, tol=1e-10, FP64, 1 RHS per apply, "
                                + ("3 applies per step (one per field, one at a time)" if args.serial else
-                                  f"{len(lanes)} applies per step ({P} per field in flight, one context and "
-                                  "stream each)"),
-                   "applies_in_flight_per_field": P, "graph_steps": args.graph_steps,
+                                  f"{len(lanes) * B} applies per step ({P * B} per field in flight: {P} "
+                                  f"context(s) and stream(s) per field, {B} source(s) per apply call)"),
+                   "applies_in_flight_per_field": P * B, "contexts_per_field": P, "sources_per_call": B,
+                   "graph_steps": args.graph_steps,
                    "block_steps": args.block_steps,
                    "lattice": list(DIMS), "m": M_DEFL, "kmax": KMAX, "tol": TOL, "mu": list(MUS),
                    "mean_k": round(float(np.mean(ks)), 1), "timed_unconverged": timed_unconverged},
@@ -430,7 +450,7 @@ def main():
     print(json.dumps(out))
 
 
-def timed_accuracy(torch, outs, gold, nstored, P, warmup, steps):
+def timed_accuracy(torch, outs, gold, nstored, P, B, warmup, steps):
     """Relative error |y - y_exact| / |y_exact| of every timed apply (the
     Results section's measure), against the stored exact results."""
     if outs is None or not nstored:
@@ -438,12 +458,14 @@ def timed_accuracy(torch, outs, gold, nstored, P, warmup, steps):
     errs, per_mu = [], {}
     for q, lane in enumerate(outs):
         f, p = q % len(MUS), q // len(MUS)
-        for i, y in enumerate(lane):
+        for i, Yb in enumerate(lane):
             r = warmup + i
-            ref = gold[f][(r * P + p) % nstored]
-            e = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
-            errs.append(e)
-            per_mu.setdefault(str(MUS[f]), []).append(e)
+            for b in range(B):
+                ref = gold[f][((r * P + p) * B + b) % nstored]
+                y = Yb[b]
+                e = float(torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref))
+                errs.append(e)
+                per_mu.setdefault(str(MUS[f]), []).append(e)
     return {"applies": len(errs), "max_rel_err": max(errs), "median_rel_err": float(np.median(errs)),
             "max_rel_err_per_mu": {k: max(v) for k, v in per_mu.items()},
             "sources": f"Gaussian seeds 1000..{1000 + nstored - 1}, cycled",

@@ -237,10 +237,6 @@ static hipGraphExec_t step_graph(sgn_ctx* c, const KrylovArgs& ka0, bool mixed, 
   return ex;
 }
 
-// A block of the block Arnoldi process was not of full rank: the apply is
-// repeated with one-vector steps.
-struct BlockFallback {};
-
 static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, double tol, int kmax, int fixed_k,
                           bool allow_block);
 
@@ -270,10 +266,20 @@ static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, doub
   const bool block = allow_block && !mixed && c->block_s > 0;
   const int sblk = block ? c->block_s : 1;
   const bool delayed = !block && (mixed || c->orth == SGN_ORTH_DELAYED);
+  BlockSpan bsp;  // the block process's basis: Q = (S V) in one matrix
   if (block) {
-    if (c->blk.ncap < c->ncap) block_alloc(c->blk, N, ldq, c->ncap);
+    if (c->blk.ncap < c->ncap || c->blk.nslots < 1) block_alloc(c->blk, N, ldq, c->ncap, 1);
     if (!(c->cheb_e > 0.0)) c->cheb_e = std::sqrt(sq_radius_estimate(c, 40, 0x5eedull));
     SGN_HIP(hipMemsetAsync(c->blk.flag, 0, sizeof(int), s));
+    bsp.S = c->Q;
+    bsp.V = c->Q + (size_t)m * ldq;
+    bsp.ldq = ldq;
+    bsp.m = m;
+    bsp.N = N;
+    bsp.ncap = c->ncap;
+    bsp.H = c->Hc;
+    bsp.ldh = c->ncap;
+    bsp.nb = 1;
   }
   // checkpoints of the block process fall on whole blocks
   auto align = [&](int kk) { return block ? std::min(kmax, (kk + sblk - 1) / sblk * sblk) : kk; };
@@ -428,7 +434,8 @@ static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, doub
         info.n_matvec += 1;
       } else if (block) {
         const int sb = std::min(sblk, seg_end - j);
-        block_step(c, j, sb, c->cheb_e, s, prof);
+        if (j == 0) block_first(bsp, c->wA, 0, &c->scal[1], 0, s);  // v_1 = x_perp / beta
+        block_step(bsp, c->blk, c->lat, c->links, j, sb, c->cheb_e, s, prof);
         j += sb;
         info.n_matvec += sb;
       } else {
@@ -493,7 +500,7 @@ static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, doub
 
   // step (vi): y = Q c
   const int n = m + k;
-  if (delayed) {
+  if (delayed || block) {
     if (mixed)
       krylov_combine<float2>(c->kw, ka, c->cvec, 0, c->wB, 0, n, s, prof);
     else

@@ -416,6 +416,290 @@ int run_batch(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double t
   return SGN_OK;
 }
 
+// The batch with the block (s-step) process (sgn_set_block_steps, FP64): per
+// source the start of sgn_apply's block process (two Gram-Schmidt passes
+// against S, v_1 = x_perp / beta), then blocks of s steps for every running
+// slot per launch, with run_batch's shared checkpoints (on whole blocks) and
+// stopping rule.  Per slot the arithmetic is that of sgn_apply with the same
+// block size, so at a fixed Krylov dimension a slot's result is bitwise the
+// single-source one.  A block that is not of full rank throws BlockFallback
+// (the caller repeats the batch with one-vector steps).
+int run_batch_block(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, double tol, int kmax, int fixed_k,
+                    sgn_info* info) {
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = c->stream;
+  Profiler* prof = c->prof.on ? &c->prof : nullptr;
+  c->prof.stream = s;
+  const int m = c->m, N = c->N, sblk = c->block_s;
+  const size_t ldq = c->ldq;
+  const int kwant = fixed_k >= 0 ? fixed_k : kmax;
+  batch_ensure(c, nr, std::max(kwant, 2));
+  BatchWork& b = c->bw;
+  const size_t ns = (size_t)b.nslots, ncap = (size_t)b.ncap, mm = (size_t)std::max(m, 1);
+  if (b.blk.ncap < b.ncap || b.blk.nslots < b.nslots) block_alloc(b.blk, N, ldq, b.ncap, b.nslots);
+  if (!(c->cheb_e > 0.0)) c->cheb_e = std::sqrt(sq_radius_estimate(c, 40, 0x5eedull));
+  double* h_err = b.hpin;
+  double* h_beta = b.hpin + ns;
+  int* h_flag = reinterpret_cast<int*>(b.hpin + 2 * ns);
+  int* h_fin = h_flag + ns;
+  auto align = [&](int kk) { return std::min(kwant, (kk + sblk - 1) / sblk * sblk); };
+
+  // step (iii) per source: two passes against S, c0 = S^dag x, beta, 1/beta
+  SGN_HIP(hipMemsetAsync(b.flag, 0, sizeof(int) * ns, s));
+  SGN_HIP(hipMemsetAsync(b.fin, 0, sizeof(int) * ns, s));
+  SGN_HIP(hipMemsetAsync(b.blk.flag, 0, sizeof(int) * ns, s));
+  for (int r = 0; r < nr; ++r) {
+    double2* xr = b.xin + (size_t)r * ldq;
+    double2* u0 = b.u + (size_t)r * ldq;
+    wilson_pack(c->lat, X_abi + (size_t)r * N, xr, s);
+    dev_check_finite(xr, (size_t)N, b.fin + r, s);
+    SGN_HIP(hipMemcpyAsync(u0, xr, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+    if (c->lr_m > 0) {  // LR-deflation, step (iii): L^dag x, x_- = (1 - R L^dag) x
+      double2* lc = b.lrc + (size_t)r * c->lr_m;
+      gs_dot(b.gs, c->lrL, ldq, N, c->lr_m, u0, lc, s, prof);
+      gs_update(b.gs, c->lrR, ldq, N, c->lr_m, lc, u0, nullptr, 0, s, prof);
+    }
+    if (m > 0) {
+      double2* hout = b.cv + (size_t)r * ncap;         // m sums, then beta
+      double2* h1 = b.cv + (ns + (size_t)r) * ncap;    // first-pass coefficients
+      double2* h2 = b.F + (size_t)r * mm;              // second-pass coefficients
+      gs_dot(b.gs, c->S, ldq, N, m, u0, h1, s, prof);
+      gs_update(b.gs, c->S, ldq, N, m, h1, u0, nullptr, 0, s, prof);
+      gs_dot(b.gs, c->S, ldq, N, m, u0, h2, s, prof);
+      GsFinal fin{h1, hout, b.beta + r, b.inv + r, b.flag + r};
+      gs_update(b.gs, c->S, ldq, N, m, h2, u0, &fin, 0, s, prof);
+      SGN_HIP(hipMemcpyAsync(b.c0 + (size_t)r * mm, hout, sizeof(double2) * m, hipMemcpyDeviceToDevice, s));
+    } else {
+      gs_norm(b.gs, N, u0, b.beta + r, b.inv + r, b.flag + r, s, prof);
+    }
+  }
+  SGN_HIP(hipMemcpyAsync(h_fin, b.fin, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipMemcpyAsync(h_flag, b.flag, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r < nr; ++r)
+    if (h_fin[r] != 0 || h_flag[r] < 0) throw SgnError{SGN_EINVAL, "x contains NaN or Inf"};
+
+  KrylovArgs base;
+  base.tune = c->tune;
+  base.N = N;
+  base.ldq = ldq;
+  base.m = m;
+  base.S = c->S;
+  base.V = b.V;
+  base.vstride = b.vstride;
+  base.ustride = ldq;
+  base.z = b.z;
+  base.zstride = ldq;
+  base.H = b.H;
+  base.ldh = b.ncap;
+  base.hstride = ncap * ncap;
+  base.c0 = b.c0;
+  base.c0stride = (int)mm;
+  base.beta = b.beta;
+  base.flag = b.flag;
+  base.brk_tol = 1e-12;
+  base.u = b.u;
+  auto fill = [&](KrylovArgs& ka, const std::vector<int>& slots, int j) {
+    ka.nb = (int)slots.size();
+    for (int z = 0; z < ka.nb; ++z) {
+      ka.act[z] = slots[z];
+      ka.jv[z] = j;
+    }
+  };
+  BlockSpan span;
+  span.S = c->S;
+  span.V = static_cast<double2*>(b.V);
+  span.vstride = b.vstride;
+  span.ldq = ldq;
+  span.m = m;
+  span.N = N;
+  span.ncap = b.ncap;
+  span.H = b.H;
+  span.hstride = ncap * ncap;
+  span.ldh = b.ncap;
+  auto span_for = [&](const std::vector<int>& slots) {
+    BlockSpan sp = span;
+    sp.nb = (int)slots.size();
+    for (int z = 0; z < sp.nb; ++z) sp.act[z] = slots[z];
+    return sp;
+  };
+
+  std::vector<SlotResult> res(nr);
+  std::vector<int> nprev(nr, -1);
+  std::vector<int> active, at_zero;  // x_perp = 0: y = S sgn(T) S^dag x, no Krylov step
+  for (int r = 0; r < nr; ++r) (h_flag[r] > 0 ? at_zero : active).push_back(r);
+  int ncheck = 0, newton_total = 0, n_matvec = 0;
+  double ms_sign = 0.0;
+  CkModel model;
+  int prev_ck = -1;
+  int next_ck;
+  const bool hinted = b.k_hint > 0 && b.tol_hint == tol;
+  if (fixed_k >= 0)
+    next_ck = fixed_k;
+  else if (hinted)
+    next_ck = align(std::min(kmax, std::max(2, even_k(b.k_hint))));
+  else
+    next_ck = align(std::min(kmax, std::max(2, even_k(std::min(32, kmax / 2)))));
+
+  // y_r = Q_r c_r for finished slots (grouped by their dimension)
+  auto finish = [&](const std::vector<int>& slots, const double2* cvcur) {
+    std::map<int, std::vector<int>> byn;
+    for (int r : slots) byn[m + res[r].k].push_back(r);
+    for (auto& g : byn) {
+      KrylovArgs kf = base;
+      fill(kf, g.second, 0);
+      krylov_combine<double2>(b.kw, kf, cvcur, (int)ncap, b.y, ldq, g.first, s, prof);
+      for (int r : g.second) {
+        if (c->lr_m > 0) {
+          double2* lc = b.lrc + (size_t)r * c->lr_m;
+          dev_cmul(c->lrSgn, lc, c->lr_m, s);
+          gs_add(b.gs, c->lrR, ldq, N, c->lr_m, lc, b.y + (size_t)r * ldq, s, prof);
+        }
+        wilson_unpack(c->lat, b.y + (size_t)r * ldq, Y_abi + (size_t)r * N, s);
+      }
+    }
+  };
+
+  // checkpoint (step (v)) for the slots of `slots` after k steps: signs,
+  // coefficients, changes; the finished ones are assembled and leave
+  auto checkpoint = [&](std::vector<int>& slots, int k) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (k > 0) {
+      SGN_HIP(hipMemcpyAsync(h_flag, b.blk.flag, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+      SGN_HIP(hipStreamSynchronize(s));
+      for (int r : slots)
+        if (h_flag[r] != 0) throw BlockFallback{};
+    }
+    for (int r : slots) {
+      res[r].k = k;
+      res[r].breakdown = (k == 0);
+    }
+    double2* cvcur = b.cv + (size_t)(ncheck & 1) * ns * ncap;
+    double2* cvprev = b.cv + (size_t)((ncheck + 1) & 1) * ns * ncap;
+    {
+      const int n = m + k, nb = (int)slots.size();
+      const size_t nn = (size_t)n * n;
+      double2* Apat = b.F;
+      double2* Fout = b.F + nn * ns;
+      if (n > 0) {
+        KrylovArgs kc = base;
+        fill(kc, slots, k);
+        krylov_patch(b.kw, kc, n, Apat, nn, false, s);
+        const int it = dense_sign_batched(b.dense, n, nb, Apat, n, nn, Fout, n, nn, s, prof);
+        newton_total += std::max(it, 0);
+      }
+      SlotMap cm;
+      cm.n = nb;
+      for (int z = 0; z < nb; ++z) {
+        cm.slot[z] = slots[z];
+        cm.aux[z] = nprev[slots[z]];
+      }
+      if (k == 0)
+        for (int z = 0; z < nb; ++z) SGN_HIP(hipMemsetAsync(b.beta + slots[z], 0, sizeof(double), s));
+      dense_coeffs_batched(n, m, Fout, n, nn, b.c0, (int)mm, b.beta, cvcur, cvprev, (int)ncap, cm, b.err, s);
+    }
+    SGN_HIP(hipMemcpyAsync(h_err, b.err, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+    SGN_HIP(hipStreamSynchronize(s));
+    ms_sign += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ++ncheck;
+    std::vector<int> done_now, still;
+    double worst = 0.0;
+    double rate = model.rate(b.rate_hint < 0.0 ? b.rate_hint : 0.0);
+    if (prev_ck >= 0) {
+      double w = 0.0;
+      for (int r : slots) w = std::max(w, h_err[r]);
+      if (w < 1e29) {
+        CkModel probe = model;
+        probe.hist.push_back(CkSpan{prev_ck, k, w});
+        rate = probe.rate(rate);
+      }
+    }
+    for (int r : slots) {
+      const double e = h_err[r];
+      res[r].err = e;
+      nprev[r] = m + res[r].k;
+      const bool ok = prev_ck >= 0 && e < 1e29 && CkModel::bound(e, k - prev_ck, rate) <= tol;
+      if (fixed_k >= 0 || res[r].breakdown || ok || k == kwant) {
+        res[r].done = true;
+        res[r].converged = fixed_k >= 0 || res[r].breakdown || ok;
+        done_now.push_back(r);
+      } else {
+        still.push_back(r);
+        worst = std::max(worst, e);
+      }
+    }
+    if (!done_now.empty()) finish(done_now, cvcur);
+    if (k == 0) {
+      slots.swap(still);
+      return;
+    }
+    if (still.empty() && fixed_k < 0 && b.k_hint == 0 && prev_ck > 0) {
+      b.k_hint = prev_ck;
+      b.tol_hint = tol;
+    }
+    slots.swap(still);
+    if (slots.empty()) return;
+    if (prev_ck >= 0 && worst < 1e29) model.hist.push_back(CkSpan{prev_ck, k, worst});
+    prev_ck = k;
+    rate = model.rate(b.rate_hint < 0.0 ? b.rate_hint : 0.0);
+    if (model.hist.size() >= 2 && CkModel::usable(rate) && b.rate_hint == 0.0) b.rate_hint = rate;
+    next_ck = align(model.next(k, kwant, tol, rate, hinted && model.hist.empty()));
+  };
+
+  if (!at_zero.empty()) checkpoint(at_zero, 0);
+  if (kwant == 0 && !active.empty()) {
+    // no Krylov part: y = S sgn(T_m) S^dag x
+    checkpoint(active, 0);
+  }
+  if (!active.empty()) block_first(span_for(active), b.u, ldq, b.inv, 1, s);
+  for (int j = 0; j < kwant && !active.empty();) {
+    const int seg_end = std::min(next_ck, kwant);
+    const int sb = std::min(sblk, seg_end - j);
+    block_step(span_for(active), b.blk, c->lat, c->links, j, sb, c->cheb_e, s, prof);
+    j += sb;
+    n_matvec += sb * (int)active.size();
+    if (j == next_ck || j == kwant) checkpoint(active, j);
+  }
+  SGN_HIP(hipMemcpyAsync(h_beta, b.beta, sizeof(double) * nr, hipMemcpyDeviceToHost, s));
+  SGN_HIP(hipStreamSynchronize(s));
+  if (prof) c->prof.flush();
+  const double ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  bool all = true;
+  sgn_info agg{};
+  for (int r = 0; r < nr; ++r) {
+    sgn_info in{};
+    in.k_used = res[r].k;
+    in.converged = res[r].converged ? 1 : 0;
+    in.newton_iters = newton_total;
+    in.n_matvec = res[r].k;
+    in.n_checkpoints = ncheck;
+    in.breakdown = res[r].breakdown ? 1 : 0;
+    in.err_est = res[r].err;
+    in.beta = h_beta[r];
+    in.ms_sign = ms_sign;
+    in.ms_total = ms_total;
+    in.ms_arnoldi = ms_total - ms_sign;
+    if (info) info[r] = in;
+    all = all && res[r].converged;
+    agg.k_used = std::max(agg.k_used, in.k_used);
+    agg.err_est = std::max(agg.err_est, in.err_est);
+  }
+  agg.converged = all ? 1 : 0;
+  agg.newton_iters = newton_total;
+  agg.n_matvec = n_matvec;
+  agg.n_checkpoints = ncheck;
+  agg.ms_sign = ms_sign;
+  agg.ms_total = ms_total;
+  agg.ms_arnoldi = ms_total - ms_sign;
+  c->info = agg;
+  if (!all) {
+    c->last_error = "kmax reached before the requested tolerance";
+    return SGN_ENOCONV;
+  }
+  return SGN_OK;
+}
+
 int batched_entry(sgn_ctx* c, int nrhs, const double* X, double* Y, double tol, int kmax, int fixed_k,
                   sgn_info* info) {
   SGN_REQUIRE(nrhs >= 1, SGN_EINVAL, "nrhs must be positive");
@@ -425,8 +709,19 @@ int batched_entry(sgn_ctx* c, int nrhs, const double* X, double* Y, double tol, 
   int status = SGN_OK;
   for (int r0 = 0; r0 < nrhs; r0 += kMaxBatch) {
     const int nr = std::min(kMaxBatch, nrhs - r0);
-    const int st = run_batch(c, nr, Xc + (size_t)r0 * c->N, Yc + (size_t)r0 * c->N, tol, kmax, fixed_k,
-                             info ? info + r0 : nullptr);
+    const double2* Xr = Xc + (size_t)r0 * c->N;
+    double2* Yr = Yc + (size_t)r0 * c->N;
+    sgn_info* ir = info ? info + r0 : nullptr;
+    int st;
+    if (c->block_s > 0 && c->prec == SGN_PREC_FP64) {
+      try {
+        st = run_batch_block(c, nr, Xr, Yr, tol, kmax, fixed_k, ir);
+      } catch (const BlockFallback&) {
+        st = run_batch(c, nr, Xr, Yr, tol, kmax, fixed_k, ir);
+      }
+    } else {
+      st = run_batch(c, nr, Xr, Yr, tol, kmax, fixed_k, ir);
+    }
     if (st != SGN_OK) status = st;
   }
   return status;

@@ -29,6 +29,14 @@
 // block vectors side by side in the 16-wide dimension: two real products per
 // 16 x 4 fragment of Q give the complex result without cross-lane sums.
 // Every sum has a fixed order, so results do not depend on the launch.
+//
+// A launch carries one or several right-hand sides of one field at the same
+// basis size (the batched applies advance in lockstep): the Schur columns S
+// are shared, each source has its own Krylov columns V_r, block vectors,
+// coefficients, factors and Hessenberg matrix at fixed strides, and the
+// launch position z (fastest in the workgroup numbering, so that the
+// workgroups reading the same rows of S run together) selects slot act[z].
+// Per slot the arithmetic does not depend on the other slots.
 #include "internal.h"
 #include "context.h"
 
@@ -42,6 +50,27 @@ namespace {
 
 __device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
+// k-steps whose loads a lane issues together in the block products
+constexpr int kUnroll = 8;
+// fewest rows per wavefront of the dot pass
+constexpr int kMinRowsPerWave = 128;
+
+// the composite basis of one launch: column c < m is S[c], column c >= m of
+// slot r is V_r[c - m] (V_r = V + r vstride), all with leading dimension ldq
+struct BlockGeo {
+  const double2* S;
+  const double2* V;
+  size_t vstride;
+  size_t ldq;
+  int m, p, s, N;
+  int nb;
+  int act[kMaxBatch];
+};
+
+__device__ inline const double2* qcol(const double2* S, const double2* Vr, int m, size_t ldq, int c) {
+  return c < m ? S + (size_t)c * ldq : Vr + (size_t)(c - m) * ldq;
+}
+
 __device__ inline double2 wsum2(double2 v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -51,9 +80,19 @@ __device__ inline double2 wsum2(double2 v) {
   return v;
 }
 
+// v_1 = u * inv per slot: the first Krylov column
+__global__ void bstart_kernel(BlockGeo g, const double2* __restrict__ u, size_t ustride,
+                              const double* __restrict__ inv, int istride) {
+  const int z = blockIdx.y, r = g.act[z];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  double2* v = const_cast<double2*>(g.V) + (size_t)r * g.vstride;
+  v[i] = cscale(u[(size_t)r * ustride + i], inv[(size_t)r * istride]);
+}
+
 // ---------------------------------------------------------------------------
 // dot pass: partial sums of conj(col_c) . W_v over row chunks.  Columns c < p
-// are Q's; with ncol = p + s, columns p + u are W_u (the Gram matrix).
+// are the basis; with ncol = p + s, columns p + u are W_u (the Gram matrix).
 // Wavefront: 16 columns x rpw rows; lane (li, lk) = (lane % 16, lane / 16)
 // holds, per k-step of four rows, row lk of column li (B fragment) and of
 // block vector li % 8, real part for li < 8, imaginary for li >= 8 (A
@@ -61,53 +100,55 @@ __device__ inline double2 wsum2(double2 v) {
 //   Re C[j][v] = D1[v][j] + D2[v+8][j],  Im C[j][v] = D1[v+8][j] - D2[v][j].
 // Workgroup: four wavefronts on consecutive row ranges, summed in order.
 struct BDot {
-  const double2* Q;
-  size_t ldq;
-  int p;
-  const double2* W;
-  size_t ldw;
-  int s;
+  const double2* W;  // slot block vectors, ld ldq
+  size_t wstride;
   int ncol;
-  int N;
-  int rpw;        // rows per wavefront, a multiple of 4
-  double2* part;  // [chunk][ncol][kBlockMax]
+  int rpw;  // rows per wavefront, a multiple of 4
+  int ncg;  // column groups of 16
+  double2* part;  // per slot [chunk][ncol][kBlockMax]
+  size_t pstride;
 };
 
-__global__ void __launch_bounds__(256) bdot_kernel(BDot a) {
+__global__ void __launch_bounds__(256) bdot_kernel(BlockGeo g, BDot a) {
+  const int z = blockIdx.x % g.nb, rest = blockIdx.x / g.nb;
+  const int cg = rest % a.ncg, chunk = rest / a.ncg;
+  const int r = g.act[z];
+  const double2* Vr = g.V + (size_t)r * g.vstride;
+  const double2* Wr = a.W + (size_t)r * a.wstride;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int c = blockIdx.x * 16 + li;
+  const int c = cg * 16 + li;
   const int v = li & 7;
   const bool imag = li >= 8;
-  const int r0 = (blockIdx.y * 4 + wave) * a.rpw;
-  const int r1 = min(r0 + a.rpw, a.N);
+  const int r0 = (chunk * 4 + wave) * a.rpw;
+  const int r1 = min(r0 + a.rpw, g.N);
   const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
   // a column past ncol reads column ncol - 1 (its sums are not written)
   const int cc = min(c, a.ncol - 1);
-  const double2* qp = (cc < a.p ? a.Q + (size_t)cc * a.ldq : a.W + (size_t)(cc - a.p) * a.ldw) + r0 + lk;
+  const double2* qp = (cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk;
   // the A fragment: the lane's real or imaginary part, loaded as one double
-  const bool vok = v < a.s;
-  const double* wp = vok ? reinterpret_cast<const double*>(a.W + (size_t)v * a.ldw + r0 + lk) + (imag ? 1 : 0)
+  const bool vok = v < g.s;
+  const double* wp = vok ? reinterpret_cast<const double*>(Wr + (size_t)v * g.ldq + r0 + lk) + (imag ? 1 : 0)
                          : reinterpret_cast<const double*>(&sgn_block_zero_entry);
   const int dw = vok ? 8 : 0;  // four rows, in doubles
   v4d d1 = {0.0, 0.0, 0.0, 0.0}, d2 = {0.0, 0.0, 0.0, 0.0};
   int it = 0;
-  for (; it + 4 <= nit; it += 4) {
-    double2 qv[4];
-    double wv[4];
+  for (; it + kUnroll <= nit; it += kUnroll) {
+    double2 qv[kUnroll];
+    double wv[kUnroll];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kUnroll; ++u) {
       qv[u] = qp[4 * u];
       wv[u] = wp[dw * u];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kUnroll; ++u) {
       d1 = mfma(wv[u], qv[u].x, d1);
       d2 = mfma(wv[u], qv[u].y, d2);
     }
-    qp += 16;
-    wp += 4 * dw;
+    qp += 4 * kUnroll;
+    wp += kUnroll * dw;
   }
   for (; it < nit; ++it) {
     const double2 qv = *qp;
@@ -131,7 +172,7 @@ __global__ void __launch_bounds__(256) bdot_kernel(BDot a) {
       c1 = cadd(c1, red[w][lane][1]);
     }
     // vectors past s have zero fragments, so their sums are zero
-    double2* o = a.part + ((size_t)blockIdx.y * a.ncol + c) * kBlockMax;
+    double2* o = a.part + (size_t)r * a.pstride + ((size_t)chunk * a.ncol + c) * kBlockMax;
     o[lk] = c0;
     o[lk + 4] = c1;
   }
@@ -141,13 +182,26 @@ __global__ void __launch_bounds__(256) bdot_kernel(BDot a) {
 // workgroup, 8 threads per entry (every 8th chunk), then the 8 in order.
 // Entry e = c * kBlockMax + v; c < p goes to C[c][v] (and C1[c][v] + C[c][v]
 // to Ct[c][v] if Ct), c >= p to G[c - p][v].
-__global__ void __launch_bounds__(256) bred_kernel(const double2* __restrict__ part, int nchunk, int nent, int p,
-                                                   double2* __restrict__ C, double2* __restrict__ G,
-                                                   const double2* __restrict__ C1, double2* __restrict__ Ct) {
+struct BRed {
+  const double2* part;
+  size_t pstride;
+  int nchunk, nent, nblk;
+  double2* C;
+  const double2* C1;
+  double2* Ct;
+  size_t cstride;
+  double2* G;
+  size_t gstride;
+};
+
+__global__ void __launch_bounds__(256) bred_kernel(BlockGeo g, BRed a) {
+  const int z = blockIdx.x % g.nb, blk = blockIdx.x / g.nb;
+  const int r = g.act[z];
+  const double2* __restrict__ part = a.part + (size_t)r * a.pstride;
   const int el = threadIdx.x & 31, q = threadIdx.x >> 5;
-  const int e = blockIdx.x * 32 + el;
-  const double2 zero = make_double2(0.0, 0.0);
-  double2 acc = zero;
+  const int e = blk * 32 + el;
+  const int nchunk = a.nchunk, nent = a.nent;
+  double2 acc = make_double2(0.0, 0.0);
   if (e < nent)
     for (int t0 = q; t0 < nchunk; t0 += 64) {
       double2 v[8];
@@ -160,71 +214,61 @@ __global__ void __launch_bounds__(256) bred_kernel(const double2* __restrict__ p
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
     }
-  __shared__ double2 r[8][33];
-  r[q][el] = acc;
+  __shared__ double2 rs[8][33];
+  rs[q][el] = acc;
   __syncthreads();
   if (q == 0 && e < nent) {
-    double2 t = r[0][el];
-    for (int w = 1; w < 8; ++w) t = cadd(t, r[w][el]);
+    double2 t = rs[0][el];
+    for (int w = 1; w < 8; ++w) t = cadd(t, rs[w][el]);
     const int c = e / kBlockMax;
-    if (c < p) {
-      C[e] = t;
-      if (Ct) Ct[e] = cadd(C1[e], t);
+    const size_t co = (size_t)r * a.cstride;
+    if (c < g.p) {
+      a.C[co + e] = t;
+      if (a.Ct) a.Ct[co + e] = cadd(a.C1[co + e], t);
     } else {
-      G[e - p * kBlockMax] = t;
+      a.G[(size_t)r * a.gstride + e - g.p * kBlockMax] = t;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Q C on the matrix cores: 16 rows of Q (column-major, ld ldq) times the
-// coefficients C[c][v] of columns c < ncol, for the k-steps (four columns)
-// k0, k0 + dk, ... .  Lane (li, lk) holds row li of column 4 ks + lk (A
-// fragment) and that column's coefficient for block vector li % 8 (B
-// fragment), so that
+// Q C on the matrix cores: 16 rows of the composite basis (S, Vr; ld ldq)
+// times the coefficients C[c][v] of columns c < ncol, for the k-steps (four
+// columns) k0, k0 + dk, ... .  Lane (li, lk) holds row li of column
+// 4 ks + lk (A fragment) and that column's coefficient for block vector
+// li % 8 (B fragment), so that
 //   D += Re(Q) [Re C | Im C] + Im(Q) [-Im C | Re C]
 // is [Re | Im] of (Q C) for the 16 rows and 8 vectors (rows lk + 4 t in item
-// t, vector li % 8, real part for li < 8).  A partial last k-step reads the
-// zero entry for columns past ncol.
-__device__ inline v4d qc_steps(const double2* __restrict__ Q, size_t ldq, int row, int ncol,
-                               const double2* __restrict__ C, int v, bool imag, bool vok, int lk, int k0, int dk,
-                               v4d d) {
+// t, vector li % 8, real part for li < 8).  Columns past ncol read the zero
+// entry.
+__device__ inline v4d qc_steps(const double2* __restrict__ S, const double2* __restrict__ Vr, int m, size_t ldq,
+                               int row, int ncol, const double2* __restrict__ C, int v, bool imag, bool vok, int lk,
+                               int k0, int dk, v4d d) {
   const double2* zero = &sgn_block_zero_entry;
-  const int nfull = ncol >> 2, nk = (ncol + 3) >> 2;
-  const double2* qp = Q + (size_t)(4 * k0 + lk) * ldq + row;
-  const double2* cp = vok ? C + (size_t)(4 * k0 + lk) * kBlockMax + v : zero;
-  const size_t dq = (size_t)4 * dk * ldq;
-  const int dc = vok ? 4 * dk * kBlockMax : 0;
+  const int nk = (ncol + 3) >> 2;
   int ks = k0;
-  for (; ks + 3 * dk < nfull; ks += 4 * dk) {
-    double2 qv[4], cv[4];
+  for (; ks + (kUnroll - 1) * dk < nk; ks += kUnroll * dk) {
+    double2 qv[kUnroll], cv[kUnroll];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      qv[u] = qp[u * dq];
-      cv[u] = cp[u * dc];
+    for (int u = 0; u < kUnroll; ++u) {
+      const int col = 4 * (ks + u * dk) + lk;
+      const bool ok = col < ncol;
+      qv[u] = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
+      cv[u] = *((ok & vok) ? C + (size_t)col * kBlockMax + v : zero);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kUnroll; ++u) {
       const double b1 = imag ? cv[u].y : cv[u].x;
       const double b2 = imag ? cv[u].x : -cv[u].y;
       d = mfma(qv[u].x, b1, d);
       d = mfma(qv[u].y, b2, d);
     }
-    qp += 4 * dq;
-    cp += 4 * dc;
   }
-  for (; ks < nfull; ks += dk) {
-    const double2 qv = *qp, cv = *cp;
-    const double b1 = imag ? cv.y : cv.x;
-    const double b2 = imag ? cv.x : -cv.y;
-    d = mfma(qv.x, b1, d);
-    d = mfma(qv.y, b2, d);
-    qp += dq;
-    cp += dc;
-  }
-  if (ks < nk) {
-    const bool ok = 4 * ks + lk < ncol;
-    const double2 qv = *(ok ? qp : zero), cv = *(ok ? cp : zero);
+  for (; ks < nk; ks += dk) {
+    const int col = 4 * ks + lk;
+    const bool ok = col < ncol;
+    const double2 qv = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
+    const double2 cv = *((ok & vok) ? C + (size_t)col * kBlockMax + v : zero);
     const double b1 = imag ? cv.y : cv.x;
     const double b2 = imag ? cv.x : -cv.y;
     d = mfma(qv.x, b1, d);
@@ -243,78 +287,89 @@ __device__ inline void qc_pairs(const v4d& d, double2 (&res)[4]) {
 // j): M[i] = (Rc Th)[r][i] - P[r][i-1] for i <= j (P = H_{p x (p-1)} Ct, zero
 // for rows r >= p), H[r][p-1+j] = sum_{i <= j} M[i] Rbi[i][j]; zero below the
 // subdiagonal.  Rc(r, 0) = [r == p-1]; Rc(r, i) = Ct[r][i-1] (r < p) or
-// R[r-p][i-1] (r >= p, upper triangular).
+// R[r-p][i-1] (r >= p, upper triangular).  Per slot: Ct, P at cstride (P
+// laid out [v][r] with ld ldp), R and Rbi at rstride, H at hstride.
 struct BHess {
-  int p, s;
   double e;
-  const double2* Ct;   // [p][kBlockMax]
-  const double2* P;    // [v][r], ld ldp: H_{p x (p-1)} Ct
+  const double2* Ct;
+  const double2* P;
+  size_t cstride;
   int ldp;
-  const double2* R;    // [kBlockMax][kBlockMax]
-  const double2* Rbi;  // [kBlockMax][kBlockMax]
+  const double2* R;
+  const double2* Rbi;
+  size_t rstride;
   double2* H;
+  size_t hstride;
   int ldh;
 };
 
-__device__ inline double2 rc_entry(const BHess& h, int r, int i) {
-  if (i == 0) return make_double2(r == h.p - 1 ? 1.0 : 0.0, 0.0);
-  if (r < h.p) return h.Ct[(size_t)r * kBlockMax + i - 1];
-  const int rr = r - h.p;
-  return rr <= i - 1 ? h.R[rr * kBlockMax + i - 1] : make_double2(0.0, 0.0);
-}
-
-__device__ void hess_entry(const BHess& h, int idx) {
+__device__ void hess_entry(const BlockGeo& g, const BHess& h, int r_slot, int idx) {
   const int r = idx / kBlockMax, j = idx % kBlockMax;
-  if (r >= h.p + h.s || j >= h.s) return;
+  const int p = g.p;
+  if (r >= p + g.s || j >= g.s) return;
+  const double2* Ct = h.Ct + (size_t)r_slot * h.cstride;
+  const double2* P = h.P + (size_t)r_slot * h.cstride;
+  const double2* R = h.R + (size_t)r_slot * h.rstride;
+  const double2* Rbi = h.Rbi + (size_t)r_slot * h.rstride;
+  auto rc = [&](int i) -> double2 {
+    if (i == 0) return make_double2(r == p - 1 ? 1.0 : 0.0, 0.0);
+    if (r < p) return Ct[(size_t)r * kBlockMax + i - 1];
+    const int rr = r - p;
+    return rr <= i - 1 ? R[rr * kBlockMax + i - 1] : make_double2(0.0, 0.0);
+  };
   double2 acc = make_double2(0.0, 0.0);
   for (int i = 0; i <= j; ++i) {
     double2 mi;
     if (i == 0) {
-      mi = cscale(rc_entry(h, r, 1), h.e);
+      mi = cscale(rc(1), h.e);
     } else {
-      mi = cscale(cadd(rc_entry(h, r, i - 1), rc_entry(h, r, i + 1)), 0.5 * h.e);
-      if (r < h.p) mi = csub(mi, h.P[(size_t)(i - 1) * h.ldp + r]);
+      mi = cscale(cadd(rc(i - 1), rc(i + 1)), 0.5 * h.e);
+      if (r < p) mi = csub(mi, P[(size_t)(i - 1) * h.ldp + r]);
     }
-    acc = cfma(mi, h.Rbi[i * kBlockMax + j], acc);
+    acc = cfma(mi, Rbi[i * kBlockMax + j], acc);
   }
   // column p-1+j has its subdiagonal in row p+j; below it H is zero
-  h.H[(size_t)(h.p - 1 + j) * h.ldh + r] = (r <= h.p + j) ? acc : make_double2(0.0, 0.0);
+  h.H[(size_t)r_slot * h.hstride + (size_t)(p - 1 + j) * h.ldh + r] = (r <= p + j) ? acc : make_double2(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
 // update pass: Wout = (Win - Q C) [Rinv].  Wavefront: 16 rows x all p
 // columns.  With Rinv (the second pass) the workgroups past the rows also
-// write the block's Hessenberg columns (hess).
+// write the block's Hessenberg columns (hess).  Workgroup id = z + nb b.
 struct BUpd {
-  const double2* Q;
-  size_t ldq;
-  int p;
-  const double2* C;  // [p][kBlockMax]
+  const double2* C;
+  size_t cstride;
   const double2* Win;
+  size_t winstride;
   double2* Wout;
-  size_t ldw;
-  int s;
-  const double2* Rinv;  // [kBlockMax][kBlockMax] upper triangular, or null
-  int N;
-  int nrowblk;          // workgroups on rows
+  size_t woutstride;
+  const double2* Rinv;  // per slot [kBlockMax][kBlockMax] upper triangular at rstride, or null
+  size_t rstride;
+  int nrowblk;  // workgroups on rows
   BHess hess;
 };
 
-__global__ void __launch_bounds__(256) bupdate_kernel(BUpd a) {
-  if ((int)blockIdx.x >= a.nrowblk) {
-    hess_entry(a.hess, ((int)blockIdx.x - a.nrowblk) * 256 + threadIdx.x);
+__global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
+  const int z = blockIdx.x % g.nb, bid = blockIdx.x / g.nb;
+  const int rs = g.act[z];
+  if (bid >= a.nrowblk) {
+    hess_entry(g, a.hess, rs, (bid - a.nrowblk) * 256 + threadIdx.x);
     return;
   }
+  const double2* Vr = g.V + (size_t)rs * g.vstride;
+  const double2* Cr = a.C + (size_t)rs * a.cstride;
+  const double2* Win = a.Win + (size_t)rs * a.winstride;
+  double2* Wout = a.Wout + (size_t)rs * a.woutstride;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = (blockIdx.x * 4 + wave) * 16;
-  const bool active = r0 < a.N;  // wavefront-uniform
-  const int row = min(r0 + li, a.N - 1);
+  const int r0 = (bid * 4 + wave) * 16;
+  const bool active = r0 < g.N;  // wavefront-uniform
+  const int row = min(r0 + li, g.N - 1);
   const int v = li & 7;
-  const bool vok = v < a.s;
+  const bool vok = v < g.s;
   v4d d = {0.0, 0.0, 0.0, 0.0};
-  if (active) d = qc_steps(a.Q, a.ldq, row, a.p, a.C, v, li >= 8, vok, lk, 0, 1, d);
+  if (active) d = qc_steps(g.S, Vr, g.m, g.ldq, row, g.p, Cr, v, li >= 8, vok, lk, 0, 1, d);
   double2 res[4];
   qc_pairs(d, res);
   if (!a.Rinv) {
@@ -322,21 +377,22 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BUpd a) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int rr = r0 + lk + 4 * t;
-        if (rr < a.N) {
-          const size_t o = (size_t)v * a.ldw + rr;
-          a.Wout[o] = csub(a.Win[o], res[t]);
+        if (rr < g.N) {
+          const size_t o = (size_t)v * g.ldq + rr;
+          Wout[o] = csub(Win[o], res[t]);
         }
       }
     return;
   }
   // second pass: W'' = Win - Q C, then W'' Rinv per row (through LDS)
+  const double2* Ri = a.Rinv + (size_t)rs * a.rstride;
   __shared__ double2 tile[4][16][kBlockMax];
   if (li < 8)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int rr = r0 + lk + 4 * t;
       double2 val = make_double2(0.0, 0.0);
-      if (active && vok && rr < a.N) val = csub(a.Win[(size_t)v * a.ldw + rr], res[t]);
+      if (active && vok && rr < g.N) val = csub(Win[(size_t)v * g.ldq + rr], res[t]);
       tile[wave][lk + 4 * t][v] = val;
     }
   __syncthreads();
@@ -347,40 +403,46 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BUpd a) {
     const int rl = idx >> 3, vv = idx & 7;
     double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < kBlockMax; ++u) acc = cfma(tile[wave][rl][u], a.Rinv[u * kBlockMax + vv], acc);
+    for (int u = 0; u < kBlockMax; ++u) acc = cfma(tile[wave][rl][u], Ri[u * kBlockMax + vv], acc);
     const int rr = r0 + rl;
-    if (vv < a.s && rr < a.N) a.Wout[(size_t)vv * a.ldw + rr] = acc;
+    if (vv < g.s && rr < g.N) Wout[(size_t)vv * g.ldq + rr] = acc;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Between the two passes' reductions and the second update: workgroup 0
-// factors the block, G'' = G - C2^dag C2 = R^dag R (R upper), and forms R^-1
-// and Rb^-1 (Rb = [1, Ct[p-1][0 .. s-2]; 0, R[0 .. s-2][0 .. s-2]]); it
-// raises flag when the block is not numerically of full rank (a pivot below
-// 1e-12 of the block's size, or below 1e-7 of the largest pivot) or not
-// finite.  Workgroups 1.. form P = H_{p x (p-1)} Ct for 16 rows each (the
-// four wavefronts take every fourth k-step, summed in order), from the
-// first column where a row of the tile can be nonzero (H is upper
-// Hessenberg below the T block, T upper triangular).
+// Between the two passes' reductions and the second update: per slot, one
+// workgroup factors the block, G'' = G - C2^dag C2 = R^dag R (R upper), and
+// forms R^-1 and Rb^-1 (Rb = [1, Ct[p-1][0 .. s-2]; 0, R[0 .. s-2][0 .. s-2]]);
+// it raises the slot's flag when the block is not numerically of full rank
+// (a pivot below 1e-12 of the block's size, or below 1e-7 of the largest
+// pivot) or not finite.  The other workgroups form P = H_{p x (p-1)} Ct for
+// 16 rows each (the four wavefronts take every fourth k-step, summed in
+// order), from the first column where a row of the tile can be nonzero (H is
+// upper Hessenberg below the T block, T upper triangular).  Workgroup id =
+// z + nb t: t = 0 factors, t >= 1 is row tile t - 1.
 struct BSmall {
-  int p, s, m;
-  const double2* C2;  // [p][kBlockMax]
-  const double2* Ct;  // [p][kBlockMax] C1 + C2
-  const double2* G;   // [s][kBlockMax]
+  const double2* C2;
+  const double2* Ct;
+  size_t cstride;
+  const double2* G;
+  size_t gstride;
   const double2* H;
+  size_t hstride;
   int ldh;
   double2* P;  // [v][r], ld ldp
   int ldp;
-  double2* R;     // [kBlockMax][kBlockMax]
-  double2* Rinv;  // [kBlockMax][kBlockMax]
-  double2* Rbi;   // [kBlockMax][kBlockMax]
+  double2* R;  // per slot: R, R^-1, Rb^-1 (kBlockMax^2 each) at rstride
+  size_t rstride;
   int* flag;
 };
 
-__device__ void block_factor(const BSmall& a) {
+__device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
   const int tid = threadIdx.x;
-  const int s = a.s, p = a.p;
+  const int s = gg.s, p = gg.p;
+  const double2* C2 = a.C2 + (size_t)rs * a.cstride;
+  const double2* Ct = a.Ct + (size_t)rs * a.cstride;
+  const double2* G = a.G + (size_t)rs * a.gstride;
+  double2* Rout = a.R + (size_t)rs * a.rstride;
   __shared__ double2 red[4][64];
   __shared__ double redn[4][64];
   __shared__ double2 g[kBlockMax][kBlockMax], R[kBlockMax][kBlockMax], Ri[kBlockMax][kBlockMax],
@@ -396,19 +458,19 @@ __device__ void block_factor(const BSmall& a) {
     if (u < s && v < s)
       for (int cb = q; cb < p; cb += 32) {
         // eight columns' loads in flight (clamped), then their sums in order
-        double2 x[8], y[8], z[8];
+        double2 x[8], y[8], w[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const size_t c = (size_t)min(cb + 4 * t, p - 1) * kBlockMax;
-          x[t] = a.C2[c + u];
-          y[t] = a.C2[c + v];
-          z[t] = a.Ct[c + v];
+          x[t] = C2[c + u];
+          y[t] = C2[c + v];
+          w[t] = Ct[c + v];
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t)
           if (cb + 4 * t < p) {
             acc = cfmac(x[t], y[t], acc);
-            nn += cabs2(z[t]);
+            nn += cabs2(w[t]);
           }
       }
     red[q][ent] = acc;
@@ -423,16 +485,16 @@ __device__ void block_factor(const BSmall& a) {
   __syncthreads();
   if (tid < kBlockMax * kBlockMax) {
     const double2 sub = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
-    g[u][v] = (u < s && v < s) ? csub(a.G[u * kBlockMax + v], sub) : make_double2(0.0, 0.0);
+    g[u][v] = (u < s && v < s) ? csub(G[u * kBlockMax + v], sub) : make_double2(0.0, 0.0);
   }
   if (tid == 0) {
     bad = 0;
-    double r = 0.0;
+    double rf = 0.0;
     for (int w = 0; w < s; ++w) {
       const int e = w * kBlockMax + w;
-      r = fmax(r, a.G[e].x + redn[0][e] + redn[1][e] + redn[2][e] + redn[3][e]);
+      rf = fmax(rf, G[e].x + redn[0][e] + redn[1][e] + redn[2][e] + redn[3][e]);
     }
-    ref_s = r;
+    ref_s = rf;
   }
   __syncthreads();
   // right-looking Cholesky: step j forms row j of R and updates the trailing block
@@ -449,13 +511,14 @@ __device__ void block_factor(const BSmall& a) {
     if (tid < kBlockMax && tid >= j && tid < s)
       R[j][tid] = tid == j ? make_double2(piv[j], 0.0) : cscale(g[j][tid], 1.0 / piv[j]);
     __syncthreads();
-    if (tid < kBlockMax * kBlockMax && u > j && v > j && u < s && v < s) g[u][v] = csub(g[u][v], cmulc(R[j][u], R[j][v]));
+    if (tid < kBlockMax * kBlockMax && u > j && v > j && u < s && v < s)
+      g[u][v] = csub(g[u][v], cmulc(R[j][u], R[j][v]));
     __syncthreads();
   }
   // Rb from R and the last basis column's coefficients
   if (tid < kBlockMax * kBlockMax && u < s && v < s) {
     if (u == 0)
-      Rb[0][v] = v == 0 ? make_double2(1.0, 0.0) : a.Ct[(size_t)(p - 1) * kBlockMax + v - 1];
+      Rb[0][v] = v == 0 ? make_double2(1.0, 0.0) : Ct[(size_t)(p - 1) * kBlockMax + v - 1];
     else if (v >= u)
       Rb[u][v] = R[u - 1][v - 1];
   }
@@ -477,9 +540,9 @@ __device__ void block_factor(const BSmall& a) {
   }
   __syncthreads();
   if (tid < kBlockMax * kBlockMax) {
-    a.R[tid] = R[u][v];
-    a.Rinv[tid] = Ri[u][v];
-    a.Rbi[tid] = Rbi[u][v];
+    Rout[tid] = R[u][v];
+    Rout[kBlockMax * kBlockMax + tid] = Ri[u][v];
+    Rout[2 * kBlockMax * kBlockMax + tid] = Rbi[u][v];
   }
   if (tid == 0) {
     double dmin = HUGE_VAL, dmax = 0.0;
@@ -487,25 +550,30 @@ __device__ void block_factor(const BSmall& a) {
       dmin = fmin(dmin, piv[j]);
       dmax = fmax(dmax, piv[j]);
     }
-    const double r = ref_s;
-    if (bad || !(r > 0.0) || !isfinite(r) || dmin * dmin < 1e-24 * r || dmin < 1e-7 * dmax) a.flag[0] = 1;
+    const double rf = ref_s;
+    if (bad || !(rf > 0.0) || !isfinite(rf) || dmin * dmin < 1e-24 * rf || dmin < 1e-7 * dmax) a.flag[rs] = 1;
   }
 }
 
-__global__ void __launch_bounds__(256) bsmall_kernel(BSmall a) {
-  if (blockIdx.x == 0) {
-    block_factor(a);
+__global__ void __launch_bounds__(256) bsmall_kernel(BlockGeo g, BSmall a) {
+  const int z = blockIdx.x % g.nb, t = blockIdx.x / g.nb;
+  const int rs = g.act[z];
+  if (t == 0) {
+    block_factor(g, a, rs);
     return;
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = (blockIdx.x - 1) * 16;
-  const int row = min(r0 + li, a.p - 1);
+  const int p = g.p;
+  const int r0 = (t - 1) * 16;
+  const int row = min(r0 + li, p - 1);
   const int v = li & 7;
-  const int c0 = r0 < a.m ? r0 : max(a.m, r0 - 1);  // columns below c0 are zero in these rows
+  const int c0 = r0 < g.m ? r0 : max(g.m, r0 - 1);  // columns below c0 are zero in these rows
+  const double2* H = a.H + (size_t)rs * a.hstride;
+  const double2* Ct = a.Ct + (size_t)rs * a.cstride;
   v4d d = {0.0, 0.0, 0.0, 0.0};
-  d = qc_steps(a.H, a.ldh, row, a.p - 1, a.Ct, v, li >= 8, v < a.s, lk, (c0 >> 2) + wave, 4, d);
+  d = qc_steps(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, v, li >= 8, v < g.s, lk, (c0 >> 2) + wave, 4, d);
   __shared__ v4d red[4][64];
   red[wave][lane] = d;
   __syncthreads();
@@ -515,39 +583,60 @@ __global__ void __launch_bounds__(256) bsmall_kernel(BSmall a) {
   for (int w = 1; w < 4; ++w) d += red[w][lane];
   double2 res[4];
   qc_pairs(d, res);
-  if (li < 8 && v < a.s)
+  double2* P = a.P + (size_t)rs * a.cstride;
+  if (li < 8 && v < g.s)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int rr = r0 + lk + 4 * t;
-      if (rr < a.p) a.P[(size_t)v * a.ldp + rr] = res[t];
+    for (int tt = 0; tt < 4; ++tt) {
+      const int rr = r0 + lk + 4 * tt;
+      if (rr < p) P[(size_t)v * a.ldp + rr] = res[tt];
     }
 }
 
 int nchunks_for(int N, int& rpw) {
-  // rows per wavefront: 64 or more, so that at most 128 chunks of four
-  // wavefronts cover N
+  // rows per wavefront: kMinRowsPerWave or more, so that at most 128 chunks
+  // of four wavefronts cover N
   const int want = (N + 4 * 128 - 1) / (4 * 128);
-  rpw = std::max(64, (want + 3) & ~3);
+  rpw = std::max(kMinRowsPerWave, (want + 3) & ~3);
   return (N + 4 * rpw - 1) / (4 * rpw);
+}
+
+BlockGeo make_geo(const BlockSpan& sp) {
+  BlockGeo g;
+  g.S = sp.S;
+  g.V = sp.V;
+  g.vstride = sp.vstride;
+  g.ldq = sp.ldq;
+  g.m = sp.m;
+  g.p = 0;
+  g.s = 0;
+  g.N = sp.N;
+  g.nb = sp.nb;
+  for (int z = 0; z < sp.nb; ++z) g.act[z] = sp.act[z];
+  return g;
 }
 
 }  // namespace
 
-void block_alloc(BlockWork& b, int N, size_t ldq, int ncap) {
+void block_alloc(BlockWork& b, int N, size_t ldq, int ncap, int nslots) {
   block_free(b);
   int rpw = 0;
   const int nch = nchunks_for(N, rpw);
-  SGN_HIP(hipMalloc(&b.W, sizeof(double2) * ldq * kBlockMax));
-  SGN_HIP(hipMalloc(&b.part, sizeof(double2) * (size_t)nch * (ncap + kBlockMax) * kBlockMax));
-  SGN_HIP(hipMalloc(&b.C1, sizeof(double2) * (size_t)ncap * kBlockMax));
-  SGN_HIP(hipMalloc(&b.C2, sizeof(double2) * (size_t)ncap * kBlockMax));
-  SGN_HIP(hipMalloc(&b.Ct, sizeof(double2) * (size_t)ncap * kBlockMax));
-  SGN_HIP(hipMalloc(&b.P, sizeof(double2) * (size_t)ncap * kBlockMax));
-  SGN_HIP(hipMalloc(&b.G, sizeof(double2) * kBlockMax * kBlockMax));
-  SGN_HIP(hipMalloc(&b.R, sizeof(double2) * kBlockMax * kBlockMax * 3));
-  b.Rinv = b.R + kBlockMax * kBlockMax;
-  b.Rbi = b.R + 2 * kBlockMax * kBlockMax;
-  SGN_HIP(hipMalloc(&b.flag, sizeof(int)));
+  const size_t S = (size_t)nslots;
+  b.nslots = nslots;
+  b.wstride = ldq * kBlockMax;
+  b.pstride = (size_t)nch * (ncap + kBlockMax) * kBlockMax;
+  b.cstride = (size_t)ncap * kBlockMax;
+  b.gstride = kBlockMax * kBlockMax;
+  b.rstride = 3 * kBlockMax * kBlockMax;
+  SGN_HIP(hipMalloc(&b.W, sizeof(double2) * b.wstride * S));
+  SGN_HIP(hipMalloc(&b.part, sizeof(double2) * b.pstride * S));
+  SGN_HIP(hipMalloc(&b.C1, sizeof(double2) * b.cstride * S));
+  SGN_HIP(hipMalloc(&b.C2, sizeof(double2) * b.cstride * S));
+  SGN_HIP(hipMalloc(&b.Ct, sizeof(double2) * b.cstride * S));
+  SGN_HIP(hipMalloc(&b.P, sizeof(double2) * b.cstride * S));
+  SGN_HIP(hipMalloc(&b.G, sizeof(double2) * b.gstride * S));
+  SGN_HIP(hipMalloc(&b.R, sizeof(double2) * b.rstride * S));
+  SGN_HIP(hipMalloc(&b.flag, sizeof(int) * S));
   b.ncap = ncap;
 }
 
@@ -557,62 +646,78 @@ void block_free(BlockWork& b) {
       (void)hipFree(*p);
       *p = nullptr;
     }
-  b.Rinv = b.Rbi = nullptr;
   if (b.flag) (void)hipFree(b.flag);
   b.flag = nullptr;
   b.ncap = 0;
+  b.nslots = 0;
 }
 
-void block_step(sgn_ctx* c, int k, int sb, double e, hipStream_t s, Profiler* prof) {
-  BlockWork& b = c->blk;
-  const int m = c->m, N = c->N, p = m + 1 + k;
-  const size_t ldq = c->ldq;
-  SGN_REQUIRE(sb >= 1 && sb <= kBlockMax && p + sb <= c->ncap && b.ncap >= c->ncap, SGN_EINVAL,
-              "block step exceeds the workspace");
-  double2* Q = c->Q;
-  double2* W = b.W;
-  const double2* w0 = Q + (size_t)(p - 1) * ldq;
+void block_first(const BlockSpan& sp, const double2* u, size_t ustride, const double* inv, int istride,
+                 hipStream_t s) {
+  BlockGeo g = make_geo(sp);
+  hipLaunchKernelGGL(bstart_kernel, dim3((sp.N + 255) / 256, sp.nb), dim3(256), 0, s, g, u, ustride, inv, istride);
+  SGN_HIP(hipGetLastError());
+}
+
+void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const double2* links, int k, int sb, double e,
+                hipStream_t s, Profiler* prof) {
+  const int m = sp.m, N = sp.N, p = m + 1 + k, nb = sp.nb;
+  const size_t ldq = sp.ldq;
+  SGN_REQUIRE(sb >= 1 && sb <= kBlockMax && p + sb <= sp.ncap && b.ncap >= sp.ncap && nb >= 1 && nb <= kMaxBatch &&
+                  nb <= b.nslots,
+              SGN_EINVAL, "block step exceeds the workspace");
+  BlockGeo g = make_geo(sp);
+  g.p = p;
+  g.s = sb;
+  // the newest basis column q_{p-1} = V_r[p-1-m]
+  const double2* w0 = sp.V + (size_t)(p - 1 - m) * ldq;
   // Krylov directions: W_1 = A W_0 / e, W_{i+1} = 2 A W_i / e - W_{i-1}
-  if (k == 0)  // W_0 = v_1 = x_perp / beta, written to Q on the way
-    wilson_apply_cheb(c->lat, c->links, c->wA, W, &c->scal[1], Q + (size_t)m * ldq, nullptr, 1.0 / e, 0.0, s, prof);
-  else
-    wilson_apply_cheb(c->lat, c->links, w0, W, nullptr, nullptr, nullptr, 1.0 / e, 0.0, s, prof);
+  SlotMap map;
+  map.n = nb;
+  for (int z = 0; z < nb; ++z) map.slot[z] = sp.act[z];
+  wilson_apply_cheb_slots(lat, links, w0, sp.vstride, b.W, b.wstride, nullptr, 0, 1.0 / e, 0.0, map, s, prof);
   for (int i = 1; i < sb; ++i)
-    wilson_apply_cheb(c->lat, c->links, W + (size_t)(i - 1) * ldq, W + (size_t)i * ldq, nullptr, nullptr,
-                      i == 1 ? w0 : W + (size_t)(i - 2) * ldq, 2.0 / e, -1.0, s, prof);
+    wilson_apply_cheb_slots(lat, links, b.W + (size_t)(i - 1) * ldq, b.wstride, b.W + (size_t)i * ldq, b.wstride,
+                            i == 1 ? w0 : b.W + (size_t)(i - 2) * ldq, i == 1 ? sp.vstride : b.wstride, 2.0 / e,
+                            -1.0, map, s, prof);
   int rpw = 0;
   const int nch = nchunks_for(N, rpw);
   auto dot = [&](double2* C, int ncol, const double2* C1, double2* Ct) {
-    BDot d{Q, ldq, p, W, ldq, sb, ncol, N, rpw, b.part};
+    const int ncg = (ncol + 15) / 16;
+    BDot d{b.W, b.wstride, ncol, rpw, ncg, b.part, b.pstride};
     // Q (and W as columns) read once, W once per column group, partials written
-    const double bytes = 16.0 * N * ((double)ncol + sb) + 16.0 * nch * ncol * kBlockMax;
-    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb, bdot_kernel, dim3((ncol + 15) / 16, nch), dim3(256), 0,
-                s, d);
-    const int nent = ncol * kBlockMax;
-    prof_launch(prof, K_BRED, 16.0 * (double)nch * nent + 16.0 * nent, 2.0 * nch * nent, bred_kernel,
-                dim3((nent + 31) / 32), dim3(256), 0, s, (const double2*)b.part, nch, nent, p, C, b.G, C1, Ct);
+    const double bytes = (16.0 * N * ((double)ncol + sb) + 16.0 * nch * ncol * kBlockMax) * nb;
+    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, bdot_kernel, dim3(ncg * nch * nb), dim3(256), 0, s,
+                g, d);
+    const int nent = ncol * kBlockMax, nblk = (nent + 31) / 32;
+    BRed rd{b.part, b.pstride, nch, nent, nblk, C, C1, Ct, b.cstride, b.G, b.gstride};
+    prof_launch(prof, K_BRED, (16.0 * (double)nch * nent + 16.0 * nent) * nb, 2.0 * nch * nent * nb, bred_kernel,
+                dim3(nblk * nb), dim3(256), 0, s, g, rd);
   };
   const int nrowblk = (N + 63) / 64;
+  const double upd_bytes = (16.0 * N * ((double)p + 2.0 * sb) + 16.0 * p * sb) * nb;
   // pass 1
   dot(b.C1, p, nullptr, nullptr);
   {
-    BUpd u{Q, ldq, p, b.C1, W, W, ldq, sb, nullptr, N, nrowblk, BHess{}};
-    prof_launch(prof, K_BUPDATE, 16.0 * N * ((double)p + 2.0 * sb) + 16.0 * p * sb, 8.0 * N * p * sb, bupdate_kernel,
-                dim3(nrowblk), dim3(256), 0, s, u);
+    BUpd u{b.C1, b.cstride, b.W, b.wstride, b.W, b.wstride, nullptr, 0, nrowblk, BHess{}};
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3(nrowblk * nb), dim3(256), 0, s,
+                g, u);
   }
   // pass 2 with the Gram matrix of the projected block
   dot(b.C2, p + sb, b.C1, b.Ct);
   {
-    BSmall sm{p, sb, m, b.C2, b.Ct, b.G, c->Hc, c->ncap, b.P, c->ncap, b.R, b.Rinv, b.Rbi, b.flag};
-    const double hb = 16.0 * ((double)p * p / 2 + 3.0 * p * sb);
-    prof_launch(prof, K_BSMALL, hb, 8.0 * p * p * sb / 2, bsmall_kernel, dim3(1 + (p + 15) / 16), dim3(256), 0, s,
-                sm);
+    BSmall sm{b.C2, b.Ct, b.cstride, b.G, b.gstride, sp.H, sp.hstride, sp.ldh, b.P, sp.ncap, b.R, b.rstride, b.flag};
+    const double hb = 16.0 * ((double)p * p / 2 + 3.0 * p * sb) * nb;
+    prof_launch(prof, K_BSMALL, hb, 8.0 * p * p * sb / 2 * nb, bsmall_kernel, dim3((1 + (p + 15) / 16) * nb),
+                dim3(256), 0, s, g, sm);
   }
   {
-    BHess h{p, sb, e, b.Ct, b.P, c->ncap, b.R, b.Rbi, c->Hc, c->ncap};
-    BUpd u{Q, ldq, p, b.C2, W, Q + (size_t)p * ldq, ldq, sb, b.Rinv, N, nrowblk, h};
+    BHess h{e, b.Ct, b.P, b.cstride, sp.ncap, b.R, b.R + 2 * kBlockMax * kBlockMax, b.rstride, sp.H, sp.hstride,
+            sp.ldh};
+    BUpd u{b.C2, b.cstride, b.W, b.wstride, const_cast<double2*>(sp.V) + (size_t)(p - m) * ldq, sp.vstride,
+           b.R + kBlockMax * kBlockMax, b.rstride, nrowblk, h};
     const int nh = ((p + sb) * kBlockMax + 255) / 256;
-    prof_launch(prof, K_BUPDATE, 16.0 * N * ((double)p + 2.0 * sb) + 16.0 * p * sb, 8.0 * N * p * sb, bupdate_kernel,
-                dim3(nrowblk + nh), dim3(256), 0, s, u);
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3((nrowblk + nh) * nb),
+                dim3(256), 0, s, g, u);
   }
 }

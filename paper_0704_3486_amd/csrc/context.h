@@ -39,6 +39,7 @@ struct BatchWork {
   GsWork gs;
   KrylovWork kw;
   DenseWork dense;
+  BlockWork blk;  // block (s-step) process, per slot
   // checkpoint placement learned by earlier batched applies (as k_hint, rate_hint)
   int k_hint = 0;
   double tol_hint = 0.0;
@@ -70,6 +71,7 @@ struct BatchWork {
     gs_free(gs);
     krylov_free(kw);
     dense_destroy(dense);
+    block_free(blk);
     nslots = kcap = ncap = 0;
     prec = m = lrm = -1;
   }
@@ -312,11 +314,10 @@ inline void check_adjoint(const sgn_ctx* c) {
 }
 
 
-// One block of sb <= kBlockMax Arnoldi steps from k finished steps (block.hip):
-// Q columns m + k + 1 .. m + k + sb and H columns m + k .. m + k + sb - 1; at
-// k = 0 it also writes v_1 = wA * scal[1].  e: half-width of the Chebyshev
-// interval.  A block that is not of full rank raises blk.flag.
-void block_step(sgn_ctx* c, int k, int sb, double e, hipStream_t s, Profiler* prof);
+// A block of the block Arnoldi process was not of full rank: the apply is
+// repeated with one-vector steps.
+struct BlockFallback {};
+
 // 1.1 x the spectral radius of A^2 from an Arnoldi run of `steps` steps on A^2
 // (deflate.hip)
 double sq_radius_estimate(sgn_ctx* c, int steps, unsigned long long seed);

@@ -150,25 +150,6 @@ void gs_update(const GsWork& g, const double2* Q, size_t ldq, int N, int ncol, c
 void gs_norm(const GsWork& g, int N, const double2* w, double* beta, double* inv_beta, int* flag,
              hipStream_t s, Profiler* prof);
 
-// workspace of the block (s-step) Arnoldi process (block.hip)
-constexpr int kBlockMax = 8;  // largest block
-struct BlockWork {
-  int ncap = 0;               // Q columns the buffers serve
-  double2* W = nullptr;       // ldq x kBlockMax block vectors
-  double2* part = nullptr;    // dot partials [chunk][column][kBlockMax]
-  double2* C1 = nullptr;      // [ncap][kBlockMax] first-pass coefficients
-  double2* C2 = nullptr;      // [ncap][kBlockMax] second-pass coefficients
-  double2* Ct = nullptr;      // [ncap][kBlockMax] their sum
-  double2* P = nullptr;       // [kBlockMax][ncap] H times Ct
-  double2* G = nullptr;       // [kBlockMax][kBlockMax] Gram matrix of the projected block
-  double2* R = nullptr;       // [3][kBlockMax][kBlockMax]: Cholesky factor R, R^-1, Rb^-1
-  double2* Rinv = nullptr;
-  double2* Rbi = nullptr;
-  int* flag = nullptr;        // set when a block is not of full rank
-};
-void block_alloc(BlockWork& b, int N, size_t ldq, int ncap);
-void block_free(BlockWork& b);
-
 // Wilson kernels (wilson.hip)
 struct Lattice {
   int L[4];
@@ -198,11 +179,6 @@ void axpby_abi(const double2* x, double2* y, double a, double b, bool g5, size_t
 void wilson_apply(const Lattice& lat, const double2* links, const double2* in, double2* out,
                   const double* inv_beta, double2* copy_out, hipStream_t s, Profiler* prof);
 
-// out = ca H_w(mu) (in * scale) + cb prev (prev nullable), optional copy_out =
-// in * scale: one step of a three-term polynomial recurrence in the stencil
-void wilson_apply_cheb(const Lattice& lat, const double2* links, const double2* in, double2* out,
-                       const double* inv_beta, double2* copy_out, const double2* prev, double ca, double cb,
-                       hipStream_t s, Profiler* prof);
 
 // most right-hand sides one launch carries; launch index z (blockIdx) works
 // on slot[z], aux[z] is a per-slot integer the caller defines
@@ -228,6 +204,57 @@ void wilson_apply_multi(const Lattice& lat, const double2* links, const double2*
 void wilson_apply_multi32(const Lattice& lat, const float2* links, const float2* in, size_t istride, float2* out,
                           size_t ostride, int nrhs, bool split, hipStream_t s, Profiler* prof);
 void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t s);
+
+// workspace of the block (s-step) Arnoldi process (block.hip), per slot at
+// the given strides (nslots right-hand sides)
+constexpr int kBlockMax = 8;  // largest block
+struct BlockWork {
+  int ncap = 0;               // basis columns the buffers serve
+  int nslots = 0;
+  double2* W = nullptr;       // ldq x kBlockMax block vectors
+  double2* part = nullptr;    // dot partials [chunk][column][kBlockMax]
+  double2* C1 = nullptr;      // [ncap][kBlockMax] first-pass coefficients
+  double2* C2 = nullptr;      // [ncap][kBlockMax] second-pass coefficients
+  double2* Ct = nullptr;      // [ncap][kBlockMax] their sum
+  double2* P = nullptr;       // [kBlockMax][ncap] H times Ct
+  double2* G = nullptr;       // [kBlockMax][kBlockMax] Gram matrix of the projected block
+  double2* R = nullptr;       // [3][kBlockMax][kBlockMax]: Cholesky factor R, R^-1, Rb^-1
+  int* flag = nullptr;        // set when a block is not of full rank
+  size_t wstride = 0, pstride = 0, cstride = 0, gstride = 0, rstride = 0;
+};
+void block_alloc(BlockWork& b, int N, size_t ldq, int ncap, int nslots);
+void block_free(BlockWork& b);
+// The composite bases of one launch of the block process: Schur columns S
+// (m, shared), Krylov columns V_r = V + r vstride (basis column c >= m is
+// V_r[c - m]), Hessenberg matrices H + r hstride (ld ldh); nb slots act[z];
+// p + s <= ncap for every block.
+struct BlockSpan {
+  const double2* S = nullptr;
+  double2* V = nullptr;
+  size_t vstride = 0, ldq = 0;
+  int m = 0, N = 0, ncap = 0;
+  double2* H = nullptr;
+  size_t hstride = 0;
+  int ldh = 0;
+  int nb = 0;
+  int act[kMaxBatch] = {};
+};
+// v_1 of every slot: V_r[0] = u_r * inv_r (u at ustride, inv at istride)
+void block_first(const BlockSpan& sp, const double2* u, size_t ustride, const double* inv, int istride,
+                 hipStream_t s);
+// One block of sb <= kBlockMax Arnoldi steps from k finished steps for every
+// slot: basis columns m + k + 1 .. m + k + sb and Hessenberg columns
+// m + k .. m + k + sb - 1; e: half-width of the Chebyshev interval.  A block
+// that is not of full rank raises its slot's b.flag.
+void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const double2* links, int k, int sb, double e,
+                hipStream_t s, Profiler* prof);
+
+// Out_r = ca H_w(mu) In_r + cb Prev_r (Prev nullable) for the slots of map,
+// at fixed slot strides: one step of a three-term polynomial recurrence in
+// the stencil
+void wilson_apply_cheb_slots(const Lattice& lat, const double2* links, const double2* in, size_t istride,
+                             double2* out, size_t ostride, const double2* prev, size_t pstride, double ca, double cb,
+                             const SlotMap& map, hipStream_t s, Profiler* prof);
 
 // dense kernels (dense.hip)
 struct DenseWork {

@@ -277,15 +277,15 @@ __device__ inline C shfl_xor_c(C v, int mask) {
 // in direction order.  The site's own spinor entries for the second phase
 // are loaded with the hop operands, so a workgroup waits on memory once.
 // blockIdx.y = right-hand side (slot map).  Optional: scale = *inv_beta on
-// input and output, copy_out = In * scale; with cheb, Out = ca H_w In + cb
-// prev (one right-hand side; prev null: cb ignored), a step of a three-term
-// polynomial recurrence.
+// input and output, copy_out = In * scale; with cheb, Out_r = ca H_w In_r +
+// cb Prev_r (Prev_r = prev + slot pstride; prev null: cb ignored), a step of
+// a three-term polynomial recurrence.
 template <typename C>
 __global__ void __launch_bounds__(256)
 wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
                      size_t ostride, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx, int Ly,
                      int Lz, int Lt, double kappa_d, double emu_d, double emmu_d, SlotMap map, SiteOrder order,
-                     const C* __restrict__ prev, double ca, double cb, int cheb) {
+                     const C* __restrict__ prev, size_t pstride, double ca, double cb, int cheb) {
   using R = typename Real<C>::type;
   constexpr int kThreads = 256, kOut = 12 * kSiteGroup;
   const int V = Lx * Ly * Lz * Lt;
@@ -384,7 +384,7 @@ wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size
     C val = tscale(tsub(self[q], tscale(acc, kappa)), g5 * scale);
     if (cheb) {
       val = tscale(val, (R)ca);
-      if (prev) val = tadd(val, tscale(prev[idx], (R)cb));
+      if (prev) val = tadd(val, tscale(prev[(size_t)slot * pstride + idx], (R)cb));
     }
     w[idx] = val;
     if (copy_out) copy_out[idx] = tscale(self[q], scale);
@@ -569,18 +569,19 @@ void wilson_apply(const Lattice& lat, const double2* links, const double2* in, d
   prof_launch(prof, K_WILSON, per_site * V, 1392.0 * V, wilson_hw_dir_kernel<double2>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, 1), dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0,
               inv_beta, copy_out, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{},
-              site_order(lat), (const double2*)nullptr, 1.0, 0.0, 0);
+              site_order(lat), (const double2*)nullptr, (size_t)0, 1.0, 0.0, 0);
 }
 
-void wilson_apply_cheb(const Lattice& lat, const double2* links, const double2* in, double2* out,
-                       const double* inv_beta, double2* copy_out, const double2* prev, double ca, double cb,
-                       hipStream_t s, Profiler* prof) {
+void wilson_apply_cheb_slots(const Lattice& lat, const double2* links, const double2* in, size_t istride,
+                             double2* out, size_t ostride, const double2* prev, size_t pstride, double ca, double cb,
+                             const SlotMap& map, hipStream_t s, Profiler* prof) {
+  SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
   const int V = lat.V;
-  const double per_site = (48.0 + (copy_out ? 12.0 : 0.0) + (prev ? 12.0 : 0.0)) * 16.0;
-  prof_launch(prof, K_WILSON, per_site * V, 1392.0 * V, wilson_hw_dir_kernel<double2>,
-              dim3((V + kSiteGroup - 1) / kSiteGroup, 1), dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0,
-              inv_beta, copy_out, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{},
-              site_order(lat), prev, ca, cb, 1);
+  const double per_site = (48.0 + (prev ? 12.0 : 0.0)) * 16.0;
+  prof_launch(prof, K_WILSON, per_site * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<double2>,
+              dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
+              (const double*)nullptr, (double2*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
+              lat.emmu, map, site_order(lat), prev, pstride, ca, cb, 1);
 }
 
 // several right-hand sides: one hop per thread (bitwise the single-RHS
@@ -598,8 +599,8 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
   if (split || nrhs == 1) {
     hipLaunchKernelGGL((wilson_hw_dir_kernel<C>), dim3((V + kSiteGroup - 1) / kSiteGroup, nrhs),
                        dim3(256), 0, s, links, in, istride, out, ostride, nullptr, nullptr, L0, L1, L2,
-                       L3, lat.kappa, lat.emu, lat.emmu, SlotMap{}, site_order(lat), (const C*)nullptr, 1.0, 0.0,
-                       0);
+                       L3, lat.kappa, lat.emu, lat.emmu, SlotMap{}, site_order(lat), (const C*)nullptr, (size_t)0,
+                       1.0, 0.0, 0);
   } else if (nrhs >= 4 && sizeof(C) == 8) {
     hipLaunchKernelGGL((wilson_hw_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), blk, 0, s, links, in, istride, out,
                        ostride, nrhs, L0, L1, L2, L3, lat.kappa, lat.emu, lat.emmu);
@@ -625,7 +626,7 @@ void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t 
   prof_launch(prof, K_WILSON, 48.0 * b * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
               (const double*)nullptr, (C*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
-              lat.emmu, map, site_order(lat), (const C*)nullptr, 1.0, 0.0, 0);
+              lat.emmu, map, site_order(lat), (const C*)nullptr, (size_t)0, 1.0, 0.0, 0);
 }
 template void wilson_apply_slots<double2>(const Lattice&, const double2*, const double2*, size_t, double2*, size_t,
                                           const SlotMap&, hipStream_t, Profiler*);
