@@ -59,6 +59,7 @@ STENCIL_DIMS = (32, 32, 32, 32)
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs, stored with the hash of the source it was measured on (stale -> null)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_krylov_6x6x6x6_m20_fp64.txt")
+TRAFFIC_FILE_BLOCK = os.path.join(ROOT, "profiles", "hbm_traffic_block_6x6x6x6_m20_fp64_batch8.txt")
 DIMS = (6, 6, 6, 6)
 MUS = (0.0, 0.2, 0.5)
 M_W = -1.6
@@ -121,6 +122,10 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
                          "whose per-kernel averages then compare with the HIP-event ones)")
+    ap.add_argument("--counters", action="store_true",
+                    help="only one batched call per field of the headline configuration, with the library's "
+                         "algorithmic bytes per launch of each kernel class (the run that rocprofv3 counter "
+                         "passes wrap)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of 2 GiB three times (the reference for the "
                          "HBM traffic counters) and exit")
@@ -160,6 +165,9 @@ def main():
         return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.counters:
+        print(json.dumps(counters_leg(sg, synth, torch, args.block_steps, args.batch)))
+        return
     dev = torch.device("cuda:0")
     links = synth.random_links(DIMS, synth.GAUGE_SEED)
     N = 12 * int(np.prod(DIMS))
@@ -323,14 +331,20 @@ def main():
     for c in ctxs:
         sg.sgn_set_step_graphs(c, 0)  # the profiled pass times direct launches
 
-    # profiled pass over the same steps, one apply at a time (HIP events on
-    # each context's stream)
+    # profiled pass over the same steps and calls as the timed region (B
+    # sources per call), one field at a time (HIP events on each context's
+    # stream)
     for c in ctxs:
         sg.sgn_profile_reset(c)
         sg.sgn_set_profiling(c, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ks_prof = run_serial(args.warmup, args.steps)
+    ks_prof = []
+    if args.serial:
+        ks_prof = run_serial(args.warmup, args.steps)
+    else:
+        for q in range(len(MUS)):
+            lane_steps(q, args.warmup, args.steps, ks_prof, False)
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t1
     kstats = {}
@@ -448,6 +462,34 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def counters_leg(sg, synth, torch, block_steps, B):
+    """One batched call of B sources per field of the headline configuration
+    (profiling on: the library's algorithmic bytes per launch), for the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes that wrap this command."""
+    links = synth.random_links(DIMS, synth.GAUGE_SEED)
+    N = 12 * int(np.prod(DIMS))
+    X = torch.stack([torch.from_numpy(synth.gaussian_source(DIMS, 1000 + r)) for r in range(B)]).cuda()
+    Y = torch.empty_like(X)
+    stats = {}
+    for mu in MUS:
+        ctx = sg.sgn_create(links, DIMS, mu, M_W)
+        sg.sgn_deflate(ctx, M_DEFL)
+        sg.sgn_set_block_steps(ctx, block_steps)
+        sg.sgn_profile_reset(ctx)
+        sg.sgn_set_profiling(ctx, True)
+        sg.sgn_apply_batched(ctx, X, Y, TOL, KMAX)
+        torch.cuda.synchronize()
+        for name, st in sg.sgn_profile_read(ctx).items():
+            a = stats.setdefault(name, {"launches": 0, "bytes": 0.0})
+            a["launches"] += st["launches"]
+            a["bytes"] += st["bytes"]
+        sg.sgn_destroy(ctx)
+    return {"workload": f"6^4, mu in {list(MUS)}, m={M_DEFL}, {B} sources per batched call, block steps "
+                        f"{block_steps}, tol {TOL}, N={N}",
+            "per_class": {k: {"launches": v["launches"], "algorithmic_bytes_per_launch": round(v["bytes"] / v["launches"])}
+                          for k, v in stats.items() if v["launches"]}}
 
 
 def timed_accuracy(torch, outs, gold, nstored, P, B, warmup, steps):
@@ -749,14 +791,17 @@ def stored_traffic(kernel):
     or None if absent or measured on a different source of the kernel."""
     import hashlib
 
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
     rec = None
-    with open(TRAFFIC_FILE) as f:
-        for line in f:
-            if line.startswith("traffic_json:"):
-                rec = json.loads(line.split(":", 1)[1])
-    if not rec or rec.get("kernel") != kernel:
+    for path in (TRAFFIC_FILE, TRAFFIC_FILE_BLOCK):
+        if not os.path.exists(path):
+            continue
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_json:"):
+                    r = json.loads(line.split(":", 1)[1])
+                    if r.get("kernel") == kernel:
+                        rec = r
+    if not rec:
         return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:

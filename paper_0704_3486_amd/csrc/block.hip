@@ -52,8 +52,10 @@ __device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_
 
 // k-steps whose loads a lane issues together in the block products
 constexpr int kUnroll = 8;
-// fewest rows per wavefront of the dot pass
+// fewest rows per wavefront of the dot pass, and its tiles of 16 columns
+// per wavefront (sharing the block-vector loads)
 constexpr int kMinRowsPerWave = 128;
+constexpr int kDotTiles = 2;
 
 // the composite basis of one launch: column c < m is S[c], column c >= m of
 // slot r is V_r[c - m] (V_r = V + r vstride), all with leading dimension ldq
@@ -66,6 +68,20 @@ struct BlockGeo {
   int nb;
   int act[kMaxBatch];
 };
+
+// Workgroup i runs on XCD i % 8 (round-robin dispatch).  Map i to (tile b,
+// index z within the tile, z < per) so that the workgroups of one tile run on
+// one XCD, whose L2 then serves what they share (the rows of the Schur
+// columns for every slot, the slot's block vectors for every column group):
+// i = 8 (z + per q) + x -> b = 8 q + x.  A grid of 8 per ceil(ntiles / 8)
+// workgroups covers every (b, z) once; false for the padding (b >= ntiles).
+__device__ inline bool xcd_tile(int i, int per, int ntiles, int& b, int& z) {
+  const int x = i & 7, l = i >> 3;
+  z = l % per;
+  b = (l / per) * 8 + x;
+  return b < ntiles;
+}
+inline unsigned xcd_grid(int per, int ntiles) { return 8u * (unsigned)per * (unsigned)((ntiles + 7) / 8); }
 
 __device__ inline const double2* qcol(const double2* S, const double2* Vr, int m, size_t ldq, int c) {
   return c < m ? S + (size_t)c * ldq : Vr + (size_t)(c - m) * ldq;
@@ -104,72 +120,101 @@ struct BDot {
   size_t wstride;
   int ncol;
   int rpw;  // rows per wavefront, a multiple of 4
-  int ncg;  // column groups of 16
+  int ncg;  // column groups
+  int nch;  // row chunks
   double2* part;  // per slot [chunk][ncol][kBlockMax]
   size_t pstride;
 };
 
 __global__ void __launch_bounds__(256) bdot_kernel(BlockGeo g, BDot a) {
-  const int z = blockIdx.x % g.nb, rest = blockIdx.x / g.nb;
-  const int cg = rest % a.ncg, chunk = rest / a.ncg;
+  // tile = row chunk: all slots and column groups of a chunk on one XCD
+  int chunk, inner;
+  if (!xcd_tile(blockIdx.x, g.nb * a.ncg, a.nch, chunk, inner)) return;
+  const int z = inner % g.nb, cg = inner / g.nb;
   const int r = g.act[z];
   const double2* Vr = g.V + (size_t)r * g.vstride;
   const double2* Wr = a.W + (size_t)r * a.wstride;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int c = cg * 16 + li;
   const int v = li & 7;
   const bool imag = li >= 8;
   const int r0 = (chunk * 4 + wave) * a.rpw;
   const int r1 = min(r0 + a.rpw, g.N);
   const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
-  // a column past ncol reads column ncol - 1 (its sums are not written)
-  const int cc = min(c, a.ncol - 1);
-  const double2* qp = (cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk;
+  // kDotTiles tiles of 16 columns share the A fragment; a column past ncol
+  // reads column ncol - 1 (its sums are not written)
+  const double2* qp[kDotTiles];
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t) {
+    const int cc = min((cg * kDotTiles + t) * 16 + li, a.ncol - 1);
+    qp[t] = (cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk;
+  }
   // the A fragment: the lane's real or imaginary part, loaded as one double
   const bool vok = v < g.s;
   const double* wp = vok ? reinterpret_cast<const double*>(Wr + (size_t)v * g.ldq + r0 + lk) + (imag ? 1 : 0)
                          : reinterpret_cast<const double*>(&sgn_block_zero_entry);
   const int dw = vok ? 8 : 0;  // four rows, in doubles
-  v4d d1 = {0.0, 0.0, 0.0, 0.0}, d2 = {0.0, 0.0, 0.0, 0.0};
-  int it = 0;
-  for (; it + kUnroll <= nit; it += kUnroll) {
-    double2 qv[kUnroll];
-    double wv[kUnroll];
+  v4d d1[kDotTiles], d2[kDotTiles];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      qv[u] = qp[4 * u];
+  for (int t = 0; t < kDotTiles; ++t) {
+    d1[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    d2[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  constexpr int U = kUnroll / 2;
+  int it = 0;
+  for (; it + U <= nit; it += U) {
+    double2 qv[U][kDotTiles];
+    double wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int t = 0; t < kDotTiles; ++t) qv[u][t] = qp[t][4 * u];
       wv[u] = wp[dw * u];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      d1 = mfma(wv[u], qv[u].x, d1);
-      d2 = mfma(wv[u], qv[u].y, d2);
-    }
-    qp += 4 * kUnroll;
-    wp += kUnroll * dw;
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < kDotTiles; ++t) {
+        d1[t] = mfma(wv[u], qv[u][t].x, d1[t]);
+        d2[t] = mfma(wv[u], qv[u][t].y, d2[t]);
+      }
+#pragma unroll
+    for (int t = 0; t < kDotTiles; ++t) qp[t] += 4 * U;
+    wp += U * dw;
   }
   for (; it < nit; ++it) {
-    const double2 qv = *qp;
     const double wv = *wp;
-    d1 = mfma(wv, qv.x, d1);
-    d2 = mfma(wv, qv.y, d2);
-    qp += 4;
+#pragma unroll
+    for (int t = 0; t < kDotTiles; ++t) {
+      const double2 qv = *qp[t];
+      d1[t] = mfma(wv, qv.x, d1[t]);
+      d2[t] = mfma(wv, qv.y, d2[t]);
+      qp[t] += 4;
+    }
     wp += dw;
   }
-  // lane (j = li, lk): items t hold rows lk + 4 t of D: vectors lk, lk + 4
-  double2 c0 = make_double2(d1[0] + d2[2], d1[2] - d2[0]);
-  double2 c1 = make_double2(d1[1] + d2[3], d1[3] - d2[1]);
-  __shared__ double2 red[4][64][2];
-  red[wave][lane][0] = c0;
-  red[wave][lane][1] = c1;
+  // lane (j = li, lk): items of D hold rows lk + 4 t: vectors lk, lk + 4
+  __shared__ double2 red[4][64][2 * kDotTiles];
+  double2 cs[kDotTiles][2];
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t) {
+    cs[t][0] = make_double2(d1[t][0] + d2[t][2], d1[t][2] - d2[t][0]);
+    cs[t][1] = make_double2(d1[t][1] + d2[t][3], d1[t][3] - d2[t][1]);
+    red[wave][lane][2 * t] = cs[t][0];
+    red[wave][lane][2 * t + 1] = cs[t][1];
+  }
   __syncthreads();
-  if (wave == 0 && c < a.ncol) {
+  if (wave != 0) return;
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t) {
+    const int c = (cg * kDotTiles + t) * 16 + li;
+    if (c >= a.ncol) continue;
+    double2 c0 = cs[t][0], c1 = cs[t][1];
 #pragma unroll
     for (int w = 1; w < 4; ++w) {
-      c0 = cadd(c0, red[w][lane][0]);
-      c1 = cadd(c1, red[w][lane][1]);
+      c0 = cadd(c0, red[w][lane][2 * t]);
+      c1 = cadd(c1, red[w][lane][2 * t + 1]);
     }
     // vectors past s have zero fragments, so their sums are zero
     double2* o = a.part + (size_t)r * a.pstride + ((size_t)chunk * a.ncol + c) * kBlockMax;
@@ -346,11 +391,13 @@ struct BUpd {
   const double2* Rinv;  // per slot [kBlockMax][kBlockMax] upper triangular at rstride, or null
   size_t rstride;
   int nrowblk;  // workgroups on rows
+  int nhess;    // workgroups on the Hessenberg columns (with Rinv)
   BHess hess;
 };
 
 __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
-  const int z = blockIdx.x % g.nb, bid = blockIdx.x / g.nb;
+  int z, bid;
+  if (!xcd_tile(blockIdx.x, g.nb, a.nrowblk + a.nhess, bid, z)) return;
   const int rs = g.act[z];
   if (bid >= a.nrowblk) {
     hess_entry(g, a.hess, rs, (bid - a.nrowblk) * 256 + threadIdx.x);
@@ -683,25 +730,28 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
   int rpw = 0;
   const int nch = nchunks_for(N, rpw);
   auto dot = [&](double2* C, int ncol, const double2* C1, double2* Ct) {
-    const int ncg = (ncol + 15) / 16;
-    BDot d{b.W, b.wstride, ncol, rpw, ncg, b.part, b.pstride};
-    // Q (and W as columns) read once, W once per column group, partials written
-    const double bytes = (16.0 * N * ((double)ncol + sb) + 16.0 * nch * ncol * kBlockMax) * nb;
-    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, bdot_kernel, dim3(ncg * nch * nb), dim3(256), 0, s,
-                g, d);
+    const int ncg = (ncol + 16 * kDotTiles - 1) / (16 * kDotTiles);
+    BDot d{b.W, b.wstride, ncol, rpw, ncg, nch, b.part, b.pstride};
+    // the basis read once (S once for the launch, the slots' own columns and
+    // W as columns per slot), W once per slot, partials written
+    const double bytes =
+        16.0 * N * ((double)m + (double)nb * (ncol - m + sb)) + 16.0 * nch * ncol * kBlockMax * (double)nb;
+    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, bdot_kernel, dim3(xcd_grid(nb * ncg, nch)), dim3(256),
+                0, s, g, d);
     const int nent = ncol * kBlockMax, nblk = (nent + 31) / 32;
     BRed rd{b.part, b.pstride, nch, nent, nblk, C, C1, Ct, b.cstride, b.G, b.gstride};
     prof_launch(prof, K_BRED, (16.0 * (double)nch * nent + 16.0 * nent) * nb, 2.0 * nch * nent * nb, bred_kernel,
                 dim3(nblk * nb), dim3(256), 0, s, g, rd);
   };
   const int nrowblk = (N + 63) / 64;
-  const double upd_bytes = (16.0 * N * ((double)p + 2.0 * sb) + 16.0 * p * sb) * nb;
+  // the basis (S once for the launch), W read and written, the coefficients
+  const double upd_bytes = 16.0 * N * ((double)m + (double)nb * (p - m + 2.0 * sb)) + 16.0 * p * sb * (double)nb;
   // pass 1
   dot(b.C1, p, nullptr, nullptr);
   {
-    BUpd u{b.C1, b.cstride, b.W, b.wstride, b.W, b.wstride, nullptr, 0, nrowblk, BHess{}};
-    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3(nrowblk * nb), dim3(256), 0, s,
-                g, u);
+    BUpd u{b.C1, b.cstride, b.W, b.wstride, b.W, b.wstride, nullptr, 0, nrowblk, 0, BHess{}};
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3(xcd_grid(nb, nrowblk)),
+                dim3(256), 0, s, g, u);
   }
   // pass 2 with the Gram matrix of the projected block
   dot(b.C2, p + sb, b.C1, b.Ct);
@@ -714,10 +764,10 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
   {
     BHess h{e, b.Ct, b.P, b.cstride, sp.ncap, b.R, b.R + 2 * kBlockMax * kBlockMax, b.rstride, sp.H, sp.hstride,
             sp.ldh};
-    BUpd u{b.C2, b.cstride, b.W, b.wstride, const_cast<double2*>(sp.V) + (size_t)(p - m) * ldq, sp.vstride,
-           b.R + kBlockMax * kBlockMax, b.rstride, nrowblk, h};
     const int nh = ((p + sb) * kBlockMax + 255) / 256;
-    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3((nrowblk + nh) * nb),
+    BUpd u{b.C2, b.cstride, b.W, b.wstride, const_cast<double2*>(sp.V) + (size_t)(p - m) * ldq, sp.vstride,
+           b.R + kBlockMax * kBlockMax, b.rstride, nrowblk, nh, h};
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3(xcd_grid(nb, nrowblk + nh)),
                 dim3(256), 0, s, g, u);
   }
 }

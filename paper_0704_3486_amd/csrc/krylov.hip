@@ -653,15 +653,12 @@ static void check_args(const KrylovWork& w, const KrylovArgs& A) {
   }
 }
 
-// sum over the launch slots of the finished columns J, split into the FP64
-// Schur part and the Krylov part (for the algorithmic byte counts)
+// columns a launch reads, for the algorithmic byte counts: the FP64 Schur
+// part, shared by the slots (once), and the sum of the slots' Krylov parts
 static void col_sums(const KrylovArgs& A, double& sum_m, double& sum_k) {
-  sum_m = 0.0;
+  sum_m = A.m;
   sum_k = 0.0;
-  for (int z = 0; z < A.nb; ++z) {
-    sum_m += A.m;
-    sum_k += A.jv[z];
-  }
+  for (int z = 0; z < A.nb; ++z) sum_k += A.jv[z];
 }
 
 bool krylov_tune_valid(const KrylovTune& t) {
@@ -719,12 +716,14 @@ void krylov_dot(const KrylovWork& w, const KrylovArgs& Ain, bool with_z, hipStre
   // algorithmic bytes: Q, u, z read once; a, b written
   const size_t nwg = (size_t)w.nrt_dot * ngroups * A.nb;
   SGN_REQUIRE(nwg * 256 < (size_t(1) << 32), SGN_EINVAL, "krylov: dot grid too large");
-  prof_launch(prof, K_KDOT, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * (sm + sk),
-              16.0 * (double)A.N * (sm + sk), dot_kernel_for<VT>(A.tune.cpw), dim3((unsigned)nwg), dim3(256), 0, s,
+  // per-slot work counts S for every slot
+  const double cols = A.nb * (double)A.m + sk;
+  prof_launch(prof, K_KDOT, qbytes + A.nb * A.N * (16.0 + (with_z ? vb : 0.0)) + 32.0 * cols,
+              16.0 * (double)A.N * cols, dot_kernel_for<VT>(A.tune.cpw), dim3((unsigned)nwg), dim3(256), 0, s,
               A, with_z ? 1 : 0);
   // partial sums of every row tile read, a, b written
-  prof_launch(prof, K_KRED, 32.0 * (sm + sk) * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot,
-              4.0 * (sm + sk) * w.nrt_dot, kred_kernel, dim3(std::max(1, (Jmax + 31) / 32), 1, A.nb), dim3(256), 0, s,
+  prof_launch(prof, K_KRED, 32.0 * cols * (w.nrt_dot + 1.0) + 32.0 * A.nb * w.nrt_dot,
+              4.0 * cols * w.nrt_dot, kred_kernel, dim3(std::max(1, (Jmax + 31) / 32), 1, A.nb), dim3(256), 0, s,
               A);
 }
 
@@ -749,7 +748,8 @@ void krylov_update(const KrylovWork& w, const KrylovArgs& Ain, hipStream_t s, Pr
   const double qbytes = (double)A.N * (16.0 * sm + vb * sk);
   // read Q, u, z; write v_J, u' (+ its low-precision copy)
   const double vec = A.N * (16.0 + vb + vb + 16.0 + (A.ulonext ? vb : 0.0));
-  prof_launch(prof, K_KUPDATE, qbytes + A.nb * vec + 32.0 * (sm + sk), 16.0 * (double)A.N * (sm + sk),
+  const double cols = A.nb * (double)A.m + sk;  // per-slot work counts S for every slot
+  prof_launch(prof, K_KUPDATE, qbytes + A.nb * vec + 32.0 * cols, 16.0 * (double)A.N * cols,
               update_kernel_for<VT>(A.tune), dim3((unsigned)nwg), dim3(nthr), 0, s, A, nh);
 }
 
@@ -762,7 +762,7 @@ void krylov_combine(const KrylovWork& w, const KrylovArgs& Ain, const double2* c
   SGN_REQUIRE(ncol >= 0 && ncol <= w.ncol_cap, SGN_EINVAL, "krylov: ncol exceeds workspace");
   const double vb = (double)sizeof(VT);
   const int nm = std::min(ncol, A.m);
-  prof_launch(prof, K_KCOMBINE, A.nb * (double)A.N * (16.0 * nm + vb * (ncol - nm) + 16.0),
+  prof_launch(prof, K_KCOMBINE, (double)A.N * (16.0 * nm + A.nb * (vb * (ncol - nm) + 16.0)),
               A.nb * 8.0 * (double)A.N * ncol, kcombine_kernel<VT>, dim3((A.N + 63) / 64, 1, A.nb), dim3(kUThreads),
               0, s, A, coef, cstride, y, ystride, ncol);
 }

@@ -577,8 +577,10 @@ void wilson_apply_cheb_slots(const Lattice& lat, const double2* links, const dou
                              const SlotMap& map, hipStream_t s, Profiler* prof) {
   SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
   const int V = lat.V;
-  const double per_site = (48.0 + (prev ? 12.0 : 0.0)) * 16.0;
-  prof_launch(prof, K_WILSON, per_site * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<double2>,
+  // per site: the links (24 stored entries) once, per slot read v and
+  // prev, write w (12 each)
+  const double bytes = (24.0 + (24.0 + (prev ? 12.0 : 0.0)) * map.n) * 16.0 * V;
+  prof_launch(prof, K_WILSON, bytes, 1392.0 * V * map.n, wilson_hw_dir_kernel<double2>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
               (const double*)nullptr, (double2*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
               lat.emmu, map, site_order(lat), prev, pstride, ca, cb, 1);
@@ -621,9 +623,9 @@ void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t 
                         const SlotMap& map, hipStream_t s, Profiler* prof) {
   SGN_REQUIRE(map.n >= 1 && map.n <= kMaxBatch, SGN_EINVAL, "wilson: slot map must hold 1..64 slots");
   const int V = lat.V;
-  // per site and slot: read v (12), write w (12), the links (24 stored entries)
+  // per site: the links (24 stored entries) once, per slot read v (12) and write w (12)
   const double b = (double)sizeof(C);
-  prof_launch(prof, K_WILSON, 48.0 * b * V * map.n, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
+  prof_launch(prof, K_WILSON, (24.0 + 24.0 * map.n) * b * V, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
               (const double*)nullptr, (C*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
               lat.emmu, map, site_order(lat), (const C*)nullptr, (size_t)0, 1.0, 0.0, 0);
