@@ -53,7 +53,7 @@ HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_k
 # the same for the block (s-step) process
 HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
                      "block_factor": "bsmall_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
-BLOCK_STEPS = 8  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
+BLOCK_STEPS = 16  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
 BATCH = 8  # sources per batched apply call of each context in the timed region
 STENCIL_DIMS = (32, 32, 32, 32)
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE

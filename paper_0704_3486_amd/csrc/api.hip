@@ -1140,7 +1140,7 @@ int sgn_set_orthogonalization(sgn_ctx* c, int mode) {
 
 int sgn_set_block_steps(sgn_ctx* c, int sb) {
   return guarded(c, [&] {
-    SGN_REQUIRE(sb >= 0 && sb <= kBlockMax, SGN_EINVAL, "block steps must be 0 (off) or 1..8");
+    SGN_REQUIRE(sb >= 0 && sb <= kBlockMax, SGN_EINVAL, "block steps must be 0 (off) or 1..16");
     c->block_s = sb;
     return SGN_OK;
   });

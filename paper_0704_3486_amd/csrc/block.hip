@@ -25,9 +25,10 @@
 //
 // The two block products are tall and skinny (Q^dag W: p x N times N x s;
 // Q C: N x p times p x s), so they run on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64) with the real and imaginary parts of the s <= 8
-// block vectors side by side in the 16-wide dimension: two real products per
-// 16 x 4 fragment of Q give the complex result without cross-lane sums.
+// (v_mfma_f64_16x16x4f64) with the real and imaginary parts of 8 block
+// vectors side by side in the 16-wide dimension (s <= 16: two halves): two
+// real products per 16 x 4 fragment of Q and half give the complex result
+// without cross-lane sums.
 // Every sum has a fixed order, so results do not depend on the launch.
 //
 // A launch carries one or several right-hand sides of one field at the same
@@ -107,11 +108,18 @@ __global__ void bstart_kernel(BlockGeo g, const double2* __restrict__ u, size_t 
 }
 
 // ---------------------------------------------------------------------------
+// The s <= 16 block vectors fill the matrix instruction's 16-wide dimension
+// in halves of 8: half h holds vectors 8 h .. 8 h + 7, real parts in rows
+// (or columns) 0..7 and imaginary parts in 8..15.  kHalves halves cover
+// kBlockMax vectors; a launch uses nh = ceil(s / 8) of them.
+constexpr int kHalves = kBlockMax / 8;
+
 // dot pass: partial sums of conj(col_c) . W_v over row chunks.  Columns c < p
 // are the basis; with ncol = p + s, columns p + u are W_u (the Gram matrix).
-// Wavefront: 16 columns x rpw rows; lane (li, lk) = (lane % 16, lane / 16)
-// holds, per k-step of four rows, row lk of column li (B fragment) and of
-// block vector li % 8, real part for li < 8, imaginary for li >= 8 (A
+// Wavefront: 32 columns (two tiles of 16 sharing the A fragments) x rpw
+// rows; lane (li, lk) = (lane % 16, lane / 16) holds, per k-step of four
+// rows, row lk of column li of each tile (B fragment) and, per half, of
+// block vector 8 h + li % 8, real part for li < 8, imaginary for li >= 8 (A
 // fragment).  D1 = A Re(Q), D2 = A Im(Q) give
 //   Re C[j][v] = D1[v][j] + D2[v+8][j],  Im C[j][v] = D1[v+8][j] - D2[v][j].
 // Workgroup: four wavefronts on consecutive row ranges, summed in order.
@@ -139,87 +147,112 @@ __global__ void __launch_bounds__(256) bdot_kernel(BlockGeo g, BDot a) {
   const int li = lane & 15, lk = lane >> 4;
   const int v = li & 7;
   const bool imag = li >= 8;
+  const int nh = (g.s + 7) >> 3;  // halves in use (uniform)
   const int r0 = (chunk * 4 + wave) * a.rpw;
   const int r1 = min(r0 + a.rpw, g.N);
   const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
-  // kDotTiles tiles of 16 columns share the A fragment; a column past ncol
-  // reads column ncol - 1 (its sums are not written)
+  // a column past ncol reads column ncol - 1 (its sums are not written)
   const double2* qp[kDotTiles];
 #pragma unroll
   for (int t = 0; t < kDotTiles; ++t) {
     const int cc = min((cg * kDotTiles + t) * 16 + li, a.ncol - 1);
     qp[t] = (cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk;
   }
-  // the A fragment: the lane's real or imaginary part, loaded as one double
-  const bool vok = v < g.s;
-  const double* wp = vok ? reinterpret_cast<const double*>(Wr + (size_t)v * g.ldq + r0 + lk) + (imag ? 1 : 0)
-                         : reinterpret_cast<const double*>(&sgn_block_zero_entry);
-  const int dw = vok ? 8 : 0;  // four rows, in doubles
-  v4d d1[kDotTiles], d2[kDotTiles];
+  // the A fragments: the lane's real or imaginary part, loaded as one double
+  const double* wp[kHalves];
+  int dw[kHalves];
 #pragma unroll
-  for (int t = 0; t < kDotTiles; ++t) {
-    d1[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    d2[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < kHalves; ++h) {
+    const bool vok = 8 * h + v < g.s;
+    wp[h] = vok ? reinterpret_cast<const double*>(Wr + (size_t)(8 * h + v) * g.ldq + r0 + lk) + (imag ? 1 : 0)
+                : reinterpret_cast<const double*>(&sgn_block_zero_entry);
+    dw[h] = vok ? 8 : 0;  // four rows, in doubles
   }
+  v4d d1[kHalves][kDotTiles], d2[kHalves][kDotTiles];
+#pragma unroll
+  for (int h = 0; h < kHalves; ++h)
+#pragma unroll
+    for (int t = 0; t < kDotTiles; ++t) {
+      d1[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
+      d2[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
   constexpr int U = kUnroll / 2;
   int it = 0;
   for (; it + U <= nit; it += U) {
     double2 qv[U][kDotTiles];
-    double wv[U];
+    double wv[U][kHalves];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
       for (int t = 0; t < kDotTiles; ++t) qv[u][t] = qp[t][4 * u];
-      wv[u] = wp[dw * u];
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h) wv[u][h] = wp[h][dw[h] * u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int t = 0; t < kDotTiles; ++t) {
-        d1[t] = mfma(wv[u], qv[u][t].x, d1[t]);
-        d2[t] = mfma(wv[u], qv[u][t].y, d2[t]);
-      }
+      for (int h = 0; h < kHalves; ++h)
+        if (h < nh)
+#pragma unroll
+          for (int t = 0; t < kDotTiles; ++t) {
+            d1[h][t] = mfma(wv[u][h], qv[u][t].x, d1[h][t]);
+            d2[h][t] = mfma(wv[u][h], qv[u][t].y, d2[h][t]);
+          }
 #pragma unroll
     for (int t = 0; t < kDotTiles; ++t) qp[t] += 4 * U;
-    wp += U * dw;
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) wp[h] += U * dw[h];
   }
   for (; it < nit; ++it) {
-    const double wv = *wp;
+    double wv[kHalves];
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) wv[h] = *wp[h];
 #pragma unroll
     for (int t = 0; t < kDotTiles; ++t) {
       const double2 qv = *qp[t];
-      d1[t] = mfma(wv, qv.x, d1[t]);
-      d2[t] = mfma(wv, qv.y, d2[t]);
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h)
+        if (h < nh) {
+          d1[h][t] = mfma(wv[h], qv.x, d1[h][t]);
+          d2[h][t] = mfma(wv[h], qv.y, d2[h][t]);
+        }
       qp[t] += 4;
     }
-    wp += dw;
-  }
-  // lane (j = li, lk): items of D hold rows lk + 4 t: vectors lk, lk + 4
-  __shared__ double2 red[4][64][2 * kDotTiles];
-  double2 cs[kDotTiles][2];
 #pragma unroll
-  for (int t = 0; t < kDotTiles; ++t) {
-    cs[t][0] = make_double2(d1[t][0] + d2[t][2], d1[t][2] - d2[t][0]);
-    cs[t][1] = make_double2(d1[t][1] + d2[t][3], d1[t][3] - d2[t][1]);
-    red[wave][lane][2 * t] = cs[t][0];
-    red[wave][lane][2 * t + 1] = cs[t][1];
+    for (int h = 0; h < kHalves; ++h) wp[h] += dw[h];
   }
+  // lane (j = li, lk): items of half h's D hold rows lk + 4 t: vectors
+  // 8 h + lk and 8 h + lk + 4
+  __shared__ double2 red[4][64][2 * kDotTiles * kHalves];
+  double2 cs[kDotTiles][kHalves][2];
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t)
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      cs[t][h][0] = make_double2(d1[h][t][0] + d2[h][t][2], d1[h][t][2] - d2[h][t][0]);
+      cs[t][h][1] = make_double2(d1[h][t][1] + d2[h][t][3], d1[h][t][3] - d2[h][t][1]);
+      red[wave][lane][(t * kHalves + h) * 2] = cs[t][h][0];
+      red[wave][lane][(t * kHalves + h) * 2 + 1] = cs[t][h][1];
+    }
   __syncthreads();
   if (wave != 0) return;
 #pragma unroll
   for (int t = 0; t < kDotTiles; ++t) {
     const int c = (cg * kDotTiles + t) * 16 + li;
     if (c >= a.ncol) continue;
-    double2 c0 = cs[t][0], c1 = cs[t][1];
-#pragma unroll
-    for (int w = 1; w < 4; ++w) {
-      c0 = cadd(c0, red[w][lane][2 * t]);
-      c1 = cadd(c1, red[w][lane][2 * t + 1]);
-    }
-    // vectors past s have zero fragments, so their sums are zero
     double2* o = a.part + (size_t)r * a.pstride + ((size_t)chunk * a.ncol + c) * kBlockMax;
-    o[lk] = c0;
-    o[lk + 4] = c1;
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      double2 c0 = cs[t][h][0], c1 = cs[t][h][1];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        c0 = cadd(c0, red[w][lane][(t * kHalves + h) * 2]);
+        c1 = cadd(c1, red[w][lane][(t * kHalves + h) * 2 + 1]);
+      }
+      // vectors past s have zero fragments, so their sums are zero
+      o[8 * h + lk] = c0;
+      o[8 * h + lk + 4] = c1;
+    }
   }
 }
 
@@ -281,45 +314,58 @@ __global__ void __launch_bounds__(256) bred_kernel(BlockGeo g, BRed a) {
 // times the coefficients C[c][v] of columns c < ncol, for the k-steps (four
 // columns) k0, k0 + dk, ... .  Lane (li, lk) holds row li of column
 // 4 ks + lk (A fragment) and that column's coefficient for block vector
-// li % 8 (B fragment), so that
-//   D += Re(Q) [Re C | Im C] + Im(Q) [-Im C | Re C]
-// is [Re | Im] of (Q C) for the 16 rows and 8 vectors (rows lk + 4 t in item
-// t, vector li % 8, real part for li < 8).  Columns past ncol read the zero
-// entry.
-__device__ inline v4d qc_steps(const double2* __restrict__ S, const double2* __restrict__ Vr, int m, size_t ldq,
-                               int row, int ncol, const double2* __restrict__ C, int v, bool imag, bool vok, int lk,
-                               int k0, int dk, v4d d) {
+// 8 h + li % 8 of each half h (B fragments), so that
+//   D[h] += Re(Q) [Re C | Im C] + Im(Q) [-Im C | Re C]
+// is [Re | Im] of (Q C) for the 16 rows and half h's 8 vectors (rows lk + 4 t
+// in item t, vector 8 h + li % 8, real part for li < 8).  Columns past ncol
+// read the zero entry; halves h >= nh are skipped.
+__device__ inline void qc_steps(const double2* __restrict__ S, const double2* __restrict__ Vr, int m, size_t ldq,
+                                int row, int ncol, const double2* __restrict__ C, int v, bool imag, int s, int lk,
+                                int k0, int dk, v4d (&d)[kHalves]) {
   const double2* zero = &sgn_block_zero_entry;
   const int nk = (ncol + 3) >> 2;
-  int ks = k0;
-  for (; ks + (kUnroll - 1) * dk < nk; ks += kUnroll * dk) {
-    double2 qv[kUnroll], cv[kUnroll];
+  const int nh = (s + 7) >> 3;
+  bool vok[kHalves];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+  for (int h = 0; h < kHalves; ++h) vok[h] = 8 * h + v < s;
+  int ks = k0;
+  constexpr int U = kUnroll / kHalves;
+  for (; ks + (U - 1) * dk < nk; ks += U * dk) {
+    double2 qv[U], cv[U][kHalves];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
       const int col = 4 * (ks + u * dk) + lk;
       const bool ok = col < ncol;
       qv[u] = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
-      cv[u] = *((ok & vok) ? C + (size_t)col * kBlockMax + v : zero);
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h)
+        cv[u][h] = *((ok & vok[h]) ? C + (size_t)col * kBlockMax + 8 * h + v : zero);
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double b1 = imag ? cv[u].y : cv[u].x;
-      const double b2 = imag ? cv[u].x : -cv[u].y;
-      d = mfma(qv[u].x, b1, d);
-      d = mfma(qv[u].y, b2, d);
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h)
+        if (h < nh) {
+          const double b1 = imag ? cv[u][h].y : cv[u][h].x;
+          const double b2 = imag ? cv[u][h].x : -cv[u][h].y;
+          d[h] = mfma(qv[u].x, b1, d[h]);
+          d[h] = mfma(qv[u].y, b2, d[h]);
+        }
   }
   for (; ks < nk; ks += dk) {
     const int col = 4 * ks + lk;
     const bool ok = col < ncol;
     const double2 qv = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
-    const double2 cv = *((ok & vok) ? C + (size_t)col * kBlockMax + v : zero);
-    const double b1 = imag ? cv.y : cv.x;
-    const double b2 = imag ? cv.x : -cv.y;
-    d = mfma(qv.x, b1, d);
-    d = mfma(qv.y, b2, d);
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h)
+      if (h < nh) {
+        const double2 cv = *((ok & vok[h]) ? C + (size_t)col * kBlockMax + 8 * h + v : zero);
+        const double b1 = imag ? cv.y : cv.x;
+        const double b2 = imag ? cv.x : -cv.y;
+        d[h] = mfma(qv.x, b1, d[h]);
+        d[h] = mfma(qv.y, b2, d[h]);
+      }
   }
-  return d;
 }
 
 // complex entries (Re in lane li < 8, Im from lane li + 8) of a Q C tile
@@ -380,7 +426,8 @@ __device__ void hess_entry(const BlockGeo& g, const BHess& h, int r_slot, int id
 // ---------------------------------------------------------------------------
 // update pass: Wout = (Win - Q C) [Rinv].  Wavefront: 16 rows x all p
 // columns.  With Rinv (the second pass) the workgroups past the rows also
-// write the block's Hessenberg columns (hess).  Workgroup id = z + nb b.
+// write the block's Hessenberg columns (hess).  Tile = row block; the slots
+// of a row block run on one XCD.
 struct BUpd {
   const double2* C;
   size_t cstride;
@@ -414,19 +461,25 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   const bool active = r0 < g.N;  // wavefront-uniform
   const int row = min(r0 + li, g.N - 1);
   const int v = li & 7;
-  const bool vok = v < g.s;
-  v4d d = {0.0, 0.0, 0.0, 0.0};
-  if (active) d = qc_steps(g.S, Vr, g.m, g.ldq, row, g.p, Cr, v, li >= 8, vok, lk, 0, 1, d);
-  double2 res[4];
-  qc_pairs(d, res);
-  if (!a.Rinv) {
-    if (active && li < 8 && vok)
+  v4d d[kHalves];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int rr = r0 + lk + 4 * t;
-        if (rr < g.N) {
-          const size_t o = (size_t)v * g.ldq + rr;
-          Wout[o] = csub(Win[o], res[t]);
+  for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (active) qc_steps(g.S, Vr, g.m, g.ldq, row, g.p, Cr, v, li >= 8, g.s, lk, 0, 1, d);
+  double2 res[kHalves][4];
+#pragma unroll
+  for (int h = 0; h < kHalves; ++h) qc_pairs(d[h], res[h]);
+  if (!a.Rinv) {
+    if (active && li < 8)
+#pragma unroll
+      for (int h = 0; h < kHalves; ++h) {
+        if (8 * h + v >= g.s) continue;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int rr = r0 + lk + 4 * t;
+          if (rr < g.N) {
+            const size_t o = (size_t)(8 * h + v) * g.ldq + rr;
+            Wout[o] = csub(Win[o], res[h][t]);
+          }
         }
       }
     return;
@@ -436,18 +489,21 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   __shared__ double2 tile[4][16][kBlockMax];
   if (li < 8)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int rr = r0 + lk + 4 * t;
-      double2 val = make_double2(0.0, 0.0);
-      if (active && vok && rr < g.N) val = csub(Win[(size_t)v * g.ldq + rr], res[t]);
-      tile[wave][lk + 4 * t][v] = val;
-    }
+    for (int h = 0; h < kHalves; ++h)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int rr = r0 + lk + 4 * t, vv = 8 * h + v;
+        double2 val = make_double2(0.0, 0.0);
+        if (active && vv < g.s && rr < g.N) val = csub(Win[(size_t)vv * g.ldq + rr], res[h][t]);
+        tile[wave][lk + 4 * t][vv] = val;
+      }
   __syncthreads();
   if (!active) return;
+  constexpr int kOut = 16 * kBlockMax / 64;  // outputs per lane
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int idx = lane + 64 * h;
-    const int rl = idx >> 3, vv = idx & 7;
+  for (int q = 0; q < kOut; ++q) {
+    const int idx = lane + 64 * q;
+    const int rl = idx / kBlockMax, vv = idx % kBlockMax;
     double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < kBlockMax; ++u) acc = cfma(tile[wave][rl][u], Ri[u * kBlockMax + vv], acc);
@@ -462,11 +518,14 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
 // forms R^-1 and Rb^-1 (Rb = [1, Ct[p-1][0 .. s-2]; 0, R[0 .. s-2][0 .. s-2]]);
 // it raises the slot's flag when the block is not numerically of full rank
 // (a pivot below 1e-12 of the block's size, or below 1e-7 of the largest
-// pivot) or not finite.  The other workgroups form P = H_{p x (p-1)} Ct for
-// 16 rows each (the four wavefronts take every fourth k-step, summed in
-// order), from the first column where a row of the tile can be nonzero (H is
-// upper Hessenberg below the T block, T upper triangular).  Workgroup id =
-// z + nb t: t = 0 factors, t >= 1 is row tile t - 1.
+// pivot) or not finite.  C2^dag C2 and the diagonal of Ct^dag Ct (the block
+// vectors' size before projection) run on the matrix cores, the four
+// wavefronts taking every fourth k-step.  The other workgroups form
+// P = H_{p x (p-1)} Ct for 16 rows each (the four wavefronts take every
+// fourth k-step, summed in order), from the first column where a row of the
+// tile can be nonzero (H is upper Hessenberg below the T block, T upper
+// triangular).  Workgroup id = z + nb t: t = 0 factors, t >= 1 is row tile
+// t - 1.
 struct BSmall {
   const double2* C2;
   const double2* Ct;
@@ -484,62 +543,76 @@ struct BSmall {
 };
 
 __device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
-  const int tid = threadIdx.x;
+  constexpr int B = kBlockMax;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int s = gg.s, p = gg.p;
   const double2* C2 = a.C2 + (size_t)rs * a.cstride;
   const double2* Ct = a.Ct + (size_t)rs * a.cstride;
   const double2* G = a.G + (size_t)rs * a.gstride;
   double2* Rout = a.R + (size_t)rs * a.rstride;
-  __shared__ double2 red[4][64];
+  __shared__ v4d red[4][4][64];
   __shared__ double redn[4][64];
-  __shared__ double2 g[kBlockMax][kBlockMax], R[kBlockMax][kBlockMax], Ri[kBlockMax][kBlockMax],
-      Rb[kBlockMax][kBlockMax], Rbi[kBlockMax][kBlockMax];
-  __shared__ double piv[kBlockMax], ref_s;
+  __shared__ double2 g[B][B], R[B][B], Ri[B][B], Rb[B][B], Rbi[B][B];
+  __shared__ double piv[B], ref_s;
   __shared__ int bad;
-  const int ent = tid & 63, q = tid >> 6, u = ent >> 3, v = ent & 7;
+  // C2^dag C2 (16 x 16 complex) on the matrix cores: A = C2^dag (row u, k = c),
+  // B = C2 (k = c, column v); lane (li, lk) loads C2[c][li] for c = 4 ks + lk.
+  // Re += Re A Re B + Im A Im B... with A = conj(C2)^T:
+  //   Re(conj(a) b) = ar br + ai bi,  Im(conj(a) b) = ar bi - ai br
   {
-    // G'' entries (u, v) by four threads (columns c = q, q + 4, ...), and
-    // |Ct[:, v]|^2 (the block vectors' size before projection)
-    double2 acc = make_double2(0.0, 0.0);
+    const int li = lane & 15, lk = lane >> 4;
+    v4d dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
     double nn = 0.0;
-    if (u < s && v < s)
-      for (int cb = q; cb < p; cb += 32) {
-        // eight columns' loads in flight (clamped), then their sums in order
-        double2 x[8], y[8], w[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const size_t c = (size_t)min(cb + 4 * t, p - 1) * kBlockMax;
-          x[t] = C2[c + u];
-          y[t] = C2[c + v];
-          w[t] = Ct[c + v];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if (cb + 4 * t < p) {
-            acc = cfmac(x[t], y[t], acc);
-            nn += cabs2(w[t]);
-          }
-      }
-    red[q][ent] = acc;
-    redn[q][ent] = nn;
+    const double2* zero = &sgn_block_zero_entry;
+    const int nk = (p + 3) >> 2;
+    for (int ks = wave; ks < nk; ks += 4) {
+      const int c = 4 * ks + lk;
+      const bool ok = c < p && li < s;
+      const double2 x = *(ok ? C2 + (size_t)c * B + li : zero);
+      const double2 y = *(ok ? Ct + (size_t)c * B + li : zero);
+      dre = mfma(x.x, x.x, dre);
+      dre = mfma(x.y, x.y, dre);
+      dim = mfma(x.x, x.y, dim);
+      dim = mfma(-x.y, x.x, dim);
+      nn += cabs2(y);
+    }
+    red[wave][0][lane] = dre;
+    red[wave][1][lane] = dim;
+    redn[wave][lane] = nn;
   }
-  if (tid < kBlockMax * kBlockMax) {
+  if (tid < B * B) {
+    const int u = tid / B, v = tid % B;
     R[u][v] = make_double2(0.0, 0.0);
     Ri[u][v] = make_double2(0.0, 0.0);
     Rb[u][v] = make_double2(0.0, 0.0);
     Rbi[u][v] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  if (tid < kBlockMax * kBlockMax) {
-    const double2 sub = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
-    g[u][v] = (u < s && v < s) ? csub(G[u * kBlockMax + v], sub) : make_double2(0.0, 0.0);
+  if (tid < 64) {
+    // D[u][v] sits in lane v + 16 (u % 4), item u / 4
+    const int v = tid & 15, u0 = tid >> 4;
+    v4d sre = red[0][0][tid], sim = red[0][1][tid];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      sre += red[w][0][tid];
+      sim += red[w][1][tid];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int u = u0 + 4 * t;
+      g[u][v] = (u < s && v < s) ? csub(G[u * B + v], make_double2(sre[t], sim[t])) : make_double2(0.0, 0.0);
+    }
   }
   if (tid == 0) {
     bad = 0;
+    // |Ct[:, v]|^2 summed over the lanes holding v (li = v) and the wavefronts
     double rf = 0.0;
-    for (int w = 0; w < s; ++w) {
-      const int e = w * kBlockMax + w;
-      rf = fmax(rf, G[e].x + redn[0][e] + redn[1][e] + redn[2][e] + redn[3][e]);
+    for (int v = 0; v < s; ++v) {
+      double t = 0.0;
+      for (int w = 0; w < 4; ++w)
+        for (int q = 0; q < 4; ++q) t += redn[w][v + 16 * q];
+      rf = fmax(rf, G[v * B + v].x + t);
     }
     ref_s = rf;
   }
@@ -555,25 +628,29 @@ __device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
       piv[j] = sqrt(dj);
     }
     __syncthreads();
-    if (tid < kBlockMax && tid >= j && tid < s)
-      R[j][tid] = tid == j ? make_double2(piv[j], 0.0) : cscale(g[j][tid], 1.0 / piv[j]);
+    if (tid < B && tid >= j && tid < s) R[j][tid] = tid == j ? make_double2(piv[j], 0.0) : cscale(g[j][tid], 1.0 / piv[j]);
     __syncthreads();
-    if (tid < kBlockMax * kBlockMax && u > j && v > j && u < s && v < s)
-      g[u][v] = csub(g[u][v], cmulc(R[j][u], R[j][v]));
+    if (tid < B * B) {
+      const int u = tid / B, v = tid % B;
+      if (u > j && v > j && u < s && v < s) g[u][v] = csub(g[u][v], cmulc(R[j][u], R[j][v]));
+    }
     __syncthreads();
   }
   // Rb from R and the last basis column's coefficients
-  if (tid < kBlockMax * kBlockMax && u < s && v < s) {
-    if (u == 0)
-      Rb[0][v] = v == 0 ? make_double2(1.0, 0.0) : Ct[(size_t)(p - 1) * kBlockMax + v - 1];
-    else if (v >= u)
-      Rb[u][v] = R[u - 1][v - 1];
+  if (tid < B * B) {
+    const int u = tid / B, v = tid % B;
+    if (u < s && v < s) {
+      if (u == 0)
+        Rb[0][v] = v == 0 ? make_double2(1.0, 0.0) : Ct[(size_t)(p - 1) * B + v - 1];
+      else if (v >= u)
+        Rb[u][v] = R[u - 1][v - 1];
+    }
   }
   __syncthreads();
   // inverses of the two upper triangular factors, one column per thread
-  if (tid < 2 * kBlockMax) {
-    const int col = tid & 7;
-    const bool second = tid >= kBlockMax;
+  if (tid < 2 * B) {
+    const int col = tid % B;
+    const bool second = tid >= B;
     auto& M = second ? Rb : R;
     auto& X = second ? Rbi : Ri;
     if (col < s) {
@@ -586,10 +663,11 @@ __device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
     }
   }
   __syncthreads();
-  if (tid < kBlockMax * kBlockMax) {
+  if (tid < B * B) {
+    const int u = tid / B, v = tid % B;
     Rout[tid] = R[u][v];
-    Rout[kBlockMax * kBlockMax + tid] = Ri[u][v];
-    Rout[2 * kBlockMax * kBlockMax + tid] = Rbi[u][v];
+    Rout[B * B + tid] = Ri[u][v];
+    Rout[2 * B * B + tid] = Rbi[u][v];
   }
   if (tid == 0) {
     double dmin = HUGE_VAL, dmax = 0.0;
@@ -619,24 +697,31 @@ __global__ void __launch_bounds__(256) bsmall_kernel(BlockGeo g, BSmall a) {
   const int c0 = r0 < g.m ? r0 : max(g.m, r0 - 1);  // columns below c0 are zero in these rows
   const double2* H = a.H + (size_t)rs * a.hstride;
   const double2* Ct = a.Ct + (size_t)rs * a.cstride;
-  v4d d = {0.0, 0.0, 0.0, 0.0};
-  d = qc_steps(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, v, li >= 8, v < g.s, lk, (c0 >> 2) + wave, 4, d);
-  __shared__ v4d red[4][64];
-  red[wave][lane] = d;
+  v4d d[kHalves];
+#pragma unroll
+  for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
+  // only the columns 0 .. s-2 of Ct enter P
+  qc_steps(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, v, li >= 8, g.s - 1, lk, (c0 >> 2) + wave, 4, d);
+  __shared__ v4d red[4][kHalves][64];
+#pragma unroll
+  for (int h = 0; h < kHalves; ++h) red[wave][h][lane] = d[h];
   __syncthreads();
   if (wave != 0) return;
-  d = red[0][lane];
-#pragma unroll
-  for (int w = 1; w < 4; ++w) d += red[w][lane];
-  double2 res[4];
-  qc_pairs(d, res);
   double2* P = a.P + (size_t)rs * a.cstride;
-  if (li < 8 && v < g.s)
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const int rr = r0 + lk + 4 * tt;
-      if (rr < p) P[(size_t)v * a.ldp + rr] = res[tt];
-    }
+  for (int h = 0; h < kHalves; ++h) {
+    v4d dh = red[0][h][lane];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) dh += red[w][h][lane];
+    double2 res[4];
+    qc_pairs(dh, res);
+    if (li < 8 && 8 * h + v < g.s - 1)
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        const int rr = r0 + lk + 4 * tt;
+        if (rr < p) P[(size_t)(8 * h + v) * a.ldp + rr] = res[tt];
+      }
+  }
 }
 
 int nchunks_for(int N, int& rpw) {

@@ -207,7 +207,7 @@ void wilson_links_f32(const double2* links, float2* links32, int V, hipStream_t 
 
 // workspace of the block (s-step) Arnoldi process (block.hip), per slot at
 // the given strides (nslots right-hand sides)
-constexpr int kBlockMax = 8;  // largest block
+constexpr int kBlockMax = 16;  // largest block
 struct BlockWork {
   int ncap = 0;               // basis columns the buffers serve
   int nslots = 0;

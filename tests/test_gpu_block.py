@@ -53,7 +53,7 @@ def small_problem():
     return dims, mu, links, A, Ad, S, T, x
 
 
-@pytest.mark.parametrize("s", [1, 3, 8])
+@pytest.mark.parametrize("s", [1, 3, 8, 11, 16])
 @pytest.mark.parametrize("m", [0, 12])
 @pytest.mark.parametrize("k", [8, 43, 100])
 def test_block_fixed_k_matches_oracle_arnoldi(env, small_problem, s, m, k):
@@ -85,9 +85,10 @@ def test_block_fixed_k_matches_oracle_arnoldi(env, small_problem, s, m, k):
         sg.sgn_destroy(ctx)
 
 
+@pytest.mark.parametrize("sb", [8, 16])
 @pytest.mark.parametrize("mu", [0.0, 0.2, 0.5])
-def test_block_6x6_sources_at_tol_1e10_vs_exact(env, mu):
-    # the headline configuration with blocks of eight steps: every source
+def test_block_6x6_sources_at_tol_1e10_vs_exact(env, mu, sb):
+    # the headline configuration with blocks of sb steps: every source
     # within 1e-10 of the exact result, checkpoints on whole blocks
     sg, torch = env
     dims = (6, 6, 6, 6)
@@ -99,7 +100,7 @@ def test_block_6x6_sources_at_tol_1e10_vs_exact(env, mu):
     ctx = sg.sgn_create(links, dims, mu, M_W)
     try:
         assert sg.sgn_deflate(ctx, 20) == sg.SGN_OK
-        sg.sgn_set_block_steps(ctx, 8)
+        sg.sgn_set_block_steps(ctx, sb)
         y = torch.empty(Y.shape[1], dtype=torch.complex128, device="cuda")
         errs = []
         for r in range(Y.shape[0]):
@@ -108,8 +109,8 @@ def test_block_6x6_sources_at_tol_1e10_vs_exact(env, mu):
             info = sg.sgn_last_info(ctx)
             e = _rel(y.cpu().numpy(), Y[r])
             errs.append(e)
-            print(mu, r, info["k_used"], info["n_checkpoints"], f"{e:.3e}", flush=True)
-            assert st == sg.SGN_OK and info["k_used"] % 8 == 0
+            print(mu, sb, r, info["k_used"], info["n_checkpoints"], f"{e:.3e}", flush=True)
+            assert st == sg.SGN_OK and info["k_used"] % sb == 0
         assert max(errs) < 1e-10, errs
     finally:
         sg.sgn_destroy(ctx)
@@ -173,7 +174,7 @@ def test_block_edge_cases(env, small_problem):
     N = x.size
     ctx = sg.sgn_create(links, dims, mu, M_W)
     try:
-        for bad in (-1, 9):
+        for bad in (-1, 17):
             with pytest.raises(sg.SgnError) as e:
                 sg.sgn_set_block_steps(ctx, bad)
             assert e.value.status == sg.SGN_EINVAL
