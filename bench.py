@@ -51,8 +51,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_kernel<double2>",
                "krylov_reduce": "kred_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
 # the same for the block (s-step) process
-HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
-                     "block_factor": "bsmall_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
+HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel<false>", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
+                     "block_factor": "bsmall_kernel<false>", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
 BLOCK_STEPS = 16  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
 BATCH = 8  # sources per batched apply call of each context in the timed region
 STENCIL_DIMS = (32, 32, 32, 32)
@@ -356,7 +356,12 @@ def main():
         sg.sgn_set_profiling(c, False)
     kern = kernel_table(kstats)
     log("kernels: " + json.dumps(kern))
-    kmap = HBM_KERNELS_BLOCK if args.block_steps else HBM_KERNELS
+    kmap = HBM_KERNELS
+    if args.block_steps:
+        kmap = dict(HBM_KERNELS_BLOCK)
+        if args.block_steps > 8:  # the three-multiplication forms of the sweeps
+            kmap.update({"block_dot": "bdot3_kernel", "block_update": "bupdate_kernel<true>",
+                         "block_factor": "bsmall_kernel<true>"})
     hbm_kernels = {k: v for k, v in kern.items() if k in kmap}
     dom = max(hbm_kernels, key=lambda k: hbm_kernels[k]["total_ms"]) if hbm_kernels else None
     roofline = None

@@ -256,6 +256,106 @@ __global__ void __launch_bounds__(256) bdot_kernel(BlockGeo g, BDot a) {
   }
 }
 
+// The dot pass for s > 8 with three real products per fragment (the
+// Gauss form of the complex product): lane (li, lk) holds row lk of block
+// vector li (A fragment, both parts) and of column li of each tile (B
+// fragment);
+//   T1 = Wr^T Re(Q),  T2 = Wi^T Im(Q),  T3 = (Wr + Wi)^T (Re(Q) - Im(Q)),
+//   Re C = T1 + T2,  Im C = T3 - T1 + T2,
+// a quarter fewer matrix-core instructions than two halves of 8.
+__global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
+  int chunk, inner;
+  if (!xcd_tile(blockIdx.x, g.nb * a.ncg, a.nch, chunk, inner)) return;
+  const int z = inner % g.nb, cg = inner / g.nb;
+  const int r = g.act[z];
+  const double2* Vr = g.V + (size_t)r * g.vstride;
+  const double2* Wr = a.W + (size_t)r * a.wstride;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = (chunk * 4 + wave) * a.rpw;
+  const int r1 = min(r0 + a.rpw, g.N);
+  const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
+  const double2* qp[kDotTiles];
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t) {
+    const int cc = min((cg * kDotTiles + t) * 16 + li, a.ncol - 1);
+    qp[t] = (cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk;
+  }
+  const bool vok = li < g.s;
+  const double2* wp = vok ? Wr + (size_t)li * g.ldq + r0 + lk : &sgn_block_zero_entry;
+  const int dw = vok ? 4 : 0;
+  v4d t1[kDotTiles], t2[kDotTiles], t3[kDotTiles];
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t) {
+    t1[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    t2[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    t3[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  constexpr int U = kUnroll / 2;
+  int it = 0;
+  for (; it + U <= nit; it += U) {
+    double2 qv[U][kDotTiles], wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int t = 0; t < kDotTiles; ++t) qv[u][t] = qp[t][4 * u];
+      wv[u] = wp[dw * u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double ws = wv[u].x + wv[u].y;
+#pragma unroll
+      for (int t = 0; t < kDotTiles; ++t) {
+        t1[t] = mfma(wv[u].x, qv[u][t].x, t1[t]);
+        t2[t] = mfma(wv[u].y, qv[u][t].y, t2[t]);
+        t3[t] = mfma(ws, qv[u][t].x - qv[u][t].y, t3[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kDotTiles; ++t) qp[t] += 4 * U;
+    wp += U * dw;
+  }
+  for (; it < nit; ++it) {
+    const double2 wv = *wp;
+    const double ws = wv.x + wv.y;
+#pragma unroll
+    for (int t = 0; t < kDotTiles; ++t) {
+      const double2 qv = *qp[t];
+      t1[t] = mfma(wv.x, qv.x, t1[t]);
+      t2[t] = mfma(wv.y, qv.y, t2[t]);
+      t3[t] = mfma(ws, qv.x - qv.y, t3[t]);
+      qp[t] += 4;
+    }
+    wp += dw;
+  }
+  // lane (j = li, lk): item q holds vector lk + 4 q of column j
+  __shared__ double2 red[4][64][4 * kDotTiles];
+  double2 cs[kDotTiles][4];
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cs[t][q] = make_double2(t1[t][q] + t2[t][q], t3[t][q] - t1[t][q] + t2[t][q]);
+      red[wave][lane][4 * t + q] = cs[t][q];
+    }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int t = 0; t < kDotTiles; ++t) {
+    const int c = (cg * kDotTiles + t) * 16 + li;
+    if (c >= a.ncol) continue;
+    double2* o = a.part + (size_t)r * a.pstride + ((size_t)chunk * a.ncol + c) * kBlockMax;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2 acc = cs[t][q];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) acc = cadd(acc, red[w][lane][4 * t + q]);
+      o[lk + 4 * q] = acc;  // zero for vectors past s
+    }
+  }
+}
+
 // sum of the dot partials over chunks in a fixed order: 32 entries per
 // workgroup, 8 threads per entry (every 8th chunk), then the 8 in order.
 // Entry e = c * kBlockMax + v; c < p goes to C[c][v] (and C1[c][v] + C[c][v]
@@ -368,6 +468,47 @@ __device__ inline void qc_steps(const double2* __restrict__ S, const double2* __
   }
 }
 
+// Q C for s > 8 with three real products per fragment (the Gauss form):
+// lane (li, lk) holds row li of column 4 ks + lk (A fragment) and that
+// column's coefficient for block vector li (B fragment);
+//   T1 = Re(Q) Re(C),  T2 = Im(Q) Im(C),  T3 = (Re Q + Im Q)(Re C + Im C),
+//   Re(Q C) = T1 - T2,  Im(Q C) = T3 - T1 - T2
+// for the 16 rows (rows lk + 4 t in item t) and vector li.
+__device__ inline void qc_steps3(const double2* __restrict__ S, const double2* __restrict__ Vr, int m, size_t ldq,
+                                 int row, int ncol, const double2* __restrict__ C, int s, int li, int lk, int k0,
+                                 int dk, v4d& t1, v4d& t2, v4d& t3) {
+  const double2* zero = &sgn_block_zero_entry;
+  const int nk = (ncol + 3) >> 2;
+  const bool vok = li < s;
+  int ks = k0;
+  constexpr int U = kUnroll / 2;
+  for (; ks + (U - 1) * dk < nk; ks += U * dk) {
+    double2 qv[U], cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = 4 * (ks + u * dk) + lk;
+      const bool ok = col < ncol;
+      qv[u] = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
+      cv[u] = *((ok & vok) ? C + (size_t)col * kBlockMax + li : zero);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      t1 = mfma(qv[u].x, cv[u].x, t1);
+      t2 = mfma(qv[u].y, cv[u].y, t2);
+      t3 = mfma(qv[u].x + qv[u].y, cv[u].x + cv[u].y, t3);
+    }
+  }
+  for (; ks < nk; ks += dk) {
+    const int col = 4 * ks + lk;
+    const bool ok = col < ncol;
+    const double2 qv = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
+    const double2 cv = *((ok & vok) ? C + (size_t)col * kBlockMax + li : zero);
+    t1 = mfma(qv.x, cv.x, t1);
+    t2 = mfma(qv.y, cv.y, t2);
+    t3 = mfma(qv.x + qv.y, cv.x + cv.y, t3);
+  }
+}
+
 // complex entries (Re in lane li < 8, Im from lane li + 8) of a Q C tile
 __device__ inline void qc_pairs(const v4d& d, double2 (&res)[4]) {
 #pragma unroll
@@ -442,6 +583,7 @@ struct BUpd {
   BHess hess;
 };
 
+template <bool G>
 __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   int z, bid;
   if (!xcd_tile(blockIdx.x, g.nb, a.nrowblk + a.nhess, bid, z)) return;
@@ -461,52 +603,81 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   const bool active = r0 < g.N;  // wavefront-uniform
   const int row = min(r0 + li, g.N - 1);
   const int v = li & 7;
-  v4d d[kHalves];
-#pragma unroll
-  for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
-  if (active) qc_steps(g.S, Vr, g.m, g.ldq, row, g.p, Cr, v, li >= 8, g.s, lk, 0, 1, d);
+  // res[h][t]: (Q C)[row r0 + lk + 4 t][vector vec(h)] in the lanes that own one
   double2 res[kHalves][4];
+  bool own[kHalves];
+  int vec[kHalves];
+  if constexpr (G) {
+    v4d t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
+    if (active) qc_steps3(g.S, Vr, g.m, g.ldq, row, g.p, Cr, g.s, li, lk, 0, 1, t1, t2, t3);
 #pragma unroll
-  for (int h = 0; h < kHalves; ++h) qc_pairs(d[h], res[h]);
+    for (int t = 0; t < 4; ++t) res[0][t] = make_double2(t1[t] - t2[t], t3[t] - t1[t] - t2[t]);
+    own[0] = li < g.s;
+    vec[0] = li;
+#pragma unroll
+    for (int h = 1; h < kHalves; ++h) own[h] = false;
+  } else {
+    v4d d[kHalves];
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (active) qc_steps(g.S, Vr, g.m, g.ldq, row, g.p, Cr, v, li >= 8, g.s, lk, 0, 1, d);
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      qc_pairs(d[h], res[h]);
+      vec[h] = 8 * h + v;
+      own[h] = li < 8 && vec[h] < g.s;
+    }
+  }
   if (!a.Rinv) {
-    if (active && li < 8)
+    if (active)
 #pragma unroll
       for (int h = 0; h < kHalves; ++h) {
-        if (8 * h + v >= g.s) continue;
+        if (!own[h]) continue;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int rr = r0 + lk + 4 * t;
           if (rr < g.N) {
-            const size_t o = (size_t)(8 * h + v) * g.ldq + rr;
+            const size_t o = (size_t)vec[h] * g.ldq + rr;
             Wout[o] = csub(Win[o], res[h][t]);
           }
         }
       }
     return;
   }
-  // second pass: W'' = Win - Q C, then W'' Rinv per row (through LDS)
-  const double2* Ri = a.Rinv + (size_t)rs * a.rstride;
+  // second pass: W'' = Win - Q C, then W'' Rinv per row (through LDS; the
+  // workgroup's slot is the same for all four wavefronts)
   __shared__ double2 tile[4][16][kBlockMax];
-  if (li < 8)
+  __shared__ double2 ri[kBlockMax * kBlockMax];
+  {
+    const double2* Ri = a.Rinv + (size_t)rs * a.rstride;
+    for (int e = threadIdx.x; e < kBlockMax * kBlockMax; e += 256) ri[e] = Ri[e];
+  }
+  // every (row, vector) of the tile: vectors past s and rows past N as zero
 #pragma unroll
-    for (int h = 0; h < kHalves; ++h)
+  for (int h = 0; h < kHalves; ++h) {
+    const bool writer = G ? h == 0 : li < 8;
+    if (!writer) continue;
+    const int vv = G ? li : 8 * h + v;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int rr = r0 + lk + 4 * t, vv = 8 * h + v;
-        double2 val = make_double2(0.0, 0.0);
-        if (active && vv < g.s && rr < g.N) val = csub(Win[(size_t)vv * g.ldq + rr], res[h][t]);
-        tile[wave][lk + 4 * t][vv] = val;
-      }
+    for (int t = 0; t < 4; ++t) {
+      const int rr = r0 + lk + 4 * t;
+      double2 val = make_double2(0.0, 0.0);
+      if (active && own[h] && rr < g.N) val = csub(Win[(size_t)vv * g.ldq + rr], res[h][t]);
+      tile[wave][lk + 4 * t][vv] = val;
+    }
+  }
   __syncthreads();
   if (!active) return;
   constexpr int kOut = 16 * kBlockMax / 64;  // outputs per lane
-#pragma unroll
+  // (not unrolled: this epilogue would otherwise set the kernel's register
+  // count, and with it the occupancy of the sweep above)
+#pragma unroll 1
   for (int q = 0; q < kOut; ++q) {
     const int idx = lane + 64 * q;
     const int rl = idx / kBlockMax, vv = idx % kBlockMax;
     double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int u = 0; u < kBlockMax; ++u) acc = cfma(tile[wave][rl][u], Ri[u * kBlockMax + vv], acc);
+#pragma unroll 4
+    for (int u = 0; u < kBlockMax; ++u) acc = cfma(tile[wave][rl][u], ri[u * kBlockMax + vv], acc);
     const int rr = r0 + rl;
     if (vv < g.s && rr < g.N) Wout[(size_t)vv * g.ldq + rr] = acc;
   }
@@ -680,6 +851,7 @@ __device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
   }
 }
 
+template <bool G>
 __global__ void __launch_bounds__(256) bsmall_kernel(BlockGeo g, BSmall a) {
   const int z = blockIdx.x % g.nb, t = blockIdx.x / g.nb;
   const int rs = g.act[z];
@@ -697,30 +869,53 @@ __global__ void __launch_bounds__(256) bsmall_kernel(BlockGeo g, BSmall a) {
   const int c0 = r0 < g.m ? r0 : max(g.m, r0 - 1);  // columns below c0 are zero in these rows
   const double2* H = a.H + (size_t)rs * a.hstride;
   const double2* Ct = a.Ct + (size_t)rs * a.cstride;
-  v4d d[kHalves];
-#pragma unroll
-  for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
-  // only the columns 0 .. s-2 of Ct enter P
-  qc_steps(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, v, li >= 8, g.s - 1, lk, (c0 >> 2) + wave, 4, d);
-  __shared__ v4d red[4][kHalves][64];
-#pragma unroll
-  for (int h = 0; h < kHalves; ++h) red[wave][h][lane] = d[h];
-  __syncthreads();
-  if (wave != 0) return;
   double2* P = a.P + (size_t)rs * a.cstride;
+  // only the columns 0 .. s-2 of Ct enter P
+  if constexpr (G) {
+    v4d t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
+    qc_steps3(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, g.s - 1, li, lk, (c0 >> 2) + wave, 4, t1, t2, t3);
+    __shared__ v4d red3[4][3][64];
+    red3[wave][0][lane] = t1;
+    red3[wave][1][lane] = t2;
+    red3[wave][2][lane] = t3;
+    __syncthreads();
+    if (wave != 0) return;
 #pragma unroll
-  for (int h = 0; h < kHalves; ++h) {
-    v4d dh = red[0][h][lane];
-#pragma unroll
-    for (int w = 1; w < 4; ++w) dh += red[w][h][lane];
-    double2 res[4];
-    qc_pairs(dh, res);
-    if (li < 8 && 8 * h + v < g.s - 1)
+    for (int w = 1; w < 4; ++w) {
+      t1 += red3[w][0][lane];
+      t2 += red3[w][1][lane];
+      t3 += red3[w][2][lane];
+    }
+    if (li < g.s - 1)
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int rr = r0 + lk + 4 * tt;
-        if (rr < p) P[(size_t)(8 * h + v) * a.ldp + rr] = res[tt];
+        if (rr < p) P[(size_t)li * a.ldp + rr] = make_double2(t1[tt] - t2[tt], t3[tt] - t1[tt] - t2[tt]);
       }
+  } else {
+    v4d d[kHalves];
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
+    qc_steps(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, v, li >= 8, g.s - 1, lk, (c0 >> 2) + wave, 4, d);
+    __shared__ v4d red[4][kHalves][64];
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) red[wave][h][lane] = d[h];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int h = 0; h < kHalves; ++h) {
+      v4d dh = red[0][h][lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) dh += red[w][h][lane];
+      double2 res[4];
+      qc_pairs(dh, res);
+      if (li < 8 && 8 * h + v < g.s - 1)
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int rr = r0 + lk + 4 * tt;
+          if (rr < p) P[(size_t)(8 * h + v) * a.ldp + rr] = res[tt];
+        }
+    }
   }
 }
 
@@ -814,6 +1009,8 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
                             -1.0, map, s, prof);
   int rpw = 0;
   const int nch = nchunks_for(N, rpw);
+  // more than 8 block vectors: the products in their three-multiplication form
+  const bool gauss = sb > 8;
   auto dot = [&](double2* C, int ncol, const double2* C1, double2* Ct) {
     const int ncg = (ncol + 16 * kDotTiles - 1) / (16 * kDotTiles);
     BDot d{b.W, b.wstride, ncol, rpw, ncg, nch, b.part, b.pstride};
@@ -821,8 +1018,8 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
     // W as columns per slot), W once per slot, partials written
     const double bytes =
         16.0 * N * ((double)m + (double)nb * (ncol - m + sb)) + 16.0 * nch * ncol * kBlockMax * (double)nb;
-    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, bdot_kernel, dim3(xcd_grid(nb * ncg, nch)), dim3(256),
-                0, s, g, d);
+    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, gauss ? bdot3_kernel : bdot_kernel,
+                dim3(xcd_grid(nb * ncg, nch)), dim3(256), 0, s, g, d);
     const int nent = ncol * kBlockMax, nblk = (nent + 31) / 32;
     BRed rd{b.part, b.pstride, nch, nent, nblk, C, C1, Ct, b.cstride, b.G, b.gstride};
     prof_launch(prof, K_BRED, (16.0 * (double)nch * nent + 16.0 * nent) * nb, 2.0 * nch * nent * nb, bred_kernel,
@@ -835,7 +1032,7 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
   dot(b.C1, p, nullptr, nullptr);
   {
     BUpd u{b.C1, b.cstride, b.W, b.wstride, b.W, b.wstride, nullptr, 0, nrowblk, 0, BHess{}};
-    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3(xcd_grid(nb, nrowblk)),
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, gauss ? bupdate_kernel<true> : bupdate_kernel<false>, dim3(xcd_grid(nb, nrowblk)),
                 dim3(256), 0, s, g, u);
   }
   // pass 2 with the Gram matrix of the projected block
@@ -843,8 +1040,8 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
   {
     BSmall sm{b.C2, b.Ct, b.cstride, b.G, b.gstride, sp.H, sp.hstride, sp.ldh, b.P, sp.ncap, b.R, b.rstride, b.flag};
     const double hb = 16.0 * ((double)p * p / 2 + 3.0 * p * sb) * nb;
-    prof_launch(prof, K_BSMALL, hb, 8.0 * p * p * sb / 2 * nb, bsmall_kernel, dim3((1 + (p + 15) / 16) * nb),
-                dim3(256), 0, s, g, sm);
+    prof_launch(prof, K_BSMALL, hb, 8.0 * p * p * sb / 2 * nb, sb - 1 > 8 ? bsmall_kernel<true> : bsmall_kernel<false>,
+                dim3((1 + (p + 15) / 16) * nb), dim3(256), 0, s, g, sm);
   }
   {
     BHess h{e, b.Ct, b.P, b.cstride, sp.ncap, b.R, b.R + 2 * kBlockMax * kBlockMax, b.rstride, sp.H, sp.hstride,
@@ -852,7 +1049,8 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
     const int nh = ((p + sb) * kBlockMax + 255) / 256;
     BUpd u{b.C2, b.cstride, b.W, b.wstride, const_cast<double2*>(sp.V) + (size_t)(p - m) * ldq, sp.vstride,
            b.R + kBlockMax * kBlockMax, b.rstride, nrowblk, nh, h};
-    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, bupdate_kernel, dim3(xcd_grid(nb, nrowblk + nh)),
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, gauss ? bupdate_kernel<true> : bupdate_kernel<false>,
+                dim3(xcd_grid(nb, nrowblk + nh)),
                 dim3(256), 0, s, g, u);
   }
 }
