@@ -4,7 +4,9 @@
 // instruction v_mfma_f64_16x16x4f64 (one 16 x 16 real block += 16 x 4 times
 // 4 x 16 per wavefront): a complex 16 x 16 block takes four of them per
 // k-step of four,
-//     Re C += Re A Re B - Im A Im B,     Im C += Re A Im B + Im A Re B.
+//     Re C += Re A Re B - Im A Im B,     Im C += Re A Im B + Im A Re B,
+// or, in the Newton-Schulz products, three (the three-multiplication form:
+// Re A Re B, Im A Im B and (Re A + Im A)(Re B + Im B)).
 // Operand fragments come straight from global memory (the small sign's
 // matrices live in L2; a lane loads one complex entry per fragment, rows of
 // A and columns of B 16 entries apart), two k-steps ahead of the products,
@@ -100,16 +102,40 @@ struct KWalk {
   }
 };
 
-template <int TM, int TN>
-__device__ inline void mma(const Frag<TM, TN>& f, v4d (&re)[TM][TN], v4d (&im)[TM][TN]) {
+// One k-step of the complex products.  G3 (the Newton-Schulz products): the
+// three-multiplication form, re += Re A Re B, im += Im A Im B,
+// tx += (Re A + Im A)(Re B + Im B), turned into Re C = re - im and
+// Im C = tx - re - im by finish3 (a quarter fewer matrix-core instructions;
+// the iteration corrects its own rounding).  Otherwise the four real
+// products straight into Re C and Im C.
+template <int TM, int TN, bool G3>
+__device__ inline void mma(const Frag<TM, TN>& f, v4d (&re)[TM][TN], v4d (&im)[TM][TN], v4d (&tx)[TM][TN]) {
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
-      re[a][b] = mfma(f.a[a].x, f.b[b].x, re[a][b]);
-      re[a][b] = mfma(-f.a[a].y, f.b[b].y, re[a][b]);
-      im[a][b] = mfma(f.a[a].x, f.b[b].y, im[a][b]);
-      im[a][b] = mfma(f.a[a].y, f.b[b].x, im[a][b]);
+      if constexpr (G3) {
+        re[a][b] = mfma(f.a[a].x, f.b[b].x, re[a][b]);
+        im[a][b] = mfma(f.a[a].y, f.b[b].y, im[a][b]);
+        tx[a][b] = mfma(f.a[a].x + f.a[a].y, f.b[b].x + f.b[b].y, tx[a][b]);
+      } else {
+        re[a][b] = mfma(f.a[a].x, f.b[b].x, re[a][b]);
+        re[a][b] = mfma(-f.a[a].y, f.b[b].y, re[a][b]);
+        im[a][b] = mfma(f.a[a].x, f.b[b].y, im[a][b]);
+        im[a][b] = mfma(f.a[a].y, f.b[b].x, im[a][b]);
+      }
+    }
+}
+
+template <int TM, int TN>
+__device__ inline void finish3(v4d (&re)[TM][TN], v4d (&im)[TM][TN], const v4d (&tx)[TM][TN]) {
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const v4d r = re[a][b] - im[a][b];
+      im[a][b] = tx[a][b] - re[a][b] - im[a][b];
+      re[a][b] = r;
     }
 }
 
@@ -117,10 +143,10 @@ __device__ inline void mma(const Frag<TM, TN>& f, v4d (&re)[TM][TN], v4d (&im)[T
 // body is unrolled three times so the fragments rotate through three register
 // sets without copies (a copy of a just-loaded register would wait for the
 // load).  Steps past K multiply zeros, which leaves the sums unchanged.
-template <int TM, int TN>
+template <int TM, int TN, bool G3>
 __device__ inline void kloop(const ZgArgs& g, const double2* __restrict__ A, const double2* __restrict__ B,
                              const int* ar, const bool* aok, const int* bc, const bool* bok, int lk, int first,
-                             int stride, v4d (&re)[TM][TN], v4d (&im)[TM][TN]) {
+                             int stride, v4d (&re)[TM][TN], v4d (&im)[TM][TN], v4d (&tx)[TM][TN]) {
   const int S = (g.K + 3) / 4;
   if (first >= S) return;
   KWalk<TM, TN> w;
@@ -147,13 +173,13 @@ __device__ inline void kloop(const ZgArgs& g, const double2* __restrict__ A, con
   for (int st = first; st < S; st += 3 * stride) {
     w.load(f2);
     w.advance();
-    mma<TM, TN>(f0, re, im);
+    mma<TM, TN, G3>(f0, re, im, tx);
     w.load(f0);
     w.advance();
-    mma<TM, TN>(f1, re, im);
+    mma<TM, TN, G3>(f1, re, im, tx);
     w.load(f1);
     w.advance();
-    mma<TM, TN>(f2, re, im);
+    mma<TM, TN, G3>(f2, re, im, tx);
   }
 }
 
@@ -200,13 +226,15 @@ __global__ void __launch_bounds__(256) zgemm_kernel(ZgArgs g) {
   const int i0 = (blockIdx.y * 2 + (w & 1)) * (16 * TM);
   const int j0 = (blockIdx.x * 2 + (w >> 1)) * (16 * TN);
 
-  v4d re[TM][TN], im[TM][TN];
+  constexpr bool G3 = MODE != ZG_PLAIN;
+  v4d re[TM][TN], im[TM][TN], tx[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
       re[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
       im[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      tx[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
     }
   int ar[TM], bc[TN];
   bool aok[TM], bok[TN];
@@ -222,7 +250,8 @@ __global__ void __launch_bounds__(256) zgemm_kernel(ZgArgs g) {
     bok[b] = j < g.N;
     bc[b] = min(j, g.N - 1);
   }
-  kloop<TM, TN>(g, A, B, ar, aok, bc, bok, lk, 0, 1, re, im);
+  kloop<TM, TN, G3>(g, A, B, ar, aok, bc, bok, lk, 0, 1, re, im, tx);
+  if constexpr (G3) finish3<TM, TN>(re, im, tx);
 
   double psum = 0.0;
   const bool final_out = MODE == ZG_NS_UPDATE && g.state[bz] == 1;
@@ -255,11 +284,14 @@ __global__ void __launch_bounds__(256) zgemm_splitk_kernel(ZgArgs g) {
   const int li = lane & 15, lk = lane >> 4;
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
 
-  v4d re[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}}, im[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}};
+  constexpr bool G3 = MODE != ZG_PLAIN;
+  v4d re[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}}, im[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}},
+      tx[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}};
   const int i = i0 + li, j = j0 + li;
   const int ar[1] = {min(i, g.M - 1)}, bc[1] = {min(j, g.N - 1)};
   const bool aok[1] = {i < g.M}, bok[1] = {j < g.N};
-  kloop<1, 1>(g, A, B, ar, aok, bc, bok, lk, w, 4, re, im);
+  kloop<1, 1, G3>(g, A, B, ar, aok, bc, bok, lk, w, 4, re, im, tx);
+  if constexpr (G3) finish3<1, 1>(re, im, tx);
 
   // partial products of wavefronts 1..3 -> LDS [w - 1][item][lane]
   __shared__ double red[3][8][64];
