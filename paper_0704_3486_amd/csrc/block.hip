@@ -51,6 +51,16 @@ namespace {
 
 __device__ inline v4d mfma(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
+// Loads through pointers known to address device (global) memory: global
+// rather than flat instructions, which would also wait on the LDS counter.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef const d2v __attribute__((address_space(1)))* gptr;
+__device__ inline gptr to_global(const double2* p) { return (gptr)p; }
+__device__ inline double2 gload(gptr p) {
+  const d2v v = *p;
+  return make_double2(v.x, v.y);
+}
+
 // k-steps whose loads a lane issues together in the block products
 constexpr int kUnroll = 8;
 // fewest rows per wavefront of the dot pass, and its tiles of 16 columns
@@ -276,14 +286,14 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   const int r0 = (chunk * 4 + wave) * a.rpw;
   const int r1 = min(r0 + a.rpw, g.N);
   const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
-  const double2* qp[kDotTiles];
+  gptr qp[kDotTiles];
 #pragma unroll
   for (int t = 0; t < kDotTiles; ++t) {
     const int cc = min((cg * kDotTiles + t) * 16 + li, a.ncol - 1);
-    qp[t] = (cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk;
+    qp[t] = to_global((cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk);
   }
   const bool vok = li < g.s;
-  const double2* wp = vok ? Wr + (size_t)li * g.ldq + r0 + lk : &sgn_block_zero_entry;
+  gptr wp = to_global(vok ? Wr + (size_t)li * g.ldq + r0 + lk : &sgn_block_zero_entry);
   const int dw = vok ? 4 : 0;
   v4d t1[kDotTiles], t2[kDotTiles], t3[kDotTiles];
 #pragma unroll
@@ -292,16 +302,21 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
     t2[t] = v4d{0.0, 0.0, 0.0, 0.0};
     t3[t] = v4d{0.0, 0.0, 0.0, 0.0};
   }
+  // groups of U k-steps, the loads of the next group issued before the
+  // products of the current one (two register sets)
   constexpr int U = kUnroll / 2;
-  int it = 0;
-  for (; it + U <= nit; it += U) {
-    double2 qv[U][kDotTiles], wv[U];
+  auto load = [&](double2 (&qv)[U][kDotTiles], double2 (&wv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < kDotTiles; ++t) qv[u][t] = qp[t][4 * u];
-      wv[u] = wp[dw * u];
+      for (int t = 0; t < kDotTiles; ++t) qv[u][t] = gload(qp[t] + 4 * u);
+      wv[u] = gload(wp + dw * u);
     }
+#pragma unroll
+    for (int t = 0; t < kDotTiles; ++t) qp[t] += 4 * U;
+    wp += U * dw;
+  };
+  auto mul = [&](const double2 (&qv)[U][kDotTiles], const double2 (&wv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const double ws = wv[u].x + wv[u].y;
@@ -312,16 +327,28 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
         t3[t] = mfma(ws, qv[u][t].x - qv[u][t].y, t3[t]);
       }
     }
-#pragma unroll
-    for (int t = 0; t < kDotTiles; ++t) qp[t] += 4 * U;
-    wp += U * dw;
+  };
+  int it = 0;
+  {
+    double2 qa[U][kDotTiles], wa[U], qb[U][kDotTiles], wb[U];
+    if (nit >= U) load(qa, wa);
+    for (; it + 2 * U <= nit; it += 2 * U) {
+      load(qb, wb);
+      mul(qa, wa);
+      if (it + 3 * U <= nit) load(qa, wa);
+      mul(qb, wb);
+    }
+    if (it + U <= nit) {
+      mul(qa, wa);
+      it += U;
+    }
   }
   for (; it < nit; ++it) {
-    const double2 wv = *wp;
+    const double2 wv = gload(wp);
     const double ws = wv.x + wv.y;
 #pragma unroll
     for (int t = 0; t < kDotTiles; ++t) {
-      const double2 qv = *qp[t];
+      const double2 qv = gload(qp[t]);
       t1[t] = mfma(wv.x, qv.x, t1[t]);
       t2[t] = mfma(wv.y, qv.y, t2[t]);
       t3[t] = mfma(ws, qv.x - qv.y, t3[t]);
