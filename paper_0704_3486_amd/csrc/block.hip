@@ -504,7 +504,7 @@ __device__ inline void qc_steps(const double2* __restrict__ S, const double2* __
 __device__ inline void qc_steps3(const double2* __restrict__ S, const double2* __restrict__ Vr, int m, size_t ldq,
                                  int row, int ncol, const double2* __restrict__ C, int s, int li, int lk, int k0,
                                  int dk, v4d& t1, v4d& t2, v4d& t3) {
-  const double2* zero = &sgn_block_zero_entry;
+  const gptr zero = to_global(&sgn_block_zero_entry);
   const int nk = (ncol + 3) >> 2;
   const bool vok = li < s;
   int ks = k0;
@@ -515,8 +515,8 @@ __device__ inline void qc_steps3(const double2* __restrict__ S, const double2* _
     for (int u = 0; u < U; ++u) {
       const int col = 4 * (ks + u * dk) + lk;
       const bool ok = col < ncol;
-      qv[u] = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
-      cv[u] = *((ok & vok) ? C + (size_t)col * kBlockMax + li : zero);
+      qv[u] = gload(ok ? to_global(qcol(S, Vr, m, ldq, col) + row) : zero);
+      cv[u] = gload((ok & vok) ? to_global(C + (size_t)col * kBlockMax + li) : zero);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -528,8 +528,8 @@ __device__ inline void qc_steps3(const double2* __restrict__ S, const double2* _
   for (; ks < nk; ks += dk) {
     const int col = 4 * ks + lk;
     const bool ok = col < ncol;
-    const double2 qv = *(ok ? qcol(S, Vr, m, ldq, col) + row : zero);
-    const double2 cv = *((ok & vok) ? C + (size_t)col * kBlockMax + li : zero);
+    const double2 qv = gload(ok ? to_global(qcol(S, Vr, m, ldq, col) + row) : zero);
+    const double2 cv = gload((ok & vok) ? to_global(C + (size_t)col * kBlockMax + li) : zero);
     t1 = mfma(qv.x, cv.x, t1);
     t2 = mfma(qv.y, cv.y, t2);
     t3 = mfma(qv.x + qv.y, cv.x + cv.y, t3);
@@ -764,7 +764,27 @@ __device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
     double nn = 0.0;
     const double2* zero = &sgn_block_zero_entry;
     const int nk = (p + 3) >> 2;
-    for (int ks = wave; ks < nk; ks += 4) {
+    // the loads of kUnroll k-steps first (one wait per group, not per step)
+    int ks = wave;
+    for (; ks + 4 * (kUnroll - 1) < nk; ks += 4 * kUnroll) {
+      double2 x[kUnroll], y[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int c = 4 * (ks + 4 * u) + lk;
+        const bool ok = c < p && li < s;
+        x[u] = *(ok ? C2 + (size_t)c * B + li : zero);
+        y[u] = *(ok ? Ct + (size_t)c * B + li : zero);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        dre = mfma(x[u].x, x[u].x, dre);
+        dre = mfma(x[u].y, x[u].y, dre);
+        dim = mfma(x[u].x, x[u].y, dim);
+        dim = mfma(-x[u].y, x[u].x, dim);
+        nn += cabs2(y[u]);
+      }
+    }
+    for (; ks < nk; ks += 4) {
       const int c = 4 * ks + lk;
       const bool ok = c < p && li < s;
       const double2 x = *(ok ? C2 + (size_t)c * B + li : zero);
