@@ -49,10 +49,10 @@ HBM_PEAK_GBPS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 # profiling class -> kernel symbol (as rocprofv3 lists it)
 HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_kernel<double2>",
-               "krylov_reduce": "kred_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
+               "krylov_reduce": "kred_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2, false>"}
 # the same for the block (s-step) process
 HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel<false>", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
-                     "block_factor": "bsmall_kernel<false>", "wilson_hw": "wilson_hw_dir_kernel<double2>"}
+                     "block_factor": "bsmall_kernel<false>", "wilson_hw": "wilson_hw_dir_kernel<double2, true>"}
 BLOCK_STEPS = 16  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
 BATCH = 8  # sources per batched apply call of each context in the timed region
 STENCIL_DIMS = (32, 32, 32, 32)

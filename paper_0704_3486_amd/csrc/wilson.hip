@@ -277,15 +277,15 @@ __device__ inline C shfl_xor_c(C v, int mask) {
 // in direction order.  The site's own spinor entries for the second phase
 // are loaded with the hop operands, so a workgroup waits on memory once.
 // blockIdx.y = right-hand side (slot map).  Optional: scale = *inv_beta on
-// input and output, copy_out = In * scale; with cheb, Out_r = ca H_w In_r +
+// input and output, copy_out = In * scale; with CHEB, Out_r = ca H_w In_r +
 // cb Prev_r (Prev_r = prev + slot pstride; prev null: cb ignored), a step of
 // a three-term polynomial recurrence.
-template <typename C>
+template <typename C, bool CHEB>
 __global__ void __launch_bounds__(256)
 wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size_t istride, C* __restrict__ out,
                      size_t ostride, const double* __restrict__ inv_beta, C* __restrict__ copy_out, int Lx, int Ly,
                      int Lz, int Lt, double kappa_d, double emu_d, double emmu_d, SlotMap map, SiteOrder order,
-                     const C* __restrict__ prev, size_t pstride, double ca, double cb, int cheb) {
+                     const C* __restrict__ prev, size_t pstride, double ca, double cb) {
   using R = typename Real<C>::type;
   constexpr int kThreads = 256, kOut = 12 * kSiteGroup;
   const int V = Lx * Ly * Lz * Lt;
@@ -300,11 +300,15 @@ wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size
   const C* __restrict__ v = in + (size_t)slot * istride;
   // second-phase outputs of this thread: p = tid + q kThreads < kOut, i.e.
   // component p / kSiteGroup of site n0 + p % kSiteGroup
-  C self[2];
+  C self[2], pv[2];
+  const C* __restrict__ pr = (CHEB && prev) ? prev + (size_t)slot * pstride : nullptr;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int p = threadIdx.x + q * kThreads, nn = n0 + p % kSiteGroup;
-    self[q] = (p < kOut && nn < V) ? v[(size_t)(p / kSiteGroup) * V + nn] : mk<C>(0, 0);
+    const bool ok = p < kOut && nn < V;
+    self[q] = ok ? v[(size_t)(p / kSiteGroup) * V + nn] : mk<C>(0, 0);
+    // the recurrence's previous term, loaded with the operands (one wait)
+    if constexpr (CHEB) pv[q] = (ok && pr) ? pr[(size_t)(p / kSiteGroup) * V + nn] : mk<C>(0, 0);
   }
   const int x = nc % Lx;
   const int y = (nc / Lx) % Ly;
@@ -382,9 +386,9 @@ wilson_hw_dir_kernel(const C* __restrict__ links, const C* __restrict__ in, size
     // gamma5 (psi - kappa * hops), all times 1/beta
     const R g5 = comp < 6 ? (R)1 : (R)-1;
     C val = tscale(tsub(self[q], tscale(acc, kappa)), g5 * scale);
-    if (cheb) {
+    if constexpr (CHEB) {
       val = tscale(val, (R)ca);
-      if (prev) val = tadd(val, tscale(prev[(size_t)slot * pstride + idx], (R)cb));
+      if (pr) val = tadd(val, tscale(pv[q], (R)cb));
     }
     w[idx] = val;
     if (copy_out) copy_out[idx] = tscale(self[q], scale);
@@ -566,10 +570,10 @@ void wilson_apply(const Lattice& lat, const double2* links, const double2* in, d
   // algorithmic bytes: read v (12), write w (12), 4 links of 6 stored entries
   // (24) per site; + copy (12)
   const double per_site = (48.0 + (copy_out ? 12.0 : 0.0)) * 16.0;
-  prof_launch(prof, K_WILSON, per_site * V, 1392.0 * V, wilson_hw_dir_kernel<double2>,
+  prof_launch(prof, K_WILSON, per_site * V, 1392.0 * V, wilson_hw_dir_kernel<double2, false>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, 1), dim3(256), 0, s, links, in, (size_t)0, out, (size_t)0,
               inv_beta, copy_out, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu, lat.emmu, SlotMap{},
-              site_order(lat), (const double2*)nullptr, (size_t)0, 1.0, 0.0, 0);
+              site_order(lat), (const double2*)nullptr, (size_t)0, 1.0, 0.0);
 }
 
 void wilson_apply_cheb_slots(const Lattice& lat, const double2* links, const double2* in, size_t istride,
@@ -580,10 +584,10 @@ void wilson_apply_cheb_slots(const Lattice& lat, const double2* links, const dou
   // per site: the links (24 stored entries) once, per slot read v and
   // prev, write w (12 each)
   const double bytes = (24.0 + (24.0 + (prev ? 12.0 : 0.0)) * map.n) * 16.0 * V;
-  prof_launch(prof, K_WILSON, bytes, 1392.0 * V * map.n, wilson_hw_dir_kernel<double2>,
+  prof_launch(prof, K_WILSON, bytes, 1392.0 * V * map.n, wilson_hw_dir_kernel<double2, true>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
               (const double*)nullptr, (double2*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
-              lat.emmu, map, site_order(lat), prev, pstride, ca, cb, 1);
+              lat.emmu, map, site_order(lat), prev, pstride, ca, cb);
 }
 
 // several right-hand sides: one hop per thread (bitwise the single-RHS
@@ -599,10 +603,10 @@ static void wilson_multi(const Lattice& lat, const C* links, const C* in, size_t
   const unsigned gx = (V + kWilsonBlock - 1) / kWilsonBlock;
   const int L0 = lat.L[0], L1 = lat.L[1], L2 = lat.L[2], L3 = lat.L[3];
   if (split || nrhs == 1) {
-    hipLaunchKernelGGL((wilson_hw_dir_kernel<C>), dim3((V + kSiteGroup - 1) / kSiteGroup, nrhs),
+    hipLaunchKernelGGL((wilson_hw_dir_kernel<C, false>), dim3((V + kSiteGroup - 1) / kSiteGroup, nrhs),
                        dim3(256), 0, s, links, in, istride, out, ostride, nullptr, nullptr, L0, L1, L2,
                        L3, lat.kappa, lat.emu, lat.emmu, SlotMap{}, site_order(lat), (const C*)nullptr, (size_t)0,
-                       1.0, 0.0, 0);
+                       1.0, 0.0);
   } else if (nrhs >= 4 && sizeof(C) == 8) {
     hipLaunchKernelGGL((wilson_hw_kernel<C, 4>), dim3(gx, (nrhs + 3) / 4), blk, 0, s, links, in, istride, out,
                        ostride, nrhs, L0, L1, L2, L3, lat.kappa, lat.emu, lat.emmu);
@@ -625,10 +629,10 @@ void wilson_apply_slots(const Lattice& lat, const C* links, const C* in, size_t 
   const int V = lat.V;
   // per site: the links (24 stored entries) once, per slot read v (12) and write w (12)
   const double b = (double)sizeof(C);
-  prof_launch(prof, K_WILSON, (24.0 + 24.0 * map.n) * b * V, 1392.0 * V * map.n, wilson_hw_dir_kernel<C>,
+  prof_launch(prof, K_WILSON, (24.0 + 24.0 * map.n) * b * V, 1392.0 * V * map.n, wilson_hw_dir_kernel<C, false>,
               dim3((V + kSiteGroup - 1) / kSiteGroup, map.n), dim3(256), 0, s, links, in, istride, out, ostride,
               (const double*)nullptr, (C*)nullptr, lat.L[0], lat.L[1], lat.L[2], lat.L[3], lat.kappa, lat.emu,
-              lat.emmu, map, site_order(lat), (const C*)nullptr, (size_t)0, 1.0, 0.0, 0);
+              lat.emmu, map, site_order(lat), (const C*)nullptr, (size_t)0, 1.0, 0.0);
 }
 template void wilson_apply_slots<double2>(const Lattice&, const double2*, const double2*, size_t, double2*, size_t,
                                           const SlotMap&, hipStream_t, Profiler*);
