@@ -119,9 +119,12 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay runs of this many Arnoldi steps as captured HIP graphs in the timed applies "
                          "(sgn_set_step_graphs; bitwise the same results; 0: direct launches)")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the one-source-at-a-time latency leg (for kernel-trace runs: the traced launches "
+                         "are then those of the timed region and the profiled pass)")
     ap.add_argument("--serial", action="store_true",
-                    help="time the steps one apply at a time (no overlap of the fields; for profiler runs, "
-                         "whose per-kernel averages then compare with the HIP-event ones)")
+                    help="run the timed region's lanes one after another (no overlap of the fields; for "
+                         "kernel-trace runs, whose per-kernel averages then compare with the HIP-event ones)")
     ap.add_argument("--counters", action="store_true",
                     help="only one batched call per field of the headline configuration, with the library's "
                          "algorithmic bytes per launch of each kernel class (the run that rocprofv3 counter "
@@ -194,7 +197,7 @@ def main():
         streams.append(st)
 
     P = 1 if args.serial else max(1, args.per_field)
-    B = 1 if args.serial else max(1, args.batch)
+    B = max(1, args.batch)
     # sources: the seeds whose exact results are stored for every field
     # (1000 .. 1000 + n - 1, dense Roberts sign of the oracle), cycled; so
     # every timed apply is checked against the exact y
@@ -300,7 +303,13 @@ def main():
                 field_steps(f, r, 1, ks)
         return ks
 
-    runner = run_serial if args.serial else run_concurrent
+    def run_lanes_serial(first, count, timed=False):
+        ks = []
+        for q in range(len(lanes)):
+            lane_steps(q, first, count, ks, timed)
+        return ks
+
+    runner = run_lanes_serial if args.serial else run_concurrent
     runner(0, args.warmup)
     torch.cuda.synchronize()
     unconverged.clear()
@@ -313,19 +322,20 @@ def main():
     value = applies / elapsed
     mode = "serial" if args.serial else f"{len(lanes)} streams"
     log(f"timed ({mode}): {applies} applies in {elapsed:.3f} s -> {value:.2f} applies/s, mean k {np.mean(ks):.1f}")
-    timed_acc = timed_accuracy(torch, outs if not args.serial else None, gold, nstored, P, B, args.warmup,
-                               args.steps)
+    timed_acc = timed_accuracy(torch, outs, gold, nstored, P, B, args.warmup, args.steps)
     log(f"timed applies vs exact: {timed_acc}")
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_serial(args.warmup, args.steps)
-    torch.cuda.synchronize()
-    elapsed_serial = time.perf_counter() - t0
-    n_serial = args.steps * len(MUS)
-    latency = {"ms_per_apply": round(1e3 * elapsed_serial / n_serial, 3),
-               "applies_per_s_one_at_a_time": round(n_serial / elapsed_serial, 3)}
-    log(f"serial: {latency}")
+    latency = None
+    if not args.no_latency:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_serial(args.warmup, args.steps)
+        torch.cuda.synchronize()
+        elapsed_serial = time.perf_counter() - t0
+        n_serial = args.steps * len(MUS)
+        latency = {"ms_per_apply": round(1e3 * elapsed_serial / n_serial, 3),
+                   "applies_per_s_one_at_a_time": round(n_serial / elapsed_serial, 3)}
+        log(f"serial: {latency}")
     for c in extra:
         sg.sgn_destroy(c)
     for c in ctxs:
@@ -340,11 +350,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ks_prof = []
-    if args.serial:
-        ks_prof = run_serial(args.warmup, args.steps)
-    else:
-        for q in range(len(MUS)):
-            lane_steps(q, args.warmup, args.steps, ks_prof, False)
+    for q in range(len(lanes)):
+        lane_steps(q, args.warmup, args.steps, ks_prof, False)
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t1
     kstats = {}
@@ -439,7 +446,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sgn(H_w(mu))x, 6^4 lattice (N=15552), m_w=-1.6, mu in {0.0,0.2,0.5}, "
                                "m=20 Schur deflation, kmax=500, tol=1e-10, FP64, 1 RHS per apply, "
-                               + ("3 applies per step (one per field, one at a time)" if args.serial else
+                               + (f"{len(lanes) * B} applies per step (the fields one after another, {B} "
+                                  f"source(s) per apply call)" if args.serial else
                                   f"{len(lanes) * B} applies per step ({P * B} per field in flight: {P} "
                                   f"context(s) and stream(s) per field, {B} source(s) per apply call)"),
                    "applies_in_flight_per_field": P * B, "contexts_per_field": P, "sources_per_call": B,
