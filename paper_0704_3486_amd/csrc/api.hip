@@ -371,9 +371,9 @@ static int run_apply_impl(sgn_ctx* c, const double2* x_abi, double2* y_abi, doub
         else
           krylov_dot<double2>(c->kw, ka, false, s, prof);
         krylov_patch(c->kw, ka, n, c->F, 0, true, s);
-        it = dense_sign(c->dense, n, c->F, n, c->F, n, s, prof);
+        it = dense_sign(c->dense, n, c->F, n, c->F, n, s, prof, c->cheb_e);
       } else {
-        it = dense_sign(c->dense, n, c->Hc, ncap, c->F, n, s, prof);
+        it = dense_sign(c->dense, n, c->Hc, ncap, c->F, n, s, prof, c->cheb_e);
       }
     }
     newton_total += it;

@@ -585,7 +585,7 @@ int run_batch_block(sgn_ctx* c, int nr, const double2* X_abi, double2* Y_abi, do
         KrylovArgs kc = base;
         fill(kc, slots, k);
         krylov_patch(b.kw, kc, n, Apat, nn, false, s);
-        const int it = dense_sign_batched(b.dense, n, nb, Apat, n, nn, Fout, n, nn, s, prof);
+        const int it = dense_sign_batched(b.dense, n, nb, Apat, n, nn, Fout, n, nn, s, prof, c->cheb_e);
         newton_total += std::max(it, 0);
       }
       SlotMap cm;

@@ -600,10 +600,10 @@ __global__ void __launch_bounds__(256) colsum_kernel(const double2* __restrict__
 }
 
 // X = A / |A|_1 (the 1-norm as the largest column sum; every workgroup takes
-// the maximum itself)
+// the maximum itself), or A / max(radius, |A|_1 / 2) for a smaller radius
 __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __restrict__ A, int lda, size_t astride,
                                                              const double* __restrict__ cs, double2* __restrict__ X,
-                                                             int n, size_t nn) {
+                                                             int n, size_t nn, double radius) {
   const int b = blockIdx.y;
   __shared__ double red[256];
   double mx = 0.0;
@@ -614,7 +614,11 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
     if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
-  const double inv = red[0] > 0.0 ? 1.0 / red[0] : 1.0;
+  // the divisor: |A|_1, or the radius estimate when it is smaller (but not
+  // below half the 1-norm)
+  const double n1 = red[0];
+  const double div = (radius > 0.0 && radius < n1) ? fmax(radius, 0.5 * n1) : n1;
+  const double inv = div > 0.0 ? 1.0 / div : 1.0;
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nn) return;
   const int j = (int)(e / n), i = (int)(e - (size_t)j * n);
@@ -659,7 +663,8 @@ static void ns_reserve(DenseWork& d, int n, int nb) {
 // matrices whose iteration met the stopping test (their F_b is written); the
 // others diverged or did not settle within the iteration limit.
 static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F,
-                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done) {
+                                 int ldf, size_t fstride, hipStream_t s, Profiler* prof, unsigned long long& done,
+                                 double radius) {
   SGN_REQUIRE(nb <= kMaxBatch, SGN_EINVAL, "dense_sign: batch too large");
   dense_alloc(d, n, nb);
   const size_t nn = (size_t)n * n;
@@ -670,7 +675,7 @@ static int dense_sign_ns_batched(DenseWork& d, int n, int nb, const double2* A, 
   hipLaunchKernelGGL(colsum_kernel, dim3((n + 3) / 4, nb), dim3(256), 0, s, A, lda, astride, d.spart, n);
   SGN_HIP(hipGetLastError());
   hipLaunchKernelGGL(scale_by_norm1_kernel, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, s, A, lda, astride,
-                     d.spart, d.S, n, nn);
+                     d.spart, d.S, n, nn, radius);
   SGN_HIP(hipGetLastError());
   hipLaunchKernelGGL(ns_init_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, state, iters, nb);
   SGN_HIP(hipGetLastError());
@@ -731,11 +736,11 @@ void dense_reserve(DenseWork& d, int n, int nb) {
 }
 
 int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,
-                       size_t fstride, hipStream_t s, Profiler* prof) {
+                       size_t fstride, hipStream_t s, Profiler* prof, double radius) {
   SGN_REQUIRE(n >= 1 && nb >= 1, SGN_EINVAL, "dense_sign: n and the batch must be positive");
   if (d.method == 1) return dense_sign_newton_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof);
   unsigned long long done = 0;
-  int it = dense_sign_ns_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof, done);
+  int it = dense_sign_ns_batched(d, n, nb, A, lda, astride, F, ldf, fstride, s, prof, done, radius);
   // Roberts' iteration for each matrix Newton-Schulz did not settle, one at a
   // time (as it would run for that matrix alone)
   for (int b = 0; b < nb; ++b)
@@ -746,6 +751,6 @@ int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, s
 }
 
 int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
-               Profiler* prof) {
-  return dense_sign_batched(d, n, 1, A, lda, 0, F, ldf, 0, s, prof);
+               Profiler* prof, double radius) {
+  return dense_sign_batched(d, n, 1, A, lda, 0, F, ldf, 0, s, prof, radius);
 }

@@ -288,13 +288,20 @@ void dense_destroy(DenseWork& d);
 // allocate everything dense_sign_batched needs up to order n and batch nb,
 // so that later calls of at most that size allocate nothing
 void dense_reserve(DenseWork& d, int n, int nb);
-// F = sgn(A) (n x n, ld = lda); returns iterations; throws SGN_ESINGULAR
+// F = sgn(A) (n x n, ld = lda); returns iterations; throws SGN_ESINGULAR.
+// radius: an estimate of the spectral radius of A's eigenvalues of largest
+// modulus (0: none); see dense_sign_batched
 int dense_sign(DenseWork& d, int n, const double2* A, int lda, double2* F, int ldf, hipStream_t s,
-               Profiler* prof);
+               Profiler* prof, double radius = 0.0);
 // F_b = sgn(A_b) for nb <= kMaxBatch matrices at strides astride / fstride;
-// each matrix stops on its own test, so F_b is bitwise the single-matrix result
+// each matrix stops on its own test, so F_b is bitwise the single-matrix result.
+// The Newton-Schulz start X_0 = A / |A|_1, or A / max(radius, |A|_1 / 2)
+// when 0 < radius < |A|_1: the composite Arnoldi matrices' largest Ritz
+// values sit near the operator's spectral radius, well below the 1-norm, and
+// the smaller divisor saves the steps that grow the small eigenvalues (a
+// start outside the iteration's basin is caught and falls back to Roberts)
 int dense_sign_batched(DenseWork& d, int n, int nb, const double2* A, int lda, size_t astride, double2* F, int ldf,
-                       size_t fstride, hipStream_t s, Profiler* prof);
+                       size_t fstride, hipStream_t s, Profiler* prof, double radius = 0.0);
 // c[i] = sum_{q<m} F[i][q] c0[q] + beta * F[i][m]  (i < n); err = |c - cprev_pad| / |c| if cprev
 void dense_coeffs(int n, int m, const double2* F, int ldf, const double2* c0, const double* beta, double2* c,
                   const double2* cprev, int nprev, double* err, hipStream_t s);
