@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(256) colsum_kernel(const double2* __restrict__
 }
 
 // X = A / |A|_1 (the 1-norm as the largest column sum; every workgroup takes
-// the maximum itself), or A / max(radius, |A|_1 / 2) for a smaller radius
+// the maximum itself), or A / max(radius, |A|_1 / 1.5) for a smaller radius
 __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __restrict__ A, int lda, size_t astride,
                                                              const double* __restrict__ cs, double2* __restrict__ X,
                                                              int n, size_t nn, double radius) {
@@ -614,10 +614,12 @@ __global__ void __launch_bounds__(256) scale_by_norm1_kernel(const double2* __re
     if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
-  // the divisor: |A|_1, or the radius estimate when it is smaller (but not
-  // below half the 1-norm)
+  // the divisor: |A|_1, or the radius estimate when it is smaller but not
+  // below 2/3 of the 1-norm: every eigenvalue then has |z| <= 1.5 < sqrt(3),
+  // and a real z in (0, sqrt(3)) stays positive under z (3 - z^2) / 2, so a
+  // radius estimate that is too small cannot turn a real eigenvalue's sign
   const double n1 = red[0];
-  const double div = (radius > 0.0 && radius < n1) ? fmax(radius, 0.5 * n1) : n1;
+  const double div = (radius > 0.0 && radius < n1) ? fmax(radius, n1 / 1.5) : n1;
   const double inv = div > 0.0 ? 1.0 / div : 1.0;
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nn) return;
