@@ -67,6 +67,9 @@ constexpr int kUnroll = 8;
 // per wavefront (sharing the block-vector loads)
 constexpr int kMinRowsPerWave = 128;
 constexpr int kDotTiles = 2;
+// tiles per wavefront of the three-multiplication dot pass (more vectors per
+// tile: the block-vector loads shared by four tiles)
+constexpr int kDot3Tiles = 4;
 
 // the composite basis of one launch: column c < m is S[c], column c >= m of
 // slot r is V_r[c - m] (V_r = V + r vstride), all with leading dimension ldq
@@ -286,42 +289,42 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   const int r0 = (chunk * 4 + wave) * a.rpw;
   const int r1 = min(r0 + a.rpw, g.N);
   const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
-  gptr qp[kDotTiles];
+  gptr qp[kDot3Tiles];
 #pragma unroll
-  for (int t = 0; t < kDotTiles; ++t) {
-    const int cc = min((cg * kDotTiles + t) * 16 + li, a.ncol - 1);
+  for (int t = 0; t < kDot3Tiles; ++t) {
+    const int cc = min((cg * kDot3Tiles + t) * 16 + li, a.ncol - 1);
     qp[t] = to_global((cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk);
   }
   const bool vok = li < g.s;
   gptr wp = to_global(vok ? Wr + (size_t)li * g.ldq + r0 + lk : &sgn_block_zero_entry);
   const int dw = vok ? 4 : 0;
-  v4d t1[kDotTiles], t2[kDotTiles], t3[kDotTiles];
+  v4d t1[kDot3Tiles], t2[kDot3Tiles], t3[kDot3Tiles];
 #pragma unroll
-  for (int t = 0; t < kDotTiles; ++t) {
+  for (int t = 0; t < kDot3Tiles; ++t) {
     t1[t] = v4d{0.0, 0.0, 0.0, 0.0};
     t2[t] = v4d{0.0, 0.0, 0.0, 0.0};
     t3[t] = v4d{0.0, 0.0, 0.0, 0.0};
   }
   // groups of U k-steps, the loads of the next group issued before the
   // products of the current one (two register sets)
-  constexpr int U = kUnroll / 2;
-  auto load = [&](double2 (&qv)[U][kDotTiles], double2 (&wv)[U]) {
+  constexpr int U = kUnroll / 4;
+  auto load = [&](double2 (&qv)[U][kDot3Tiles], double2 (&wv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < kDotTiles; ++t) qv[u][t] = gload(qp[t] + 4 * u);
+      for (int t = 0; t < kDot3Tiles; ++t) qv[u][t] = gload(qp[t] + 4 * u);
       wv[u] = gload(wp + dw * u);
     }
 #pragma unroll
-    for (int t = 0; t < kDotTiles; ++t) qp[t] += 4 * U;
+    for (int t = 0; t < kDot3Tiles; ++t) qp[t] += 4 * U;
     wp += U * dw;
   };
-  auto mul = [&](const double2 (&qv)[U][kDotTiles], const double2 (&wv)[U]) {
+  auto mul = [&](const double2 (&qv)[U][kDot3Tiles], const double2 (&wv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const double ws = wv[u].x + wv[u].y;
 #pragma unroll
-      for (int t = 0; t < kDotTiles; ++t) {
+      for (int t = 0; t < kDot3Tiles; ++t) {
         t1[t] = mfma(wv[u].x, qv[u][t].x, t1[t]);
         t2[t] = mfma(wv[u].y, qv[u][t].y, t2[t]);
         t3[t] = mfma(ws, qv[u][t].x - qv[u][t].y, t3[t]);
@@ -330,7 +333,7 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   };
   int it = 0;
   {
-    double2 qa[U][kDotTiles], wa[U], qb[U][kDotTiles], wb[U];
+    double2 qa[U][kDot3Tiles], wa[U], qb[U][kDot3Tiles], wb[U];
     if (nit >= U) load(qa, wa);
     for (; it + 2 * U <= nit; it += 2 * U) {
       load(qb, wb);
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
     const double2 wv = gload(wp);
     const double ws = wv.x + wv.y;
 #pragma unroll
-    for (int t = 0; t < kDotTiles; ++t) {
+    for (int t = 0; t < kDot3Tiles; ++t) {
       const double2 qv = gload(qp[t]);
       t1[t] = mfma(wv.x, qv.x, t1[t]);
       t2[t] = mfma(wv.y, qv.y, t2[t]);
@@ -357,10 +360,10 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
     wp += dw;
   }
   // lane (j = li, lk): item q holds vector lk + 4 q of column j
-  __shared__ double2 red[4][64][4 * kDotTiles];
-  double2 cs[kDotTiles][4];
+  __shared__ double2 red[4][64][4 * kDot3Tiles];
+  double2 cs[kDot3Tiles][4];
 #pragma unroll
-  for (int t = 0; t < kDotTiles; ++t)
+  for (int t = 0; t < kDot3Tiles; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       cs[t][q] = make_double2(t1[t][q] + t2[t][q], t3[t][q] - t1[t][q] + t2[t][q]);
@@ -369,8 +372,8 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   __syncthreads();
   if (wave != 0) return;
 #pragma unroll
-  for (int t = 0; t < kDotTiles; ++t) {
-    const int c = (cg * kDotTiles + t) * 16 + li;
+  for (int t = 0; t < kDot3Tiles; ++t) {
+    const int c = (cg * kDot3Tiles + t) * 16 + li;
     if (c >= a.ncol) continue;
     double2* o = a.part + (size_t)r * a.pstride + ((size_t)chunk * a.ncol + c) * kBlockMax;
 #pragma unroll
@@ -1059,7 +1062,8 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
   // more than 8 block vectors: the products in their three-multiplication form
   const bool gauss = sb > 8;
   auto dot = [&](double2* C, int ncol, const double2* C1, double2* Ct) {
-    const int ncg = (ncol + 16 * kDotTiles - 1) / (16 * kDotTiles);
+    const int tiles = gauss ? kDot3Tiles : kDotTiles;
+    const int ncg = (ncol + 16 * tiles - 1) / (16 * tiles);
     BDot d{b.W, b.wstride, ncol, rpw, ncg, nch, b.part, b.pstride};
     // the basis read once (S once for the launch, the slots' own columns and
     // W as columns per slot), W once per slot, partials written
