@@ -51,7 +51,7 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_KERNELS = {"krylov_update": "kupdate_kernel<double2>", "krylov_dot": "kdot_kernel<double2>",
                "krylov_reduce": "kred_kernel", "wilson_hw": "wilson_hw_dir_kernel<double2, false>"}
 # the same for the block (s-step) process
-HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel<false>", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
+HBM_KERNELS_BLOCK = {"block_update": "bupdate_kernel<false, 1>", "block_dot": "bdot_kernel", "block_reduce": "bred_kernel",
                      "block_factor": "bsmall_kernel<false>", "wilson_hw": "wilson_hw_dir_kernel<double2, true>"}
 BLOCK_STEPS = 16  # Arnoldi steps per block of the headline applies (sgn_set_block_steps)
 BATCH = 8  # sources per batched apply call of each context in the timed region
@@ -367,7 +367,8 @@ def main():
     if args.block_steps:
         kmap = dict(HBM_KERNELS_BLOCK)
         if args.block_steps > 8:  # the three-multiplication forms of the sweeps
-            kmap.update({"block_dot": "bdot3_kernel", "block_update": "bupdate_kernel<true>",
+            kmap.update({"block_dot": "bdot3_kernel<4>" if B >= 4 else "bdot3_kernel<2>",
+                         "block_update": "bupdate_kernel<true, 2>" if B >= 4 else "bupdate_kernel<true, 1>",
                          "block_factor": "bsmall_kernel<true>"})
     hbm_kernels = {k: v for k, v in kern.items() if k in kmap}
     dom = max(hbm_kernels, key=lambda k: hbm_kernels[k]["total_ms"]) if hbm_kernels else None

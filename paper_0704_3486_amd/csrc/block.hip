@@ -67,9 +67,13 @@ constexpr int kUnroll = 8;
 // per wavefront (sharing the block-vector loads)
 constexpr int kMinRowsPerWave = 128;
 constexpr int kDotTiles = 2;
-// tiles per wavefront of the three-multiplication dot pass (more vectors per
-// tile: the block-vector loads shared by four tiles)
+// tiles per wavefront of the three-multiplication dot pass in a launch of
+// several slots (the block-vector loads shared by four tiles; a single slot
+// keeps two, for twice the workgroups)
 constexpr int kDot3Tiles = 4;
+constexpr int kDot3TilesSingle = 2;
+// slots from which a launch takes the wide tiles (dot) and row blocks (update)
+constexpr int kWideFrom = 4;
 
 // the composite basis of one launch: column c < m is S[c], column c >= m of
 // slot r is V_r[c - m] (V_r = V + r vstride), all with leading dimension ldq
@@ -276,6 +280,7 @@ __global__ void __launch_bounds__(256) bdot_kernel(BlockGeo g, BDot a) {
 //   T1 = Wr^T Re(Q),  T2 = Wi^T Im(Q),  T3 = (Wr + Wi)^T (Re(Q) - Im(Q)),
 //   Re C = T1 + T2,  Im C = T3 - T1 + T2,
 // a quarter fewer matrix-core instructions than two halves of 8.
+template <int T>
 __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   int chunk, inner;
   if (!xcd_tile(blockIdx.x, g.nb * a.ncg, a.nch, chunk, inner)) return;
@@ -289,18 +294,18 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   const int r0 = (chunk * 4 + wave) * a.rpw;
   const int r1 = min(r0 + a.rpw, g.N);
   const int nit = r1 > r0 ? (r1 - r0) >> 2 : 0;
-  gptr qp[kDot3Tiles];
+  gptr qp[T];
 #pragma unroll
-  for (int t = 0; t < kDot3Tiles; ++t) {
-    const int cc = min((cg * kDot3Tiles + t) * 16 + li, a.ncol - 1);
+  for (int t = 0; t < T; ++t) {
+    const int cc = min((cg * T + t) * 16 + li, a.ncol - 1);
     qp[t] = to_global((cc < g.p ? qcol(g.S, Vr, g.m, g.ldq, cc) : Wr + (size_t)(cc - g.p) * g.ldq) + r0 + lk);
   }
   const bool vok = li < g.s;
   gptr wp = to_global(vok ? Wr + (size_t)li * g.ldq + r0 + lk : &sgn_block_zero_entry);
   const int dw = vok ? 4 : 0;
-  v4d t1[kDot3Tiles], t2[kDot3Tiles], t3[kDot3Tiles];
+  v4d t1[T], t2[T], t3[T];
 #pragma unroll
-  for (int t = 0; t < kDot3Tiles; ++t) {
+  for (int t = 0; t < T; ++t) {
     t1[t] = v4d{0.0, 0.0, 0.0, 0.0};
     t2[t] = v4d{0.0, 0.0, 0.0, 0.0};
     t3[t] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -308,23 +313,23 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   // groups of U k-steps, the loads of the next group issued before the
   // products of the current one (two register sets)
   constexpr int U = kUnroll / 4;
-  auto load = [&](double2 (&qv)[U][kDot3Tiles], double2 (&wv)[U]) {
+  auto load = [&](double2 (&qv)[U][T], double2 (&wv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < kDot3Tiles; ++t) qv[u][t] = gload(qp[t] + 4 * u);
+      for (int t = 0; t < T; ++t) qv[u][t] = gload(qp[t] + 4 * u);
       wv[u] = gload(wp + dw * u);
     }
 #pragma unroll
-    for (int t = 0; t < kDot3Tiles; ++t) qp[t] += 4 * U;
+    for (int t = 0; t < T; ++t) qp[t] += 4 * U;
     wp += U * dw;
   };
-  auto mul = [&](const double2 (&qv)[U][kDot3Tiles], const double2 (&wv)[U]) {
+  auto mul = [&](const double2 (&qv)[U][T], const double2 (&wv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const double ws = wv[u].x + wv[u].y;
 #pragma unroll
-      for (int t = 0; t < kDot3Tiles; ++t) {
+      for (int t = 0; t < T; ++t) {
         t1[t] = mfma(wv[u].x, qv[u][t].x, t1[t]);
         t2[t] = mfma(wv[u].y, qv[u][t].y, t2[t]);
         t3[t] = mfma(ws, qv[u][t].x - qv[u][t].y, t3[t]);
@@ -333,7 +338,7 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   };
   int it = 0;
   {
-    double2 qa[U][kDot3Tiles], wa[U], qb[U][kDot3Tiles], wb[U];
+    double2 qa[U][T], wa[U], qb[U][T], wb[U];
     if (nit >= U) load(qa, wa);
     for (; it + 2 * U <= nit; it += 2 * U) {
       load(qb, wb);
@@ -350,7 +355,7 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
     const double2 wv = gload(wp);
     const double ws = wv.x + wv.y;
 #pragma unroll
-    for (int t = 0; t < kDot3Tiles; ++t) {
+    for (int t = 0; t < T; ++t) {
       const double2 qv = gload(qp[t]);
       t1[t] = mfma(wv.x, qv.x, t1[t]);
       t2[t] = mfma(wv.y, qv.y, t2[t]);
@@ -360,10 +365,10 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
     wp += dw;
   }
   // lane (j = li, lk): item q holds vector lk + 4 q of column j
-  __shared__ double2 red[4][64][4 * kDot3Tiles];
-  double2 cs[kDot3Tiles][4];
+  __shared__ double2 red[4][64][4 * T];
+  double2 cs[T][4];
 #pragma unroll
-  for (int t = 0; t < kDot3Tiles; ++t)
+  for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       cs[t][q] = make_double2(t1[t][q] + t2[t][q], t3[t][q] - t1[t][q] + t2[t][q]);
@@ -372,8 +377,8 @@ __global__ void __launch_bounds__(256) bdot3_kernel(BlockGeo g, BDot a) {
   __syncthreads();
   if (wave != 0) return;
 #pragma unroll
-  for (int t = 0; t < kDot3Tiles; ++t) {
-    const int c = (cg * kDot3Tiles + t) * 16 + li;
+  for (int t = 0; t < T; ++t) {
+    const int c = (cg * T + t) * 16 + li;
     if (c >= a.ncol) continue;
     double2* o = a.part + (size_t)r * a.pstride + ((size_t)chunk * a.ncol + c) * kBlockMax;
 #pragma unroll
@@ -503,39 +508,51 @@ __device__ inline void qc_steps(const double2* __restrict__ S, const double2* __
 // column's coefficient for block vector li (B fragment);
 //   T1 = Re(Q) Re(C),  T2 = Im(Q) Im(C),  T3 = (Re Q + Im Q)(Re C + Im C),
 //   Re(Q C) = T1 - T2,  Im(Q C) = T3 - T1 - T2
-// for the 16 rows (rows lk + 4 t in item t) and vector li.
+// for the 16 rows (rows lk + 4 t in item t) and vector li.  RB blocks of 16
+// rows (rows[b]: this lane's row of block b) share each coefficient load.
+template <int RB>
 __device__ inline void qc_steps3(const double2* __restrict__ S, const double2* __restrict__ Vr, int m, size_t ldq,
-                                 int row, int ncol, const double2* __restrict__ C, int s, int li, int lk, int k0,
-                                 int dk, v4d& t1, v4d& t2, v4d& t3) {
+                                 const int (&rows)[RB], int ncol, const double2* __restrict__ C, int s, int li,
+                                 int lk, int k0, int dk, v4d (&t1)[RB], v4d (&t2)[RB], v4d (&t3)[RB]) {
   const gptr zero = to_global(&sgn_block_zero_entry);
   const int nk = (ncol + 3) >> 2;
   const bool vok = li < s;
   int ks = k0;
-  constexpr int U = kUnroll / 2;
+  constexpr int U = kUnroll / (2 * RB);
   for (; ks + (U - 1) * dk < nk; ks += U * dk) {
-    double2 qv[U], cv[U];
+    double2 qv[U][RB], cv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int col = 4 * (ks + u * dk) + lk;
       const bool ok = col < ncol;
-      qv[u] = gload(ok ? to_global(qcol(S, Vr, m, ldq, col) + row) : zero);
+      const double2* qc = qcol(S, Vr, m, ldq, col);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) qv[u][b] = gload(ok ? to_global(qc + rows[b]) : zero);
       cv[u] = gload((ok & vok) ? to_global(C + (size_t)col * kBlockMax + li) : zero);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      t1 = mfma(qv[u].x, cv[u].x, t1);
-      t2 = mfma(qv[u].y, cv[u].y, t2);
-      t3 = mfma(qv[u].x + qv[u].y, cv[u].x + cv[u].y, t3);
+      const double cs = cv[u].x + cv[u].y;
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        t1[b] = mfma(qv[u][b].x, cv[u].x, t1[b]);
+        t2[b] = mfma(qv[u][b].y, cv[u].y, t2[b]);
+        t3[b] = mfma(qv[u][b].x + qv[u][b].y, cs, t3[b]);
+      }
     }
   }
   for (; ks < nk; ks += dk) {
     const int col = 4 * ks + lk;
     const bool ok = col < ncol;
-    const double2 qv = gload(ok ? to_global(qcol(S, Vr, m, ldq, col) + row) : zero);
+    const double2* qc = qcol(S, Vr, m, ldq, col);
     const double2 cv = gload((ok & vok) ? to_global(C + (size_t)col * kBlockMax + li) : zero);
-    t1 = mfma(qv.x, cv.x, t1);
-    t2 = mfma(qv.y, cv.y, t2);
-    t3 = mfma(qv.x + qv.y, cv.x + cv.y, t3);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const double2 qv = gload(ok ? to_global(qc + rows[b]) : zero);
+      t1[b] = mfma(qv.x, cv.x, t1[b]);
+      t2[b] = mfma(qv.y, cv.y, t2[b]);
+      t3[b] = mfma(qv.x + qv.y, cv.x + cv.y, t3[b]);
+    }
   }
 }
 
@@ -613,8 +630,11 @@ struct BUpd {
   BHess hess;
 };
 
-template <bool G>
+template <bool G, int RB>
 __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
+  // RB blocks of 16 rows per wavefront, sharing each coefficient load (the
+  // three-multiplication form only; the packed form takes one)
+  static_assert(G || RB == 1, "row blocks need the three-multiplication form");
   int z, bid;
   if (!xcd_tile(blockIdx.x, g.nb, a.nrowblk + a.nhess, bid, z)) return;
   const int rs = g.act[z];
@@ -629,31 +649,43 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = (bid * 4 + wave) * 16;
+  const int r0 = (bid * 4 + wave) * 16 * RB;
   const bool active = r0 < g.N;  // wavefront-uniform
-  const int row = min(r0 + li, g.N - 1);
   const int v = li & 7;
-  // res[h][t]: (Q C)[row r0 + lk + 4 t][vector vec(h)] in the lanes that own one
-  double2 res[kHalves][4];
+  // res[b][h][t]: (Q C)[row r0 + 16 b + lk + 4 t][vector vec(h)] in the lanes
+  // that own one
+  double2 res[RB][kHalves][4];
   bool own[kHalves];
   int vec[kHalves];
   if constexpr (G) {
-    v4d t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
-    if (active) qc_steps3(g.S, Vr, g.m, g.ldq, row, g.p, Cr, g.s, li, lk, 0, 1, t1, t2, t3);
+    v4d t1[RB], t2[RB], t3[RB];
+    int rows[RB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) res[0][t] = make_double2(t1[t] - t2[t], t3[t] - t1[t] - t2[t]);
+    for (int b = 0; b < RB; ++b) {
+      t1[b] = v4d{0.0, 0.0, 0.0, 0.0};
+      t2[b] = t1[b];
+      t3[b] = t1[b];
+      rows[b] = min(r0 + 16 * b + li, g.N - 1);
+    }
+    if (active) qc_steps3<RB>(g.S, Vr, g.m, g.ldq, rows, g.p, Cr, g.s, li, lk, 0, 1, t1, t2, t3);
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        res[b][0][t] = make_double2(t1[b][t] - t2[b][t], t3[b][t] - t1[b][t] - t2[b][t]);
     own[0] = li < g.s;
     vec[0] = li;
 #pragma unroll
     for (int h = 1; h < kHalves; ++h) own[h] = false;
   } else {
+    const int row = min(r0 + li, g.N - 1);
     v4d d[kHalves];
 #pragma unroll
     for (int h = 0; h < kHalves; ++h) d[h] = v4d{0.0, 0.0, 0.0, 0.0};
     if (active) qc_steps(g.S, Vr, g.m, g.ldq, row, g.p, Cr, v, li >= 8, g.s, lk, 0, 1, d);
 #pragma unroll
     for (int h = 0; h < kHalves; ++h) {
-      qc_pairs(d[h], res[h]);
+      qc_pairs(d[h], res[0][h]);
       vec[h] = 8 * h + v;
       own[h] = li < 8 && vec[h] < g.s;
     }
@@ -661,22 +693,24 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   if (!a.Rinv) {
     if (active)
 #pragma unroll
-      for (int h = 0; h < kHalves; ++h) {
-        if (!own[h]) continue;
+      for (int b = 0; b < RB; ++b)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int rr = r0 + lk + 4 * t;
-          if (rr < g.N) {
-            const size_t o = (size_t)vec[h] * g.ldq + rr;
-            Wout[o] = csub(Win[o], res[h][t]);
+        for (int h = 0; h < kHalves; ++h) {
+          if (!own[h]) continue;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int rr = r0 + 16 * b + lk + 4 * t;
+            if (rr < g.N) {
+              const size_t o = (size_t)vec[h] * g.ldq + rr;
+              Wout[o] = csub(Win[o], res[b][h][t]);
+            }
           }
         }
-      }
     return;
   }
   // second pass: W'' = Win - Q C, then W'' Rinv per row (through LDS; the
   // workgroup's slot is the same for all four wavefronts)
-  __shared__ double2 tile[4][16][kBlockMax];
+  __shared__ double2 tile[4][16 * RB][kBlockMax];
   __shared__ double2 ri[kBlockMax * kBlockMax];
   {
     const double2* Ri = a.Rinv + (size_t)rs * a.rstride;
@@ -684,21 +718,23 @@ __global__ void __launch_bounds__(256) bupdate_kernel(BlockGeo g, BUpd a) {
   }
   // every (row, vector) of the tile: vectors past s and rows past N as zero
 #pragma unroll
-  for (int h = 0; h < kHalves; ++h) {
-    const bool writer = G ? h == 0 : li < 8;
-    if (!writer) continue;
-    const int vv = G ? li : 8 * h + v;
+  for (int b = 0; b < RB; ++b)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int rr = r0 + lk + 4 * t;
-      double2 val = make_double2(0.0, 0.0);
-      if (active && own[h] && rr < g.N) val = csub(Win[(size_t)vv * g.ldq + rr], res[h][t]);
-      tile[wave][lk + 4 * t][vv] = val;
+    for (int h = 0; h < kHalves; ++h) {
+      const bool writer = G ? h == 0 : li < 8;
+      if (!writer) continue;
+      const int vv = G ? li : 8 * h + v;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int rl = 16 * b + lk + 4 * t, rr = r0 + rl;
+        double2 val = make_double2(0.0, 0.0);
+        if (active && own[h] && rr < g.N) val = csub(Win[(size_t)vv * g.ldq + rr], res[b][h][t]);
+        tile[wave][rl][vv] = val;
+      }
     }
-  }
   __syncthreads();
   if (!active) return;
-  constexpr int kOut = 16 * kBlockMax / 64;  // outputs per lane
+  constexpr int kOut = 16 * RB * kBlockMax / 64;  // outputs per lane
   // (not unrolled: this epilogue would otherwise set the kernel's register
   // count, and with it the occupancy of the sweep above)
 #pragma unroll 1
@@ -922,25 +958,27 @@ __global__ void __launch_bounds__(256) bsmall_kernel(BlockGeo g, BSmall a) {
   double2* P = a.P + (size_t)rs * a.cstride;
   // only the columns 0 .. s-2 of Ct enter P
   if constexpr (G) {
-    v4d t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
-    qc_steps3(H, H, 0, (size_t)a.ldh, row, p - 1, Ct, g.s - 1, li, lk, (c0 >> 2) + wave, 4, t1, t2, t3);
+    v4d t1[1] = {v4d{0.0, 0.0, 0.0, 0.0}}, t2[1] = {t1[0]}, t3[1] = {t1[0]};
+    const int rows[1] = {row};
+    qc_steps3<1>(H, H, 0, (size_t)a.ldh, rows, p - 1, Ct, g.s - 1, li, lk, (c0 >> 2) + wave, 4, t1, t2, t3);
     __shared__ v4d red3[4][3][64];
-    red3[wave][0][lane] = t1;
-    red3[wave][1][lane] = t2;
-    red3[wave][2][lane] = t3;
+    red3[wave][0][lane] = t1[0];
+    red3[wave][1][lane] = t2[0];
+    red3[wave][2][lane] = t3[0];
     __syncthreads();
     if (wave != 0) return;
+    v4d u1 = t1[0], u2 = t2[0], u3 = t3[0];
 #pragma unroll
     for (int w = 1; w < 4; ++w) {
-      t1 += red3[w][0][lane];
-      t2 += red3[w][1][lane];
-      t3 += red3[w][2][lane];
+      u1 += red3[w][0][lane];
+      u2 += red3[w][1][lane];
+      u3 += red3[w][2][lane];
     }
     if (li < g.s - 1)
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int rr = r0 + lk + 4 * tt;
-        if (rr < p) P[(size_t)li * a.ldp + rr] = make_double2(t1[tt] - t2[tt], t3[tt] - t1[tt] - t2[tt]);
+        if (rr < p) P[(size_t)li * a.ldp + rr] = make_double2(u1[tt] - u2[tt], u3[tt] - u1[tt] - u2[tt]);
       }
   } else {
     v4d d[kHalves];
@@ -1061,30 +1099,39 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
   const int nch = nchunks_for(N, rpw);
   // more than 8 block vectors: the products in their three-multiplication form
   const bool gauss = sb > 8;
+  // launches of several slots: four column tiles per dot wavefront and two
+  // blocks of 16 rows per update wavefront (three-multiplication form); the
+  // arithmetic of every entry is the same either way
+  const bool wide = gauss && nb >= kWideFrom;
+  const int tiles = !gauss ? kDotTiles : wide ? kDot3Tiles : kDot3TilesSingle;
+  void (*dot_kernel)(BlockGeo, BDot) =
+      !gauss ? bdot_kernel : wide ? bdot3_kernel<kDot3Tiles> : bdot3_kernel<kDot3TilesSingle>;
+  const int rb = wide ? 2 : 1;
+  void (*upd_kernel)(BlockGeo, BUpd) =
+      !gauss ? bupdate_kernel<false, 1> : wide ? bupdate_kernel<true, 2> : bupdate_kernel<true, 1>;
   auto dot = [&](double2* C, int ncol, const double2* C1, double2* Ct) {
-    const int tiles = gauss ? kDot3Tiles : kDotTiles;
     const int ncg = (ncol + 16 * tiles - 1) / (16 * tiles);
     BDot d{b.W, b.wstride, ncol, rpw, ncg, nch, b.part, b.pstride};
     // the basis read once (S once for the launch, the slots' own columns and
     // W as columns per slot), W once per slot, partials written
     const double bytes =
         16.0 * N * ((double)m + (double)nb * (ncol - m + sb)) + 16.0 * nch * ncol * kBlockMax * (double)nb;
-    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, gauss ? bdot3_kernel : bdot_kernel,
-                dim3(xcd_grid(nb * ncg, nch)), dim3(256), 0, s, g, d);
+    prof_launch(prof, K_BDOT, bytes, 8.0 * N * ncol * sb * nb, dot_kernel, dim3(xcd_grid(nb * ncg, nch)), dim3(256),
+                0, s, g, d);
     const int nent = ncol * kBlockMax, nblk = (nent + 31) / 32;
     BRed rd{b.part, b.pstride, nch, nent, nblk, C, C1, Ct, b.cstride, b.G, b.gstride};
     prof_launch(prof, K_BRED, (16.0 * (double)nch * nent + 16.0 * nent) * nb, 2.0 * nch * nent * nb, bred_kernel,
                 dim3(nblk * nb), dim3(256), 0, s, g, rd);
   };
-  const int nrowblk = (N + 63) / 64;
+  const int nrowblk = (N + 64 * rb - 1) / (64 * rb);
   // the basis (S once for the launch), W read and written, the coefficients
   const double upd_bytes = 16.0 * N * ((double)m + (double)nb * (p - m + 2.0 * sb)) + 16.0 * p * sb * (double)nb;
   // pass 1
   dot(b.C1, p, nullptr, nullptr);
   {
     BUpd u{b.C1, b.cstride, b.W, b.wstride, b.W, b.wstride, nullptr, 0, nrowblk, 0, BHess{}};
-    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, gauss ? bupdate_kernel<true> : bupdate_kernel<false>, dim3(xcd_grid(nb, nrowblk)),
-                dim3(256), 0, s, g, u);
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, upd_kernel, dim3(xcd_grid(nb, nrowblk)), dim3(256),
+                0, s, g, u);
   }
   // pass 2 with the Gram matrix of the projected block
   dot(b.C2, p + sb, b.C1, b.Ct);
@@ -1100,8 +1147,7 @@ void block_step(const BlockSpan& sp, BlockWork& b, const Lattice& lat, const dou
     const int nh = ((p + sb) * kBlockMax + 255) / 256;
     BUpd u{b.C2, b.cstride, b.W, b.wstride, const_cast<double2*>(sp.V) + (size_t)(p - m) * ldq, sp.vstride,
            b.R + kBlockMax * kBlockMax, b.rstride, nrowblk, nh, h};
-    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, gauss ? bupdate_kernel<true> : bupdate_kernel<false>,
-                dim3(xcd_grid(nb, nrowblk + nh)),
+    prof_launch(prof, K_BUPDATE, upd_bytes, 8.0 * N * p * sb * nb, upd_kernel, dim3(xcd_grid(nb, nrowblk + nh)),
                 dim3(256), 0, s, g, u);
   }
 }
