@@ -34,11 +34,12 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-# per-file additions: the block sweeps keep their matrix-core accumulators in
-# ordinary VGPRs (otherwise the loop-carried accumulators of the dot pass's
-# four tiles are copied to and from the AGPRs on every iteration, and the
-# kernel's register count allows one wavefront per SIMD)
-FILE_FLAGS = {"block.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# per-file additions: the block sweeps and the small-sign products keep their
+# matrix-core accumulators in ordinary VGPRs (otherwise loop-carried
+# accumulators are copied to and from the AGPRs on every iteration, and the
+# widest kernels' register counts allow one wavefront per SIMD)
+_VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+FILE_FLAGS = {"block.hip": _VGPR_FORM, "zgemm.hip": _VGPR_FORM}
 
 
 def _compile(src):

@@ -11,10 +11,11 @@
 // matrices live in L2; a lane loads one complex entry per fragment, rows of
 // A and columns of B 16 entries apart), two k-steps ahead of the products,
 // clamped at the matrix edges and zeroed outside.  Three launch shapes by
-// the number of 16 x 16 output blocks: for a few hundred blocks the four
-// wavefronts of a workgroup split the k-steps of one block (summed in a
-// fixed order through LDS); otherwise 2 x 2 wavefronts each own 1 x 1 or
-// 2 x 2 blocks.  blockIdx.z selects the matrix of a batch.  The shape
+// the number of 16 x 16 output blocks: up to a couple of thousand blocks the
+// four wavefronts of a workgroup split the k-steps of one block (or of 2 x 2
+// blocks in launches of several large enough matrices), summed in a fixed
+// order through LDS; otherwise 2 x 2 wavefronts each own 1 x 1 or 2 x 2
+// blocks.  blockIdx.z selects the matrix of a batch.  The shape
 // depends on a matrix's size only, so every matrix's arithmetic is the same
 // alone and in any batch (no cross-matrix sums).
 //
@@ -267,11 +268,14 @@ __global__ void __launch_bounds__(256) zgemm_kernel(ZgArgs g) {
   }
 }
 
-// Small problems (one matrix of a few hundred): a workgroup owns one 16 x 16
-// block and its four wavefronts split the k-steps (wavefront w takes steps
-// w, w + 4, ...); wavefront 0 adds the four partial products in a fixed
-// order from LDS.  Four times the wavefronts of one block per wavefront.
-template <int MODE>
+// Small problems (one matrix of a few hundred): a workgroup owns T x T
+// blocks of 16 x 16 and its four wavefronts split the k-steps (wavefront w
+// takes steps w, w + 4, ...); wavefront 0 adds the four partial products in
+// a fixed order from LDS.  Four times the wavefronts of one block per
+// wavefront; T = 2 shares each operand fragment between two blocks (half
+// the loads per matrix-core instruction).  Every entry's sum runs over the
+// same k-steps in the same order for either T.
+template <int MODE, int T>
 __global__ void __launch_bounds__(256) zgemm_splitk_kernel(ZgArgs g) {
   const int bz = blockIdx.z;
   if (MODE == ZG_NS_SQUARE && g.state[bz] != 0) return;
@@ -282,42 +286,69 @@ __global__ void __launch_bounds__(256) zgemm_splitk_kernel(ZgArgs g) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop control
   const int li = lane & 15, lk = lane >> 4;
-  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int i0 = blockIdx.y * 16 * T, j0 = blockIdx.x * 16 * T;
 
   constexpr bool G3 = MODE != ZG_PLAIN;
-  v4d re[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}}, im[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}},
-      tx[1][1] = {v4d{0.0, 0.0, 0.0, 0.0}};
-  const int i = i0 + li, j = j0 + li;
-  const int ar[1] = {min(i, g.M - 1)}, bc[1] = {min(j, g.N - 1)};
-  const bool aok[1] = {i < g.M}, bok[1] = {j < g.N};
-  kloop<1, 1, G3>(g, A, B, ar, aok, bc, bok, lk, w, 4, re, im, tx);
-  if constexpr (G3) finish3<1, 1>(re, im, tx);
+  v4d re[T][T], im[T][T], tx[T][T];
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      re[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      im[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+      tx[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  int ar[T], bc[T];
+  bool aok[T], bok[T];
+#pragma unroll
+  for (int a = 0; a < T; ++a) {
+    const int i = i0 + 16 * a + li, j = j0 + 16 * a + li;
+    aok[a] = i < g.M;
+    ar[a] = min(i, g.M - 1);
+    bok[a] = j < g.N;
+    bc[a] = min(j, g.N - 1);
+  }
+  kloop<T, T, G3>(g, A, B, ar, aok, bc, bok, lk, w, 4, re, im, tx);
+  if constexpr (G3) finish3<T, T>(re, im, tx);
 
-  // partial products of wavefronts 1..3 -> LDS [w - 1][item][lane]
-  __shared__ double red[3][8][64];
+  // partial products of wavefronts 1..3 -> LDS [w - 1][block][item][lane]
+  __shared__ double red[3][T * T][8][64];
   if (w > 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      red[w - 1][r][lane] = re[0][0][r];
-      red[w - 1][4 + r][lane] = im[0][0][r];
-    }
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          red[w - 1][a * T + b][r][lane] = re[a][b][r];
+          red[w - 1][a * T + b][4 + r][lane] = im[a][b][r];
+        }
   }
   __syncthreads();
   if (w != 0) return;
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      re[0][0][r] += red[q][r][lane];
-      im[0][0][r] += red[q][4 + r][lane];
-    }
   const bool final_out = MODE == ZG_NS_UPDATE && g.state[bz] == 1;
-  double psum = store_block<MODE>(g, C, bz, i0, j0 + li, lk, re[0][0], im[0][0], final_out);
-  if (MODE == ZG_NS_SQUARE) {
+  // |P - I|^2 partials per 16 x 16 block (row-major over the blocks), the
+  // same set for either T
+  const int nbx = (g.N + 15) / 16;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
-    if (lane == 0) g.part[(size_t)bz * g.nparts + (size_t)blockIdx.y * gridDim.x + blockIdx.x] = psum;
-  }
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          re[a][b][r] += red[q][a * T + b][r][lane];
+          im[a][b][r] += red[q][a * T + b][4 + r][lane];
+        }
+      double psum = store_block<MODE>(g, C, bz, i0 + 16 * a, j0 + 16 * b + li, lk, re[a][b], im[a][b], final_out);
+      if (MODE == ZG_NS_SQUARE) {
+        const int by = blockIdx.y * T + a, bx = blockIdx.x * T + b;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
+        if (lane == 0 && by * 16 < g.M && bx * 16 < g.N) g.part[(size_t)bz * g.nparts + (size_t)by * nbx + bx] = psum;
+      }
+    }
 }
 
 // per matrix: r = sqrt(sum |P - I|^2 / n) in a fixed order, then the state
@@ -364,17 +395,17 @@ void launch(const ZgArgs& g, int nb, hipStream_t s) {
   SGN_HIP(hipGetLastError());
 }
 
-template <int MODE>
+template <int MODE, int T>
 void launch_splitk(const ZgArgs& g, int nb, hipStream_t s) {
-  const int gx = (g.N + 15) / 16, gy = (g.M + 15) / 16;
+  const int gx = (g.N + 16 * T - 1) / (16 * T), gy = (g.M + 16 * T - 1) / (16 * T);
   SGN_REQUIRE(gy <= 65535 && nb <= 65535, SGN_EINVAL, "zgemm: grid too large");
-  hipLaunchKernelGGL((zgemm_splitk_kernel<MODE>), dim3(gx, gy, nb), dim3(256), 0, s, g);
+  hipLaunchKernelGGL((zgemm_splitk_kernel<MODE, T>), dim3(gx, gy, nb), dim3(256), 0, s, g);
   SGN_HIP(hipGetLastError());
 }
 
 // launch shape by the output size of one matrix (never by the batch, so a
 // matrix gets the same arithmetic alone and in any batch): 0 = split k-steps
-// over the wavefronts of a 16 x 16 block (up to 2047 blocks, n < 724),
+// over the wavefronts of a workgroup (up to 2047 blocks of 16 x 16, n < 724),
 // 1 = 2 x 2 wavefronts of 16 x 16 blocks, 2 = 2 x 2 wavefronts of 32 x 32
 // blocks (16384 blocks and more)
 int shape(int M, int N) {
@@ -384,10 +415,19 @@ int shape(int M, int N) {
   return 2;
 }
 
+// Split-k workgroups own 2 x 2 blocks when a launch has four or more
+// matrices of 256 blocks or more (enough workgroups), else one: the entries'
+// sums and the residual partials are the same either way.
 template <int MODE>
 void launch_auto(const ZgArgs& g, int nb, hipStream_t s) {
+  const long long blocks16 = (long long)((g.M + 15) / 16) * ((g.N + 15) / 16);
   switch (shape(g.M, g.N)) {
-    case 0: launch_splitk<MODE>(g, nb, s); break;
+    case 0:
+      if (nb >= 4 && blocks16 >= 256)
+        launch_splitk<MODE, 2>(g, nb, s);
+      else
+        launch_splitk<MODE, 1>(g, nb, s);
+      break;
     case 1: launch<1, 1, MODE>(g, nb, s); break;
     default: launch<2, 2, MODE>(g, nb, s); break;
   }
