@@ -278,6 +278,37 @@ def test_block_batched_fixed_k_bitwise_single(env, small_problem):
         sg.sgn_destroy(ctx)
 
 
+@pytest.mark.parametrize("k", [48, 256])
+def test_block16_batched_wide_forms_bitwise_single(env, small_problem, k):
+    # five slots take the wide sweep forms (four column tiles per dot
+    # wavefront, two row blocks per update wavefront) and, at k = 256 (a
+    # composite matrix of 268), the small-sign products with 2 x 2 blocks per
+    # split-k workgroup; single applies take the narrow forms.  Every entry's
+    # sums run in the same order, so the results are bitwise equal.
+    sg, torch = env
+    dims, mu, links, A, Ad, S, T, x = small_problem
+    ctx = sg.sgn_create(links, dims, mu, M_W)
+    try:
+        sg.sgn_deflate_import(ctx, _dev(torch, S), T)
+        sg.sgn_set_block_steps(ctx, 16)
+        nsrc = 5
+        X = torch.stack([_dev(torch, synth.gaussian_source(dims, 1000 + r)) for r in range(nsrc)])
+        Y = torch.empty_like(X)
+        infos = sg.sgn_apply_batched_fixed(ctx, X, Y, k)
+        assert all(i["k_used"] == k for i in infos)
+        for r in range(nsrc):
+            y = torch.empty_like(X[r])
+            sg.sgn_apply_fixed(ctx, X[r].clone(), y, k)
+            assert torch.equal(y, Y[r]), r
+        if k == 48:
+            for r in (0, nsrc - 1):
+                st = arnoldi.modified_arnoldi(lambda v: A @ v, X[r].cpu().numpy(), S, k)
+                ref = arnoldi.approx_definition(S, T, st)
+                assert _rel(Y[r].cpu().numpy(), ref) < 1e-10
+    finally:
+        sg.sgn_destroy(ctx)
+
+
 def test_block_batched_6x6_vs_exact(env):
     # a batch of sources on the headline field at tol 1e-10, against the
     # stored exact results; a zero source and a source in the Schur space ride
