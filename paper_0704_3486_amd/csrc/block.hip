@@ -874,22 +874,22 @@ __device__ void block_factor(const BlockGeo& gg, const BSmall& a, int rs) {
     ref_s = rf;
   }
   __syncthreads();
-  // right-looking Cholesky: step j forms row j of R and updates the trailing block
+  // right-looking Cholesky: step j forms row j of R and updates the trailing
+  // block.  Every thread takes the pivot from g[j][j] itself and row j of R
+  // from row j of g (which step j leaves alone), so a step needs one barrier.
   for (int j = 0; j < s; ++j) {
+    double dj = g[j][j].x;
+    const bool okp = dj > 0.0 && isfinite(dj);
+    if (!okp) dj = 1.0;
+    const double pj = sqrt(dj), ip = 1.0 / pj;
     if (tid == 0) {
-      double dj = g[j][j].x;
-      if (!(dj > 0.0) || !isfinite(dj)) {
-        bad = 1;
-        dj = 1.0;
-      }
-      piv[j] = sqrt(dj);
+      piv[j] = pj;
+      if (!okp) bad = 1;
     }
-    __syncthreads();
-    if (tid < B && tid >= j && tid < s) R[j][tid] = tid == j ? make_double2(piv[j], 0.0) : cscale(g[j][tid], 1.0 / piv[j]);
-    __syncthreads();
+    if (tid < B && tid >= j && tid < s) R[j][tid] = tid == j ? make_double2(pj, 0.0) : cscale(g[j][tid], ip);
     if (tid < B * B) {
       const int u = tid / B, v = tid % B;
-      if (u > j && v > j && u < s && v < s) g[u][v] = csub(g[u][v], cmulc(R[j][u], R[j][v]));
+      if (u > j && v > j && u < s && v < s) g[u][v] = csub(g[u][v], cmulc(cscale(g[j][u], ip), cscale(g[j][v], ip)));
     }
     __syncthreads();
   }
