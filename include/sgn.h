@@ -337,8 +337,8 @@ void sgn_session_destroy(sgn_session* s);
  * SGN_PREC_MIXED: the links, the stencil and the stored Krylov vectors v_j are
  * FP32; the Schur vectors S_m, the candidate vector being orthogonalised,
  * every dot product, the re-orthogonalisation, the composite matrix H, its
- * sign (Roberts) and the assembly of y stay FP64 (always the delayed
- * schedule).  x and y stay complex128 at the ABI. */
+ * sign (sgn_set_sign_method) and the assembly of y stay FP64 (always the
+ * delayed schedule).  x and y stay complex128 at the ABI. */
 int sgn_set_precision(sgn_ctx* ctx, int prec);
 /* The context's precision (SGN_PREC_*), or SGN_ESTATE for a NULL context. */
 int sgn_get_precision(const sgn_ctx* ctx);
@@ -456,10 +456,13 @@ int sgn_matvec(sgn_ctx* ctx, const double* x, double* y);
  * every call of this library.  x, y: device, N entries, distinct. */
 int sgn_matvec_noalloc(sgn_ctx* ctx, const double* x, double* y);
 
-/* F = sgn(A) for a dense n x n complex128 column-major device matrix, by
- * scaled Roberts/Newton iteration (Eq. Roberts) with a Gauss-Jordan inverse.
- * Uses the context's stream and workspace.  iters (nullable) receives the
- * iteration count.  SGN_ESINGULAR on a singular iterate. */
+/* F = sgn(A) for a dense n x n complex128 column-major device matrix, by the
+ * context's sign method (sgn_set_sign_method): the inverse-free
+ * Newton-Schulz iteration on the matrix cores from A / |A|_1, falling back to
+ * Roberts' iteration (Eq. Roberts) with a Gauss-Jordan inverse, or Roberts'
+ * iteration alone.  Uses the context's stream and workspace.  iters
+ * (nullable) receives the iteration count.  SGN_ESINGULAR on a singular
+ * iterate. */
 int sgn_dense_sign(sgn_ctx* ctx, int n, const double* A, double* F, int* iters);
 
 /* C = A B for complex128 column-major device matrices (A: M x K, ld lda;
