@@ -140,11 +140,13 @@ __device__ inline void finish3(v4d (&re)[TM][TN], v4d (&im)[TM][TN], const v4d (
     }
 }
 
-// The k-steps with two in flight ahead of the one being multiplied; the loop
-// body is unrolled three times so the fragments rotate through three register
-// sets without copies (a copy of a just-loaded register would wait for the
-// load).  Steps past K multiply zeros, which leaves the sums unchanged.
-template <int TM, int TN, bool G3>
+// The k-steps with NF - 1 in flight ahead of the one being multiplied (NF =
+// 3, or 2 where the register count would otherwise cost occupancy); the loop
+// body is unrolled NF times so the fragments rotate through NF register sets
+// without copies (a copy of a just-loaded register would wait for the load).
+// Steps past K multiply zeros, which leaves the sums unchanged; the k-steps
+// are multiplied in the same order for either NF.
+template <int TM, int TN, bool G3, int NF = 3>
 __device__ inline void kloop(const ZgArgs& g, const double2* __restrict__ A, const double2* __restrict__ B,
                              const int* ar, const bool* aok, const int* bc, const bool* bok, int lk, int first,
                              int stride, v4d (&re)[TM][TN], v4d (&im)[TM][TN], v4d (&tx)[TM][TN]) {
@@ -166,21 +168,36 @@ __device__ inline void kloop(const ZgArgs& g, const double2* __restrict__ A, con
     w.pb[b] = B + (size_t)bc[b] * g.ldb + (4 * first + lk);
     w.bok[b] = bok[b];
   }
-  Frag<TM, TN> f0, f1, f2;
-  w.load(f0);
-  w.advance();
-  w.load(f1);
-  w.advance();
-  for (int st = first; st < S; st += 3 * stride) {
-    w.load(f2);
-    w.advance();
-    mma<TM, TN, G3>(f0, re, im, tx);
+  static_assert(NF == 2 || NF == 3, "two or three fragment sets");
+  if constexpr (NF == 3) {
+    Frag<TM, TN> f0, f1, f2;
     w.load(f0);
     w.advance();
-    mma<TM, TN, G3>(f1, re, im, tx);
     w.load(f1);
     w.advance();
-    mma<TM, TN, G3>(f2, re, im, tx);
+    for (int st = first; st < S; st += 3 * stride) {
+      w.load(f2);
+      w.advance();
+      mma<TM, TN, G3>(f0, re, im, tx);
+      w.load(f0);
+      w.advance();
+      mma<TM, TN, G3>(f1, re, im, tx);
+      w.load(f1);
+      w.advance();
+      mma<TM, TN, G3>(f2, re, im, tx);
+    }
+  } else {
+    Frag<TM, TN> f0, f1;
+    w.load(f0);
+    w.advance();
+    for (int st = first; st < S; st += 2 * stride) {
+      w.load(f1);
+      w.advance();
+      mma<TM, TN, G3>(f0, re, im, tx);
+      w.load(f0);
+      w.advance();
+      mma<TM, TN, G3>(f1, re, im, tx);
+    }
   }
 }
 
@@ -308,7 +325,8 @@ __global__ void __launch_bounds__(256) zgemm_splitk_kernel(ZgArgs g) {
     bok[a] = j < g.N;
     bc[a] = min(j, g.N - 1);
   }
-  kloop<T, T, G3>(g, A, B, ar, aok, bc, bok, lk, w, 4, re, im, tx);
+  // 2 x 2 blocks: one fragment set in flight (three waves per SIMD, not two)
+  kloop<T, T, G3, (T > 1 ? 2 : 3)>(g, A, B, ar, aok, bc, bok, lk, w, 4, re, im, tx);
   if constexpr (G3) finish3<T, T>(re, im, tx);
 
   // partial products of wavefronts 1..3 -> LDS [w - 1][block][item][lane]
