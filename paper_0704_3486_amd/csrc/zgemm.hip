@@ -107,8 +107,9 @@ struct KWalk {
 // three-multiplication form, re += Re A Re B, im += Im A Im B,
 // tx += (Re A + Im A)(Re B + Im B), turned into Re C = re - im and
 // Im C = tx - re - im by finish3 (a quarter fewer matrix-core instructions;
-// the iteration corrects its own rounding).  Otherwise the four real
-// products straight into Re C and Im C.
+// the extra rounding of Im C is a few units of (|Re A| + |Im A|) (|Re B| +
+// |Im B|) per entry, and the iteration does not amplify rounding of that
+// size).  Otherwise the four real products straight into Re C and Im C.
 template <int TM, int TN, bool G3>
 __device__ inline void mma(const Frag<TM, TN>& f, v4d (&re)[TM][TN], v4d (&im)[TM][TN], v4d (&tx)[TM][TN]) {
 #pragma unroll
