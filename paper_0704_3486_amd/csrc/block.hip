@@ -68,8 +68,8 @@ constexpr int kUnroll = 8;
 constexpr int kMinRowsPerWave = 128;
 constexpr int kDotTiles = 2;
 // tiles per wavefront of the three-multiplication dot pass in a launch of
-// several slots (the block-vector loads shared by four tiles; a single slot
-// keeps two, for twice the workgroups)
+// kWideFrom or more slots (the block-vector loads shared by four tiles);
+// launches of fewer slots keep two, for twice the workgroups
 constexpr int kDot3Tiles = 4;
 constexpr int kDot3TilesSingle = 2;
 // slots from which a launch takes the wide tiles (dot) and row blocks (update)
